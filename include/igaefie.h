@@ -1,0 +1,180 @@
+/*
+ * igaefie.h -- C ABI of the MI355X (gfx950) isogeometric EFIE library.
+ *
+ * The library discretises the electric field integral equation
+ *     -gamma_t e_i = V_kappa w            (Sec. 2.2, eq. (eq:EFIE))
+ * with the div-conforming multipatch spline space S^1 on NURBS patches
+ * (Sec. 3.2) and applies the Galerkin matrix of eq. (eq:MSLtested),
+ *     A_ij = int int G_k(x-y) phi_j(x).phi_i(y) - k^-2 G_k(x-y) div phi_j div phi_i,
+ * G_k(r) = e^{ikr}/(4 pi r) (eq:HelmholtzGreen), compressed by the
+ * interpolation-based fast multipole method of Sec. 4.2: exact element-pair
+ * quadrature in the near field, tensor Chebyshev interpolation of the localized
+ * kernel (eq:lockernel) in the parameter domain for admissible cluster pairs
+ * (eq:admissibility, Algorithm 1), with the K_1^(a,b) / K_2 blocks and moment
+ * matrices of eq. (eq:FMMlr) and nested cluster bases.  Linear systems are solved
+ * with restarted complex GMRES (Sec. 5).
+ *
+ * Conventions
+ *   - every call returns int: IGE_OK (0) or a negative IGE_E* code; the text of the
+ *     last error of the calling thread is returned by ige_last_error();
+ *   - complex numbers are (re, im) pairs of double (ige_c64), bit-compatible with
+ *     C99 double _Complex and torch.complex128;
+ *   - a vector of N unknowns uses the canonical unknown order: patch ascending,
+ *     then component (0: u-flux, 1: v-flux), then (i2 major, i1 minor); an interface
+ *     unknown is numbered where it first occurs and carries sign +1 there and the
+ *     sign that makes the normal flux continuous on the other patch;
+ *   - r right-hand sides are stored column after column (column c at offset c*N);
+ *   - ptr_kind IGE_HOST: pointers are host memory, the call is synchronous;
+ *     IGE_DEVICE: pointers are device memory of the context's device and the call is
+ *     ordered on the context's stream (it returns before the work completes);
+ *   - the caller owns every buffer it passes; the library copies what it keeps.
+ *
+ * Errors: IGE_EINVAL bad argument / shape / non-conforming geometry;
+ *         IGE_ENOMEM device or host allocation failed;
+ *         IGE_ENOTCONV GMRES stopped at maxit (x holds the last iterate, stats valid);
+ *         IGE_EDEVICE a HIP runtime call failed.
+ */
+#ifndef IGAEFIE_H
+#define IGAEFIE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { IGE_OK = 0, IGE_EINVAL = -1, IGE_ENOMEM = -2, IGE_ENOTCONV = -3, IGE_EDEVICE = -4 };
+enum { IGE_HOST = 0, IGE_DEVICE = 1 };
+
+typedef struct { double re, im; } ige_c64;
+
+typedef struct ige_ctx_s *ige_ctx;
+typedef struct ige_geom_s *ige_geom;
+typedef struct ige_op_s *ige_op;
+
+/* Text of the last error raised on the calling thread ("" if none).  Owned by the
+ * library; valid until the next call on this thread. */
+const char *ige_last_error(void);
+
+/* Library version string. */
+const char *ige_version(void);
+
+/* Context: one device and one HIP stream.  device: HIP device ordinal, or -1 for a
+ * host-only context that can create geometries and plan operators (ige_op_plan)
+ * but not assemble or apply them; it makes no HIP call.
+ * hip_stream: a hipStream_t to order all work on, or NULL for a stream the context
+ * creates and owns.  One context per host thread. */
+int ige_ctx_create(int device, void *hip_stream, ige_ctx *out);
+int ige_ctx_destroy(ige_ctx ctx);
+
+/* Geometry: n_patches NURBS maps F_j : [0,1]^2 -> Gamma_j (Sec. 3.1, eq. (def::geom)).
+ *   degree [2P]    (p_u, p_v) of each patch, 1..8
+ *   n_ctrl [2P]    (n_u, n_v) control points per direction
+ *   knots          per patch the open knot vector in u (n_u+p_u+1 values, starting at 0,
+ *                  ending at 1, non-decreasing) followed by the one in v; patches
+ *                  concatenated
+ *   ctrl [sum n_u n_v][4]  control point (x, y, z) and weight w > 0, u index fastest
+ * The patches must form a closed, watertight surface whose interfaces coincide as
+ * parametrised curves up to orientation (Sec. 3.1), with d_uF x d_vF pointing
+ * outwards.  The data are copied; each patch is converted to rational Bezier form
+ * per knot span (Bezier extraction, Sec. 5).  IGE_EINVAL on malformed input or an
+ * edge without exactly one partner edge. */
+int ige_geom_create(ige_ctx ctx, int n_patches, const int *degree, const int *n_ctrl, const double *knots,
+                    const double *ctrl, ige_geom *out);
+int ige_geom_destroy(ige_geom geom);
+
+/* Discretisation and compression parameters.
+ *   p             spline degree of S^1 (Sec. 3.2: S^{p,p-1} x S^{p-1,p}), 1..3
+ *   level         m: 2^m x 2^m elements per patch (Sec. 4.1), 0..10
+ *   kappa         wavenumber > 0
+ *   q             interpolation degree (q+1 Chebyshev nodes per direction), 1..15
+ *   eta           admissibility parameter (eq:admissibility); 0 disables the far
+ *                 field (dense operator by element quadrature)
+ *   gauss_near    g: g x g Gauss points per element for disjoint element pairs (1..8)
+ *   gauss_singular gs: Gauss points per variable of the singular sub-rules (1..12)
+ *   leaf_depth    d: leaf clusters are 2^d x 2^d elements (leaf level max(0, m-d));
+ *                 -1 selects ceil(log2((q+1)/(p+1))) */
+typedef struct {
+    int p, level;
+    double kappa;
+    int q;
+    double eta;
+    int gauss_near, gauss_singular, leaf_depth;
+} ige_params;
+
+/* Assemble the operator on the device: element and cluster-node geometry, the
+ * near-field Galerkin entries (element-pair quadrature, accumulated in the glued
+ * basis as a CSR matrix), the far-field partition and the moment and transfer
+ * tables.  Synchronous. */
+int ige_op_assemble(ige_geom geom, const ige_params *params, ige_op *out);
+int ige_op_destroy(ige_op op);
+
+/* Host-only part of ige_op_assemble: unknowns, cluster and block-cluster trees and
+ * the near-field sparsity pattern, without device work (any context).  The result
+ * answers ige_op_info / ige_op_dofmap / ige_op_partition; ige_apply, ige_solve and
+ * ige_rhs_plane_wave return IGE_EINVAL on it. */
+int ige_op_plan(ige_geom geom, const ige_params *params, ige_op *out);
+
+typedef struct {
+    int64_t n_dof;          /* N glued unknowns */
+    int64_t n_elements;     /* P 4^m */
+    int64_t near_nnz;       /* stored near-field entries */
+    int64_t far_pairs;      /* admissible (ordered) cluster pairs */
+    int64_t near_leaf_pairs;
+    int64_t singular_pairs; /* element pairs that share a corner */
+    int32_t leaf_level, q;
+    int64_t device_bytes;   /* device memory held by the operator */
+    double assemble_ms;     /* wall time of ige_op_assemble */
+} ige_op_info_t;
+int ige_op_info(ige_op op, ige_op_info_t *out);
+
+/* Copy the unknown table to host memory: dof[P][2][n+p][n+p] global index (-1 where
+ * the slot is unused) and sgn[P][2][n+p][n+p] (+1/-1), layout [patch][component][i2][i1]. */
+int ige_op_dofmap(ige_op op, int32_t *dof, int8_t *sgn);
+
+/* Copy the block-cluster partition to host memory, each list sorted:
+ *   far [far_pairs][3]        (level, target cluster, source cluster)
+ *   near [near_leaf_pairs][2] (target leaf cluster, source leaf cluster)
+ * cluster id on level l: patch*4^l + k2*2^l + k1.  Either pointer may be NULL. */
+int ige_op_partition(ige_op op, int32_t *far, int32_t *near);
+
+/* y = A x for r right-hand sides (A the compressed operator).  x, y: N*r complex. */
+int ige_apply(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind);
+
+/* Per-stage device times (ms) of the most recent ige_apply with profiling enabled
+ * (ige_op_set_profiling(op, 1)); stages: 0 P2M, 1 M2M, 2 M2L, 3 M2L reduce,
+ * 4 L2L, 5 near SpMV, 6 L2P.  n: capacity of ms[]; returns the stage count. */
+int ige_op_set_profiling(ige_op op, int on);
+int ige_op_stage_times(ige_op op, double *ms, int n);
+
+/* Right-hand side f_i = - int_Gamma e_inc . phi_i dsigma for r plane waves
+ * e_inc(x) = pol * exp(i kappa dir.x) (Sec. 3.2, eq. (eq:linsys) with the rotated
+ * trace pairing written out): dir [r][3] unit vectors (host), pol [r][3] complex
+ * (host), f: N*r complex in ptr_kind memory.  Solving A w = f gives the surface
+ * current w with e_s = V~ w (eq:ESLP). */
+int ige_rhs_plane_wave(ige_op op, int r, const double *dir, const ige_c64 *pol, ige_c64 *f, int ptr_kind);
+
+typedef struct {
+    double tol;      /* stop at ||f - A x|| <= tol ||f|| (relative, x0 as passed) */
+    int restart;     /* Krylov basis size before restart (>= 1) */
+    int maxit;       /* total iteration cap */
+} ige_solve_opts;
+
+typedef struct {
+    int iters;
+    double relres;   /* true relative residual ||f - A x|| / ||f|| at exit */
+    double seconds;
+} ige_solve_stats;
+
+/* Solve A x = f with restarted complex GMRES (Arnoldi with classical Gram-Schmidt
+ * and reorthogonalisation, Givens rotations), per right-hand side.  x holds the
+ * initial guess on entry.  stats: one entry per right-hand side (may be NULL).
+ * IGE_ENOTCONV if some column stopped at maxit. */
+int ige_solve(ige_op op, int r, const ige_c64 *f, ige_c64 *x, int ptr_kind, const ige_solve_opts *opts,
+              ige_solve_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,296 @@
+"""Python binding of the igaefie C ABI (include/igaefie.h).
+
+Argument marshalling only: every step of the method runs in the HIP library
+`libigaefie.so` built in this directory.  The functions `ige_*` mirror the C
+entry points one to one; `Context`, `Geometry` and `Operator` are thin owners of
+the handles.  Device vectors are torch tensors (complex128, contiguous, on the
+context's device); host vectors are numpy arrays.  There is no fallback: if the
+library is missing, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libigaefie.so")
+
+IGE_OK, IGE_EINVAL, IGE_ENOMEM, IGE_ENOTCONV, IGE_EDEVICE = 0, -1, -2, -3, -4
+IGE_HOST, IGE_DEVICE = 0, 1
+
+
+class IgeError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"igaefie error {code}: {msg}")
+        self.code = code
+
+
+class ige_params(C.Structure):
+    _fields_ = [("p", C.c_int), ("level", C.c_int), ("kappa", C.c_double), ("q", C.c_int), ("eta", C.c_double),
+                ("gauss_near", C.c_int), ("gauss_singular", C.c_int), ("leaf_depth", C.c_int)]
+
+
+class ige_op_info_t(C.Structure):
+    _fields_ = [("n_dof", C.c_int64), ("n_elements", C.c_int64), ("near_nnz", C.c_int64),
+                ("far_pairs", C.c_int64), ("near_leaf_pairs", C.c_int64), ("singular_pairs", C.c_int64),
+                ("leaf_level", C.c_int32), ("q", C.c_int32), ("device_bytes", C.c_int64),
+                ("assemble_ms", C.c_double)]
+
+
+class ige_solve_opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("restart", C.c_int), ("maxit", C.c_int)]
+
+
+class ige_solve_stats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("relres", C.c_double), ("seconds", C.c_double)]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or paper_1807_03097_amd/build.py")
+_lib = C.CDLL(LIB_PATH)
+
+_V = C.c_void_p
+_SIGS = {
+    "ige_last_error": (C.c_char_p, []),
+    "ige_version": (C.c_char_p, []),
+    "ige_ctx_create": (C.c_int, [C.c_int, _V, C.POINTER(_V)]),
+    "ige_ctx_destroy": (C.c_int, [_V]),
+    "ige_geom_create": (C.c_int, [_V, C.c_int, _V, _V, _V, _V, C.POINTER(_V)]),
+    "ige_geom_destroy": (C.c_int, [_V]),
+    "ige_op_assemble": (C.c_int, [_V, C.POINTER(ige_params), C.POINTER(_V)]),
+    "ige_op_plan": (C.c_int, [_V, C.POINTER(ige_params), C.POINTER(_V)]),
+    "ige_op_destroy": (C.c_int, [_V]),
+    "ige_op_info": (C.c_int, [_V, C.POINTER(ige_op_info_t)]),
+    "ige_op_dofmap": (C.c_int, [_V, _V, _V]),
+    "ige_op_partition": (C.c_int, [_V, _V, _V]),
+    "ige_apply": (C.c_int, [_V, C.c_int, _V, _V, C.c_int]),
+    "ige_op_set_profiling": (C.c_int, [_V, C.c_int]),
+    "ige_op_stage_times": (C.c_int, [_V, _V, C.c_int]),
+    "ige_rhs_plane_wave": (C.c_int, [_V, C.c_int, _V, _V, _V, C.c_int]),
+    "ige_solve": (C.c_int, [_V, C.c_int, _V, _V, C.c_int, C.POINTER(ige_solve_opts), _V]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def _check(rc):
+    if rc < 0:
+        raise IgeError(rc, _lib.ige_last_error().decode())
+    return rc
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data_as(_V)
+    return _V(a.data_ptr())   # torch tensor
+
+
+def _kind(a):
+    return IGE_HOST if isinstance(a, np.ndarray) else IGE_DEVICE
+
+
+# --- one-to-one wrappers -------------------------------------------------------
+def ige_last_error():
+    return _lib.ige_last_error().decode()
+
+
+def ige_version():
+    return _lib.ige_version().decode()
+
+
+def ige_ctx_create(device=0, stream=None):
+    h = _V()
+    _check(_lib.ige_ctx_create(device, _V(stream) if stream else None, C.byref(h)))
+    return h
+
+
+def ige_ctx_destroy(h):
+    _check(_lib.ige_ctx_destroy(h))
+
+
+def ige_geom_create(ctx, deg, nctrl, knots, ctrl):
+    deg = np.ascontiguousarray(deg, np.int32)
+    nctrl = np.ascontiguousarray(nctrl, np.int32)
+    knots = np.ascontiguousarray(knots, np.float64)
+    ctrl = np.ascontiguousarray(ctrl, np.float64)
+    h = _V()
+    _check(_lib.ige_geom_create(ctx, len(deg) // 2, _ptr(deg), _ptr(nctrl), _ptr(knots), _ptr(ctrl), C.byref(h)))
+    return h
+
+
+def ige_geom_destroy(h):
+    _check(_lib.ige_geom_destroy(h))
+
+
+def ige_op_assemble(geom, prm: ige_params):
+    h = _V()
+    _check(_lib.ige_op_assemble(geom, C.byref(prm), C.byref(h)))
+    return h
+
+
+def ige_op_plan(geom, prm: ige_params):
+    h = _V()
+    _check(_lib.ige_op_plan(geom, C.byref(prm), C.byref(h)))
+    return h
+
+
+def ige_op_destroy(h):
+    _check(_lib.ige_op_destroy(h))
+
+
+def ige_op_info(op):
+    info = ige_op_info_t()
+    _check(_lib.ige_op_info(op, C.byref(info)))
+    return info
+
+
+def ige_op_dofmap(op, dof, sgn):
+    _check(_lib.ige_op_dofmap(op, _ptr(dof), _ptr(sgn)))
+
+
+def ige_op_partition(op, far, near):
+    _check(_lib.ige_op_partition(op, _ptr(far), _ptr(near)))
+
+
+def ige_apply(op, r, x, y, ptr_kind):
+    _check(_lib.ige_apply(op, r, _ptr(x), _ptr(y), ptr_kind))
+
+
+def ige_op_set_profiling(op, on):
+    _check(_lib.ige_op_set_profiling(op, int(on)))
+
+
+def ige_op_stage_times(op):
+    ms = np.zeros(8)
+    n = _check(_lib.ige_op_stage_times(op, _ptr(ms), 8))
+    return ms[:n]
+
+
+def ige_rhs_plane_wave(op, r, dirs, pols, f, ptr_kind):
+    dirs = np.ascontiguousarray(dirs, np.float64)
+    pols = np.ascontiguousarray(pols, np.complex128)
+    _check(_lib.ige_rhs_plane_wave(op, r, _ptr(dirs), _ptr(pols), _ptr(f), ptr_kind))
+
+
+def ige_solve(op, r, f, x, ptr_kind, opts: ige_solve_opts, stats=None):
+    arr = (ige_solve_stats * r)() if stats is None else stats
+    rc = _lib.ige_solve(op, r, _ptr(f), _ptr(x), ptr_kind, C.byref(opts), C.cast(arr, _V))
+    if rc < 0 and rc != IGE_ENOTCONV:
+        _check(rc)
+    return rc, arr
+
+
+# --- owners ---------------------------------------------------------------------
+class Context:
+    """device=-1 creates a host-only context (planning only, no HIP calls)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self.device = device
+        self.h = ige_ctx_create(device, stream)
+
+    def close(self):
+        if self.h:
+            ige_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Geometry:
+    def __init__(self, ctx: Context, patches):
+        from . import workloads
+        self.ctx = ctx
+        self.h = ige_geom_create(ctx.h, *workloads.pack(patches))
+
+    def close(self):
+        if self.h:
+            ige_geom_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Operator:
+    def __init__(self, geom: Geometry, p: int, level: int, kappa: float, q: int = 8, eta: float = 1.0,
+                 gauss_near: int = 5, gauss_singular: int = 5, leaf_depth: int = -1, plan_only: bool = False):
+        self.geom = geom
+        self.prm = ige_params(p, level, kappa, q, eta, gauss_near, gauss_singular, leaf_depth)
+        self.h = ige_op_plan(geom.h, self.prm) if plan_only else ige_op_assemble(geom.h, self.prm)
+        self.info = ige_op_info(self.h)
+        self.N = int(self.info.n_dof)
+        self.p, self.level = p, level
+
+    def close(self):
+        if self.h:
+            ige_op_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def dofmap(self):
+        nb = (1 << self.level) + self.p
+        P = self.geom_patches()
+        dof = np.zeros((P, 2, nb, nb), np.int32)
+        sgn = np.zeros((P, 2, nb, nb), np.int8)
+        ige_op_dofmap(self.h, dof, sgn)
+        return dof, sgn
+
+    def geom_patches(self):
+        return int(self.info.n_elements) >> (2 * self.level)
+
+    def partition(self):
+        far = np.zeros((int(self.info.far_pairs), 3), np.int32)
+        near = np.zeros((int(self.info.near_leaf_pairs), 2), np.int32)
+        ige_op_partition(self.h, far, near)
+        return {"L": int(self.info.leaf_level), "far": far, "near": near}
+
+    def apply(self, x, y=None):
+        """y = A x; x numpy (host) or torch (device) of shape (N,) or (r, N)."""
+        r = 1 if x.ndim == 1 else x.shape[0]
+        if y is None:
+            if isinstance(x, np.ndarray):
+                y = np.zeros_like(x, dtype=np.complex128)
+            else:
+                y = x.new_zeros(x.shape)
+        ige_apply(self.h, r, x, y, _kind(x))
+        return y
+
+    def rhs_plane_wave(self, dirs, pols, out=None):
+        dirs = np.atleast_2d(dirs)
+        r = dirs.shape[0]
+        if out is None:
+            out = np.zeros((r, self.N), np.complex128)
+        ige_rhs_plane_wave(self.h, r, dirs, np.atleast_2d(pols), out, _kind(out))
+        return out
+
+    def solve(self, f, x0=None, tol=1e-8, restart=1500, maxit=10000):
+        r = 1 if f.ndim == 1 else f.shape[0]
+        if x0 is None:
+            x0 = np.zeros_like(f) if isinstance(f, np.ndarray) else f.new_zeros(f.shape)
+        opts = ige_solve_opts(tol, restart, maxit)
+        rc, stats = ige_solve(self.h, r, f, x0, _kind(f), opts)
+        return x0, [(s.iters, s.relres, s.seconds) for s in stats], rc
+
+    def set_profiling(self, on=True):
+        ige_op_set_profiling(self.h, on)
+
+    def stage_times(self):
+        return ige_op_stage_times(self.h)

@@ -1,0 +1,630 @@
+// C ABI of the igaefie library: contexts, geometry, operator assembly, apply,
+// right-hand side and GMRES.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "op.hpp"
+
+namespace {
+thread_local std::string g_err;
+
+template <class F>
+int guard(F &&f)
+{
+    try {
+        f();
+        g_err.clear();
+        return IGE_OK;
+    } catch (const ige::Status &s) {
+        g_err = s.msg;
+        return s.code;
+    } catch (const std::bad_alloc &) {
+        g_err = "host allocation failed";
+        return IGE_ENOMEM;
+    } catch (const std::exception &e) {
+        g_err = e.what();
+        return IGE_EINVAL;
+    }
+}
+
+using ige::DBuf;
+
+void set_device(ige_ctx ctx) { IGE_HIP(hipSetDevice(ctx->device)); }
+
+double2 c2(std::complex<double> z) { return make_double2(z.real(), z.imag()); }
+std::complex<double> cz(double2 a) { return {a.x, a.y}; }
+
+// y = A x for one right-hand side; x, y device pointers
+void apply_one(ige_op op, const double2 *x, double2 *y)
+{
+    hipStream_t s = op->ctx->stream;
+    const bool prof = op->profiling;
+    auto mark = [&](int i) {
+        if (prof) IGE_HIP(hipEventRecord(op->ev[i], s));
+    };
+    const bool far = !op->work.empty();
+    mark(0);
+    if (far) ige::launch_p2m(op, x);
+    mark(1);
+    if (far) ige::launch_m2m(op);
+    mark(2);
+    if (far) ige::launch_m2l(op);
+    mark(3);
+    if (far) ige::launch_m2l_reduce(op);
+    mark(4);
+    if (far) ige::launch_l2l(op);
+    mark(5);
+    ige::launch_spmv(op, x, y);
+    mark(6);
+    if (far) ige::launch_l2p(op, y);
+    mark(7);
+    if (prof) {
+        IGE_HIP(hipEventSynchronize(op->ev[7]));
+        for (int i = 0; i < 7; ++i) {
+            float ms = 0.f;
+            IGE_HIP(hipEventElapsedTime(&ms, op->ev[i], op->ev[i + 1]));
+            op->stage_ms[i] = ms;
+        }
+    }
+}
+
+void ensure_staging(ige_op op)
+{
+    if (!op->d_x.p) op->d_x.alloc(op->D.N);
+    if (!op->d_y.p) op->d_y.alloc(op->D.N);
+}
+
+}  // namespace
+
+namespace ige {
+void set_error(const std::string &msg) { g_err = msg; }
+}  // namespace ige
+
+extern "C" {
+
+const char *ige_last_error(void) { return g_err.c_str(); }
+
+const char *ige_version(void) { return "igaefie 0.1 (gfx950)"; }
+
+int ige_ctx_create(int device, void *hip_stream, ige_ctx *out)
+{
+    return guard([&] {
+        IGE_REQUIRE(out != nullptr, "out is null");
+        if (device == -1) {   // host-only context
+            auto *c = new ige_ctx_s();
+            c->device = -1;
+            *out = c;
+            return;
+        }
+        int cnt = 0;
+        IGE_HIP(hipGetDeviceCount(&cnt));
+        IGE_REQUIRE(device >= 0 && device < cnt, "device ordinal out of range");
+        auto *c = new ige_ctx_s();
+        c->device = device;
+        try {
+            IGE_HIP(hipSetDevice(device));
+            if (hip_stream) {
+                c->stream = (hipStream_t)hip_stream;
+            } else {
+                IGE_HIP(hipStreamCreate(&c->stream));
+                c->own_stream = true;
+            }
+        } catch (...) {
+            delete c;
+            throw;
+        }
+        *out = c;
+    });
+}
+
+int ige_ctx_destroy(ige_ctx ctx)
+{
+    return guard([&] {
+        if (!ctx) return;
+        if (ctx->device < 0) {
+            delete ctx;
+            return;
+        }
+        if (ctx->own_stream && ctx->stream) {
+            (void)hipSetDevice(ctx->device);
+            (void)hipStreamDestroy(ctx->stream);
+        }
+        delete ctx;
+    });
+}
+
+int ige_geom_create(ige_ctx ctx, int n_patches, const int *degree, const int *n_ctrl, const double *knots,
+                    const double *ctrl, ige_geom *out)
+{
+    return guard([&] {
+        IGE_REQUIRE(ctx && out, "null argument");
+        auto *g = new ige_geom_s();
+        g->ctx = ctx;
+        try {
+            ige::build_geometry(g->G, n_patches, degree, n_ctrl, knots, ctrl);
+        } catch (...) {
+            delete g;
+            throw;
+        }
+        *out = g;
+    });
+}
+
+int ige_geom_destroy(ige_geom geom)
+{
+    return guard([&] { delete geom; });
+}
+
+namespace {
+
+void check_params(const ige_params &P)
+{
+    IGE_REQUIRE(P.p >= 1 && P.p <= ige::kMaxP, "p must be 1..3");
+    IGE_REQUIRE(P.level >= 0 && P.level <= 10, "level must be 0..10");
+    IGE_REQUIRE(std::isfinite(P.kappa) && P.kappa > 0.0, "kappa must be positive");
+    IGE_REQUIRE(P.q >= 1 && P.q + 1 <= ige::kMaxQ1, "q must be 1..15");
+    IGE_REQUIRE(std::isfinite(P.eta) && P.eta >= 0.0, "eta must be >= 0");
+    IGE_REQUIRE(P.gauss_near >= 1 && P.gauss_near <= ige::kMaxG, "gauss_near must be 1..8");
+    IGE_REQUIRE(P.gauss_singular >= 1 && P.gauss_singular <= ige::kMaxGs, "gauss_singular must be 1..12");
+    IGE_REQUIRE(P.leaf_depth >= -1 && P.leaf_depth <= 10, "leaf_depth must be -1..10");
+}
+
+// host part: unknowns, trees, near pattern, singular pairs, far tables
+void plan(ige_op op, const ige_geom_s *geom, ige::NearPattern &A, std::vector<ige::SingularPair> &sing)
+{
+    const ige_params &P = op->prm;
+    int d = P.leaf_depth;
+    if (d < 0) d = std::max(0, (int)std::ceil(std::log2((P.q + 1.0) / (P.p + 1.0)) - 1e-12));
+    ige::build_discretisation(op->D, geom->G, P.p, P.level);
+    ige::build_partition(op->T, geom->G, op->D, P.eta, d);
+    ige::build_far_tables(op->F, op->D, op->T, P.q);
+    ige::build_near_pattern(A, op->D, op->T);
+    op->nnz = A.rowptr.back();
+    std::vector<double> corners;
+    ige::build_singular_pairs(sing, corners, geom->G, op->D, op->T);
+    op->nsing = (int64_t)sing.size();
+    op->lvl_off.assign(op->T.L + 2, 0);
+    for (int l = 0; l <= op->T.L; ++l) op->lvl_off[l + 1] = op->lvl_off[l] + ((int64_t)op->D.P << (2 * l));
+    op->NC = (int)op->lvl_off[op->T.L + 1];
+}
+
+}  // namespace
+
+int ige_op_plan(ige_geom geom, const ige_params *prm, ige_op *out)
+{
+    return guard([&] {
+        IGE_REQUIRE(geom && prm && out, "null argument");
+        check_params(*prm);
+        const auto t0 = std::chrono::steady_clock::now();
+        auto *op = new ige_op_s();
+        op->ctx = geom->ctx;
+        op->prm = *prm;
+        op->assembled = false;
+        try {
+            ige::NearPattern A;
+            std::vector<ige::SingularPair> sing;
+            plan(op, geom, A, sing);
+        } catch (...) {
+            delete op;
+            throw;
+        }
+        op->assemble_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        *out = op;
+    });
+}
+
+int ige_op_assemble(ige_geom geom, const ige_params *prm, ige_op *out)
+{
+    return guard([&] {
+        IGE_REQUIRE(geom && prm && out, "null argument");
+        const ige_params P = *prm;
+        check_params(P);
+        IGE_REQUIRE(geom->ctx->device >= 0, "ige_op_assemble needs a device context");
+        const auto t0 = std::chrono::steady_clock::now();
+        ige_ctx ctx = geom->ctx;
+        set_device(ctx);
+        hipStream_t s = ctx->stream;
+        auto *op = new ige_op_s();
+        op->ctx = ctx;
+        op->prm = P;
+        try {
+            ige::NearPattern A;
+            std::vector<ige::SingularPair> sing;
+            plan(op, geom, A, sing);
+            op->assembled = true;
+            const auto &D = op->D;
+            const auto &T = op->T;
+            const auto &F = op->F;
+            ige::DevOp &v = op->view;
+            v.P = D.P; v.p = D.p; v.m = D.m; v.n = D.n; v.nb = D.nb; v.N = D.N; v.nl = 2 * D.p * (D.p + 1);
+            v.L = T.L; v.s = T.s; v.SL = 1 << T.L;
+            v.q = P.q; v.Q1 = P.q + 1; v.Q = v.Q1 * v.Q1;
+            v.g = P.gauss_near; v.G2 = v.g * v.g; v.gs = P.gauss_singular;
+            v.kappa = P.kappa; v.h = 1.0 / D.n; v.scale_tol = 1e-9 * geom->G.scale;
+            v.rowlen = F.rowlen;
+            // geometry and tables
+            op->d_hdr.upload(geom->G.hdr, s);
+            op->d_brk.upload(geom->G.brk, s);
+            op->d_cp.upload(geom->G.cp, s);
+            v.geo = ige::GeomView{op->d_hdr.p, op->d_brk.p, op->d_cp.p};
+            op->d_dof.upload(D.dof, s);
+            op->d_sgn.upload(D.sgn, s);
+            v.dof = op->d_dof.p; v.sgn = op->d_sgn.p;
+            op->d_ext_p.upload(D.ext_p, s);
+            op->d_ext_q.upload(D.ext_q, s);
+            v.ext_p = op->d_ext_p.p; v.ext_q = op->d_ext_q.p;
+            std::vector<double> gx(v.g), gw(v.g), sx(v.gs), sw(v.gs);
+            ige::gauss_legendre01(v.g, gx.data(), gw.data());
+            ige::gauss_legendre01(v.gs, sx.data(), sw.data());
+            op->d_gx.upload(gx, s); op->d_gw.upload(gw, s); op->d_sx.upload(sx, s); op->d_sw.upload(sw, s);
+            v.gx = op->d_gx.p; v.gw = op->d_gw.p; v.sx = op->d_sx.p; v.sw = op->d_sw.p;
+            std::vector<int32_t> inc((size_t)D.N * 2 * 5);
+            for (size_t i = 0; i < D.inc.size(); ++i)
+                for (int k = 0; k < 5; ++k) inc[i * 5 + k] = D.inc[i][k];
+            op->d_inc.upload(inc, s);
+            v.inc = op->d_inc.p;
+            op->d_err.alloc(1);
+            IGE_HIP(hipMemsetAsync(op->d_err.p, 0, sizeof(int), s));
+            v.err = op->d_err.p;
+            // a0: element data
+            const int64_t E = (int64_t)D.P * D.n * D.n;
+            op->d_eX.alloc((size_t)E * 3 * v.G2);
+            op->d_ePsi.alloc((size_t)E * 4 * v.nl * v.G2);
+            op->d_eC.alloc((size_t)E * 12);
+            v.eX = op->d_eX.p; v.ePsi = op->d_ePsi.p; v.eC = op->d_eC.p;
+            ige::launch_element_data(op);
+            // near-field pattern and quadrature
+            op->d_rowptr.upload(A.rowptr, s);
+            op->d_col.upload(A.col, s);
+            op->d_val.alloc(op->nnz);
+            IGE_HIP(hipMemsetAsync(op->d_val.p, 0, sizeof(double2) * op->nnz, s));
+            v.rowptr = op->d_rowptr.p; v.col = op->d_col.p; v.val = op->d_val.p;
+            op->d_sing.upload(sing, s);
+            std::vector<int32_t> nearflat(T.near.size() * 2);
+            for (size_t i = 0; i < T.near.size(); ++i) {
+                nearflat[2 * i] = T.near[i][0];
+                nearflat[2 * i + 1] = T.near[i][1];
+            }
+            op->d_near.upload(nearflat, s);
+            ige::launch_near_regular(op, (int64_t)T.near.size());
+            ige::launch_near_singular(op);
+            // cluster tree and far field
+            op->d_lvl_off.upload(op->lvl_off, s);
+            v.lvl_off = op->d_lvl_off.p;
+            op->d_xn.upload(F.xn, s);
+            op->d_T0.upload(F.T0, s);
+            op->d_T1.upload(F.T1, s);
+            op->d_Mp.upload(F.Mp, s);
+            op->d_Mq.upload(F.Mq, s);
+            op->d_Mdp.upload(F.Mdp, s);
+            v.xn = op->d_xn.p; v.T0 = op->d_T0.p; v.T1 = op->d_T1.p;
+            v.Mp = op->d_Mp.p; v.Mq = op->d_Mq.p; v.Mdp = op->d_Mdp.p;
+            op->d_nodeX.alloc((size_t)op->NC * 3 * v.Q);
+            op->d_nodeT.alloc((size_t)op->NC * 6 * v.Q);
+            v.nodeX = op->d_nodeX.p; v.nodeT = op->d_nodeT.p;
+            ige::launch_node_geometry(op);
+            // M2L work items: partners of each target in chunks
+            const int CH = 8;
+            std::vector<int32_t> partner;
+            op->wrk_of_tgt.assign(op->NC + 1, 0);
+            {
+                size_t i = 0;
+                std::vector<int32_t> cnt(op->NC, 0);
+                while (i < T.far.size()) {
+                    const int lvl = T.far[i][0], tg = T.far[i][1];
+                    const int gc = (int)op->lvl_off[lvl] + tg;
+                    size_t k = i;
+                    while (k < T.far.size() && T.far[k][0] == lvl && T.far[k][1] == tg) {
+                        partner.push_back((int32_t)(op->lvl_off[lvl] + T.far[k][2]));
+                        ++k;
+                    }
+                    const int beg = (int)(partner.size() - (k - i));
+                    for (int b = beg; b < (int)partner.size(); b += CH) {
+                        op->work.push_back({gc, b, std::min((int)partner.size(), b + CH)});
+                        cnt[gc]++;
+                    }
+                    i = k;
+                }
+                for (int c = 0; c < op->NC; ++c) op->wrk_of_tgt[c + 1] = op->wrk_of_tgt[c] + cnt[c];
+            }
+            op->d_work.upload(op->work, s);
+            op->d_partner.upload(partner, s);
+            op->d_wrk_of_tgt.upload(op->wrk_of_tgt, s);
+            op->d_mom.alloc((size_t)op->NC * 3 * v.Q);
+            op->d_src.alloc((size_t)op->NC * 4 * v.Q);
+            op->d_loc.alloc((size_t)op->NC * 3 * v.Q);
+            op->d_part.alloc(std::max<size_t>(1, op->work.size()) * 4 * v.Q);
+            for (auto &e : op->ev) IGE_HIP(hipEventCreate(&e));
+            IGE_HIP(hipStreamSynchronize(s));
+            int err = 0;
+            IGE_HIP(hipMemcpy(&err, op->d_err.p, sizeof(int), hipMemcpyDeviceToHost));
+            IGE_REQUIRE(err == 0, "near-field assembly produced entries outside the sparsity pattern");
+        } catch (...) {
+            delete op;
+            throw;
+        }
+        op->assemble_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        *out = op;
+    });
+}
+
+int ige_op_destroy(ige_op op)
+{
+    return guard([&] {
+        if (!op) return;
+        if (!op->assembled) {
+            delete op;
+            return;
+        }
+        (void)hipSetDevice(op->ctx->device);
+        (void)hipStreamSynchronize(op->ctx->stream);
+        for (auto &e : op->ev)
+            if (e) (void)hipEventDestroy(e);
+        delete op;
+    });
+}
+
+int ige_op_info(ige_op op, ige_op_info_t *out)
+{
+    return guard([&] {
+        IGE_REQUIRE(op && out, "null argument");
+        ige_op_info_t r{};
+        r.n_dof = op->D.N;
+        r.n_elements = (int64_t)op->D.P * op->D.n * op->D.n;
+        r.near_nnz = op->nnz;
+        r.far_pairs = (int64_t)op->T.far.size();
+        r.near_leaf_pairs = (int64_t)op->T.near.size();
+        r.singular_pairs = op->nsing;
+        r.leaf_level = op->T.L;
+        r.q = op->prm.q;
+        size_t b = 0;
+        b += op->d_hdr.bytes() + op->d_brk.bytes() + op->d_cp.bytes() + op->d_dof.bytes() + op->d_sgn.bytes();
+        b += op->d_ext_p.bytes() + op->d_ext_q.bytes() + op->d_eX.bytes() + op->d_ePsi.bytes() + op->d_eC.bytes();
+        b += op->d_rowptr.bytes() + op->d_col.bytes() + op->d_val.bytes() + op->d_nodeX.bytes() + op->d_nodeT.bytes();
+        b += op->d_Mp.bytes() * 3 + op->d_inc.bytes() + op->d_sing.bytes() + op->d_near.bytes() + op->d_work.bytes();
+        b += op->d_partner.bytes() + op->d_mom.bytes() + op->d_src.bytes() + op->d_loc.bytes() + op->d_part.bytes();
+        b += op->d_x.bytes() + op->d_y.bytes() + op->d_V.bytes() + op->d_w.bytes() + op->d_r.bytes();
+        r.device_bytes = (int64_t)b;
+        r.assemble_ms = op->assemble_ms;
+        *out = r;
+    });
+}
+
+int ige_op_dofmap(ige_op op, int32_t *dof, int8_t *sgn)
+{
+    return guard([&] {
+        IGE_REQUIRE(op, "null operator");
+        if (dof) std::memcpy(dof, op->D.dof.data(), sizeof(int32_t) * op->D.dof.size());
+        if (sgn) std::memcpy(sgn, op->D.sgn.data(), op->D.sgn.size());
+    });
+}
+
+int ige_op_partition(ige_op op, int32_t *far, int32_t *near)
+{
+    return guard([&] {
+        IGE_REQUIRE(op, "null operator");
+        if (far)
+            for (size_t i = 0; i < op->T.far.size(); ++i)
+                for (int k = 0; k < 3; ++k) far[3 * i + k] = op->T.far[i][k];
+        if (near)
+            for (size_t i = 0; i < op->T.near.size(); ++i)
+                for (int k = 0; k < 2; ++k) near[2 * i + k] = op->T.near[i][k];
+    });
+}
+
+int ige_op_set_profiling(ige_op op, int on)
+{
+    return guard([&] {
+        IGE_REQUIRE(op, "null operator");
+        op->profiling = on != 0;
+    });
+}
+
+int ige_op_stage_times(ige_op op, double *ms, int n)
+{
+    int cnt = 0;
+    int rc = guard([&] {
+        IGE_REQUIRE(op && ms, "null argument");
+        for (int i = 0; i < std::min(n, 7); ++i) ms[i] = op->stage_ms[i];
+        cnt = 7;
+    });
+    return rc == IGE_OK ? cnt : rc;
+}
+
+int ige_apply(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind)
+{
+    return guard([&] {
+        IGE_REQUIRE(op && x && y && r >= 1, "bad apply arguments");
+        IGE_REQUIRE(op->assembled, "operator was planned, not assembled");
+        IGE_REQUIRE(ptr_kind == IGE_HOST || ptr_kind == IGE_DEVICE, "bad ptr_kind");
+        set_device(op->ctx);
+        const int64_t N = op->D.N;
+        hipStream_t s = op->ctx->stream;
+        if (ptr_kind == IGE_HOST) ensure_staging(op);
+        for (int c = 0; c < r; ++c) {
+            const double2 *xc = reinterpret_cast<const double2 *>(x) + (size_t)c * N;
+            double2 *yc = reinterpret_cast<double2 *>(y) + (size_t)c * N;
+            if (ptr_kind == IGE_HOST) {
+                IGE_HIP(hipMemcpyAsync(op->d_x.p, xc, sizeof(double2) * N, hipMemcpyHostToDevice, s));
+                apply_one(op, op->d_x.p, op->d_y.p);
+                IGE_HIP(hipMemcpyAsync(yc, op->d_y.p, sizeof(double2) * N, hipMemcpyDeviceToHost, s));
+                IGE_HIP(hipStreamSynchronize(s));
+            } else {
+                apply_one(op, xc, yc);
+            }
+        }
+    });
+}
+
+int ige_rhs_plane_wave(ige_op op, int r, const double *dir, const ige_c64 *pol, ige_c64 *f, int ptr_kind)
+{
+    return guard([&] {
+        IGE_REQUIRE(op && dir && pol && f && r >= 1, "bad rhs arguments");
+        IGE_REQUIRE(op->assembled, "operator was planned, not assembled");
+        IGE_REQUIRE(ptr_kind == IGE_HOST || ptr_kind == IGE_DEVICE, "bad ptr_kind");
+        set_device(op->ctx);
+        const int64_t N = op->D.N;
+        hipStream_t s = op->ctx->stream;
+        if (ptr_kind == IGE_HOST) ensure_staging(op);
+        for (int c = 0; c < r; ++c) {
+            const double *d = dir + 3 * c;
+            IGE_REQUIRE(std::isfinite(d[0]) && std::isfinite(d[1]) && std::isfinite(d[2]), "direction must be finite");
+            const ige_c64 *pc = pol + 3 * c;
+            double2 *fc = reinterpret_cast<double2 *>(f) + (size_t)c * N;
+            double2 *dst = (ptr_kind == IGE_HOST) ? op->d_y.p : fc;
+            ige::launch_rhs_plane(op, d, make_double2(pc[0].re, pc[0].im), make_double2(pc[1].re, pc[1].im),
+                                  make_double2(pc[2].re, pc[2].im), dst);
+            if (ptr_kind == IGE_HOST) {
+                IGE_HIP(hipMemcpyAsync(fc, op->d_y.p, sizeof(double2) * N, hipMemcpyDeviceToHost, s));
+                IGE_HIP(hipStreamSynchronize(s));
+            }
+        }
+    });
+}
+
+int ige_solve(ige_op op, int r, const ige_c64 *f, ige_c64 *x, int ptr_kind, const ige_solve_opts *opts,
+              ige_solve_stats *stats)
+{
+    bool notconv = false;
+    int rc = guard([&] {
+        IGE_REQUIRE(op && f && x && opts && r >= 1, "bad solve arguments");
+        IGE_REQUIRE(op->assembled, "operator was planned, not assembled");
+        IGE_REQUIRE(ptr_kind == IGE_HOST || ptr_kind == IGE_DEVICE, "bad ptr_kind");
+        IGE_REQUIRE(opts->restart >= 1 && opts->maxit >= 0 && std::isfinite(opts->tol) && opts->tol >= 0.0,
+                    "bad solve options");
+        set_device(op->ctx);
+        const int64_t N = op->D.N;
+        const int m = opts->restart;
+        hipStream_t s = op->ctx->stream;
+        if (op->gm_cap < m) {
+            op->d_V.alloc((size_t)(m + 1) * N);
+            op->gm_cap = m;
+        }
+        if (!op->d_w.p) op->d_w.alloc(N);
+        if (!op->d_r.p) op->d_r.alloc(2 * N);   // f and x (host pointers are staged here)
+        if (op->d_h.n < (size_t)(m + 2)) op->d_h.alloc((size_t)(m + 2));
+        if (!op->d_red.p) op->d_red.alloc(4);
+        double2 *V = op->d_V.p, *w = op->d_w.p;
+        using C = std::complex<double>;
+        for (int c = 0; c < r; ++c) {
+            const auto t0 = std::chrono::steady_clock::now();
+            const double2 *fc;
+            double2 *xc;
+            if (ptr_kind == IGE_HOST) {
+                IGE_HIP(hipMemcpyAsync(op->d_r.p, reinterpret_cast<const double2 *>(f) + (size_t)c * N,
+                                       sizeof(double2) * N, hipMemcpyHostToDevice, s));
+                IGE_HIP(hipMemcpyAsync(op->d_r.p + N, reinterpret_cast<double2 *>(x) + (size_t)c * N,
+                                       sizeof(double2) * N, hipMemcpyHostToDevice, s));
+                fc = op->d_r.p;
+                xc = op->d_r.p + N;
+            } else {
+                fc = reinterpret_cast<const double2 *>(f) + (size_t)c * N;
+                xc = reinterpret_cast<double2 *>(x) + (size_t)c * N;
+            }
+            auto norm = [&](const double2 *v) {
+                double h = 0;
+                ige::launch_norm2(op, N, v, op->d_red.p);
+                IGE_HIP(hipMemcpyAsync(&h, op->d_red.p, sizeof(double), hipMemcpyDeviceToHost, s));
+                IGE_HIP(hipStreamSynchronize(s));
+                return h;
+            };
+            // residual r = f - A x into V[0]
+            auto residual = [&]() {
+                apply_one(op, xc, w);
+                ige::launch_scale_copy(op, N, make_double2(1, 0), fc, V);
+                ige::launch_axpby(op, N, make_double2(-1, 0), w, make_double2(1, 0), V);
+                return norm(V);
+            };
+            const double bnorm = norm(fc);
+            int it = 0;
+            double beta = residual();
+            double relres = bnorm > 0 ? beta / bnorm : 0.0;
+            std::vector<C> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1);
+            std::vector<double2> hbuf(m + 2);
+            while (bnorm > 0 && relres > opts->tol && it < opts->maxit) {
+                ige::launch_scale_copy(op, N, make_double2(1.0 / beta, 0), V, V);
+                std::fill(g.begin(), g.end(), C(0));
+                g[0] = beta;
+                int jdone = 0;
+                bool conv = false;
+                for (int jj = 0; jj < m && it < opts->maxit; ++jj) {
+                    double2 *vj1 = V + (size_t)(jj + 1) * N;
+                    apply_one(op, V + (size_t)jj * N, vj1);
+                    // classical Gram-Schmidt, twice
+                    std::vector<C> hcol(jj + 2, C(0));
+                    for (int pass = 0; pass < 2; ++pass) {
+                        ige::launch_dotc(op, V, N, jj + 1, vj1, op->d_h.p);
+                        ige::launch_gemv_sub(op, V, N, jj + 1, op->d_h.p, vj1);
+                        IGE_HIP(hipMemcpyAsync(hbuf.data(), op->d_h.p, sizeof(double2) * (jj + 1), hipMemcpyDeviceToHost, s));
+                        IGE_HIP(hipStreamSynchronize(s));
+                        for (int i = 0; i <= jj; ++i) hcol[i] += cz(hbuf[i]);
+                    }
+                    const double hn = norm(vj1);
+                    hcol[jj + 1] = hn;
+                    if (hn > 0) ige::launch_scale_copy(op, N, make_double2(1.0 / hn, 0), vj1, vj1);
+                    // apply previous rotations [[conj c, conj s], [-s, c]], then the new one
+                    for (int i = 0; i < jj; ++i) {
+                        const C t = std::conj(cs[i]) * hcol[i] + std::conj(sn[i]) * hcol[i + 1];
+                        hcol[i + 1] = -sn[i] * hcol[i] + cs[i] * hcol[i + 1];
+                        hcol[i] = t;
+                    }
+                    const double rho = std::sqrt(std::norm(hcol[jj]) + std::norm(hcol[jj + 1]));
+                    cs[jj] = rho > 0 ? hcol[jj] / rho : C(1);
+                    sn[jj] = rho > 0 ? hcol[jj + 1] / rho : C(0);
+                    hcol[jj] = rho;
+                    hcol[jj + 1] = 0;
+                    g[jj + 1] = -sn[jj] * g[jj];
+                    g[jj] = std::conj(cs[jj]) * g[jj];
+                    for (int i = 0; i <= jj; ++i) H[(size_t)i * m + jj] = hcol[i];
+                    ++it;
+                    jdone = jj + 1;
+                    if (std::abs(g[jj + 1]) <= opts->tol * bnorm) {
+                        conv = true;
+                        break;
+                    }
+                }
+                // y = H^-1 g (upper triangular), x += V y
+                std::vector<C> yv(jdone);
+                for (int i = jdone - 1; i >= 0; --i) {
+                    C acc = g[i];
+                    for (int k = i + 1; k < jdone; ++k) acc -= H[(size_t)i * m + k] * yv[k];
+                    yv[i] = acc / H[(size_t)i * m + i];
+                }
+                std::vector<double2> ny(jdone);
+                for (int i = 0; i < jdone; ++i) ny[i] = c2(-yv[i]);
+                IGE_HIP(hipMemcpyAsync(op->d_h.p, ny.data(), sizeof(double2) * jdone, hipMemcpyHostToDevice, s));
+                ige::launch_gemv_sub(op, V, N, jdone, op->d_h.p, xc);
+                beta = residual();
+                relres = beta / bnorm;
+                (void)conv;
+            }
+            if (ptr_kind == IGE_HOST) {
+                IGE_HIP(hipMemcpyAsync(reinterpret_cast<double2 *>(x) + (size_t)c * N, xc, sizeof(double2) * N,
+                                       hipMemcpyDeviceToHost, s));
+            }
+            IGE_HIP(hipStreamSynchronize(s));
+            if (relres > opts->tol) notconv = true;
+            if (stats) {
+                stats[c].iters = it;
+                stats[c].relres = relres;
+                stats[c].seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            }
+        }
+    });
+    if (rc == IGE_OK && notconv) {
+        g_err = "GMRES reached maxit before the tolerance";
+        return IGE_ENOTCONV;
+    }
+    return rc;
+}
+
+}  // extern "C"

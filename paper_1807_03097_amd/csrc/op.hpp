@@ -1,0 +1,141 @@
+// The assembled operator: host tables and device buffers, plus the kernel
+// launchers that implement assembly, apply, right-hand side and GMRES steps.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <memory>
+#include <vector>
+
+#include "common.hpp"
+#include "setup.hpp"
+
+struct ige_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+};
+
+struct ige_geom_s {
+    ige_ctx ctx = nullptr;
+    ige::Geometry G;
+};
+
+namespace ige {
+
+using cd = double2;   // complex double as (re, im)
+
+// Device view of the operator, passed by value to kernels.
+struct DevOp {
+    int P, p, m, n, nb, N, nl, L, s, SL;   // SL = 2^L leaf clusters per patch side
+    int q, Q1, Q, g, G2, gs;
+    double kappa, h, scale_tol;
+    GeomView geo;
+    const int32_t *dof;
+    const int8_t *sgn;
+    const double *ext_p, *ext_q;       // [n][p+1][p+1], [n][p][p]
+    const double *gx, *gw, *sx, *sw;   // regular / singular 1-D Gauss rules on [0,1]
+    // element data at the regular Gauss points
+    const double *eX;      // [E][3][G2]
+    const double *ePsi;    // [E][4][nl][G2]  weight * (phi_hat d_aF (3 comps), div phi_hat)
+    const double *eC;      // [E][4][3] element corners
+    // near field (glued CSR)
+    const int64_t *rowptr;
+    const int32_t *col;
+    double2 *val;
+    // cluster tree
+    const int64_t *lvl_off;   // [L+2] first global cluster id of each level
+    const double *nodeX;      // [NC][3][Q]
+    const double *nodeT;      // [NC][6][Q]  d_uF (3), d_vF (3)
+    const double *xn;         // [Q1] Chebyshev nodes
+    const double *T0, *T1;    // [Q1][Q1]
+    const double *Mp, *Mq, *Mdp;   // [SL][Q1][rowlen]
+    int rowlen;
+    const int32_t *inc;       // [N][2][5]
+    int *err;                 // assembly consistency counter (entries outside the pattern)
+};
+
+struct M2LWork {
+    int32_t tgt;      // global cluster id
+    int32_t beg, end; // range in the partner array
+};
+
+}  // namespace ige
+
+struct ige_op_s {
+    ige_ctx ctx = nullptr;
+    ige_params prm{};
+    bool assembled = false;   // false: planned on the host only
+    ige::Discretisation D;
+    ige::Partition T;
+    ige::FarTables F;
+    int64_t nnz = 0;
+    int64_t nsing = 0;
+    double assemble_ms = 0.0;
+    bool profiling = false;
+    double stage_ms[8] = {0};
+    hipEvent_t ev[9] = {};
+    int NC = 0;                     // clusters on all levels 0..L
+    std::vector<int64_t> lvl_off;   // host copy
+    std::vector<ige::M2LWork> work; // M2L work items (targets with chunks of partners)
+    std::vector<int32_t> wrk_of_tgt;    // [NC+1] range of work items per target cluster
+
+    // device buffers
+    ige::DBuf<ige::PatchHdr> d_hdr;
+    ige::DBuf<double> d_brk, d_cp;
+    ige::DBuf<int32_t> d_dof;
+    ige::DBuf<int8_t> d_sgn;
+    ige::DBuf<double> d_ext_p, d_ext_q, d_gx, d_gw, d_sx, d_sw;
+    ige::DBuf<double> d_eX, d_ePsi, d_eC;
+    ige::DBuf<int64_t> d_rowptr;
+    ige::DBuf<int32_t> d_col;
+    ige::DBuf<double2> d_val;
+    ige::DBuf<int64_t> d_lvl_off;
+    ige::DBuf<double> d_nodeX, d_nodeT, d_xn, d_T0, d_T1, d_Mp, d_Mq, d_Mdp;
+    ige::DBuf<int32_t> d_inc;
+    ige::DBuf<ige::SingularPair> d_sing;
+    ige::DBuf<int32_t> d_near;          // [nnear][2]
+    ige::DBuf<ige::M2LWork> d_work;
+    ige::DBuf<int32_t> d_partner;       // source global cluster id per work entry
+    ige::DBuf<int32_t> d_wrk_of_tgt;
+    ige::DBuf<int> d_err;
+    // apply workspaces (one right-hand side at a time)
+    ige::DBuf<double2> d_mom;    // [NC][3][Q]   s^1, s^2, d
+    ige::DBuf<double2> d_src;    // [NC][4][Q]   v_x, v_y, v_z, d
+    ige::DBuf<double2> d_part;   // [nwork][4][Q]
+    ige::DBuf<double2> d_loc;    // [NC][3][Q]   t^1, t^2, t^d
+    ige::DBuf<double2> d_x, d_y; // staging for host pointers
+    // GMRES workspace
+    ige::DBuf<double2> d_V, d_w, d_r;
+    ige::DBuf<double2> d_h;
+    ige::DBuf<double> d_red;
+    int gm_cap = 0;
+
+    ige::DevOp view{};
+};
+
+namespace ige {
+
+// assembly
+void launch_element_data(ige_op op);
+void launch_node_geometry(ige_op op);
+void launch_near_regular(ige_op op, int64_t n_near);
+void launch_near_singular(ige_op op);
+// apply pieces (one right-hand side)
+void launch_p2m(ige_op op, const double2 *x);
+void launch_m2m(ige_op op);
+void launch_m2l(ige_op op);
+void launch_m2l_reduce(ige_op op);
+void launch_l2l(ige_op op);
+void launch_spmv(ige_op op, const double2 *x, double2 *y);
+void launch_l2p(ige_op op, double2 *y);
+void launch_rhs_plane(ige_op op, const double *dir, double2 pol0, double2 pol1, double2 pol2, double2 *f);
+// GMRES helpers
+void launch_dotc(ige_op op, const double2 *V, int64_t ldv, int k, const double2 *w, double2 *out);
+void launch_gemv_sub(ige_op op, const double2 *V, int64_t ldv, int k, const double2 *hcoef, double2 *w);
+void launch_axpby(ige_op op, int64_t n, double2 a, const double2 *x, double2 b, double2 *y);
+void launch_scale_copy(ige_op op, int64_t n, double2 a, const double2 *x, double2 *y);
+void launch_norm2(ige_op op, int64_t n, const double2 *x, double *out);
+
+}  // namespace ige

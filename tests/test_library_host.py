@@ -1,0 +1,84 @@
+"""CPU checks of the HIP library: the shared object loads, exports every entry
+point the header declares, and its host-side planning (glued unknowns, cluster
+and block-cluster trees) equals the oracle's bit for bit.  No device calls."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1807_03097_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(ige_[a-z0-9_]+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1807_03097_amd import binding
+    lib = ctypes.CDLL(binding.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 15
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+    assert binding.ige_version().startswith("igaefie")
+
+
+def test_invalid_geometry_is_rejected():
+    from paper_1807_03097_amd import binding as B
+    ctx = B.Context(-1)
+    pats = W.cube_sphere()
+    bad = [dict(p) for p in pats]
+    bad[0] = dict(bad[0], ctrl=bad[0]["ctrl"].copy())
+    bad[0]["ctrl"][1, 1, 3] = -1.0          # negative weight
+    with pytest.raises(B.IgeError) as e:
+        B.Geometry(ctx, bad)
+    assert e.value.code == B.IGE_EINVAL
+    with pytest.raises(B.IgeError):
+        B.Geometry(ctx, pats[:5])           # open surface: an edge without partner
+    moved = [dict(p) for p in pats]
+    moved[2] = dict(moved[2], ctrl=moved[2]["ctrl"] + np.array([0, 0, 1e-3, 0]))
+    with pytest.raises(B.IgeError):
+        B.Geometry(ctx, moved)              # interfaces do not coincide
+    g = B.Geometry(ctx, pats)
+    with pytest.raises(B.IgeError):
+        B.Operator(g, 0, 2, 1.0, plan_only=True)     # p < 1
+    with pytest.raises(B.IgeError):
+        B.Operator(g, 1, 2, -1.0, plan_only=True)    # kappa <= 0
+    op = B.Operator(g, 1, 1, 1.0, plan_only=True)
+    with pytest.raises(B.IgeError):
+        op.apply(np.zeros(op.N, np.complex128))      # planned, not assembled
+
+
+@pytest.mark.parametrize("geom,p,m,eta,d,q", [
+    ("sphere", 1, 2, 0.0, -1, 8), ("sphere", 2, 3, 1.6, 1, 8), ("sphere", 2, 5, 1.0, 2, 8),
+    ("torus", 2, 4, 1.0, 2, 6), ("cube", 1, 4, 0.7, 1, 4), ("jittered", 2, 4, 1.0, 2, 8),
+    ("multispan", 2, 3, 1.0, 1, 6),
+])
+def test_plan_matches_oracle(oracle_mod, geom, p, m, eta, d, q):
+    from paper_1807_03097_amd import binding as B
+    pats = {"sphere": W.cube_sphere, "torus": W.torus, "cube": W.flat_cube,
+            "jittered": lambda: W.jitter(W.cube_sphere(), 0.01, 3),
+            "multispan": lambda: [W.refine_patch_knots(pt, 2, 2) for pt in W.cube_sphere()]}[geom]()
+    ctx = B.Context(-1)
+    g = B.Geometry(ctx, pats)
+    op = B.Operator(g, p, m, 8.0, q, eta, leaf_depth=d, plan_only=True)
+    o = oracle_mod.Oracle(pats, p, m, 8.0, g=2)
+    assert op.N == o.N
+    dof, sgn = op.dofmap()
+    assert np.array_equal(dof, o.dof) and np.array_equal(sgn, o.sgn)
+    dd = d if d >= 0 else int(np.ceil(np.log2((q + 1) / (p + 1)) - 1e-12))
+    tr = o.block_tree(eta if eta > 0 else 0.0, dd)
+    pt = op.partition()
+    assert pt["L"] == tr["L"]
+    assert np.array_equal(pt["far"], tr["far"])
+    assert np.array_equal(pt["near"], tr["near"])
