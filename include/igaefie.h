@@ -142,9 +142,12 @@ int ige_op_partition(ige_op op, int32_t *far, int32_t *near);
 /* y = A x for r right-hand sides (A the compressed operator).  x, y: N*r complex. */
 int ige_apply(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind);
 
-/* Per-stage device times (ms) of the most recent ige_apply with profiling enabled
- * (ige_op_set_profiling(op, 1)); stages: 0 P2M, 1 M2M, 2 M2L, 3 M2L reduce,
- * 4 L2L, 5 near SpMV, 6 L2P.  n: capacity of ms[]; returns the stage count. */
+/* Stage profiling.  ige_op_set_profiling(op, 1) creates HIP events and clears the
+ * record; every later single-column apply records its stage boundaries on the
+ * context stream (no host synchronisation).  ige_op_stage_times synchronises the
+ * stream and returns the average device time (ms) per stage over the last (up to
+ * 256) recorded applies: 0 P2M, 1 M2M, 2 M2L, 3 M2L reduce, 4 L2L, 5 near SpMV,
+ * 6 L2P.  n: capacity of ms[]; returns the stage count (7). */
 int ige_op_set_profiling(ige_op op, int on);
 int ige_op_stage_times(ige_op op, double *ms, int n);
 

@@ -11,6 +11,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import sys
 
 import numpy as np
 
@@ -46,6 +47,13 @@ class ige_solve_opts(C.Structure):
 class ige_solve_stats(C.Structure):
     _fields_ = [("iters", C.c_int), ("relres", C.c_double), ("seconds", C.c_double)]
 
+
+# One HIP runtime per process: torch ships its own libamdhip64 (same soname);
+# loading torch first lets this library bind to that runtime instead of a second one.
+try:
+    import torch  # noqa: F401
+except ImportError:   # torch is optional for host-pointer use
+    torch = None
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or paper_1807_03097_amd/build.py")
@@ -200,6 +208,8 @@ class Context:
             self.h = None
 
     def __del__(self):
+        if sys.is_finalizing():   # the HIP runtime may already be gone
+            return
         try:
             self.close()
         except Exception:
@@ -218,6 +228,8 @@ class Geometry:
             self.h = None
 
     def __del__(self):
+        if sys.is_finalizing():   # the HIP runtime may already be gone
+            return
         try:
             self.close()
         except Exception:
@@ -240,6 +252,8 @@ class Operator:
             self.h = None
 
     def __del__(self):
+        if sys.is_finalizing():   # the HIP runtime may already be gone
+            return
         try:
             self.close()
         except Exception:

@@ -41,13 +41,15 @@ void set_device(ige_ctx ctx) { IGE_HIP(hipSetDevice(ctx->device)); }
 double2 c2(std::complex<double> z) { return make_double2(z.real(), z.imag()); }
 std::complex<double> cz(double2 a) { return {a.x, a.y}; }
 
-// y = A x for one right-hand side; x, y device pointers
+// y = A x for one right-hand side; x, y device pointers.  With profiling on, the
+// stage boundaries are recorded into one of kProfSlots event sets (no host sync).
 void apply_one(ige_op op, const double2 *x, double2 *y)
 {
     hipStream_t s = op->ctx->stream;
     const bool prof = op->profiling;
+    hipEvent_t *ev = prof ? op->prof_ev.data() + (size_t)(op->prof_count % ige_op_s::kProfSlots) * 8 : nullptr;
     auto mark = [&](int i) {
-        if (prof) IGE_HIP(hipEventRecord(op->ev[i], s));
+        if (prof) IGE_HIP(hipEventRecord(ev[i], s));
     };
     const bool far = !op->work.empty();
     mark(0);
@@ -65,14 +67,7 @@ void apply_one(ige_op op, const double2 *x, double2 *y)
     mark(6);
     if (far) ige::launch_l2p(op, y);
     mark(7);
-    if (prof) {
-        IGE_HIP(hipEventSynchronize(op->ev[7]));
-        for (int i = 0; i < 7; ++i) {
-            float ms = 0.f;
-            IGE_HIP(hipEventElapsedTime(&ms, op->ev[i], op->ev[i + 1]));
-            op->stage_ms[i] = ms;
-        }
-    }
+    if (prof) op->prof_count++;
 }
 
 void ensure_staging(ige_op op)
@@ -342,7 +337,6 @@ int ige_op_assemble(ige_geom geom, const ige_params *prm, ige_op *out)
             op->d_src.alloc((size_t)op->NC * 4 * v.Q);
             op->d_loc.alloc((size_t)op->NC * 3 * v.Q);
             op->d_part.alloc(std::max<size_t>(1, op->work.size()) * 4 * v.Q);
-            for (auto &e : op->ev) IGE_HIP(hipEventCreate(&e));
             IGE_HIP(hipStreamSynchronize(s));
             int err = 0;
             IGE_HIP(hipMemcpy(&err, op->d_err.p, sizeof(int), hipMemcpyDeviceToHost));
@@ -367,7 +361,7 @@ int ige_op_destroy(ige_op op)
         }
         (void)hipSetDevice(op->ctx->device);
         (void)hipStreamSynchronize(op->ctx->stream);
-        for (auto &e : op->ev)
+        for (auto &e : op->prof_ev)
             if (e) (void)hipEventDestroy(e);
         delete op;
     });
@@ -425,7 +419,14 @@ int ige_op_set_profiling(ige_op op, int on)
 {
     return guard([&] {
         IGE_REQUIRE(op, "null operator");
+        IGE_REQUIRE(op->assembled, "operator was planned, not assembled");
+        set_device(op->ctx);
+        if (on && op->prof_ev.empty()) {
+            op->prof_ev.assign((size_t)ige_op_s::kProfSlots * 8, nullptr);
+            for (auto &e : op->prof_ev) IGE_HIP(hipEventCreate(&e));
+        }
         op->profiling = on != 0;
+        op->prof_count = 0;
     });
 }
 
@@ -434,8 +435,22 @@ int ige_op_stage_times(ige_op op, double *ms, int n)
     int cnt = 0;
     int rc = guard([&] {
         IGE_REQUIRE(op && ms, "null argument");
-        for (int i = 0; i < std::min(n, 7); ++i) ms[i] = op->stage_ms[i];
-        cnt = 7;
+        const int nst = 7;
+        for (int i = 0; i < std::min(n, nst); ++i) ms[i] = 0.0;
+        const int64_t k = std::min<int64_t>(op->prof_count, ige_op_s::kProfSlots);
+        if (k > 0) {
+            set_device(op->ctx);
+            IGE_HIP(hipStreamSynchronize(op->ctx->stream));
+            for (int64_t sl = 0; sl < k; ++sl) {
+                hipEvent_t *ev = op->prof_ev.data() + sl * 8;
+                for (int i = 0; i < std::min(n, nst); ++i) {
+                    float t = 0.f;
+                    IGE_HIP(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
+                    ms[i] += t / (double)k;
+                }
+            }
+        }
+        cnt = nst;
     });
     return rc == IGE_OK ? cnt : rc;
 }

@@ -74,8 +74,9 @@ struct ige_op_s {
     int64_t nsing = 0;
     double assemble_ms = 0.0;
     bool profiling = false;
-    double stage_ms[8] = {0};
-    hipEvent_t ev[9] = {};
+    static constexpr int kProfSlots = 256;
+    std::vector<hipEvent_t> prof_ev;   // [kProfSlots][8] stage boundary events
+    int64_t prof_count = 0;
     int NC = 0;                     // clusters on all levels 0..L
     std::vector<int64_t> lvl_off;   // host copy
     std::vector<ige::M2LWork> work; // M2L work items (targets with chunks of partners)
