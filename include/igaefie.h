@@ -177,6 +177,12 @@ typedef struct {
 int ige_solve(ige_op op, int r, const ige_c64 *f, ige_c64 *x, int ptr_kind, const ige_solve_opts *opts,
               ige_solve_stats *stats);
 
+/* Diagnostic: evaluate on the context's device the Helmholtz kernel
+ * G_k(r) = e^{ikr}/(4 pi r) (Sec. 2.2, eq. (eq:HelmholtzGreen)) exactly as the
+ * coupling stage does, from squared distances r2[n] > 0 (host memory) into
+ * out[n] (host memory).  Synchronous. */
+int ige_helmholtz_eval(ige_ctx ctx, int64_t n, double kappa, const double *r2, ige_c64 *out);
+
 #ifdef __cplusplus
 }
 #endif

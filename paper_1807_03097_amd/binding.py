@@ -78,6 +78,7 @@ _SIGS = {
     "ige_op_stage_times": (C.c_int, [_V, _V, C.c_int]),
     "ige_rhs_plane_wave": (C.c_int, [_V, C.c_int, _V, _V, _V, C.c_int]),
     "ige_solve": (C.c_int, [_V, C.c_int, _V, _V, C.c_int, C.POINTER(ige_solve_opts), _V]),
+    "ige_helmholtz_eval": (C.c_int, [_V, C.c_int64, C.c_double, _V, _V]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -192,6 +193,13 @@ def ige_solve(op, r, f, x, ptr_kind, opts: ige_solve_opts, stats=None):
     if rc < 0 and rc != IGE_ENOTCONV:
         _check(rc)
     return rc, arr
+
+
+def ige_helmholtz_eval(ctx, kappa, r2):
+    r2 = np.ascontiguousarray(r2, np.float64)
+    out = np.zeros(len(r2), np.complex128)
+    _check(_lib.ige_helmholtz_eval(ctx, len(r2), kappa, _ptr(r2), _ptr(out)))
+    return out
 
 
 # --- owners ---------------------------------------------------------------------

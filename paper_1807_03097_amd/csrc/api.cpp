@@ -336,6 +336,7 @@ int ige_op_assemble(ige_geom geom, const ige_params *prm, ige_op *out)
             op->d_mom.alloc((size_t)op->NC * 3 * v.Q);
             op->d_src.alloc((size_t)op->NC * 4 * v.Q);
             op->d_loc.alloc((size_t)op->NC * 3 * v.Q);
+            op->d_ybuf.alloc((size_t)D.P * v.SL * v.SL * 2 * F.rowlen * F.rowlen);
             op->d_part.alloc(std::max<size_t>(1, op->work.size()) * 4 * v.Q);
             IGE_HIP(hipStreamSynchronize(s));
             int err = 0;
@@ -640,6 +641,26 @@ int ige_solve(ige_op op, int r, const ige_c64 *f, ige_c64 *x, int ptr_kind, cons
         return IGE_ENOTCONV;
     }
     return rc;
+}
+
+int ige_helmholtz_eval(ige_ctx ctx, int64_t n, double kappa, const double *r2, ige_c64 *out)
+{
+    return guard([&] {
+        IGE_REQUIRE(ctx && r2 && out && n >= 0, "bad arguments");
+        IGE_REQUIRE(ctx->device >= 0, "needs a device context");
+        IGE_REQUIRE(std::isfinite(kappa) && kappa > 0.0, "kappa must be positive");
+        for (int64_t i = 0; i < n; ++i) IGE_REQUIRE(std::isfinite(r2[i]) && r2[i] > 0.0, "r2 must be positive");
+        if (n == 0) return;
+        set_device(ctx);
+        DBuf<double> dr;
+        DBuf<double2> dout;
+        dr.alloc(n);
+        dout.alloc(n);
+        IGE_HIP(hipMemcpyAsync(dr.p, r2, sizeof(double) * n, hipMemcpyHostToDevice, ctx->stream));
+        ige::launch_helmholtz_eval(ctx->stream, n, kappa, dr.p, dout.p);
+        IGE_HIP(hipMemcpyAsync(out, dout.p, sizeof(double2) * n, hipMemcpyDeviceToHost, ctx->stream));
+        IGE_HIP(hipStreamSynchronize(ctx->stream));
+    });
 }
 
 }  // extern "C"

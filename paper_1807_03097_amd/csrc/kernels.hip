@@ -14,6 +14,8 @@
 //   a10 GMRES vector kernels
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "op.hpp"
 
 namespace ige {
@@ -27,12 +29,66 @@ __device__ inline double2 cmul(double2 a, double2 b) { return make_double2(a.x *
 __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ inline double2 cscale(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
 
-// Helmholtz kernel e^{i k r} / (4 pi r)
+// Helmholtz kernel e^{i k r} / (4 pi r) (library sincos, correctly rounded sqrt):
+// used by the assembly kernels
 __device__ inline double2 helmholtz(double kappa, double r)
 {
     double sn, cs;
     sincos(kappa * r, &sn, &cs);
     const double f = kInv4Pi / r;
+    return make_double2(cs * f, sn * f);
+}
+
+// Helmholtz kernel from r^2 for the coupling stage.
+//   1/r: hardware reciprocal square root refined by two Newton steps
+//        y <- y (3/2 - r^2 y^2 / 2);
+//   sin, cos of kappa r: Cody-Waite reduction t = kappa r - k pi/2 with pi/2 split
+//        into three doubles (exact products by fused multiply-add), then the Taylor
+//        polynomials of sin (to t^17) and cos (to t^18) on |t| <= pi/4, whose
+//        truncation error is below 1e-19; the quadrant k mod 4 selects signs.
+// Valid for kappa r < 2^30.
+constexpr double kTwoOverPi = 0.6366197723675814;
+constexpr double kPio2_1 = 1.5707963267948966;
+constexpr double kPio2_2 = 6.123233995736766e-17;
+constexpr double kPio2_3 = -1.4973849048591698e-33;
+
+__device__ inline double2 helmholtz_r2(double kappa, double r2)
+{
+    double y = __builtin_amdgcn_rsq(r2);
+    const double hh = 0.5 * r2;
+    y = y * fma(-hh * y, y, 1.5);
+    y = y * fma(-hh * y, y, 1.5);
+    const double x = kappa * (r2 * y);
+    const double k = rint(x * kTwoOverPi);
+    double t = fma(-k, kPio2_1, x);
+    t = fma(-k, kPio2_2, t);
+    t = fma(-k, kPio2_3, t);
+    const double z = t * t;
+    double ps = -1.0 / 355687428096000.0;             // -1/17!
+    ps = fma(ps, z, 1.0 / 1307674368000.0);           //  1/15!
+    ps = fma(ps, z, -1.0 / 6227020800.0);             // -1/13!
+    ps = fma(ps, z, 1.0 / 39916800.0);                //  1/11!
+    ps = fma(ps, z, -1.0 / 362880.0);                 // -1/9!
+    ps = fma(ps, z, 1.0 / 5040.0);                    //  1/7!
+    ps = fma(ps, z, -1.0 / 120.0);                    // -1/5!
+    ps = fma(ps, z, 1.0 / 6.0);                       //  1/3!  (sign applied below)
+    const double s = fma(-t * z, ps, t);              // t - t z (1/3! - z/5! + ...)
+    double pc = 1.0 / 6402373705728000.0;             //  1/18!
+    pc = fma(pc, z, -1.0 / 20922789888000.0);         // -1/16!
+    pc = fma(pc, z, 1.0 / 87178291200.0);             //  1/14!
+    pc = fma(pc, z, -1.0 / 479001600.0);              // -1/12!
+    pc = fma(pc, z, 1.0 / 3628800.0);                 //  1/10!
+    pc = fma(pc, z, -1.0 / 40320.0);                  // -1/8!
+    pc = fma(pc, z, 1.0 / 720.0);                     //  1/6!
+    pc = fma(pc, z, -1.0 / 24.0);                     // -1/4!
+    pc = fma(pc, z, 0.5);                             //  1/2!  (sign applied below)
+    const double c = fma(-z, pc, 1.0);                // 1 - z (1/2! - z/4! + ...)
+    const int q = (int)k & 3;
+    double sn = (q & 1) ? c : s;
+    double cs = (q & 1) ? s : c;
+    if (q & 2) sn = -sn;
+    if ((q + 1) & 2) cs = -cs;
+    const double f = kInv4Pi * y;
     return make_double2(cs * f, sn * f);
 }
 
@@ -606,9 +662,12 @@ __global__ __launch_bounds__(256) void k_m2m(DevOp o, int lvl, double2 *mom, dou
 // a5: M2L. Work item = (target cluster, range of far partners).  The localized
 // kernel is interpolated in both parameter squares:
 //   u[m] += sum_m' G(|x_m - x'_m'|) (v_x, v_y, v_z, d)'[m']
-// Threads: target node m, source-node part (parts split the m' loop).
+// Threads: kM2LNT target nodes each (register blocking: every source value read
+// from LDS serves kM2LNT targets) x a part of the source nodes; the parts are
+// summed once per work item through LDS.
 // ---------------------------------------------------------------------------
 constexpr int kM2LThreads = 256;
+constexpr int kM2LNT = 3;
 
 __global__ __launch_bounds__(kM2LThreads) void k_m2l(DevOp o, const M2LWork *work, const int32_t *partner,
                                                       const double2 *src, double2 *part)
@@ -616,25 +675,33 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l(DevOp o, const M2LWork *wor
     extern __shared__ double smd[];
     const M2LWork wk = work[blockIdx.x];
     const int Q = o.Q;
-    const int parts = kM2LThreads / Q;
-    const int chunk = (Q + parts - 1) / parts;
+    const int TPG = (Q + kM2LNT - 1) / kM2LNT;
+    const int S = min(kM2LThreads / TPG, Q);
+    const int SP = (Q + S - 1) / S;
     const int tid = threadIdx.x;
-    const int mm = tid % Q, pp = tid / Q;
-    const bool active = pp < parts;
-    double *sX = smd;                                   // [3][Q]
-    double2 *sV = reinterpret_cast<double2 *>(sX + 3 * Q);   // [4][Q]
-    double2 *red = sV + 4 * Q;                          // [parts][4][Q]
-    double xt0 = 0, xt1 = 0, xt2 = 0;
-    if (active) {
-        const double *X = o.nodeX + (size_t)wk.tgt * 3 * Q;
-        xt0 = X[mm];
-        xt1 = X[Q + mm];
-        xt2 = X[2 * Q + mm];
+    const int mt = tid % TPG, sp = tid / TPG;
+    const bool active = sp < S;
+    double *sX = smd;                                          // [3][Q]
+    double2 *sV = reinterpret_cast<double2 *>(sX + 3 * Q);     // [4][Q]
+    double2 *red = reinterpret_cast<double2 *>(smd);           // [S][Q][4] after the partner loop
+    double xt[kM2LNT][3];
+    bool val[kM2LNT];
+    double2 acc[kM2LNT][4];
+    const double *Xt = o.nodeX + (size_t)wk.tgt * 3 * Q;
+#pragma unroll
+    for (int k = 0; k < kM2LNT; ++k) {
+        const int mm = mt + k * TPG;
+        val[k] = active && mm < Q;
+        const int mc = val[k] ? mm : 0;
+        xt[k][0] = Xt[mc];
+        xt[k][1] = Xt[Q + mc];
+        xt[k][2] = Xt[2 * Q + mc];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[k][j] = make_double2(0.0, 0.0);
     }
-    double2 u0 = make_double2(0, 0), u1 = u0, u2 = u0, u3 = u0;
-    const int mb = pp * chunk, me = min(Q, mb + chunk);
-    for (int k = wk.beg; k < wk.end; ++k) {
-        const int sc = partner[k];
+    const int mb = min(Q, sp * SP), me = min(Q, mb + SP);
+    for (int kp = wk.beg; kp < wk.end; ++kp) {
+        const int sc = partner[kp];
         __syncthreads();
         const double *Xs = o.nodeX + (size_t)sc * 3 * Q;
         const double2 *Vs = src + (size_t)sc * 4 * Q;
@@ -643,26 +710,34 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l(DevOp o, const M2LWork *wor
         __syncthreads();
         if (active) {
             for (int ms = mb; ms < me; ++ms) {
-                const double d0 = xt0 - sX[ms], d1 = xt1 - sX[Q + ms], d2 = xt2 - sX[2 * Q + ms];
-                const double2 G = helmholtz(o.kappa, sqrt(d0 * d0 + d1 * d1 + d2 * d2));
-                u0 = cadd(u0, cmul(G, sV[ms]));
-                u1 = cadd(u1, cmul(G, sV[Q + ms]));
-                u2 = cadd(u2, cmul(G, sV[2 * Q + ms]));
-                u3 = cadd(u3, cmul(G, sV[3 * Q + ms]));
+                const double x0 = sX[ms], x1 = sX[Q + ms], x2 = sX[2 * Q + ms];
+                const double2 v0 = sV[ms], v1 = sV[Q + ms], v2 = sV[2 * Q + ms], v3 = sV[3 * Q + ms];
+#pragma unroll
+                for (int k = 0; k < kM2LNT; ++k) {
+                    const double d0 = xt[k][0] - x0, d1 = xt[k][1] - x1, d2 = xt[k][2] - x2;
+                    const double r2 = fma(d0, d0, fma(d1, d1, d2 * d2));
+                    const double2 G = helmholtz_r2(o.kappa, r2);
+                    acc[k][0] = cadd(acc[k][0], cmul(G, v0));
+                    acc[k][1] = cadd(acc[k][1], cmul(G, v1));
+                    acc[k][2] = cadd(acc[k][2], cmul(G, v2));
+                    acc[k][3] = cadd(acc[k][3], cmul(G, v3));
+                }
             }
         }
     }
     __syncthreads();
-    if (active) {
-        red[(pp * 4 + 0) * Q + mm] = u0;
-        red[(pp * 4 + 1) * Q + mm] = u1;
-        red[(pp * 4 + 2) * Q + mm] = u2;
-        red[(pp * 4 + 3) * Q + mm] = u3;
-    }
+#pragma unroll
+    for (int k = 0; k < kM2LNT; ++k)
+        if (val[k]) {
+            const int mm = mt + k * TPG;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) red[((size_t)sp * Q + mm) * 4 + j] = acc[k][j];
+        }
     __syncthreads();
     for (int i = tid; i < 4 * Q; i += kM2LThreads) {
+        const int j = i / Q, mm = i % Q;
         double2 v = make_double2(0, 0);
-        for (int q2 = 0; q2 < parts; ++q2) v = cadd(v, red[q2 * 4 * Q + i]);
+        for (int q2 = 0; q2 < S; ++q2) v = cadd(v, red[((size_t)q2 * Q + mm) * 4 + j]);
         part[(size_t)blockIdx.x * 4 * Q + i] = v;
     }
 }
@@ -748,13 +823,62 @@ __global__ __launch_bounds__(256) void k_spmv(DevOp o, const double2 *x, double2
 }
 
 // ---------------------------------------------------------------------------
-// a7: L2P fused with the scatter T^T, one thread per unknown
+// a7: L2P.  Per leaf cluster, the test-side moments of the local spline pieces
+// against the local fields (tensor contraction, u then v):
+//   Y0[i2][i1] = sum Mp(k1)[m1][i1] Mq(k2)[m2][i2] t^1[m2][m1] + Mdp(k1) Mq(k2) t^d
+//   Y1[i2][i1] = sum Mq(k1)[m1][i1] Mp(k2)[m2][i2] t^2[m2][m1] + Mq(k1) Mdp(k2) t^d
+// then one thread per unknown gathers (with the gluing sign) the entries of the
+// leaf clusters that its incarnations touch: the scatter T^T without atomics.
 // ---------------------------------------------------------------------------
-__global__ void k_l2p(DevOp o, const double2 *loc, double2 *y)
+__global__ __launch_bounds__(256) void k_l2p_leaf(DevOp o, const double2 *loc, double2 *ybuf)
+{
+    extern __shared__ double2 sm2[];
+    const int id = blockIdx.x;
+    const int SL = o.SL, s = o.s, p = o.p, Q1 = o.Q1, Q = o.Q, RL = o.rowlen;
+    const int r = id % (SL * SL), k2 = r / SL, k1 = r % SL;
+    const int gc = (int)o.lvl_off[o.L] + id;
+    const double2 *t = loc + (size_t)gc * 3 * Q;
+    const double *Mpu = o.Mp + (size_t)k1 * Q1 * RL, *Mqu = o.Mq + (size_t)k1 * Q1 * RL, *Mdu = o.Mdp + (size_t)k1 * Q1 * RL;
+    const double *Mpv = o.Mp + (size_t)k2 * Q1 * RL, *Mqv = o.Mq + (size_t)k2 * Q1 * RL, *Mdv = o.Mdp + (size_t)k2 * Q1 * RL;
+    double2 *W0 = sm2;                 // [Q1 (m2)][RL (i1)]  component 0 field + divergence
+    double2 *W1 = W0 + Q1 * RL;        // component 1 field
+    double2 *W1d = W1 + Q1 * RL;       // component 1 divergence
+    const int w1a = s + p, w1b = s + p - 1;
+    for (int i = threadIdx.x; i < Q1 * RL; i += blockDim.x) {
+        const int m2 = i / RL, i1 = i % RL;
+        double2 a = make_double2(0, 0), b = make_double2(0, 0), bd = make_double2(0, 0);
+        for (int m1 = 0; m1 < Q1; ++m1) {
+            const double2 f1 = t[m2 * Q1 + m1], f2 = t[Q + m2 * Q1 + m1], fd = t[2 * Q + m2 * Q1 + m1];
+            if (i1 < w1a) a = cadd(a, cadd(cscale(Mpu[m1 * RL + i1], f1), cscale(Mdu[m1 * RL + i1], fd)));
+            if (i1 < w1b) {
+                b = cadd(b, cscale(Mqu[m1 * RL + i1], f2));
+                bd = cadd(bd, cscale(Mqu[m1 * RL + i1], fd));
+            }
+        }
+        W0[i] = a;
+        W1[i] = b;
+        W1d[i] = bd;
+    }
+    __syncthreads();
+    double2 *Y = ybuf + (size_t)id * 2 * RL * RL;
+    for (int i = threadIdx.x; i < 2 * RL * RL; i += blockDim.x) {
+        const int c = i / (RL * RL), rem = i % (RL * RL), i2 = rem / RL, i1 = rem % RL;
+        double2 v = make_double2(0, 0);
+        if (c == 0 && i2 < s + p - 1 && i1 < w1a) {
+            for (int m2 = 0; m2 < Q1; ++m2) v = cadd(v, cscale(Mqv[m2 * RL + i2], W0[m2 * RL + i1]));
+        } else if (c == 1 && i2 < s + p && i1 < w1b) {
+            for (int m2 = 0; m2 < Q1; ++m2)
+                v = cadd(v, cadd(cscale(Mpv[m2 * RL + i2], W1[m2 * RL + i1]), cscale(Mdv[m2 * RL + i2], W1d[m2 * RL + i1])));
+        }
+        Y[i] = v;
+    }
+}
+
+__global__ void k_l2p_gather(DevOp o, const double2 *ybuf, double2 *y)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= o.N) return;
-    const int Q1 = o.Q1, Q = o.Q, RL = o.rowlen, s = o.s, p = o.p, SL = o.SL, n = o.n;
+    const int s = o.s, p = o.p, SL = o.SL, n = o.n, RL = o.rowlen;
     double2 acc = make_double2(0, 0);
     for (int c = 0; c < 2; ++c) {
         const int32_t *in = o.inc + ((size_t)i * 2 + c) * 5;
@@ -767,28 +891,9 @@ __global__ void k_l2p(DevOp o, const double2 *loc, double2 *y)
         const int k2b = max(0, i2 - dv) / s, k2e = min(n - 1, i2) / s;
         for (int k2 = k2b; k2 <= k2e; ++k2)
             for (int k1 = k1b; k1 <= k1e; ++k1) {
-                const int il1 = i1 - k1 * s, il2 = i2 - k2 * s;
-                const int gc = (int)o.lvl_off[o.L] + (j * SL + k2) * SL + k1;
-                const double2 *t = loc + (size_t)gc * 3 * Q;
-                const double *Au, *Av, *Bu, *Bv;   // field moments (A) and divergence moments (B)
-                const double2 *tf = (a == 0) ? t : t + Q;
-                if (a == 0) {
-                    Au = o.Mp + (size_t)k1 * Q1 * RL; Av = o.Mq + (size_t)k2 * Q1 * RL;
-                    Bu = o.Mdp + (size_t)k1 * Q1 * RL; Bv = Av;
-                } else {
-                    Au = o.Mq + (size_t)k1 * Q1 * RL; Av = o.Mp + (size_t)k2 * Q1 * RL;
-                    Bu = Au; Bv = o.Mdp + (size_t)k2 * Q1 * RL;
-                }
-                double2 sum = make_double2(0, 0);
-                for (int m2 = 0; m2 < Q1; ++m2) {
-                    double2 zf = make_double2(0, 0), zd = make_double2(0, 0);
-                    for (int m1 = 0; m1 < Q1; ++m1) {
-                        zf = cadd(zf, cscale(Au[m1 * RL + il1], tf[m2 * Q1 + m1]));
-                        zd = cadd(zd, cscale(Bu[m1 * RL + il1], t[2 * Q + m2 * Q1 + m1]));
-                    }
-                    sum = cadd(sum, cadd(cscale(Av[m2 * RL + il2], zf), cscale(Bv[m2 * RL + il2], zd)));
-                }
-                acc = cadd(acc, cscale(sg, sum));
+                const int leaf = (j * SL + k2) * SL + k1;
+                const double2 v = ybuf[(((size_t)leaf * 2 + a) * RL + (i2 - k2 * s)) * RL + (i1 - k1 * s)];
+                acc = cadd(acc, cscale(sg, v));
             }
     }
     y[i] = cadd(y[i], acc);
@@ -909,7 +1014,19 @@ __global__ __launch_bounds__(kRedThreads) void k_norm2(int64_t n, const double2 
     if (threadIdx.x == 0) out[0] = sqrt(r.x);
 }
 
+__global__ void k_helmholtz_eval(int64_t n, double kappa, const double *r2, double2 *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = helmholtz_r2(kappa, r2[i]);
+}
+
 }  // namespace
+
+void launch_helmholtz_eval(hipStream_t s, int64_t n, double kappa, const double *r2, double2 *out)
+{
+    hipLaunchKernelGGL(k_helmholtz_eval, dim3((n + 255) / 256), dim3(256), 0, s, n, kappa, r2, out);
+    IGE_HIP(hipGetLastError());
+}
 
 // ---------------------------------------------------------------------------
 // launchers
@@ -998,14 +1115,19 @@ void launch_m2m(ige_op op)
     }
 }
 
+size_t m2l_shared_bytes(int Q)
+{
+    const int TPG = (Q + kM2LNT - 1) / kM2LNT;
+    const int S = std::min(kM2LThreads / TPG, Q);
+    return std::max(sizeof(double) * 3 * Q + sizeof(double2) * 4 * Q, sizeof(double2) * 4 * (size_t)Q * S);
+}
+
 void launch_m2l(ige_op op)
 {
     const DevOp &o = op->view;
     if (op->work.empty()) return;
-    const int parts = kM2LThreads / o.Q;
-    const size_t shm = sizeof(double) * 3 * o.Q + sizeof(double2) * 4 * o.Q + sizeof(double2) * 4 * o.Q * parts;
-    hipLaunchKernelGGL(k_m2l, dim3(op->work.size()), dim3(kM2LThreads), shm, op->ctx->stream, o, op->d_work.p,
-                       op->d_partner.p, op->d_src.p, op->d_part.p);
+    hipLaunchKernelGGL(k_m2l, dim3(op->work.size()), dim3(kM2LThreads), m2l_shared_bytes(o.Q), op->ctx->stream, o,
+                       op->d_work.p, op->d_partner.p, op->d_src.p, op->d_part.p);
     IGE_LAUNCH_CHECK();
 }
 
@@ -1040,7 +1162,11 @@ void launch_spmv(ige_op op, const double2 *x, double2 *y)
 void launch_l2p(ige_op op, double2 *y)
 {
     const DevOp &o = op->view;
-    hipLaunchKernelGGL(k_l2p, dim3((o.N + 127) / 128), dim3(128), 0, op->ctx->stream, o, op->d_loc.p, y);
+    const int nleaf = o.P * o.SL * o.SL;
+    const size_t shm = sizeof(double2) * 3 * (size_t)o.Q1 * o.rowlen;
+    hipLaunchKernelGGL(k_l2p_leaf, dim3(nleaf), dim3(256), shm, op->ctx->stream, o, op->d_loc.p, op->d_ybuf.p);
+    IGE_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_l2p_gather, dim3((o.N + 255) / 256), dim3(256), 0, op->ctx->stream, o, op->d_ybuf.p, y);
     IGE_LAUNCH_CHECK();
 }
 

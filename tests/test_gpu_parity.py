@@ -78,6 +78,19 @@ def test_apply_matches_oracle(oracle_mod, ctx, case):
     assert _rel(Y[1], op.apply(X[1].copy())) == 0.0
 
 
+def test_coupling_kernel_evaluation_accuracy(ctx):
+    """The coupling stage's own evaluation of e^{ikr}/(4 pi r) (eq:HelmholtzGreen)
+    against numpy's exp over r in [1e-3, 30] and kappa up to 40."""
+    from paper_1807_03097_amd import binding as B
+    r = np.r_[np.linspace(1e-3, 30.0, 200001), np.geomspace(1e-6, 1e-3, 1000)]
+    for kappa in (0.5, 8.0, 40.0):
+        got = B.ige_helmholtz_eval(ctx.h, kappa, r * r)
+        ref = np.exp(1j * kappa * r) / (4 * np.pi * r)
+        err = np.max(np.abs(got - ref) / np.abs(ref))
+        _say(f"  kappa={kappa} max rel err {err:.2e}")
+        assert err <= 5e-15 * max(1.0, kappa * 30.0)
+
+
 def test_dense_matrix_columns_match_oracle(oracle_mod, ctx):
     """eta = 0: the library's operator is the dense Galerkin matrix; compare all
     columns (unit vectors) with the oracle's matrix."""
