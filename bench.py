@@ -34,7 +34,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--eta", type=float, default=1.6)
-    ap.add_argument("--leaf-depth", type=int, default=2)
+    ap.add_argument("--leaf-depth", type=int, default=3)
     ap.add_argument("--level", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=16, help="rows of the bounded oracle sample")
@@ -112,25 +112,38 @@ def main():
     st = {n: float(v) for n, v in zip(names, stages)}
     log("stage ms: " + " ".join(f"{k}={v:.4f}" for k, v in st.items()) + f"  step={ms_step:.4f} ms wall/step={1e3 * wall / args.steps:.4f}")
 
-    # roofline of the dominant kernel
-    dom = max(st, key=st.get)
-    Q = (q + 1) ** 2
-    if dom == "near_spmv":
-        traffic_alg = info.near_nnz * (16 + 4) + (N + 1) * 8 + 2 * N * 16
-        achieved = traffic_alg / (st[dom] * 1e-3) / 1e9
-        roof = {"kernel": "near_spmv", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "algorithmic_bytes": int(traffic_alg)}
-    else:
+    # roofline of the dominant kernel (durations from the timed region)
+    def roofline(stage_ms):
+        dom = max(stage_ms, key=stage_ms.get)
+        Q = (q + 1) ** 2
+        if dom == "near_spmv":
+            traffic_alg = info.near_nnz * (16 + 4) + (N + 1) * 8 + 2 * N * 16
+            achieved = traffic_alg / (stage_ms[dom] * 1e-3) / 1e9
+            return {"kernel": "k_spmv", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes": int(traffic_alg),
+                    "avg_ms": stage_ms[dom]}
         # M2L: per interpolation-node pair the kernel G(|x - x'|) and four complex
         # multiply-adds; counted as 46 FP64 operations (distance 8, sqrt/rcp/sin/cos 4,
         # scaling 2, complex MACs 32)
         entries = info.far_pairs * Q * Q
         flops = entries * 46.0
-        achieved = flops / (st[dom] * 1e-3) / 1e12
-        roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+        achieved = flops / (stage_ms[dom] * 1e-3) / 1e12
+        return {"kernel": "k_" + dom, "bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
-                "node_pairs": int(entries)}
+                "node_pairs": int(entries), "avg_ms": stage_ms[dom]}
+
+    roof = roofline(st)
+    # the same kernels timed in isolation (stages in order on one stream)
+    op.set_overlap(False)
+    op.set_profiling(True)
+    for _ in range(min(args.steps, 20)):
+        op.apply(x, y)
+    torch.cuda.synchronize()
+    st_iso = {n: float(v) for n, v in zip(names, op.stage_times())}
+    op.set_profiling(False)
+    op.set_overlap(True)
+    roof_iso = roofline(st_iso)
+    log("isolated stage ms: " + " ".join(f"{k}={v:.4f}" for k, v in st_iso.items()))
 
     # parity spot check against the oracle (sampled rows) + CPU baseline
     yh = y.cpu().numpy()
@@ -161,6 +174,8 @@ def main():
         "stage_ms": st,
         "assemble_s": t_asm,
         "roofline": roof,
+        "roofline_isolated": roof_iso,
+        "stage_ms_isolated": st_iso,
         "cpu_baseline": cpu,
         "parity_sampled_rel_err": parity,
     }

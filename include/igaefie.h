@@ -88,7 +88,7 @@ int ige_geom_destroy(ige_geom geom);
  *   p             spline degree of S^1 (Sec. 3.2: S^{p,p-1} x S^{p-1,p}), 1..3
  *   level         m: 2^m x 2^m elements per patch (Sec. 4.1), 0..10
  *   kappa         wavenumber > 0
- *   q             interpolation degree (q+1 Chebyshev nodes per direction), 1..15
+ *   q             interpolation degree (q+1 Chebyshev nodes per direction), 1..11
  *   eta           admissibility parameter (eq:admissibility); 0 disables the far
  *                 field (dense operator by element quadrature)
  *   gauss_near    g: g x g Gauss points per element for disjoint element pairs (1..8)
@@ -149,6 +149,11 @@ int ige_apply(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind);
  * 256) recorded applies: 0 P2M, 1 M2M, 2 M2L, 3 M2L reduce, 4 L2L, 5 near SpMV,
  * 6 L2P.  n: capacity of ms[]; returns the stage count (7). */
 int ige_op_set_profiling(ige_op op, int on);
+
+/* Scheduling knob: on (default) runs the near-field product on a second stream
+ * concurrently with the far-field pipeline; off runs every stage in order on the
+ * context stream (used to time each kernel in isolation). */
+int ige_op_set_overlap(ige_op op, int on);
 int ige_op_stage_times(ige_op op, double *ms, int n);
 
 /* Right-hand side f_i = - int_Gamma e_inc . phi_i dsigma for r plane waves

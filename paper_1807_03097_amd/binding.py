@@ -75,6 +75,7 @@ _SIGS = {
     "ige_op_partition": (C.c_int, [_V, _V, _V]),
     "ige_apply": (C.c_int, [_V, C.c_int, _V, _V, C.c_int]),
     "ige_op_set_profiling": (C.c_int, [_V, C.c_int]),
+    "ige_op_set_overlap": (C.c_int, [_V, C.c_int]),
     "ige_op_stage_times": (C.c_int, [_V, _V, C.c_int]),
     "ige_rhs_plane_wave": (C.c_int, [_V, C.c_int, _V, _V, _V, C.c_int]),
     "ige_solve": (C.c_int, [_V, C.c_int, _V, _V, C.c_int, C.POINTER(ige_solve_opts), _V]),
@@ -173,6 +174,10 @@ def ige_apply(op, r, x, y, ptr_kind):
 
 def ige_op_set_profiling(op, on):
     _check(_lib.ige_op_set_profiling(op, int(on)))
+
+
+def ige_op_set_overlap(op, on):
+    _check(_lib.ige_op_set_overlap(op, int(on)))
 
 
 def ige_op_stage_times(op):
@@ -313,6 +318,9 @@ class Operator:
 
     def set_profiling(self, on=True):
         ige_op_set_profiling(self.h, on)
+
+    def set_overlap(self, on=True):
+        ige_op_set_overlap(self.h, on)
 
     def stage_times(self):
         return ige_op_stage_times(self.h)

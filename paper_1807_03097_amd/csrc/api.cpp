@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -41,32 +42,77 @@ void set_device(ige_ctx ctx) { IGE_HIP(hipSetDevice(ctx->device)); }
 double2 c2(std::complex<double> z) { return make_double2(z.real(), z.imag()); }
 std::complex<double> cz(double2 a) { return {a.x, a.y}; }
 
-// y = A x for one right-hand side; x, y device pointers.  With profiling on, the
-// stage boundaries are recorded into one of kProfSlots event sets (no host sync).
+// y = A x for one right-hand side; x, y device pointers.
+// The near-field product (memory bound) runs on the operator's second stream while
+// the far-field pipeline (arithmetic bound) runs on the context stream; the L2P
+// gather joins both.  With profiling on, stage boundaries are recorded into one of
+// kProfSlots event sets on the stream each stage runs on (no host sync).
 void apply_one(ige_op op, const double2 *x, double2 *y)
 {
-    hipStream_t s = op->ctx->stream;
+    hipStream_t s = op->ctx->stream, s2 = op->aux;
     const bool prof = op->profiling;
-    hipEvent_t *ev = prof ? op->prof_ev.data() + (size_t)(op->prof_count % ige_op_s::kProfSlots) * 8 : nullptr;
-    auto mark = [&](int i) {
-        if (prof) IGE_HIP(hipEventRecord(ev[i], s));
+    hipEvent_t *ev = prof ? op->prof_ev.data() + (size_t)(op->prof_count % ige_op_s::kProfSlots) * ige_op_s::kProfEv
+                          : nullptr;
+    auto mark = [&](int i, hipStream_t st) {
+        if (prof) IGE_HIP(hipEventRecord(ev[i], st));
     };
     const bool far = !op->work.empty();
-    mark(0);
-    if (far) ige::launch_p2m(op, x);
-    mark(1);
-    if (far) ige::launch_m2m(op);
-    mark(2);
-    if (far) ige::launch_m2l(op);
-    mark(3);
-    if (far) ige::launch_m2l_reduce(op);
-    mark(4);
-    if (far) ige::launch_l2l(op);
-    mark(5);
-    ige::launch_spmv(op, x, y);
-    mark(6);
-    if (far) ige::launch_l2p(op, y);
-    mark(7);
+    if (!far || !op->overlap) {
+        if (far) {
+            mark(0, s);
+            ige::launch_p2m(op, x);
+            mark(1, s);
+            ige::launch_m2m(op);
+            mark(2, s);
+            ige::launch_m2l(op);
+            mark(3, s);
+            ige::launch_m2l_reduce(op);
+            mark(4, s);
+            ige::launch_l2l(op);
+            mark(5, s);
+            ige::launch_l2p_leaf(op);
+            mark(6, s);
+        }
+        mark(7, s);
+        ige::launch_spmv(op, x, y, s);
+        mark(8, s);
+        if (far) {
+            mark(9, s);
+            ige::launch_l2p_gather(op, y);
+            mark(10, s);
+        }
+        if (prof) {
+            if (!far)
+                for (int i : {0, 1, 2, 3, 4, 5, 6, 9, 10}) mark(i, s);
+            op->prof_count++;
+        }
+        return;
+    }
+    // the small upward-pass kernels go first; the near-field product then shares
+    // the device with the long coupling stage
+    mark(0, s);
+    ige::launch_p2m(op, x);
+    mark(1, s);
+    ige::launch_m2m(op);
+    mark(2, s);
+    IGE_HIP(hipEventRecord(op->ev_fork, s));
+    IGE_HIP(hipStreamWaitEvent(s2, op->ev_fork, 0));
+    mark(7, s2);
+    ige::launch_spmv(op, x, y, s2);
+    mark(8, s2);
+    IGE_HIP(hipEventRecord(op->ev_join, s2));
+    ige::launch_m2l(op);
+    mark(3, s);
+    ige::launch_m2l_reduce(op);
+    mark(4, s);
+    ige::launch_l2l(op);
+    mark(5, s);
+    ige::launch_l2p_leaf(op);
+    mark(6, s);
+    IGE_HIP(hipStreamWaitEvent(s, op->ev_join, 0));
+    mark(9, s);
+    ige::launch_l2p_gather(op, y);
+    mark(10, s);
     if (prof) op->prof_count++;
 }
 
@@ -164,7 +210,7 @@ void check_params(const ige_params &P)
     IGE_REQUIRE(P.p >= 1 && P.p <= ige::kMaxP, "p must be 1..3");
     IGE_REQUIRE(P.level >= 0 && P.level <= 10, "level must be 0..10");
     IGE_REQUIRE(std::isfinite(P.kappa) && P.kappa > 0.0, "kappa must be positive");
-    IGE_REQUIRE(P.q >= 1 && P.q + 1 <= ige::kMaxQ1, "q must be 1..15");
+    IGE_REQUIRE(P.q >= 1 && P.q <= 11, "q must be 1..11");
     IGE_REQUIRE(std::isfinite(P.eta) && P.eta >= 0.0, "eta must be >= 0");
     IGE_REQUIRE(P.gauss_near >= 1 && P.gauss_near <= ige::kMaxG, "gauss_near must be 1..8");
     IGE_REQUIRE(P.gauss_singular >= 1 && P.gauss_singular <= ige::kMaxGs, "gauss_singular must be 1..12");
@@ -307,7 +353,11 @@ int ige_op_assemble(ige_geom geom, const ige_params *prm, ige_op *out)
             v.nodeX = op->d_nodeX.p; v.nodeT = op->d_nodeT.p;
             ige::launch_node_geometry(op);
             // M2L work items: partners of each target in chunks
-            const int CH = 8;
+            // partners per M2L work item (tuning knob IGE_M2L_CHUNK, default 8)
+            int CH = 8;
+            if (const char *e = std::getenv("IGE_M2L_CHUNK")) CH = std::max(1, std::min(64, std::atoi(e)));
+            op->overlap = true;
+            if (const char *e = std::getenv("IGE_OVERLAP")) op->overlap = std::atoi(e) != 0;
             std::vector<int32_t> partner;
             op->wrk_of_tgt.assign(op->NC + 1, 0);
             {
@@ -338,6 +388,9 @@ int ige_op_assemble(ige_geom geom, const ige_params *prm, ige_op *out)
             op->d_loc.alloc((size_t)op->NC * 3 * v.Q);
             op->d_ybuf.alloc((size_t)D.P * v.SL * v.SL * 2 * F.rowlen * F.rowlen);
             op->d_part.alloc(std::max<size_t>(1, op->work.size()) * 4 * v.Q);
+            IGE_HIP(hipStreamCreate(&op->aux));
+            IGE_HIP(hipEventCreateWithFlags(&op->ev_fork, hipEventDisableTiming));
+            IGE_HIP(hipEventCreateWithFlags(&op->ev_join, hipEventDisableTiming));
             IGE_HIP(hipStreamSynchronize(s));
             int err = 0;
             IGE_HIP(hipMemcpy(&err, op->d_err.p, sizeof(int), hipMemcpyDeviceToHost));
@@ -364,6 +417,12 @@ int ige_op_destroy(ige_op op)
         (void)hipStreamSynchronize(op->ctx->stream);
         for (auto &e : op->prof_ev)
             if (e) (void)hipEventDestroy(e);
+        if (op->aux) {
+            (void)hipStreamSynchronize(op->aux);
+            (void)hipStreamDestroy(op->aux);
+        }
+        if (op->ev_fork) (void)hipEventDestroy(op->ev_fork);
+        if (op->ev_join) (void)hipEventDestroy(op->ev_join);
         delete op;
     });
 }
@@ -423,11 +482,19 @@ int ige_op_set_profiling(ige_op op, int on)
         IGE_REQUIRE(op->assembled, "operator was planned, not assembled");
         set_device(op->ctx);
         if (on && op->prof_ev.empty()) {
-            op->prof_ev.assign((size_t)ige_op_s::kProfSlots * 8, nullptr);
+            op->prof_ev.assign((size_t)ige_op_s::kProfSlots * ige_op_s::kProfEv, nullptr);
             for (auto &e : op->prof_ev) IGE_HIP(hipEventCreate(&e));
         }
         op->profiling = on != 0;
         op->prof_count = 0;
+    });
+}
+
+int ige_op_set_overlap(ige_op op, int on)
+{
+    return guard([&] {
+        IGE_REQUIRE(op, "null operator");
+        op->overlap = on != 0;
     });
 }
 
@@ -442,12 +509,21 @@ int ige_op_stage_times(ige_op op, double *ms, int n)
         if (k > 0) {
             set_device(op->ctx);
             IGE_HIP(hipStreamSynchronize(op->ctx->stream));
+            IGE_HIP(hipStreamSynchronize(op->aux));
+            // stage -> (begin event, end event); L2P = leaf part + gather part
+            const int pairs[7][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}, {7, 8}, {5, 6}};
             for (int64_t sl = 0; sl < k; ++sl) {
-                hipEvent_t *ev = op->prof_ev.data() + sl * 8;
+                hipEvent_t *ev = op->prof_ev.data() + sl * ige_op_s::kProfEv;
                 for (int i = 0; i < std::min(n, nst); ++i) {
                     float t = 0.f;
-                    IGE_HIP(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
-                    ms[i] += t / (double)k;
+                    IGE_HIP(hipEventElapsedTime(&t, ev[pairs[i][0]], ev[pairs[i][1]]));
+                    double v = t;
+                    if (i == 6) {
+                        float t2 = 0.f;
+                        IGE_HIP(hipEventElapsedTime(&t2, ev[9], ev[10]));
+                        v += t2;
+                    }
+                    ms[i] += v / (double)k;
                 }
             }
         }

@@ -620,34 +620,41 @@ __global__ __launch_bounds__(256) void k_m2m(DevOp o, int lvl, double2 *mom, dou
     const int S = 1 << lvl, Q1 = o.Q1, Q = o.Q;
     const int j = id / (S * S), r = id % (S * S), k2 = r / S, k1 = r % S;
     const int gc = (int)o.lvl_off[lvl] + id;
-    double2 *W = sm2;             // [3][Q1][Q1]  (n2, m1)
-    double2 *acc = W + 3 * Q;     // [3][Q]
-    for (int i = threadIdx.x; i < 3 * Q; i += blockDim.x) acc[i] = make_double2(0, 0);
-    for (int c = 0; c < 4; ++c) {
+    double2 *ch = sm2;            // [4 children][3 fields][Q]
+    double2 *W = ch + 12 * Q;     // [4][3][Q1 (n2)][Q1 (m1)]
+    // one read phase: the moments of the four children
+    for (int i = threadIdx.x; i < 12 * Q; i += blockDim.x) {
+        const int c = i / (3 * Q), rem = i % (3 * Q);
         const int c1 = c & 1, c2 = c >> 1;
-        const int cid = (j * 2 * S + 2 * k2 + c2) * 2 * S + 2 * k1 + c1;
-        const int cgc = (int)o.lvl_off[lvl + 1] + cid;
-        const double2 *ch = mom + (size_t)cgc * 3 * Q;
-        const double *Tu = c1 ? o.T1 : o.T0, *Tv = c2 ? o.T1 : o.T0;
-        __syncthreads();
-        for (int i = threadIdx.x; i < 3 * Q; i += blockDim.x) {
-            const int f = i / Q, rem = i % Q, n2 = rem / Q1, m1 = rem % Q1;
-            double2 z = make_double2(0, 0);
-            for (int n1 = 0; n1 < Q1; ++n1) z = cadd(z, cscale(Tu[n1 * Q1 + m1], ch[f * Q + n2 * Q1 + n1]));
-            W[i] = z;
+        const int cgc = (int)o.lvl_off[lvl + 1] + (j * 2 * S + 2 * k2 + c2) * 2 * S + 2 * k1 + c1;
+        ch[i] = mom[(size_t)cgc * 3 * Q + rem];
+    }
+    __syncthreads();
+    // contract along u: W[c][f][n2][m1] = sum_n1 T_c1[n1][m1] child_c[f][n2][n1]
+    for (int i = threadIdx.x; i < 12 * Q; i += blockDim.x) {
+        const int c = i / (3 * Q), rem = i % (3 * Q), f = rem / Q, nm = rem % Q, n2 = nm / Q1, m1 = nm % Q1;
+        const double *Tu = (c & 1) ? o.T1 : o.T0;
+        const double2 *cf = ch + (size_t)(c * 3 + f) * Q + n2 * Q1;
+        double2 z = make_double2(0, 0);
+        for (int n1 = 0; n1 < Q1; ++n1) z = cadd(z, cscale(Tu[n1 * Q1 + m1], cf[n1]));
+        W[i] = z;
+    }
+    __syncthreads();
+    // contract along v and sum the children: parent[f][m2][m1]
+    for (int i = threadIdx.x; i < 3 * Q; i += blockDim.x) {
+        const int f = i / Q, mm = i % Q, m2 = mm / Q1, m1 = mm % Q1;
+        double2 z = make_double2(0, 0);
+        for (int c = 0; c < 4; ++c) {
+            const double *Tv = (c >> 1) ? o.T1 : o.T0;
+            const double2 *wf = W + (size_t)(c * 3 + f) * Q;
+            for (int n2 = 0; n2 < Q1; ++n2) z = cadd(z, cscale(Tv[n2 * Q1 + m2], wf[n2 * Q1 + m1]));
         }
-        __syncthreads();
-        for (int i = threadIdx.x; i < 3 * Q; i += blockDim.x) {
-            const int f = i / Q, rem = i % Q, m2 = rem / Q1, m1 = rem % Q1;
-            double2 z = acc[i];
-            for (int n2 = 0; n2 < Q1; ++n2) z = cadd(z, cscale(Tv[n2 * Q1 + m2], W[f * Q + n2 * Q1 + m1]));
-            acc[i] = z;
-        }
+        ch[i] = z;   // children no longer needed
     }
     __syncthreads();
     for (int mm = threadIdx.x; mm < Q; mm += blockDim.x) {
         double2 *M = mom + (size_t)gc * 3 * Q;
-        const double2 s1 = acc[mm], s2v = acc[Q + mm], d = acc[2 * Q + mm];
+        const double2 s1 = ch[mm], s2v = ch[Q + mm], d = ch[2 * Q + mm];
         M[mm] = s1;
         M[Q + mm] = s2v;
         M[2 * Q + mm] = d;
@@ -809,11 +816,35 @@ __global__ __launch_bounds__(256) void k_spmv(DevOp o, const double2 *x, double2
     if (row >= o.N) return;
     const int64_t b = o.rowptr[row], e = o.rowptr[row + 1];
     double re = 0.0, im = 0.0;
-    for (int64_t k = b + lane; k < e; k += kWave) {
+    // four independent streaming loads in flight per lane; the matrix is read once
+    // per apply, so its loads bypass the caches (x stays cached)
+    int64_t k = b + lane;
+    for (; k + 3 * kWave < e; k += 4 * kWave) {
+        typedef double d2v __attribute__((ext_vector_type(2)));
+        d2v a[4];
+        int c[4];
+        const d2v *vv = reinterpret_cast<const d2v *>(o.val);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a[u] = __builtin_nontemporal_load(vv + k + u * kWave);
+            c[u] = __builtin_nontemporal_load(&o.col[k + u * kWave]);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double2 v = x[c[u]];
+            re = fma(a[u].x, v.x, re);
+            re = fma(-a[u].y, v.y, re);
+            im = fma(a[u].x, v.y, im);
+            im = fma(a[u].y, v.x, im);
+        }
+    }
+    for (; k < e; k += kWave) {
         const double2 a = o.val[k];
         const double2 v = x[o.col[k]];
-        re += a.x * v.x - a.y * v.y;
-        im += a.x * v.y + a.y * v.x;
+        re = fma(a.x, v.x, re);
+        re = fma(-a.y, v.y, re);
+        im = fma(a.x, v.y, im);
+        im = fma(a.y, v.x, im);
     }
     for (int off = kWave / 2; off >= 1; off >>= 1) {
         re += __shfl_xor(re, off, kWave);
@@ -1107,7 +1138,7 @@ void launch_p2m(ige_op op, const double2 *x)
 void launch_m2m(ige_op op)
 {
     const DevOp &o = op->view;
-    const size_t shm = sizeof(double2) * 6 * o.Q;
+    const size_t shm = sizeof(double2) * 24 * o.Q;
     for (int lvl = o.L - 1; lvl >= 0; --lvl) {
         const int ncl = o.P << (2 * lvl);
         hipLaunchKernelGGL(k_m2m, dim3(ncl), dim3(256), shm, op->ctx->stream, o, lvl, op->d_mom.p, op->d_src.p);
@@ -1150,22 +1181,26 @@ void launch_l2l(ige_op op)
     }
 }
 
-void launch_spmv(ige_op op, const double2 *x, double2 *y)
+void launch_spmv(ige_op op, const double2 *x, double2 *y, hipStream_t st)
 {
     const DevOp &o = op->view;
     const int rows_per_block = 256 / kWave;
-    hipLaunchKernelGGL(k_spmv, dim3((o.N + rows_per_block - 1) / rows_per_block), dim3(256), 0, op->ctx->stream, o, x,
-                       y);
+    hipLaunchKernelGGL(k_spmv, dim3((o.N + rows_per_block - 1) / rows_per_block), dim3(256), 0, st, o, x, y);
     IGE_LAUNCH_CHECK();
 }
 
-void launch_l2p(ige_op op, double2 *y)
+void launch_l2p_leaf(ige_op op)
 {
     const DevOp &o = op->view;
     const int nleaf = o.P * o.SL * o.SL;
     const size_t shm = sizeof(double2) * 3 * (size_t)o.Q1 * o.rowlen;
     hipLaunchKernelGGL(k_l2p_leaf, dim3(nleaf), dim3(256), shm, op->ctx->stream, o, op->d_loc.p, op->d_ybuf.p);
     IGE_LAUNCH_CHECK();
+}
+
+void launch_l2p_gather(ige_op op, double2 *y)
+{
+    const DevOp &o = op->view;
     hipLaunchKernelGGL(k_l2p_gather, dim3((o.N + 255) / 256), dim3(256), 0, op->ctx->stream, o, op->d_ybuf.p, y);
     IGE_LAUNCH_CHECK();
 }

@@ -75,7 +75,11 @@ struct ige_op_s {
     double assemble_ms = 0.0;
     bool profiling = false;
     static constexpr int kProfSlots = 256;
-    std::vector<hipEvent_t> prof_ev;   // [kProfSlots][8] stage boundary events
+    static constexpr int kProfEv = 11;
+    std::vector<hipEvent_t> prof_ev;   // [kProfSlots][kProfEv] stage boundary events
+    hipStream_t aux = nullptr;         // second stream: near-field product
+    bool overlap = true;               // near field concurrent with the far field
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int64_t prof_count = 0;
     int NC = 0;                     // clusters on all levels 0..L
     std::vector<int64_t> lvl_off;   // host copy
@@ -130,8 +134,9 @@ void launch_m2m(ige_op op);
 void launch_m2l(ige_op op);
 void launch_m2l_reduce(ige_op op);
 void launch_l2l(ige_op op);
-void launch_spmv(ige_op op, const double2 *x, double2 *y);
-void launch_l2p(ige_op op, double2 *y);
+void launch_spmv(ige_op op, const double2 *x, double2 *y, hipStream_t st);
+void launch_l2p_leaf(ige_op op);
+void launch_l2p_gather(ige_op op, double2 *y);
 void launch_rhs_plane(ige_op op, const double *dir, double2 pol0, double2 pol1, double2 pol2, double2 *f);
 // GMRES helpers
 void launch_dotc(ige_op op, const double2 *V, int64_t ldv, int k, const double2 *w, double2 *out);
