@@ -532,6 +532,24 @@ int ige_op_stage_times(ige_op op, double *ms, int n)
     return rc == IGE_OK ? cnt : rc;
 }
 
+namespace {
+// batched workspaces for r columns
+void ensure_batched(ige_op op, int r)
+{
+    if (op->bcap >= r) return;
+    const ige::DevOp &v = op->view;
+    const size_t Q = v.Q;
+    op->d_bmom.alloc((size_t)op->NC * 3 * Q * r);
+    op->d_bsrc.alloc((size_t)op->NC * 4 * Q * r);
+    op->d_bloc.alloc((size_t)op->NC * 3 * Q * r);
+    op->d_bpart.alloc(std::max<size_t>(1, op->work.size()) * 4 * Q * r);
+    op->d_bybuf.alloc((size_t)v.P * v.SL * v.SL * 2 * v.rowlen * v.rowlen * r);
+    op->d_bxt.alloc((size_t)v.N * r);
+    op->d_byt.alloc((size_t)v.N * r);
+    op->bcap = r;
+}
+}  // namespace
+
 int ige_apply(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind)
 {
     return guard([&] {
@@ -541,18 +559,38 @@ int ige_apply(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind)
         set_device(op->ctx);
         const int64_t N = op->D.N;
         hipStream_t s = op->ctx->stream;
-        if (ptr_kind == IGE_HOST) ensure_staging(op);
-        for (int c = 0; c < r; ++c) {
-            const double2 *xc = reinterpret_cast<const double2 *>(x) + (size_t)c * N;
-            double2 *yc = reinterpret_cast<double2 *>(y) + (size_t)c * N;
+        if (r == 1) {
             if (ptr_kind == IGE_HOST) {
-                IGE_HIP(hipMemcpyAsync(op->d_x.p, xc, sizeof(double2) * N, hipMemcpyHostToDevice, s));
+                ensure_staging(op);
+                IGE_HIP(hipMemcpyAsync(op->d_x.p, x, sizeof(double2) * N, hipMemcpyHostToDevice, s));
                 apply_one(op, op->d_x.p, op->d_y.p);
-                IGE_HIP(hipMemcpyAsync(yc, op->d_y.p, sizeof(double2) * N, hipMemcpyDeviceToHost, s));
+                IGE_HIP(hipMemcpyAsync(y, op->d_y.p, sizeof(double2) * N, hipMemcpyDeviceToHost, s));
                 IGE_HIP(hipStreamSynchronize(s));
             } else {
-                apply_one(op, xc, yc);
+                apply_one(op, reinterpret_cast<const double2 *>(x), reinterpret_cast<double2 *>(y));
             }
+            return;
+        }
+        ensure_batched(op, r);
+        const double2 *xd = reinterpret_cast<const double2 *>(x);
+        double2 *yd = reinterpret_cast<double2 *>(y);
+        if (ptr_kind == IGE_HOST) {
+            if (op->d_bx.n < (size_t)N * r) {
+                op->d_bx.alloc((size_t)N * r);
+                op->d_by.alloc((size_t)N * r);
+            }
+            IGE_HIP(hipMemcpyAsync(op->d_bx.p, x, sizeof(double2) * N * r, hipMemcpyHostToDevice, s));
+            xd = op->d_bx.p;
+            yd = op->d_by.p;
+        }
+        hipEvent_t *ev = op->profiling
+                             ? op->prof_ev.data() + (size_t)(op->prof_count % ige_op_s::kProfSlots) * ige_op_s::kProfEv
+                             : nullptr;
+        ige::apply_batched(op, r, xd, yd, op->d_bxt.p, op->d_byt.p, ev);
+        if (ev) op->prof_count++;
+        if (ptr_kind == IGE_HOST) {
+            IGE_HIP(hipMemcpyAsync(y, op->d_by.p, sizeof(double2) * N * r, hipMemcpyDeviceToHost, s));
+            IGE_HIP(hipStreamSynchronize(s));
         }
     });
 }

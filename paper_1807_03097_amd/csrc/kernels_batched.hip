@@ -1,0 +1,615 @@
+// Batched (several right-hand sides) variants of the apply kernels.
+//
+// Layout: the r columns are innermost everywhere, x_t / y_t are [N][r], cluster
+// arrays [cluster][field][Q][r]; a block handles a chunk of kRB columns
+// (blockIdx.y), so the kernel values G of the coupling stage and the near-field
+// matrix entries are read or computed once per chunk instead of once per column.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "op.hpp"
+
+namespace ige {
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kRBMax = 8;   // largest column chunk
+
+__device__ __constant__ double kInv4PiB = 0.07957747154594767;
+
+__device__ inline double2 cmulb(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ inline double2 caddb(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ inline double2 cscaleb(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
+
+// same evaluation as the single-column coupling stage (see kernels.hip)
+constexpr double kTwoOverPi = 0.6366197723675814;
+constexpr double kPio2_1 = 1.5707963267948966;
+constexpr double kPio2_2 = 6.123233995736766e-17;
+constexpr double kPio2_3 = -1.4973849048591698e-33;
+
+__device__ inline double2 helmholtz_r2b(double kappa, double r2)
+{
+    double y = __builtin_amdgcn_rsq(r2);
+    const double hh = 0.5 * r2;
+    y = y * fma(-hh * y, y, 1.5);
+    y = y * fma(-hh * y, y, 1.5);
+    const double x = kappa * (r2 * y);
+    const double k = rint(x * kTwoOverPi);
+    double t = fma(-k, kPio2_1, x);
+    t = fma(-k, kPio2_2, t);
+    t = fma(-k, kPio2_3, t);
+    const double z = t * t;
+    double ps = -1.0 / 355687428096000.0;
+    ps = fma(ps, z, 1.0 / 1307674368000.0);
+    ps = fma(ps, z, -1.0 / 6227020800.0);
+    ps = fma(ps, z, 1.0 / 39916800.0);
+    ps = fma(ps, z, -1.0 / 362880.0);
+    ps = fma(ps, z, 1.0 / 5040.0);
+    ps = fma(ps, z, -1.0 / 120.0);
+    ps = fma(ps, z, 1.0 / 6.0);
+    const double s = fma(-t * z, ps, t);
+    double pc = 1.0 / 6402373705728000.0;
+    pc = fma(pc, z, -1.0 / 20922789888000.0);
+    pc = fma(pc, z, 1.0 / 87178291200.0);
+    pc = fma(pc, z, -1.0 / 479001600.0);
+    pc = fma(pc, z, 1.0 / 3628800.0);
+    pc = fma(pc, z, -1.0 / 40320.0);
+    pc = fma(pc, z, 1.0 / 720.0);
+    pc = fma(pc, z, -1.0 / 24.0);
+    pc = fma(pc, z, 0.5);
+    const double c = fma(-z, pc, 1.0);
+    const int q = (int)k & 3;
+    double sn = (q & 1) ? c : s;
+    double cs = (q & 1) ? s : c;
+    if (q & 2) sn = -sn;
+    if ((q + 1) & 2) cs = -cs;
+    const double f = kInv4PiB * y;
+    return make_double2(cs * f, sn * f);
+}
+
+// x [r][N] -> xt [N][r] and back
+__global__ void k_to_rows(int64_t N, int r, const double2 *x, double2 *xt)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N * r) return;
+    const int64_t i = t / r;
+    const int c = (int)(t % r);
+    xt[t] = x[(size_t)c * N + i];
+}
+
+__global__ void k_to_cols(int64_t N, int r, const double2 *yt, double2 *y)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N * r) return;
+    const int c = (int)(t / N);
+    const int64_t i = t % N;
+    y[t] = yt[i * r + c];
+}
+
+// ---------------------------------------------------------------------------
+// near-field product, kRB columns per pass over a row
+// ---------------------------------------------------------------------------
+template <int kRB>
+__global__ __launch_bounds__(256) void k_spmm(DevOp o, int r, const double2 *xt, double2 *yt)
+{
+    // lane = (entry slot, column): kRB lanes share one matrix entry and read the
+    // kRB consecutive columns of x_t[j] (one contiguous line); 64/kRB entries per step
+    constexpr int EPS = kWave / kRB;
+    const int row = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave;
+    const int c = lane % kRB, es = lane / kRB;
+    const int c0 = blockIdx.y * kRB;
+    const bool cok = c0 + c < r;
+    if (row >= o.N) return;
+    const int64_t b = o.rowptr[row], e = o.rowptr[row + 1];
+    double re = 0.0, im = 0.0;
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    const d2v *vv = reinterpret_cast<const d2v *>(o.val);
+    int64_t k = b + es;
+    for (; k + EPS < e; k += 2 * EPS) {
+        const d2v a0 = __builtin_nontemporal_load(vv + k);
+        const d2v a1 = __builtin_nontemporal_load(vv + k + EPS);
+        const int j0 = __builtin_nontemporal_load(o.col + k);
+        const int j1 = __builtin_nontemporal_load(o.col + k + EPS);
+        const double2 v0 = cok ? xt[(size_t)j0 * r + c0 + c] : make_double2(0, 0);
+        const double2 v1 = cok ? xt[(size_t)j1 * r + c0 + c] : make_double2(0, 0);
+        re = fma(a0.x, v0.x, re);
+        re = fma(-a0.y, v0.y, re);
+        im = fma(a0.x, v0.y, im);
+        im = fma(a0.y, v0.x, im);
+        re = fma(a1.x, v1.x, re);
+        re = fma(-a1.y, v1.y, re);
+        im = fma(a1.x, v1.y, im);
+        im = fma(a1.y, v1.x, im);
+    }
+    for (; k < e; k += EPS) {
+        const d2v a0 = vv[k];
+        const int j0 = o.col[k];
+        const double2 v0 = cok ? xt[(size_t)j0 * r + c0 + c] : make_double2(0, 0);
+        re = fma(a0.x, v0.x, re);
+        re = fma(-a0.y, v0.y, re);
+        im = fma(a0.x, v0.y, im);
+        im = fma(a0.y, v0.x, im);
+    }
+    // sum over the entry slots (lanes with the same column)
+    for (int off = kWave / 2; off >= kRB; off >>= 1) {
+        re += __shfl_xor(re, off, kWave);
+        im += __shfl_xor(im, off, kWave);
+    }
+    if (es == 0 && cok) yt[(size_t)row * r + c0 + c] = make_double2(re, im);
+}
+
+// ---------------------------------------------------------------------------
+// P2M on the leaves (gather of the glued coefficients fused), kRB columns
+// ---------------------------------------------------------------------------
+template <int kRB>
+__global__ __launch_bounds__(256) void k_p2m_b(DevOp o, int r, const double2 *xt, double2 *mom, double2 *src)
+{
+    extern __shared__ double2 sm2[];
+    const int id = blockIdx.x;
+    const int c0 = blockIdx.y * kRB, nc = min(kRB, r - c0);
+    const int SL = o.SL, s = o.s, p = o.p, Q1 = o.Q1, Q = o.Q, RL = o.rowlen;
+    const int j = id / (SL * SL), rr = id % (SL * SL), k2 = rr / SL, k1 = rr % SL;
+    const int gc = (int)o.lvl_off[o.L] + id;
+    const int w1a = s + p, w2a = s + p - 1, w1b = s + p - 1, w2b = s + p;
+    double2 *X1 = sm2;                         // [w2a][w1a][kRB]
+    double2 *X2 = X1 + w2a * w1a * kRB;        // [w2b][w1b][kRB]
+    double2 *Z1 = X2 + w2b * w1b * kRB;        // [w2a][Q1][kRB]
+    double2 *Zd = Z1 + w2a * Q1 * kRB;
+    double2 *Z2 = Zd + w2a * Q1 * kRB;         // [w2b][Q1][kRB]
+    for (int i = threadIdx.x; i < w2a * w1a * kRB; i += blockDim.x) {
+        const int c = i % kRB, t = i / kRB, i2 = t / w1a, i1 = t % w1a;
+        const size_t off = (((size_t)j * 2 + 0) * o.nb + (k2 * s + i2)) * o.nb + (k1 * s + i1);
+        X1[i] = c < nc ? cscaleb((double)o.sgn[off], xt[(size_t)o.dof[off] * r + c0 + c]) : make_double2(0, 0);
+    }
+    for (int i = threadIdx.x; i < w2b * w1b * kRB; i += blockDim.x) {
+        const int c = i % kRB, t = i / kRB, i2 = t / w1b, i1 = t % w1b;
+        const size_t off = (((size_t)j * 2 + 1) * o.nb + (k2 * s + i2)) * o.nb + (k1 * s + i1);
+        X2[i] = c < nc ? cscaleb((double)o.sgn[off], xt[(size_t)o.dof[off] * r + c0 + c]) : make_double2(0, 0);
+    }
+    __syncthreads();
+    const double *Mpu = o.Mp + (size_t)k1 * Q1 * RL, *Mqu = o.Mq + (size_t)k1 * Q1 * RL, *Mdu = o.Mdp + (size_t)k1 * Q1 * RL;
+    const double *Mpv = o.Mp + (size_t)k2 * Q1 * RL, *Mqv = o.Mq + (size_t)k2 * Q1 * RL, *Mdv = o.Mdp + (size_t)k2 * Q1 * RL;
+    for (int i = threadIdx.x; i < w2a * Q1 * kRB; i += blockDim.x) {
+        const int c = i % kRB, t = i / kRB, i2 = t / Q1, m1 = t % Q1;
+        double2 z = make_double2(0, 0), zd = make_double2(0, 0);
+        for (int i1 = 0; i1 < w1a; ++i1) {
+            const double2 v = X1[(i2 * w1a + i1) * kRB + c];
+            z = caddb(z, cscaleb(Mpu[m1 * RL + i1], v));
+            zd = caddb(zd, cscaleb(Mdu[m1 * RL + i1], v));
+        }
+        Z1[i] = z;
+        Zd[i] = zd;
+    }
+    for (int i = threadIdx.x; i < w2b * Q1 * kRB; i += blockDim.x) {
+        const int c = i % kRB, t = i / kRB, i2 = t / Q1, m1 = t % Q1;
+        double2 z = make_double2(0, 0);
+        for (int i1 = 0; i1 < w1b; ++i1) z = caddb(z, cscaleb(Mqu[m1 * RL + i1], X2[(i2 * w1b + i1) * kRB + c]));
+        Z2[i] = z;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < Q * kRB; i += blockDim.x) {
+        const int c = i % kRB, mm = i / kRB, m2 = mm / Q1, m1 = mm % Q1;
+        if (c >= nc) continue;
+        double2 s1 = make_double2(0, 0), s2v = make_double2(0, 0), d = make_double2(0, 0);
+        for (int i2 = 0; i2 < w2a; ++i2) {
+            s1 = caddb(s1, cscaleb(Mqv[m2 * RL + i2], Z1[(i2 * Q1 + m1) * kRB + c]));
+            d = caddb(d, cscaleb(Mqv[m2 * RL + i2], Zd[(i2 * Q1 + m1) * kRB + c]));
+        }
+        for (int i2 = 0; i2 < w2b; ++i2) {
+            s2v = caddb(s2v, cscaleb(Mpv[m2 * RL + i2], Z2[(i2 * Q1 + m1) * kRB + c]));
+            d = caddb(d, cscaleb(Mdv[m2 * RL + i2], Z2[(i2 * Q1 + m1) * kRB + c]));
+        }
+        const size_t col = c0 + c;
+        double2 *M = mom + (size_t)gc * 3 * Q * r;
+        M[((size_t)0 * Q + mm) * r + col] = s1;
+        M[((size_t)1 * Q + mm) * r + col] = s2v;
+        M[((size_t)2 * Q + mm) * r + col] = d;
+        const double *T = o.nodeT + (size_t)gc * 6 * Q;
+        double2 *S = src + (size_t)gc * 4 * Q * r;
+        for (int k = 0; k < 3; ++k)
+            S[((size_t)k * Q + mm) * r + col] = caddb(cscaleb(T[k * Q + mm], s1), cscaleb(T[(3 + k) * Q + mm], s2v));
+        S[((size_t)3 * Q + mm) * r + col] = d;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// M2M, kRB columns
+// ---------------------------------------------------------------------------
+template <int kRB>
+__global__ __launch_bounds__(256) void k_m2m_b(DevOp o, int lvl, int r, double2 *mom, double2 *src)
+{
+    extern __shared__ double2 sm2[];
+    const int id = blockIdx.x;
+    const int c0 = blockIdx.y * kRB, nc = min(kRB, r - c0);
+    const int S = 1 << lvl, Q1 = o.Q1, Q = o.Q;
+    const int j = id / (S * S), rr = id % (S * S), k2 = rr / S, k1 = rr % S;
+    const int gc = (int)o.lvl_off[lvl] + id;
+    double2 *acc = sm2;               // [3 fields][Q][kRB]
+    double2 *W = acc + 3 * Q * kRB;   // [Q1 (n2)][Q1 (m1)][kRB], one field of one child at a time
+    for (int i = threadIdx.x; i < 3 * Q * kRB; i += blockDim.x) acc[i] = make_double2(0, 0);
+    for (int ch = 0; ch < 4; ++ch) {
+        const int c1 = ch & 1, c2 = ch >> 1;
+        const int cgc = (int)o.lvl_off[lvl + 1] + (j * 2 * S + 2 * k2 + c2) * 2 * S + 2 * k1 + c1;
+        const double2 *cm = mom + (size_t)cgc * 3 * Q * r;
+        const double *Tu = c1 ? o.T1 : o.T0, *Tv = c2 ? o.T1 : o.T0;
+        for (int f = 0; f < 3; ++f) {
+            __syncthreads();
+            for (int i = threadIdx.x; i < Q * kRB; i += blockDim.x) {
+                const int c = i % kRB, nm = i / kRB, n2 = nm / Q1, m1 = nm % Q1;
+                double2 z = make_double2(0, 0);
+                if (c < nc)
+                    for (int n1 = 0; n1 < Q1; ++n1)
+                        z = caddb(z, cscaleb(Tu[n1 * Q1 + m1], cm[((size_t)f * Q + n2 * Q1 + n1) * r + c0 + c]));
+                W[i] = z;
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < Q * kRB; i += blockDim.x) {
+                const int c = i % kRB, mm = i / kRB, m2 = mm / Q1, m1 = mm % Q1;
+                double2 z = acc[(f * Q + mm) * kRB + c];
+                for (int n2 = 0; n2 < Q1; ++n2) z = caddb(z, cscaleb(Tv[n2 * Q1 + m2], W[(n2 * Q1 + m1) * kRB + c]));
+                acc[(f * Q + mm) * kRB + c] = z;
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < Q * kRB; i += blockDim.x) {
+        const int c = i % kRB, mm = i / kRB;
+        if (c >= nc) continue;
+        const size_t col = c0 + c;
+        const double2 s1 = acc[(0 * Q + mm) * kRB + c], s2v = acc[(1 * Q + mm) * kRB + c], d = acc[(2 * Q + mm) * kRB + c];
+        double2 *M = mom + (size_t)gc * 3 * Q * r;
+        M[((size_t)0 * Q + mm) * r + col] = s1;
+        M[((size_t)1 * Q + mm) * r + col] = s2v;
+        M[((size_t)2 * Q + mm) * r + col] = d;
+        const double *T = o.nodeT + (size_t)gc * 6 * Q;
+        double2 *Sv = src + (size_t)gc * 4 * Q * r;
+        for (int k = 0; k < 3; ++k)
+            Sv[((size_t)k * Q + mm) * r + col] = caddb(cscaleb(T[k * Q + mm], s1), cscaleb(T[(3 + k) * Q + mm], s2v));
+        Sv[((size_t)3 * Q + mm) * r + col] = d;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// M2L, kRB columns: one kernel value per node pair serves 4 kRB products, and
+// every source value read from LDS serves kNTB target nodes of the thread.
+// Threads: kNTB target nodes x a part of the source nodes; parts summed in LDS,
+// one field at a time.
+// ---------------------------------------------------------------------------
+constexpr int kM2LThreadsB = 256;
+constexpr int kNTB = 3;
+
+template <int kRB>
+__global__ __launch_bounds__(kM2LThreadsB) void k_m2l_b(DevOp o, int r, const M2LWork *work, const int32_t *partner,
+                                                         const double2 *src, double2 *part)
+{
+    extern __shared__ double smd[];
+    const M2LWork wk = work[blockIdx.x];
+    const int c0 = blockIdx.y * kRB, nc = min(kRB, r - c0);
+    const int Q = o.Q;
+    const int TPG = (Q + kNTB - 1) / kNTB;
+    const int S = max(1, min(kM2LThreadsB / TPG, Q));
+    const int SP = (Q + S - 1) / S;
+    const int tid = threadIdx.x;
+    const int mt = tid % TPG, sp = tid / TPG;
+    const bool active = sp < S;
+    double *sX = smd;                                          // [3][Q]
+    double2 *sV = reinterpret_cast<double2 *>(sX + 3 * Q);     // [4][Q][kRB]
+    double2 *red = reinterpret_cast<double2 *>(smd);           // [S][Q][kRB] (one field at a time)
+    const double *Xt = o.nodeX + (size_t)wk.tgt * 3 * Q;
+    double xt[kNTB][3];
+    bool val[kNTB];
+#pragma unroll
+    for (int t = 0; t < kNTB; ++t) {
+        const int mm = mt + t * TPG;
+        val[t] = active && mm < Q;
+        const int mc = val[t] ? mm : 0;
+        xt[t][0] = Xt[mc];
+        xt[t][1] = Xt[Q + mc];
+        xt[t][2] = Xt[2 * Q + mc];
+    }
+    double2 acc[kNTB][4][kRB];
+#pragma unroll
+    for (int t = 0; t < kNTB; ++t)
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+#pragma unroll
+            for (int c = 0; c < kRB; ++c) acc[t][f][c] = make_double2(0, 0);
+    const int mb = min(Q, sp * SP), me = min(Q, mb + SP);
+    for (int kp = wk.beg; kp < wk.end; ++kp) {
+        const int sc = partner[kp];
+        __syncthreads();
+        const double *Xs = o.nodeX + (size_t)sc * 3 * Q;
+        const double2 *Vs = src + (size_t)sc * 4 * Q * r;
+        for (int i = tid; i < 3 * Q; i += kM2LThreadsB) sX[i] = Xs[i];
+        for (int i = tid; i < 4 * Q * kRB; i += kM2LThreadsB) {
+            const int c = i % kRB, fm = i / kRB;
+            sV[i] = c < nc ? Vs[(size_t)fm * r + c0 + c] : make_double2(0, 0);
+        }
+        __syncthreads();
+        if (active) {
+            for (int ms = mb; ms < me; ++ms) {
+                const double x0 = sX[ms], x1 = sX[Q + ms], x2 = sX[2 * Q + ms];
+                double2 G[kNTB];
+#pragma unroll
+                for (int t = 0; t < kNTB; ++t) {
+                    const double d0 = xt[t][0] - x0, d1 = xt[t][1] - x1, d2 = xt[t][2] - x2;
+                    G[t] = helmholtz_r2b(o.kappa, fma(d0, d0, fma(d1, d1, d2 * d2)));
+                }
+#pragma unroll
+                for (int f = 0; f < 4; ++f) {
+                    const double2 *vf = sV + ((size_t)f * Q + ms) * kRB;
+#pragma unroll
+                    for (int c = 0; c < kRB; ++c) {
+                        const double2 v = vf[c];
+#pragma unroll
+                        for (int t = 0; t < kNTB; ++t) acc[t][f][c] = caddb(acc[t][f][c], cmulb(G[t], v));
+                    }
+                }
+            }
+        }
+    }
+    for (int f = 0; f < 4; ++f) {
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < kNTB; ++t)
+            if (val[t])
+#pragma unroll
+                for (int c = 0; c < kRB; ++c) red[((size_t)sp * Q + mt + t * TPG) * kRB + c] = acc[t][f][c];
+        __syncthreads();
+        for (int i = tid; i < Q * kRB; i += kM2LThreadsB) {
+            const int c = i % kRB, mm = i / kRB;
+            if (c >= nc) continue;
+            double2 v = make_double2(0, 0);
+            for (int q2 = 0; q2 < S; ++q2) v = caddb(v, red[((size_t)q2 * Q + mm) * kRB + c]);
+            part[(((size_t)blockIdx.x * 4 + f) * Q + mm) * r + c0 + c] = v;
+        }
+    }
+}
+
+__global__ void k_m2l_reduce_b(DevOp o, int r, const int32_t *wrk_of_tgt, const double2 *part, double2 *loc)
+{
+    const int gc = blockIdx.x, Q = o.Q;
+    const int b = wrk_of_tgt[gc], e = wrk_of_tgt[gc + 1];
+    const double ik2 = 1.0 / (o.kappa * o.kappa);
+    for (int t = threadIdx.x; t < Q * r; t += blockDim.x) {
+        const int mm = t / r, c = t % r;
+        double2 u[4] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
+        for (int w = b; w < e; ++w)
+            for (int k = 0; k < 4; ++k) u[k] = caddb(u[k], part[(((size_t)w * 4 + k) * Q + mm) * r + c]);
+        const double *T = o.nodeT + (size_t)gc * 6 * Q;
+        double2 t1 = make_double2(0, 0), t2 = make_double2(0, 0);
+        for (int k = 0; k < 3; ++k) {
+            t1 = caddb(t1, cscaleb(T[k * Q + mm], u[k]));
+            t2 = caddb(t2, cscaleb(T[(3 + k) * Q + mm], u[k]));
+        }
+        double2 *L = loc + (size_t)gc * 3 * Q * r;
+        L[((size_t)0 * Q + mm) * r + c] = t1;
+        L[((size_t)1 * Q + mm) * r + c] = t2;
+        L[((size_t)2 * Q + mm) * r + c] = cscaleb(-ik2, u[3]);
+    }
+}
+
+template <int kRB>
+__global__ __launch_bounds__(256) void k_l2l_b(DevOp o, int lvl, int r, double2 *loc)
+{
+    extern __shared__ double2 sm2[];
+    const int id = blockIdx.x;
+    const int c0 = blockIdx.y * kRB, nc = min(kRB, r - c0);
+    const int S = 1 << lvl, Q1 = o.Q1, Q = o.Q;
+    const int j = id / (S * S), rr = id % (S * S), k2 = rr / S, k1 = rr % S;
+    const int gc = (int)o.lvl_off[lvl] + id;
+    const int Sp = S / 2;
+    const int pgc = (int)o.lvl_off[lvl - 1] + (j * Sp + k2 / 2) * Sp + k1 / 2;
+    const int c1 = k1 & 1, c2 = k2 & 1;
+    const double *Tu = c1 ? o.T1 : o.T0, *Tv = c2 ? o.T1 : o.T0;
+    const double2 *par = loc + (size_t)pgc * 3 * Q * r;
+    double2 *W = sm2;   // [3][Q1 (m2)][Q1 (n1)][kRB]
+    for (int i = threadIdx.x; i < 3 * Q * kRB; i += blockDim.x) {
+        const int c = i % kRB, t = i / kRB, f = t / Q, rem = t % Q, m2 = rem / Q1, n1 = rem % Q1;
+        double2 z = make_double2(0, 0);
+        if (c < nc)
+            for (int m1 = 0; m1 < Q1; ++m1)
+                z = caddb(z, cscaleb(Tu[n1 * Q1 + m1], par[((size_t)f * Q + m2 * Q1 + m1) * r + c0 + c]));
+        W[i] = z;
+    }
+    __syncthreads();
+    double2 *chd = loc + (size_t)gc * 3 * Q * r;
+    for (int i = threadIdx.x; i < 3 * Q * kRB; i += blockDim.x) {
+        const int c = i % kRB, t = i / kRB, f = t / Q, rem = t % Q, n2 = rem / Q1, n1 = rem % Q1;
+        if (c >= nc) continue;
+        double2 z = chd[((size_t)f * Q + rem) * r + c0 + c];
+        for (int m2 = 0; m2 < Q1; ++m2) z = caddb(z, cscaleb(Tv[n2 * Q1 + m2], W[((f * Q) + m2 * Q1 + n1) * kRB + c]));
+        chd[((size_t)f * Q + rem) * r + c0 + c] = z;
+    }
+}
+
+template <int kRB>
+__global__ __launch_bounds__(256) void k_l2p_leaf_b(DevOp o, int r, const double2 *loc, double2 *ybuf)
+{
+    extern __shared__ double2 sm2[];
+    const int id = blockIdx.x;
+    const int c0 = blockIdx.y * kRB, nc = min(kRB, r - c0);
+    const int SL = o.SL, s = o.s, p = o.p, Q1 = o.Q1, Q = o.Q, RL = o.rowlen;
+    const int rr = id % (SL * SL), k2 = rr / SL, k1 = rr % SL;
+    const int gc = (int)o.lvl_off[o.L] + id;
+    const double2 *t = loc + (size_t)gc * 3 * Q * r;
+    const double *Mpu = o.Mp + (size_t)k1 * Q1 * RL, *Mqu = o.Mq + (size_t)k1 * Q1 * RL, *Mdu = o.Mdp + (size_t)k1 * Q1 * RL;
+    const double *Mpv = o.Mp + (size_t)k2 * Q1 * RL, *Mqv = o.Mq + (size_t)k2 * Q1 * RL, *Mdv = o.Mdp + (size_t)k2 * Q1 * RL;
+    double2 *W0 = sm2;                    // [Q1][RL][kRB]
+    double2 *W1 = W0 + Q1 * RL * kRB;
+    double2 *W1d = W1 + Q1 * RL * kRB;
+    const int w1a = s + p, w1b = s + p - 1;
+    for (int i = threadIdx.x; i < Q1 * RL * kRB; i += blockDim.x) {
+        const int c = i % kRB, tt = i / kRB, m2 = tt / RL, i1 = tt % RL;
+        double2 a = make_double2(0, 0), b = make_double2(0, 0), bd = make_double2(0, 0);
+        if (c < nc)
+            for (int m1 = 0; m1 < Q1; ++m1) {
+                const size_t col = c0 + c;
+                const double2 f1 = t[((size_t)0 * Q + m2 * Q1 + m1) * r + col];
+                const double2 f2 = t[((size_t)1 * Q + m2 * Q1 + m1) * r + col];
+                const double2 fd = t[((size_t)2 * Q + m2 * Q1 + m1) * r + col];
+                if (i1 < w1a) a = caddb(a, caddb(cscaleb(Mpu[m1 * RL + i1], f1), cscaleb(Mdu[m1 * RL + i1], fd)));
+                if (i1 < w1b) {
+                    b = caddb(b, cscaleb(Mqu[m1 * RL + i1], f2));
+                    bd = caddb(bd, cscaleb(Mqu[m1 * RL + i1], fd));
+                }
+            }
+        W0[i] = a;
+        W1[i] = b;
+        W1d[i] = bd;
+    }
+    __syncthreads();
+    double2 *Y = ybuf + (size_t)id * 2 * RL * RL * r;
+    for (int i = threadIdx.x; i < 2 * RL * RL * kRB; i += blockDim.x) {
+        const int c = i % kRB, tt = i / kRB, ch = tt / (RL * RL), rem = tt % (RL * RL), i2 = rem / RL, i1 = rem % RL;
+        if (c >= nc) continue;
+        double2 v = make_double2(0, 0);
+        if (ch == 0 && i2 < s + p - 1 && i1 < w1a) {
+            for (int m2 = 0; m2 < Q1; ++m2) v = caddb(v, cscaleb(Mqv[m2 * RL + i2], W0[(m2 * RL + i1) * kRB + c]));
+        } else if (ch == 1 && i2 < s + p && i1 < w1b) {
+            for (int m2 = 0; m2 < Q1; ++m2)
+                v = caddb(v, caddb(cscaleb(Mpv[m2 * RL + i2], W1[(m2 * RL + i1) * kRB + c]),
+                                   cscaleb(Mdv[m2 * RL + i2], W1d[(m2 * RL + i1) * kRB + c])));
+        }
+        Y[(size_t)tt * r + c0 + c] = v;
+    }
+}
+
+__global__ void k_l2p_gather_b(DevOp o, int r, const double2 *ybuf, double2 *yt)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)o.N * r) return;
+    const int i = (int)(t / r), col = (int)(t % r);
+    const int s = o.s, p = o.p, SL = o.SL, n = o.n, RL = o.rowlen;
+    double2 acc = make_double2(0, 0);
+    for (int c = 0; c < 2; ++c) {
+        const int32_t *in = o.inc + ((size_t)i * 2 + c) * 5;
+        const int j = in[0];
+        if (j < 0) continue;
+        const int a = in[1], i1 = in[2], i2 = in[3];
+        const double sg = (double)in[4];
+        const int du = (a == 0) ? p : p - 1, dv = (a == 0) ? p - 1 : p;
+        const int k1b = max(0, i1 - du) / s, k1e = min(n - 1, i1) / s;
+        const int k2b = max(0, i2 - dv) / s, k2e = min(n - 1, i2) / s;
+        for (int k2 = k2b; k2 <= k2e; ++k2)
+            for (int k1 = k1b; k1 <= k1e; ++k1) {
+                const int leaf = (j * SL + k2) * SL + k1;
+                const double2 v = ybuf[((((size_t)leaf * 2 + a) * RL + (i2 - k2 * s)) * RL + (i1 - k1 * s)) * r + col];
+                acc = caddb(acc, cscaleb(sg, v));
+            }
+    }
+    yt[t] = caddb(yt[t], acc);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// batched apply: y = A x for r columns (x, y: [r][N] device); xt, yt: [N][r]
+// scratch; the operator's batched workspaces must hold r columns.
+// Each kernel takes the largest column chunk (8, 4, 2, 1) whose LDS fits 64 KB.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kLdsMax = 64 * 1024;
+
+int pick_rb(size_t bytes_per_col, size_t fixed = 0)
+{
+    for (int rb = kRBMax; rb > 1; rb /= 2)
+        if (fixed + bytes_per_col * rb <= kLdsMax) return rb;
+    return 1;
+}
+}  // namespace
+
+#define IGE_RB_SWITCH(rb, KERNEL, grid, block, shm, stream, ...)                                             \
+    switch (rb) {                                                                                            \
+        case 8: hipLaunchKernelGGL(KERNEL<8>, grid, block, shm, stream, __VA_ARGS__); break;                \
+        case 4: hipLaunchKernelGGL(KERNEL<4>, grid, block, shm, stream, __VA_ARGS__); break;                \
+        case 2: hipLaunchKernelGGL(KERNEL<2>, grid, block, shm, stream, __VA_ARGS__); break;                \
+        default: hipLaunchKernelGGL(KERNEL<1>, grid, block, shm, stream, __VA_ARGS__); break;               \
+    }                                                                                                        \
+    IGE_HIP(hipGetLastError())
+
+void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, double2 *yt, hipEvent_t *ev)
+{
+    const DevOp &o = op->view;
+    hipStream_t s = op->ctx->stream;
+    auto mark = [&](int i) {
+        if (ev) IGE_HIP(hipEventRecord(ev[i], s));
+    };
+    const int64_t N = o.N;
+    const int64_t tot = N * r;
+    auto chunks = [&](int rb) { return (r + rb - 1) / rb; };
+    hipLaunchKernelGGL(k_to_rows, dim3((tot + 255) / 256), dim3(256), 0, s, N, r, x, xt);
+    IGE_HIP(hipGetLastError());
+    const bool far = !op->work.empty();
+    mark(0);
+    if (far) {
+        const int nleaf = o.P * o.SL * o.SL;
+        const size_t w1a = o.s + o.p;
+        {
+            const size_t per = sizeof(double2) * (2 * w1a * w1a + 3 * w1a * o.Q1);
+            const int rb = pick_rb(per);
+            IGE_RB_SWITCH(rb, k_p2m_b, dim3(nleaf, chunks(rb)), dim3(256), per * rb, s, o, r, xt, op->d_bmom.p,
+                          op->d_bsrc.p);
+        }
+        mark(1);
+        {
+            const size_t per = sizeof(double2) * 4 * o.Q;
+            const int rb = pick_rb(per);
+            for (int lvl = o.L - 1; lvl >= 0; --lvl) {
+                IGE_RB_SWITCH(rb, k_m2m_b, dim3(o.P << (2 * lvl), chunks(rb)), dim3(256), per * rb, s, o, lvl, r,
+                              op->d_bmom.p, op->d_bsrc.p);
+            }
+        }
+        mark(2);
+        {
+            const int TPG = (o.Q + kNTB - 1) / kNTB;
+            const int S = std::max(1, std::min(kM2LThreadsB / TPG, o.Q));
+            const size_t fixed = sizeof(double) * 3 * o.Q;
+            const size_t per = std::max(sizeof(double2) * 4 * o.Q, sizeof(double2) * (size_t)S * o.Q);
+            const int rb = std::min(4, pick_rb(per, fixed));   // registers: 3 targets x 4 fields x rb columns
+            IGE_RB_SWITCH(rb, k_m2l_b, dim3(op->work.size(), chunks(rb)), dim3(kM2LThreadsB), fixed + per * rb, s, o,
+                          r, op->d_work.p, op->d_partner.p, op->d_bsrc.p, op->d_bpart.p);
+        }
+        mark(3);
+        hipLaunchKernelGGL(k_m2l_reduce_b, dim3(op->NC), dim3(256), 0, s, o, r, op->d_wrk_of_tgt.p, op->d_bpart.p,
+                           op->d_bloc.p);
+        IGE_HIP(hipGetLastError());
+        mark(4);
+        {
+            const size_t per = sizeof(double2) * 3 * o.Q;
+            const int rb = pick_rb(per);
+            for (int lvl = 1; lvl <= o.L; ++lvl) {
+                IGE_RB_SWITCH(rb, k_l2l_b, dim3(o.P << (2 * lvl), chunks(rb)), dim3(256), per * rb, s, o, lvl, r,
+                              op->d_bloc.p);
+            }
+        }
+        mark(5);
+        {
+            const size_t per = sizeof(double2) * 3 * (size_t)o.Q1 * o.rowlen;
+            const int rb = pick_rb(per);
+            IGE_RB_SWITCH(rb, k_l2p_leaf_b, dim3(nleaf, chunks(rb)), dim3(256), per * rb, s, o, r, op->d_bloc.p,
+                          op->d_bybuf.p);
+        }
+        mark(6);
+    } else {
+        for (int i = 1; i <= 6; ++i) mark(i);
+    }
+    const int rows_per_block = 256 / kWave;
+    mark(7);
+    IGE_RB_SWITCH(8, k_spmm, dim3((N + rows_per_block - 1) / rows_per_block, chunks(8)), dim3(256), 0, s, o, r, xt,
+                  yt);
+    mark(8);
+    mark(9);
+    if (far) {
+        hipLaunchKernelGGL(k_l2p_gather_b, dim3((tot + 255) / 256), dim3(256), 0, s, o, r, op->d_bybuf.p, yt);
+        IGE_HIP(hipGetLastError());
+    }
+    mark(10);
+    hipLaunchKernelGGL(k_to_cols, dim3((tot + 255) / 256), dim3(256), 0, s, N, r, yt, y);
+    IGE_HIP(hipGetLastError());
+}
+
+}  // namespace ige

@@ -112,6 +112,9 @@ struct ige_op_s {
     ige::DBuf<double2> d_loc;    // [NC][3][Q]   t^1, t^2, t^d
     ige::DBuf<double2> d_ybuf;   // [leaves][2][rowlen][rowlen] L2P results per leaf
     ige::DBuf<double2> d_x, d_y; // staging for host pointers
+    // batched-apply workspaces (r columns, column index innermost)
+    int bcap = 0;
+    ige::DBuf<double2> d_bmom, d_bsrc, d_bpart, d_bloc, d_bybuf, d_bxt, d_byt, d_bx, d_by;
     // GMRES workspace
     ige::DBuf<double2> d_V, d_w, d_r;
     ige::DBuf<double2> d_h;
@@ -144,6 +147,7 @@ void launch_gemv_sub(ige_op op, const double2 *V, int64_t ldv, int k, const doub
 void launch_axpby(ige_op op, int64_t n, double2 a, const double2 *x, double2 b, double2 *y);
 void launch_scale_copy(ige_op op, int64_t n, double2 a, const double2 *x, double2 *y);
 void launch_norm2(ige_op op, int64_t n, const double2 *x, double *out);
+void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, double2 *yt, hipEvent_t *ev);
 void launch_helmholtz_eval(hipStream_t s, int64_t n, double kappa, const double *r2, double2 *out);
 
 }  // namespace ige
