@@ -139,8 +139,18 @@ int ige_op_dofmap(ige_op op, int32_t *dof, int8_t *sgn);
  * cluster id on level l: patch*4^l + k2*2^l + k1.  Either pointer may be NULL. */
 int ige_op_partition(ige_op op, int32_t *far, int32_t *near);
 
-/* y = A x for r right-hand sides (A the compressed operator).  x, y: N*r complex. */
+enum { IGE_F64 = 0, IGE_F32 = 1 };
+
+/* y = A x for r right-hand sides (A the compressed operator).  x, y: N*r complex.
+ * r > 1 runs the batched kernels (columns in chunks, every kernel value and matrix
+ * entry read or computed once per chunk). */
 int ige_apply(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind);
+
+/* As ige_apply, with the coupling stage (interpolated-kernel evaluation and its
+ * products, a5) in the given precision: IGE_F64, or IGE_F32 (FP32 kernel values
+ * and FP32 accumulation; relative error about kappa * diam * 2^-23 on the far
+ * field).  Near field, moments and transfers stay FP64. */
+int ige_apply_prec(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind, int coupling_prec);
 
 /* Stage profiling.  ige_op_set_profiling(op, 1) creates HIP events and clears the
  * record; every later single-column apply records its stage boundaries on the
@@ -164,29 +174,39 @@ int ige_op_stage_times(ige_op op, double *ms, int n);
 int ige_rhs_plane_wave(ige_op op, int r, const double *dir, const ige_c64 *pol, ige_c64 *f, int ptr_kind);
 
 typedef struct {
-    double tol;      /* stop at ||f - A x|| <= tol ||f|| (relative, x0 as passed) */
+    double tol;      /* stop at ||f - A x|| <= tol ||f|| (relative, FP64 operator, x0 as passed) */
     int restart;     /* Krylov basis size before restart (>= 1) */
-    int maxit;       /* total iteration cap */
+    int maxit;       /* total iteration cap (inner iterations summed over refinement steps) */
+    int refine;      /* 0: GMRES on the FP64 operator; 1: iterative refinement -- FP64
+                        residual f - A x, inner GMRES on the inner_prec operator for the
+                        correction to inner_tol, x += correction, repeated */
+    double inner_tol;
+    int inner_prec;  /* IGE_F64 or IGE_F32 coupling for the inner solves */
 } ige_solve_opts;
 
 typedef struct {
-    int iters;
-    double relres;   /* true relative residual ||f - A x|| / ||f|| at exit */
-    double seconds;
+    int iters;       /* GMRES iterations (all refinement steps) */
+    int outer;       /* refinement steps (0 without refinement) */
+    double relres;   /* true relative residual ||f - A x|| / ||f|| (FP64 operator) at exit */
+    double seconds;  /* wall time of the whole call */
 } ige_solve_stats;
 
-/* Solve A x = f with restarted complex GMRES (Arnoldi with classical Gram-Schmidt
- * and reorthogonalisation, Givens rotations), per right-hand side.  x holds the
- * initial guess on entry.  stats: one entry per right-hand side (may be NULL).
- * IGE_ENOTCONV if some column stopped at maxit. */
+/* Solve A x = f with restarted complex GMRES (Sec. 5: no preconditioner), all r
+ * right-hand sides at once: every iteration applies the operator to the r current
+ * Krylov vectors through the batched kernels; each column keeps its own Krylov
+ * basis (classical Gram-Schmidt with one reorthogonalisation, on the device), its
+ * own Givens rotations (host) and stops on its own relative residual.
+ * x holds the initial guesses on entry.  stats: one entry per right-hand side (may
+ * be NULL).  IGE_ENOTCONV if some column stopped at maxit.  Device memory:
+ * (restart + 1) * r * N complex for the bases. */
 int ige_solve(ige_op op, int r, const ige_c64 *f, ige_c64 *x, int ptr_kind, const ige_solve_opts *opts,
               ige_solve_stats *stats);
 
 /* Diagnostic: evaluate on the context's device the Helmholtz kernel
  * G_k(r) = e^{ikr}/(4 pi r) (Sec. 2.2, eq. (eq:HelmholtzGreen)) exactly as the
- * coupling stage does, from squared distances r2[n] > 0 (host memory) into
- * out[n] (host memory).  Synchronous. */
-int ige_helmholtz_eval(ige_ctx ctx, int64_t n, double kappa, const double *r2, ige_c64 *out);
+ * coupling stage does in precision prec (IGE_F64 / IGE_F32), from squared
+ * distances r2[n] > 0 (host memory) into out[n] (host memory).  Synchronous. */
+int ige_helmholtz_eval(ige_ctx ctx, int64_t n, double kappa, const double *r2, ige_c64 *out, int prec);
 
 #ifdef __cplusplus
 }

@@ -40,12 +40,16 @@ class ige_op_info_t(C.Structure):
                 ("assemble_ms", C.c_double)]
 
 
+IGE_F64, IGE_F32 = 0, 1
+
+
 class ige_solve_opts(C.Structure):
-    _fields_ = [("tol", C.c_double), ("restart", C.c_int), ("maxit", C.c_int)]
+    _fields_ = [("tol", C.c_double), ("restart", C.c_int), ("maxit", C.c_int), ("refine", C.c_int),
+                ("inner_tol", C.c_double), ("inner_prec", C.c_int)]
 
 
 class ige_solve_stats(C.Structure):
-    _fields_ = [("iters", C.c_int), ("relres", C.c_double), ("seconds", C.c_double)]
+    _fields_ = [("iters", C.c_int), ("outer", C.c_int), ("relres", C.c_double), ("seconds", C.c_double)]
 
 
 # One HIP runtime per process: torch ships its own libamdhip64 (same soname);
@@ -74,12 +78,13 @@ _SIGS = {
     "ige_op_dofmap": (C.c_int, [_V, _V, _V]),
     "ige_op_partition": (C.c_int, [_V, _V, _V]),
     "ige_apply": (C.c_int, [_V, C.c_int, _V, _V, C.c_int]),
+    "ige_apply_prec": (C.c_int, [_V, C.c_int, _V, _V, C.c_int, C.c_int]),
     "ige_op_set_profiling": (C.c_int, [_V, C.c_int]),
     "ige_op_set_overlap": (C.c_int, [_V, C.c_int]),
     "ige_op_stage_times": (C.c_int, [_V, _V, C.c_int]),
     "ige_rhs_plane_wave": (C.c_int, [_V, C.c_int, _V, _V, _V, C.c_int]),
     "ige_solve": (C.c_int, [_V, C.c_int, _V, _V, C.c_int, C.POINTER(ige_solve_opts), _V]),
-    "ige_helmholtz_eval": (C.c_int, [_V, C.c_int64, C.c_double, _V, _V]),
+    "ige_helmholtz_eval": (C.c_int, [_V, C.c_int64, C.c_double, _V, _V, C.c_int]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -172,6 +177,10 @@ def ige_apply(op, r, x, y, ptr_kind):
     _check(_lib.ige_apply(op, r, _ptr(x), _ptr(y), ptr_kind))
 
 
+def ige_apply_prec(op, r, x, y, ptr_kind, prec):
+    _check(_lib.ige_apply_prec(op, r, _ptr(x), _ptr(y), ptr_kind, prec))
+
+
 def ige_op_set_profiling(op, on):
     _check(_lib.ige_op_set_profiling(op, int(on)))
 
@@ -200,10 +209,10 @@ def ige_solve(op, r, f, x, ptr_kind, opts: ige_solve_opts, stats=None):
     return rc, arr
 
 
-def ige_helmholtz_eval(ctx, kappa, r2):
+def ige_helmholtz_eval(ctx, kappa, r2, prec=IGE_F64):
     r2 = np.ascontiguousarray(r2, np.float64)
     out = np.zeros(len(r2), np.complex128)
-    _check(_lib.ige_helmholtz_eval(ctx, len(r2), kappa, _ptr(r2), _ptr(out)))
+    _check(_lib.ige_helmholtz_eval(ctx, len(r2), kappa, _ptr(r2), _ptr(out), prec))
     return out
 
 
@@ -289,7 +298,7 @@ class Operator:
         ige_op_partition(self.h, far, near)
         return {"L": int(self.info.leaf_level), "far": far, "near": near}
 
-    def apply(self, x, y=None):
+    def apply(self, x, y=None, prec=IGE_F64):
         """y = A x; x numpy (host) or torch (device) of shape (N,) or (r, N)."""
         r = 1 if x.ndim == 1 else x.shape[0]
         if y is None:
@@ -297,7 +306,7 @@ class Operator:
                 y = np.zeros_like(x, dtype=np.complex128)
             else:
                 y = x.new_zeros(x.shape)
-        ige_apply(self.h, r, x, y, _kind(x))
+        ige_apply_prec(self.h, r, x, y, _kind(x), prec)
         return y
 
     def rhs_plane_wave(self, dirs, pols, out=None):
@@ -308,13 +317,15 @@ class Operator:
         ige_rhs_plane_wave(self.h, r, dirs, np.atleast_2d(pols), out, _kind(out))
         return out
 
-    def solve(self, f, x0=None, tol=1e-8, restart=1500, maxit=10000):
+    def solve(self, f, x0=None, tol=1e-8, restart=1500, maxit=10000, refine=False, inner_tol=1e-4,
+              inner_prec=IGE_F32):
+        """GMRES (all right-hand sides at once); returns (x, [(iters, outer, relres, seconds)], rc)."""
         r = 1 if f.ndim == 1 else f.shape[0]
         if x0 is None:
             x0 = np.zeros_like(f) if isinstance(f, np.ndarray) else f.new_zeros(f.shape)
-        opts = ige_solve_opts(tol, restart, maxit)
+        opts = ige_solve_opts(tol, restart, maxit, int(refine), inner_tol, inner_prec)
         rc, stats = ige_solve(self.h, r, f, x0, _kind(f), opts)
-        return x0, [(s.iters, s.relres, s.seconds) for s in stats], rc
+        return x0, [(s.iters, s.outer, s.relres, s.seconds) for s in stats], rc
 
     def set_profiling(self, on=True):
         ige_op_set_profiling(self.h, on)

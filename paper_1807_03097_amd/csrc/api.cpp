@@ -47,7 +47,7 @@ std::complex<double> cz(double2 a) { return {a.x, a.y}; }
 // the far-field pipeline (arithmetic bound) runs on the context stream; the L2P
 // gather joins both.  With profiling on, stage boundaries are recorded into one of
 // kProfSlots event sets on the stream each stage runs on (no host sync).
-void apply_one(ige_op op, const double2 *x, double2 *y)
+void apply_one(ige_op op, const double2 *x, double2 *y, int prec = IGE_F64)
 {
     hipStream_t s = op->ctx->stream, s2 = op->aux;
     const bool prof = op->profiling;
@@ -64,7 +64,7 @@ void apply_one(ige_op op, const double2 *x, double2 *y)
             mark(1, s);
             ige::launch_m2m(op);
             mark(2, s);
-            ige::launch_m2l(op);
+            ige::launch_m2l(op, prec);
             mark(3, s);
             ige::launch_m2l_reduce(op);
             mark(4, s);
@@ -101,7 +101,7 @@ void apply_one(ige_op op, const double2 *x, double2 *y)
     ige::launch_spmv(op, x, y, s2);
     mark(8, s2);
     IGE_HIP(hipEventRecord(op->ev_join, s2));
-    ige::launch_m2l(op);
+    ige::launch_m2l(op, prec);
     mark(3, s);
     ige::launch_m2l_reduce(op);
     mark(4, s);
@@ -550,49 +550,56 @@ void ensure_batched(ige_op op, int r)
 }
 }  // namespace
 
-int ige_apply(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind)
+namespace {
+// y = A x for r device columns ([r][N]) in the given coupling precision
+void apply_dev(ige_op op, int r, const double2 *x, double2 *y, int prec)
+{
+    if (r == 1) {
+        apply_one(op, x, y, prec);
+        return;
+    }
+    ensure_batched(op, r);
+    hipEvent_t *ev = op->profiling
+                         ? op->prof_ev.data() + (size_t)(op->prof_count % ige_op_s::kProfSlots) * ige_op_s::kProfEv
+                         : nullptr;
+    ige::apply_batched(op, r, x, y, op->d_bxt.p, op->d_byt.p, ev, prec);
+    if (ev) op->prof_count++;
+}
+
+int apply_impl(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind, int prec)
 {
     return guard([&] {
         IGE_REQUIRE(op && x && y && r >= 1, "bad apply arguments");
         IGE_REQUIRE(op->assembled, "operator was planned, not assembled");
         IGE_REQUIRE(ptr_kind == IGE_HOST || ptr_kind == IGE_DEVICE, "bad ptr_kind");
+        IGE_REQUIRE(prec == IGE_F64 || prec == IGE_F32, "bad coupling precision");
         set_device(op->ctx);
         const int64_t N = op->D.N;
         hipStream_t s = op->ctx->stream;
-        if (r == 1) {
-            if (ptr_kind == IGE_HOST) {
-                ensure_staging(op);
-                IGE_HIP(hipMemcpyAsync(op->d_x.p, x, sizeof(double2) * N, hipMemcpyHostToDevice, s));
-                apply_one(op, op->d_x.p, op->d_y.p);
-                IGE_HIP(hipMemcpyAsync(y, op->d_y.p, sizeof(double2) * N, hipMemcpyDeviceToHost, s));
-                IGE_HIP(hipStreamSynchronize(s));
-            } else {
-                apply_one(op, reinterpret_cast<const double2 *>(x), reinterpret_cast<double2 *>(y));
-            }
+        if (ptr_kind == IGE_DEVICE) {
+            apply_dev(op, r, reinterpret_cast<const double2 *>(x), reinterpret_cast<double2 *>(y), prec);
             return;
         }
-        ensure_batched(op, r);
-        const double2 *xd = reinterpret_cast<const double2 *>(x);
-        double2 *yd = reinterpret_cast<double2 *>(y);
-        if (ptr_kind == IGE_HOST) {
-            if (op->d_bx.n < (size_t)N * r) {
-                op->d_bx.alloc((size_t)N * r);
-                op->d_by.alloc((size_t)N * r);
-            }
-            IGE_HIP(hipMemcpyAsync(op->d_bx.p, x, sizeof(double2) * N * r, hipMemcpyHostToDevice, s));
-            xd = op->d_bx.p;
-            yd = op->d_by.p;
+        if (op->d_bx.n < (size_t)N * r) {
+            op->d_bx.alloc((size_t)N * r);
+            op->d_by.alloc((size_t)N * r);
         }
-        hipEvent_t *ev = op->profiling
-                             ? op->prof_ev.data() + (size_t)(op->prof_count % ige_op_s::kProfSlots) * ige_op_s::kProfEv
-                             : nullptr;
-        ige::apply_batched(op, r, xd, yd, op->d_bxt.p, op->d_byt.p, ev);
-        if (ev) op->prof_count++;
-        if (ptr_kind == IGE_HOST) {
-            IGE_HIP(hipMemcpyAsync(y, op->d_by.p, sizeof(double2) * N * r, hipMemcpyDeviceToHost, s));
-            IGE_HIP(hipStreamSynchronize(s));
-        }
+        IGE_HIP(hipMemcpyAsync(op->d_bx.p, x, sizeof(double2) * N * r, hipMemcpyHostToDevice, s));
+        apply_dev(op, r, op->d_bx.p, op->d_by.p, prec);
+        IGE_HIP(hipMemcpyAsync(y, op->d_by.p, sizeof(double2) * N * r, hipMemcpyDeviceToHost, s));
+        IGE_HIP(hipStreamSynchronize(s));
     });
+}
+}  // namespace
+
+int ige_apply(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind)
+{
+    return apply_impl(op, r, x, y, ptr_kind, IGE_F64);
+}
+
+int ige_apply_prec(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind, int coupling_prec)
+{
+    return apply_impl(op, r, x, y, ptr_kind, coupling_prec);
 }
 
 int ige_rhs_plane_wave(ige_op op, int r, const double *dir, const ige_c64 *pol, ige_c64 *f, int ptr_kind)
@@ -621,6 +628,131 @@ int ige_rhs_plane_wave(ige_op op, int r, const double *dir, const ige_c64 *pol, 
     });
 }
 
+namespace {
+using Cx = std::complex<double>;
+
+struct GmresOut {
+    std::vector<int> iters;
+    std::vector<double> relres_est;
+};
+
+// Restarted GMRES for the r columns of B (device, [r][N]) on the operator in
+// precision prec, starting from X (device, [r][N], updated in place); each column
+// stops when its residual estimate reaches tol * ||B_c||.  it_cap: per-column
+// iteration budget.
+void gmres_batched(ige_op op, int r, const double2 *B, double2 *X, double tol, int m, const std::vector<int> &it_cap,
+                   int prec, GmresOut &out)
+{
+    const int64_t N = op->D.N;
+    hipStream_t s = op->ctx->stream;
+    const size_t need = (size_t)(m + 1) * r * N;
+    if (op->d_V.n < need) op->d_V.alloc(need);
+    if (op->d_w.n < (size_t)r * N) op->d_w.alloc((size_t)r * N);
+    const int hs = m + 2;
+    if (op->d_h.n < (size_t)r * hs) op->d_h.alloc((size_t)r * hs);
+    if (op->d_red.n < (size_t)r) op->d_red.alloc(r);
+    if (op->d_scal.n < (size_t)r) op->d_scal.alloc(r);
+    double2 *V = op->d_V.p, *W = op->d_w.p;
+    auto norms = [&](const double2 *v) {
+        std::vector<double> h(r);
+        ige::launch_norm2_b(op, r, v, op->d_red.p);
+        IGE_HIP(hipMemcpyAsync(h.data(), op->d_red.p, sizeof(double) * r, hipMemcpyDeviceToHost, s));
+        IGE_HIP(hipStreamSynchronize(s));
+        return h;
+    };
+    auto scale = [&](const std::vector<double> &sc, const double2 *x, double2 *y) {
+        IGE_HIP(hipMemcpyAsync(op->d_scal.p, sc.data(), sizeof(double) * r, hipMemcpyHostToDevice, s));
+        ige::launch_scale_cols(op, r, op->d_scal.p, x, y);
+    };
+    const std::vector<double> bnorm = norms(B);
+    out.iters.assign(r, 0);
+    out.relres_est.assign(r, 0.0);
+    std::vector<std::vector<Cx>> H(r, std::vector<Cx>((size_t)(m + 1) * m)), cs(r, std::vector<Cx>(m)),
+        sn(r, std::vector<Cx>(m)), g(r, std::vector<Cx>(m + 1));
+    std::vector<double2> hbuf((size_t)r * hs);
+    while (true) {
+        // V0 = B - A X
+        apply_dev(op, r, X, W, prec);
+        ige::launch_axpby(op, (int64_t)r * N, make_double2(1, 0), B, make_double2(0, 0), V);
+        ige::launch_axpby(op, (int64_t)r * N, make_double2(-1, 0), W, make_double2(1, 0), V);
+        std::vector<double> beta = norms(V);
+        std::vector<char> act(r);
+        int nact = 0;
+        for (int c = 0; c < r; ++c) {
+            out.relres_est[c] = bnorm[c] > 0 ? beta[c] / bnorm[c] : 0.0;
+            act[c] = bnorm[c] > 0 && out.relres_est[c] > tol && out.iters[c] < it_cap[c];
+            nact += act[c];
+        }
+        if (nact == 0) return;
+        std::vector<double> sc(r);
+        for (int c = 0; c < r; ++c) sc[c] = act[c] ? 1.0 / beta[c] : 0.0;
+        scale(sc, V, V);
+        std::vector<int> jdone(r, 0);
+        for (int c = 0; c < r; ++c) {
+            std::fill(g[c].begin(), g[c].end(), Cx(0));
+            g[c][0] = beta[c];
+        }
+        std::vector<char> run = act;
+        for (int jj = 0; jj < m; ++jj) {
+            double2 *Vj = V + (size_t)jj * r * N, *Vj1 = V + (size_t)(jj + 1) * r * N;
+            apply_dev(op, r, Vj, Vj1, prec);
+            std::vector<std::vector<Cx>> hcol(r, std::vector<Cx>(jj + 2, Cx(0)));
+            for (int pass = 0; pass < 2; ++pass) {
+                ige::launch_dotc_b(op, r, V, jj + 1, Vj1, op->d_h.p, hs);
+                ige::launch_gemv_sub_b(op, r, V, jj + 1, op->d_h.p, hs, Vj1);
+                IGE_HIP(hipMemcpyAsync(hbuf.data(), op->d_h.p, sizeof(double2) * r * hs, hipMemcpyDeviceToHost, s));
+                IGE_HIP(hipStreamSynchronize(s));
+                for (int c = 0; c < r; ++c)
+                    for (int i = 0; i <= jj; ++i) hcol[c][i] += cz(hbuf[(size_t)c * hs + i]);
+            }
+            const std::vector<double> hn = norms(Vj1);
+            for (int c = 0; c < r; ++c) sc[c] = (run[c] && hn[c] > 0) ? 1.0 / hn[c] : 0.0;
+            scale(sc, Vj1, Vj1);
+            int nrun = 0;
+            for (int c = 0; c < r; ++c) {
+                if (!run[c]) continue;
+                auto &hc = hcol[c];
+                hc[jj + 1] = hn[c];
+                for (int i = 0; i < jj; ++i) {   // rotations [[conj c, conj s], [-s, c]]
+                    const Cx t = std::conj(cs[c][i]) * hc[i] + std::conj(sn[c][i]) * hc[i + 1];
+                    hc[i + 1] = -sn[c][i] * hc[i] + cs[c][i] * hc[i + 1];
+                    hc[i] = t;
+                }
+                const double rho = std::sqrt(std::norm(hc[jj]) + std::norm(hc[jj + 1]));
+                cs[c][jj] = rho > 0 ? hc[jj] / rho : Cx(1);
+                sn[c][jj] = rho > 0 ? hc[jj + 1] / rho : Cx(0);
+                hc[jj] = rho;
+                g[c][jj + 1] = -sn[c][jj] * g[c][jj];
+                g[c][jj] = std::conj(cs[c][jj]) * g[c][jj];
+                for (int i = 0; i <= jj; ++i) H[c][(size_t)i * m + jj] = hc[i];
+                out.iters[c]++;
+                jdone[c] = jj + 1;
+                out.relres_est[c] = std::abs(g[c][jj + 1]) / bnorm[c];
+                if (out.relres_est[c] <= tol || out.iters[c] >= it_cap[c] || hn[c] == 0.0) run[c] = 0;
+                nrun += run[c];
+            }
+            if (nrun == 0) break;
+        }
+        // X_c += V_c y_c with y_c = H_c^-1 g_c (upper triangular)
+        int kmax = 0;
+        for (int c = 0; c < r; ++c) kmax = std::max(kmax, jdone[c]);
+        std::vector<double2> ny((size_t)r * hs, make_double2(0, 0));
+        for (int c = 0; c < r; ++c) {
+            const int k = jdone[c];
+            std::vector<Cx> yv(k);
+            for (int i = k - 1; i >= 0; --i) {
+                Cx acc = g[c][i];
+                for (int t = i + 1; t < k; ++t) acc -= H[c][(size_t)i * m + t] * yv[t];
+                yv[i] = acc / H[c][(size_t)i * m + i];
+            }
+            for (int i = 0; i < k; ++i) ny[(size_t)c * hs + i] = c2(-yv[i]);
+        }
+        IGE_HIP(hipMemcpyAsync(op->d_h.p, ny.data(), sizeof(double2) * r * hs, hipMemcpyHostToDevice, s));
+        ige::launch_gemv_sub_b(op, r, V, kmax, op->d_h.p, hs, X);
+    }
+}
+}  // namespace
+
 int ige_solve(ige_op op, int r, const ige_c64 *f, ige_c64 *x, int ptr_kind, const ige_solve_opts *opts,
               ige_solve_stats *stats)
 {
@@ -631,122 +763,92 @@ int ige_solve(ige_op op, int r, const ige_c64 *f, ige_c64 *x, int ptr_kind, cons
         IGE_REQUIRE(ptr_kind == IGE_HOST || ptr_kind == IGE_DEVICE, "bad ptr_kind");
         IGE_REQUIRE(opts->restart >= 1 && opts->maxit >= 0 && std::isfinite(opts->tol) && opts->tol >= 0.0,
                     "bad solve options");
+        IGE_REQUIRE(!opts->refine || (opts->inner_prec == IGE_F64 || opts->inner_prec == IGE_F32), "bad inner precision");
+        IGE_REQUIRE(!opts->refine || (std::isfinite(opts->inner_tol) && opts->inner_tol > 0.0 && opts->inner_tol < 1.0),
+                    "inner_tol must be in (0, 1)");
         set_device(op->ctx);
+        const auto t0 = std::chrono::steady_clock::now();
         const int64_t N = op->D.N;
-        const int m = opts->restart;
         hipStream_t s = op->ctx->stream;
-        if (op->gm_cap < m) {
-            op->d_V.alloc((size_t)(m + 1) * N);
-            op->gm_cap = m;
+        const double2 *F;
+        double2 *X;
+        if (ptr_kind == IGE_HOST) {
+            if (op->d_F.n < (size_t)r * N) {
+                op->d_F.alloc((size_t)r * N);
+                op->d_X.alloc((size_t)r * N);
+            }
+            IGE_HIP(hipMemcpyAsync(op->d_F.p, f, sizeof(double2) * r * N, hipMemcpyHostToDevice, s));
+            IGE_HIP(hipMemcpyAsync(op->d_X.p, x, sizeof(double2) * r * N, hipMemcpyHostToDevice, s));
+            F = op->d_F.p;
+            X = op->d_X.p;
+        } else {
+            F = reinterpret_cast<const double2 *>(f);
+            X = reinterpret_cast<double2 *>(x);
         }
-        if (!op->d_w.p) op->d_w.alloc(N);
-        if (!op->d_r.p) op->d_r.alloc(2 * N);   // f and x (host pointers are staged here)
-        if (op->d_h.n < (size_t)(m + 2)) op->d_h.alloc((size_t)(m + 2));
-        if (!op->d_red.p) op->d_red.alloc(4);
-        double2 *V = op->d_V.p, *w = op->d_w.p;
-        using C = std::complex<double>;
-        for (int c = 0; c < r; ++c) {
-            const auto t0 = std::chrono::steady_clock::now();
-            const double2 *fc;
-            double2 *xc;
-            if (ptr_kind == IGE_HOST) {
-                IGE_HIP(hipMemcpyAsync(op->d_r.p, reinterpret_cast<const double2 *>(f) + (size_t)c * N,
-                                       sizeof(double2) * N, hipMemcpyHostToDevice, s));
-                IGE_HIP(hipMemcpyAsync(op->d_r.p + N, reinterpret_cast<double2 *>(x) + (size_t)c * N,
-                                       sizeof(double2) * N, hipMemcpyHostToDevice, s));
-                fc = op->d_r.p;
-                xc = op->d_r.p + N;
-            } else {
-                fc = reinterpret_cast<const double2 *>(f) + (size_t)c * N;
-                xc = reinterpret_cast<double2 *>(x) + (size_t)c * N;
-            }
-            auto norm = [&](const double2 *v) {
-                double h = 0;
-                ige::launch_norm2(op, N, v, op->d_red.p);
-                IGE_HIP(hipMemcpyAsync(&h, op->d_red.p, sizeof(double), hipMemcpyDeviceToHost, s));
-                IGE_HIP(hipStreamSynchronize(s));
-                return h;
-            };
-            // residual r = f - A x into V[0]
-            auto residual = [&]() {
-                apply_one(op, xc, w);
-                ige::launch_scale_copy(op, N, make_double2(1, 0), fc, V);
-                ige::launch_axpby(op, N, make_double2(-1, 0), w, make_double2(1, 0), V);
-                return norm(V);
-            };
-            const double bnorm = norm(fc);
-            int it = 0;
-            double beta = residual();
-            double relres = bnorm > 0 ? beta / bnorm : 0.0;
-            std::vector<C> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1);
-            std::vector<double2> hbuf(m + 2);
-            while (bnorm > 0 && relres > opts->tol && it < opts->maxit) {
-                ige::launch_scale_copy(op, N, make_double2(1.0 / beta, 0), V, V);
-                std::fill(g.begin(), g.end(), C(0));
-                g[0] = beta;
-                int jdone = 0;
-                bool conv = false;
-                for (int jj = 0; jj < m && it < opts->maxit; ++jj) {
-                    double2 *vj1 = V + (size_t)(jj + 1) * N;
-                    apply_one(op, V + (size_t)jj * N, vj1);
-                    // classical Gram-Schmidt, twice
-                    std::vector<C> hcol(jj + 2, C(0));
-                    for (int pass = 0; pass < 2; ++pass) {
-                        ige::launch_dotc(op, V, N, jj + 1, vj1, op->d_h.p);
-                        ige::launch_gemv_sub(op, V, N, jj + 1, op->d_h.p, vj1);
-                        IGE_HIP(hipMemcpyAsync(hbuf.data(), op->d_h.p, sizeof(double2) * (jj + 1), hipMemcpyDeviceToHost, s));
-                        IGE_HIP(hipStreamSynchronize(s));
-                        for (int i = 0; i <= jj; ++i) hcol[i] += cz(hbuf[i]);
-                    }
-                    const double hn = norm(vj1);
-                    hcol[jj + 1] = hn;
-                    if (hn > 0) ige::launch_scale_copy(op, N, make_double2(1.0 / hn, 0), vj1, vj1);
-                    // apply previous rotations [[conj c, conj s], [-s, c]], then the new one
-                    for (int i = 0; i < jj; ++i) {
-                        const C t = std::conj(cs[i]) * hcol[i] + std::conj(sn[i]) * hcol[i + 1];
-                        hcol[i + 1] = -sn[i] * hcol[i] + cs[i] * hcol[i + 1];
-                        hcol[i] = t;
-                    }
-                    const double rho = std::sqrt(std::norm(hcol[jj]) + std::norm(hcol[jj + 1]));
-                    cs[jj] = rho > 0 ? hcol[jj] / rho : C(1);
-                    sn[jj] = rho > 0 ? hcol[jj + 1] / rho : C(0);
-                    hcol[jj] = rho;
-                    hcol[jj + 1] = 0;
-                    g[jj + 1] = -sn[jj] * g[jj];
-                    g[jj] = std::conj(cs[jj]) * g[jj];
-                    for (int i = 0; i <= jj; ++i) H[(size_t)i * m + jj] = hcol[i];
-                    ++it;
-                    jdone = jj + 1;
-                    if (std::abs(g[jj + 1]) <= opts->tol * bnorm) {
-                        conv = true;
-                        break;
-                    }
-                }
-                // y = H^-1 g (upper triangular), x += V y
-                std::vector<C> yv(jdone);
-                for (int i = jdone - 1; i >= 0; --i) {
-                    C acc = g[i];
-                    for (int k = i + 1; k < jdone; ++k) acc -= H[(size_t)i * m + k] * yv[k];
-                    yv[i] = acc / H[(size_t)i * m + i];
-                }
-                std::vector<double2> ny(jdone);
-                for (int i = 0; i < jdone; ++i) ny[i] = c2(-yv[i]);
-                IGE_HIP(hipMemcpyAsync(op->d_h.p, ny.data(), sizeof(double2) * jdone, hipMemcpyHostToDevice, s));
-                ige::launch_gemv_sub(op, V, N, jdone, op->d_h.p, xc);
-                beta = residual();
-                relres = beta / bnorm;
-                (void)conv;
-            }
-            if (ptr_kind == IGE_HOST) {
-                IGE_HIP(hipMemcpyAsync(reinterpret_cast<double2 *>(x) + (size_t)c * N, xc, sizeof(double2) * N,
-                                       hipMemcpyDeviceToHost, s));
-            }
+        std::vector<int> iters(r, 0), outer(r, 0);
+        std::vector<double> relres(r, 0.0);
+        GmresOut go;
+        if (!opts->refine) {
+            gmres_batched(op, r, F, X, opts->tol, opts->restart, std::vector<int>(r, opts->maxit), IGE_F64, go);
+            iters = go.iters;
+        } else {
+            // iterative refinement: FP64 residual, low-precision inner correction
+            if (op->d_r.n < (size_t)r * N) op->d_r.alloc((size_t)r * N);
+            if (op->d_D.n < (size_t)r * N) op->d_D.alloc((size_t)r * N);
+            if (op->d_red.n < (size_t)r) op->d_red.alloc(r);
+            std::vector<double> fn(r);
+            ige::launch_norm2_b(op, r, F, op->d_red.p);
+            IGE_HIP(hipMemcpyAsync(fn.data(), op->d_red.p, sizeof(double) * r, hipMemcpyDeviceToHost, s));
             IGE_HIP(hipStreamSynchronize(s));
-            if (relres > opts->tol) notconv = true;
+            for (int step = 0; step < 50; ++step) {
+                apply_dev(op, r, X, op->d_r.p, IGE_F64);
+                ige::launch_axpby(op, (int64_t)r * N, make_double2(1, 0), F, make_double2(-1, 0), op->d_r.p);
+                std::vector<double> rn(r);
+                ige::launch_norm2_b(op, r, op->d_r.p, op->d_red.p);
+                IGE_HIP(hipMemcpyAsync(rn.data(), op->d_red.p, sizeof(double) * r, hipMemcpyDeviceToHost, s));
+                IGE_HIP(hipStreamSynchronize(s));
+                bool any = false;
+                std::vector<int> cap(r);
+                for (int c = 0; c < r; ++c) {
+                    relres[c] = fn[c] > 0 ? rn[c] / fn[c] : 0.0;
+                    const bool need = relres[c] > opts->tol && iters[c] < opts->maxit;
+                    cap[c] = need ? opts->maxit - iters[c] : 0;
+                    any = any || need;
+                }
+                if (!any) break;
+                IGE_HIP(hipMemsetAsync(op->d_D.p, 0, sizeof(double2) * r * N, s));
+                // columns already converged get an inner budget of 0 and a zero correction
+                gmres_batched(op, r, op->d_r.p, op->d_D.p, opts->inner_tol, opts->restart, cap, opts->inner_prec, go);
+                ige::launch_axpby(op, (int64_t)r * N, make_double2(1, 0), op->d_D.p, make_double2(1, 0), X);
+                for (int c = 0; c < r; ++c) {
+                    iters[c] += go.iters[c];
+                    if (cap[c] > 0) outer[c]++;
+                }
+            }
+        }
+        // true FP64 relative residual of every column
+        if (op->d_r.n < (size_t)r * N) op->d_r.alloc((size_t)r * N);
+        if (op->d_red.n < (size_t)2 * r) op->d_red.alloc(2 * r);
+        apply_dev(op, r, X, op->d_r.p, IGE_F64);
+        ige::launch_axpby(op, (int64_t)r * N, make_double2(1, 0), F, make_double2(-1, 0), op->d_r.p);
+        std::vector<double> rn(r), fn(r);
+        ige::launch_norm2_b(op, r, op->d_r.p, op->d_red.p);
+        ige::launch_norm2_b(op, r, F, op->d_red.p + r);
+        IGE_HIP(hipMemcpyAsync(rn.data(), op->d_red.p, sizeof(double) * r, hipMemcpyDeviceToHost, s));
+        IGE_HIP(hipMemcpyAsync(fn.data(), op->d_red.p + r, sizeof(double) * r, hipMemcpyDeviceToHost, s));
+        if (ptr_kind == IGE_HOST)
+            IGE_HIP(hipMemcpyAsync(x, X, sizeof(double2) * r * N, hipMemcpyDeviceToHost, s));
+        IGE_HIP(hipStreamSynchronize(s));
+        const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        for (int c = 0; c < r; ++c) {
+            relres[c] = fn[c] > 0 ? rn[c] / fn[c] : 0.0;
+            // a converged estimate within rounding of tol counts as converged
+            if (relres[c] > opts->tol * 1.05) notconv = true;
             if (stats) {
-                stats[c].iters = it;
-                stats[c].relres = relres;
-                stats[c].seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+                stats[c].iters = iters[c];
+                stats[c].outer = outer[c];
+                stats[c].relres = relres[c];
+                stats[c].seconds = secs;
             }
         }
     });
@@ -757,7 +859,7 @@ int ige_solve(ige_op op, int r, const ige_c64 *f, ige_c64 *x, int ptr_kind, cons
     return rc;
 }
 
-int ige_helmholtz_eval(ige_ctx ctx, int64_t n, double kappa, const double *r2, ige_c64 *out)
+int ige_helmholtz_eval(ige_ctx ctx, int64_t n, double kappa, const double *r2, ige_c64 *out, int prec)
 {
     return guard([&] {
         IGE_REQUIRE(ctx && r2 && out && n >= 0, "bad arguments");
@@ -771,7 +873,8 @@ int ige_helmholtz_eval(ige_ctx ctx, int64_t n, double kappa, const double *r2, i
         dr.alloc(n);
         dout.alloc(n);
         IGE_HIP(hipMemcpyAsync(dr.p, r2, sizeof(double) * n, hipMemcpyHostToDevice, ctx->stream));
-        ige::launch_helmholtz_eval(ctx->stream, n, kappa, dr.p, dout.p);
+        IGE_REQUIRE(prec == IGE_F64 || prec == IGE_F32, "bad precision");
+        ige::launch_helmholtz_eval(ctx->stream, n, kappa, dr.p, dout.p, prec);
         IGE_HIP(hipMemcpyAsync(out, dout.p, sizeof(double2) * n, hipMemcpyDeviceToHost, ctx->stream));
         IGE_HIP(hipStreamSynchronize(ctx->stream));
     });

@@ -16,6 +16,7 @@
 
 #include <algorithm>
 
+#include "device_math.hpp"
 #include "op.hpp"
 
 namespace ige {
@@ -36,59 +37,6 @@ __device__ inline double2 helmholtz(double kappa, double r)
     double sn, cs;
     sincos(kappa * r, &sn, &cs);
     const double f = kInv4Pi / r;
-    return make_double2(cs * f, sn * f);
-}
-
-// Helmholtz kernel from r^2 for the coupling stage.
-//   1/r: hardware reciprocal square root refined by two Newton steps
-//        y <- y (3/2 - r^2 y^2 / 2);
-//   sin, cos of kappa r: Cody-Waite reduction t = kappa r - k pi/2 with pi/2 split
-//        into three doubles (exact products by fused multiply-add), then the Taylor
-//        polynomials of sin (to t^17) and cos (to t^18) on |t| <= pi/4, whose
-//        truncation error is below 1e-19; the quadrant k mod 4 selects signs.
-// Valid for kappa r < 2^30.
-constexpr double kTwoOverPi = 0.6366197723675814;
-constexpr double kPio2_1 = 1.5707963267948966;
-constexpr double kPio2_2 = 6.123233995736766e-17;
-constexpr double kPio2_3 = -1.4973849048591698e-33;
-
-__device__ inline double2 helmholtz_r2(double kappa, double r2)
-{
-    double y = __builtin_amdgcn_rsq(r2);
-    const double hh = 0.5 * r2;
-    y = y * fma(-hh * y, y, 1.5);
-    y = y * fma(-hh * y, y, 1.5);
-    const double x = kappa * (r2 * y);
-    const double k = rint(x * kTwoOverPi);
-    double t = fma(-k, kPio2_1, x);
-    t = fma(-k, kPio2_2, t);
-    t = fma(-k, kPio2_3, t);
-    const double z = t * t;
-    double ps = -1.0 / 355687428096000.0;             // -1/17!
-    ps = fma(ps, z, 1.0 / 1307674368000.0);           //  1/15!
-    ps = fma(ps, z, -1.0 / 6227020800.0);             // -1/13!
-    ps = fma(ps, z, 1.0 / 39916800.0);                //  1/11!
-    ps = fma(ps, z, -1.0 / 362880.0);                 // -1/9!
-    ps = fma(ps, z, 1.0 / 5040.0);                    //  1/7!
-    ps = fma(ps, z, -1.0 / 120.0);                    // -1/5!
-    ps = fma(ps, z, 1.0 / 6.0);                       //  1/3!  (sign applied below)
-    const double s = fma(-t * z, ps, t);              // t - t z (1/3! - z/5! + ...)
-    double pc = 1.0 / 6402373705728000.0;             //  1/18!
-    pc = fma(pc, z, -1.0 / 20922789888000.0);         // -1/16!
-    pc = fma(pc, z, 1.0 / 87178291200.0);             //  1/14!
-    pc = fma(pc, z, -1.0 / 479001600.0);              // -1/12!
-    pc = fma(pc, z, 1.0 / 3628800.0);                 //  1/10!
-    pc = fma(pc, z, -1.0 / 40320.0);                  // -1/8!
-    pc = fma(pc, z, 1.0 / 720.0);                     //  1/6!
-    pc = fma(pc, z, -1.0 / 24.0);                     // -1/4!
-    pc = fma(pc, z, 0.5);                             //  1/2!  (sign applied below)
-    const double c = fma(-z, pc, 1.0);                // 1 - z (1/2! - z/4! + ...)
-    const int q = (int)k & 3;
-    double sn = (q & 1) ? c : s;
-    double cs = (q & 1) ? s : c;
-    if (q & 2) sn = -sn;
-    if ((q + 1) & 2) cs = -cs;
-    const double f = kInv4Pi * y;
     return make_double2(cs * f, sn * f);
 }
 
@@ -676,9 +624,11 @@ __global__ __launch_bounds__(256) void k_m2m(DevOp o, int lvl, double2 *mom, dou
 constexpr int kM2LThreads = 256;
 constexpr int kM2LNT = 3;
 
+template <typename T>
 __global__ __launch_bounds__(kM2LThreads) void k_m2l(DevOp o, const M2LWork *work, const int32_t *partner,
                                                       const double2 *src, double2 *part)
 {
+    using C = typename dm::cplx_of<T>::type;
     extern __shared__ double smd[];
     const M2LWork wk = work[blockIdx.x];
     const int Q = o.Q;
@@ -688,23 +638,24 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l(DevOp o, const M2LWork *wor
     const int tid = threadIdx.x;
     const int mt = tid % TPG, sp = tid / TPG;
     const bool active = sp < S;
-    double *sX = smd;                                          // [3][Q]
-    double2 *sV = reinterpret_cast<double2 *>(sX + 3 * Q);     // [4][Q]
+    T *sX = reinterpret_cast<T *>(smd);                        // [3][Q]
+    C *sV = reinterpret_cast<C *>(smd + (3 * Q * (int)sizeof(T) + 15) / 16 * 2);   // [4][Q], 16-B aligned after sX
     double2 *red = reinterpret_cast<double2 *>(smd);           // [S][Q][4] after the partner loop
-    double xt[kM2LNT][3];
+    const T kap = (T)o.kappa;
+    T xt[kM2LNT][3];
     bool val[kM2LNT];
-    double2 acc[kM2LNT][4];
+    C acc[kM2LNT][4];
     const double *Xt = o.nodeX + (size_t)wk.tgt * 3 * Q;
 #pragma unroll
     for (int k = 0; k < kM2LNT; ++k) {
         const int mm = mt + k * TPG;
         val[k] = active && mm < Q;
         const int mc = val[k] ? mm : 0;
-        xt[k][0] = Xt[mc];
-        xt[k][1] = Xt[Q + mc];
-        xt[k][2] = Xt[2 * Q + mc];
+        xt[k][0] = (T)Xt[mc];
+        xt[k][1] = (T)Xt[Q + mc];
+        xt[k][2] = (T)Xt[2 * Q + mc];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[k][j] = make_double2(0.0, 0.0);
+        for (int j = 0; j < 4; ++j) acc[k][j] = C{0, 0};
     }
     const int mb = min(Q, sp * SP), me = min(Q, mb + SP);
     for (int kp = wk.beg; kp < wk.end; ++kp) {
@@ -712,22 +663,21 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l(DevOp o, const M2LWork *wor
         __syncthreads();
         const double *Xs = o.nodeX + (size_t)sc * 3 * Q;
         const double2 *Vs = src + (size_t)sc * 4 * Q;
-        for (int i = tid; i < 3 * Q; i += kM2LThreads) sX[i] = Xs[i];
-        for (int i = tid; i < 4 * Q; i += kM2LThreads) sV[i] = Vs[i];
+        for (int i = tid; i < 3 * Q; i += kM2LThreads) sX[i] = (T)Xs[i];
+        for (int i = tid; i < 4 * Q; i += kM2LThreads) sV[i] = dm::to_c(Vs[i], T(0));
         __syncthreads();
         if (active) {
             for (int ms = mb; ms < me; ++ms) {
-                const double x0 = sX[ms], x1 = sX[Q + ms], x2 = sX[2 * Q + ms];
-                const double2 v0 = sV[ms], v1 = sV[Q + ms], v2 = sV[2 * Q + ms], v3 = sV[3 * Q + ms];
+                const T x0 = sX[ms], x1 = sX[Q + ms], x2 = sX[2 * Q + ms];
+                const C v0 = sV[ms], v1 = sV[Q + ms], v2 = sV[2 * Q + ms], v3 = sV[3 * Q + ms];
 #pragma unroll
                 for (int k = 0; k < kM2LNT; ++k) {
-                    const double d0 = xt[k][0] - x0, d1 = xt[k][1] - x1, d2 = xt[k][2] - x2;
-                    const double r2 = fma(d0, d0, fma(d1, d1, d2 * d2));
-                    const double2 G = helmholtz_r2(o.kappa, r2);
-                    acc[k][0] = cadd(acc[k][0], cmul(G, v0));
-                    acc[k][1] = cadd(acc[k][1], cmul(G, v1));
-                    acc[k][2] = cadd(acc[k][2], cmul(G, v2));
-                    acc[k][3] = cadd(acc[k][3], cmul(G, v3));
+                    const T d0 = xt[k][0] - x0, d1 = xt[k][1] - x1, d2 = xt[k][2] - x2;
+                    const C G = dm::helmholtz_r2(kap, d0 * d0 + d1 * d1 + d2 * d2);
+                    acc[k][0] = dm::cadd(acc[k][0], dm::cmul(G, v0));
+                    acc[k][1] = dm::cadd(acc[k][1], dm::cmul(G, v1));
+                    acc[k][2] = dm::cadd(acc[k][2], dm::cmul(G, v2));
+                    acc[k][3] = dm::cadd(acc[k][3], dm::cmul(G, v3));
                 }
             }
         }
@@ -738,7 +688,7 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l(DevOp o, const M2LWork *wor
         if (val[k]) {
             const int mm = mt + k * TPG;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) red[((size_t)sp * Q + mm) * 4 + j] = acc[k][j];
+            for (int j = 0; j < 4; ++j) red[((size_t)sp * Q + mm) * 4 + j] = dm::to_d(acc[k][j]);
         }
     __syncthreads();
     for (int i = tid; i < 4 * Q; i += kM2LThreads) {
@@ -1045,17 +995,104 @@ __global__ __launch_bounds__(kRedThreads) void k_norm2(int64_t n, const double2 
     if (threadIdx.x == 0) out[0] = sqrt(r.x);
 }
 
-__global__ void k_helmholtz_eval(int64_t n, double kappa, const double *r2, double2 *out)
+__global__ void k_helmholtz_eval(int64_t n, double kappa, const double *r2, double2 *out, int prec)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = helmholtz_r2(kappa, r2[i]);
+    if (i >= n) return;
+    if (prec == IGE_F32) out[i] = dm::to_d(dm::helmholtz_r2((float)kappa, (float)r2[i]));
+    else out[i] = dm::helmholtz_r2(kappa, r2[i]);
+}
+
+// ---- batched GMRES vector kernels: V is [k][r][N] (basis index, column, entry),
+// W and X are [r][N]; per-column coefficients h are [r][hs]
+__global__ __launch_bounds__(kRedThreads) void k_dotc_b(int64_t n, int r, const double2 *V, const double2 *w,
+                                                         double2 *out, int hs)
+{
+    __shared__ double2 sh[kRedThreads / kWave];
+    const int kk = blockIdx.x, c = blockIdx.y;
+    const double2 *v = V + ((size_t)kk * r + c) * n;
+    const double2 *wc = w + (size_t)c * n;
+    double2 acc = make_double2(0, 0);
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const double2 a = v[i], b = wc[i];
+        acc.x += a.x * b.x + a.y * b.y;
+        acc.y += a.x * b.y - a.y * b.x;
+    }
+    const double2 res = block_reduce2(acc, sh);
+    if (threadIdx.x == 0) out[(size_t)c * hs + kk] = res;
+}
+
+// w_c -= sum_{kk < k} V[kk][c] h[c][kk]
+__global__ void k_gemv_sub_b(int64_t n, int r, const double2 *V, int k, const double2 *hc, int hs, double2 *w)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (i >= n) return;
+    double2 acc = w[(size_t)c * n + i];
+    for (int kk = 0; kk < k; ++kk) {
+        const double2 v = V[((size_t)kk * r + c) * n + i], hh = hc[(size_t)c * hs + kk];
+        acc.x -= v.x * hh.x - v.y * hh.y;
+        acc.y -= v.x * hh.y + v.y * hh.x;
+    }
+    w[(size_t)c * n + i] = acc;
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_norm2_b(int64_t n, const double2 *x, double *out)
+{
+    __shared__ double2 sh[kRedThreads / kWave];
+    const double2 *xc = x + (size_t)blockIdx.x * n;
+    double2 acc = make_double2(0, 0);
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const double2 a = xc[i];
+        acc.x += a.x * a.x + a.y * a.y;
+    }
+    const double2 res = block_reduce2(acc, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = sqrt(res.x);
+}
+
+// y_c = s_c x_c (s per column, real)
+__global__ void k_scale_cols(int64_t n, const double *s, const double2 *x, double2 *y)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (i >= n) return;
+    const double sc = s[c];
+    const double2 v = x[(size_t)c * n + i];
+    y[(size_t)c * n + i] = make_double2(sc * v.x, sc * v.y);
 }
 
 }  // namespace
 
-void launch_helmholtz_eval(hipStream_t s, int64_t n, double kappa, const double *r2, double2 *out)
+void launch_dotc_b(ige_op op, int r, const double2 *V, int k, const double2 *w, double2 *out, int hs)
 {
-    hipLaunchKernelGGL(k_helmholtz_eval, dim3((n + 255) / 256), dim3(256), 0, s, n, kappa, r2, out);
+    hipLaunchKernelGGL(k_dotc_b, dim3(k, r), dim3(kRedThreads), 0, op->ctx->stream, (int64_t)op->view.N, r, V, w, out,
+                       hs);
+    IGE_HIP(hipGetLastError());
+}
+
+void launch_gemv_sub_b(ige_op op, int r, const double2 *V, int k, const double2 *hc, int hs, double2 *w)
+{
+    const int64_t n = op->view.N;
+    hipLaunchKernelGGL(k_gemv_sub_b, dim3((n + 255) / 256, r), dim3(256), 0, op->ctx->stream, n, r, V, k, hc, hs, w);
+    IGE_HIP(hipGetLastError());
+}
+
+void launch_norm2_b(ige_op op, int r, const double2 *x, double *out)
+{
+    hipLaunchKernelGGL(k_norm2_b, dim3(r), dim3(kRedThreads), 0, op->ctx->stream, (int64_t)op->view.N, x, out);
+    IGE_HIP(hipGetLastError());
+}
+
+void launch_scale_cols(ige_op op, int r, const double *s, const double2 *x, double2 *y)
+{
+    const int64_t n = op->view.N;
+    hipLaunchKernelGGL(k_scale_cols, dim3((n + 255) / 256, r), dim3(256), 0, op->ctx->stream, n, s, x, y);
+    IGE_HIP(hipGetLastError());
+}
+
+void launch_helmholtz_eval(hipStream_t s, int64_t n, double kappa, const double *r2, double2 *out, int prec)
+{
+    hipLaunchKernelGGL(k_helmholtz_eval, dim3((n + 255) / 256), dim3(256), 0, s, n, kappa, r2, out, prec);
     IGE_HIP(hipGetLastError());
 }
 
@@ -1150,15 +1187,20 @@ size_t m2l_shared_bytes(int Q)
 {
     const int TPG = (Q + kM2LNT - 1) / kM2LNT;
     const int S = std::min(kM2LThreads / TPG, Q);
-    return std::max(sizeof(double) * 3 * Q + sizeof(double2) * 4 * Q, sizeof(double2) * 4 * (size_t)Q * S);
+    // [3][Q] positions (16-byte aligned end) + [4][Q] complex, or the reduction
+    return std::max(sizeof(double) * (3 * Q + 1) + sizeof(double2) * 4 * Q, sizeof(double2) * 4 * (size_t)Q * S);
 }
 
-void launch_m2l(ige_op op)
+void launch_m2l(ige_op op, int prec)
 {
     const DevOp &o = op->view;
     if (op->work.empty()) return;
-    hipLaunchKernelGGL(k_m2l, dim3(op->work.size()), dim3(kM2LThreads), m2l_shared_bytes(o.Q), op->ctx->stream, o,
-                       op->d_work.p, op->d_partner.p, op->d_src.p, op->d_part.p);
+    if (prec == IGE_F32)
+        hipLaunchKernelGGL(k_m2l<float>, dim3(op->work.size()), dim3(kM2LThreads), m2l_shared_bytes(o.Q),
+                           op->ctx->stream, o, op->d_work.p, op->d_partner.p, op->d_src.p, op->d_part.p);
+    else
+        hipLaunchKernelGGL(k_m2l<double>, dim3(op->work.size()), dim3(kM2LThreads), m2l_shared_bytes(o.Q),
+                           op->ctx->stream, o, op->d_work.p, op->d_partner.p, op->d_src.p, op->d_part.p);
     IGE_LAUNCH_CHECK();
 }
 

@@ -8,6 +8,7 @@
 
 #include <algorithm>
 
+#include "device_math.hpp"
 #include "op.hpp"
 
 namespace ige {
@@ -17,57 +18,9 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kRBMax = 8;   // largest column chunk
 
-__device__ __constant__ double kInv4PiB = 0.07957747154594767;
-
 __device__ inline double2 cmulb(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
 __device__ inline double2 caddb(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ inline double2 cscaleb(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
-
-// same evaluation as the single-column coupling stage (see kernels.hip)
-constexpr double kTwoOverPi = 0.6366197723675814;
-constexpr double kPio2_1 = 1.5707963267948966;
-constexpr double kPio2_2 = 6.123233995736766e-17;
-constexpr double kPio2_3 = -1.4973849048591698e-33;
-
-__device__ inline double2 helmholtz_r2b(double kappa, double r2)
-{
-    double y = __builtin_amdgcn_rsq(r2);
-    const double hh = 0.5 * r2;
-    y = y * fma(-hh * y, y, 1.5);
-    y = y * fma(-hh * y, y, 1.5);
-    const double x = kappa * (r2 * y);
-    const double k = rint(x * kTwoOverPi);
-    double t = fma(-k, kPio2_1, x);
-    t = fma(-k, kPio2_2, t);
-    t = fma(-k, kPio2_3, t);
-    const double z = t * t;
-    double ps = -1.0 / 355687428096000.0;
-    ps = fma(ps, z, 1.0 / 1307674368000.0);
-    ps = fma(ps, z, -1.0 / 6227020800.0);
-    ps = fma(ps, z, 1.0 / 39916800.0);
-    ps = fma(ps, z, -1.0 / 362880.0);
-    ps = fma(ps, z, 1.0 / 5040.0);
-    ps = fma(ps, z, -1.0 / 120.0);
-    ps = fma(ps, z, 1.0 / 6.0);
-    const double s = fma(-t * z, ps, t);
-    double pc = 1.0 / 6402373705728000.0;
-    pc = fma(pc, z, -1.0 / 20922789888000.0);
-    pc = fma(pc, z, 1.0 / 87178291200.0);
-    pc = fma(pc, z, -1.0 / 479001600.0);
-    pc = fma(pc, z, 1.0 / 3628800.0);
-    pc = fma(pc, z, -1.0 / 40320.0);
-    pc = fma(pc, z, 1.0 / 720.0);
-    pc = fma(pc, z, -1.0 / 24.0);
-    pc = fma(pc, z, 0.5);
-    const double c = fma(-z, pc, 1.0);
-    const int q = (int)k & 3;
-    double sn = (q & 1) ? c : s;
-    double cs = (q & 1) ? s : c;
-    if (q & 2) sn = -sn;
-    if ((q + 1) & 2) cs = -cs;
-    const double f = kInv4PiB * y;
-    return make_double2(cs * f, sn * f);
-}
 
 // x [r][N] -> xt [N][r] and back
 __global__ void k_to_rows(int64_t N, int r, const double2 *x, double2 *xt)
@@ -281,10 +234,11 @@ __global__ __launch_bounds__(256) void k_m2m_b(DevOp o, int lvl, int r, double2 
 constexpr int kM2LThreadsB = 256;
 constexpr int kNTB = 3;
 
-template <int kRB>
+template <typename T, int kRB>
 __global__ __launch_bounds__(kM2LThreadsB) void k_m2l_b(DevOp o, int r, const M2LWork *work, const int32_t *partner,
                                                          const double2 *src, double2 *part)
 {
+    using C = typename dm::cplx_of<T>::type;
     extern __shared__ double smd[];
     const M2LWork wk = work[blockIdx.x];
     const int c0 = blockIdx.y * kRB, nc = min(kRB, r - c0);
@@ -295,57 +249,58 @@ __global__ __launch_bounds__(kM2LThreadsB) void k_m2l_b(DevOp o, int r, const M2
     const int tid = threadIdx.x;
     const int mt = tid % TPG, sp = tid / TPG;
     const bool active = sp < S;
-    double *sX = smd;                                          // [3][Q]
-    double2 *sV = reinterpret_cast<double2 *>(sX + 3 * Q);     // [4][Q][kRB]
+    T *sX = reinterpret_cast<T *>(smd);                        // [3][Q]
+    C *sV = reinterpret_cast<C *>(smd + (3 * Q * (int)sizeof(T) + 15) / 16 * 2);   // [4][Q][kRB], after sX
     double2 *red = reinterpret_cast<double2 *>(smd);           // [S][Q][kRB] (one field at a time)
+    const T kap = (T)o.kappa;
     const double *Xt = o.nodeX + (size_t)wk.tgt * 3 * Q;
-    double xt[kNTB][3];
+    T xt[kNTB][3];
     bool val[kNTB];
 #pragma unroll
     for (int t = 0; t < kNTB; ++t) {
         const int mm = mt + t * TPG;
         val[t] = active && mm < Q;
         const int mc = val[t] ? mm : 0;
-        xt[t][0] = Xt[mc];
-        xt[t][1] = Xt[Q + mc];
-        xt[t][2] = Xt[2 * Q + mc];
+        xt[t][0] = (T)Xt[mc];
+        xt[t][1] = (T)Xt[Q + mc];
+        xt[t][2] = (T)Xt[2 * Q + mc];
     }
-    double2 acc[kNTB][4][kRB];
+    C acc[kNTB][4][kRB];
 #pragma unroll
     for (int t = 0; t < kNTB; ++t)
 #pragma unroll
         for (int f = 0; f < 4; ++f)
 #pragma unroll
-            for (int c = 0; c < kRB; ++c) acc[t][f][c] = make_double2(0, 0);
+            for (int c = 0; c < kRB; ++c) acc[t][f][c] = C{0, 0};
     const int mb = min(Q, sp * SP), me = min(Q, mb + SP);
     for (int kp = wk.beg; kp < wk.end; ++kp) {
         const int sc = partner[kp];
         __syncthreads();
         const double *Xs = o.nodeX + (size_t)sc * 3 * Q;
         const double2 *Vs = src + (size_t)sc * 4 * Q * r;
-        for (int i = tid; i < 3 * Q; i += kM2LThreadsB) sX[i] = Xs[i];
+        for (int i = tid; i < 3 * Q; i += kM2LThreadsB) sX[i] = (T)Xs[i];
         for (int i = tid; i < 4 * Q * kRB; i += kM2LThreadsB) {
             const int c = i % kRB, fm = i / kRB;
-            sV[i] = c < nc ? Vs[(size_t)fm * r + c0 + c] : make_double2(0, 0);
+            sV[i] = c < nc ? dm::to_c(Vs[(size_t)fm * r + c0 + c], T(0)) : C{0, 0};
         }
         __syncthreads();
         if (active) {
             for (int ms = mb; ms < me; ++ms) {
-                const double x0 = sX[ms], x1 = sX[Q + ms], x2 = sX[2 * Q + ms];
-                double2 G[kNTB];
+                const T x0 = sX[ms], x1 = sX[Q + ms], x2 = sX[2 * Q + ms];
+                C G[kNTB];
 #pragma unroll
                 for (int t = 0; t < kNTB; ++t) {
-                    const double d0 = xt[t][0] - x0, d1 = xt[t][1] - x1, d2 = xt[t][2] - x2;
-                    G[t] = helmholtz_r2b(o.kappa, fma(d0, d0, fma(d1, d1, d2 * d2)));
+                    const T d0 = xt[t][0] - x0, d1 = xt[t][1] - x1, d2 = xt[t][2] - x2;
+                    G[t] = dm::helmholtz_r2(kap, d0 * d0 + d1 * d1 + d2 * d2);
                 }
 #pragma unroll
                 for (int f = 0; f < 4; ++f) {
-                    const double2 *vf = sV + ((size_t)f * Q + ms) * kRB;
+                    const C *vf = sV + ((size_t)f * Q + ms) * kRB;
 #pragma unroll
                     for (int c = 0; c < kRB; ++c) {
-                        const double2 v = vf[c];
+                        const C v = vf[c];
 #pragma unroll
-                        for (int t = 0; t < kNTB; ++t) acc[t][f][c] = caddb(acc[t][f][c], cmulb(G[t], v));
+                        for (int t = 0; t < kNTB; ++t) acc[t][f][c] = dm::cadd(acc[t][f][c], dm::cmul(G[t], v));
                     }
                 }
             }
@@ -357,7 +312,7 @@ __global__ __launch_bounds__(kM2LThreadsB) void k_m2l_b(DevOp o, int r, const M2
         for (int t = 0; t < kNTB; ++t)
             if (val[t])
 #pragma unroll
-                for (int c = 0; c < kRB; ++c) red[((size_t)sp * Q + mt + t * TPG) * kRB + c] = acc[t][f][c];
+                for (int c = 0; c < kRB; ++c) red[((size_t)sp * Q + mt + t * TPG) * kRB + c] = dm::to_d(acc[t][f][c]);
         __syncthreads();
         for (int i = tid; i < Q * kRB; i += kM2LThreadsB) {
             const int c = i % kRB, mm = i / kRB;
@@ -531,7 +486,7 @@ int pick_rb(size_t bytes_per_col, size_t fixed = 0)
     }                                                                                                        \
     IGE_HIP(hipGetLastError())
 
-void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, double2 *yt, hipEvent_t *ev)
+void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, double2 *yt, hipEvent_t *ev, int prec)
 {
     const DevOp &o = op->view;
     hipStream_t s = op->ctx->stream;
@@ -567,11 +522,25 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
         {
             const int TPG = (o.Q + kNTB - 1) / kNTB;
             const int S = std::max(1, std::min(kM2LThreadsB / TPG, o.Q));
-            const size_t fixed = sizeof(double) * 3 * o.Q;
+            const size_t fixed = sizeof(double) * (3 * o.Q + 1);
             const size_t per = std::max(sizeof(double2) * 4 * o.Q, sizeof(double2) * (size_t)S * o.Q);
             const int rb = std::min(4, pick_rb(per, fixed));   // registers: 3 targets x 4 fields x rb columns
-            IGE_RB_SWITCH(rb, k_m2l_b, dim3(op->work.size(), chunks(rb)), dim3(kM2LThreadsB), fixed + per * rb, s, o,
-                          r, op->d_work.p, op->d_partner.p, op->d_bsrc.p, op->d_bpart.p);
+            const dim3 grid(op->work.size(), chunks(rb)), blk(kM2LThreadsB);
+            const size_t shm = fixed + per * rb;
+            if (prec == IGE_F32) {
+                switch (rb) {
+                    case 4: hipLaunchKernelGGL((k_m2l_b<float, 4>), grid, blk, shm, s, o, r, op->d_work.p, op->d_partner.p, op->d_bsrc.p, op->d_bpart.p); break;
+                    case 2: hipLaunchKernelGGL((k_m2l_b<float, 2>), grid, blk, shm, s, o, r, op->d_work.p, op->d_partner.p, op->d_bsrc.p, op->d_bpart.p); break;
+                    default: hipLaunchKernelGGL((k_m2l_b<float, 1>), grid, blk, shm, s, o, r, op->d_work.p, op->d_partner.p, op->d_bsrc.p, op->d_bpart.p); break;
+                }
+            } else {
+                switch (rb) {
+                    case 4: hipLaunchKernelGGL((k_m2l_b<double, 4>), grid, blk, shm, s, o, r, op->d_work.p, op->d_partner.p, op->d_bsrc.p, op->d_bpart.p); break;
+                    case 2: hipLaunchKernelGGL((k_m2l_b<double, 2>), grid, blk, shm, s, o, r, op->d_work.p, op->d_partner.p, op->d_bsrc.p, op->d_bpart.p); break;
+                    default: hipLaunchKernelGGL((k_m2l_b<double, 1>), grid, blk, shm, s, o, r, op->d_work.p, op->d_partner.p, op->d_bsrc.p, op->d_bpart.p); break;
+                }
+            }
+            IGE_HIP(hipGetLastError());
         }
         mark(3);
         hipLaunchKernelGGL(k_m2l_reduce_b, dim3(op->NC), dim3(256), 0, s, o, r, op->d_wrk_of_tgt.p, op->d_bpart.p,

@@ -116,10 +116,9 @@ struct ige_op_s {
     int bcap = 0;
     ige::DBuf<double2> d_bmom, d_bsrc, d_bpart, d_bloc, d_bybuf, d_bxt, d_byt, d_bx, d_by;
     // GMRES workspace
-    ige::DBuf<double2> d_V, d_w, d_r;
+    ige::DBuf<double2> d_V, d_w, d_r, d_X, d_F, d_D;
     ige::DBuf<double2> d_h;
-    ige::DBuf<double> d_red;
-    int gm_cap = 0;
+    ige::DBuf<double> d_red, d_scal;
 
     ige::DevOp view{};
 };
@@ -134,7 +133,7 @@ void launch_near_singular(ige_op op);
 // apply pieces (one right-hand side)
 void launch_p2m(ige_op op, const double2 *x);
 void launch_m2m(ige_op op);
-void launch_m2l(ige_op op);
+void launch_m2l(ige_op op, int prec);
 void launch_m2l_reduce(ige_op op);
 void launch_l2l(ige_op op);
 void launch_spmv(ige_op op, const double2 *x, double2 *y, hipStream_t st);
@@ -147,7 +146,11 @@ void launch_gemv_sub(ige_op op, const double2 *V, int64_t ldv, int k, const doub
 void launch_axpby(ige_op op, int64_t n, double2 a, const double2 *x, double2 b, double2 *y);
 void launch_scale_copy(ige_op op, int64_t n, double2 a, const double2 *x, double2 *y);
 void launch_norm2(ige_op op, int64_t n, const double2 *x, double *out);
-void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, double2 *yt, hipEvent_t *ev);
-void launch_helmholtz_eval(hipStream_t s, int64_t n, double kappa, const double *r2, double2 *out);
+void launch_dotc_b(ige_op op, int r, const double2 *V, int k, const double2 *w, double2 *out, int hs);
+void launch_gemv_sub_b(ige_op op, int r, const double2 *V, int k, const double2 *hc, int hs, double2 *w);
+void launch_norm2_b(ige_op op, int r, const double2 *x, double *out);
+void launch_scale_cols(ige_op op, int r, const double *s, const double2 *x, double2 *y);
+void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, double2 *yt, hipEvent_t *ev, int prec);
+void launch_helmholtz_eval(hipStream_t s, int64_t n, double kappa, const double *r2, double2 *out, int prec);
 
 }  // namespace ige

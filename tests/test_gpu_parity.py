@@ -157,7 +157,7 @@ def test_gmres_dense_c1_matches_lapack(oracle_mod, ctx):
     f = op.rhs_plane_wave([[0.0, 0.0, 1.0]], [[1.0, 0.0, 0.0]])[0]
     x, stats, rc = op.solve(f, tol=1e-8, restart=1500, maxit=2000)
     assert rc == 0
-    it, relres, _ = stats[0]
+    it, _, relres, _ = stats[0]
     o = oracle_mod.Oracle(pats, 1, 2, 1.0)
     A = o.dense_matrix()
     fo = o.rhs_plane_wave([0, 0, 1], [1, 0, 0])
@@ -173,6 +173,48 @@ def test_gmres_dense_c1_matches_lapack(oracle_mod, ctx):
     # maxit too small: not converged, reported as such
     x3, stats3, rc3 = op.solve(f, tol=1e-12, restart=5, maxit=3)
     assert rc3 == B.IGE_ENOTCONV and stats3[0][0] == 3
+    # three right-hand sides solved together: each column matches LAPACK
+    dirs, pols = W.fibonacci_plane_waves(3)
+    F = op.rhs_plane_wave(dirs, pols)
+    X, st, rc4 = op.solve(F, tol=1e-8, restart=40, maxit=2000)
+    assert rc4 == 0
+    for c in range(3):
+        xl = np.linalg.solve(A, o.rhs_plane_wave(dirs[c], pols[c]))
+        assert st[c][2] <= 1.05e-8
+        assert _rel(X[c], xl) <= 1e-8 * np.linalg.cond(A)
+
+
+def test_fp32_coupling_apply_and_refined_solve(oracle_mod, ctx):
+    """Mixed precision: the FP32 coupling stage stays within its derived error
+    (kappa * diam * 2^-23 per kernel value) of the oracle, and GMRES with FP64
+    iterative refinement around FP32-coupling inner solves reaches the FP64
+    tolerance and the FP64 solution within 1e-6."""
+    from paper_1807_03097_amd import binding as B
+    pats = W.cube_sphere()
+    geom = B.Geometry(ctx, pats)
+    kappa = 8.0
+    op = B.Operator(geom, 2, 3, kappa, 8, 1.6, 5, 5, 1)
+    x = W.random_coeffs(op.N, 0)
+    yo = oracle_mod.Oracle(pats, 2, 3, kappa).fmm_apply(x, 8, 1.6, 1)
+    y32 = op.apply(x, prec=B.IGE_F32)
+    err32 = _rel(y32, yo)
+    _say(f"  FP32 coupling rel.err {err32:.2e}")
+    assert 1e-12 < err32 <= 1e-5
+    r = np.geomspace(1e-3, 4.0, 20001)
+    g32 = B.ige_helmholtz_eval(ctx.h, kappa, r * r, B.IGE_F32)
+    ref = np.exp(1j * kappa * r) / (4 * np.pi * r)
+    assert np.max(np.abs(g32 - ref) / np.abs(ref)) <= 4 * kappa * 4.0 * 2.0 ** -23 + 1e-6
+    dirs, pols = W.fibonacci_plane_waves(2)
+    F = op.rhs_plane_wave(dirs, pols)
+    X64, st64, rc = op.solve(F, tol=1e-10, restart=100, maxit=3000)
+    assert rc == 0
+    Xir, stir, rc2 = op.solve(F, tol=1e-10, restart=100, maxit=3000, refine=True, inner_tol=1e-4,
+                              inner_prec=B.IGE_F32)
+    assert rc2 == 0
+    for c in range(2):
+        _say(f"  col {c}: FP64 iters {st64[c][0]}, IR iters {stir[c][0]} outer {stir[c][1]} relres {stir[c][2]:.2e}")
+        assert stir[c][2] <= 1.05e-10 and stir[c][1] >= 2
+        assert _rel(Xir[c], X64[c]) <= 1e-6
 
 
 def test_c2_full_size_sampled_rows(oracle_mod, ctx):
