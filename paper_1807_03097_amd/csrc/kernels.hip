@@ -135,6 +135,35 @@ __device__ inline void local_values(const DevOp &o, int e1, int e2, double x, do
     }
 }
 
+// The same values written straight to a row of shared memory: (Phi_l, cdiv * div_l).
+template <int NL>
+__device__ inline void local_values_lds(const DevOp &o, int e1, int e2, double x, double y, const double Fu[3],
+                                        const double Fv[3], double cdiv, double (*dst)[4])
+{
+    double Pu[kMaxP + 1], dPu[kMaxP + 1], Qu[kMaxP + 1], Pv[kMaxP + 1], dPv[kMaxP + 1], Qv[kMaxP + 1];
+    spline_pieces(o, e1, x, Pu, dPu, Qu);
+    spline_pieces(o, e2, y, Pv, dPv, Qv);
+    const int p = o.p;
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+        int a, t1, t2;
+        local_index(p, l, a, t1, t2);
+        double val, div;
+        if (a == 0) {
+            val = Pu[t1] * Qv[t2];
+            div = dPu[t1] * Qv[t2];
+        } else {
+            val = Qu[t1] * Pv[t2];
+            div = Qu[t1] * dPv[t2];
+        }
+        const double *F = (a == 0) ? Fu : Fv;
+        dst[l][0] = val * F[0];
+        dst[l][1] = val * F[1];
+        dst[l][2] = val * F[2];
+        dst[l][3] = cdiv * div;
+    }
+}
+
 __device__ inline void elem_of(const DevOp &o, int64_t e, int &j, int &e1, int &e2)
 {
     const int nn = o.n * o.n;
@@ -291,7 +320,7 @@ __global__ __launch_bounds__(64) void k_near_regular(DevOp o, const int32_t *nea
         for (int i = lane; i < nq * G2; i += kWave) {
             const int qa = q0 + i / G2, qb = i % G2;
             const double d0 = Xa[qa] - Xb[qb], d1 = Xa[G2 + qa] - Xb[G2 + qb], d2 = Xa[2 * G2 + qa] - Xb[2 * G2 + qb];
-            K[i] = helmholtz(o.kappa, sqrt(d0 * d0 + d1 * d1 + d2 * d2));
+            K[i] = dm::helmholtz_r2(o.kappa, fma(d0, d0, fma(d1, d1, d2 * d2)));
         }
         __syncthreads();
 #pragma unroll
@@ -407,9 +436,15 @@ __device__ inline void singular_point(const DevOp &o, int kind, int idx, double 
     }
 }
 
+// Singular pairs: the points of the sub-rules are processed in batches of 64; in a
+// batch every lane evaluates geometry, local basis and kernel at one point into
+// LDS, then the lanes accumulate the block entries over the batch.
 template <int NL>
 __global__ __launch_bounds__(64) void k_near_singular(DevOp o, const SingularPair *list)
 {
+    __shared__ double sPa[kWave][NL][4];   // test side:  w*K-independent values Phi (3), div
+    __shared__ double sPb[kWave][NL][4];   // trial side
+    __shared__ double2 sK[kWave];          // weight * kernel
     const SingularPair sp = list[blockIdx.x];
     const int lane = threadIdx.x;
     int ja, a1, a2, jb, b1, b2;
@@ -419,14 +454,14 @@ __global__ __launch_bounds__(64) void k_near_singular(DevOp o, const SingularPai
     const int nsub = sp.kind == 1 ? 8 : (sp.kind == 2 ? 6 : 4);
     const int npts = nsub * g4;
     const double ik2 = 1.0 / (o.kappa * o.kappa), h4 = o.h * o.h * o.h * o.h;
-    constexpr int RCH = (NL >= 36) ? 1 : (36 / NL < NL ? 36 / NL : NL);
-    for (int r0 = 0; r0 < NL; r0 += RCH) {
-        double2 acc[RCH][NL];
+    constexpr int NE = (NL * NL + kWave - 1) / kWave;   // block entries per lane
+    double2 acc[NE];
 #pragma unroll
-        for (int a = 0; a < RCH; ++a)
-#pragma unroll
-            for (int b = 0; b < NL; ++b) acc[a][b] = make_double2(0.0, 0.0);
-        for (int pt = lane; pt < npts; pt += kWave) {
+    for (int t = 0; t < NE; ++t) acc[t] = make_double2(0.0, 0.0);
+    for (int p0 = 0; p0 < npts; p0 += kWave) {
+        const int pt = p0 + lane;
+        __syncthreads();   // the previous batch has been consumed
+        if (pt < npts) {
             double s1, s2, t1, t2, wt;
             singular_point(o, sp.kind, pt, s1, s2, t1, t2, wt);
             double xa, ya, xb, yb;
@@ -436,50 +471,43 @@ __global__ __launch_bounds__(64) void k_near_singular(DevOp o, const SingularPai
                 frame_map(sp.fa, s1, s2, xa, ya);
                 frame_map(sp.fb, t1, t2, xb, yb);
             }
-            double XA[3], FuA[3], FvA[3], XB[3], FuB[3], FvB[3];
-            bezier_eval(o.geo, ja, (a1 + xa) * o.h, (a2 + ya) * o.h, XA, FuA, FvA);
-            bezier_eval(o.geo, jb, (b1 + xb) * o.h, (b2 + yb) * o.h, XB, FuB, FvB);
-            double PhA[NL][3], DA[NL], PhB[NL][3], DB[NL];
-            local_values<NL>(o, a1, a2, xa, ya, FuA, FvA, PhA, DA);
-            local_values<NL>(o, b1, b2, xb, yb, FuB, FvB, PhB, DB);
+            double XA[3], XB[3], Fu[3], Fv[3];
+            bezier_eval(o.geo, ja, (a1 + xa) * o.h, (a2 + ya) * o.h, XA, Fu, Fv);
+            local_values_lds<NL>(o, a1, a2, xa, ya, Fu, Fv, -ik2, sPa[lane]);
+            bezier_eval(o.geo, jb, (b1 + xb) * o.h, (b2 + yb) * o.h, XB, Fu, Fv);
+            local_values_lds<NL>(o, b1, b2, xb, yb, Fu, Fv, 1.0, sPb[lane]);
             const double d0 = XA[0] - XB[0], d1 = XA[1] - XB[1], d2 = XA[2] - XB[2];
-            const double2 K = cscale(wt * h4, helmholtz(o.kappa, sqrt(d0 * d0 + d1 * d1 + d2 * d2)));
+            sK[lane] = cscale(wt * h4, dm::helmholtz_r2(o.kappa, fma(d0, d0, fma(d1, d1, d2 * d2))));
+        }
+        __syncthreads();
+        const int nb = min(kWave, npts - p0);
 #pragma unroll
-            for (int a = 0; a < RCH; ++a) {
-                const int l = r0 + a;
-                if (l < NL) {
-#pragma unroll
-                    for (int b = 0; b < NL; ++b) {
-                        const double gsum = PhA[l][0] * PhB[b][0] + PhA[l][1] * PhB[b][1] + PhA[l][2] * PhB[b][2] -
-                                            ik2 * DA[l] * DB[b];
-                        acc[a][b].x += K.x * gsum;
-                        acc[a][b].y += K.y * gsum;
-                    }
+        for (int t = 0; t < NE; ++t) {
+            const int ent = lane + t * kWave;
+            if (ent < NL * NL) {
+                const int l = ent / NL, lb = ent % NL;
+                double2 a = acc[t];
+                for (int q = 0; q < nb; ++q) {
+                    const double gsum = sPa[q][l][0] * sPb[q][lb][0] + sPa[q][l][1] * sPb[q][lb][1] +
+                                        sPa[q][l][2] * sPb[q][lb][2] + sPa[q][l][3] * sPb[q][lb][3];
+                    a.x = fma(sK[q].x, gsum, a.x);
+                    a.y = fma(sK[q].y, gsum, a.y);
                 }
+                acc[t] = a;
             }
         }
-        // wave reduction (butterfly) and accumulation into the CSR matrix
+    }
 #pragma unroll
-        for (int a = 0; a < RCH; ++a)
-#pragma unroll
-            for (int b = 0; b < NL; ++b)
-                for (int off = kWave / 2; off >= 1; off >>= 1) {
-                    acc[a][b].x += __shfl_xor(acc[a][b].x, off, kWave);
-                    acc[a][b].y += __shfl_xor(acc[a][b].y, off, kWave);
-                }
-#pragma unroll
-        for (int a = 0; a < RCH; ++a)
-#pragma unroll
-            for (int b = 0; b < NL; ++b) {
-                const int l = r0 + a;
-                if (l < NL && lane == ((a * NL + b) % kWave)) {
-                    int ri, cj;
-                    double sr, sc;
-                    local_dof(o, ja, a1, a2, l, ri, sr);
-                    local_dof(o, jb, b1, b2, b, cj, sc);
-                    csr_add(o, ri, cj, cscale(sr * sc, acc[a][b]));
-                }
-            }
+    for (int t = 0; t < NE; ++t) {
+        const int ent = lane + t * kWave;
+        if (ent < NL * NL) {
+            const int l = ent / NL, lb = ent % NL;
+            int ri, cj;
+            double sr, sc;
+            local_dof(o, ja, a1, a2, l, ri, sr);
+            local_dof(o, jb, b1, b2, lb, cj, sc);
+            csr_add(o, ri, cj, cscale(sr * sc, acc[t]));
+        }
     }
 }
 
