@@ -218,7 +218,7 @@ void check_params(const ige_params &P)
 }
 
 // host part: unknowns, trees, near pattern, singular pairs, far tables
-void plan(ige_op op, const ige_geom_s *geom, ige::NearPattern &A, std::vector<ige::SingularPair> &sing)
+void plan(ige_op op, const ige_geom_s *geom, ige::NearBlocks &A, std::vector<ige::SingularPair> &sing)
 {
     const ige_params &P = op->prm;
     int d = P.leaf_depth;
@@ -226,10 +226,13 @@ void plan(ige_op op, const ige_geom_s *geom, ige::NearPattern &A, std::vector<ig
     ige::build_discretisation(op->D, geom->G, P.p, P.level);
     ige::build_partition(op->T, geom->G, op->D, P.eta, d);
     ige::build_far_tables(op->F, op->D, op->T, P.q);
-    ige::build_near_pattern(A, op->D, op->T);
-    op->nnz = A.rowptr.back();
+    // row chunks per near-field block (tuning knob IGE_NEAR_CHUNKS, default 2)
+    int nch = 2;
+    if (const char *e = std::getenv("IGE_NEAR_CHUNKS")) nch = std::max(1, std::min(64, std::atoi(e)));
+    ige::build_near_blocks(A, op->D, op->T, nch);
+    op->nnz = A.nblk() * A.nF * A.nF;
     std::vector<double> corners;
-    ige::build_singular_pairs(sing, corners, geom->G, op->D, op->T);
+    ige::build_singular_pairs(sing, corners, geom->G, op->D, op->T, A);
     op->nsing = (int64_t)sing.size();
     op->lvl_off.assign(op->T.L + 2, 0);
     for (int l = 0; l <= op->T.L; ++l) op->lvl_off[l + 1] = op->lvl_off[l] + ((int64_t)op->D.P << (2 * l));
@@ -249,7 +252,7 @@ int ige_op_plan(ige_geom geom, const ige_params *prm, ige_op *out)
         op->prm = *prm;
         op->assembled = false;
         try {
-            ige::NearPattern A;
+            ige::NearBlocks A;
             std::vector<ige::SingularPair> sing;
             plan(op, geom, A, sing);
         } catch (...) {
@@ -277,7 +280,7 @@ int ige_op_assemble(ige_geom geom, const ige_params *prm, ige_op *out)
         op->ctx = ctx;
         op->prm = P;
         try {
-            ige::NearPattern A;
+            ige::NearBlocks A;
             std::vector<ige::SingularPair> sing;
             plan(op, geom, A, sing);
             op->assembled = true;
@@ -319,23 +322,26 @@ int ige_op_assemble(ige_geom geom, const ige_params *prm, ige_op *out)
             const int64_t E = (int64_t)D.P * D.n * D.n;
             op->d_eX.alloc((size_t)E * 3 * v.G2);
             op->d_ePsi.alloc((size_t)E * 4 * v.nl * v.G2);
+            const size_t fragE = ige::psi_fragment_doubles(v.nl, v.G2);
+            op->d_ePsiF.alloc((size_t)E * fragE);
+            IGE_HIP(hipMemsetAsync(op->d_ePsiF.p, 0, sizeof(double) * E * fragE, s));
             op->d_eC.alloc((size_t)E * 12);
-            v.eX = op->d_eX.p; v.ePsi = op->d_ePsi.p; v.eC = op->d_eC.p;
+            v.eX = op->d_eX.p; v.ePsi = op->d_ePsi.p; v.ePsiF = op->d_ePsiF.p; v.eC = op->d_eC.p;
             ige::launch_element_data(op);
-            // near-field pattern and quadrature
-            op->d_rowptr.upload(A.rowptr, s);
-            op->d_col.upload(A.col, s);
-            op->d_val.alloc(op->nnz);
-            IGE_HIP(hipMemsetAsync(op->d_val.p, 0, sizeof(double2) * op->nnz, s));
-            v.rowptr = op->d_rowptr.p; v.col = op->d_col.p; v.val = op->d_val.p;
+            // near-field blocks and quadrature
+            v.W = A.W; v.nF = A.nF; v.nch = A.nch; v.rc = A.rc; v.nblk = A.nblk();
+            op->d_bpair.upload(A.pair, s);
+            op->d_leafdof.upload(A.leafdof, s);
+            op->d_leafsgn.upload(A.leafsgn, s);
+            op->d_red_ptr.upload(A.red_ptr, s);
+            op->d_red_idx.upload(A.red_idx, s);
+            op->d_bval.alloc(std::max<int64_t>(1, op->nnz));
+            IGE_HIP(hipMemsetAsync(op->d_bval.p, 0, sizeof(double2) * op->nnz, s));
+            op->d_npart.alloc(std::max<int64_t>(1, A.nslots()));
+            v.bpair = op->d_bpair.p; v.bval = op->d_bval.p; v.leafdof = op->d_leafdof.p; v.leafsgn = op->d_leafsgn.p;
+            v.red_ptr = op->d_red_ptr.p; v.red_idx = op->d_red_idx.p;
             op->d_sing.upload(sing, s);
-            std::vector<int32_t> nearflat(T.near.size() * 2);
-            for (size_t i = 0; i < T.near.size(); ++i) {
-                nearflat[2 * i] = T.near[i][0];
-                nearflat[2 * i + 1] = T.near[i][1];
-            }
-            op->d_near.upload(nearflat, s);
-            ige::launch_near_regular(op, (int64_t)T.near.size());
+            ige::launch_near_regular(op);
             ige::launch_near_singular(op);
             // cluster tree and far field
             op->d_lvl_off.upload(op->lvl_off, s);
@@ -394,7 +400,7 @@ int ige_op_assemble(ige_geom geom, const ige_params *prm, ige_op *out)
             IGE_HIP(hipStreamSynchronize(s));
             int err = 0;
             IGE_HIP(hipMemcpy(&err, op->d_err.p, sizeof(int), hipMemcpyDeviceToHost));
-            IGE_REQUIRE(err == 0, "near-field assembly produced entries outside the sparsity pattern");
+            IGE_REQUIRE(err == 0, "near-field assembly produced entries outside the leaf function slots");
         } catch (...) {
             delete op;
             throw;
@@ -443,8 +449,10 @@ int ige_op_info(ige_op op, ige_op_info_t *out)
         size_t b = 0;
         b += op->d_hdr.bytes() + op->d_brk.bytes() + op->d_cp.bytes() + op->d_dof.bytes() + op->d_sgn.bytes();
         b += op->d_ext_p.bytes() + op->d_ext_q.bytes() + op->d_eX.bytes() + op->d_ePsi.bytes() + op->d_eC.bytes();
-        b += op->d_rowptr.bytes() + op->d_col.bytes() + op->d_val.bytes() + op->d_nodeX.bytes() + op->d_nodeT.bytes();
-        b += op->d_Mp.bytes() * 3 + op->d_inc.bytes() + op->d_sing.bytes() + op->d_near.bytes() + op->d_work.bytes();
+        b += op->d_ePsiF.bytes() + op->d_bpair.bytes() + op->d_leafdof.bytes() + op->d_leafsgn.bytes();
+        b += op->d_red_ptr.bytes() + op->d_red_idx.bytes() + op->d_bval.bytes() + op->d_npart.bytes() + op->d_bnpart.bytes();
+        b += op->d_nodeX.bytes() + op->d_nodeT.bytes();
+        b += op->d_Mp.bytes() * 3 + op->d_inc.bytes() + op->d_sing.bytes() + op->d_work.bytes();
         b += op->d_partner.bytes() + op->d_mom.bytes() + op->d_src.bytes() + op->d_loc.bytes() + op->d_part.bytes();
         b += op->d_x.bytes() + op->d_y.bytes() + op->d_V.bytes() + op->d_w.bytes() + op->d_r.bytes();
         r.device_bytes = (int64_t)b;
@@ -545,6 +553,7 @@ void ensure_batched(ige_op op, int r)
     op->d_bpart.alloc(std::max<size_t>(1, op->work.size()) * 4 * Q * r);
     op->d_bybuf.alloc((size_t)v.P * v.SL * v.SL * 2 * v.rowlen * v.rowlen * r);
     op->d_bxt.alloc((size_t)v.N * r);
+    op->d_bnpart.alloc(std::max<size_t>(1, (size_t)v.nblk * v.nF * (1 + v.nch)) * 4);
     op->d_byt.alloc((size_t)v.N * r);
     op->bcap = r;
 }

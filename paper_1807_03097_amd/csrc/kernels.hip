@@ -3,13 +3,15 @@
 //   a0  element_data / node_geometry : geometry from the rational Bezier form at the
 //       regular Gauss points of every element and at the Chebyshev nodes of every cluster
 //   a1  near_regular / near_singular : element-pair Galerkin quadrature of the near field,
-//       accumulated into the glued CSR matrix
+//       accumulated into dense blocks over leaf function slots (regular pairs on the
+//       FP64 matrix cores)
 //   a3  p2m   leaf moments, fused with the gather x_super = T x (1-D factors of T)
 //   a4  m2m   upward transfer of the moments (nested cluster bases)
 //   a5  m2l   coupling of admissible cluster pairs with the interpolated kernel
 //   a6  l2l   downward transfer
 //   a7  l2p   test-side moments, fused with the scatter T^T
-//   a8  spmv  near-field product
+//   a8  near_blk + near_gather: near-field product over the stored blocks and their
+//       transposes, then a fixed-order sum per unknown
 //   a9  rhs   plane-wave right-hand side
 //   a10 GMRES vector kernels
 #include <hip/hip_runtime.h>
@@ -24,6 +26,7 @@ namespace ige {
 namespace {
 
 constexpr int kWave = 64;
+typedef double dx4 __attribute__((ext_vector_type(4)));   // FP64 matrix-core accumulator
 __device__ __constant__ double kInv4Pi = 0.07957747154594767;   // 1/(4 pi)
 
 __device__ inline double2 cmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
@@ -88,6 +91,116 @@ __device__ inline void spline_pieces(const DevOp &o, int e, double x, double *Pv
         for (int a = 0; a < p; ++a) v += c[a] * Bq[a];
         Qv[t] = v;
     }
+}
+
+// Fixed-degree variants (fully unrolled, no scratch): Bernstein values and
+// derivatives, spline pieces and rational Bezier patch evaluation.
+template <int DEG>
+__device__ inline void bernstein_t(double x, double *B, double *D)
+{
+    if constexpr (DEG == 0) {
+        B[0] = 1.0;
+        D[0] = 0.0;
+    } else {
+        double T[DEG];
+        T[0] = 1.0;
+#pragma unroll
+        for (int k = 1; k < DEG; ++k) {
+            T[k] = x * T[k - 1];
+#pragma unroll
+            for (int i = k - 1; i >= 1; --i) T[i] = (1.0 - x) * T[i] + x * T[i - 1];
+            T[0] = (1.0 - x) * T[0];
+        }
+#pragma unroll
+        for (int i = 0; i <= DEG; ++i) {
+            const double lo = (i >= 1) ? T[i >= 1 ? i - 1 : 0] : 0.0;
+            const double hi = (i <= DEG - 1) ? T[i <= DEG - 1 ? i : 0] : 0.0;
+            D[i] = DEG * (lo - hi);
+            B[i] = (1.0 - x) * hi + x * lo;
+        }
+    }
+}
+
+template <int P>
+__device__ inline void spline_pieces_t(const DevOp &o, int e, double x, double *Pv, double *Pd, double *Qv)
+{
+    double B[P + 1], D[P + 1];
+    bernstein_t<P>(x, B, D);
+#pragma unroll
+    for (int t = 0; t <= P; ++t) {
+        double v = 0.0, d = 0.0;
+        const double *c = o.ext_p + ((size_t)e * (P + 1) + t) * (P + 1);
+#pragma unroll
+        for (int a = 0; a <= P; ++a) {
+            v += c[a] * B[a];
+            d += c[a] * D[a];
+        }
+        Pv[t] = v;
+        Pd[t] = d / o.h;
+    }
+    double Bq[P], Dq[P];
+    bernstein_t<P - 1>(x, Bq, Dq);
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+        double v = 0.0;
+        const double *c = o.ext_q + ((size_t)e * P + t) * P;
+#pragma unroll
+        for (int a = 0; a < P; ++a) v += c[a] * Bq[a];
+        Qv[t] = v;
+    }
+}
+
+template <int PU, int PV>
+__device__ inline void bezier_eval_t(const GeomView &g, const PatchHdr &h, double u, double v, double X[3],
+                                     double Xu[3], double Xv[3])
+{
+    int su = 0, sv = 0;
+    while (su < h.su - 1 && u >= g.brk[h.brk_u + su + 1]) ++su;
+    while (sv < h.sv - 1 && v >= g.brk[h.brk_v + sv + 1]) ++sv;
+    const double ua = g.brk[h.brk_u + su], ub = g.brk[h.brk_u + su + 1];
+    const double va = g.brk[h.brk_v + sv], vb = g.brk[h.brk_v + sv + 1];
+    const double t = (u - ua) / (ub - ua), s = (v - va) / (vb - va);
+    double Bu[PU + 1], Du[PU + 1], Bv[PV + 1], Dv[PV + 1];
+    bernstein_t<PU>(t, Bu, Du);
+    bernstein_t<PV>(s, Bv, Dv);
+    const double *c = g.cp + h.cp + (size_t)(sv * h.su + su) * (PV + 1) * (PU + 1) * 4;
+    double A[4] = {0, 0, 0, 0}, Au[4] = {0, 0, 0, 0}, Av[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int j2 = 0; j2 <= PV; ++j2)
+#pragma unroll
+        for (int j1 = 0; j1 <= PU; ++j1) {
+            const double *Pc = c + (j2 * (PU + 1) + j1) * 4;
+            const double b = Bu[j1] * Bv[j2], bu = Du[j1] * Bv[j2], bv = Bu[j1] * Dv[j2];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                A[k] += b * Pc[k];
+                Au[k] += bu * Pc[k];
+                Av[k] += bv * Pc[k];
+            }
+        }
+    const double iw = 1.0 / A[3], du = 1.0 / (ub - ua), dv = 1.0 / (vb - va);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        X[k] = A[k] * iw;
+        Xu[k] = (Au[k] - X[k] * Au[3]) * iw * du;
+        Xv[k] = (Av[k] - X[k] * Av[3]) * iw * dv;
+    }
+}
+
+// other degrees: out of line, so that its stack arrays do not enlarge the callers
+__device__ __noinline__ void geom_eval_generic(const GeomView &g, int j, double u, double v, double X[3], double Xu[3],
+                                               double Xv[3])
+{
+    bezier_eval(g, j, u, v, X, Xu, Xv);
+}
+
+// patch evaluation with unrolled paths for bilinear and biquadratic patches
+__device__ inline void geom_eval(const GeomView &g, int j, double u, double v, double X[3], double Xu[3], double Xv[3])
+{
+    const PatchHdr h = g.hdr[j];
+    if (h.pu == 2 && h.pv == 2) bezier_eval_t<2, 2>(g, h, u, v, X, Xu, Xv);
+    else if (h.pu == 1 && h.pv == 1) bezier_eval_t<1, 1>(g, h, u, v, X, Xu, Xv);
+    else geom_eval_generic(g, j, u, v, X, Xu, Xv);
 }
 
 // local glued function l of an element: (component, t1, t2)
@@ -164,6 +277,30 @@ __device__ inline void local_values_lds(const DevOp &o, int e1, int e2, double x
     }
 }
 
+// (Phi_l, cdiv * div_l) for the NL = 2P(P+1) local functions, into rows of shared memory
+template <int P>
+__device__ inline void local_values_lds_t(const DevOp &o, int e1, int e2, double x, double y, const double Fu[3],
+                                          const double Fv[3], double cdiv, double (*dst)[4])
+{
+    constexpr int NL = 2 * P * (P + 1);
+    double Pu[P + 1], dPu[P + 1], Qu[P], Pv[P + 1], dPv[P + 1], Qv[P];
+    spline_pieces_t<P>(o, e1, x, Pu, dPu, Qu);
+    spline_pieces_t<P>(o, e2, y, Pv, dPv, Qv);
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+        const bool a0 = l < P * (P + 1);
+        const int r = a0 ? l : l - P * (P + 1);
+        const int t2 = a0 ? r / (P + 1) : r / P, t1 = a0 ? r % (P + 1) : r % P;
+        const double val = a0 ? Pu[t1] * Qv[t2] : Qu[t1] * Pv[t2];
+        const double div = a0 ? dPu[t1] * Qv[t2] : Qu[t1] * dPv[t2];
+        const double *F = a0 ? Fu : Fv;
+        dst[l][0] = val * F[0];
+        dst[l][1] = val * F[1];
+        dst[l][2] = val * F[2];
+        dst[l][3] = cdiv * div;
+    }
+}
+
 __device__ inline void elem_of(const DevOp &o, int64_t e, int &j, int &e1, int &e2)
 {
     const int nn = o.n * o.n;
@@ -182,30 +319,43 @@ __device__ inline void local_dof(const DevOp &o, int j, int e1, int e2, int l, i
     sg = (double)o.sgn[off];
 }
 
-// CSR accumulate A[i][j] += v
-__device__ inline void csr_add(const DevOp &o, int i, int jcol, double2 v)
+// leaf cluster of element (j, e1, e2) and the leaf-local slot of its local function l
+__device__ inline int leaf_of(const DevOp &o, int j, int e1, int e2)
 {
-    int64_t lo = o.rowptr[i], hi = o.rowptr[i + 1] - 1;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (o.col[mid] < jcol) lo = mid + 1;
-        else hi = mid;
-    }
-    // the pattern contains every (i, j) of a near element pair
-    if (o.col[lo] != jcol) {
-        atomicAdd(o.err, 1);
-        return;
-    }
-    double *dst = reinterpret_cast<double *>(o.val + lo);
-    atomicAdd(dst, v.x);
-    atomicAdd(dst + 1, v.y);
+    return (j * o.SL + e2 / o.s) * o.SL + e1 / o.s;
 }
+__device__ inline int elem_slot(const DevOp &o, int e1, int e2, int l)
+{
+    int a, t1, t2;
+    local_index(o.p, l, a, t1, t2);
+    return leaf_slot(o.W, a, e1 % o.s + t1, e2 % o.s + t2);
+}
+
+// block entry B_b[kr][kc] += s_r s_c v (signs of the glued unknowns folded in)
+__device__ inline void blk_add(const DevOp &o, int64_t b, int lt, int ls, int kr, int kc, double2 v)
+{
+    const int nF = o.nF;
+    const double sg = (double)o.leafsgn[(size_t)lt * nF + kr] * (double)o.leafsgn[(size_t)ls * nF + kc];
+    if (sg == 0.0) return;   // slot without an unknown
+    double *dst = reinterpret_cast<double *>(o.bval + ((size_t)b * nF + kr) * nF + kc);
+    atomicAdd(dst, sg * v.x);
+    atomicAdd(dst + 1, sg * v.y);
+}
+
+// FP64 matrix-core instruction 16x16x4: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; accumulator register j of lane l holds D[l / 16 + 4 j][l % 16].
+// Operand order: for step t a lane supplies the entry with quadrature index
+// q = frag_q(t, lane) in reduction slot lane / 16, so that accumulator register j of
+// a first product over tile qt is the operand of step t = 4 qt + j of a second.
+__device__ inline int frag_q(int t, int lane) { return 16 * (t >> 2) + 4 * (t & 3) + (lane >> 4); }
 
 // ---------------------------------------------------------------------------
 // a0: element data at the regular Gauss points
 // ---------------------------------------------------------------------------
+// ePsiF[e][c][lt][t][lane] = ePsi[e][c][16 lt + lane % 16][frag_q(t, lane)] (zero padded
+// to 16-row tiles in l and to 4*QT steps in q, QT = ceil(G2 / 16))
 template <int NL>
-__global__ void k_element_data(DevOp o, double *eX, double *ePsi, double *eC)
+__global__ void k_element_data(DevOp o, double *eX, double *ePsi, double *ePsiF, double *eC)
 {
     const int64_t e = blockIdx.x;
     int j, e1, e2;
@@ -221,9 +371,16 @@ __global__ void k_element_data(DevOp o, double *eX, double *ePsi, double *eC)
         double Phi[NL][3], Dv[NL];
         local_values<NL>(o, e1, e2, x, y, Fu, Fv, Phi, Dv);
         for (int d = 0; d < 3; ++d) eX[((size_t)e * 3 + d) * G2 + q] = X[d];
+        constexpr int LT = (NL + 15) / 16;
+        const int T = 4 * ((G2 + 15) / 16);
+        const int t = 4 * (q / 16) + (q % 16) / 4, lq = 16 * (q % 4);
+        double *F = ePsiF + (size_t)e * 4 * LT * T * 64;
         for (int l = 0; l < NL; ++l) {
             for (int d = 0; d < 3; ++d) ePsi[(((size_t)e * 4 + d) * NL + l) * G2 + q] = w * Phi[l][d];
             ePsi[(((size_t)e * 4 + 3) * NL + l) * G2 + q] = w * Dv[l];
+            const int lt = l / 16, lane = l % 16 + lq;
+            for (int d = 0; d < 3; ++d) F[((d * LT + lt) * T + t) * 64 + lane] = w * Phi[l][d];
+            F[((3 * LT + lt) * T + t) * 64 + lane] = w * Dv[l];
         }
     }
     if (threadIdx.x < 4) {
@@ -269,109 +426,166 @@ __device__ inline bool share_corner(const DevOp &o, int64_t e, int64_t f)
 }
 
 // ---------------------------------------------------------------------------
-// a1: regular element pairs (no shared corner), one wavefront per element pair.
-//   B[l][l'] = sum_c S_c sum_q Psi_l^c(q) sum_q' K(q,q') Psi'_l'^c(q'),
-//   S = (1, 1, 1, -kappa^-2), weights folded into Psi.
+// a1: regular element pairs (no shared corner).  With S = (1, 1, 1, -kappa^-2) and
+// the weights folded into Psi,
+//   B[l][l'] = sum_c S_c sum_q Psi_e^c[l][q] sum_q' K(q, q') Psi_f^c[l'][q'],
+// computed as two products on the FP64 matrix cores per trial element f:
+//   Y_c(q', l) = sum_q K(q, q') Psi_e^c[l][q]      (K as operand A, Psi_e as B)
+//   B(l, l') += sum_q' Y_c(q', l) Psi_f^c[l'][q']  (Y from the accumulators as A)
+// The accumulator layout of the first product (row lane/16 + 4 j) is the operand
+// layout of the second when its reduction slots are ordered by frag_q.
+// A workgroup takes one block, one test element e of the target leaf and a square
+// of sb x sb trial elements of the source leaf (one wave per trial element at a
+// time); the block rows of e are summed in shared memory, then added to the block.
 // ---------------------------------------------------------------------------
-constexpr int kQB = 16;   // test points per LDS block of kernel values
-
-template <int NL>
-__global__ __launch_bounds__(64) void k_near_regular(DevOp o, const int32_t *near)
+template <int NL, int QT>
+__global__ __launch_bounds__(256) void k_near_regular(DevOp o, int sb)
 {
-    extern __shared__ double smem[];
-    const int s2 = o.s * o.s;
-    const int64_t blk = blockIdx.x;
-    const int64_t lp = blk / ((int64_t)s2 * s2);
-    const int r = (int)(blk % ((int64_t)s2 * s2));
-    const int ti = r / s2, tj = r % s2;
-    const int lt = near[2 * lp], ls = near[2 * lp + 1];
+    constexpr int LT = (NL + 15) / 16, T = 4 * QT;
+    extern __shared__ double2 sacc[];                 // [NL][2 Wsb^2]
+    __shared__ double sXe[3][16 * QT];                // test element points (zero padded)
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int s = o.s, s2 = s * s, nsb = s / sb, Wsb = sb + o.p, nslot = 2 * Wsb * Wsb;
+    int64_t blk = blockIdx.x;
+    const int sub = (int)(blk % (nsb * nsb));
+    blk /= nsb * nsb;
+    const int ti = (int)(blk % s2);
+    const int64_t b = blk / s2;
+    const int lt = o.bpair[2 * b], ls = o.bpair[2 * b + 1];
     const int SL = o.SL;
-    const int jt = lt / (SL * SL), jr = lt % (SL * SL);
-    const int js = ls / (SL * SL), jsr = ls % (SL * SL);
-    const int te1 = (jr % SL) * o.s + ti % o.s, te2 = (jr / SL) * o.s + ti / o.s;
-    const int fe1 = (jsr % SL) * o.s + tj % o.s, fe2 = (jsr / SL) * o.s + tj / o.s;
+    const int jt = lt / (SL * SL), jr = lt % (SL * SL), js = ls / (SL * SL), jsr = ls % (SL * SL);
+    const int tl1 = ti % s, tl2 = ti / s;                       // e inside its leaf
+    const int te1 = (jr % SL) * s + tl1, te2 = (jr / SL) * s + tl2;
+    const int sl1 = (sub % nsb) * sb, sl2 = (sub / nsb) * sb;   // trial square inside its leaf
+    const int fx0 = (jsr % SL) * s + sl1, fy0 = (jsr / SL) * s + sl2;
     const int64_t e = ((int64_t)jt * o.n + te2) * o.n + te1;
-    const int64_t f = ((int64_t)js * o.n + fe2) * o.n + fe1;
-    if (share_corner(o, e, f)) return;   // handled by the singular kernel
-
-    const int G2 = o.G2, lane = threadIdx.x;
-    double *Xa = smem;                    // [3][G2]
-    double *Xb = Xa + 3 * G2;             // [3][G2]
-    double2 *K = reinterpret_cast<double2 *>(Xb + 3 * G2);   // [kQB][G2]
-    double2 *part = K + kQB * G2;         // [4][NL][NL]
-    for (int i = lane; i < 3 * G2; i += kWave) {
-        Xa[i] = o.eX[e * 3 * G2 + i];
-        Xb[i] = o.eX[f * 3 * G2 + i];
+    const int G2 = o.G2;
+    for (int i = threadIdx.x; i < NL * nslot; i += blockDim.x) sacc[i] = make_double2(0.0, 0.0);
+    for (int i = threadIdx.x; i < 3 * 16 * QT; i += blockDim.x) {
+        const int d = i / (16 * QT), q = i % (16 * QT);
+        sXe[d][q] = q < G2 ? o.eX[(e * 3 + d) * G2 + q] : 0.0;
     }
-    const double *Pa = o.ePsi + e * 4 * NL * G2;
-    const double *Pb = o.ePsi + f * 4 * NL * G2;
+    constexpr size_t FE = (size_t)4 * LT * T * 64;
     const double ik2 = 1.0 / (o.kappa * o.kappa);
-
-    constexpr int NC = 4 * NL;
-    constexpr int NPL = (NC + kWave - 1) / kWave;   // combos per lane
-    double2 acc[NPL][NL];
+    double pa[4][LT][T];
+    {
+        const double *Fe = o.ePsiF + (size_t)e * FE;
 #pragma unroll
-    for (int c = 0; c < NPL; ++c)
+        for (int c = 0; c < 4; ++c)
 #pragma unroll
-        for (int l = 0; l < NL; ++l) acc[c][l] = make_double2(0.0, 0.0);
+            for (int u = 0; u < LT; ++u)
+#pragma unroll
+                for (int t = 0; t < T; ++t)
+                    pa[c][u][t] = Fe[((c * LT + u) * T + t) * 64 + lane] * (c == 3 ? -ik2 : 1.0);
+    }
     __syncthreads();
-    for (int q0 = 0; q0 < G2; q0 += kQB) {
-        const int nq = min(kQB, G2 - q0);
-        for (int i = lane; i < nq * G2; i += kWave) {
-            const int qa = q0 + i / G2, qb = i % G2;
-            const double d0 = Xa[qa] - Xb[qb], d1 = Xa[G2 + qa] - Xb[G2 + qb], d2 = Xa[2 * G2 + qa] - Xb[2 * G2 + qb];
-            K[i] = dm::helmholtz_r2(o.kappa, fma(d0, d0, fma(d1, d1, d2 * d2)));
-        }
-        __syncthreads();
+    for (int fi = wv; fi < sb * sb; fi += 4) {
+        const int fe1 = fx0 + fi % sb, fe2 = fy0 + fi / sb;
+        const int64_t f = ((int64_t)js * o.n + fe2) * o.n + fe1;
+        if (share_corner(o, e, f)) continue;   // handled by the singular kernel
+        // kernel values as operand A: row q' = 16 qt + lane % 16, slot q = frag_q(t, lane)
+        double kre[QT][T], kim[QT][T];
 #pragma unroll
-        for (int cc = 0; cc < NPL; ++cc) {
-            const int combo = lane + cc * kWave;
-            if (combo < NC) {
-                const int c = combo / NL, lb = combo % NL;
-                const double *pb = Pb + ((size_t)c * NL + lb) * G2;
-                for (int qq = 0; qq < nq; ++qq) {
-                    double2 z = make_double2(0.0, 0.0);
-                    const double2 *Kr = K + qq * G2;
-                    for (int qb = 0; qb < G2; ++qb) {
-                        const double w = pb[qb];
-                        z.x += Kr[qb].x * w;
-                        z.y += Kr[qb].y * w;
-                    }
-                    const double *pa = Pa + (size_t)c * NL * G2 + q0 + qq;
+        for (int qt = 0; qt < QT; ++qt) {
+            const int qb = 16 * qt + (lane & 15);
+            const bool okb = qb < G2;
+            double xb0 = 0.0, xb1 = 0.0, xb2 = 0.0;
+            if (okb) {
+                xb0 = o.eX[(f * 3 + 0) * G2 + qb];
+                xb1 = o.eX[(f * 3 + 1) * G2 + qb];
+                xb2 = o.eX[(f * 3 + 2) * G2 + qb];
+            }
 #pragma unroll
-                    for (int l = 0; l < NL; ++l) {
-                        const double a = pa[(size_t)l * G2];
-                        acc[cc][l].x += a * z.x;
-                        acc[cc][l].y += a * z.y;
-                    }
+            for (int t = 0; t < T; ++t) {
+                const int qa = frag_q(t, lane);
+                double2 K = make_double2(0.0, 0.0);
+                if (okb && qa < G2) {
+                    const double d0 = sXe[0][qa] - xb0, d1 = sXe[1][qa] - xb1, d2 = sXe[2][qa] - xb2;
+                    K = dm::helmholtz_r2(o.kappa, fma(d0, d0, fma(d1, d1, d2 * d2)));
                 }
+                kre[qt][t] = K.x;
+                kim[qt][t] = K.y;
             }
         }
-        __syncthreads();
-    }
+        dx4 br[LT][LT], bi[LT][LT];
 #pragma unroll
-    for (int cc = 0; cc < NPL; ++cc) {
-        const int combo = lane + cc * kWave;
-        if (combo < NC) {
-            const int c = combo / NL, lb = combo % NL;
-            const double sc = (c == 3) ? -ik2 : 1.0;
+        for (int u = 0; u < LT; ++u)
 #pragma unroll
-            for (int l = 0; l < NL; ++l) part[((size_t)c * NL + l) * NL + lb] = cscale(sc, acc[cc][l]);
+            for (int v = 0; v < LT; ++v) {
+                br[u][v] = dx4{0.0, 0.0, 0.0, 0.0};
+                bi[u][v] = dx4{0.0, 0.0, 0.0, 0.0};
+            }
+        const double *Ff = o.ePsiF + (size_t)f * FE;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            dx4 yr[QT][LT], yi[QT][LT];
+#pragma unroll
+            for (int qt = 0; qt < QT; ++qt)
+#pragma unroll
+                for (int u = 0; u < LT; ++u) {
+                    yr[qt][u] = dx4{0.0, 0.0, 0.0, 0.0};
+                    yi[qt][u] = dx4{0.0, 0.0, 0.0, 0.0};
+                }
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+#pragma unroll
+                for (int qt = 0; qt < QT; ++qt)
+#pragma unroll
+                    for (int u = 0; u < LT; ++u) {
+                        yr[qt][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(kre[qt][t], pa[c][u][t], yr[qt][u], 0, 0, 0);
+                        yi[qt][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(kim[qt][t], pa[c][u][t], yi[qt][u], 0, 0, 0);
+                    }
+#pragma unroll
+            for (int v = 0; v < LT; ++v)
+#pragma unroll
+                for (int qt = 0; qt < QT; ++qt)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const double pb = Ff[((c * LT + v) * T + 4 * qt + j) * 64 + lane];
+#pragma unroll
+                        for (int u = 0; u < LT; ++u) {
+                            br[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(yr[qt][u][j], pb, br[u][v], 0, 0, 0);
+                            bi[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(yi[qt][u][j], pb, bi[u][v], 0, 0, 0);
+                        }
+                    }
+        }
+        // rows l = 16 u + lane / 16 + 4 j, columns l' = 16 v + lane % 16
+#pragma unroll
+        for (int v = 0; v < LT; ++v) {
+            const int lb = 16 * v + (lane & 15);
+            if (lb >= NL) continue;
+            int a, t1, t2;
+            local_index(o.p, lb, a, t1, t2);
+            const int slot = a * Wsb * Wsb + (fe2 - fy0 + t2) * Wsb + (fe1 - fx0 + t1);
+#pragma unroll
+            for (int u = 0; u < LT; ++u)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int l = 16 * u + (lane >> 4) + 4 * j;
+                    if (l < NL) {
+                        atomicAdd(&sacc[l * nslot + slot].x, br[u][v][j]);
+                        atomicAdd(&sacc[l * nslot + slot].y, bi[u][v][j]);
+                    }
+                }
         }
     }
     __syncthreads();
-    int jtp, a1, a2, jsp, b1, b2;
-    elem_of(o, e, jtp, a1, a2);
-    elem_of(o, f, jsp, b1, b2);
-    for (int i = lane; i < NL * NL; i += kWave) {
-        const int l = i / NL, lb = i % NL;
-        double2 v = make_double2(0.0, 0.0);
-        for (int c = 0; c < 4; ++c) v = cadd(v, part[((size_t)c * NL + l) * NL + lb]);
-        int ri, cj;
-        double sr, sc;
-        local_dof(o, jtp, a1, a2, l, ri, sr);
-        local_dof(o, jsp, b1, b2, lb, cj, sc);
-        csr_add(o, ri, cj, cscale(sr * sc, v));
+    const int W = o.W;
+    for (int i = threadIdx.x; i < NL * nslot; i += blockDim.x) {
+        const double2 v = sacc[i];
+        if (v.x == 0.0 && v.y == 0.0) continue;
+        const int l = i / nslot, sl = i % nslot;
+        const int a = sl / (Wsb * Wsb), r = sl % (Wsb * Wsb);
+        const int i1 = sl1 + r % Wsb, i2 = sl2 + r / Wsb;
+        if (i1 >= (a == 0 ? W : W - 1) || i2 >= (a == 0 ? W - 1 : W)) {
+            atomicAdd(o.err, 1);
+            continue;
+        }
+        const int kc = leaf_slot(W, a, i1, i2);
+        int ar, t1, t2;
+        local_index(o.p, l, ar, t1, t2);
+        const int kr = leaf_slot(W, ar, tl1 + t1, tl2 + t2);
+        blk_add(o, b, lt, ls, kr, kc, v);
     }
 }
 
@@ -436,17 +650,22 @@ __device__ inline void singular_point(const DevOp &o, int kind, int idx, double 
     }
 }
 
-// Singular pairs: the points of the sub-rules are processed in batches of 64; in a
-// batch every lane evaluates geometry, local basis and kernel at one point into
-// LDS, then the lanes accumulate the block entries over the batch.
-template <int NL>
+// Singular pairs: one wave per pair.  The points of the sub-rules are processed in
+// batches of 32: the lower half-wave evaluates geometry and local values on the
+// test element, the upper half on the trial element, into shared memory; then
+//   B[l][l'] += sum_q K_q sum_c Psi_a[q][l][c] Psi_b[q][l'][c]
+// runs on the FP64 matrix cores with the four components c as the reduction slots
+// of one instruction per point (K_q = weight * kernel folded into the test side).
+template <int P>
 __global__ __launch_bounds__(64) void k_near_singular(DevOp o, const SingularPair *list)
 {
-    __shared__ double sPa[kWave][NL][4];   // test side:  w*K-independent values Phi (3), div
-    __shared__ double sPb[kWave][NL][4];   // trial side
-    __shared__ double2 sK[kWave];          // weight * kernel
+    constexpr int NL = 2 * P * (P + 1), LT = (NL + 15) / 16, NB = 32;
+    __shared__ double sPa[NB][NL][4];
+    __shared__ double sPb[NB][NL][4];
+    __shared__ double2 sK[NB];
+    __shared__ double sX[NB][3];
     const SingularPair sp = list[blockIdx.x];
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x, half = lane >> 5, qi = lane & 31;
     int ja, a1, a2, jb, b1, b2;
     elem_of(o, sp.e, ja, a1, a2);
     elem_of(o, sp.f, jb, b1, b2);
@@ -454,15 +673,21 @@ __global__ __launch_bounds__(64) void k_near_singular(DevOp o, const SingularPai
     const int nsub = sp.kind == 1 ? 8 : (sp.kind == 2 ? 6 : 4);
     const int npts = nsub * g4;
     const double ik2 = 1.0 / (o.kappa * o.kappa), h4 = o.h * o.h * o.h * o.h;
-    constexpr int NE = (NL * NL + kWave - 1) / kWave;   // block entries per lane
-    double2 acc[NE];
+    dx4 br[LT][LT], bi[LT][LT];
 #pragma unroll
-    for (int t = 0; t < NE; ++t) acc[t] = make_double2(0.0, 0.0);
-    for (int p0 = 0; p0 < npts; p0 += kWave) {
-        const int pt = p0 + lane;
+    for (int u = 0; u < LT; ++u)
+#pragma unroll
+        for (int v = 0; v < LT; ++v) {
+            br[u][v] = dx4{0.0, 0.0, 0.0, 0.0};
+            bi[u][v] = dx4{0.0, 0.0, 0.0, 0.0};
+        }
+    const int c = lane >> 4, m = lane & 15;
+    for (int p0 = 0; p0 < npts; p0 += NB) {
+        const int pt = p0 + qi;
+        double X[3] = {0.0, 0.0, 0.0}, wt = 0.0;
         __syncthreads();   // the previous batch has been consumed
         if (pt < npts) {
-            double s1, s2, t1, t2, wt;
+            double s1, s2, t1, t2;
             singular_point(o, sp.kind, pt, s1, s2, t1, t2, wt);
             double xa, ya, xb, yb;
             if (sp.kind == 1) {
@@ -471,44 +696,60 @@ __global__ __launch_bounds__(64) void k_near_singular(DevOp o, const SingularPai
                 frame_map(sp.fa, s1, s2, xa, ya);
                 frame_map(sp.fb, t1, t2, xb, yb);
             }
-            double XA[3], XB[3], Fu[3], Fv[3];
-            bezier_eval(o.geo, ja, (a1 + xa) * o.h, (a2 + ya) * o.h, XA, Fu, Fv);
-            local_values_lds<NL>(o, a1, a2, xa, ya, Fu, Fv, -ik2, sPa[lane]);
-            bezier_eval(o.geo, jb, (b1 + xb) * o.h, (b2 + yb) * o.h, XB, Fu, Fv);
-            local_values_lds<NL>(o, b1, b2, xb, yb, Fu, Fv, 1.0, sPb[lane]);
-            const double d0 = XA[0] - XB[0], d1 = XA[1] - XB[1], d2 = XA[2] - XB[2];
-            sK[lane] = cscale(wt * h4, dm::helmholtz_r2(o.kappa, fma(d0, d0, fma(d1, d1, d2 * d2))));
-        }
-        __syncthreads();
-        const int nb = min(kWave, npts - p0);
-#pragma unroll
-        for (int t = 0; t < NE; ++t) {
-            const int ent = lane + t * kWave;
-            if (ent < NL * NL) {
-                const int l = ent / NL, lb = ent % NL;
-                double2 a = acc[t];
-                for (int q = 0; q < nb; ++q) {
-                    const double gsum = sPa[q][l][0] * sPb[q][lb][0] + sPa[q][l][1] * sPb[q][lb][1] +
-                                        sPa[q][l][2] * sPb[q][lb][2] + sPa[q][l][3] * sPb[q][lb][3];
-                    a.x = fma(sK[q].x, gsum, a.x);
-                    a.y = fma(sK[q].y, gsum, a.y);
-                }
-                acc[t] = a;
+            double Fu[3], Fv[3];
+            if (half == 0) {
+                geom_eval(o.geo, ja, (a1 + xa) * o.h, (a2 + ya) * o.h, X, Fu, Fv);
+                local_values_lds_t<P>(o, a1, a2, xa, ya, Fu, Fv, -ik2, sPa[qi]);
+            } else {
+                geom_eval(o.geo, jb, (b1 + xb) * o.h, (b2 + yb) * o.h, X, Fu, Fv);
+                local_values_lds_t<P>(o, b1, b2, xb, yb, Fu, Fv, 1.0, sPb[qi]);
+                sX[qi][0] = X[0];
+                sX[qi][1] = X[1];
+                sX[qi][2] = X[2];
             }
         }
-    }
+        __syncthreads();
+        if (half == 0) {
+            double2 K = make_double2(0.0, 0.0);
+            if (pt < npts) {
+                const double d0 = X[0] - sX[qi][0], d1 = X[1] - sX[qi][1], d2 = X[2] - sX[qi][2];
+                K = cscale(wt * h4, dm::helmholtz_r2(o.kappa, fma(d0, d0, fma(d1, d1, d2 * d2))));
+            }
+            sK[qi] = K;
+        }
+        __syncthreads();
+        const int nb = min(NB, npts - p0);
+        for (int q = 0; q < nb; ++q) {
+            const double2 K = sK[q];
+            double av[LT], bv[LT];
 #pragma unroll
-    for (int t = 0; t < NE; ++t) {
-        const int ent = lane + t * kWave;
-        if (ent < NL * NL) {
-            const int l = ent / NL, lb = ent % NL;
-            int ri, cj;
-            double sr, sc;
-            local_dof(o, ja, a1, a2, l, ri, sr);
-            local_dof(o, jb, b1, b2, lb, cj, sc);
-            csr_add(o, ri, cj, cscale(sr * sc, acc[t]));
+            for (int u = 0; u < LT; ++u) {
+                const int l = 16 * u + m;
+                av[u] = l < NL ? sPa[q][l][c] : 0.0;
+                bv[u] = l < NL ? sPb[q][l][c] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < LT; ++u)
+#pragma unroll
+                for (int v = 0; v < LT; ++v) {
+                    br[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(K.x * av[u], bv[v], br[u][v], 0, 0, 0);
+                    bi[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(K.y * av[u], bv[v], bi[u][v], 0, 0, 0);
+                }
         }
     }
+    // lane holds B[16 u + lane/16 + 4 j][16 v + lane % 16]
+    const int la = leaf_of(o, ja, a1, a2), lb_ = leaf_of(o, jb, b1, b2);
+#pragma unroll
+    for (int u = 0; u < LT; ++u)
+#pragma unroll
+        for (int v = 0; v < LT; ++v)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int l = 16 * u + (lane >> 4) + 4 * j, lb = 16 * v + (lane & 15);
+                if (l < NL && lb < NL)
+                    blk_add(o, sp.blk, la, lb_, elem_slot(o, a1, a2, l), elem_slot(o, b1, b2, lb),
+                            make_double2(br[u][v][j], bi[u][v][j]));
+            }
 }
 
 // ---------------------------------------------------------------------------
@@ -785,50 +1026,137 @@ __global__ __launch_bounds__(256) void k_l2l(DevOp o, int lvl, double2 *loc)
 }
 
 // ---------------------------------------------------------------------------
-// a8: near-field SpMV, one wavefront per row
+// a8: near-field product.  A workgroup streams rc rows of one stored block B
+// (target leaf t, source leaf s) once: every row gives the row partial
+// (B x_s)[k] and, for t != s, the same loads give the column partials of B^T x_t
+// over the chunk.  Lanes own columns (coalesced 16-byte loads, bypassing the
+// caches); the four waves take every fourth row and combine their column
+// partials in a fixed order.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_spmv(DevOp o, const double2 *x, double2 *y)
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+__device__ inline double wave_sum(double v)
 {
-    const int row = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    const int lane = threadIdx.x % kWave;
-    if (row >= o.N) return;
-    const int64_t b = o.rowptr[row], e = o.rowptr[row + 1];
+#pragma unroll
+    for (int off = kWave / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+template <int U>
+__global__ __launch_bounds__(256) void k_near_blk(DevOp o, const double2 *x, double2 *part)
+{
+    __shared__ double2 sxr[64 * U];
+    __shared__ double2 syc[3][64 * U];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t b = blockIdx.x / o.nch;
+    const int ch = blockIdx.x % o.nch;
+    const int lt = o.bpair[2 * b], ls = o.bpair[2 * b + 1];
+    const int nF = o.nF, r0 = ch * o.rc, r1 = min(nF, r0 + o.rc);
+    d2v xc[U], yc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int c = lane + 64 * u;
+        const int d = c < nF ? o.leafdof[(size_t)ls * nF + c] : -1;
+        const double2 v = d >= 0 ? x[d] : make_double2(0.0, 0.0);
+        xc[u] = d2v{v.x, v.y};
+        yc[u] = d2v{0.0, 0.0};
+    }
+    for (int k = threadIdx.x; k < r1 - r0; k += blockDim.x) {
+        const int d = o.leafdof[(size_t)lt * nF + r0 + k];
+        sxr[k] = d >= 0 ? x[d] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    const d2v *B = reinterpret_cast<const d2v *>(o.bval) + (size_t)b * nF * nF;
+    int r = r0 + wv;
+    // two rows per step: 2U independent streaming loads in flight per lane
+    for (; r + 4 < r1; r += 8) {
+        d2v a0[U], a1[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int c = lane + 64 * u;
+            a0[u] = c < nF ? __builtin_nontemporal_load(B + (size_t)r * nF + c) : d2v{0.0, 0.0};
+            a1[u] = c < nF ? __builtin_nontemporal_load(B + (size_t)(r + 4) * nF + c) : d2v{0.0, 0.0};
+        }
+        const double2 x0 = sxr[r - r0], x1 = sxr[r + 4 - r0];
+        double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            re0 = fma(a0[u].x, xc[u].x, fma(-a0[u].y, xc[u].y, re0));
+            im0 = fma(a0[u].x, xc[u].y, fma(a0[u].y, xc[u].x, im0));
+            re1 = fma(a1[u].x, xc[u].x, fma(-a1[u].y, xc[u].y, re1));
+            im1 = fma(a1[u].x, xc[u].y, fma(a1[u].y, xc[u].x, im1));
+            yc[u].x = fma(a0[u].x, x0.x, fma(-a0[u].y, x0.y, yc[u].x));
+            yc[u].y = fma(a0[u].x, x0.y, fma(a0[u].y, x0.x, yc[u].y));
+            yc[u].x = fma(a1[u].x, x1.x, fma(-a1[u].y, x1.y, yc[u].x));
+            yc[u].y = fma(a1[u].x, x1.y, fma(a1[u].y, x1.x, yc[u].y));
+        }
+        re0 = wave_sum(re0);
+        im0 = wave_sum(im0);
+        re1 = wave_sum(re1);
+        im1 = wave_sum(im1);
+        if (lane == 0) {
+            part[(size_t)b * nF + r] = make_double2(re0, im0);
+            part[(size_t)b * nF + r + 4] = make_double2(re1, im1);
+        }
+    }
+    for (; r < r1; r += 4) {
+        d2v a0[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int c = lane + 64 * u;
+            a0[u] = c < nF ? __builtin_nontemporal_load(B + (size_t)r * nF + c) : d2v{0.0, 0.0};
+        }
+        const double2 x0 = sxr[r - r0];
+        double re0 = 0.0, im0 = 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            re0 = fma(a0[u].x, xc[u].x, fma(-a0[u].y, xc[u].y, re0));
+            im0 = fma(a0[u].x, xc[u].y, fma(a0[u].y, xc[u].x, im0));
+            yc[u].x = fma(a0[u].x, x0.x, fma(-a0[u].y, x0.y, yc[u].x));
+            yc[u].y = fma(a0[u].x, x0.y, fma(a0[u].y, x0.x, yc[u].y));
+        }
+        re0 = wave_sum(re0);
+        im0 = wave_sum(im0);
+        if (lane == 0) part[(size_t)b * nF + r] = make_double2(re0, im0);
+    }
+    if (lt == ls) return;   // diagonal block: no transposed product (uniform branch)
+    if (wv > 0)
+#pragma unroll
+        for (int u = 0; u < U; ++u) syc[wv - 1][lane + 64 * u] = make_double2(yc[u].x, yc[u].y);
+    __syncthreads();
+    if (wv == 0) {
+        double2 *cp = part + (size_t)o.nblk * nF + ((size_t)b * o.nch + ch) * nF;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int c = lane + 64 * u;
+            if (c < nF) {
+                const double2 s1 = syc[0][c], s2 = syc[1][c], s3 = syc[2][c];
+                cp[c] = make_double2(((yc[u].x + s1.x) + s2.x) + s3.x, ((yc[u].y + s1.y) + s2.y) + s3.y);
+            }
+        }
+    }
+}
+
+// y[i] = sum of the partial results of unknown i: 16 lanes take every 16th entry of
+// its list, then a fixed butterfly (the order does not depend on the launch)
+__global__ __launch_bounds__(256) void k_near_gather(int N, const int64_t *ptr, const int32_t *idx,
+                                                     const double2 *part, double2 *y)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = (int)(t >> 4), sub = (int)(t & 15);
     double re = 0.0, im = 0.0;
-    // four independent streaming loads in flight per lane; the matrix is read once
-    // per apply, so its loads bypass the caches (x stays cached)
-    int64_t k = b + lane;
-    for (; k + 3 * kWave < e; k += 4 * kWave) {
-        typedef double d2v __attribute__((ext_vector_type(2)));
-        d2v a[4];
-        int c[4];
-        const d2v *vv = reinterpret_cast<const d2v *>(o.val);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            a[u] = __builtin_nontemporal_load(vv + k + u * kWave);
-            c[u] = __builtin_nontemporal_load(&o.col[k + u * kWave]);
+    if (i < N)
+        for (int64_t k = ptr[i] + sub; k < ptr[i + 1]; k += 16) {
+            const double2 v = part[idx[k]];
+            re += v.x;
+            im += v.y;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const double2 v = x[c[u]];
-            re = fma(a[u].x, v.x, re);
-            re = fma(-a[u].y, v.y, re);
-            im = fma(a[u].x, v.y, im);
-            im = fma(a[u].y, v.x, im);
-        }
+    for (int off = 8; off >= 1; off >>= 1) {
+        re += __shfl_xor(re, off, 16);
+        im += __shfl_xor(im, off, 16);
     }
-    for (; k < e; k += kWave) {
-        const double2 a = o.val[k];
-        const double2 v = x[o.col[k]];
-        re = fma(a.x, v.x, re);
-        re = fma(-a.y, v.y, re);
-        im = fma(a.x, v.y, im);
-        im = fma(a.y, v.x, im);
-    }
-    for (int off = kWave / 2; off >= 1; off >>= 1) {
-        re += __shfl_xor(re, off, kWave);
-        im += __shfl_xor(im, off, kWave);
-    }
-    if (lane == 0) y[row] = make_double2(re, im);
+    if (i < N && sub == 0) y[i] = make_double2(re, im);
 }
 
 // ---------------------------------------------------------------------------
@@ -1136,9 +1464,9 @@ void launch_element_data(ige_op op)
     const int threads = 64;
     hipStream_t s = op->ctx->stream;
     switch (o.p) {
-        case 1: hipLaunchKernelGGL(k_element_data<4>, dim3(E), dim3(threads), 0, s, o, op->d_eX.p, op->d_ePsi.p, op->d_eC.p); break;
-        case 2: hipLaunchKernelGGL(k_element_data<12>, dim3(E), dim3(threads), 0, s, o, op->d_eX.p, op->d_ePsi.p, op->d_eC.p); break;
-        default: hipLaunchKernelGGL(k_element_data<24>, dim3(E), dim3(threads), 0, s, o, op->d_eX.p, op->d_ePsi.p, op->d_eC.p); break;
+        case 1: hipLaunchKernelGGL(k_element_data<4>, dim3(E), dim3(threads), 0, s, o, op->d_eX.p, op->d_ePsi.p, op->d_ePsiF.p, op->d_eC.p); break;
+        case 2: hipLaunchKernelGGL(k_element_data<12>, dim3(E), dim3(threads), 0, s, o, op->d_eX.p, op->d_ePsi.p, op->d_ePsiF.p, op->d_eC.p); break;
+        default: hipLaunchKernelGGL(k_element_data<24>, dim3(E), dim3(threads), 0, s, o, op->d_eX.p, op->d_ePsi.p, op->d_ePsiF.p, op->d_eC.p); break;
     }
     IGE_LAUNCH_CHECK();
 }
@@ -1152,27 +1480,44 @@ void launch_node_geometry(ige_op op)
     IGE_LAUNCH_CHECK();
 }
 
-void launch_near_regular(ige_op op, int64_t n_near)
+size_t psi_fragment_doubles(int nl, int G2)
+{
+    const int LT = (nl + 15) / 16, QT = (G2 + 15) / 16;
+    return (size_t)4 * LT * 4 * QT * 64;
+}
+
+namespace {
+template <int NL>
+void launch_near_regular_nl(ige_op op, dim3 grid, size_t shm, int sb)
 {
     const DevOp &o = op->view;
-    const int64_t s4 = (int64_t)o.s * o.s * o.s * o.s;
-    const int64_t nblk = n_near * s4;
-    if (nblk == 0) return;
-    const size_t shm_base = sizeof(double) * 6 * o.G2 + sizeof(double2) * kQB * o.G2;
     hipStream_t s = op->ctx->stream;
+    switch ((o.G2 + 15) / 16) {
+        case 1: hipLaunchKernelGGL((k_near_regular<NL, 1>), grid, dim3(256), shm, s, o, sb); break;
+        case 2: hipLaunchKernelGGL((k_near_regular<NL, 2>), grid, dim3(256), shm, s, o, sb); break;
+        case 3: hipLaunchKernelGGL((k_near_regular<NL, 3>), grid, dim3(256), shm, s, o, sb); break;
+        default: hipLaunchKernelGGL((k_near_regular<NL, 4>), grid, dim3(256), shm, s, o, sb); break;
+    }
+}
+}  // namespace
+
+void launch_near_regular(ige_op op)
+{
+    const DevOp &o = op->view;
+    if (o.nblk == 0) return;
+    IGE_REQUIRE(o.G2 <= 64, "regular near-field rule limited to 8 x 8 points");
+    // trial squares of sb x sb elements: the largest power of two <= s whose block
+    // rows fit in 48 KB of shared memory
+    int sb = o.s;
+    auto shm_of = [&](int q) { return sizeof(double2) * o.nl * 2 * (size_t)(q + o.p) * (q + o.p); };
+    while (sb > 1 && shm_of(sb) > 48 * 1024) sb /= 2;
+    const int nsb = o.s / sb;
+    const dim3 grid((unsigned)(o.nblk * o.s * o.s * nsb * nsb));
+    const size_t shm = shm_of(sb);
     switch (o.p) {
-        case 1:
-            hipLaunchKernelGGL(k_near_regular<4>, dim3(nblk), dim3(64), shm_base + sizeof(double2) * 4 * 16, s, o,
-                               op->d_near.p);
-            break;
-        case 2:
-            hipLaunchKernelGGL(k_near_regular<12>, dim3(nblk), dim3(64), shm_base + sizeof(double2) * 4 * 144, s, o,
-                               op->d_near.p);
-            break;
-        default:
-            hipLaunchKernelGGL(k_near_regular<24>, dim3(nblk), dim3(64), shm_base + sizeof(double2) * 4 * 576, s, o,
-                               op->d_near.p);
-            break;
+        case 1: launch_near_regular_nl<4>(op, grid, shm, sb); break;
+        case 2: launch_near_regular_nl<12>(op, grid, shm, sb); break;
+        default: launch_near_regular_nl<24>(op, grid, shm, sb); break;
     }
     IGE_LAUNCH_CHECK();
 }
@@ -1183,9 +1528,9 @@ void launch_near_singular(ige_op op)
     if (op->nsing == 0) return;
     hipStream_t s = op->ctx->stream;
     switch (o.p) {
-        case 1: hipLaunchKernelGGL(k_near_singular<4>, dim3(op->nsing), dim3(64), 0, s, o, op->d_sing.p); break;
-        case 2: hipLaunchKernelGGL(k_near_singular<12>, dim3(op->nsing), dim3(64), 0, s, o, op->d_sing.p); break;
-        default: hipLaunchKernelGGL(k_near_singular<24>, dim3(op->nsing), dim3(64), 0, s, o, op->d_sing.p); break;
+        case 1: hipLaunchKernelGGL(k_near_singular<1>, dim3(op->nsing), dim3(64), 0, s, o, op->d_sing.p); break;
+        case 2: hipLaunchKernelGGL(k_near_singular<2>, dim3(op->nsing), dim3(64), 0, s, o, op->d_sing.p); break;
+        default: hipLaunchKernelGGL(k_near_singular<3>, dim3(op->nsing), dim3(64), 0, s, o, op->d_sing.p); break;
     }
     IGE_LAUNCH_CHECK();
 }
@@ -1251,11 +1596,35 @@ void launch_l2l(ige_op op)
     }
 }
 
+int near_blk_u(int nF)
+{
+    const int u = (nF + 63) / 64;
+    for (int c : {1, 2, 3, 4, 6, 8, 12, 16})
+        if (u <= c) return c;
+    return 16;
+}
+
 void launch_spmv(ige_op op, const double2 *x, double2 *y, hipStream_t st)
 {
     const DevOp &o = op->view;
-    const int rows_per_block = 256 / kWave;
-    hipLaunchKernelGGL(k_spmv, dim3((o.N + rows_per_block - 1) / rows_per_block), dim3(256), 0, st, o, x, y);
+    if (o.nblk == 0) {
+        IGE_HIP(hipMemsetAsync(y, 0, sizeof(double2) * o.N, st));
+        return;
+    }
+    const dim3 grid((unsigned)(o.nblk * o.nch)), blk(256);
+    double2 *part = op->d_npart.p;
+    switch (near_blk_u(o.nF)) {
+        case 1: hipLaunchKernelGGL(k_near_blk<1>, grid, blk, 0, st, o, x, part); break;
+        case 2: hipLaunchKernelGGL(k_near_blk<2>, grid, blk, 0, st, o, x, part); break;
+        case 3: hipLaunchKernelGGL(k_near_blk<3>, grid, blk, 0, st, o, x, part); break;
+        case 4: hipLaunchKernelGGL(k_near_blk<4>, grid, blk, 0, st, o, x, part); break;
+        case 6: hipLaunchKernelGGL(k_near_blk<6>, grid, blk, 0, st, o, x, part); break;
+        case 8: hipLaunchKernelGGL(k_near_blk<8>, grid, blk, 0, st, o, x, part); break;
+        case 12: hipLaunchKernelGGL(k_near_blk<12>, grid, blk, 0, st, o, x, part); break;
+        default: hipLaunchKernelGGL(k_near_blk<16>, grid, blk, 0, st, o, x, part); break;
+    }
+    IGE_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_near_gather, dim3((unsigned)(((int64_t)o.N * 16 + 255) / 256)), dim3(256), 0, st, o.N, o.red_ptr, o.red_idx, part, y);
     IGE_LAUNCH_CHECK();
 }
 

@@ -3,7 +3,7 @@
 // Layout: the r columns are innermost everywhere, x_t / y_t are [N][r], cluster
 // arrays [cluster][field][Q][r]; a block handles a chunk of kRB columns
 // (blockIdx.y), so the kernel values G of the coupling stage and the near-field
-// matrix entries are read or computed once per chunk instead of once per column.
+// block entries are read or computed once per chunk instead of once per column.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -42,56 +42,154 @@ __global__ void k_to_cols(int64_t N, int r, const double2 *yt, double2 *y)
 }
 
 // ---------------------------------------------------------------------------
-// near-field product, kRB columns per pass over a row
+// near-field product over the stored blocks, RB columns per pass: every block
+// entry is loaded once per pass and used for the RB columns of both the block and
+// its transpose (same partial-result layout as one column, times RB)
 // ---------------------------------------------------------------------------
-template <int kRB>
-__global__ __launch_bounds__(256) void k_spmm(DevOp o, int r, const double2 *xt, double2 *yt)
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+__device__ inline double wave_sum_b(double v)
 {
-    // lane = (entry slot, column): kRB lanes share one matrix entry and read the
-    // kRB consecutive columns of x_t[j] (one contiguous line); 64/kRB entries per step
-    constexpr int EPS = kWave / kRB;
-    const int row = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    const int lane = threadIdx.x % kWave;
-    const int c = lane % kRB, es = lane / kRB;
-    const int c0 = blockIdx.y * kRB;
-    const bool cok = c0 + c < r;
-    if (row >= o.N) return;
-    const int64_t b = o.rowptr[row], e = o.rowptr[row + 1];
+#pragma unroll
+    for (int off = kWave / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+template <int U, int RB>
+__global__ __launch_bounds__(256) void k_near_blk_b(DevOp o, int r, int c0, const double2 *xt, double2 *part)
+{
+    __shared__ double2 sxr[64 * U][RB];
+    __shared__ double2 syc[64 * U][RB];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t b = blockIdx.x / o.nch;
+    const int ch = blockIdx.x % o.nch;
+    const int lt = o.bpair[2 * b], ls = o.bpair[2 * b + 1];
+    const int nF = o.nF, r0 = ch * o.rc, r1 = min(nF, r0 + o.rc);
+    const int nc = min(RB, r - c0);
+    d2v xc[U][RB], yc[U][RB];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int c = lane + 64 * u;
+        const int d = c < nF ? o.leafdof[(size_t)ls * nF + c] : -1;
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+            const double2 v = (d >= 0 && j < nc) ? xt[(size_t)d * r + c0 + j] : make_double2(0.0, 0.0);
+            xc[u][j] = d2v{v.x, v.y};
+            yc[u][j] = d2v{0.0, 0.0};
+        }
+    }
+    for (int k = threadIdx.x; k < (r1 - r0) * RB; k += blockDim.x) {
+        const int row = k / RB, j = k % RB;
+        const int d = o.leafdof[(size_t)lt * nF + r0 + row];
+        sxr[row][j] = (d >= 0 && j < nc) ? xt[(size_t)d * r + c0 + j] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    const d2v *B = reinterpret_cast<const d2v *>(o.bval) + (size_t)b * nF * nF;
+    for (int rr = r0 + wv; rr < r1; rr += 4) {
+        d2v a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int c = lane + 64 * u;
+            a[u] = c < nF ? __builtin_nontemporal_load(B + (size_t)rr * nF + c) : d2v{0.0, 0.0};
+        }
+        double re[RB], im[RB];
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+            re[j] = 0.0;
+            im[j] = 0.0;
+            const double2 xr = sxr[rr - r0][j];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                re[j] = fma(a[u].x, xc[u][j].x, fma(-a[u].y, xc[u][j].y, re[j]));
+                im[j] = fma(a[u].x, xc[u][j].y, fma(a[u].y, xc[u][j].x, im[j]));
+                yc[u][j].x = fma(a[u].x, xr.x, fma(-a[u].y, xr.y, yc[u][j].x));
+                yc[u][j].y = fma(a[u].x, xr.y, fma(a[u].y, xr.x, yc[u][j].y));
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+            re[j] = wave_sum_b(re[j]);
+            im[j] = wave_sum_b(im[j]);
+        }
+        if (lane == 0)
+#pragma unroll
+            for (int j = 0; j < RB; ++j) part[((size_t)b * nF + rr) * RB + j] = make_double2(re[j], im[j]);
+    }
+    if (lt == ls) return;   // diagonal block (uniform branch)
+    // combine the waves' column partials in a fixed order
+    for (int w = 0; w < 4; ++w) {
+        if (wv == w)
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int c = lane + 64 * u;
+                if (c < nF)
+#pragma unroll
+                    for (int j = 0; j < RB; ++j) {
+                        const double2 prev = w == 0 ? make_double2(0.0, 0.0) : syc[c][j];
+                        syc[c][j] = make_double2(prev.x + yc[u][j].x, prev.y + yc[u][j].y);
+                    }
+            }
+        __syncthreads();
+    }
+    double2 *cp = part + ((size_t)o.nblk * nF + ((size_t)b * o.nch + ch) * nF) * RB;
+    for (int k = threadIdx.x; k < nF * RB; k += blockDim.x) cp[k] = syc[k / RB][k % RB];
+}
+
+// 16 lanes per unknown (RB columns innermost), fixed butterfly over the 16
+template <int RB>
+__global__ __launch_bounds__(256) void k_near_gather_b(int N, int r, int c0, const int64_t *ptr,
+                                                       const int32_t *idx, const double2 *part, double2 *yt)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = (int)(t % RB), sub = (int)((t / RB) & 15);
+    const int64_t i = t / (16 * RB);
     double re = 0.0, im = 0.0;
-    typedef double d2v __attribute__((ext_vector_type(2)));
-    const d2v *vv = reinterpret_cast<const d2v *>(o.val);
-    int64_t k = b + es;
-    for (; k + EPS < e; k += 2 * EPS) {
-        const d2v a0 = __builtin_nontemporal_load(vv + k);
-        const d2v a1 = __builtin_nontemporal_load(vv + k + EPS);
-        const int j0 = __builtin_nontemporal_load(o.col + k);
-        const int j1 = __builtin_nontemporal_load(o.col + k + EPS);
-        const double2 v0 = cok ? xt[(size_t)j0 * r + c0 + c] : make_double2(0, 0);
-        const double2 v1 = cok ? xt[(size_t)j1 * r + c0 + c] : make_double2(0, 0);
-        re = fma(a0.x, v0.x, re);
-        re = fma(-a0.y, v0.y, re);
-        im = fma(a0.x, v0.y, im);
-        im = fma(a0.y, v0.x, im);
-        re = fma(a1.x, v1.x, re);
-        re = fma(-a1.y, v1.y, re);
-        im = fma(a1.x, v1.y, im);
-        im = fma(a1.y, v1.x, im);
+    if (i < N)
+        for (int64_t k = ptr[i] + sub; k < ptr[i + 1]; k += 16) {
+            const double2 v = part[(size_t)idx[k] * RB + j];
+            re += v.x;
+            im += v.y;
+        }
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1) {
+        re += __shfl_xor(re, off * RB, 16 * RB);
+        im += __shfl_xor(im, off * RB, 16 * RB);
     }
-    for (; k < e; k += EPS) {
-        const d2v a0 = vv[k];
-        const int j0 = o.col[k];
-        const double2 v0 = cok ? xt[(size_t)j0 * r + c0 + c] : make_double2(0, 0);
-        re = fma(a0.x, v0.x, re);
-        re = fma(-a0.y, v0.y, re);
-        im = fma(a0.x, v0.y, im);
-        im = fma(a0.y, v0.x, im);
+    if (i < N && sub == 0 && c0 + j < r) yt[(size_t)i * r + c0 + j] = make_double2(re, im);
+}
+
+template <int U, int RB>
+void near_batched_u(ige_op op, int r, const double2 *xt, double2 *yt, hipStream_t s)
+{
+    const DevOp &o = op->view;
+    for (int c0 = 0; c0 < r; c0 += RB) {
+        hipLaunchKernelGGL((k_near_blk_b<U, RB>), dim3((unsigned)(o.nblk * o.nch)), dim3(256), 0, s, o, r, c0, xt,
+                           op->d_bnpart.p);
+        IGE_HIP(hipGetLastError());
+        const int64_t tot = (int64_t)o.N * RB * 16;
+        hipLaunchKernelGGL(k_near_gather_b<RB>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, o.N, r, c0,
+                           o.red_ptr, o.red_idx, op->d_bnpart.p, yt);
+        IGE_HIP(hipGetLastError());
     }
-    // sum over the entry slots (lanes with the same column)
-    for (int off = kWave / 2; off >= kRB; off >>= 1) {
-        re += __shfl_xor(re, off, kWave);
-        im += __shfl_xor(im, off, kWave);
+}
+
+void near_batched(ige_op op, int r, const double2 *xt, double2 *yt, hipStream_t s)
+{
+    const DevOp &o = op->view;
+    if (o.nblk == 0) {
+        IGE_HIP(hipMemsetAsync(yt, 0, sizeof(double2) * o.N * r, s));
+        return;
     }
-    if (es == 0 && cok) yt[(size_t)row * r + c0 + c] = make_double2(re, im);
+    switch (near_blk_u(o.nF)) {
+        case 1: near_batched_u<1, 4>(op, r, xt, yt, s); break;
+        case 2: near_batched_u<2, 4>(op, r, xt, yt, s); break;
+        case 3: near_batched_u<3, 4>(op, r, xt, yt, s); break;
+        case 4: near_batched_u<4, 4>(op, r, xt, yt, s); break;
+        case 6: near_batched_u<6, 2>(op, r, xt, yt, s); break;
+        case 8: near_batched_u<8, 2>(op, r, xt, yt, s); break;
+        case 12: near_batched_u<12, 1>(op, r, xt, yt, s); break;
+        default: near_batched_u<16, 1>(op, r, xt, yt, s); break;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -566,10 +664,8 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
     } else {
         for (int i = 1; i <= 6; ++i) mark(i);
     }
-    const int rows_per_block = 256 / kWave;
     mark(7);
-    IGE_RB_SWITCH(8, k_spmm, dim3((N + rows_per_block - 1) / rows_per_block, chunks(8)), dim3(256), 0, s, o, r, xt,
-                  yt);
+    near_batched(op, r, xt, yt, s);
     mark(8);
     mark(9);
     if (far) {

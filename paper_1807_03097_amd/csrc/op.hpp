@@ -39,11 +39,17 @@ struct DevOp {
     // element data at the regular Gauss points
     const double *eX;      // [E][3][G2]
     const double *ePsi;    // [E][4][nl][G2]  weight * (phi_hat d_aF (3 comps), div phi_hat)
+    const double *ePsiF;   // the same values in matrix-core operand order, see k_element_data
     const double *eC;      // [E][4][3] element corners
-    // near field (glued CSR)
-    const int64_t *rowptr;
-    const int32_t *col;
-    double2 *val;
+    // near field: dense blocks over leaf function slots
+    int W, nF, nch, rc;
+    int64_t nblk;
+    const int32_t *bpair;     // [nblk][2]
+    double2 *bval;            // [nblk][nF][nF]
+    const int32_t *leafdof;   // [nleaf][nF]
+    const int8_t *leafsgn;    // [nleaf][nF]
+    const int64_t *red_ptr;   // [N+1]
+    const int32_t *red_idx;
     // cluster tree
     const int64_t *lvl_off;   // [L+2] first global cluster id of each level
     const double *nodeX;      // [NC][3][Q]
@@ -92,15 +98,16 @@ struct ige_op_s {
     ige::DBuf<int32_t> d_dof;
     ige::DBuf<int8_t> d_sgn;
     ige::DBuf<double> d_ext_p, d_ext_q, d_gx, d_gw, d_sx, d_sw;
-    ige::DBuf<double> d_eX, d_ePsi, d_eC;
-    ige::DBuf<int64_t> d_rowptr;
-    ige::DBuf<int32_t> d_col;
-    ige::DBuf<double2> d_val;
+    ige::DBuf<double> d_eX, d_ePsi, d_ePsiF, d_eC;
+    ige::DBuf<int32_t> d_bpair, d_leafdof, d_red_idx;
+    ige::DBuf<int8_t> d_leafsgn;
+    ige::DBuf<int64_t> d_red_ptr;
+    ige::DBuf<double2> d_bval;
+    ige::DBuf<double2> d_npart;        // near-field partial results [nslots]
     ige::DBuf<int64_t> d_lvl_off;
     ige::DBuf<double> d_nodeX, d_nodeT, d_xn, d_T0, d_T1, d_Mp, d_Mq, d_Mdp;
     ige::DBuf<int32_t> d_inc;
     ige::DBuf<ige::SingularPair> d_sing;
-    ige::DBuf<int32_t> d_near;          // [nnear][2]
     ige::DBuf<ige::M2LWork> d_work;
     ige::DBuf<int32_t> d_partner;       // source global cluster id per work entry
     ige::DBuf<int32_t> d_wrk_of_tgt;
@@ -114,6 +121,7 @@ struct ige_op_s {
     ige::DBuf<double2> d_x, d_y; // staging for host pointers
     // batched-apply workspaces (r columns, column index innermost)
     int bcap = 0;
+    ige::DBuf<double2> d_bnpart;       // near-field partial results [nslots][rb]
     ige::DBuf<double2> d_bmom, d_bsrc, d_bpart, d_bloc, d_bybuf, d_bxt, d_byt, d_bx, d_by;
     // GMRES workspace
     ige::DBuf<double2> d_V, d_w, d_r, d_X, d_F, d_D;
@@ -128,7 +136,9 @@ namespace ige {
 // assembly
 void launch_element_data(ige_op op);
 void launch_node_geometry(ige_op op);
-void launch_near_regular(ige_op op, int64_t n_near);
+void launch_near_regular(ige_op op);
+// doubles of matrix-core operand data per element (see k_element_data)
+size_t psi_fragment_doubles(int nl, int G2);
 void launch_near_singular(ige_op op);
 // apply pieces (one right-hand side)
 void launch_p2m(ige_op op, const double2 *x);
@@ -137,6 +147,7 @@ void launch_m2l(ige_op op, int prec);
 void launch_m2l_reduce(ige_op op);
 void launch_l2l(ige_op op);
 void launch_spmv(ige_op op, const double2 *x, double2 *y, hipStream_t st);
+int near_blk_u(int nF);   // 64-column groups per block row (template choice)
 void launch_l2p_leaf(ige_op op);
 void launch_l2p_gather(ige_op op, double2 *y);
 void launch_rhs_plane(ige_op op, const double *dir, double2 pol0, double2 pol1, double2 pol2, double2 *f);

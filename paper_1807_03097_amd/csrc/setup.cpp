@@ -500,62 +500,70 @@ void build_partition(Partition &T, const Geometry &G, const Discretisation &D, d
 // ---------------------------------------------------------------------------
 // near-field sparsity pattern in the glued basis
 // ---------------------------------------------------------------------------
-void build_near_pattern(NearPattern &A, const Discretisation &D, const Partition &T)
+void build_near_blocks(NearBlocks &B, const Discretisation &D, const Partition &T, int nch)
 {
     const int p = D.p, nb = D.nb, s = T.s, S = 1 << T.L;
+    const int W = s + p;
+    B.W = W;
+    B.nF = 2 * W * (W - 1);
+    IGE_REQUIRE(B.nF <= kMaxLeafSlots, "leaf clusters too large for the near-field blocks (lower leaf_depth)");
+    const int nF = B.nF;
     const size_t nleaf = (size_t)D.P * S * S;
-    // unknowns touching each leaf cluster (sorted, unique)
-    std::vector<std::vector<int32_t>> dofs(nleaf);
-    std::vector<std::vector<int32_t>> clusters_of(D.N);
+    B.leafdof.assign(nleaf * nF, -1);
+    B.leafsgn.assign(nleaf * nF, 0);
     for (int j = 0; j < D.P; ++j)
         for (int k2 = 0; k2 < S; ++k2)
             for (int k1 = 0; k1 < S; ++k1) {
                 const size_t lid = ((size_t)j * S + k2) * S + k1;
-                auto &v = dofs[lid];
                 for (int a = 0; a < 2; ++a) {
-                    const int w1 = (a == 0) ? s + p : s + p - 1, w2 = (a == 0) ? s + p - 1 : s + p;
-                    for (int i2 = k2 * s; i2 < k2 * s + w2; ++i2)
-                        for (int i1 = k1 * s; i1 < k1 * s + w1; ++i1) {
-                            const int32_t d = D.dof[(((size_t)j * 2 + a) * nb + i2) * nb + i1];
-                            if (d >= 0) v.push_back(d);
+                    const int w1 = (a == 0) ? W : W - 1, w2 = (a == 0) ? W - 1 : W;
+                    for (int i2 = 0; i2 < w2; ++i2)
+                        for (int i1 = 0; i1 < w1; ++i1) {
+                            const size_t off = (((size_t)j * 2 + a) * nb + k2 * s + i2) * nb + k1 * s + i1;
+                            const int k = leaf_slot(W, a, i1, i2);
+                            B.leafdof[lid * nF + k] = D.dof[off];
+                            B.leafsgn[lid * nF + k] = D.dof[off] >= 0 ? D.sgn[off] : 0;
                         }
                 }
-                std::sort(v.begin(), v.end());
-                v.erase(std::unique(v.begin(), v.end()), v.end());
-                for (int32_t d : v) clusters_of[d].push_back((int32_t)lid);
             }
-    // per leaf: union of the unknowns of its near partners
-    std::vector<std::vector<int32_t>> nearcols(nleaf);
-    {
-        size_t i = 0;
-        while (i < T.near.size()) {
-            const int32_t t = T.near[i][0];
-            std::vector<int32_t> &acc = nearcols[t];
-            size_t k = i;
-            while (k < T.near.size() && T.near[k][0] == t) {
-                const auto &v = dofs[T.near[k][1]];
-                acc.insert(acc.end(), v.begin(), v.end());
-                ++k;
+    // one block per unordered pair; the block tree is symmetric
+    B.pair.clear();
+    for (const auto &np : T.near) {
+        if (np[0] > np[1]) continue;
+        IGE_REQUIRE(std::binary_search(T.near.begin(), T.near.end(), std::array<int32_t, 2>{np[1], np[0]}),
+                    "near leaf pairs are not symmetric");
+        B.pair.push_back(np[0]);
+        B.pair.push_back(np[1]);
+    }
+    B.nch = std::max(1, std::min(nch, nF));
+    B.rc = (nF + B.nch - 1) / B.nch;
+    B.nch = (nF + B.rc - 1) / B.rc;
+    const int64_t nblk = B.nblk();
+    IGE_REQUIRE(B.nslots() < ((int64_t)1 << 31), "near field too large for 32-bit partial indices");
+    // fixed-order reduction lists: for every unknown its row partials and (for
+    // off-diagonal blocks) its column partials, in block order
+    std::vector<int64_t> cnt((size_t)D.N + 1, 0);
+    auto visit = [&](auto &&emit) {
+        for (int64_t b = 0; b < nblk; ++b) {
+            const int lt = B.pair[2 * b], ls = B.pair[2 * b + 1];
+            for (int k = 0; k < nF; ++k) {
+                const int32_t d = B.leafdof[(size_t)lt * nF + k];
+                if (d >= 0) emit(d, b * nF + k);
             }
-            std::sort(acc.begin(), acc.end());
-            acc.erase(std::unique(acc.begin(), acc.end()), acc.end());
-            i = k;
+            if (lt == ls) continue;
+            for (int ch = 0; ch < B.nch; ++ch)
+                for (int k = 0; k < nF; ++k) {
+                    const int32_t d = B.leafdof[(size_t)ls * nF + k];
+                    if (d >= 0) emit(d, nblk * nF + (b * B.nch + ch) * nF + k);
+                }
         }
-    }
-    A.rowptr.assign((size_t)D.N + 1, 0);
-    std::vector<std::vector<int32_t>> rows(D.N);
-#pragma omp parallel for schedule(dynamic, 64)
-    for (int d = 0; d < D.N; ++d) {
-        std::vector<int32_t> acc;
-        for (int32_t lid : clusters_of[d]) acc.insert(acc.end(), nearcols[lid].begin(), nearcols[lid].end());
-        std::sort(acc.begin(), acc.end());
-        acc.erase(std::unique(acc.begin(), acc.end()), acc.end());
-        rows[d].swap(acc);
-    }
-    for (int d = 0; d < D.N; ++d) A.rowptr[d + 1] = A.rowptr[d] + (int64_t)rows[d].size();
-    A.col.resize(A.rowptr[D.N]);
-#pragma omp parallel for schedule(static)
-    for (int d = 0; d < D.N; ++d) std::copy(rows[d].begin(), rows[d].end(), A.col.begin() + A.rowptr[d]);
+    };
+    visit([&](int32_t d, int64_t) { cnt[d + 1]++; });
+    for (int i = 0; i < D.N; ++i) cnt[i + 1] += cnt[i];
+    B.red_ptr = cnt;
+    B.red_idx.assign(cnt[D.N], 0);
+    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+    visit([&](int32_t d, int64_t slot) { B.red_idx[fill[d]++] = (int32_t)slot; });
 }
 
 // ---------------------------------------------------------------------------
@@ -576,7 +584,7 @@ int frame_code(int origin, int towards_a2)
 }  // namespace
 
 void build_singular_pairs(std::vector<SingularPair> &S, std::vector<double> &corners, const Geometry &G,
-                          const Discretisation &D, const Partition &T)
+                          const Discretisation &D, const Partition &T, const NearBlocks &B)
 {
     const int n = D.n, s = T.s, SL = 1 << T.L;
     const std::vector<double> V = vertex_images(G, n);
@@ -603,8 +611,8 @@ void build_singular_pairs(std::vector<SingularPair> &S, std::vector<double> &cor
             }
     const double tol = 1e-9 * G.scale;
     S.clear();
-    for (const auto &np : T.near) {
-        const int lt = np[0], ls = np[1];
+    for (int64_t blk = 0; blk < B.nblk(); ++blk) {
+        const int lt = B.pair[2 * blk], ls = B.pair[2 * blk + 1];
         const int jt = lt / (SL * SL), rt = lt % (SL * SL), jt2 = rt / SL, jt1 = rt % SL;
         const int js = ls / (SL * SL), rs = ls % (SL * SL), js2 = rs / SL, js1 = rs % SL;
         for (int a2 = 0; a2 < s; ++a2)
@@ -623,7 +631,7 @@ void build_singular_pairs(std::vector<SingularPair> &S, std::vector<double> &cor
                                     ++ns;
                                 }
                         if (ns == 0) continue;
-                        SingularPair sp{(int32_t)e, (int32_t)f, 0, 0, 0};
+                        SingularPair sp{(int32_t)e, (int32_t)f, 0, 0, 0, (int32_t)blk};
                         if (ns == 4) {
                             IGE_REQUIRE(e == f, "distinct elements share all corners");
                             sp.kind = 1;

@@ -56,22 +56,45 @@ struct Partition {
 
 void build_partition(Partition &T, const Geometry &G, const Discretisation &D, double eta, int leaf_depth);
 
-// glued near-field sparsity pattern (rows = test unknowns)
-struct NearPattern {
-    std::vector<int64_t> rowptr;   // N+1
-    std::vector<int32_t> col;
+// Near field as dense blocks over leaf function slots.  The functions whose
+// support meets a leaf cluster (2^d x 2^d elements, degree p) are numbered by a
+// leaf-local slot: component 0 has (W) x (W-1) functions, component 1 (W-1) x (W),
+// W = 2^d + p, so nF = 2 W (W-1) slots per leaf.  The operator is complex
+// symmetric, so one block is stored per unordered near leaf pair (t <= s); the
+// block of (s, t) is its transpose.  Block entries are in glued unknowns (signs
+// folded in).  The product writes per-block partial results, which a fixed-order
+// reduction sums per unknown (deterministic).
+struct NearBlocks {
+    int W = 0, nF = 0;
+    int nch = 1, rc = 0;                 // row chunks per block, rows per chunk
+    std::vector<int32_t> pair;           // [nblk][2] (target leaf, source leaf), target <= source
+    std::vector<int32_t> leafdof;        // [nleaf][nF] glued unknown, -1 = no function
+    std::vector<int8_t> leafsgn;         // [nleaf][nF]
+    std::vector<int64_t> red_ptr;        // [N+1]
+    std::vector<int32_t> red_idx;        // partial-result slots, in block order
+    int64_t nblk() const { return (int64_t)pair.size() / 2; }
+    // partial-result slots: rows [nblk][nF], then columns [nblk][nch][nF]
+    int64_t nslots() const { return nblk() * nF * (1 + nch); }
 };
-void build_near_pattern(NearPattern &A, const Discretisation &D, const Partition &T);
+constexpr int kMaxLeafSlots = 1024;
+__host__ __device__ inline int leaf_slot(int W, int a, int i1, int i2)
+{
+    return a == 0 ? i2 * W + i1 : W * (W - 1) + i2 * (W - 1) + i1;
+}
+void build_near_blocks(NearBlocks &B, const Discretisation &D, const Partition &T, int nch);
 
 // singular element pairs inside the near field: (test element, trial element,
 // kind 1 identical / 2 edge / 3 vertex, frame code test, frame code trial)
+// Only pairs whose leaf pair is stored (leaf(e) <= leaf(f)) are kept; blk is the
+// index of that block.
 struct SingularPair {
     int32_t e, f;
     int32_t kind;
     int32_t fa, fb;   // frame code: bit0 = o1, bit1 = o2, bit2 = swap (see kernels)
+    int32_t blk;
 };
 void build_singular_pairs(std::vector<SingularPair> &S, std::vector<double> &corners, const Geometry &G,
-                          const Discretisation &D, const Partition &T);
+                          const Discretisation &D, const Partition &T, const NearBlocks &B);
 
 // 1-D moment tables of the leaf clusters and transfer matrices
 struct FarTables {
