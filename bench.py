@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=16, help="rows of the bounded oracle sample")
     ap.add_argument("--nrhs", type=int, default=1, help="right-hand sides per apply (batched kernels when > 1)")
+    ap.add_argument("--store-coupling", type=int, default=-1, choices=(-1, 0, 1),
+                    help="coupling blocks: 1 stored, 0 evaluated per apply, -1 stored if they fit")
     ap.add_argument("--verbose", action="store_true")
     return ap.parse_args()
 
@@ -83,7 +85,7 @@ def main():
     ctx = B.Context(0, stream.cuda_stream)
     geom = B.Geometry(ctx, pats)
     t0 = time.perf_counter()
-    op = B.Operator(geom, p, m, kappa, q, eta, 5, 5, d)
+    op = B.Operator(geom, p, m, kappa, q, eta, 5, 5, d, store_coupling=args.store_coupling)
     t_asm = time.perf_counter() - t0
     info = op.info
     N = op.N
@@ -175,6 +177,7 @@ def main():
         "config": {"workload": f"FMM matvec: 6-patch NURBS sphere, level {m}, p={p}, kappa={kappa}, q={q}, "
                                f"5x5 Gauss near field, x ~ N(0,1)+iN(0,1) seed 0",
                    "n_dof": N, "nrhs": r, "eta": eta, "leaf_depth": d, "near_nnz": int(info.near_nnz),
+                   "store_coupling": args.store_coupling,
                    "far_pairs": int(info.far_pairs), "parallelism": "single GPU"},
         "stage_ms": st,
         "assemble_s": t_asm,

@@ -94,13 +94,20 @@ int ige_geom_destroy(ige_geom geom);
  *   gauss_near    g: g x g Gauss points per element for disjoint element pairs (1..8)
  *   gauss_singular gs: Gauss points per variable of the singular sub-rules (1..12)
  *   leaf_depth    d: leaf clusters are 2^d x 2^d elements (leaf level max(0, m-d));
- *                 -1 selects ceil(log2((q+1)/(p+1))) */
+ *                 -1 selects ceil(log2((q+1)/(p+1)))
+ *   store_coupling 1: the interpolated kernel matrices G of the admissible blocks
+ *                 (Sec. 4.2, the couplings of the H^2 representation) are computed once
+ *                 at assembly and stored, one Q x Q complex block per unordered
+ *                 cluster pair (G of (s, t) is the transpose of G of (t, s)); every
+ *                 apply then streams them (Q^2 * 16 bytes per pair).  0 or -1: G is
+ *                 evaluated in every apply (the default: measured faster). */
 typedef struct {
     int p, level;
     double kappa;
     int q;
     double eta;
     int gauss_near, gauss_singular, leaf_depth;
+    int store_coupling;
 } ige_params;
 
 /* Assemble the operator on the device: element and cluster-node geometry, the
@@ -146,10 +153,12 @@ enum { IGE_F64 = 0, IGE_F32 = 1 };
  * entry read or computed once per chunk). */
 int ige_apply(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind);
 
-/* As ige_apply, with the coupling stage (interpolated-kernel evaluation and its
- * products, a5) in the given precision: IGE_F64, or IGE_F32 (FP32 kernel values
- * and FP32 accumulation; relative error about kappa * diam * 2^-23 on the far
- * field).  Near field, moments and transfers stay FP64. */
+/* As ige_apply, with the coupling stage (interpolated-kernel values and their
+ * products, a5) in the given precision: IGE_F64, or IGE_F32 (FP32 kernel values:
+ * evaluated and accumulated in FP32 when generated on the fly, an FP32 copy of the
+ * stored blocks with FP64 accumulation when stored; relative error about
+ * kappa * diam * 2^-23 on the far field).  Near field, moments and transfers stay
+ * FP64.  The FP32 copy is made on the first FP32 apply (half the FP64 block bytes). */
 int ige_apply_prec(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind, int coupling_prec);
 
 /* Stage profiling.  ige_op_set_profiling(op, 1) creates HIP events and clears the

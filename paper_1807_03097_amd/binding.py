@@ -30,7 +30,8 @@ class IgeError(RuntimeError):
 
 class ige_params(C.Structure):
     _fields_ = [("p", C.c_int), ("level", C.c_int), ("kappa", C.c_double), ("q", C.c_int), ("eta", C.c_double),
-                ("gauss_near", C.c_int), ("gauss_singular", C.c_int), ("leaf_depth", C.c_int)]
+                ("gauss_near", C.c_int), ("gauss_singular", C.c_int), ("leaf_depth", C.c_int),
+                ("store_coupling", C.c_int)]
 
 
 class ige_op_info_t(C.Structure):
@@ -260,9 +261,10 @@ class Geometry:
 
 class Operator:
     def __init__(self, geom: Geometry, p: int, level: int, kappa: float, q: int = 8, eta: float = 1.0,
-                 gauss_near: int = 5, gauss_singular: int = 5, leaf_depth: int = -1, plan_only: bool = False):
+                 gauss_near: int = 5, gauss_singular: int = 5, leaf_depth: int = -1, plan_only: bool = False,
+                 store_coupling: int = -1):
         self.geom = geom
-        self.prm = ige_params(p, level, kappa, q, eta, gauss_near, gauss_singular, leaf_depth)
+        self.prm = ige_params(p, level, kappa, q, eta, gauss_near, gauss_singular, leaf_depth, store_coupling)
         self.h = ige_op_plan(geom.h, self.prm) if plan_only else ige_op_assemble(geom.h, self.prm)
         self.info = ige_op_info(self.h)
         self.N = int(self.info.n_dof)

@@ -215,6 +215,7 @@ void check_params(const ige_params &P)
     IGE_REQUIRE(P.gauss_near >= 1 && P.gauss_near <= ige::kMaxG, "gauss_near must be 1..8");
     IGE_REQUIRE(P.gauss_singular >= 1 && P.gauss_singular <= ige::kMaxGs, "gauss_singular must be 1..12");
     IGE_REQUIRE(P.leaf_depth >= -1 && P.leaf_depth <= 10, "leaf_depth must be -1..10");
+    IGE_REQUIRE(P.store_coupling >= -1 && P.store_coupling <= 1, "store_coupling must be -1, 0 or 1");
 }
 
 // host part: unknowns, trees, near pattern, singular pairs, far tables
@@ -386,6 +387,51 @@ int ige_op_assemble(ige_geom geom, const ige_params *prm, ige_op *out)
                 }
                 for (int c = 0; c < op->NC; ++c) op->wrk_of_tgt[c + 1] = op->wrk_of_tgt[c] + cnt[c];
             }
+            // unordered far pairs (t < s) and, per cluster, its partial couplings in
+            // pair order: slot 2k = row side of pair k (cluster t), 2k+1 = column side (s)
+            {
+                std::vector<int32_t> fpair;
+                for (const auto &f : T.far) {
+                    const int32_t gt = (int32_t)(op->lvl_off[f[0]] + f[1]), gs = (int32_t)(op->lvl_off[f[0]] + f[2]);
+                    IGE_REQUIRE(gt != gs, "a cluster is admissible with itself");
+                    if (gt > gs) continue;
+                    IGE_REQUIRE(std::binary_search(T.far.begin(), T.far.end(),
+                                                   std::array<int32_t, 3>{f[0], f[2], f[1]}),
+                                "far pairs are not symmetric");
+                    fpair.push_back(gt);
+                    fpair.push_back(gs);
+                }
+                op->nfp = (int64_t)fpair.size() / 2;
+                IGE_REQUIRE(2 * op->nfp == (int64_t)T.far.size(), "far pairs are not symmetric");
+                std::vector<int64_t> fptr((size_t)op->NC + 1, 0);
+                for (int64_t k = 0; k < op->nfp; ++k) {
+                    fptr[fpair[2 * k] + 1]++;
+                    fptr[fpair[2 * k + 1] + 1]++;
+                }
+                for (int c = 0; c < op->NC; ++c) fptr[c + 1] += fptr[c];
+                std::vector<int32_t> fidx(fptr[op->NC]);
+                std::vector<int64_t> fill(fptr.begin(), fptr.end() - 1);
+                for (int64_t k = 0; k < op->nfp; ++k) {
+                    fidx[fill[fpair[2 * k]]++] = (int32_t)(2 * k);
+                    fidx[fill[fpair[2 * k + 1]]++] = (int32_t)(2 * k + 1);
+                }
+                // store the blocks only when asked: streaming them was measured slower
+                // than evaluating the kernel per apply, at one and at many columns
+                op->stored = P.store_coupling == 1 && op->nfp > 0;
+                // single column with stored blocks: streamed (default) or evaluated
+                // per apply (IGE_M2L_ONE=generate)
+                op->m2l_generate_one = false;
+                if (const char *e = std::getenv("IGE_M2L_ONE")) op->m2l_generate_one = std::string(e) == "generate";
+                if (op->stored) {
+                    const int rbm = ige::coupling_rb_max(v.Q);
+                    op->d_fpair.upload(fpair, s);
+                    op->d_fred_ptr.upload(fptr, s);
+                    op->d_fred_idx.upload(fidx, s);
+                    op->d_gpart.alloc((size_t)2 * op->nfp * 4 * v.Q * rbm);
+                    op->d_gtmp.alloc((size_t)op->NC * ige::coupling_split() * 4 * v.Q * rbm);
+                }
+                if (op->stored) op->d_G.alloc((size_t)op->nfp * v.Q * v.Q);
+            }
             op->d_work.upload(op->work, s);
             op->d_partner.upload(partner, s);
             op->d_wrk_of_tgt.upload(op->wrk_of_tgt, s);
@@ -394,6 +440,7 @@ int ige_op_assemble(ige_geom geom, const ige_params *prm, ige_op *out)
             op->d_loc.alloc((size_t)op->NC * 3 * v.Q);
             op->d_ybuf.alloc((size_t)D.P * v.SL * v.SL * 2 * F.rowlen * F.rowlen);
             op->d_part.alloc(std::max<size_t>(1, op->work.size()) * 4 * v.Q);
+            if (op->stored) ige::store_coupling(op);
             IGE_HIP(hipStreamCreate(&op->aux));
             IGE_HIP(hipEventCreateWithFlags(&op->ev_fork, hipEventDisableTiming));
             IGE_HIP(hipEventCreateWithFlags(&op->ev_join, hipEventDisableTiming));
@@ -451,7 +498,8 @@ int ige_op_info(ige_op op, ige_op_info_t *out)
         b += op->d_ext_p.bytes() + op->d_ext_q.bytes() + op->d_eX.bytes() + op->d_ePsi.bytes() + op->d_eC.bytes();
         b += op->d_ePsiF.bytes() + op->d_bpair.bytes() + op->d_leafdof.bytes() + op->d_leafsgn.bytes();
         b += op->d_red_ptr.bytes() + op->d_red_idx.bytes() + op->d_bval.bytes() + op->d_npart.bytes() + op->d_bnpart.bytes();
-        b += op->d_nodeX.bytes() + op->d_nodeT.bytes();
+        b += op->d_nodeX.bytes() + op->d_nodeT.bytes() + op->d_G.bytes() + op->d_G32.bytes() + op->d_gpart.bytes() + op->d_gtmp.bytes();
+        b += op->d_fpair.bytes() + op->d_fred_ptr.bytes() + op->d_fred_idx.bytes();
         b += op->d_Mp.bytes() * 3 + op->d_inc.bytes() + op->d_sing.bytes() + op->d_work.bytes();
         b += op->d_partner.bytes() + op->d_mom.bytes() + op->d_src.bytes() + op->d_loc.bytes() + op->d_part.bytes();
         b += op->d_x.bytes() + op->d_y.bytes() + op->d_V.bytes() + op->d_w.bytes() + op->d_r.bytes();

@@ -1568,6 +1568,10 @@ void launch_m2l(ige_op op, int prec)
 {
     const DevOp &o = op->view;
     if (op->work.empty()) return;
+    if (op->stored && !op->m2l_generate_one) {
+        m2l_stored_one(op, prec);
+        return;
+    }
     if (prec == IGE_F32)
         hipLaunchKernelGGL(k_m2l<float>, dim3(op->work.size()), dim3(kM2LThreads), m2l_shared_bytes(o.Q),
                            op->ctx->stream, o, op->d_work.p, op->d_partner.p, op->d_src.p, op->d_part.p);
@@ -1580,6 +1584,10 @@ void launch_m2l(ige_op op, int prec)
 void launch_m2l_reduce(ige_op op)
 {
     const DevOp &o = op->view;
+    if (op->stored && !op->m2l_generate_one) {
+        m2l_stored_reduce_one(op);
+        return;
+    }
     hipLaunchKernelGGL(k_m2l_reduce, dim3(op->NC), dim3(128), 0, op->ctx->stream, o, op->d_wrk_of_tgt.p,
                        op->d_part.p, op->d_loc.p);
     IGE_LAUNCH_CHECK();

@@ -617,33 +617,38 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
             }
         }
         mark(2);
-        {
-            const int TPG = (o.Q + kNTB - 1) / kNTB;
-            const int S = std::max(1, std::min(kM2LThreadsB / TPG, o.Q));
-            const size_t fixed = sizeof(double) * (3 * o.Q + 1);
-            const size_t per = std::max(sizeof(double2) * 4 * o.Q, sizeof(double2) * (size_t)S * o.Q);
-            const int rb = std::min(4, pick_rb(per, fixed));   // registers: 3 targets x 4 fields x rb columns
-            const dim3 grid(op->work.size(), chunks(rb)), blk(kM2LThreadsB);
-            const size_t shm = fixed + per * rb;
-            if (prec == IGE_F32) {
-                switch (rb) {
-                    case 4: hipLaunchKernelGGL((k_m2l_b<float, 4>), grid, blk, shm, s, o, r, op->d_work.p, op->d_partner.p, op->d_bsrc.p, op->d_bpart.p); break;
-                    case 2: hipLaunchKernelGGL((k_m2l_b<float, 2>), grid, blk, shm, s, o, r, op->d_work.p, op->d_partner.p, op->d_bsrc.p, op->d_bpart.p); break;
-                    default: hipLaunchKernelGGL((k_m2l_b<float, 1>), grid, blk, shm, s, o, r, op->d_work.p, op->d_partner.p, op->d_bsrc.p, op->d_bpart.p); break;
+        if (op->stored) {
+            m2l_stored(op, r, prec, op->d_bsrc.p, op->d_bloc.p, s);
+            mark(3);
+        } else {
+            {
+                const int TPG = (o.Q + kNTB - 1) / kNTB;
+                const int S = std::max(1, std::min(kM2LThreadsB / TPG, o.Q));
+                const size_t fixed = sizeof(double) * (3 * o.Q + 1);
+                const size_t per = std::max(sizeof(double2) * 4 * o.Q, sizeof(double2) * (size_t)S * o.Q);
+                const int rb = std::min(4, pick_rb(per, fixed));   // registers: 3 targets x 4 fields x rb columns
+                const dim3 grid(op->work.size(), chunks(rb)), blk(kM2LThreadsB);
+                const size_t shm = fixed + per * rb;
+                if (prec == IGE_F32) {
+                    switch (rb) {
+                        case 4: hipLaunchKernelGGL((k_m2l_b<float, 4>), grid, blk, shm, s, o, r, op->d_work.p, op->d_partner.p, op->d_bsrc.p, op->d_bpart.p); break;
+                        case 2: hipLaunchKernelGGL((k_m2l_b<float, 2>), grid, blk, shm, s, o, r, op->d_work.p, op->d_partner.p, op->d_bsrc.p, op->d_bpart.p); break;
+                        default: hipLaunchKernelGGL((k_m2l_b<float, 1>), grid, blk, shm, s, o, r, op->d_work.p, op->d_partner.p, op->d_bsrc.p, op->d_bpart.p); break;
+                    }
+                } else {
+                    switch (rb) {
+                        case 4: hipLaunchKernelGGL((k_m2l_b<double, 4>), grid, blk, shm, s, o, r, op->d_work.p, op->d_partner.p, op->d_bsrc.p, op->d_bpart.p); break;
+                        case 2: hipLaunchKernelGGL((k_m2l_b<double, 2>), grid, blk, shm, s, o, r, op->d_work.p, op->d_partner.p, op->d_bsrc.p, op->d_bpart.p); break;
+                        default: hipLaunchKernelGGL((k_m2l_b<double, 1>), grid, blk, shm, s, o, r, op->d_work.p, op->d_partner.p, op->d_bsrc.p, op->d_bpart.p); break;
+                    }
                 }
-            } else {
-                switch (rb) {
-                    case 4: hipLaunchKernelGGL((k_m2l_b<double, 4>), grid, blk, shm, s, o, r, op->d_work.p, op->d_partner.p, op->d_bsrc.p, op->d_bpart.p); break;
-                    case 2: hipLaunchKernelGGL((k_m2l_b<double, 2>), grid, blk, shm, s, o, r, op->d_work.p, op->d_partner.p, op->d_bsrc.p, op->d_bpart.p); break;
-                    default: hipLaunchKernelGGL((k_m2l_b<double, 1>), grid, blk, shm, s, o, r, op->d_work.p, op->d_partner.p, op->d_bsrc.p, op->d_bpart.p); break;
-                }
+                IGE_HIP(hipGetLastError());
             }
+            mark(3);
+            hipLaunchKernelGGL(k_m2l_reduce_b, dim3(op->NC), dim3(256), 0, s, o, r, op->d_wrk_of_tgt.p, op->d_bpart.p,
+                               op->d_bloc.p);
             IGE_HIP(hipGetLastError());
         }
-        mark(3);
-        hipLaunchKernelGGL(k_m2l_reduce_b, dim3(op->NC), dim3(256), 0, s, o, r, op->d_wrk_of_tgt.p, op->d_bpart.p,
-                           op->d_bloc.p);
-        IGE_HIP(hipGetLastError());
         mark(4);
         {
             const size_t per = sizeof(double2) * 3 * o.Q;

@@ -91,6 +91,10 @@ struct ige_op_s {
     std::vector<int64_t> lvl_off;   // host copy
     std::vector<ige::M2LWork> work; // M2L work items (targets with chunks of partners)
     std::vector<int32_t> wrk_of_tgt;    // [NC+1] range of work items per target cluster
+    // stored coupling blocks (one per unordered far pair)
+    bool stored = false;
+    bool m2l_generate_one = true;   // single column: evaluate the kernel per apply even when stored
+    int64_t nfp = 0;
 
     // device buffers
     ige::DBuf<ige::PatchHdr> d_hdr;
@@ -112,6 +116,13 @@ struct ige_op_s {
     ige::DBuf<int32_t> d_partner;       // source global cluster id per work entry
     ige::DBuf<int32_t> d_wrk_of_tgt;
     ige::DBuf<int> d_err;
+    ige::DBuf<int32_t> d_fpair;         // [nfp][2] global cluster ids, t < s
+    ige::DBuf<double2> d_G;             // [nfp][Q][Q]
+    ige::DBuf<float2> d_G32;            // FP32 copy, made on first use
+    ige::DBuf<int64_t> d_fred_ptr;      // [NC+1]
+    ige::DBuf<int32_t> d_fred_idx;      // partial slots per cluster, fixed order
+    ige::DBuf<double2> d_gpart;         // [2 nfp][4][Q][rb]
+    ige::DBuf<double2> d_gtmp;          // [NC][split][4][Q][rb]
     // apply workspaces (one right-hand side at a time)
     ige::DBuf<double2> d_mom;    // [NC][3][Q]   s^1, s^2, d
     ige::DBuf<double2> d_src;    // [NC][4][Q]   v_x, v_y, v_z, d
@@ -144,6 +155,16 @@ void launch_near_singular(ige_op op);
 void launch_p2m(ige_op op, const double2 *x);
 void launch_m2m(ige_op op);
 void launch_m2l(ige_op op, int prec);
+// stored coupling blocks: build, FP32 copy, and the M2L + reduce of r columns
+// (fields [NC][4][Q][r] in, test-side fields [NC][3][Q][r] out)
+void store_coupling(ige_op op);
+void ensure_coupling32(ige_op op);
+int coupling_rb_max(int Q);
+int coupling_split();
+void m2l_stored(ige_op op, int r, int prec, const double2 *src, double2 *loc, hipStream_t s);
+// one column on the context stream (d_src -> d_gpart, then d_gpart -> d_loc)
+void m2l_stored_one(ige_op op, int prec);
+void m2l_stored_reduce_one(ige_op op);
 void launch_m2l_reduce(ige_op op);
 void launch_l2l(ige_op op);
 void launch_spmv(ige_op op, const double2 *x, double2 *y, hipStream_t st);

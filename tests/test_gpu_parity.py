@@ -80,6 +80,36 @@ def test_apply_matches_oracle(oracle_mod, ctx, case):
         assert _rel(Y[c], yc) <= 1e-14
 
 
+@pytest.mark.parametrize("case", [CASES[2], CASES[4], CASES[8]], ids=["sphere-d1", "torus-d1", "sphere-d0"])
+def test_stored_and_generated_coupling_match_oracle(oracle_mod, ctx, case):
+    """The stored coupling blocks (one per unordered pair, applied with their
+    transposes) and the per-apply evaluation give the same operator."""
+    from paper_1807_03097_amd import binding as B
+    name, p, m, kappa, q, eta, d, g, gs = case
+    _say(f"case {case}")
+    pats = _geom(name)
+    geom = B.Geometry(ctx, pats)
+    o = oracle_mod.Oracle(pats, p, m, kappa, g=g, gs=gs)
+    x = W.random_coeffs(op_n := B.Operator(geom, p, m, kappa, q, eta, g, gs, d, plan_only=True).N, 0)
+    yo = o.fmm_apply(x, q, eta, d)
+    X = np.stack([x] + [W.random_coeffs(op_n, s) for s in range(1, 7)])
+    res = {}
+    for store in (1, 0):
+        op = B.Operator(geom, p, m, kappa, q, eta, g, gs, d, store_coupling=store)
+        y = op.apply(x)
+        err = _rel(y, yo)
+        Y = op.apply(X)
+        errb = _rel(Y[0], yo)
+        y32 = op.apply(x, prec=B.IGE_F32)
+        err32 = _rel(y32, yo)
+        _say(f"  store={store}: err={err:.2e} batched={errb:.2e} fp32={err32:.2e}")
+        assert err <= TOL and errb <= TOL
+        assert 1e-12 < err32 <= 1e-5
+        res[store] = (y, Y)
+        op.close()
+    assert _rel(res[1][1], res[0][1]) <= 1e-13
+
+
 def test_coupling_kernel_evaluation_accuracy(ctx):
     """The coupling stage's own evaluation of e^{ikr}/(4 pi r) (eq:HelmholtzGreen)
     against numpy's exp over r in [1e-3, 30] and kappa up to 40."""
