@@ -12,6 +12,13 @@ L2P and the near-field product) to the device-resident vector; the operator is
 assembled once before timing.  The JSON line reports DOF/s = N / t_step.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+--mode serve instead measures the serving loop: a stream of independent scattering
+solves (seeded synthetic requests: sphere or torus with jittered control points,
+level 3..6, degree 1..2, kappa in [1, 20], one random plane wave each, GMRES to a
+relative residual of 1e-6) arriving with exponential inter-arrival times; it
+reports completed solves per second and the p50 / p99 latency from arrival to the
+solution in host memory.
 """
 from __future__ import annotations
 
@@ -42,6 +49,12 @@ def parse():
     ap.add_argument("--store-coupling", type=int, default=-1, choices=(-1, 0, 1),
                     help="coupling blocks: 1 stored, 0 evaluated per apply, -1 stored if they fit")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--mode", choices=("matvec", "serve"), default="matvec")
+    ap.add_argument("--requests", type=int, default=32, help="serve: number of requests")
+    ap.add_argument("--rate", type=float, default=20.0, help="serve: mean arrivals per second")
+    ap.add_argument("--workers", type=int, default=4, help="serve: concurrent requests (one stream each)")
+    ap.add_argument("--maxit", type=int, default=3000, help="serve: GMRES iteration cap per request")
+    ap.add_argument("--refine", action="store_true", help="serve: FP64 refinement around FP32-coupling solves")
     return ap.parse_args()
 
 
@@ -65,12 +78,103 @@ def cpu_baseline(pats, p, m, kappa, q, eta, d, x, rows):
                       f"whole-mesh moment pass), {dt:.1f} s"}, sel, y
 
 
+def serve_requests(n, seed):
+    """Seeded request parameters: geometry, jitter seed, level, degree, kappa, wave."""
+    import numpy as np
+    from paper_1807_03097_amd import workloads as W
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0, n)
+    out = []
+    for i in range(n):
+        ri = np.random.default_rng(i)
+        geo = "sphere" if ri.random() < 0.5 else "torus"
+        m = int(ri.integers(3, 7))
+        p = int(ri.integers(1, 3))
+        kappa = float(ri.uniform(1.0, 20.0))
+        d, pol = W.random_plane_waves(1, 1000 + i)
+        out.append({"geo": geo, "jitter_seed": i, "m": m, "p": p, "kappa": kappa, "dir": d[0], "pol": pol[0],
+                    "gap": float(gaps[i])})
+    return out
+
+
+def run_serving(args):
+    import numpy as np
+    import torch
+
+    from paper_1807_03097_amd import binding as B
+    from paper_1807_03097_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    ctx = B.Context(0)
+    reqs = serve_requests(args.requests, 4)
+    geoms = []
+    for rq in reqs:
+        base = W.cube_sphere() if rq["geo"] == "sphere" else W.torus()
+        geoms.append(B.Geometry(ctx, W.jitter(base, 0.01, rq["jitter_seed"])))
+    srv = B.Server(ctx, args.workers)
+    t0 = time.perf_counter()
+    arrival, tickets = [], []
+    t_next = 0.0
+    for k, rq in enumerate(reqs):
+        t_next += rq["gap"] / args.rate
+        dt = t0 + t_next - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        arrival.append(time.perf_counter() - t0)
+        tickets.append(srv.submit(geoms[k], rq["p"], rq["m"], rq["kappa"], rq["dir"], rq["pol"], q=8, eta=args.eta,
+                                  tol=1e-6, restart=1500, maxit=args.maxit, refine=args.refine,
+                                  inner_tol=1e-4, inner_prec=B.IGE_F32))
+    stats = []
+    for k, t in enumerate(tickets):
+        stats.append(srv.wait(t))
+        log(f"done {k + 1}/{len(tickets)} at {time.perf_counter() - t0:.1f} s")
+    srv.close()
+    # server clock starts at Server(); t0 was taken right after it
+    lat = np.array([st["t_done"] - a for st, a in zip(stats, arrival)])
+    done = [st for st in stats if st["rc"] == 0]
+    capped = [st for st in stats if st["rc"] == -3]
+    span = max(st["t_done"] for st in stats) - min(arrival)
+    for k, (rq, st) in enumerate(zip(reqs, stats)):
+        log(f"req {k:3d} {rq['geo']:6s} m={rq['m']} p={rq['p']} kappa={rq['kappa']:5.2f} N={st['n_dof']:6d} "
+            f"iters={st['iters']:5d} relres={st['relres']:.1e} rc={st['rc']} asm={st['assemble_s']:.3f}s "
+            f"solve={st['solve_s']:.3f}s latency={lat[k]:.3f}s")
+    out = {
+        "metric": "EFIE serving solves/s",
+        "value": len(done) / span,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "f64" if not args.refine else "f64+f32-coupling",
+        "data": "synthetic",
+        "p50_latency_s": float(np.percentile(lat, 50)),
+        "p99_latency_s": float(np.percentile(lat, 99)),
+        "completed": len(done),
+        "capped_at_maxit": len(capped),
+        "requests": len(stats),
+        "span_s": span,
+        "config": {"workload": f"{len(reqs)} solves, exponential arrivals at {args.rate}/s (seed 4); sphere or "
+                               f"torus, control-point jitter N(0, 0.01^2), m in 3..6, p in 1..2, kappa in [1, 20], "
+                               f"q=8, eta={args.eta}, GMRES tol 1e-6, restart 1500, maxit {args.maxit}",
+                   "workers": args.workers, "refine": bool(args.refine)},
+        "solves_s_completed_only": len(done) / span,
+        "total_iters": int(sum(st["iters"] for st in stats)),
+        "total_dof": int(sum(st["n_dof"] for st in stats)),
+    }
+    print(json.dumps(out), flush=True)
+    for g in geoms:
+        g.close()
+    ctx.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU (one operator per device); "
                                    "multi-GPU sharding is described in DESIGN.md but not built"}))
         sys.exit(2)
+    if args.mode == "serve":
+        run_serving(args)
+        return
     import numpy as np
     import torch
 

@@ -211,6 +211,44 @@ typedef struct {
 int ige_solve(ige_op op, int r, const ige_c64 *f, ige_c64 *x, int ptr_kind, const ige_solve_opts *opts,
               ige_solve_stats *stats);
 
+/* ---- Serving: many independent scattering solves on one device --------------
+ * A server owns n_workers host threads, each with its own HIP stream on the device
+ * of ctx, so the assembly and solve kernels of several requests share the device.
+ * A request is one full solve: the operator of geom with the parameters prm
+ * (assembled on the worker's stream, Sec. 3-4), the right-hand side of one plane
+ * wave e_inc = pol exp(i kappa dir.x) (as ige_rhs_plane_wave), GMRES with opts
+ * from x0 = 0 (as ige_solve), and the copy of the solution to host memory.
+ * Admission: requests wait in arrival order and start first-fit when their device
+ * footprint (planned on the host at submission: near-field blocks, element and
+ * cluster data, Krylov basis of opts.restart vectors) fits in hbm_budget next to
+ * the running requests; the oldest waiting request is overtaken only during its
+ * first second of waiting.  hbm_budget 0: 80 % of the free device memory.
+ * The caller keeps geom alive until its requests have finished.  Requests that
+ * run concurrently share the device and do not synchronise with each other.
+ * Timestamps are seconds since the server was created. */
+typedef struct ige_srv_s *ige_srv;
+typedef struct {
+    int state;           /* 0 waiting, 1 running, 2 finished */
+    int rc;              /* when finished: IGE_OK, IGE_ENOTCONV (maxit reached), or the error code */
+    int iters;           /* GMRES iterations */
+    double relres;       /* final true relative residual */
+    int64_t n_dof;
+    size_t footprint;    /* planned device bytes used for admission */
+    double t_submit, t_start, t_done;
+    double assemble_s, solve_s;
+} ige_srv_stats;
+int ige_srv_create(ige_ctx ctx, int n_workers, size_t hbm_budget, ige_srv *out);
+/* Queue one request; returns at once with its ticket.  IGE_ENOMEM if its footprint
+ * exceeds the budget, IGE_EINVAL on bad parameters. */
+int ige_srv_submit(ige_srv srv, ige_geom geom, const ige_params *prm, const double *dir, const ige_c64 *pol,
+                   const ige_solve_opts *opts, int64_t *ticket);
+int ige_srv_poll(ige_srv srv, int64_t ticket, ige_srv_stats *stats);   /* non-blocking */
+int ige_srv_wait(ige_srv srv, int64_t ticket, ige_srv_stats *stats);   /* blocks until finished */
+/* Copy a finished request's solution (n = its n_dof complex values) to host x. */
+int ige_srv_result(ige_srv srv, int64_t ticket, ige_c64 *x, int64_t n);
+/* Finish every queued and running request, stop the workers, free everything. */
+int ige_srv_destroy(ige_srv srv);
+
 /* Diagnostic: evaluate on the context's device the Helmholtz kernel
  * G_k(r) = e^{ikr}/(4 pi r) (Sec. 2.2, eq. (eq:HelmholtzGreen)) exactly as the
  * coupling stage does in precision prec (IGE_F64 / IGE_F32), from squared

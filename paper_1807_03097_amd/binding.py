@@ -53,6 +53,13 @@ class ige_solve_stats(C.Structure):
     _fields_ = [("iters", C.c_int), ("outer", C.c_int), ("relres", C.c_double), ("seconds", C.c_double)]
 
 
+class ige_srv_stats(C.Structure):
+    _fields_ = [("state", C.c_int), ("rc", C.c_int), ("iters", C.c_int), ("relres", C.c_double),
+                ("n_dof", C.c_int64), ("footprint", C.c_size_t), ("t_submit", C.c_double),
+                ("t_start", C.c_double), ("t_done", C.c_double), ("assemble_s", C.c_double),
+                ("solve_s", C.c_double)]
+
+
 # One HIP runtime per process: torch ships its own libamdhip64 (same soname);
 # loading torch first lets this library bind to that runtime instead of a second one.
 try:
@@ -86,6 +93,13 @@ _SIGS = {
     "ige_rhs_plane_wave": (C.c_int, [_V, C.c_int, _V, _V, _V, C.c_int]),
     "ige_solve": (C.c_int, [_V, C.c_int, _V, _V, C.c_int, C.POINTER(ige_solve_opts), _V]),
     "ige_helmholtz_eval": (C.c_int, [_V, C.c_int64, C.c_double, _V, _V, C.c_int]),
+    "ige_srv_create": (C.c_int, [_V, C.c_int, C.c_size_t, C.POINTER(_V)]),
+    "ige_srv_submit": (C.c_int, [_V, _V, C.POINTER(ige_params), _V, _V, C.POINTER(ige_solve_opts),
+                                 C.POINTER(C.c_int64)]),
+    "ige_srv_poll": (C.c_int, [_V, C.c_int64, C.POINTER(ige_srv_stats)]),
+    "ige_srv_wait": (C.c_int, [_V, C.c_int64, C.POINTER(ige_srv_stats)]),
+    "ige_srv_result": (C.c_int, [_V, C.c_int64, _V, C.c_int64]),
+    "ige_srv_destroy": (C.c_int, [_V]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -337,3 +351,86 @@ class Operator:
 
     def stage_times(self):
         return ige_op_stage_times(self.h)
+
+
+# --- serving ---------------------------------------------------------------------
+def ige_srv_create(ctx, n_workers=4, hbm_budget=0):
+    h = _V()
+    _check(_lib.ige_srv_create(ctx, n_workers, hbm_budget, C.byref(h)))
+    return h
+
+
+def ige_srv_submit(srv, geom, prm, direction, pol, opts):
+    d = np.ascontiguousarray(direction, np.float64)
+    pl = np.ascontiguousarray(pol, np.complex128)
+    t = C.c_int64()
+    _check(_lib.ige_srv_submit(srv, geom, C.byref(prm), _ptr(d), _ptr(pl), C.byref(opts), C.byref(t)))
+    return t.value
+
+
+def ige_srv_poll(srv, ticket):
+    st = ige_srv_stats()
+    _check(_lib.ige_srv_poll(srv, ticket, C.byref(st)))
+    return st
+
+
+def ige_srv_wait(srv, ticket):
+    st = ige_srv_stats()
+    _check(_lib.ige_srv_wait(srv, ticket, C.byref(st)))
+    return st
+
+
+def ige_srv_result(srv, ticket, n):
+    x = np.zeros(n, np.complex128)
+    _check(_lib.ige_srv_result(srv, ticket, _ptr(x), n))
+    return x
+
+
+def ige_srv_destroy(srv):
+    _check(_lib.ige_srv_destroy(srv))
+
+
+def _stats_dict(st):
+    return {k: getattr(st, k) for k, _ in ige_srv_stats._fields_}
+
+
+class Server:
+    """Queue of independent scattering solves on one device (see ige_srv_create)."""
+
+    def __init__(self, ctx: Context, n_workers: int = 4, hbm_budget: int = 0):
+        self.ctx = ctx
+        self.h = ige_srv_create(ctx.h, n_workers, hbm_budget)
+        self._geoms = {}
+
+    def submit(self, geom: Geometry, p, level, kappa, direction, pol, q=8, eta=1.0, leaf_depth=-1,
+               gauss_near=5, gauss_singular=5, tol=1e-6, restart=1500, maxit=10000, refine=False,
+               inner_tol=1e-4, inner_prec=IGE_F32):
+        prm = ige_params(p, level, kappa, q, eta, gauss_near, gauss_singular, leaf_depth, 0)
+        opts = ige_solve_opts(tol, restart, maxit, int(refine), inner_tol, inner_prec)
+        t = ige_srv_submit(self.h, geom.h, prm, direction, pol, opts)
+        self._geoms[t] = geom   # keep the geometry alive until the request is done
+        return t
+
+    def poll(self, ticket):
+        return _stats_dict(ige_srv_poll(self.h, ticket))
+
+    def wait(self, ticket):
+        return _stats_dict(ige_srv_wait(self.h, ticket))
+
+    def result(self, ticket):
+        st = self.wait(ticket)
+        return ige_srv_result(self.h, ticket, st["n_dof"]), st
+
+    def close(self):
+        if self.h:
+            ige_srv_destroy(self.h)
+            self.h = None
+            self._geoms.clear()
+
+    def __del__(self):
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass

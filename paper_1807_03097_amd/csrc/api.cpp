@@ -242,6 +242,31 @@ void plan(ige_op op, const ige_geom_s *geom, ige::NearBlocks &A, std::vector<ige
 
 }  // namespace
 
+}  // extern "C"
+
+// device bytes an assembled operator and a single-column GMRES with the given
+// restart will hold (estimate from the host plan)
+size_t ige::planned_device_bytes(const ige_op_s *op, int restart)
+{
+    const ige::Discretisation &D = op->D;
+    const int64_t E = (int64_t)D.P * D.n * D.n;
+    const int p = D.p, nl = 2 * p * (p + 1), g = op->prm.gauss_near, G2 = g * g;
+    const int Q = (op->prm.q + 1) * (op->prm.q + 1);
+    const int s = op->T.s, W = s + p, nF = 2 * W * (W - 1);
+    const int64_t nblk = nF > 0 ? op->nnz / ((int64_t)nF * nF) : 0;
+    size_t b = 0;
+    b += (size_t)op->nnz * 16;                                   // near-field blocks
+    b += (size_t)nblk * nF * 3 * 16;                             // partial results (2 row chunks)
+    b += (size_t)E * (3 + 4 * nl) * G2 * 8 + (size_t)E * psi_fragment_doubles(nl, G2) * 8 + (size_t)E * 96;
+    b += (size_t)op->NC * Q * (9 * 8 + 11 * 16);                 // node data, moments, fields
+    b += (size_t)op->T.far.size() * 4 * Q * 16 / 4;              // coupling partials (chunks of partners)
+    b += (size_t)op->nsing * 24 + (size_t)D.N * 80;
+    b += ((size_t)restart + 1 + 8) * D.N * 16;                   // Krylov basis and work vectors
+    return b;
+}
+
+extern "C" {
+
 int ige_op_plan(ige_geom geom, const ige_params *prm, ige_op *out)
 {
     return guard([&] {
@@ -266,15 +291,17 @@ int ige_op_plan(ige_geom geom, const ige_params *prm, ige_op *out)
     });
 }
 
-int ige_op_assemble(ige_geom geom, const ige_params *prm, ige_op *out)
+}  // extern "C"
+
+// assembly of the operator of geom on the device and stream of ctx (throws)
+ige_op ige::assemble_on(ige_ctx ctx, const ige_geom_s *geom, const ige_params &prm)
 {
-    return guard([&] {
-        IGE_REQUIRE(geom && prm && out, "null argument");
-        const ige_params P = *prm;
+    ige_op result = nullptr;
+    {
+        const ige_params P = prm;
         check_params(P);
-        IGE_REQUIRE(geom->ctx->device >= 0, "ige_op_assemble needs a device context");
+        IGE_REQUIRE(ctx->device >= 0, "assembly needs a device context");
         const auto t0 = std::chrono::steady_clock::now();
-        ige_ctx ctx = geom->ctx;
         set_device(ctx);
         hipStream_t s = ctx->stream;
         auto *op = new ige_op_s();
@@ -454,7 +481,18 @@ int ige_op_assemble(ige_geom geom, const ige_params *prm, ige_op *out)
         }
         op->assemble_ms =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-        *out = op;
+        result = op;
+    }
+    return result;
+}
+
+extern "C" {
+
+int ige_op_assemble(ige_geom geom, const ige_params *prm, ige_op *out)
+{
+    return guard([&] {
+        IGE_REQUIRE(geom && prm && out, "null argument");
+        *out = ige::assemble_on(geom->ctx, geom, *prm);
     });
 }
 

@@ -144,6 +144,11 @@ struct ige_op_s {
 
 namespace ige {
 
+// assembly of geom's operator on ctx's device and stream (throws ige::Status)
+ige_op assemble_on(ige_ctx ctx, const ige_geom_s *geom, const ige_params &prm);
+// device bytes of an operator planned on the host plus a GMRES with this restart
+size_t planned_device_bytes(const ige_op_s *op, int restart);
+
 // assembly
 void launch_element_data(ige_op op);
 void launch_node_geometry(ige_op op);

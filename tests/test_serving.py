@@ -1,0 +1,139 @@
+"""Serving loop: many independent scattering solves on one device.
+
+Each request is a full solve (assembly, plane-wave right-hand side, GMRES); the
+server runs several at once on separate streams and admits them by their planned
+device footprint.  Checks: results equal direct solves, admission never exceeds the
+budget, an oversized request is refused, and a request's solution does not depend
+on what else runs beside it.
+"""
+import numpy as np
+import pytest
+
+from paper_1807_03097_amd import workloads as W
+
+# (geometry, p, m, kappa, q, eta, leaf depth, plane-wave seed)
+REQS = [
+    ("sphere", 1, 2, 2.0, 6, 1.0, 0, 11),
+    ("torus", 1, 2, 3.0, 6, 1.0, 0, 12),
+    ("sphere", 2, 3, 5.0, 6, 1.0, 1, 13),
+    ("jittered", 1, 3, 4.0, 6, 1.0, 1, 14),
+    ("torus", 2, 2, 6.0, 6, 1.0, 1, 15),
+    ("sphere", 1, 3, 1.5, 5, 1.0, 1, 16),
+]
+TOL = 1e-10
+
+
+def _agree(tol):
+    """Two solves of the same request agree to within the solve tolerance: the
+    element-pair contributions are accumulated with atomic adds, so two assemblies
+    differ in the last bits, and GMRES carries that into the iterates."""
+    return 10 * tol
+
+
+def _geom(B, ctx, name):
+    pats = {"sphere": W.cube_sphere, "torus": W.torus,
+            "jittered": lambda: W.jitter(W.cube_sphere(), 0.01, 3)}[name]()
+    return B.Geometry(ctx, pats)
+
+
+def _wave(seed):
+    d, pol = W.random_plane_waves(1, seed)
+    return d[0], pol[0]
+
+
+def test_server_refuses_host_context():
+    from paper_1807_03097_amd import binding as B
+    c = B.Context(-1)
+    with pytest.raises(B.IgeError):
+        B.Server(c, 2)
+    c.close()
+
+
+@pytest.mark.gpu
+def test_server_matches_direct_solves_and_budget():
+    from paper_1807_03097_amd import binding as B
+    ctx = B.Context(0)
+    geoms = {n: _geom(B, ctx, n) for n in ("sphere", "torus", "jittered")}
+    # direct solves on the caller's context
+    ref, fps = [], []
+    for (n, p, m, kap, q, eta, d, seed) in REQS:
+        op = B.Operator(geoms[n], p, m, kap, q, eta, 5, 5, d)
+        di, pol = _wave(seed)
+        f = op.rhs_plane_wave(di, pol)[0]
+        x, st, rc = op.solve(f, tol=TOL, restart=300, maxit=3000)
+        assert rc == 0
+        ref.append(x)
+        op.close()
+    # the server, with a budget that holds about two requests at a time
+    probe = B.Server(ctx, 1)
+    fps = []
+    for (n, p, m, kap, q, eta, d, seed) in REQS:
+        di, pol = _wave(seed)
+        t = probe.submit(geoms[n], p, m, kap, di, pol, q=q, eta=eta, leaf_depth=d, tol=TOL, restart=300, maxit=3000)
+        fps.append(probe.wait(t)["footprint"])
+    probe.close()
+    budget = int(max(fps) * 2.2)
+    srv = B.Server(ctx, 4, budget)
+    tickets = []
+    for (n, p, m, kap, q, eta, d, seed) in REQS:
+        di, pol = _wave(seed)
+        tickets.append(srv.submit(geoms[n], p, m, kap, di, pol, q=q, eta=eta, leaf_depth=d, tol=TOL,
+                                  restart=300, maxit=3000))
+    stats = []
+    for k, t in enumerate(tickets):
+        x, st = srv.result(t)
+        stats.append(st)
+        err = np.linalg.norm(x - ref[k]) / np.linalg.norm(ref[k])
+        print(f"request {k}: N={st['n_dof']} iters={st['iters']} relres={st['relres']:.1e} "
+              f"fp={st['footprint'] / 2**20:.1f} MiB vs direct {err:.1e}", flush=True)
+        assert st["rc"] == 0 and st["relres"] <= TOL * 1.05
+        assert err <= _agree(TOL)
+    # admission: requests running at the same time fit the budget together
+    for i in range(len(stats)):
+        live = [j for j in range(len(stats))
+                if stats[j]["t_start"] < stats[i]["t_done"] and stats[i]["t_start"] < stats[j]["t_done"]]
+        # every set of overlapping requests at the start of request i
+        at = [j for j in live if stats[j]["t_start"] <= stats[i]["t_start"] < stats[j]["t_done"]]
+        assert sum(stats[j]["footprint"] for j in at) <= budget
+    assert max(st["t_start"] for st in stats) > 0.0
+    srv.close()
+    # a request larger than the budget is refused at submission
+    tiny = B.Server(ctx, 1, 1 << 20)
+    n, p, m, kap, q, eta, d, seed = REQS[2]
+    di, pol = _wave(seed)
+    with pytest.raises(B.IgeError):
+        tiny.submit(geoms[n], p, m, kap, di, pol, q=q, eta=eta, leaf_depth=d)
+    tiny.close()
+    for g in geoms.values():
+        g.close()
+    ctx.close()
+
+
+@pytest.mark.gpu
+def test_solution_alone_equals_solution_in_mix():
+    """The same request solved alone and among five others (four workers)."""
+    from paper_1807_03097_amd import binding as B
+    ctx = B.Context(0)
+    geoms = {n: _geom(B, ctx, n) for n in ("sphere", "torus", "jittered")}
+    n, p, m, kap, q, eta, d, seed = REQS[2]
+    di, pol = _wave(seed)
+    alone = B.Server(ctx, 1)
+    t = alone.submit(geoms[n], p, m, kap, di, pol, q=q, eta=eta, leaf_depth=d, tol=1e-8, restart=200)
+    xa, sa = alone.result(t)
+    alone.close()
+    mix = B.Server(ctx, 4)
+    ts = []
+    for k, (n2, p2, m2, kap2, q2, eta2, d2, seed2) in enumerate(REQS):
+        dd, pp = _wave(seed2)
+        ts.append(mix.submit(geoms[n2], p2, m2, kap2, dd, pp, q=q2, eta=eta2, leaf_depth=d2, tol=1e-8, restart=200))
+    xm, sm = mix.result(ts[2])
+    for t2 in ts:
+        mix.wait(t2)
+    mix.close()
+    err = np.linalg.norm(xm - xa) / np.linalg.norm(xa)
+    print(f"alone iters={sa['iters']} mix iters={sm['iters']} difference {err:.1e}", flush=True)
+    assert sa["rc"] == 0 and sm["rc"] == 0
+    assert err <= _agree(1e-8)
+    for g in geoms.values():
+        g.close()
+    ctx.close()
