@@ -165,8 +165,9 @@ int ige_apply_prec(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind,
  * record; every later single-column apply records its stage boundaries on the
  * context stream (no host synchronisation).  ige_op_stage_times synchronises the
  * stream and returns the average device time (ms) per stage over the last (up to
- * 256) recorded applies: 0 P2M, 1 M2M, 2 M2L, 3 M2L reduce, 4 L2L, 5 near SpMV,
- * 6 L2P.  n: capacity of ms[]; returns the stage count (7). */
+ * 256) recorded applies: 0 P2M, 1 M2M, 2 M2L, 3 M2L reduce, 4 L2L, 5 near-field
+ * product (block pass and reduction), 6 L2P, 7 the block pass alone (the whole
+ * near-field product for r > 1).  n: capacity of ms[]; returns the stage count (8). */
 int ige_op_set_profiling(ige_op op, int on);
 
 /* Scheduling knob: on (default) runs the near-field product on a second stream

@@ -74,7 +74,7 @@ void apply_one(ige_op op, const double2 *x, double2 *y, int prec = IGE_F64)
             mark(6, s);
         }
         mark(7, s);
-        ige::launch_spmv(op, x, y, s);
+        ige::launch_spmv(op, x, y, s, prof ? ev[11] : nullptr);
         mark(8, s);
         if (far) {
             mark(9, s);
@@ -98,7 +98,7 @@ void apply_one(ige_op op, const double2 *x, double2 *y, int prec = IGE_F64)
     IGE_HIP(hipEventRecord(op->ev_fork, s));
     IGE_HIP(hipStreamWaitEvent(s2, op->ev_fork, 0));
     mark(7, s2);
-    ige::launch_spmv(op, x, y, s2);
+    ige::launch_spmv(op, x, y, s2, prof ? ev[11] : nullptr);
     mark(8, s2);
     IGE_HIP(hipEventRecord(op->ev_join, s2));
     ige::launch_m2l(op, prec);
@@ -597,7 +597,7 @@ int ige_op_stage_times(ige_op op, double *ms, int n)
     int cnt = 0;
     int rc = guard([&] {
         IGE_REQUIRE(op && ms, "null argument");
-        const int nst = 7;
+        const int nst = 8;
         for (int i = 0; i < std::min(n, nst); ++i) ms[i] = 0.0;
         const int64_t k = std::min<int64_t>(op->prof_count, ige_op_s::kProfSlots);
         if (k > 0) {
@@ -605,7 +605,7 @@ int ige_op_stage_times(ige_op op, double *ms, int n)
             IGE_HIP(hipStreamSynchronize(op->ctx->stream));
             IGE_HIP(hipStreamSynchronize(op->aux));
             // stage -> (begin event, end event); L2P = leaf part + gather part
-            const int pairs[7][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}, {7, 8}, {5, 6}};
+            const int pairs[8][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}, {7, 8}, {5, 6}, {7, 11}};
             for (int64_t sl = 0; sl < k; ++sl) {
                 hipEvent_t *ev = op->prof_ev.data() + sl * ige_op_s::kProfEv;
                 for (int i = 0; i < std::min(n, nst); ++i) {

@@ -1612,11 +1612,12 @@ int near_blk_u(int nF)
     return 16;
 }
 
-void launch_spmv(ige_op op, const double2 *x, double2 *y, hipStream_t st)
+void launch_spmv(ige_op op, const double2 *x, double2 *y, hipStream_t st, hipEvent_t mid)
 {
     const DevOp &o = op->view;
     if (o.nblk == 0) {
         IGE_HIP(hipMemsetAsync(y, 0, sizeof(double2) * o.N, st));
+        if (mid) IGE_HIP(hipEventRecord(mid, st));
         return;
     }
     const dim3 grid((unsigned)(o.nblk * o.nch)), blk(256);
@@ -1632,6 +1633,7 @@ void launch_spmv(ige_op op, const double2 *x, double2 *y, hipStream_t st)
         default: hipLaunchKernelGGL(k_near_blk<16>, grid, blk, 0, st, o, x, part); break;
     }
     IGE_LAUNCH_CHECK();
+    if (mid) IGE_HIP(hipEventRecord(mid, st));
     hipLaunchKernelGGL(k_near_gather, dim3((unsigned)(((int64_t)o.N * 16 + 255) / 256)), dim3(256), 0, st, o.N, o.red_ptr, o.red_idx, part, y);
     IGE_LAUNCH_CHECK();
 }

@@ -671,6 +671,7 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
     }
     mark(7);
     near_batched(op, r, xt, yt, s);
+    mark(11);
     mark(8);
     mark(9);
     if (far) {

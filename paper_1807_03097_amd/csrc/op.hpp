@@ -81,7 +81,7 @@ struct ige_op_s {
     double assemble_ms = 0.0;
     bool profiling = false;
     static constexpr int kProfSlots = 256;
-    static constexpr int kProfEv = 11;
+    static constexpr int kProfEv = 12;
     std::vector<hipEvent_t> prof_ev;   // [kProfSlots][kProfEv] stage boundary events
     hipStream_t aux = nullptr;         // second stream: near-field product
     bool overlap = true;               // near field concurrent with the far field
@@ -172,7 +172,8 @@ void m2l_stored_one(ige_op op, int prec);
 void m2l_stored_reduce_one(ige_op op);
 void launch_m2l_reduce(ige_op op);
 void launch_l2l(ige_op op);
-void launch_spmv(ige_op op, const double2 *x, double2 *y, hipStream_t st);
+// near-field product; records mid (if given) between the block pass and the reduction
+void launch_spmv(ige_op op, const double2 *x, double2 *y, hipStream_t st, hipEvent_t mid = nullptr);
 int near_blk_u(int nF);   // 64-column groups per block row (template choice)
 void launch_l2p_leaf(ige_op op);
 void launch_l2p_gather(ige_op op, double2 *y);
