@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=16, help="rows of the bounded oracle sample")
     ap.add_argument("--nrhs", type=int, default=1, help="right-hand sides per apply (batched kernels when > 1)")
+    ap.add_argument("--prec", type=int, default=0, choices=(0, 1, 2, 3),
+                    help="coupling precision: 0 FP64, 1 FP32, 2 BF16 matrix cores, 3 split BF16 (3 products)")
     ap.add_argument("--store-coupling", type=int, default=-1, choices=(-1, 0, 1),
                     help="coupling blocks: 1 stored, 0 evaluated per apply, -1 stored if they fit")
     ap.add_argument("--verbose", action="store_true")
@@ -221,7 +223,7 @@ def main():
     x = torch.from_numpy(xh).to(dev)
     y = torch.empty_like(x)
     for _ in range(args.warmup):
-        op.apply(x, y)
+        op.apply(x, y, prec=args.prec)
     torch.cuda.synchronize()
 
     op.set_profiling(True)
@@ -231,7 +233,7 @@ def main():
     ev0.record(stream)
     w0 = time.perf_counter()
     for _ in range(args.steps):
-        op.apply(x, y)
+        op.apply(x, y, prec=args.prec)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
@@ -273,7 +275,7 @@ def main():
     op.set_overlap(False)
     op.set_profiling(True)
     for _ in range(min(args.steps, 20)):
-        op.apply(x, y)
+        op.apply(x, y, prec=args.prec)
     torch.cuda.synchronize()
     st_iso = {n: float(v) for n, v in zip(names, op.stage_times())}
     op.set_profiling(False)
@@ -301,7 +303,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": ["f64", "f64 (f32 coupling)", "f64 (bf16 matrix-core coupling)",
+                  "f64 (split-bf16 matrix-core coupling)"][args.prec],
         "data": "synthetic",
         "config": {"workload": f"FMM matvec: 6-patch NURBS sphere, level {m}, p={p}, kappa={kappa}, q={q}, "
                                f"5x5 Gauss near field, x ~ N(0,1)+iN(0,1) seed 0",

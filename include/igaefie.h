@@ -146,7 +146,7 @@ int ige_op_dofmap(ige_op op, int32_t *dof, int8_t *sgn);
  * cluster id on level l: patch*4^l + k2*2^l + k1.  Either pointer may be NULL. */
 int ige_op_partition(ige_op op, int32_t *far, int32_t *near);
 
-enum { IGE_F64 = 0, IGE_F32 = 1 };
+enum { IGE_F64 = 0, IGE_F32 = 1, IGE_BF16 = 2, IGE_BF16X3 = 3 };
 
 /* y = A x for r right-hand sides (A the compressed operator).  x, y: N*r complex.
  * r > 1 runs the batched kernels (columns in chunks, every kernel value and matrix
@@ -154,11 +154,20 @@ enum { IGE_F64 = 0, IGE_F32 = 1 };
 int ige_apply(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind);
 
 /* As ige_apply, with the coupling stage (interpolated-kernel values and their
- * products, a5) in the given precision: IGE_F64, or IGE_F32 (FP32 kernel values:
- * evaluated and accumulated in FP32 when generated on the fly, an FP32 copy of the
- * stored blocks with FP64 accumulation when stored; relative error about
- * kappa * diam * 2^-23 on the far field).  Near field, moments and transfers stay
- * FP64.  The FP32 copy is made on the first FP32 apply (half the FP64 block bytes). */
+ * products, a5) in the given precision:
+ *   IGE_F64   FP64 (as ige_apply);
+ *   IGE_F32   FP32 kernel values: evaluated and accumulated in FP32 when generated
+ *             on the fly, an FP32 copy of the stored blocks with FP64 accumulation when
+ *             stored; relative error about kappa * diam * 2^-23 on the far field;
+ *   IGE_BF16  the kernel matrices rounded to BF16 once (stored, both orientations) and
+ *             applied with the source fields rounded to BF16 on the BF16 matrix cores
+ *             with FP32 accumulation (complex products as one real product);
+ *             relative error about 2^-9 on the far field;
+ *   IGE_BF16X3 the same with both factors split into a high and a low BF16 part and
+ *             three products (high*high + high*low + low*high); about 2^-16.
+ * Near field, moments and transfers stay FP64.  The FP32 copy and the BF16 blocks are
+ * made on first use (BF16: 2 * pairs * Qp * 2Qp * 2 bytes per plane, Qp = Q rounded
+ * up to 16). */
 int ige_apply_prec(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind, int coupling_prec);
 
 /* Stage profiling.  ige_op_set_profiling(op, 1) creates HIP events and clears the
@@ -191,7 +200,7 @@ typedef struct {
                         residual f - A x, inner GMRES on the inner_prec operator for the
                         correction to inner_tol, x += correction, repeated */
     double inner_tol;
-    int inner_prec;  /* IGE_F64 or IGE_F32 coupling for the inner solves */
+    int inner_prec;  /* coupling precision of the inner solves (IGE_F64 .. IGE_BF16X3) */
 } ige_solve_opts;
 
 typedef struct {

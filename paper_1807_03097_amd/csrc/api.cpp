@@ -10,6 +10,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <unordered_map>
 
 #include "op.hpp"
 
@@ -449,9 +450,43 @@ ige_op ige::assemble_on(ige_ctx ctx, const ige_geom_s *geom, const ige_params &p
                 // per apply (IGE_M2L_ONE=generate)
                 op->m2l_generate_one = false;
                 if (const char *e = std::getenv("IGE_M2L_ONE")) op->m2l_generate_one = std::string(e) == "generate";
+                if (op->nfp > 0) {
+                    op->d_fpair.upload(fpair, s);
+                    // matrix-core coupling: per target, work items of up to 32 partners
+                    // with the BF16 block slot (2 pair + orientation) of every ordered pair
+                    std::unordered_map<int64_t, int32_t> pid;
+                    pid.reserve((size_t)op->nfp * 2);
+                    for (int64_t k = 0; k < op->nfp; ++k) pid[(int64_t)fpair[2 * k] * op->NC + fpair[2 * k + 1]] = (int32_t)k;
+                    std::vector<int32_t> mpart, gslot, mcnt(op->NC, 0);
+                    op->mwork.clear();
+                    size_t i = 0;
+                    while (i < T.far.size()) {
+                        const int lvl = T.far[i][0], tg = T.far[i][1];
+                        const int32_t gt = (int32_t)(op->lvl_off[lvl] + tg);
+                        size_t k = i;
+                        const int beg = (int)mpart.size();
+                        while (k < T.far.size() && T.far[k][0] == lvl && T.far[k][1] == tg) {
+                            const int32_t gs = (int32_t)(op->lvl_off[lvl] + T.far[k][2]);
+                            mpart.push_back(gs);
+                            gslot.push_back(gt < gs ? 2 * pid.at((int64_t)gt * op->NC + gs)
+                                                    : 2 * pid.at((int64_t)gs * op->NC + gt) + 1);
+                            ++k;
+                        }
+                        for (int b = beg; b < (int)mpart.size(); b += 32) {
+                            op->mwork.push_back({gt, b, std::min((int)mpart.size(), b + 32)});
+                            mcnt[gt]++;
+                        }
+                        i = k;
+                    }
+                    std::vector<int32_t> mwt(op->NC + 1, 0);
+                    for (int c = 0; c < op->NC; ++c) mwt[c + 1] = mwt[c] + mcnt[c];
+                    op->d_mwork.upload(op->mwork, s);
+                    op->d_mpartner.upload(mpart, s);
+                    op->d_gslot.upload(gslot, s);
+                    op->d_mwrk_of_tgt.upload(mwt, s);
+                }
                 if (op->stored) {
                     const int rbm = ige::coupling_rb_max(v.Q);
-                    op->d_fpair.upload(fpair, s);
                     op->d_fred_ptr.upload(fptr, s);
                     op->d_fred_idx.upload(fidx, s);
                     op->d_gpart.alloc((size_t)2 * op->nfp * 4 * v.Q * rbm);
@@ -538,6 +573,7 @@ int ige_op_info(ige_op op, ige_op_info_t *out)
         b += op->d_red_ptr.bytes() + op->d_red_idx.bytes() + op->d_bval.bytes() + op->d_npart.bytes() + op->d_bnpart.bytes();
         b += op->d_nodeX.bytes() + op->d_nodeT.bytes() + op->d_G.bytes() + op->d_G32.bytes() + op->d_gpart.bytes() + op->d_gtmp.bytes();
         b += op->d_fpair.bytes() + op->d_fred_ptr.bytes() + op->d_fred_idx.bytes();
+        b += op->d_Gb1.bytes() + op->d_Gb3.bytes() + op->d_vb.bytes() + op->d_bmpart.bytes();
         b += op->d_Mp.bytes() * 3 + op->d_inc.bytes() + op->d_sing.bytes() + op->d_work.bytes();
         b += op->d_partner.bytes() + op->d_mom.bytes() + op->d_src.bytes() + op->d_loc.bytes() + op->d_part.bytes();
         b += op->d_x.bytes() + op->d_y.bytes() + op->d_V.bytes() + op->d_w.bytes() + op->d_r.bytes();
@@ -649,7 +685,7 @@ namespace {
 // y = A x for r device columns ([r][N]) in the given coupling precision
 void apply_dev(ige_op op, int r, const double2 *x, double2 *y, int prec)
 {
-    if (r == 1) {
+    if (r == 1 && prec <= IGE_F32) {
         apply_one(op, x, y, prec);
         return;
     }
@@ -667,7 +703,7 @@ int apply_impl(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind, int
         IGE_REQUIRE(op && x && y && r >= 1, "bad apply arguments");
         IGE_REQUIRE(op->assembled, "operator was planned, not assembled");
         IGE_REQUIRE(ptr_kind == IGE_HOST || ptr_kind == IGE_DEVICE, "bad ptr_kind");
-        IGE_REQUIRE(prec == IGE_F64 || prec == IGE_F32, "bad coupling precision");
+        IGE_REQUIRE(prec >= IGE_F64 && prec <= IGE_BF16X3, "bad coupling precision");
         set_device(op->ctx);
         const int64_t N = op->D.N;
         hipStream_t s = op->ctx->stream;
@@ -858,7 +894,7 @@ int ige_solve(ige_op op, int r, const ige_c64 *f, ige_c64 *x, int ptr_kind, cons
         IGE_REQUIRE(ptr_kind == IGE_HOST || ptr_kind == IGE_DEVICE, "bad ptr_kind");
         IGE_REQUIRE(opts->restart >= 1 && opts->maxit >= 0 && std::isfinite(opts->tol) && opts->tol >= 0.0,
                     "bad solve options");
-        IGE_REQUIRE(!opts->refine || (opts->inner_prec == IGE_F64 || opts->inner_prec == IGE_F32), "bad inner precision");
+        IGE_REQUIRE(!opts->refine || (opts->inner_prec >= IGE_F64 && opts->inner_prec <= IGE_BF16X3), "bad inner precision");
         IGE_REQUIRE(!opts->refine || (std::isfinite(opts->inner_tol) && opts->inner_tol > 0.0 && opts->inner_tol < 1.0),
                     "inner_tol must be in (0, 1)");
         set_device(op->ctx);

@@ -617,7 +617,13 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
             }
         }
         mark(2);
-        if (op->stored) {
+        if (prec == IGE_BF16 || prec == IGE_BF16X3) {
+            m2l_bf16(op, r, prec == IGE_BF16X3 ? 3 : 1, op->d_bsrc.p, s);
+            mark(3);
+            hipLaunchKernelGGL(k_m2l_reduce_b, dim3(op->NC), dim3(256), 0, s, o, r, op->d_mwrk_of_tgt.p,
+                               op->d_bmpart.p, op->d_bloc.p);
+            IGE_HIP(hipGetLastError());
+        } else if (op->stored) {
             m2l_stored(op, r, prec, op->d_bsrc.p, op->d_bloc.p, s);
             mark(3);
         } else {

@@ -123,6 +123,13 @@ struct ige_op_s {
     ige::DBuf<int32_t> d_fred_idx;      // partial slots per cluster, fixed order
     ige::DBuf<double2> d_gpart;         // [2 nfp][4][Q][rb]
     ige::DBuf<double2> d_gtmp;          // [NC][split][4][Q][rb]
+    // matrix-core coupling: BF16 blocks (1 plane, or high + low planes), work items of
+    // up to 32 partners, block slot per partner entry, operand buffer, partials
+    ige::DBuf<__bf16> d_Gb1, d_Gb3, d_vb;
+    std::vector<ige::M2LWork> mwork;
+    ige::DBuf<ige::M2LWork> d_mwork;
+    ige::DBuf<int32_t> d_mpartner, d_gslot, d_mwrk_of_tgt;
+    ige::DBuf<double2> d_bmpart;
     // apply workspaces (one right-hand side at a time)
     ige::DBuf<double2> d_mom;    // [NC][3][Q]   s^1, s^2, d
     ige::DBuf<double2> d_src;    // [NC][4][Q]   v_x, v_y, v_z, d
@@ -170,6 +177,10 @@ void m2l_stored(ige_op op, int r, int prec, const double2 *src, double2 *loc, hi
 // one column on the context stream (d_src -> d_gpart, then d_gpart -> d_loc)
 void m2l_stored_one(ige_op op, int prec);
 void m2l_stored_reduce_one(ige_op op);
+// matrix-core coupling of r columns in BF16 (split 1) or split BF16 (split 3):
+// fields [NC][4][Q][r] -> partials per work item [mwork][4][Q][r] (d_bmpart)
+void m2l_bf16(ige_op op, int r, int split, const double2 *src, hipStream_t s);
+void ensure_coupling_bf16(ige_op op, int split);
 void launch_m2l_reduce(ige_op op);
 void launch_l2l(ige_op op);
 // near-field product; records mid (if given) between the block pass and the reduction

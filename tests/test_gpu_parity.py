@@ -247,6 +247,47 @@ def test_fp32_coupling_apply_and_refined_solve(oracle_mod, ctx):
         assert _rel(Xir[c], X64[c]) <= 1e-6
 
 
+@pytest.mark.parametrize("case", [CASES[2], CASES[3], CASES[4]], ids=["sphere-m3-d1", "sphere-m4-d2", "torus-m3"])
+def test_bf16_matrix_core_coupling(oracle_mod, ctx, case):
+    """Coupling on the BF16 matrix cores: plain BF16 within 2^-9-level error of the
+    oracle, split BF16 (three products) within 2^-16-level error, one and several
+    columns (ragged column chunk) alike; FP64 refinement around split-BF16 inner solves
+    reaches the FP64 tolerance and the FP64 solution."""
+    from paper_1807_03097_amd import binding as B
+    name, p, m, kappa, q, eta, d, g, gs = case
+    _say(f"case {case}")
+    pats = _geom(name)
+    geom = B.Geometry(ctx, pats)
+    op = B.Operator(geom, p, m, kappa, q, eta, g, gs, d)
+    x = W.random_coeffs(op.N, 0)
+    yo = oracle_mod.Oracle(pats, p, m, kappa, g=g, gs=gs).fmm_apply(x, q, eta, d)
+    X = np.stack([x] + [W.random_coeffs(op.N, s) for s in range(1, 11)])
+    y64 = op.apply(X)
+    for prec, lo, hi in ((B.IGE_BF16, 1e-6, 1e-2), (B.IGE_BF16X3, 1e-12, 2e-4)):
+        y1 = op.apply(x, prec=prec)
+        Y = op.apply(X, prec=prec)
+        e1, eb = _rel(y1, yo), _rel(Y[0], yo)
+        eall = max(_rel(Y[c], y64[c]) for c in range(len(X)))
+        _say(f"  prec {prec}: 1 column {e1:.2e}, 11 columns {eb:.2e}, worst column vs FP64 {eall:.2e}")
+        assert lo < e1 <= hi and lo < eb <= hi and eall <= hi
+    if op.N > 1000:   # the unpreconditioned FP64 reference solve needs thousands of iterations
+        op.close()
+        return
+    dirs, pols = W.fibonacci_plane_waves(2)
+    F = op.rhs_plane_wave(dirs, pols)
+    X64, st64, rc = op.solve(F, tol=1e-10, restart=100, maxit=4000)
+    assert rc == 0
+    Xir, stir, rc2 = op.solve(F, tol=1e-10, restart=100, maxit=4000, refine=True, inner_tol=1e-4,
+                              inner_prec=B.IGE_BF16X3)
+    assert rc2 == 0
+    for c in range(2):
+        _say(f"  col {c}: FP64 iters {st64[c][0]}, split-BF16 IR iters {stir[c][0]} outer {stir[c][1]} "
+             f"relres {stir[c][2]:.2e}")
+        assert stir[c][2] <= 1.05e-10
+        assert _rel(Xir[c], X64[c]) <= 1e-6
+    op.close()
+
+
 def test_c2_full_size_sampled_rows(oracle_mod, ctx):
     """Matvec configuration: sphere, level 5, p = 2, kappa = 8, q = 8, 5x5 Gauss, x seed 0,
     as timed by the benchmark; rows sampled evenly, computed one by one by the oracle."""
