@@ -584,6 +584,9 @@ int pick_rb(size_t bytes_per_col, size_t fixed = 0)
     }                                                                                                        \
     IGE_HIP(hipGetLastError())
 
+int near_mfma_mtw_ok(int nF, int rc);
+void near_batched_mfma(ige_op op, int r, const double2 *xt, double2 *yt, hipStream_t s);
+
 void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, double2 *yt, hipEvent_t *ev, int prec)
 {
     const DevOp &o = op->view;
@@ -676,7 +679,8 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
         for (int i = 1; i <= 6; ++i) mark(i);
     }
     mark(7);
-    near_batched(op, r, xt, yt, s);
+    if (r >= 8 && near_mfma_mtw_ok(o.nF, o.rc)) near_batched_mfma(op, r, xt, yt, s);
+    else near_batched(op, r, xt, yt, s);
     mark(11);
     mark(8);
     mark(9);
@@ -686,6 +690,174 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
     }
     mark(10);
     hipLaunchKernelGGL(k_to_cols, dim3((tot + 255) / 256), dim3(256), 0, s, N, r, yt, y);
+    IGE_HIP(hipGetLastError());
+}
+
+}  // namespace ige
+
+// ---------------------------------------------------------------------------
+// Near-field product for many columns on the FP64 matrix cores (16x16x4: lane l
+// supplies A[l%16][l/16] and B[l/16][l%16]; accumulator register j of lane l holds
+// D[l/16 + 4j][l%16]).  For a stored block B (target leaf t, source leaf s) and the
+// row chunk [r0, r0 + rc):
+//   DIR 0: Y_t[r0 + m][n] = sum_k B[r0 + m][k] X_s[k][n]            (rows of the chunk)
+//   DIR 1: Y_s[m][n]      = sum_{k < rc} B[r0 + k][m] X_t[r0 + k][n]  (off-diagonal blocks)
+// Complex products as four real ones: Yr += Br Xr - Bi Xi, Yi += Br Xi + Bi Xr.
+// A workgroup takes one (block, row chunk) and 16 NT columns; wave w owns the column
+// tile w % NT and every (4 / NT)-th row tile.  Results go to the partial-result slots
+// ([slot][r]) that the fixed-order per-unknown reduction sums.
+// ---------------------------------------------------------------------------
+namespace ige {
+namespace {
+
+typedef double dx4b __attribute__((ext_vector_type(4)));
+
+template <int DIR, int NT, int MTW>
+__global__ __launch_bounds__(256) void k_near_mfma(DevOp o, int r, const double2 *xt, double2 *part)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int nF = o.nF;
+    const int64_t b = blockIdx.x / o.nch;
+    const int ch = blockIdx.x % o.nch;
+    const int lt = o.bpair[2 * b], ls = o.bpair[2 * b + 1];
+    if (DIR == 1 && lt == ls) return;   // diagonal blocks: no transposed product
+    const int r0 = ch * o.rc, rc = min(o.rc, nF - r0);
+    const int c0 = blockIdx.y * 16 * NT;
+    const int M = DIR == 0 ? rc : nF, K = DIR == 0 ? nF : rc;
+    const int MT = (M + 15) / 16, KS = (K + 3) / 4;
+    const int nt = wv % NT, mstep = 4 / NT, mfirst = wv / NT;
+    const int n = c0 + 16 * nt + (lane & 15);   // this lane's column (B operand and output)
+    const bool nok = n < r;
+    const double2 *Bv = o.bval + (size_t)b * nF * nF;
+    const int32_t *kdof = o.leafdof + (size_t)(DIR == 0 ? ls : lt) * nF + (DIR == 0 ? 0 : r0);
+    dx4b accr[MTW], acci[MTW];
+#pragma unroll
+    for (int i = 0; i < MTW; ++i) {
+        accr[i] = dx4b{0.0, 0.0, 0.0, 0.0};
+        acci[i] = dx4b{0.0, 0.0, 0.0, 0.0};
+    }
+    for (int s = 0; s < KS; ++s) {
+        const int k = 4 * s + (lane >> 4);   // reduction index supplied by this lane
+        double xr = 0.0, xi = 0.0;
+        if (k < K && nok) {
+            const int d = kdof[k];
+            if (d >= 0) {
+                const double2 v = xt[(size_t)d * r + n];
+                xr = v.x;
+                xi = v.y;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < MTW; ++i) {
+            const int mt = mfirst + i * mstep;
+            if (mt >= MT) break;   // uniform over the wave
+            const int m = 16 * mt + (lane & 15), ka = 4 * s + (lane >> 4);
+            double2 a = make_double2(0.0, 0.0);
+            if (m < M && ka < K) a = DIR == 0 ? Bv[(size_t)(r0 + m) * nF + ka] : Bv[(size_t)(r0 + ka) * nF + m];
+            accr[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, xr, accr[i], 0, 0, 0);
+            accr[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, xi, accr[i], 0, 0, 0);
+            acci[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, xi, acci[i], 0, 0, 0);
+            acci[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, xr, acci[i], 0, 0, 0);
+        }
+    }
+    if (!nok) return;
+#pragma unroll
+    for (int i = 0; i < MTW; ++i) {
+        const int mt = mfirst + i * mstep;
+        if (mt >= MT) break;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int m = 16 * mt + (lane >> 4) + 4 * j;
+            if (m >= M) continue;
+            const size_t slot = DIR == 0 ? (size_t)b * nF + r0 + m
+                                         : (size_t)o.nblk * nF + ((size_t)b * o.nch + ch) * nF + m;
+            part[slot * r + n] = make_double2(accr[i][j], acci[i][j]);
+        }
+    }
+}
+
+// yt[i][c] = sum of the partial results of unknown i, column c ([slot][r] layout),
+// 16 lanes per (unknown, column) with a fixed butterfly
+__global__ __launch_bounds__(256) void k_near_gather_r(int N, int r, const int64_t *ptr, const int32_t *idx,
+                                                       const double2 *part, double2 *yt)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int sub = (int)(t & 15);
+    const int64_t ic = t >> 4;
+    const int64_t i = ic / r;
+    const int c = (int)(ic % r);
+    double re = 0.0, im = 0.0;
+    if (i < N)
+        for (int64_t k = ptr[i] + sub; k < ptr[i + 1]; k += 16) {
+            const double2 v = part[(size_t)idx[k] * r + c];
+            re += v.x;
+            im += v.y;
+        }
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1) {
+        re += __shfl_xor(re, off, 16);
+        im += __shfl_xor(im, off, 16);
+    }
+    if (i < N && sub == 0) yt[(size_t)i * r + c] = make_double2(re, im);
+}
+
+template <int DIR, int NT>
+void launch_near_mfma(ige_op op, int r, const double2 *xt, double2 *part, hipStream_t s)
+{
+    const DevOp &o = op->view;
+    const int M = DIR == 0 ? o.rc : o.nF;
+    const int MT = (M + 15) / 16, mstep = 4 / NT;
+    const int mtw = (MT + mstep - 1) / mstep;
+    const dim3 grid((unsigned)(o.nblk * o.nch), (unsigned)((r + 16 * NT - 1) / (16 * NT))), blk(256);
+#define IGE_NM_CASE(W)                                                                                   \
+    case W: hipLaunchKernelGGL((k_near_mfma<DIR, NT, W>), grid, blk, 0, s, o, r, xt, part); break;
+    switch (mtw) {
+        IGE_NM_CASE(1)
+        IGE_NM_CASE(2)
+        IGE_NM_CASE(3)
+        IGE_NM_CASE(4)
+        IGE_NM_CASE(6)
+        IGE_NM_CASE(8)
+        IGE_NM_CASE(12)
+        IGE_NM_CASE(16)
+        default: throw Status{IGE_EINVAL, "near-field block too large for the matrix-core product"};
+    }
+#undef IGE_NM_CASE
+    IGE_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+int near_mfma_mtw_ok(int nF, int rc)
+{
+    for (int NT : {1, 2, 4})
+        for (int M : {rc, nF}) {
+            const int MT = (M + 15) / 16, ms = 4 / NT, w = (MT + ms - 1) / ms;
+            if (w > 16 || (w > 4 && w != 6 && w != 8 && w != 12 && w != 16)) return 0;
+        }
+    return 1;
+}
+
+void near_batched_mfma(ige_op op, int r, const double2 *xt, double2 *yt, hipStream_t s)
+{
+    const DevOp &o = op->view;
+    const size_t need = (size_t)o.nblk * o.nF * (1 + o.nch) * r;
+    if (op->d_bnpart_r.n < need) op->d_bnpart_r.alloc(need);
+    double2 *part = op->d_bnpart_r.p;
+    const int NT = r > 32 ? 4 : (r > 16 ? 2 : 1);
+    if (NT == 4) {
+        launch_near_mfma<0, 4>(op, r, xt, part, s);
+        launch_near_mfma<1, 4>(op, r, xt, part, s);
+    } else if (NT == 2) {
+        launch_near_mfma<0, 2>(op, r, xt, part, s);
+        launch_near_mfma<1, 2>(op, r, xt, part, s);
+    } else {
+        launch_near_mfma<0, 1>(op, r, xt, part, s);
+        launch_near_mfma<1, 1>(op, r, xt, part, s);
+    }
+    const int64_t tot = (int64_t)o.N * r * 16;
+    hipLaunchKernelGGL(k_near_gather_r, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, o.N, r, o.red_ptr,
+                       o.red_idx, part, yt);
     IGE_HIP(hipGetLastError());
 }
 

@@ -140,6 +140,7 @@ struct ige_op_s {
     // batched-apply workspaces (r columns, column index innermost)
     int bcap = 0;
     ige::DBuf<double2> d_bnpart;       // near-field partial results [nslots][rb]
+    ige::DBuf<double2> d_bnpart_r;     // near-field partial results [nslots][r] (matrix-core product)
     ige::DBuf<double2> d_bmom, d_bsrc, d_bpart, d_bloc, d_bybuf, d_bxt, d_byt, d_bx, d_by;
     // GMRES workspace
     ige::DBuf<double2> d_V, d_w, d_r, d_X, d_F, d_D;
