@@ -51,14 +51,22 @@ def parse():
     ap.add_argument("--store-coupling", type=int, default=-1, choices=(-1, 0, 1),
                     help="coupling blocks: 1 stored, 0 evaluated per apply, -1 stored if they fit")
     ap.add_argument("--verbose", action="store_true")
-    ap.add_argument("--mode", choices=("matvec", "serve"), default="matvec")
+    ap.add_argument("--mode", choices=("matvec", "serve", "solve"), default="matvec")
+    ap.add_argument("--p", type=int, default=2, help="solve: spline degree")
+    ap.add_argument("--kappa", type=float, default=8.0, help="solve: wavenumber")
+    ap.add_argument("--q", type=int, default=8, help="solve: interpolation degree")
+    ap.add_argument("--tol", type=float, default=1e-6, help="solve: relative residual")
+    ap.add_argument("--restart", type=int, default=1500, help="solve: GMRES restart")
+    ap.add_argument("--inner-prec", type=int, default=3, help="solve: coupling precision of refined inner solves")
+    ap.add_argument("--compare-fp64", action="store_true", help="solve: also solve in FP64 and report the difference")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (calibrates HBM byte counters)")
     ap.add_argument("--requests", type=int, default=32, help="serve: number of requests")
     ap.add_argument("--rate", type=float, default=20.0, help="serve: mean arrivals per second")
     ap.add_argument("--workers", type=int, default=4, help="serve: concurrent requests (one stream each)")
     ap.add_argument("--maxit", type=int, default=3000, help="serve: GMRES iteration cap per request")
-    ap.add_argument("--refine", action="store_true", help="serve: FP64 refinement around FP32-coupling solves")
+    ap.add_argument("--refine", action="store_true",
+                    help="serve / solve: FP64 refinement around solves with the --inner-prec coupling")
     return ap.parse_args()
 
 
@@ -114,6 +122,69 @@ def serve_requests(n, seed):
     return out
 
 
+def run_solve(args):
+    """Solves of plane-wave scattering problems on the cube-sphere (Fibonacci
+    directions, theta polarisation), all right-hand sides at once."""
+    import numpy as np
+    import torch
+
+    from paper_1807_03097_amd import binding as B
+    from paper_1807_03097_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    ctx = B.Context(0)
+    geom = B.Geometry(ctx, W.cube_sphere())
+    t0 = time.perf_counter()
+    op = B.Operator(geom, args.p, args.level, args.kappa, args.q, args.eta, 5, 5, args.leaf_depth)
+    t_asm = time.perf_counter() - t0
+    dirs, pols = W.fibonacci_plane_waves(args.nrhs)
+    F = op.rhs_plane_wave(dirs, pols)
+    log(f"N={op.N} near entries={op.info.near_nnz} far pairs={op.info.far_pairs} assembled in {t_asm:.2f} s")
+    runs = []
+    modes = [("refined" if args.refine else "fp64", args.refine)]
+    if args.compare_fp64 and args.refine:
+        modes.append(("fp64", False))
+    sols = {}
+    for name, refine in modes:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        X, st, rc = op.solve(F, tol=args.tol, restart=args.restart, maxit=args.maxit, refine=refine,
+                             inner_tol=1e-4, inner_prec=args.inner_prec)
+        dt = time.perf_counter() - t1
+        sols[name] = X
+        iters = [s_[0] for s_ in st]
+        log(f"{name}: {dt:.2f} s, rc={rc}, iterations {min(iters)}..{max(iters)}, outer {max(s_[1] for s_ in st)}, "
+            f"max relres {max(s_[2] for s_ in st):.2e}")
+        runs.append({"mode": name, "seconds": dt, "rc": rc, "solves_per_s": args.nrhs / dt,
+                     "iters_max": max(iters), "iters_mean": float(np.mean(iters)),
+                     "outer_max": max(s_[1] for s_ in st), "relres_max": max(s_[2] for s_ in st)})
+    diff = None
+    if "refined" in sols and "fp64" in sols:
+        diff = max(float(np.linalg.norm(sols["refined"][c] - sols["fp64"][c]) / np.linalg.norm(sols["fp64"][c]))
+                   for c in range(args.nrhs))
+        log(f"refined vs FP64 solutions: max relative difference {diff:.2e}")
+    prec_name = ["f64", "f32", "bf16", "split-bf16"][args.inner_prec]
+    out = {
+        "metric": "EFIE solves/s",
+        "value": runs[0]["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "f64" if not args.refine else f"f64 refinement around {prec_name} coupling",
+        "data": "synthetic",
+        "config": {"workload": f"cube-sphere, level {args.level}, p={args.p}, kappa={args.kappa}, q={args.q}, "
+                               f"eta={args.eta}, {args.nrhs} Fibonacci plane waves, GMRES tol {args.tol}, "
+                               f"restart {args.restart}", "n_dof": op.N},
+        "assemble_s": t_asm,
+        "runs": runs,
+        "refined_vs_fp64_max_rel_diff": diff,
+    }
+    print(json.dumps(out), flush=True)
+    op.close()
+    geom.close()
+    ctx.close()
+
+
 def run_serving(args):
     import numpy as np
     import torch
@@ -140,7 +211,7 @@ def run_serving(args):
         arrival.append(time.perf_counter() - t0)
         tickets.append(srv.submit(geoms[k], rq["p"], rq["m"], rq["kappa"], rq["dir"], rq["pol"], q=8, eta=args.eta,
                                   tol=1e-6, restart=1500, maxit=args.maxit, refine=args.refine,
-                                  inner_tol=1e-4, inner_prec=B.IGE_F32))
+                                  inner_tol=1e-4, inner_prec=args.inner_prec))
     stats = []
     for k, t in enumerate(tickets):
         stats.append(srv.wait(t))
@@ -161,7 +232,7 @@ def run_serving(args):
         "unit": "solves/s",
         "n_gpus": 1,
         "higher_is_better": True,
-        "dtype": "f64" if not args.refine else "f64+f32-coupling",
+        "dtype": "f64" if not args.refine else ["f64", "f32", "bf16", "split-bf16"][args.inner_prec] + " coupling + f64 refinement",
         "data": "synthetic",
         "p50_latency_s": float(np.percentile(lat, 50)),
         "p99_latency_s": float(np.percentile(lat, 99)),
@@ -191,6 +262,9 @@ def main():
         sys.exit(2)
     if args.mode == "serve":
         run_serving(args)
+        return
+    if args.mode == "solve":
+        run_solve(args)
         return
     import numpy as np
     import torch

@@ -198,7 +198,8 @@ typedef struct {
     int maxit;       /* total iteration cap (inner iterations summed over refinement steps) */
     int refine;      /* 0: GMRES on the FP64 operator; 1: iterative refinement -- FP64
                         residual f - A x, inner GMRES on the inner_prec operator for the
-                        correction to inner_tol, x += correction, repeated */
+                        correction, x += correction, repeated; each inner solve reduces
+                        its residual by max(inner_tol, tol / (2 * current relres)) */
     double inner_tol;
     int inner_prec;  /* coupling precision of the inner solves (IGE_F64 .. IGE_BF16X3) */
 } ige_solve_opts;

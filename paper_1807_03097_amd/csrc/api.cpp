@@ -771,7 +771,8 @@ struct GmresOut {
 // precision prec, starting from X (device, [r][N], updated in place); each column
 // stops when its residual estimate reaches tol * ||B_c||.  it_cap: per-column
 // iteration budget.
-void gmres_batched(ige_op op, int r, const double2 *B, double2 *X, double tol, int m, const std::vector<int> &it_cap,
+void gmres_batched(ige_op op, int r, const double2 *B, double2 *X, const std::vector<double> &tol, int m,
+                   const std::vector<int> &it_cap,
                    int prec, GmresOut &out)
 {
     const int64_t N = op->D.N;
@@ -811,7 +812,7 @@ void gmres_batched(ige_op op, int r, const double2 *B, double2 *X, double tol, i
         int nact = 0;
         for (int c = 0; c < r; ++c) {
             out.relres_est[c] = bnorm[c] > 0 ? beta[c] / bnorm[c] : 0.0;
-            act[c] = bnorm[c] > 0 && out.relres_est[c] > tol && out.iters[c] < it_cap[c];
+            act[c] = bnorm[c] > 0 && out.relres_est[c] > tol[c] && out.iters[c] < it_cap[c];
             nact += act[c];
         }
         if (nact == 0) return;
@@ -859,7 +860,7 @@ void gmres_batched(ige_op op, int r, const double2 *B, double2 *X, double tol, i
                 out.iters[c]++;
                 jdone[c] = jj + 1;
                 out.relres_est[c] = std::abs(g[c][jj + 1]) / bnorm[c];
-                if (out.relres_est[c] <= tol || out.iters[c] >= it_cap[c] || hn[c] == 0.0) run[c] = 0;
+                if (out.relres_est[c] <= tol[c] || out.iters[c] >= it_cap[c] || hn[c] == 0.0) run[c] = 0;
                 nrun += run[c];
             }
             if (nrun == 0) break;
@@ -920,7 +921,8 @@ int ige_solve(ige_op op, int r, const ige_c64 *f, ige_c64 *x, int ptr_kind, cons
         std::vector<double> relres(r, 0.0);
         GmresOut go;
         if (!opts->refine) {
-            gmres_batched(op, r, F, X, opts->tol, opts->restart, std::vector<int>(r, opts->maxit), IGE_F64, go);
+            gmres_batched(op, r, F, X, std::vector<double>(r, opts->tol), opts->restart, std::vector<int>(r, opts->maxit),
+                          IGE_F64, go);
             iters = go.iters;
         } else {
             // iterative refinement: FP64 residual, low-precision inner correction
@@ -940,16 +942,21 @@ int ige_solve(ige_op op, int r, const ige_c64 *f, ige_c64 *x, int ptr_kind, cons
                 IGE_HIP(hipStreamSynchronize(s));
                 bool any = false;
                 std::vector<int> cap(r);
+                std::vector<double> itol(r);
                 for (int c = 0; c < r; ++c) {
                     relres[c] = fn[c] > 0 ? rn[c] / fn[c] : 0.0;
                     const bool need = relres[c] > opts->tol && iters[c] < opts->maxit;
                     cap[c] = need ? opts->maxit - iters[c] : 0;
+                    // the correction needs to reduce this residual only by tol / relres
+                    // (with a margin of 1/2), and never by more than inner_tol
+                    itol[c] = relres[c] > 0 ? std::max(opts->inner_tol, 0.5 * opts->tol / relres[c]) : opts->inner_tol;
+                    itol[c] = std::min(itol[c], 0.5);
                     any = any || need;
                 }
                 if (!any) break;
                 IGE_HIP(hipMemsetAsync(op->d_D.p, 0, sizeof(double2) * r * N, s));
                 // columns already converged get an inner budget of 0 and a zero correction
-                gmres_batched(op, r, op->d_r.p, op->d_D.p, opts->inner_tol, opts->restart, cap, opts->inner_prec, go);
+                gmres_batched(op, r, op->d_r.p, op->d_D.p, itol, opts->restart, cap, opts->inner_prec, go);
                 ige::launch_axpby(op, (int64_t)r * N, make_double2(1, 0), op->d_D.p, make_double2(1, 0), X);
                 for (int c = 0; c < r; ++c) {
                     iters[c] += go.iters[c];
