@@ -60,6 +60,8 @@ typedef struct {
     int pu, pv, nu, nv;
     const double *ku, *kv;     /* knot vectors (copied) */
     const double *ctrl;        /* [nv][nu][4] (x,y,z,w) */
+    int exact;                 /* 1: exact sphere map b(u,v)/|b(u,v)| instead of the NURBS */
+    double V[4][3];            /* b = bilinear interpolation of these cube vertices (corners 00, 10, 01, 11) */
 } patch_t;
 
 typedef struct {
@@ -219,6 +221,26 @@ int or_bspline_eval(int p, const double *knots, int nk, int npts, const double *
 /* ------------------------------------------------------------------------- */
 static void patch_eval(const patch_t *pt, double u, double v, double F[3], double Fu[3], double Fv[3])
 {
+    if (pt->exact) {
+        /* radial projection of the bilinear cube face onto the unit sphere:
+         * F = b / |b|, dF = (db - F (F . db)) / |b| */
+        double b[3], bu_[3], bv_[3];
+        for (int k = 0; k < 3; ++k) {
+            b[k] = (1 - u) * (1 - v) * pt->V[0][k] + u * (1 - v) * pt->V[1][k] + (1 - u) * v * pt->V[2][k] +
+                   u * v * pt->V[3][k];
+            bu_[k] = -(1 - v) * pt->V[0][k] + (1 - v) * pt->V[1][k] - v * pt->V[2][k] + v * pt->V[3][k];
+            bv_[k] = -(1 - u) * pt->V[0][k] - u * pt->V[1][k] + (1 - u) * pt->V[2][k] + u * pt->V[3][k];
+        }
+        const double nb = sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+        for (int k = 0; k < 3; ++k) F[k] = b[k] / nb;
+        const double fu = F[0] * bu_[0] + F[1] * bu_[1] + F[2] * bu_[2];
+        const double fv = F[0] * bv_[0] + F[1] * bv_[1] + F[2] * bv_[2];
+        for (int k = 0; k < 3; ++k) {
+            if (Fu) Fu[k] = (bu_[k] - F[k] * fu) / nb;
+            if (Fv) Fv[k] = (bv_[k] - F[k] * fv) / nb;
+        }
+        return;
+    }
     double bu[512], du[512], bv[512], dv[512];
     bspline_all(pt->pu, pt->ku, pt->nu + pt->pu + 1, u, bu, du);
     bspline_all(pt->pv, pt->kv, pt->nv + pt->pv + 1, v, bv, dv);
@@ -309,6 +331,28 @@ void or_destroy(void *h)
     ctx_t *c = (ctx_t *)h;
     if (!c) return;
     free(c->store); free(c->pat); free(c->dof); free(c->sgn); free(c->kd); free(c->kd1); free(c);
+}
+
+/* Replace every patch map by the exact unit sphere: each patch's corners (from its
+ * NURBS map, on the unit sphere) are scaled onto the circumscribed cube, and the
+ * bilinear face through them is projected radially.  For the six-patch cube-sphere
+ * this is the analytic cube-sphere map, with the same corners and orientation. */
+int or_set_exact_sphere(void *h)
+{
+    ctx_t *c = (ctx_t *)h;
+    if (!c) return -1;
+    static const double cu[4][2] = {{0, 0}, {1, 0}, {0, 1}, {1, 1}};
+    for (int j = 0; j < c->P; ++j) {
+        patch_t *pt = &c->pat[j];
+        for (int k = 0; k < 4; ++k) {
+            double F[3];
+            patch_eval(pt, cu[k][0], cu[k][1], F, NULL, NULL);
+            const double a = fmax(fabs(F[0]), fmax(fabs(F[1]), fabs(F[2])));
+            for (int d = 0; d < 3; ++d) pt->V[k][d] = F[d] / a;
+        }
+        pt->exact = 1;
+    }
+    return 0;
 }
 
 int or_geom_eval(void *h, int j, int npts, const double *uv, double *out /* [npts][9] F,Fu,Fv */)

@@ -61,6 +61,7 @@ def lib():
             "or_gauss_legendre": [C.c_int, P, P],
             "or_bspline_eval": [C.c_int, P, C.c_int, C.c_int, P, P, P],
             "or_geom_eval": [P, C.c_int, C.c_int, P, P],
+            "or_set_exact_sphere": [P],
             "or_element_pair": [P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, P],
             "or_dense_matrix": [P, P],
             "or_dense_apply": [P, P, P, P],
@@ -129,7 +130,7 @@ class Oracle:
     kernel for a polynomial test kernel (used to pin the far-field algebra)."""
 
     def __init__(self, patches, p: int, m: int, kappa: float, g: int = 5, gs: int | None = None,
-                 kernel: int = 0):
+                 kernel: int = 0, exact_sphere: bool = False):
         from paper_1807_03097_amd import workloads  # seeded input packing only
         self.patches = patches
         self.P = len(patches)
@@ -148,12 +149,16 @@ class Oracle:
                             _p(dummy), _p(dsg), self.kappa, self.g, self.gs, self.kernel)
         if not h:
             raise ValueError("invalid oracle parameters")
+        if exact_sphere:   # analytic cube-sphere map (cube-sphere patches only)
+            lib().or_set_exact_sphere(h)
         self._h = h
         self.dof, self.sgn, self.N = self._build_dofs()
         lib().or_destroy(self._h)
         self._h = lib().or_create(self.P, _p(deg), _p(nctrl), _p(knots), _p(ctrl), self.p, self.m, self.N,
                                   _p(self.dof.ravel()), _p(self.sgn.ravel()), self.kappa, self.g, self.gs,
                                   self.kernel)
+        if exact_sphere:
+            lib().or_set_exact_sphere(self._h)
 
     def __del__(self):
         try:

@@ -443,3 +443,85 @@ def test_fmm_operator_is_symmetric(oracle_mod):
     a = z @ o.fmm_apply(x, 6, 1.0, 1, tree=tr)
     b = x @ o.fmm_apply(z, 6, 1.0, 1, tree=tr)
     assert abs(a - b) <= 1e-13 * abs(a)
+
+
+# ---------------------------------------------------------------------------
+# Mie series (perfectly conducting sphere): the closed-form scattering reference
+# ---------------------------------------------------------------------------
+def test_mie_series_is_a_pec_solution():
+    """The series reproduces the incident plane wave (E = x^ e^{i k z}, H = y^ e^{i k z})
+    at points inside and outside the sphere, satisfies n x E_tot = 0 and n . H_tot = 0
+    on the sphere, and obeys the optical theorem (extinction = scattering, lossless)."""
+    from oracle import mie
+    rng = np.random.default_rng(1)
+    pts = rng.standard_normal((60, 3))
+    pts /= np.linalg.norm(pts, axis=1, keepdims=True)
+    on = pts.copy()
+    pts *= rng.uniform(0.3, 3.0, (60, 1))
+    for k in (1.0, 3.0, 8.0):
+        ex = np.zeros((60, 3), complex)
+        ex[:, 0] = np.exp(1j * k * pts[:, 2])
+        hy = np.zeros((60, 3), complex)
+        hy[:, 1] = np.exp(1j * k * pts[:, 2])
+        assert np.abs(mie.fields(pts, k, "E_inc") - ex).max() < 1e-10
+        assert np.abs(mie.fields(pts, k, "H_inc") - hy).max() < 1e-10
+        Et = mie.fields(on, k, "E_inc") + mie.fields(on, k, "E_s")
+        Ht = mie.fields(on, k, "H_inc") + mie.fields(on, k, "H_s")
+        assert np.abs(np.cross(on, Et)).max() < 1e-12
+        assert np.abs(np.sum(on * Ht, 1)).max() < 1e-12
+        qe, qs = mie.efficiencies(k)
+        assert abs(qe - qs) < 1e-12 * qe
+
+
+def test_exact_sphere_geometry(oracle_mod):
+    """The oracle's analytic cube-sphere: points on the unit sphere, tangents
+    orthogonal to the normal, same corners as the NURBS patches."""
+    ob = oracle_mod.Oracle(W.cube_sphere(), 1, 1, 1.0)
+    oe = oracle_mod.Oracle(W.cube_sphere(), 1, 1, 1.0, exact_sphere=True)
+    uv = np.random.default_rng(2).uniform(0, 1, (40, 2))
+    for j in range(6):
+        G = oe.geom(j, uv)
+        F = G[:, 0:3]
+        assert np.abs(np.linalg.norm(F, axis=1) - 1).max() < 1e-14
+        assert np.abs(np.sum(F * G[:, 3:6], 1)).max() < 1e-14
+        assert np.abs(np.sum(F * G[:, 6:9], 1)).max() < 1e-14
+        c = [[0, 0], [1, 0], [0, 1], [1, 1]]
+        assert np.abs(oe.geom(j, c)[:, 0:3] - ob.geom(j, c)[:, 0:3]).max() < 1e-14
+    assert oe.N == ob.N
+
+
+def _mie_l2_error(o, w, kappa, gq=6):
+    from oracle import mie
+    x, wt = np.polynomial.legendre.leggauss(gq)
+    x, wt = (x + 1) / 2, wt / 2
+    n, h = o.n, 1.0 / o.n
+    num = den = 0.0
+    for j in range(o.P):
+        e1, e2, a, b = np.meshgrid(np.arange(n), np.arange(n), np.arange(gq), np.arange(gq), indexing="ij")
+        uv = np.stack([(e1 + x[a]) * h, (e2 + x[b]) * h], -1).reshape(-1, 2)
+        ww = (wt[a] * wt[b]).ravel() * h * h
+        G = o.geom(j, uv)
+        F, Fu, Fv = G[:, 0:3], G[:, 3:6], G[:, 6:9]
+        jac = np.linalg.norm(np.cross(Fu, Fv), axis=1)
+        ph = o.field_param(w, j, uv)
+        wh = (ph[:, 0:1] * Fu + ph[:, 1:2] * Fv) / jac[:, None]   # Piola push-forward
+        wm = mie.density(F, kappa)
+        num += np.sum(ww * jac * np.sum(np.abs(wh - wm) ** 2, 1))
+        den += np.sum(ww * jac * np.sum(np.abs(wm) ** 2, 1))
+    return np.sqrt(num / den)
+
+
+@pytest.mark.parametrize("p, lo, hi", [(1, 1.8, 2.4), (2, 3.4, 6.0)])
+def test_mie_density_converges_at_rate_p(oracle_mod, p, lo, hi):
+    """Plane wave (x^ polarised, along +z, kappa = 1) on the exact sphere: the relative
+    L2 error of the computed surface density against the Mie series falls by about
+    2^p per refinement (the paper's Mie rows: ratios about 2 for p = 1 and 4-5 for p = 2)."""
+    errs = []
+    for m in (1, 2, 3):
+        o = oracle_mod.Oracle(W.cube_sphere(), p, m, 1.0, g=5, gs=5, exact_sphere=True)
+        w = np.linalg.solve(o.dense_matrix(), o.rhs_plane_wave((0, 0, 1), (1, 0, 0)))
+        errs.append(_mie_l2_error(o, w, 1.0))
+    ratios = [errs[i] / errs[i + 1] for i in range(2)]
+    print(f"p={p}: errors {errs}, ratios {ratios}")
+    assert errs[0] < 0.5
+    assert all(lo <= r <= hi for r in ratios)
