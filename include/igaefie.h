@@ -260,6 +260,14 @@ int ige_srv_result(ige_srv srv, int64_t ticket, ige_c64 *x, int64_t n);
 /* Finish every queued and running request, stop the workers, free everything. */
 int ige_srv_destroy(ige_srv srv);
 
+/* Scattered field e_s = V~ w (Sec. 2, eq. (eq:ESLP)) of r densities w [r][N]
+ * (ptr_kind memory) at npts points [npts][3] (host) off the surface:
+ *   e_s(x) = int G(x-y) w(y) + kappa^-2 grad_x int G(x-y) div w(y) dsigma(y),
+ * each element integrated with the g x g Gauss rule of the near field, so points
+ * should stay a few element sizes away from the surface.  E: [r][npts][3] complex,
+ * host memory.  Synchronous; uses temporary device memory (E * g^2 * 88 bytes). */
+int ige_potential(ige_op op, int r, const ige_c64 *w, int ptr_kind, int npts, const double *points, ige_c64 *E);
+
 /* Diagnostic: evaluate on the context's device the Helmholtz kernel
  * G_k(r) = e^{ikr}/(4 pi r) (Sec. 2.2, eq. (eq:HelmholtzGreen)) exactly as the
  * coupling stage does in precision prec (IGE_F64 / IGE_F32), from squared

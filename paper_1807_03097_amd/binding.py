@@ -93,6 +93,7 @@ _SIGS = {
     "ige_rhs_plane_wave": (C.c_int, [_V, C.c_int, _V, _V, _V, C.c_int]),
     "ige_solve": (C.c_int, [_V, C.c_int, _V, _V, C.c_int, C.POINTER(ige_solve_opts), _V]),
     "ige_helmholtz_eval": (C.c_int, [_V, C.c_int64, C.c_double, _V, _V, C.c_int]),
+    "ige_potential": (C.c_int, [_V, C.c_int, _V, C.c_int, C.c_int, _V, _V]),
     "ige_srv_create": (C.c_int, [_V, C.c_int, C.c_size_t, C.POINTER(_V)]),
     "ige_srv_submit": (C.c_int, [_V, _V, C.POINTER(ige_params), _V, _V, C.POINTER(ige_solve_opts),
                                  C.POINTER(C.c_int64)]),
@@ -342,6 +343,14 @@ class Operator:
         opts = ige_solve_opts(tol, restart, maxit, int(refine), inner_tol, inner_prec)
         rc, stats = ige_solve(self.h, r, f, x0, _kind(f), opts)
         return x0, [(s.iters, s.outer, s.relres, s.seconds) for s in stats], rc
+
+    def potential(self, w, points):
+        """scattered field e_s = V~ w at points [npts][3] -> [npts][3] (or [r][npts][3])"""
+        points = np.ascontiguousarray(points, np.float64).reshape(-1, 3)
+        r = 1 if w.ndim == 1 else w.shape[0]
+        out = np.zeros((r, len(points), 3), np.complex128)
+        _check(_lib.ige_potential(self.h, r, _ptr(w), _kind(w), len(points), _ptr(points), _ptr(out)))
+        return out[0] if w.ndim == 1 else out
 
     def set_profiling(self, on=True):
         ige_op_set_profiling(self.h, on)

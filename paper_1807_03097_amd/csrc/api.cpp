@@ -997,6 +997,38 @@ int ige_solve(ige_op op, int r, const ige_c64 *f, ige_c64 *x, int ptr_kind, cons
     return rc;
 }
 
+int ige_potential(ige_op op, int r, const ige_c64 *w, int ptr_kind, int npts, const double *points, ige_c64 *E)
+{
+    return guard([&] {
+        IGE_REQUIRE(op && w && r >= 1 && npts >= 0 && (npts == 0 || (points && E)), "bad potential arguments");
+        IGE_REQUIRE(op->assembled, "operator was planned, not assembled");
+        IGE_REQUIRE(ptr_kind == IGE_HOST || ptr_kind == IGE_DEVICE, "bad ptr_kind");
+        for (int64_t i = 0; i < 3 * (int64_t)npts; ++i) IGE_REQUIRE(std::isfinite(points[i]), "non-finite point");
+        set_device(op->ctx);
+        hipStream_t s = op->ctx->stream;
+        const int64_t N = op->D.N;
+        ige::DBuf<double2> dw, dout;
+        ige::DBuf<double> dpts, dsrc;
+        dsrc.alloc(ige::potential_source_doubles(op));
+        dpts.alloc(std::max<size_t>(1, (size_t)3 * npts));
+        dout.alloc(std::max<size_t>(1, (size_t)3 * npts));
+        if (npts) IGE_HIP(hipMemcpyAsync(dpts.p, points, sizeof(double) * 3 * npts, hipMemcpyHostToDevice, s));
+        const double2 *W = reinterpret_cast<const double2 *>(w);
+        if (ptr_kind == IGE_HOST) {
+            dw.alloc((size_t)r * N);
+            IGE_HIP(hipMemcpyAsync(dw.p, w, sizeof(double2) * r * N, hipMemcpyHostToDevice, s));
+            W = dw.p;
+        }
+        for (int c = 0; c < r; ++c) {
+            ige::launch_potential(op, W + (size_t)c * N, npts, dpts.p, dout.p, dsrc.p);
+            if (npts)
+                IGE_HIP(hipMemcpyAsync(E + (size_t)c * 3 * npts, dout.p, sizeof(double2) * 3 * npts,
+                                       hipMemcpyDeviceToHost, s));
+        }
+        IGE_HIP(hipStreamSynchronize(s));
+    });
+}
+
 int ige_helmholtz_eval(ige_ctx ctx, int64_t n, double kappa, const double *r2, ige_c64 *out, int prec)
 {
     return guard([&] {

@@ -1694,3 +1694,102 @@ void launch_norm2(ige_op op, int64_t n, const double2 *x, double *out)
 }
 
 }  // namespace ige
+
+// ---------------------------------------------------------------------------
+// Scattered field e_s = V~ w at points off the surface (Sec. 2, eq. (eq:ESLP)):
+//   e_s(x) = sum_e sum_q [G(x - y_q) W_q + kappa^-2 grad_x G(x - y_q) D_q],
+// W_q = sum_l w_l Psi_l(q) (weighted phi_hat^a d_aF), D_q = sum_l w_l div_l(q), on the
+// regular g x g Gauss points of every element; grad_x G = (x - y) G (i kappa r - 1) / r^2.
+// ---------------------------------------------------------------------------
+namespace ige {
+namespace {
+
+// per element Gauss point: y (3), W (3 complex), D (complex) -> src[E*G2][kPotStride]
+constexpr int kPotStride = 11;
+
+template <int NL>
+__global__ void k_pot_sources(DevOp o, const double2 *w, double *src)
+{
+    const int64_t e = blockIdx.x;
+    const int G2 = o.G2;
+    int j, e1, e2;
+    elem_of(o, e, j, e1, e2);
+    double2 cf[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+        int idx;
+        double sg;
+        local_dof(o, j, e1, e2, l, idx, sg);
+        cf[l] = idx >= 0 ? cscale(sg, w[idx]) : make_double2(0.0, 0.0);
+    }
+    for (int q = threadIdx.x; q < G2; q += blockDim.x) {
+        double *s = src + ((size_t)e * G2 + q) * kPotStride;
+        for (int d = 0; d < 3; ++d) s[d] = o.eX[((size_t)e * 3 + d) * G2 + q];
+        for (int c = 0; c < 4; ++c) {
+            double2 W = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int l = 0; l < NL; ++l) W = cadd(W, cscale(o.ePsi[(((size_t)e * 4 + c) * NL + l) * G2 + q], cf[l]));
+            s[3 + 2 * c] = W.x;
+            s[4 + 2 * c] = W.y;
+        }
+    }
+}
+
+// one workgroup per target point; threads take every 256th source point, then a
+// fixed tree over the workgroup
+__global__ __launch_bounds__(256) void k_potential(int64_t nsrc, double kappa, const double *src, const double *pts,
+                                                   double2 *out)
+{
+    __shared__ double red[6][256];
+    const int t = blockIdx.x;
+    const double x0 = pts[3 * t], x1 = pts[3 * t + 1], x2 = pts[3 * t + 2];
+    const double ik2 = 1.0 / (kappa * kappa);
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t i = threadIdx.x; i < nsrc; i += blockDim.x) {
+        const double *s = src + i * kPotStride;
+        const double rv[3] = {x0 - s[0], x1 - s[1], x2 - s[2]};
+        const double rr2 = fma(rv[0], rv[0], fma(rv[1], rv[1], rv[2] * rv[2]));
+        const double kr = kappa * sqrt(rr2);
+        const double2 G = dm::helmholtz_r2(kappa, rr2);
+        // grad_x G = (x - y) G (i kappa r - 1) / r^2, times kappa^-2 and D
+        const double2 dG = make_double2((-G.x - kr * G.y) / rr2, (kr * G.x - G.y) / rr2);
+        const double2 dgD = cscale(ik2, cmul(dG, make_double2(s[9], s[10])));
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double2 v = cadd(cmul(G, make_double2(s[3 + 2 * d], s[4 + 2 * d])), cscale(rv[d], dgD));
+            acc[2 * d] += v.x;
+            acc[2 * d + 1] += v.y;
+        }
+    }
+    for (int k = 0; k < 6; ++k) red[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int off = 128; off >= 1; off >>= 1) {
+        if (threadIdx.x < off)
+            for (int k = 0; k < 6; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) out[3 * t + threadIdx.x] = make_double2(red[2 * threadIdx.x][0], red[2 * threadIdx.x + 1][0]);
+}
+
+}  // namespace
+
+size_t potential_source_doubles(ige_op op) { return (size_t)op->view.P * op->view.n * op->view.n * op->view.G2 * kPotStride; }
+
+void launch_potential(ige_op op, const double2 *w, int npts, const double *pts, double2 *out, double *src)
+{
+    const DevOp &o = op->view;
+    const int64_t E = (int64_t)o.P * o.n * o.n;
+    hipStream_t s = op->ctx->stream;
+    switch (o.p) {
+        case 1: hipLaunchKernelGGL(k_pot_sources<4>, dim3((unsigned)E), dim3(64), 0, s, o, w, src); break;
+        case 2: hipLaunchKernelGGL(k_pot_sources<12>, dim3((unsigned)E), dim3(64), 0, s, o, w, src); break;
+        default: hipLaunchKernelGGL(k_pot_sources<24>, dim3((unsigned)E), dim3(64), 0, s, o, w, src); break;
+    }
+    IGE_HIP(hipGetLastError());
+    if (npts > 0) {
+        hipLaunchKernelGGL(k_potential, dim3(npts), dim3(256), 0, s, E * o.G2, o.kappa, src, pts, out);
+        IGE_HIP(hipGetLastError());
+    }
+}
+
+}  // namespace ige

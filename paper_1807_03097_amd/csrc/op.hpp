@@ -189,6 +189,9 @@ void launch_spmv(ige_op op, const double2 *x, double2 *y, hipStream_t st, hipEve
 int near_blk_u(int nF);   // 64-column groups per block row (template choice)
 void launch_l2p_leaf(ige_op op);
 void launch_l2p_gather(ige_op op, double2 *y);
+// scattered field at npts points (device arrays; src: potential_source_doubles scratch)
+size_t potential_source_doubles(ige_op op);
+void launch_potential(ige_op op, const double2 *w, int npts, const double *pts, double2 *out, double *src);
 void launch_rhs_plane(ige_op op, const double *dir, double2 pol0, double2 pol1, double2 pol2, double2 *f);
 // GMRES helpers
 void launch_dotc(ige_op op, const double2 *V, int64_t ldv, int k, const double2 *w, double2 *out);

@@ -288,6 +288,48 @@ def test_bf16_matrix_core_coupling(oracle_mod, ctx, case):
     op.close()
 
 
+@pytest.mark.parametrize("name, p, m, kappa", [("sphere", 2, 3, 8.0), ("torus", 1, 3, 3.0), ("jittered", 2, 2, 5.0)])
+def test_potential_matches_oracle(oracle_mod, ctx, name, p, m, kappa):
+    """Scattered field e_s = V~ w at points off the surface (two columns)."""
+    from paper_1807_03097_amd import binding as B
+    pats = _geom(name)
+    geom = B.Geometry(ctx, pats)
+    op = B.Operator(geom, p, m, kappa, 6, 1.0, 5, 5, 1)
+    o = oracle_mod.Oracle(pats, p, m, kappa, g=5, gs=5)
+    w = np.stack([W.random_coeffs(op.N, 3), W.random_coeffs(op.N, 4)])
+    pts = oracle_mod.fibonacci_sphere(24, 2.5)
+    E = op.potential(w, pts)
+    for c in range(2):
+        Eo = o.potential(w[c], pts)
+        err = _rel(E[c], Eo)
+        _say(f"  {name}: column {c} rel.err {err:.2e}")
+        assert err <= TOL
+    op.close()
+
+
+def test_plane_wave_scattering_against_mie(ctx):
+    """End to end on the device: solve the plane-wave problem on the NURBS sphere and
+    evaluate the scattered field at radius 3 against the Mie series.  The NURBS sphere
+    deviates radially by up to 0.02 from the unit sphere, which bounds the agreement."""
+    from paper_1807_03097_amd import binding as B
+    from oracle import mie
+    geom = B.Geometry(ctx, W.cube_sphere())
+    kappa = 1.0
+    op = B.Operator(geom, 2, 3, kappa, 8, 1.6, 5, 5, 1)
+    f = op.rhs_plane_wave(np.array([0.0, 0.0, 1.0]), np.array([1.0, 0.0, 0.0], complex))[0]
+    x, st, rc = op.solve(f, tol=1e-10, restart=300, maxit=3000)
+    assert rc == 0
+    rng = np.random.default_rng(5)
+    pts = rng.standard_normal((40, 3))
+    pts = 3.0 * pts / np.linalg.norm(pts, axis=1, keepdims=True)
+    E = op.potential(x, pts)
+    Em = mie.fields(pts, kappa, "E_s")
+    err = np.linalg.norm(E - Em) / np.linalg.norm(Em)
+    _say(f"  scattered field vs Mie at r=3: rel.err {err:.2e} ({st[0][0]} iterations)")
+    assert err <= 0.05
+    op.close()
+
+
 def test_c2_full_size_sampled_rows(oracle_mod, ctx):
     """Matvec configuration: sphere, level 5, p = 2, kappa = 8, q = 8, 5x5 Gauss, x seed 0,
     as timed by the benchmark; rows sampled evenly, computed one by one by the oracle."""
