@@ -263,6 +263,8 @@ size_t ige::planned_device_bytes(const ige_op_s *op, int restart)
     b += (size_t)op->T.far.size() * 4 * Q * 16 / 4;              // coupling partials (chunks of partners)
     b += (size_t)op->nsing * 24 + (size_t)D.N * 80;
     b += ((size_t)restart + 1 + 8) * D.N * 16;                   // Krylov basis and work vectors
+    const ige::GsPlan gp = ige::gs_plan(D.N, 1, restart);
+    b += (ige::gs_part_count(gp, 1, restart) + ige::gs_split_count(gp, D.N, 1)) * 16;   // Gram-Schmidt scratch
     return b;
 }
 
@@ -781,9 +783,25 @@ void gmres_batched(ige_op op, int r, const double2 *B, double2 *X, const std::ve
     if (op->d_V.n < need) op->d_V.alloc(need);
     if (op->d_w.n < (size_t)r * N) op->d_w.alloc((size_t)r * N);
     const int hs = m + 2;
-    if (op->d_h.n < (size_t)r * hs) op->d_h.alloc((size_t)r * hs);
-    if (op->d_red.n < (size_t)r) op->d_red.alloc(r);
-    if (op->d_scal.n < (size_t)r) op->d_scal.alloc(r);
+    const ige::GsPlan gp = ige::gs_plan(N, r, m);
+    auto grow = [](auto &buf, size_t n) {
+        if (buf.n < n) buf.alloc(n);
+    };
+    grow(op->d_h, (size_t)2 * r * hs);
+    grow(op->d_red, (size_t)r);
+    grow(op->d_scal, (size_t)r);
+    grow(op->d_gspart, ige::gs_part_count(gp, r, m));
+    grow(op->d_gsplit, std::max<size_t>(1, ige::gs_split_count(gp, N, r)));
+    grow(op->d_hpack, (size_t)r * (m + 1));
+    grow(op->d_gnp, (size_t)r * gp.nblk);
+    grow(op->d_gn, (size_t)2 * r);
+    grow(op->d_grun, (size_t)r);
+    grow(op->d_gflag, (size_t)r);
+    grow(op->d_gact, (size_t)r);
+    op->h_hpack.ensure((size_t)r * (m + 1));
+    double2 *split = ige::gs_split_count(gp, N, r) ? op->d_gsplit.p : nullptr;
+    double2 *h1 = op->d_h.p, *h2 = op->d_h.p + (size_t)r * hs;
+    double *nb = op->d_gn.p, *nf = op->d_gn.p + r;
     double2 *V = op->d_V.p, *W = op->d_w.p;
     auto norms = [&](const double2 *v) {
         std::vector<double> h(r);
@@ -796,12 +814,16 @@ void gmres_batched(ige_op op, int r, const double2 *B, double2 *X, const std::ve
         IGE_HIP(hipMemcpyAsync(op->d_scal.p, sc.data(), sizeof(double) * r, hipMemcpyHostToDevice, s));
         ige::launch_scale_cols(op, r, op->d_scal.p, x, y);
     };
+    auto upload_mask = [&](const std::vector<char> &mk, int *dst) {
+        std::vector<int> v(mk.begin(), mk.end());
+        IGE_HIP(hipMemcpyAsync(dst, v.data(), sizeof(int) * r, hipMemcpyHostToDevice, s));
+        IGE_HIP(hipStreamSynchronize(s));   // v leaves scope
+    };
     const std::vector<double> bnorm = norms(B);
     out.iters.assign(r, 0);
     out.relres_est.assign(r, 0.0);
     std::vector<std::vector<Cx>> H(r, std::vector<Cx>((size_t)(m + 1) * m)), cs(r, std::vector<Cx>(m)),
         sn(r, std::vector<Cx>(m)), g(r, std::vector<Cx>(m + 1));
-    std::vector<double2> hbuf((size_t)r * hs);
     while (true) {
         // V0 = B - A X
         apply_dev(op, r, X, W, prec);
@@ -825,26 +847,32 @@ void gmres_batched(ige_op op, int r, const double2 *B, double2 *X, const std::ve
             g[c][0] = beta[c];
         }
         std::vector<char> run = act;
+        upload_mask(run, op->d_grun.p);
         for (int jj = 0; jj < m; ++jj) {
             double2 *Vj = V + (size_t)jj * r * N, *Vj1 = V + (size_t)(jj + 1) * r * N;
             apply_dev(op, r, Vj, Vj1, prec);
-            std::vector<std::vector<Cx>> hcol(r, std::vector<Cx>(jj + 2, Cx(0)));
-            for (int pass = 0; pass < 2; ++pass) {
-                ige::launch_dotc_b(op, r, V, jj + 1, Vj1, op->d_h.p, hs);
-                ige::launch_gemv_sub_b(op, r, V, jj + 1, op->d_h.p, hs, Vj1);
-                IGE_HIP(hipMemcpyAsync(hbuf.data(), op->d_h.p, sizeof(double2) * r * hs, hipMemcpyDeviceToHost, s));
-                IGE_HIP(hipStreamSynchronize(s));
-                for (int c = 0; c < r; ++c)
-                    for (int i = 0; i <= jj; ++i) hcol[c][i] += cz(hbuf[(size_t)c * hs + i]);
-            }
-            const std::vector<double> hn = norms(Vj1);
-            for (int c = 0; c < r; ++c) sc[c] = (run[c] && hn[c] > 0) ? 1.0 / hn[c] : 0.0;
-            scale(sc, Vj1, Vj1);
+            // Gram-Schmidt pass 1 on the running columns, pass 2 where it lost more than half
+            ige::launch_gs_dots(s, gp, N, r, V, jj + 1, Vj1, op->d_grun.p, op->d_gspart.p, h1, hs, nb);
+            ige::launch_gs_update(s, gp, N, r, V, jj + 1, h1, hs, -1.0, op->d_grun.p, Vj1, split, op->d_gnp.p);
+            ige::launch_gs_norm(s, gp, r, op->d_gnp.p, op->d_grun.p, op->d_grun.p, nb, nf, op->d_scal.p,
+                                op->d_gflag.p);
+            ige::launch_gs_dots(s, gp, N, r, V, jj + 1, Vj1, op->d_gflag.p, op->d_gspart.p, h2, hs, nullptr);
+            ige::launch_gs_update(s, gp, N, r, V, jj + 1, h2, hs, -1.0, op->d_gflag.p, Vj1, split, op->d_gnp.p);
+            ige::launch_gs_norm(s, gp, r, op->d_gnp.p, op->d_gflag.p, op->d_grun.p, nullptr, nf, op->d_scal.p,
+                                nullptr);
+            ige::launch_scale_cols(op, r, op->d_scal.p, Vj1, Vj1);
+            ige::launch_gs_pack(s, r, jj + 1, h1, h2, hs, nf, op->d_hpack.p);
+            const double2 *hp = op->h_hpack.p;
+            IGE_HIP(hipMemcpyAsync(op->h_hpack.p, op->d_hpack.p, sizeof(double2) * r * (jj + 2), hipMemcpyDeviceToHost,
+                                   s));
+            IGE_HIP(hipStreamSynchronize(s));
             int nrun = 0;
+            bool changed = false;
+            std::vector<Cx> hc(jj + 2);
             for (int c = 0; c < r; ++c) {
                 if (!run[c]) continue;
-                auto &hc = hcol[c];
-                hc[jj + 1] = hn[c];
+                for (int i = 0; i <= jj + 1; ++i) hc[i] = cz(hp[(size_t)c * (jj + 2) + i]);
+                const double hn = hc[jj + 1].real();
                 for (int i = 0; i < jj; ++i) {   // rotations [[conj c, conj s], [-s, c]]
                     const Cx t = std::conj(cs[c][i]) * hc[i] + std::conj(sn[c][i]) * hc[i + 1];
                     hc[i + 1] = -sn[c][i] * hc[i] + cs[c][i] * hc[i + 1];
@@ -860,10 +888,14 @@ void gmres_batched(ige_op op, int r, const double2 *B, double2 *X, const std::ve
                 out.iters[c]++;
                 jdone[c] = jj + 1;
                 out.relres_est[c] = std::abs(g[c][jj + 1]) / bnorm[c];
-                if (out.relres_est[c] <= tol[c] || out.iters[c] >= it_cap[c] || hn[c] == 0.0) run[c] = 0;
+                if (out.relres_est[c] <= tol[c] || out.iters[c] >= it_cap[c] || hn == 0.0) {
+                    run[c] = 0;
+                    changed = true;
+                }
                 nrun += run[c];
             }
             if (nrun == 0) break;
+            if (changed) upload_mask(run, op->d_grun.p);
         }
         // X_c += V_c y_c with y_c = H_c^-1 g_c (upper triangular)
         int kmax = 0;
@@ -877,10 +909,13 @@ void gmres_batched(ige_op op, int r, const double2 *B, double2 *X, const std::ve
                 for (int t = i + 1; t < k; ++t) acc -= H[c][(size_t)i * m + t] * yv[t];
                 yv[i] = acc / H[c][(size_t)i * m + i];
             }
-            for (int i = 0; i < k; ++i) ny[(size_t)c * hs + i] = c2(-yv[i]);
+            for (int i = 0; i < k; ++i) ny[(size_t)c * hs + i] = c2(yv[i]);
         }
         IGE_HIP(hipMemcpyAsync(op->d_h.p, ny.data(), sizeof(double2) * r * hs, hipMemcpyHostToDevice, s));
-        ige::launch_gemv_sub_b(op, r, V, kmax, op->d_h.p, hs, X);
+        std::vector<char> upd(r);
+        for (int c = 0; c < r; ++c) upd[c] = jdone[c] > 0;
+        upload_mask(upd, op->d_gact.p);
+        if (kmax > 0) ige::launch_gs_update(s, gp, N, r, V, kmax, op->d_h.p, hs, 1.0, op->d_gact.p, X, split, nullptr);
     }
 }
 }  // namespace

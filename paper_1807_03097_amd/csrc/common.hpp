@@ -148,4 +148,31 @@ struct DBuf {
     DBuf &operator=(const DBuf &) = delete;
 };
 
+// pinned host buffer (for small device-to-host transfers inside iterations)
+template <typename T>
+struct HBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    void ensure(size_t count)
+    {
+        if (count <= n) return;
+        release();
+        if (hipHostMalloc((void **)&p, sizeof(T) * count, hipHostMallocDefault) != hipSuccess) {
+            p = nullptr;
+            throw Status{IGE_ENOMEM, "hipHostMalloc of " + std::to_string(sizeof(T) * count) + " bytes failed"};
+        }
+        n = count;
+    }
+    void release()
+    {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    ~HBuf() { release(); }
+    HBuf() = default;
+    HBuf(const HBuf &) = delete;
+    HBuf &operator=(const HBuf &) = delete;
+};
+
 }  // namespace ige

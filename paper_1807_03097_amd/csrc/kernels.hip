@@ -1275,82 +1275,6 @@ __global__ void k_rhs_plane(DevOp o, double d0, double d1, double d2, double2 p0
     f[i] = acc;
 }
 
-// ---------------------------------------------------------------------------
-// a10: GMRES vector kernels (deterministic reductions)
-// ---------------------------------------------------------------------------
-constexpr int kRedThreads = 256;
-
-__device__ inline double2 block_reduce2(double2 v, double2 *sh)
-{
-    for (int off = kWave / 2; off >= 1; off >>= 1) {
-        v.x += __shfl_xor(v.x, off, kWave);
-        v.y += __shfl_xor(v.y, off, kWave);
-    }
-    const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    if (lane == 0) sh[w] = v;
-    __syncthreads();
-    double2 r = make_double2(0, 0);
-    if (threadIdx.x == 0)
-        for (int i = 0; i < (int)(blockDim.x / kWave); ++i) r = cadd(r, sh[i]);
-    return r;
-}
-
-// out[k] = sum_i conj(V_k[i]) w[i], one block per k
-__global__ __launch_bounds__(kRedThreads) void k_dotc(int64_t n, const double2 *V, int64_t ldv, const double2 *w,
-                                                       double2 *out)
-{
-    __shared__ double2 sh[kRedThreads / kWave];
-    const double2 *v = V + (size_t)blockIdx.x * ldv;
-    double2 acc = make_double2(0, 0);
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-        const double2 a = v[i], b = w[i];
-        acc.x += a.x * b.x + a.y * b.y;
-        acc.y += a.x * b.y - a.y * b.x;
-    }
-    const double2 r = block_reduce2(acc, sh);
-    if (threadIdx.x == 0) out[blockIdx.x] = r;
-}
-
-// w[i] -= sum_k V_k[i] h[k]
-__global__ void k_gemv_sub(int64_t n, const double2 *V, int64_t ldv, int k, const double2 *hc, double2 *w)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double2 acc = w[i];
-    for (int c = 0; c < k; ++c) {
-        const double2 v = V[(size_t)c * ldv + i], hh = hc[c];
-        acc.x -= v.x * hh.x - v.y * hh.y;
-        acc.y -= v.x * hh.y + v.y * hh.x;
-    }
-    w[i] = acc;
-}
-
-__global__ void k_axpby(int64_t n, double2 a, const double2 *x, double2 b, double2 *y)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    y[i] = cadd(cmul(a, x[i]), cmul(b, y[i]));
-}
-
-__global__ void k_scale_copy(int64_t n, double2 a, const double2 *x, double2 *y)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    y[i] = cmul(a, x[i]);
-}
-
-__global__ __launch_bounds__(kRedThreads) void k_norm2(int64_t n, const double2 *x, double *out)
-{
-    __shared__ double2 sh[kRedThreads / kWave];
-    double2 acc = make_double2(0, 0);
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-        const double2 a = x[i];
-        acc.x += a.x * a.x + a.y * a.y;
-    }
-    const double2 r = block_reduce2(acc, sh);
-    if (threadIdx.x == 0) out[0] = sqrt(r.x);
-}
-
 __global__ void k_helmholtz_eval(int64_t n, double kappa, const double *r2, double2 *out, int prec)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1359,92 +1283,7 @@ __global__ void k_helmholtz_eval(int64_t n, double kappa, const double *r2, doub
     else out[i] = dm::helmholtz_r2(kappa, r2[i]);
 }
 
-// ---- batched GMRES vector kernels: V is [k][r][N] (basis index, column, entry),
-// W and X are [r][N]; per-column coefficients h are [r][hs]
-__global__ __launch_bounds__(kRedThreads) void k_dotc_b(int64_t n, int r, const double2 *V, const double2 *w,
-                                                         double2 *out, int hs)
-{
-    __shared__ double2 sh[kRedThreads / kWave];
-    const int kk = blockIdx.x, c = blockIdx.y;
-    const double2 *v = V + ((size_t)kk * r + c) * n;
-    const double2 *wc = w + (size_t)c * n;
-    double2 acc = make_double2(0, 0);
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-        const double2 a = v[i], b = wc[i];
-        acc.x += a.x * b.x + a.y * b.y;
-        acc.y += a.x * b.y - a.y * b.x;
-    }
-    const double2 res = block_reduce2(acc, sh);
-    if (threadIdx.x == 0) out[(size_t)c * hs + kk] = res;
-}
-
-// w_c -= sum_{kk < k} V[kk][c] h[c][kk]
-__global__ void k_gemv_sub_b(int64_t n, int r, const double2 *V, int k, const double2 *hc, int hs, double2 *w)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int c = blockIdx.y;
-    if (i >= n) return;
-    double2 acc = w[(size_t)c * n + i];
-    for (int kk = 0; kk < k; ++kk) {
-        const double2 v = V[((size_t)kk * r + c) * n + i], hh = hc[(size_t)c * hs + kk];
-        acc.x -= v.x * hh.x - v.y * hh.y;
-        acc.y -= v.x * hh.y + v.y * hh.x;
-    }
-    w[(size_t)c * n + i] = acc;
-}
-
-__global__ __launch_bounds__(kRedThreads) void k_norm2_b(int64_t n, const double2 *x, double *out)
-{
-    __shared__ double2 sh[kRedThreads / kWave];
-    const double2 *xc = x + (size_t)blockIdx.x * n;
-    double2 acc = make_double2(0, 0);
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-        const double2 a = xc[i];
-        acc.x += a.x * a.x + a.y * a.y;
-    }
-    const double2 res = block_reduce2(acc, sh);
-    if (threadIdx.x == 0) out[blockIdx.x] = sqrt(res.x);
-}
-
-// y_c = s_c x_c (s per column, real)
-__global__ void k_scale_cols(int64_t n, const double *s, const double2 *x, double2 *y)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int c = blockIdx.y;
-    if (i >= n) return;
-    const double sc = s[c];
-    const double2 v = x[(size_t)c * n + i];
-    y[(size_t)c * n + i] = make_double2(sc * v.x, sc * v.y);
-}
-
 }  // namespace
-
-void launch_dotc_b(ige_op op, int r, const double2 *V, int k, const double2 *w, double2 *out, int hs)
-{
-    hipLaunchKernelGGL(k_dotc_b, dim3(k, r), dim3(kRedThreads), 0, op->ctx->stream, (int64_t)op->view.N, r, V, w, out,
-                       hs);
-    IGE_HIP(hipGetLastError());
-}
-
-void launch_gemv_sub_b(ige_op op, int r, const double2 *V, int k, const double2 *hc, int hs, double2 *w)
-{
-    const int64_t n = op->view.N;
-    hipLaunchKernelGGL(k_gemv_sub_b, dim3((n + 255) / 256, r), dim3(256), 0, op->ctx->stream, n, r, V, k, hc, hs, w);
-    IGE_HIP(hipGetLastError());
-}
-
-void launch_norm2_b(ige_op op, int r, const double2 *x, double *out)
-{
-    hipLaunchKernelGGL(k_norm2_b, dim3(r), dim3(kRedThreads), 0, op->ctx->stream, (int64_t)op->view.N, x, out);
-    IGE_HIP(hipGetLastError());
-}
-
-void launch_scale_cols(ige_op op, int r, const double *s, const double2 *x, double2 *y)
-{
-    const int64_t n = op->view.N;
-    hipLaunchKernelGGL(k_scale_cols, dim3((n + 255) / 256, r), dim3(256), 0, op->ctx->stream, n, s, x, y);
-    IGE_HIP(hipGetLastError());
-}
 
 void launch_helmholtz_eval(hipStream_t s, int64_t n, double kappa, const double *r2, double2 *out, int prec)
 {
@@ -1659,37 +1498,6 @@ void launch_rhs_plane(ige_op op, const double *dir, double2 pol0, double2 pol1, 
     const DevOp &o = op->view;
     hipLaunchKernelGGL(k_rhs_plane, dim3((o.N + 127) / 128), dim3(128), 0, op->ctx->stream, o, dir[0], dir[1], dir[2],
                        pol0, pol1, pol2, f);
-    IGE_LAUNCH_CHECK();
-}
-
-void launch_dotc(ige_op op, const double2 *V, int64_t ldv, int k, const double2 *w, double2 *out)
-{
-    hipLaunchKernelGGL(k_dotc, dim3(k), dim3(kRedThreads), 0, op->ctx->stream, (int64_t)op->view.N, V, ldv, w, out);
-    IGE_LAUNCH_CHECK();
-}
-
-void launch_gemv_sub(ige_op op, const double2 *V, int64_t ldv, int k, const double2 *hcoef, double2 *w)
-{
-    const int64_t n = op->view.N;
-    hipLaunchKernelGGL(k_gemv_sub, dim3((n + 255) / 256), dim3(256), 0, op->ctx->stream, n, V, ldv, k, hcoef, w);
-    IGE_LAUNCH_CHECK();
-}
-
-void launch_axpby(ige_op op, int64_t n, double2 a, const double2 *x, double2 b, double2 *y)
-{
-    hipLaunchKernelGGL(k_axpby, dim3((n + 255) / 256), dim3(256), 0, op->ctx->stream, n, a, x, b, y);
-    IGE_LAUNCH_CHECK();
-}
-
-void launch_scale_copy(ige_op op, int64_t n, double2 a, const double2 *x, double2 *y)
-{
-    hipLaunchKernelGGL(k_scale_copy, dim3((n + 255) / 256), dim3(256), 0, op->ctx->stream, n, a, x, y);
-    IGE_LAUNCH_CHECK();
-}
-
-void launch_norm2(ige_op op, int64_t n, const double2 *x, double *out)
-{
-    hipLaunchKernelGGL(k_norm2, dim3(1), dim3(kRedThreads), 0, op->ctx->stream, n, x, out);
     IGE_LAUNCH_CHECK();
 }
 

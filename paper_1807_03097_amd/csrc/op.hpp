@@ -144,8 +144,12 @@ struct ige_op_s {
     ige::DBuf<double2> d_bmom, d_bsrc, d_bpart, d_bloc, d_bybuf, d_bxt, d_byt, d_bx, d_by;
     // GMRES workspace
     ige::DBuf<double2> d_V, d_w, d_r, d_X, d_F, d_D;
-    ige::DBuf<double2> d_h;
+    ige::DBuf<double2> d_h;                          // [2][r][restart + 2] per-pass coefficients
     ige::DBuf<double> d_red, d_scal;
+    ige::DBuf<double2> d_gspart, d_gsplit, d_hpack;  // Gram-Schmidt partials, split sums, packed column
+    ige::DBuf<double> d_gnp, d_gn;                   // norm partials; [2][r] norms before / after
+    ige::DBuf<int> d_grun, d_gflag, d_gact;          // per-column masks
+    ige::HBuf<double2> h_hpack;
 
     ige::DevOp view{};
 };
@@ -193,14 +197,27 @@ void launch_l2p_gather(ige_op op, double2 *y);
 size_t potential_source_doubles(ige_op op);
 void launch_potential(ige_op op, const double2 *w, int npts, const double *pts, double2 *out, double *src);
 void launch_rhs_plane(ige_op op, const double *dir, double2 pol0, double2 pol1, double2 pol2, double2 *f);
-// GMRES helpers
-void launch_dotc(ige_op op, const double2 *V, int64_t ldv, int k, const double2 *w, double2 *out);
-void launch_gemv_sub(ige_op op, const double2 *V, int64_t ldv, int k, const double2 *hcoef, double2 *w);
+// GMRES vector kernels (V: [k][r][n], vectors [r][n]; gate/run/flag: per-column int masks)
+struct GsPlan {
+    int nchk = 0, nblk = 0;             // entry chunks of the dot and update kernels
+    int dot_groups = 1, upd_groups = 1; // basis-index groups per pass (fill the chip at small n r)
+};
+GsPlan gs_plan(int64_t n, int r, int kmax);
+size_t gs_part_count(const GsPlan &g, int r, int kmax);        // double2 partials of a dot pass
+size_t gs_split_count(const GsPlan &g, int64_t n, int r);      // double2 split sums of an update
+// h[c][kk] = <V[kk][c], w_c> (kk < k, gate columns; 0 elsewhere), nb[c] = |w_c|^2 if nb
+void launch_gs_dots(hipStream_t s, const GsPlan &g, int64_t n, int r, const double2 *V, int k, const double2 *w,
+                    const int *gate, double2 *part, double2 *h, int hs, double *nb);
+// y_c += sign V_c h_c for gate columns; npart (if given) gets per-block |y_c|^2
+void launch_gs_update(hipStream_t s, const GsPlan &g, int64_t n, int r, const double2 *V, int k, const double2 *h,
+                      int hs, double sign, const int *gate, double2 *y, double2 *split, double *npart);
+// nf = |y|^2 of gate columns; scal = 1/|y| for run columns (0 for the others);
+// flag (if given) = second Gram-Schmidt pass needed
+void launch_gs_norm(hipStream_t s, const GsPlan &g, int r, const double *npart, const int *gate, const int *run,
+                    const double *nb, double *nf, double *scal, int *flag);
+void launch_gs_pack(hipStream_t s, int r, int k, const double2 *h1, const double2 *h2, int hs, const double *nf,
+                    double2 *out);
 void launch_axpby(ige_op op, int64_t n, double2 a, const double2 *x, double2 b, double2 *y);
-void launch_scale_copy(ige_op op, int64_t n, double2 a, const double2 *x, double2 *y);
-void launch_norm2(ige_op op, int64_t n, const double2 *x, double *out);
-void launch_dotc_b(ige_op op, int r, const double2 *V, int k, const double2 *w, double2 *out, int hs);
-void launch_gemv_sub_b(ige_op op, int r, const double2 *V, int k, const double2 *hc, int hs, double2 *w);
 void launch_norm2_b(ige_op op, int r, const double2 *x, double *out);
 void launch_scale_cols(ige_op op, int r, const double *s, const double2 *x, double2 *y);
 void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, double2 *yt, hipEvent_t *ev, int prec);
