@@ -482,6 +482,13 @@ ige_op ige::assemble_on(ige_ctx ctx, const ige_geom_s *geom, const ige_params &p
                     }
                     std::vector<int32_t> mwt(op->NC + 1, 0);
                     for (int c = 0; c < op->NC; ++c) mwt[c + 1] = mwt[c] + mcnt[c];
+                    // launch order: decreasing partner count (long items first)
+                    std::vector<int32_t> morder(op->mwork.size());
+                    for (size_t w = 0; w < morder.size(); ++w) morder[w] = (int32_t)w;
+                    std::stable_sort(morder.begin(), morder.end(), [&](int32_t a, int32_t b) {
+                        return op->mwork[a].end - op->mwork[a].beg > op->mwork[b].end - op->mwork[b].beg;
+                    });
+                    op->d_morder.upload(morder, s);
                     op->d_mwork.upload(op->mwork, s);
                     op->d_mpartner.upload(mpart, s);
                     op->d_gslot.upload(gslot, s);

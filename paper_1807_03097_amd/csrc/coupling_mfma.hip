@@ -1,19 +1,29 @@
 // Coupling stage (a5) on the BF16 matrix cores, for many right-hand sides.
 //
-// The kernel matrices G of the admissible pairs are stored once in BF16, in both
-// orientations (G_ts row-major and G_st = G_ts^T row-major), so that the operand of
-// every ordered pair t <- s has its reduction index contiguous.  A complex product
-// U_t = G_ts V_s is one real product
-//   [Re U | Im U] (interleaved per column) = [Gr | Gi] (Qp x 2Qp) . [[Vr, Vi], [-Vi, Vr]]
-// with FP32 accumulation on the 16x16x32 BF16 instruction (lane l supplies
-// A[l%16][8(l/16)+i] and B[8(l/16)+i][l%16]; accumulator register j of lane l holds
-// D[4(l/16)+j][l%16]).  With split = 3 both factors are stored as a BF16 pair
-// (x = xh + xl) and the product is xh.yh + xh.yl + xl.yh (about 2^-16 relative).
+// The kernel matrices G of the admissible pairs (the dense coupling blocks of the
+// interpolation-based FMM, Sec. 4) are stored once in BF16, in both orientations
+// (G_ts and G_st = G_ts^T, rows [Re | Im]), so that the operand of every ordered pair
+// t <- s has its reduction index contiguous.  A complex product U_t = G_ts V_s over
+// all right-hand sides is one real product with stacked real and imaginary parts,
+//   [Re U; Im U] (2Qp x n) = [[Gr, -Gi], [Gi, Gr]] (2Qp x 2Qp) . [Re V; Im V] (2Qp x n),
+// whose left factor is read from the stored [Gr | Gi] rows (halves swapped for the
+// imaginary rows, sign flipped on the Gi half of the real rows), so the streamed
+// right factor holds each complex entry once.  The product runs on the 16x16x32
+// BF16 instruction with FP32 accumulation (lane l supplies A[l%16][8(l/16)+i] and
+// B[8(l/16)+i][l%16]; accumulator register j of lane l holds D[4(l/16)+j][l%16]).
+// With split = 3 both factors are stored as a BF16 pair (x = xh + xl) and the
+// product is xh.yh + xh.yl + xl.yh (about 2^-16 relative).
 //
-// Work: one workgroup per (target cluster, up to 32 partners, 8 right-hand sides);
-// the source fields are converted once per apply into the operand layout; partial
-// couplings per work item are summed by the fixed-order per-cluster reduction.
+// Work: one workgroup per (work item = target cluster and up to 32 partners, column
+// chunk of up to 64 right-hand sides), all columns of the chunk at once so that each
+// block G is read once per chunk: G is staged in shared memory (the next partner's
+// block prefetched into registers during the current product), the right factor is
+// streamed from memory into registers one reduction step ahead.  Wave wm = 0 forms
+// the real rows, wm = 1 the imaginary rows; wn splits the columns.  Partial couplings
+// per work item (FP32) are summed by the fixed-order per-cluster reduction.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "device_math.hpp"
 #include "op.hpp"
@@ -24,8 +34,6 @@ namespace {
 
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
-constexpr int kRC = 8;            // right-hand sides per column chunk
-constexpr int kNCol = 8 * kRC;    // real operand columns per chunk: 4 fields x kRC x (re, im)
 
 __device__ inline void split_bf16(double x, __bf16 &hi, __bf16 &lo)
 {
@@ -69,25 +77,25 @@ __global__ void k_gb_store(DevOp o, int64_t nfp, const int32_t *fpair, int Qp, i
     }
 }
 
-// Source fields [NC][4][Q][r] -> operand layout Vb[cluster][chunk][plane][kNCol][2Qp]
-// (planes as for G):
-// column n = 2 c + h (c = field * kRC + column in chunk, h = re/im), row k:
-// k < Qp: (Vr, Vi)[k], k >= Qp: (-Vi, Vr)[k - Qp]
-__global__ void k_vb_prep(DevOp o, int NC, int r, int nchunk, int Qp, int split, const double2 *src, __bf16 *Vb)
+// Source fields [NC][4][Q][r] -> right factor Vb[cluster][chunk][plane][ncol][2Qp]
+// (planes as for G): column n = f rc + j (field f, right-hand side ch rc + j),
+// row k < Qp: Re V[k], k >= Qp: Im V[k - Qp]; zero padded
+__global__ void k_vb_prep(DevOp o, int NC, int r, int rc, int nchunk, int ncol, int Qp, int split, const double2 *src,
+                          __bf16 *Vb)
 {
     const int Q = o.Q, K2 = 2 * Qp;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t per = (int64_t)kNCol * K2;
+    const int64_t per = (int64_t)ncol * K2;
     if (t >= (int64_t)NC * nchunk * per) return;
     const int64_t cc = t / per;   // cluster * nchunk + chunk
     const int rem = (int)(t % per), n = rem / K2, k = rem % K2;
     const int gc = (int)(cc / nchunk), ch = (int)(cc % nchunk);
-    const int c = n >> 1, h = n & 1, f = c / kRC, j = c % kRC, col = ch * kRC + j;
+    const int f = n / rc, j = n % rc, col = ch * rc + j;
     const int mm = k < Qp ? k : k - Qp;
     double v = 0.0;
-    if (mm < Q && col < r) {
+    if (mm < Q && col < r && f < 4) {
         const double2 s = src[(((size_t)gc * 4 + f) * Q + mm) * r + col];
-        v = k < Qp ? (h ? s.y : s.x) : (h ? s.x : -s.y);
+        v = k < Qp ? s.x : s.y;
     }
     __bf16 *base = Vb + (size_t)cc * (split == 3 ? 2 : 1) * per;
     if (split == 1) {
@@ -100,93 +108,157 @@ __global__ void k_vb_prep(DevOp o, int NC, int r, int nchunk, int Qp, int split,
     }
 }
 
-// 4 waves as 2 (row halves) x 2 (column halves); a wave holds MT row tiles x 2 column
-// tiles of the Qp x kNCol output
-template <int MT, int SPLIT>
-__global__ __launch_bounds__(256) void k_m2l_bf16(DevOp o, int r, int nchunk, int64_t nwork, int Qp,
-                                                  const M2LWork *work, const int32_t *partner, const int32_t *gslot,
-                                                  const __bf16 *Gb, const __bf16 *Vb, double2 *part)
+__device__ inline bf8 neg_bf8(bf8 x)
 {
-    constexpr int PL = SPLIT == 3 ? 2 : 1;   // BF16 planes per operand
-    extern __shared__ __bf16 sV[];   // [PL][kNCol][K2 + 8]
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wm = wv >> 1, wn = wv & 1;
-    const int Q = o.Q, K2 = 2 * Qp, KS = K2 / 32, QT = Qp / 16, LD = K2 + 8;
+    uint4 u = __builtin_bit_cast(uint4, x);
+    u.x ^= 0x80008000u;
+    u.y ^= 0x80008000u;
+    u.z ^= 0x80008000u;
+    u.w ^= 0x80008000u;
+    return __builtin_bit_cast(bf8, u);
+}
+
+// MT = Qp / 16 row tiles per wave, WN column waves of NT 16-column tiles each:
+// 2 WN waves, ncol = 16 WN NT columns per chunk
+template <int SPLIT, int MT, int WN, int NT>
+__global__ __launch_bounds__(128 * WN) void k_m2l_mx(DevOp o, int r, int rc, int nchunk, int64_t nwork,
+                                                     const int32_t *order, const M2LWork *work,
+                                                     const int32_t *partner, const int32_t *gslot, const __bf16 *Gb,
+                                                     const __bf16 *Vb, float2 *part)
+{
+    constexpr int PL = SPLIT == 3 ? 2 : 1;   // BF16 planes per factor
+    constexpr int QP = 16 * MT, K2 = 2 * QP, KS = K2 / 32, LD = K2 + 8;
+    constexpr int NTH = 128 * WN, NCOL = 16 * WN * NT;
+    constexpr int GCH = PL * QP * K2 / 8;           // 16-byte pieces of one block
+    constexpr int GV = (GCH + NTH - 1) / NTH;       // pieces per thread
+    constexpr bool PREF = GV <= 16;                 // next block prefetched into registers
+    extern __shared__ __bf16 sG[];                  // [PL][QP][LD]
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv / WN, wn = wv % WN;
+    const int Q = o.Q;
     // the chunks of one work item share an XCD (consecutive ids go round-robin over 8)
     const int64_t g = blockIdx.x;
-    const int64_t wi = (g / (8 * nchunk)) * 8 + g % 8;
+    const int64_t wo = (g / (8 * nchunk)) * 8 + g % 8;
     const int ch = (int)((g / 8) % nchunk);
-    if (wi >= nwork) return;
+    if (wo >= nwork) return;
+    const int64_t wi = order[wo];
     const M2LWork wk = work[wi];
-    f4 acc[MT][2];
+    if (wk.beg >= wk.end) return;
+    const size_t gper = (size_t)PL * QP * K2, vper = (size_t)NCOL * K2;
+
+    auto g_piece = [&](const __bf16 *Gp, int e) -> uint4 {
+        return *reinterpret_cast<const uint4 *>(Gp + (size_t)8 * e);
+    };
+    auto s_piece = [&](int e, uint4 v) {
+        const int pl = e / (QP * K2 / 8), rr = e % (QP * K2 / 8), row = rr / (K2 / 8), k8 = rr % (K2 / 8);
+        *reinterpret_cast<uint4 *>(sG + ((size_t)pl * QP + row) * LD + 8 * k8) = v;
+    };
+    auto b_load = [&](bf8 (&b)[NT][PL], int kp, int s) {
+        const __bf16 *Vs = Vb + ((size_t)partner[kp] * nchunk + ch) * PL * vper;
+        const int kk = 32 * s + 8 * (lane >> 4);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int n = 16 * (wn * NT + t) + (lane & 15);
+#pragma unroll
+            for (int pl = 0; pl < PL; ++pl)
+                b[t][pl] = *reinterpret_cast<const bf8 *>(Vs + (size_t)pl * vper + (size_t)n * K2 + kk);
+        }
+    };
+
+    f4 acc[MT][NT];
 #pragma unroll
     for (int a = 0; a < MT; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
-    const size_t vper = (size_t)kNCol * K2;
+        for (int t = 0; t < NT; ++t) acc[a][t] = f4{0.f, 0.f, 0.f, 0.f};
+
+    uint4 gpre[PREF ? GV : 1];
+    if (PREF) {
+        const __bf16 *Gp = Gb + (size_t)gslot[wk.beg] * gper;
+#pragma unroll
+        for (int v = 0; v < GV; ++v) {
+            const int e = tid + NTH * v;
+            if (e < GCH) gpre[v] = g_piece(Gp, e);
+        }
+    }
+    bf8 bcur[NT][PL], bnxt[NT][PL];
+    b_load(bcur, wk.beg, 0);
     for (int kp = wk.beg; kp < wk.end; ++kp) {
-        const int sc = partner[kp];
-        const __bf16 *Vs = Vb + ((size_t)sc * nchunk + ch) * PL * vper;
-        __syncthreads();
-        // stage the source operand (16-byte pieces) into shared memory
-        for (int e = threadIdx.x; e < PL * kNCol * K2 / 8; e += blockDim.x) {
-            const int pl = e / (kNCol * K2 / 8), rr = e % (kNCol * K2 / 8), n = rr / (K2 / 8), k8 = rr % (K2 / 8);
-            *reinterpret_cast<bf8 *>(sV + ((size_t)pl * kNCol + n) * LD + 8 * k8) =
-                *reinterpret_cast<const bf8 *>(Vs + (size_t)pl * vper + (size_t)n * K2 + 8 * k8);
+        __syncthreads();   // every wave is done with the previous block
+        if (PREF) {
+#pragma unroll
+            for (int v = 0; v < GV; ++v) {
+                const int e = tid + NTH * v;
+                if (e < GCH) s_piece(e, gpre[v]);
+            }
+        } else {
+            const __bf16 *Gp = Gb + (size_t)gslot[kp] * gper;
+            for (int e = tid; e < GCH; e += NTH) s_piece(e, g_piece(Gp, e));
         }
         __syncthreads();
-        const __bf16 *Gp = Gb + (size_t)gslot[kp] * PL * Qp * K2;
-        for (int s = 0; s < KS; ++s) {
-            const int kk = 32 * s + 8 * (lane >> 4);
-            bf8 bh[2], bl[2];
+        if (PREF && kp + 1 < wk.end) {
+            const __bf16 *Gp = Gb + (size_t)gslot[kp + 1] * gper;
 #pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                const int n = 16 * (2 * wn + b) + (lane & 15);
-                bh[b] = *reinterpret_cast<const bf8 *>(sV + (size_t)n * LD + kk);
-                if (SPLIT == 3) bl[b] = *reinterpret_cast<const bf8 *>(sV + ((size_t)kNCol + n) * LD + kk);
+            for (int v = 0; v < GV; ++v) {
+                const int e = tid + NTH * v;
+                if (e < GCH) gpre[v] = g_piece(Gp, e);
             }
+        }
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            if (s + 1 < KS) b_load(bnxt, kp, s + 1);
+            else if (kp + 1 < wk.end) b_load(bnxt, kp + 1, 0);
+            // left factor: real rows [Gr, -Gi], imaginary rows [Gi, Gr] of the stored [Gr | Gi]
+            const bool hi_half = 32 * s >= QP;
+            const int kk = 32 * s + 8 * (lane >> 4);
+            const int ksrc = wm == 0 ? kk : (hi_half ? kk - QP : kk + QP);
+            const bool neg = wm == 0 && hi_half;
 #pragma unroll
             for (int a = 0; a < MT; ++a) {
-                const int mt = wm * MT + a;
-                if (mt >= QT) break;   // uniform over the wave
-                const size_t ro = (size_t)(16 * mt + (lane & 15)) * K2 + kk;
-                const bf8 ah = *reinterpret_cast<const bf8 *>(Gp + ro);
+                const __bf16 *row = sG + (size_t)(16 * a + (lane & 15)) * LD + ksrc;
+                bf8 ah = *reinterpret_cast<const bf8 *>(row);
                 bf8 al;
-                if (SPLIT == 3) al = *reinterpret_cast<const bf8 *>(Gp + (size_t)Qp * K2 + ro);
+                if (SPLIT == 3) al = *reinterpret_cast<const bf8 *>(row + (size_t)QP * LD);
+                if (neg) {
+                    ah = neg_bf8(ah);
+                    if (SPLIT == 3) al = neg_bf8(al);
+                }
 #pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[b], acc[a][b], 0, 0, 0);
+                for (int t = 0; t < NT; ++t) {
+                    acc[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bcur[t][0], acc[a][t], 0, 0, 0);
                     if (SPLIT == 3) {
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[b], acc[a][b], 0, 0, 0);
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[b], acc[a][b], 0, 0, 0);
+                        acc[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bcur[t][PL - 1], acc[a][t], 0, 0, 0);
+                        acc[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bcur[t][0], acc[a][t], 0, 0, 0);
                     }
                 }
             }
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int pl = 0; pl < PL; ++pl) bcur[t][pl] = bnxt[t][pl];
         }
     }
-    // lane holds D[4 (lane/16) + j][lane % 16] of each tile: row m, column n = 2 c + h
+    // lane holds D[4 (lane/16) + j][lane % 16] of each tile: node m, column n = f rc + jc;
+    // wave half wm gives the real (0) or imaginary (1) part
 #pragma unroll
-    for (int a = 0; a < MT; ++a) {
-        const int mt = wm * MT + a;
-        if (mt >= QT) break;
+    for (int t = 0; t < NT; ++t) {
+        const int n = 16 * (wn * NT + t) + (lane & 15), f = n / rc, jc = n % rc;
+        const int col = ch * rc + jc;
+        if (f >= 4 || col >= r) continue;
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            const int n = 16 * (2 * wn + b) + (lane & 15), c = n >> 1, h = n & 1, f = c / kRC, jc = c % kRC;
-            const int col = ch * kRC + jc;
+        for (int a = 0; a < MT; ++a)
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int m = 16 * mt + 4 * (lane >> 4) + j;
-                if (m < Q && col < r) {
-                    double *dst = reinterpret_cast<double *>(part + (((size_t)wi * 4 + f) * Q + m) * r + col);
-                    dst[h] = (double)acc[a][b][j];
+                const int m = 16 * a + 4 * (lane >> 4) + j;
+                if (m < Q) {
+                    float *dst = reinterpret_cast<float *>(part + (((size_t)wi * 4 + f) * Q + m) * r + col);
+                    dst[wm] = acc[a][t][j];
                 }
             }
-        }
     }
 }
 
 }  // namespace
 
-int coupling_qp(int Q) { return 16 * ((Q + 15) / 16); }
+int coupling_qp(int Q) { return 32 * ((Q + 31) / 32); }
 
 void ensure_coupling_bf16(ige_op op, int split)
 {
@@ -202,29 +274,66 @@ void ensure_coupling_bf16(ige_op op, int split)
 }
 
 namespace {
-template <int SPLIT>
-void launch_m2l_bf16_mt(ige_op op, int r, int nchunk, int MT, const __bf16 *G, const __bf16 *Vb, size_t shm)
+
+// columns per chunk (complex columns = 4 fields x right-hand sides): the smallest of
+// 16..256 holding all 4r columns, capped so that the accumulators, the prefetched
+// block and the streamed factor stay in registers (no spills)
+int m2l_ncol(int r, int MT, int split)
+{
+    const int cap = MT >= 8 ? (split == 3 ? 64 : 128) : (MT >= 6 ? 128 : 256);
+    int nc = 16;
+    while (nc < 4 * r && nc < cap) nc *= 2;
+    return nc;
+}
+
+template <int SPLIT, int MT, int WN, int NT>
+void launch_mx(ige_op op, int r, int rc, int nchunk, const __bf16 *G, const __bf16 *Vb, hipStream_t s)
 {
     const DevOp &o = op->view;
     const int64_t nw = (int64_t)op->mwork.size();
-    const dim3 grid((unsigned)(((nw + 7) / 8) * 8 * nchunk)), blk(256);
-    hipStream_t s = op->ctx->stream;
-    const int Qp = coupling_qp(o.Q);
-#define IGE_BF16_CASE(M)                                                                                            \
-    case M:                                                                                                         \
-        hipLaunchKernelGGL((k_m2l_bf16<M, SPLIT>), grid, blk, shm, s, o, r, nchunk, nw, Qp, op->d_mwork.p,          \
-                           op->d_mpartner.p, op->d_gslot.p, G, Vb, op->d_bmpart.p);                                 \
-        break;
-    switch (MT) {
-        IGE_BF16_CASE(1)
-        IGE_BF16_CASE(2)
-        IGE_BF16_CASE(3)
-        IGE_BF16_CASE(4)
-        default: IGE_BF16_CASE(5)
-    }
-#undef IGE_BF16_CASE
+    const dim3 grid((unsigned)(((nw + 7) / 8) * 8 * nchunk)), blk(128 * WN);
+    constexpr int PL = SPLIT == 3 ? 2 : 1, QP = 16 * MT;
+    const size_t shm = sizeof(__bf16) * PL * QP * (2 * QP + 8);
+    int lds_max = 0;
+    IGE_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, op->ctx->device));
+    IGE_REQUIRE(shm <= (size_t)lds_max, "coupling block does not fit in shared memory");
+    IGE_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_m2l_mx<SPLIT, MT, WN, NT>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    hipLaunchKernelGGL((k_m2l_mx<SPLIT, MT, WN, NT>), grid, blk, shm, s, o, r, rc, nchunk, nw, op->d_morder.p,
+                       op->d_mwork.p, op->d_mpartner.p, op->d_gslot.p, G, Vb, op->d_bmpart.p);
     IGE_HIP(hipGetLastError());
 }
+
+template <int SPLIT, int MT>
+void launch_mx_cols(ige_op op, int r, int ncol, const __bf16 *G, const __bf16 *Vb, hipStream_t s)
+{
+    const int rc = ncol / 4, nchunk = (r + rc - 1) / rc;
+    switch (ncol) {
+        case 16: launch_mx<SPLIT, MT, 1, 1>(op, r, rc, nchunk, G, Vb, s); break;
+        case 32: launch_mx<SPLIT, MT, 2, 1>(op, r, rc, nchunk, G, Vb, s); break;
+        case 64: launch_mx<SPLIT, MT, 4, 1>(op, r, rc, nchunk, G, Vb, s); break;
+        case 128:
+            if constexpr (SPLIT == 1 || MT < 8) launch_mx<SPLIT, MT, 4, 2>(op, r, rc, nchunk, G, Vb, s);
+            else IGE_REQUIRE(false, "coupling chunk too wide for this interpolation degree");
+            break;
+        default:
+            if constexpr (MT <= 4) launch_mx<SPLIT, MT, 4, 4>(op, r, rc, nchunk, G, Vb, s);
+            else IGE_REQUIRE(false, "coupling chunk too wide for this interpolation degree");
+            break;
+    }
+}
+
+template <int SPLIT>
+void launch_mx_mt(ige_op op, int r, int MT, int ncol, const __bf16 *G, const __bf16 *Vb, hipStream_t s)
+{
+    switch (MT) {
+        case 2: launch_mx_cols<SPLIT, 2>(op, r, ncol, G, Vb, s); break;
+        case 4: launch_mx_cols<SPLIT, 4>(op, r, ncol, G, Vb, s); break;
+        case 6: launch_mx_cols<SPLIT, 6>(op, r, ncol, G, Vb, s); break;
+        default: launch_mx_cols<SPLIT, 8>(op, r, ncol, G, Vb, s); break;
+    }
+}
+
 }  // namespace
 
 void m2l_bf16(ige_op op, int r, int split, const double2 *src, hipStream_t s)
@@ -232,21 +341,20 @@ void m2l_bf16(ige_op op, int r, int split, const double2 *src, hipStream_t s)
     const DevOp &o = op->view;
     if (op->mwork.empty()) return;
     ensure_coupling_bf16(op, split);
-    const int Qp = coupling_qp(o.Q), K2 = 2 * Qp, QT = Qp / 16, MT = (QT + 1) / 2;
-    IGE_REQUIRE(MT <= 5, "interpolation degree too large for the matrix-core coupling");
-    const int nchunk = (r + kRC - 1) / kRC;
+    const int Qp = coupling_qp(o.Q), K2 = 2 * Qp, MT = Qp / 16;
+    IGE_REQUIRE(MT <= 8, "interpolation degree too large for the matrix-core coupling");
+    const int ncol = m2l_ncol(r, MT, split), rc = ncol / 4, nchunk = (r + rc - 1) / rc;
     const int planes = split == 3 ? 2 : 1;
-    const size_t vbn = (size_t)op->NC * nchunk * planes * kNCol * K2;
+    const size_t vbn = (size_t)op->NC * nchunk * planes * ncol * K2;
     if (op->d_vb.n < vbn) op->d_vb.alloc(vbn);
     const size_t pn = op->mwork.size() * 4 * (size_t)o.Q * r;
     if (op->d_bmpart.n < pn) op->d_bmpart.alloc(pn);
-    const int64_t nv = (int64_t)op->NC * nchunk * kNCol * K2;
-    hipLaunchKernelGGL(k_vb_prep, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s, o, op->NC, r, nchunk, Qp,
-                       split, src, op->d_vb.p);
+    const int64_t nv = (int64_t)op->NC * nchunk * ncol * K2;
+    hipLaunchKernelGGL(k_vb_prep, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s, o, op->NC, r, rc, nchunk, ncol,
+                       Qp, split, src, op->d_vb.p);
     IGE_HIP(hipGetLastError());
-    const size_t shm = sizeof(__bf16) * planes * kNCol * (K2 + 8);
-    if (split == 3) launch_m2l_bf16_mt<3>(op, r, nchunk, MT, op->d_Gb3.p, op->d_vb.p, shm);
-    else launch_m2l_bf16_mt<1>(op, r, nchunk, MT, op->d_Gb1.p, op->d_vb.p, shm);
+    if (split == 3) launch_mx_mt<3>(op, r, MT, ncol, op->d_Gb3.p, op->d_vb.p, s);
+    else launch_mx_mt<1>(op, r, MT, ncol, op->d_Gb1.p, op->d_vb.p, s);
 }
 
 }  // namespace ige

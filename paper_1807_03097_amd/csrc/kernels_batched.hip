@@ -422,7 +422,11 @@ __global__ __launch_bounds__(kM2LThreadsB) void k_m2l_b(DevOp o, int r, const M2
     }
 }
 
-__global__ void k_m2l_reduce_b(DevOp o, int r, const int32_t *wrk_of_tgt, const double2 *part, double2 *loc)
+__device__ inline double2 to_d2(double2 v) { return v; }
+__device__ inline double2 to_d2(float2 v) { return make_double2(v.x, v.y); }
+
+template <typename PT>
+__global__ void k_m2l_reduce_b(DevOp o, int r, const int32_t *wrk_of_tgt, const PT *part, double2 *loc)
 {
     const int gc = blockIdx.x, Q = o.Q;
     const int b = wrk_of_tgt[gc], e = wrk_of_tgt[gc + 1];
@@ -431,7 +435,7 @@ __global__ void k_m2l_reduce_b(DevOp o, int r, const int32_t *wrk_of_tgt, const 
         const int mm = t / r, c = t % r;
         double2 u[4] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
         for (int w = b; w < e; ++w)
-            for (int k = 0; k < 4; ++k) u[k] = caddb(u[k], part[(((size_t)w * 4 + k) * Q + mm) * r + c]);
+            for (int k = 0; k < 4; ++k) u[k] = caddb(u[k], to_d2(part[(((size_t)w * 4 + k) * Q + mm) * r + c]));
         const double *T = o.nodeT + (size_t)gc * 6 * Q;
         double2 t1 = make_double2(0, 0), t2 = make_double2(0, 0);
         for (int k = 0; k < 3; ++k) {
@@ -623,7 +627,7 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
         if (prec == IGE_BF16 || prec == IGE_BF16X3) {
             m2l_bf16(op, r, prec == IGE_BF16X3 ? 3 : 1, op->d_bsrc.p, s);
             mark(3);
-            hipLaunchKernelGGL(k_m2l_reduce_b, dim3(op->NC), dim3(256), 0, s, o, r, op->d_mwrk_of_tgt.p,
+            hipLaunchKernelGGL(k_m2l_reduce_b<float2>, dim3(op->NC), dim3(256), 0, s, o, r, op->d_mwrk_of_tgt.p,
                                op->d_bmpart.p, op->d_bloc.p);
             IGE_HIP(hipGetLastError());
         } else if (op->stored) {
@@ -654,7 +658,7 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
                 IGE_HIP(hipGetLastError());
             }
             mark(3);
-            hipLaunchKernelGGL(k_m2l_reduce_b, dim3(op->NC), dim3(256), 0, s, o, r, op->d_wrk_of_tgt.p, op->d_bpart.p,
+            hipLaunchKernelGGL(k_m2l_reduce_b<double2>, dim3(op->NC), dim3(256), 0, s, o, r, op->d_wrk_of_tgt.p, op->d_bpart.p,
                                op->d_bloc.p);
             IGE_HIP(hipGetLastError());
         }

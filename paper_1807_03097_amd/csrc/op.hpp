@@ -129,7 +129,8 @@ struct ige_op_s {
     std::vector<ige::M2LWork> mwork;
     ige::DBuf<ige::M2LWork> d_mwork;
     ige::DBuf<int32_t> d_mpartner, d_gslot, d_mwrk_of_tgt;
-    ige::DBuf<double2> d_bmpart;
+    ige::DBuf<float2> d_bmpart;          // matrix-core coupling partials [mwork][4][Q][r]
+    ige::DBuf<int32_t> d_morder;         // work items by decreasing partner count
     // apply workspaces (one right-hand side at a time)
     ige::DBuf<double2> d_mom;    // [NC][3][Q]   s^1, s^2, d
     ige::DBuf<double2> d_src;    // [NC][4][Q]   v_x, v_y, v_z, d

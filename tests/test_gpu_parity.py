@@ -263,13 +263,19 @@ def test_bf16_matrix_core_coupling(oracle_mod, ctx, case):
     yo = oracle_mod.Oracle(pats, p, m, kappa, g=g, gs=gs).fmm_apply(x, q, eta, d)
     X = np.stack([x] + [W.random_coeffs(op.N, s) for s in range(1, 11)])
     y64 = op.apply(X)
+    # 70 columns: several column chunks with a ragged last one
+    X70 = np.stack([W.random_coeffs(op.N, 100 + s) for s in range(70)])
+    y70 = op.apply(X70)
     for prec, lo, hi in ((B.IGE_BF16, 1e-6, 1e-2), (B.IGE_BF16X3, 1e-12, 2e-4)):
         y1 = op.apply(x, prec=prec)
         Y = op.apply(X, prec=prec)
+        Y70 = op.apply(X70, prec=prec)
         e1, eb = _rel(y1, yo), _rel(Y[0], yo)
         eall = max(_rel(Y[c], y64[c]) for c in range(len(X)))
-        _say(f"  prec {prec}: 1 column {e1:.2e}, 11 columns {eb:.2e}, worst column vs FP64 {eall:.2e}")
-        assert lo < e1 <= hi and lo < eb <= hi and eall <= hi
+        e70 = max(_rel(Y70[c], y70[c]) for c in range(len(X70)))
+        _say(f"  prec {prec}: 1 column {e1:.2e}, 11 columns {eb:.2e}, worst column vs FP64 {eall:.2e}, "
+             f"worst of 70 {e70:.2e}")
+        assert lo < e1 <= hi and lo < eb <= hi and eall <= hi and e70 <= hi
     if op.N > 1000:   # the unpreconditioned FP64 reference solve needs thousands of iterations
         op.close()
         return
