@@ -46,8 +46,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=16, help="rows of the bounded oracle sample")
     ap.add_argument("--nrhs", type=int, default=1, help="right-hand sides per apply (batched kernels when > 1)")
-    ap.add_argument("--prec", type=int, default=0, choices=(0, 1, 2, 3),
-                    help="coupling precision: 0 FP64, 1 FP32, 2 BF16 matrix cores, 3 split BF16 (3 products)")
+    ap.add_argument("--prec", type=int, default=0, choices=(0, 1, 2, 3, 4),
+                    help="coupling precision: 0 FP64, 1 FP32, 2 BF16 matrix cores, 3 split BF16 (3 products), "
+                         "4 split BF16 coupling and near field")
     ap.add_argument("--store-coupling", type=int, default=-1, choices=(-1, 0, 1),
                     help="coupling blocks: 1 stored, 0 evaluated per apply, -1 stored if they fit")
     ap.add_argument("--verbose", action="store_true")
@@ -57,7 +58,8 @@ def parse():
     ap.add_argument("--q", type=int, default=8, help="solve: interpolation degree")
     ap.add_argument("--tol", type=float, default=1e-6, help="solve: relative residual")
     ap.add_argument("--restart", type=int, default=1500, help="solve: GMRES restart")
-    ap.add_argument("--inner-prec", type=int, default=3, help="solve: coupling precision of refined inner solves")
+    ap.add_argument("--inner-prec", type=int, default=3, choices=(0, 1, 2, 3, 4),
+                    help="solve: precision of refined inner solves (as --prec)")
     ap.add_argument("--compare-fp64", action="store_true", help="solve: also solve in FP64 and report the difference")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (calibrates HBM byte counters)")
@@ -163,14 +165,15 @@ def run_solve(args):
         diff = max(float(np.linalg.norm(sols["refined"][c] - sols["fp64"][c]) / np.linalg.norm(sols["fp64"][c]))
                    for c in range(args.nrhs))
         log(f"refined vs FP64 solutions: max relative difference {diff:.2e}")
-    prec_name = ["f64", "f32", "bf16", "split-bf16"][args.inner_prec]
+    prec_name = ["f64", "f32 coupling", "bf16 coupling", "split-bf16 coupling",
+                 "split-bf16 coupling and near field"][args.inner_prec]
     out = {
         "metric": "EFIE solves/s",
         "value": runs[0]["solves_per_s"],
         "unit": "solves/s",
         "n_gpus": 1,
         "higher_is_better": True,
-        "dtype": "f64" if not args.refine else f"f64 refinement around {prec_name} coupling",
+        "dtype": "f64" if not args.refine else f"f64 refinement around {prec_name}",
         "data": "synthetic",
         "config": {"workload": f"cube-sphere, level {args.level}, p={args.p}, kappa={args.kappa}, q={args.q}, "
                                f"eta={args.eta}, {args.nrhs} Fibonacci plane waves, GMRES tol {args.tol}, "
@@ -232,7 +235,8 @@ def run_serving(args):
         "unit": "solves/s",
         "n_gpus": 1,
         "higher_is_better": True,
-        "dtype": "f64" if not args.refine else ["f64", "f32", "bf16", "split-bf16"][args.inner_prec] + " coupling + f64 refinement",
+        "dtype": "f64" if not args.refine else ["f64", "f32 coupling", "bf16 coupling", "split-bf16 coupling",
+                                                 "split-bf16 coupling and near field"][args.inner_prec] + " + f64 refinement",
         "data": "synthetic",
         "p50_latency_s": float(np.percentile(lat, 50)),
         "p99_latency_s": float(np.percentile(lat, 99)),
@@ -378,7 +382,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": ["f64", "f64 (f32 coupling)", "f64 (bf16 matrix-core coupling)",
-                  "f64 (split-bf16 matrix-core coupling)"][args.prec],
+                  "f64 (split-bf16 matrix-core coupling)",
+                  "f64 moments/transfers (split-bf16 coupling and near field)"][args.prec],
         "data": "synthetic",
         "config": {"workload": f"FMM matvec: 6-patch NURBS sphere, level {m}, p={p}, kappa={kappa}, q={q}, "
                                f"5x5 Gauss near field, x ~ N(0,1)+iN(0,1) seed 0",

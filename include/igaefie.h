@@ -146,7 +146,7 @@ int ige_op_dofmap(ige_op op, int32_t *dof, int8_t *sgn);
  * cluster id on level l: patch*4^l + k2*2^l + k1.  Either pointer may be NULL. */
 int ige_op_partition(ige_op op, int32_t *far, int32_t *near);
 
-enum { IGE_F64 = 0, IGE_F32 = 1, IGE_BF16 = 2, IGE_BF16X3 = 3 };
+enum { IGE_F64 = 0, IGE_F32 = 1, IGE_BF16 = 2, IGE_BF16X3 = 3, IGE_BF16X3_ALL = 4 };
 
 /* y = A x for r right-hand sides (A the compressed operator).  x, y: N*r complex.
  * r > 1 runs the batched kernels (columns in chunks, every kernel value and matrix
@@ -164,10 +164,15 @@ int ige_apply(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind);
  *             with FP32 accumulation (complex products as one real product);
  *             relative error about 2^-9 on the far field;
  *   IGE_BF16X3 the same with both factors split into a high and a low BF16 part and
- *             three products (high*high + high*low + low*high); about 2^-16.
- * Near field, moments and transfers stay FP64.  The FP32 copy and the BF16 blocks are
- * made on first use (BF16: 2 * pairs * Qp * 2Qp * 2 bytes per plane, Qp = Q rounded
- * up to 16). */
+ *             three products (high*high + high*low + low*high); about 2^-16;
+ *   IGE_BF16X3_ALL  coupling as IGE_BF16X3 and, in addition, the near-field product
+ *             from a split-BF16 copy of the FP64-assembled near-field blocks (one block
+ *             per ordered leaf pair) with FP32 accumulation; about 2^-16 on the whole
+ *             product.  Meant as the inner operator of refined solves.
+ * Unless stated, near field, moments and transfers stay FP64.  The FP32 copy and the
+ * BF16 blocks are made on first use (BF16 coupling: 2 * pairs * Qp * 2Qp * 2 bytes per
+ * plane, Qp = Q rounded up to 32; split-BF16 near field: 2 * blocks * 2 * Qn * 2Qn * 2
+ * bytes, Qn = slots per leaf rounded up to 32). */
 int ige_apply_prec(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind, int coupling_prec);
 
 /* Stage profiling.  ige_op_set_profiling(op, 1) creates HIP events and clears the
@@ -198,10 +203,11 @@ typedef struct {
     int maxit;       /* total iteration cap (inner iterations summed over refinement steps) */
     int refine;      /* 0: GMRES on the FP64 operator; 1: iterative refinement -- FP64
                         residual f - A x, inner GMRES on the inner_prec operator for the
-                        correction, x += correction, repeated; each inner solve reduces
-                        its residual by max(inner_tol, tol / (2 * current relres)) */
+                        correction, x += correction, repeated; each inner solve is at most
+                        one GMRES cycle (restart iterations) and stops when its residual
+                        estimate is reduced by max(inner_tol, tol / (2 * current relres)) */
     double inner_tol;
-    int inner_prec;  /* coupling precision of the inner solves (IGE_F64 .. IGE_BF16X3) */
+    int inner_prec;  /* precision of the inner solves (IGE_F64 .. IGE_BF16X3_ALL) */
 } ige_solve_opts;
 
 typedef struct {

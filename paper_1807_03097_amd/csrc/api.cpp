@@ -366,6 +366,7 @@ ige_op ige::assemble_on(ige_ctx ctx, const ige_geom_s *geom, const ige_params &p
             op->d_leafsgn.upload(A.leafsgn, s);
             op->d_red_ptr.upload(A.red_ptr, s);
             op->d_red_idx.upload(A.red_idx, s);
+            ige::plan_near_bf16(op, A.pair, A.leafdof, A.nF);
             op->d_bval.alloc(std::max<int64_t>(1, op->nnz));
             IGE_HIP(hipMemsetAsync(op->d_bval.p, 0, sizeof(double2) * op->nnz, s));
             op->d_npart.alloc(std::max<int64_t>(1, A.nslots()));
@@ -583,6 +584,9 @@ int ige_op_info(ige_op op, ige_op_info_t *out)
         b += op->d_nodeX.bytes() + op->d_nodeT.bytes() + op->d_G.bytes() + op->d_G32.bytes() + op->d_gpart.bytes() + op->d_gtmp.bytes();
         b += op->d_fpair.bytes() + op->d_fred_ptr.bytes() + op->d_fred_idx.bytes();
         b += op->d_Gb1.bytes() + op->d_Gb3.bytes() + op->d_vb.bytes() + op->d_bmpart.bytes();
+        b += op->d_nb3.bytes() + op->d_xnb.bytes() + op->d_nbpart.bytes() + op->d_nbwork.bytes();
+        b += op->d_nbpartner.bytes() + op->d_nbslot.bytes() + op->d_nborder.bytes() + op->d_nbred_ptr.bytes();
+        b += op->d_nbred_idx.bytes() + op->d_morder.bytes();
         b += op->d_Mp.bytes() * 3 + op->d_inc.bytes() + op->d_sing.bytes() + op->d_work.bytes();
         b += op->d_partner.bytes() + op->d_mom.bytes() + op->d_src.bytes() + op->d_loc.bytes() + op->d_part.bytes();
         b += op->d_x.bytes() + op->d_y.bytes() + op->d_V.bytes() + op->d_w.bytes() + op->d_r.bytes();
@@ -712,7 +716,7 @@ int apply_impl(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind, int
         IGE_REQUIRE(op && x && y && r >= 1, "bad apply arguments");
         IGE_REQUIRE(op->assembled, "operator was planned, not assembled");
         IGE_REQUIRE(ptr_kind == IGE_HOST || ptr_kind == IGE_DEVICE, "bad ptr_kind");
-        IGE_REQUIRE(prec >= IGE_F64 && prec <= IGE_BF16X3, "bad coupling precision");
+        IGE_REQUIRE(prec >= IGE_F64 && prec <= IGE_BF16X3_ALL, "bad coupling precision");
         set_device(op->ctx);
         const int64_t N = op->D.N;
         hipStream_t s = op->ctx->stream;
@@ -832,6 +836,9 @@ void gmres_batched(ige_op op, int r, const double2 *B, double2 *X, const std::ve
     std::vector<std::vector<Cx>> H(r, std::vector<Cx>((size_t)(m + 1) * m)), cs(r, std::vector<Cx>(m)),
         sn(r, std::vector<Cx>(m)), g(r, std::vector<Cx>(m + 1));
     while (true) {
+        bool budget = false;
+        for (int c = 0; c < r; ++c) budget = budget || out.iters[c] < it_cap[c];
+        if (!budget) return;   // every column used its iterations
         // V0 = B - A X
         apply_dev(op, r, X, W, prec);
         ige::launch_axpby(op, (int64_t)r * N, make_double2(1, 0), B, make_double2(0, 0), V);
@@ -937,7 +944,8 @@ int ige_solve(ige_op op, int r, const ige_c64 *f, ige_c64 *x, int ptr_kind, cons
         IGE_REQUIRE(ptr_kind == IGE_HOST || ptr_kind == IGE_DEVICE, "bad ptr_kind");
         IGE_REQUIRE(opts->restart >= 1 && opts->maxit >= 0 && std::isfinite(opts->tol) && opts->tol >= 0.0,
                     "bad solve options");
-        IGE_REQUIRE(!opts->refine || (opts->inner_prec >= IGE_F64 && opts->inner_prec <= IGE_BF16X3), "bad inner precision");
+        IGE_REQUIRE(!opts->refine || (opts->inner_prec >= IGE_F64 && opts->inner_prec <= IGE_BF16X3_ALL),
+                    "bad inner precision");
         IGE_REQUIRE(!opts->refine || (std::isfinite(opts->inner_tol) && opts->inner_tol > 0.0 && opts->inner_tol < 1.0),
                     "inner_tol must be in (0, 1)");
         set_device(op->ctx);
@@ -975,7 +983,10 @@ int ige_solve(ige_op op, int r, const ige_c64 *f, ige_c64 *x, int ptr_kind, cons
             ige::launch_norm2_b(op, r, F, op->d_red.p);
             IGE_HIP(hipMemcpyAsync(fn.data(), op->d_red.p, sizeof(double) * r, hipMemcpyDeviceToHost, s));
             IGE_HIP(hipStreamSynchronize(s));
-            for (int step = 0; step < 50; ++step) {
+            // each inner solve is one GMRES cycle at most: the restart is an outer step with
+            // the true FP64 residual, so a cycle never continues past the point where the
+            // inner operator's rounding stops the true inner residual from decreasing
+            for (int step = 0; step <= opts->maxit; ++step) {
                 apply_dev(op, r, X, op->d_r.p, IGE_F64);
                 ige::launch_axpby(op, (int64_t)r * N, make_double2(1, 0), F, make_double2(-1, 0), op->d_r.p);
                 std::vector<double> rn(r);
@@ -988,7 +999,7 @@ int ige_solve(ige_op op, int r, const ige_c64 *f, ige_c64 *x, int ptr_kind, cons
                 for (int c = 0; c < r; ++c) {
                     relres[c] = fn[c] > 0 ? rn[c] / fn[c] : 0.0;
                     const bool need = relres[c] > opts->tol && iters[c] < opts->maxit;
-                    cap[c] = need ? opts->maxit - iters[c] : 0;
+                    cap[c] = need ? std::min(opts->maxit - iters[c], opts->restart) : 0;
                     // the correction needs to reduce this residual only by tol / relres
                     // (with a margin of 1/2), and never by more than inner_tol
                     itol[c] = relres[c] > 0 ? std::max(opts->inner_tol, 0.5 * opts->tol / relres[c]) : opts->inner_tol;

@@ -624,8 +624,8 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
             }
         }
         mark(2);
-        if (prec == IGE_BF16 || prec == IGE_BF16X3) {
-            m2l_bf16(op, r, prec == IGE_BF16X3 ? 3 : 1, op->d_bsrc.p, s);
+        if (prec == IGE_BF16 || prec == IGE_BF16X3 || prec == IGE_BF16X3_ALL) {
+            m2l_bf16(op, r, prec == IGE_BF16 ? 1 : 3, op->d_bsrc.p, s);
             mark(3);
             hipLaunchKernelGGL(k_m2l_reduce_b<float2>, dim3(op->NC), dim3(256), 0, s, o, r, op->d_mwrk_of_tgt.p,
                                op->d_bmpart.p, op->d_bloc.p);
@@ -683,7 +683,8 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
         for (int i = 1; i <= 6; ++i) mark(i);
     }
     mark(7);
-    if (r >= 8 && near_mfma_mtw_ok(o.nF, o.rc)) near_batched_mfma(op, r, xt, yt, s);
+    if (prec == IGE_BF16X3_ALL) near_bf16(op, r, xt, yt, s);
+    else if (r >= 8 && near_mfma_mtw_ok(o.nF, o.rc)) near_batched_mfma(op, r, xt, yt, s);
     else near_batched(op, r, xt, yt, s);
     mark(11);
     mark(8);

@@ -1,0 +1,328 @@
+// Near-field product (a8) in split BF16 on the matrix cores, for the inner solves
+// of the mixed-precision iterative refinement (the near-field blocks themselves are
+// assembled in FP64 by the Galerkin quadrature of Sec. 3; this is a lower-precision
+// copy of them for the inner operator only).
+//
+// Every ordered leaf pair (t, s) of the near field gets its own block
+// A_ts = B_b (t = target leaf of the stored block b) or B_b^T (t = its source leaf),
+// stored as rows [Re | Im] over the slot index of s, zero padded to Qp (a multiple of
+// 32), each entry as a BF16 pair x = xh + xl.  For a target leaf t and its partners s:
+//   Y_t = sum_s A_ts X_s,  Yr += Ar Xr - Ai Xi,  Yi += Ai Xr + Ar Xi,
+// where each real product runs on the 16x16x32 BF16 instruction as xh.yh + xh.yl +
+// xl.yh with FP32 accumulation (about 2^-16 relative).  The right factors X_s are the
+// columns of x gathered to the function slots of leaf s (signs of the glued unknowns
+// are folded into the blocks).  Work: one workgroup per (target leaf, up to 8
+// partners, chunk of 16 NT columns), wave w owning row tiles w MTW .. w MTW + MTW - 1;
+// partial results per work item (FP32) are summed per unknown in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "op.hpp"
+
+namespace ige {
+
+namespace {
+
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+constexpr int kNearPartners = 8;   // partners per work item
+
+__device__ inline void split_pair(double x, __bf16 &hi, __bf16 &lo)
+{
+    hi = (__bf16)(float)x;
+    lo = (__bf16)(float)(x - (double)(float)hi);
+}
+
+__device__ inline bf8 neg8(bf8 x)
+{
+    uint4 u = __builtin_bit_cast(uint4, x);
+    u.x ^= 0x80008000u;
+    u.y ^= 0x80008000u;
+    u.z ^= 0x80008000u;
+    u.w ^= 0x80008000u;
+    return __builtin_bit_cast(bf8, u);
+}
+
+// Ab[2 b + ori][plane][Qp][2 Qp]: ori 0 row i = B_b[i][:], ori 1 row i = B_b[:][i]
+__global__ void k_nb_store(const double2 *bval, int64_t nblk, int nF, int Qp, __bf16 *Ab)
+{
+    const int K2 = 2 * Qp;
+    const int64_t per = (int64_t)Qp * Qp;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * nblk * per) return;
+    const int64_t po = t / per;
+    const int rem = (int)(t % per), i = rem / Qp, j = rem % Qp;
+    const int64_t b = po / 2;
+    const int ori = (int)(po % 2);
+    double2 v = make_double2(0.0, 0.0);
+    if (i < nF && j < nF) v = ori == 0 ? bval[((size_t)b * nF + i) * nF + j] : bval[((size_t)b * nF + j) * nF + i];
+    __bf16 *base = Ab + (size_t)po * 2 * Qp * K2;
+    const size_t ire = (size_t)i * K2 + j, iim = ire + Qp;
+    __bf16 h, l;
+    split_pair(v.x, h, l);
+    base[ire] = h;
+    base[(size_t)Qp * K2 + ire] = l;
+    split_pair(v.y, h, l);
+    base[iim] = h;
+    base[(size_t)Qp * K2 + iim] = l;
+}
+
+// Xb[leaf][chunk][plane][ncol][2 Qp]: column n of chunk ch is right-hand side
+// ch ncol + n; row k < Qp: Re x at slot k of the leaf, k >= Qp: Im x at slot k - Qp
+__global__ void k_xnb_prep(int64_t nleaf, int nF, int Qp, int r, int ncol, int nchunk, const int32_t *leafdof,
+                           const double2 *xt, __bf16 *Xb)
+{
+    const int K2 = 2 * Qp;
+    const int64_t per = (int64_t)ncol * K2;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nleaf * nchunk * per) return;
+    const int64_t lc = t / per;
+    const int rem = (int)(t % per), n = rem / K2, k = rem % K2;
+    const int64_t leaf = lc / nchunk;
+    const int ch = (int)(lc % nchunk), col = ch * ncol + n, j = k < Qp ? k : k - Qp;
+    double v = 0.0;
+    if (j < nF && col < r) {
+        const int d = leafdof[(size_t)leaf * nF + j];
+        if (d >= 0) {
+            const double2 x = xt[(size_t)d * r + col];
+            v = k < Qp ? x.x : x.y;
+        }
+    }
+    __bf16 h, l;
+    split_pair(v, h, l);
+    __bf16 *base = Xb + (size_t)lc * 2 * per;
+    base[rem] = h;
+    base[per + rem] = l;
+}
+
+template <int MTW, int NT>
+__global__ __launch_bounds__(256) void k_near_bx(int r, int nchunk, int Qp, int nF, int64_t nwork,
+                                                 const int32_t *order, const M2LWork *work, const int32_t *partner,
+                                                 const int32_t *aslot, const __bf16 *Ab, const __bf16 *Xb,
+                                                 float2 *part)
+{
+    constexpr int NCOL = 16 * NT;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int K2 = 2 * Qp, KS = Qp / 32, MTT = Qp / 16;
+    // the chunks of one work item share an XCD (consecutive ids go round-robin over 8)
+    const int64_t g = blockIdx.x;
+    const int64_t wo = (g / (8 * nchunk)) * 8 + g % 8;
+    const int ch = (int)((g / 8) % nchunk);
+    if (wo >= nwork) return;
+    const int64_t wi = order[wo];
+    const M2LWork wk = work[wi];
+    const size_t aper = (size_t)2 * Qp * K2, xper = (size_t)NCOL * K2;
+    f4 ar[MTW][NT], ai[MTW][NT];
+#pragma unroll
+    for (int a = 0; a < MTW; ++a)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            ar[a][t] = f4{0.f, 0.f, 0.f, 0.f};
+            ai[a][t] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+    for (int kp = wk.beg; kp < wk.end; ++kp) {
+        const __bf16 *As = Ab + (size_t)aslot[kp] * aper;
+        const __bf16 *Xs = Xb + ((size_t)partner[kp] * nchunk + ch) * 2 * xper;
+        for (int s = 0; s < KS; ++s) {
+            const int k = 32 * s + 8 * (lane >> 4);
+            bf8 xr[NT][2], xi[NT][2];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const __bf16 *xc = Xs + (size_t)(16 * t + (lane & 15)) * K2 + k;
+#pragma unroll
+                for (int pl = 0; pl < 2; ++pl) {
+                    xr[t][pl] = *reinterpret_cast<const bf8 *>(xc + pl * xper);
+                    xi[t][pl] = *reinterpret_cast<const bf8 *>(xc + pl * xper + Qp);
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < MTW; ++a) {
+                const int mt = wv * MTW + a;
+                if (mt >= MTT) break;   // uniform over the wave
+                const __bf16 *arow = As + (size_t)(16 * mt + (lane & 15)) * K2 + k;
+                bf8 br[2], bi[2], nb[2];
+#pragma unroll
+                for (int pl = 0; pl < 2; ++pl) {
+                    br[pl] = *reinterpret_cast<const bf8 *>(arow + pl * (size_t)Qp * K2);
+                    bi[pl] = *reinterpret_cast<const bf8 *>(arow + pl * (size_t)Qp * K2 + Qp);
+                    nb[pl] = neg8(bi[pl]);
+                }
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    // Yr += Ar Xr - Ai Xi
+                    ar[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(br[0], xr[t][0], ar[a][t], 0, 0, 0);
+                    ar[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(br[0], xr[t][1], ar[a][t], 0, 0, 0);
+                    ar[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(br[1], xr[t][0], ar[a][t], 0, 0, 0);
+                    ar[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nb[0], xi[t][0], ar[a][t], 0, 0, 0);
+                    ar[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nb[0], xi[t][1], ar[a][t], 0, 0, 0);
+                    ar[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nb[1], xi[t][0], ar[a][t], 0, 0, 0);
+                    // Yi += Ai Xr + Ar Xi
+                    ai[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bi[0], xr[t][0], ai[a][t], 0, 0, 0);
+                    ai[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bi[0], xr[t][1], ai[a][t], 0, 0, 0);
+                    ai[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bi[1], xr[t][0], ai[a][t], 0, 0, 0);
+                    ai[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(br[0], xi[t][0], ai[a][t], 0, 0, 0);
+                    ai[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(br[0], xi[t][1], ai[a][t], 0, 0, 0);
+                    ai[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(br[1], xi[t][0], ai[a][t], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // lane holds D[4 (lane/16) + j][lane % 16] of each tile
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int col = ch * NCOL + 16 * t + (lane & 15);
+        if (col >= r) continue;
+#pragma unroll
+        for (int a = 0; a < MTW; ++a) {
+            const int mt = wv * MTW + a;
+            if (mt >= MTT) break;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int m = 16 * mt + 4 * (lane >> 4) + j;
+                if (m < nF) part[((size_t)wi * nF + m) * r + col] = make_float2(ar[a][t][j], ai[a][t][j]);
+            }
+        }
+    }
+}
+
+// yt[i][c] = sum of the partial results of unknown i (list order), one thread per (i, c)
+__global__ void k_nb_gather(int64_t N, int r, const int64_t *ptr, const int32_t *idx, const float2 *part, double2 *yt)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N * r) return;
+    const int64_t i = t / r;
+    const int c = (int)(t % r);
+    double re = 0.0, im = 0.0;
+    for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) {
+        const float2 v = part[(size_t)idx[k] * r + c];
+        re += v.x;
+        im += v.y;
+    }
+    yt[t] = make_double2(re, im);
+}
+
+int near_qp(int nF) { return 32 * ((nF + 31) / 32); }
+
+}  // namespace
+
+void plan_near_bf16(ige_op op, const std::vector<int32_t> &pair, const std::vector<int32_t> &leafdof, int nF)
+{
+    const int64_t nblk = (int64_t)pair.size() / 2;
+    const int64_t nleaf = nF > 0 ? (int64_t)leafdof.size() / nF : 0;
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> lst(nleaf);   // per target: (source leaf, block slot)
+    for (int64_t b = 0; b < nblk; ++b) {
+        const int lt = pair[2 * b], ls = pair[2 * b + 1];
+        lst[lt].push_back({ls, (int32_t)(2 * b)});
+        if (lt != ls) lst[ls].push_back({lt, (int32_t)(2 * b + 1)});
+    }
+    std::vector<M2LWork> work;
+    std::vector<int32_t> partner, aslot;
+    for (int64_t t = 0; t < nleaf; ++t) {
+        std::sort(lst[t].begin(), lst[t].end());
+        const int beg = (int)partner.size();
+        for (const auto &e : lst[t]) {
+            partner.push_back(e.first);
+            aslot.push_back(e.second);
+        }
+        for (int b = beg; b < (int)partner.size(); b += kNearPartners)
+            work.push_back({(int32_t)t, b, std::min((int)partner.size(), b + kNearPartners)});
+    }
+    std::vector<int32_t> order(work.size());
+    for (size_t w = 0; w < order.size(); ++w) order[w] = (int32_t)w;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return work[a].end - work[a].beg > work[b].end - work[b].beg;
+    });
+    // per unknown: the partial-result rows (work item, slot) that hold it, in order
+    const int64_t N = op->D.N;
+    std::vector<int64_t> ptr(N + 1, 0);
+    for (const auto &w : work)
+        for (int j = 0; j < nF; ++j) {
+            const int d = leafdof[(size_t)w.tgt * nF + j];
+            if (d >= 0) ptr[d + 1]++;
+        }
+    for (int64_t i = 0; i < N; ++i) ptr[i + 1] += ptr[i];
+    std::vector<int32_t> idx(ptr[N]);
+    std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+    for (size_t w = 0; w < work.size(); ++w)
+        for (int j = 0; j < nF; ++j) {
+            const int d = leafdof[(size_t)work[w].tgt * nF + j];
+            if (d >= 0) idx[fill[d]++] = (int32_t)(w * nF + j);
+        }
+    hipStream_t s = op->ctx->stream;
+    op->nb_nwork = (int64_t)work.size();
+    op->d_nbwork.upload(work, s);
+    op->d_nbpartner.upload(partner, s);
+    op->d_nbslot.upload(aslot, s);
+    op->d_nborder.upload(order, s);
+    op->d_nbred_ptr.upload(ptr, s);
+    op->d_nbred_idx.upload(idx, s);
+}
+
+void ensure_near_bf16(ige_op op)
+{
+    if (op->d_nb3.p || op->view.nblk == 0) return;
+    const DevOp &o = op->view;
+    const int Qp = near_qp(o.nF);
+    op->d_nb3.alloc((size_t)2 * o.nblk * 2 * Qp * 2 * Qp);
+    const int64_t n = 2 * o.nblk * (int64_t)Qp * Qp;
+    hipLaunchKernelGGL(k_nb_store, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, op->ctx->stream, o.bval, o.nblk,
+                       o.nF, Qp, op->d_nb3.p);
+    IGE_HIP(hipGetLastError());
+}
+
+int near_bf16_ok(int nF) { return near_qp(nF) / 16 <= 4 * 4; }
+
+namespace {
+template <int MTW, int NT>
+void launch_bx(ige_op op, int r, int nchunk, int Qp, hipStream_t s)
+{
+    const DevOp &o = op->view;
+    const int64_t nw = op->nb_nwork;
+    if (nw == 0) return;
+    const dim3 grid((unsigned)(((nw + 7) / 8) * 8 * nchunk)), blk(256);
+    hipLaunchKernelGGL((k_near_bx<MTW, NT>), grid, blk, 0, s, r, nchunk, Qp, o.nF, nw, op->d_nborder.p,
+                       op->d_nbwork.p, op->d_nbpartner.p, op->d_nbslot.p, op->d_nb3.p, op->d_xnb.p, op->d_nbpart.p);
+    IGE_HIP(hipGetLastError());
+}
+
+template <int MTW>
+void launch_bx_nt(ige_op op, int r, int NT, int nchunk, int Qp, hipStream_t s)
+{
+    switch (NT) {
+        case 1: launch_bx<MTW, 1>(op, r, nchunk, Qp, s); break;
+        case 2: launch_bx<MTW, 2>(op, r, nchunk, Qp, s); break;
+        default: launch_bx<MTW, 4>(op, r, nchunk, Qp, s); break;
+    }
+}
+}  // namespace
+
+void near_bf16(ige_op op, int r, const double2 *xt, double2 *yt, hipStream_t s)
+{
+    const DevOp &o = op->view;
+    IGE_REQUIRE(near_bf16_ok(o.nF), "near-field blocks too large for the split-BF16 product");
+    ensure_near_bf16(op);
+    const int Qp = near_qp(o.nF), MTT = Qp / 16, MTW = (MTT + 3) / 4;
+    const int NT = r > 32 ? 4 : (r > 16 ? 2 : 1), ncol = 16 * NT, nchunk = (r + ncol - 1) / ncol;
+    const int64_t nleaf = (int64_t)o.P * o.SL * o.SL;
+    const size_t xn = (size_t)nleaf * nchunk * 2 * ncol * 2 * Qp;
+    if (op->d_xnb.n < xn) op->d_xnb.alloc(xn);
+    const size_t pn = (size_t)op->nb_nwork * o.nF * r;
+    if (op->d_nbpart.n < pn) op->d_nbpart.alloc(pn);
+    const int64_t nx = (int64_t)nleaf * nchunk * ncol * 2 * Qp;
+    hipLaunchKernelGGL(k_xnb_prep, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, s, nleaf, o.nF, Qp, r, ncol,
+                       nchunk, o.leafdof, xt, op->d_xnb.p);
+    IGE_HIP(hipGetLastError());
+    switch (MTW) {
+        case 1: launch_bx_nt<1>(op, r, NT, nchunk, Qp, s); break;
+        case 2: launch_bx_nt<2>(op, r, NT, nchunk, Qp, s); break;
+        case 3: launch_bx_nt<3>(op, r, NT, nchunk, Qp, s); break;
+        default: launch_bx_nt<4>(op, r, NT, nchunk, Qp, s); break;
+    }
+    const int64_t tot = (int64_t)o.N * r;
+    hipLaunchKernelGGL(k_nb_gather, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, (int64_t)o.N, r,
+                       op->d_nbred_ptr.p, op->d_nbred_idx.p, op->d_nbpart.p, yt);
+    IGE_HIP(hipGetLastError());
+}
+
+}  // namespace ige

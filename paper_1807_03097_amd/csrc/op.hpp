@@ -131,6 +131,15 @@ struct ige_op_s {
     ige::DBuf<int32_t> d_mpartner, d_gslot, d_mwrk_of_tgt;
     ige::DBuf<float2> d_bmpart;          // matrix-core coupling partials [mwork][4][Q][r]
     ige::DBuf<int32_t> d_morder;         // work items by decreasing partner count
+    // split-BF16 near-field product (inner solves): blocks per ordered leaf pair,
+    // gathered right factors, work items (target leaf, partners), FP32 partials and
+    // per-unknown reduction lists
+    ige::DBuf<__bf16> d_nb3, d_xnb;
+    ige::DBuf<float2> d_nbpart;
+    ige::DBuf<ige::M2LWork> d_nbwork;
+    ige::DBuf<int32_t> d_nbpartner, d_nbslot, d_nborder, d_nbred_idx;
+    ige::DBuf<int64_t> d_nbred_ptr;
+    int64_t nb_nwork = 0;
     // apply workspaces (one right-hand side at a time)
     ige::DBuf<double2> d_mom;    // [NC][3][Q]   s^1, s^2, d
     ige::DBuf<double2> d_src;    // [NC][4][Q]   v_x, v_y, v_z, d
@@ -187,6 +196,11 @@ void m2l_stored_reduce_one(ige_op op);
 // fields [NC][4][Q][r] -> partials per work item [mwork][4][Q][r] (d_bmpart)
 void m2l_bf16(ige_op op, int r, int split, const double2 *src, hipStream_t s);
 void ensure_coupling_bf16(ige_op op, int split);
+// split-BF16 near-field product (yt = near part of A x, [N][r] layout)
+void plan_near_bf16(ige_op op, const std::vector<int32_t> &pair, const std::vector<int32_t> &leafdof, int nF);
+void ensure_near_bf16(ige_op op);
+int near_bf16_ok(int nF);
+void near_bf16(ige_op op, int r, const double2 *xt, double2 *yt, hipStream_t s);
 void launch_m2l_reduce(ige_op op);
 void launch_l2l(ige_op op);
 // near-field product; records mid (if given) between the block pass and the reduction
