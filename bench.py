@@ -33,6 +33,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
+BF16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix cores
 
 
 def parse():
@@ -276,7 +277,7 @@ def main():
     from paper_1807_03097_amd import binding as B
     from paper_1807_03097_amd import workloads as W
 
-    p, m, kappa, q, eta, d = 2, args.level, 8.0, 8, args.eta, args.leaf_depth
+    p, m, kappa, q, eta, d = 2, args.level, args.kappa, 8, args.eta, args.leaf_depth
     pats = W.cube_sphere()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -317,7 +318,7 @@ def main():
     wall = time.perf_counter() - w0
     ms_step = ev0.elapsed_time(ev1) / args.steps
     stages = op.stage_times()
-    names = ["p2m", "m2m", "m2l", "m2l_reduce", "l2l", "near_spmv", "l2p", "near_blk"]
+    names = ["p2m", "m2m", "m2l", "m2l_reduce", "l2l", "near_spmv", "l2p", "near_blk", "m2l_kernel"]
     st = {n: float(v) for n, v in zip(names, stages)}
     log("stage ms: " + " ".join(f"{k}={v:.4f}" for k, v in st.items()) + f"  step={ms_step:.4f} ms wall/step={1e3 * wall / args.steps:.4f}")
 
@@ -325,9 +326,29 @@ def main():
     traffic_ref = load_traffic(r)
 
     def roofline(stage_ms):
-        stages = {k: v for k, v in stage_ms.items() if k != "near_blk"}
+        stages = {k: v for k, v in stage_ms.items() if k not in ("near_blk", "m2l_kernel")}
         dom = max(stages, key=stages.get)
         Q = (q + 1) ** 2
+        if dom == "near_spmv" and r > 1:
+            # many columns: matrix-core products over every ordered leaf pair (block and
+            # transposed block), the whole near-field stage timed (operands, product, sum)
+            s_el = 2 ** (m - info.leaf_level)
+            W_ = s_el + p
+            nF = 2 * W_ * (W_ - 1)
+            t_ms = stage_ms["near_blk"]
+            if args.prec == 4:
+                Qn = 32 * ((nF + 31) // 32)
+                ncol = 64 if r > 32 else (32 if r > 16 else 16)
+                issued = info.near_leaf_pairs * (-(-r // ncol)) * 12 * 2.0 * Qn * Qn * ncol
+                ach = issued / (t_ms * 1e-3) / 1e12
+                return {"kernel": "k_near_bx", "bound": "mfma", "achieved": ach, "peak": BF16_MFMA_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": ach / BF16_MFMA_PEAK_TFLOPS, "traffic": None,
+                        "issued_flop": issued, "avg_ms": t_ms}
+            flops = info.near_leaf_pairs * nF * nF * 8.0 * r
+            ach = flops / (t_ms * 1e-3) / 1e12
+            return {"kernel": "k_near_mfma", "bound": "mfma", "achieved": ach, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                    "flop": flops, "avg_ms": t_ms}
         if dom == "near_spmv":
             # the block pass: stored block entries (16 B each) streamed once per pass
             # of up to 4 columns, x read once per column
@@ -348,7 +369,30 @@ def main():
                 "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
                 "node_pairs": int(entries), "avg_ms": stage_ms[dom]}
 
+    def roofline_coupling(stage_ms):
+        """Matrix-core coupling (r > 1, BF16 precisions): issued BF16 matrix-core
+        operations of the real product [[Gr,-Gi],[Gi,Gr]] . [Re V; Im V] over padded
+        2Qp x 2Qp blocks and column chunks, over the kernel's own time."""
+        if args.prec < 2 or r == 1:
+            return None
+        Q = (q + 1) ** 2
+        Qp = 32 * ((Q + 31) // 32)
+        MT, split = Qp // 16, (1 if args.prec == 2 else 3)
+        cap = (64 if split == 3 else 128) if MT >= 8 else (128 if MT >= 6 else 256)
+        ncol = 16
+        while ncol < 4 * r and ncol < cap:
+            ncol *= 2
+        nchunk = -(-r // (ncol // 4))
+        issued = info.far_pairs * nchunk * 2.0 * (2 * Qp) * (2 * Qp) * ncol * split
+        useful = info.far_pairs * 8.0 * Q * Q * 4 * r
+        t_ms = stage_ms["m2l_kernel"]
+        ach = issued / (t_ms * 1e-3) / 1e12
+        return {"kernel": "k_m2l_mx", "bound": "mfma", "achieved": ach, "peak": BF16_MFMA_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": ach / BF16_MFMA_PEAK_TFLOPS, "traffic": None,
+                "useful_tflops": useful / (t_ms * 1e-3) / 1e12, "issued_flop": issued, "avg_ms": t_ms}
+
     roof = roofline(st)
+    roof_cpl = roofline_coupling(st)
     # the same kernels timed in isolation (stages in order on one stream)
     op.set_overlap(False)
     op.set_profiling(True)
@@ -394,6 +438,7 @@ def main():
         "assemble_s": t_asm,
         "roofline": roof,
         "roofline_isolated": roof_iso,
+        "roofline_coupling": roof_cpl,
         "stage_ms_isolated": st_iso,
         "cpu_baseline": cpu,
         "parity_sampled_rel_err": parity,

@@ -181,7 +181,9 @@ int ige_apply_prec(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind,
  * stream and returns the average device time (ms) per stage over the last (up to
  * 256) recorded applies: 0 P2M, 1 M2M, 2 M2L, 3 M2L reduce, 4 L2L, 5 near-field
  * product (block pass and reduction), 6 L2P, 7 the block pass alone (the whole
- * near-field product for r > 1).  n: capacity of ms[]; returns the stage count (8). */
+ * near-field product for r > 1), 8 the coupling product alone (stage 2 without the
+ * conversion of the source fields to the matrix-core operand layout).  n: capacity of
+ * ms[]; returns the stage count (9). */
 int ige_op_set_profiling(ige_op op, int on);
 
 /* Scheduling knob: on (default) runs the near-field product on a second stream
@@ -205,7 +207,11 @@ typedef struct {
                         residual f - A x, inner GMRES on the inner_prec operator for the
                         correction, x += correction, repeated; each inner solve is at most
                         one GMRES cycle (restart iterations) and stops when its residual
-                        estimate is reduced by max(inner_tol, tol / (2 * current relres)) */
+                        estimate is reduced by max(inner_tol, tol / (2 * current relres));
+                        a step that reduces the FP64 residual by less than 1/2 while its
+                        inner solve claimed twice as much is undone on the columns that
+                        got worse and the inner precision moves towards FP64
+                        (IGE_BF16X3_ALL or IGE_BF16 -> IGE_BF16X3 -> IGE_F64) */
     double inner_tol;
     int inner_prec;  /* precision of the inner solves (IGE_F64 .. IGE_BF16X3_ALL) */
 } ige_solve_opts;

@@ -206,8 +206,8 @@ def ige_op_set_overlap(op, on):
 
 
 def ige_op_stage_times(op):
-    ms = np.zeros(8)
-    n = _check(_lib.ige_op_stage_times(op, _ptr(ms), 8))
+    ms = np.zeros(9)
+    n = _check(_lib.ige_op_stage_times(op, _ptr(ms), 9))
     return ms[:n]
 
 

@@ -8,6 +8,7 @@
 #include <complex>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <new>
 #include <string>
 #include <unordered_map>
@@ -50,7 +51,7 @@ std::complex<double> cz(double2 a) { return {a.x, a.y}; }
 // kProfSlots event sets on the stream each stage runs on (no host sync).
 void apply_one(ige_op op, const double2 *x, double2 *y, int prec = IGE_F64)
 {
-    hipStream_t s = op->ctx->stream, s2 = op->aux;
+    hipStream_t s = ige::lstream(op), s2 = op->aux;
     const bool prof = op->profiling;
     hipEvent_t *ev = prof ? op->prof_ev.data() + (size_t)(op->prof_count % ige_op_s::kProfSlots) * ige_op_s::kProfEv
                           : nullptr;
@@ -65,6 +66,7 @@ void apply_one(ige_op op, const double2 *x, double2 *y, int prec = IGE_F64)
             mark(1, s);
             ige::launch_m2m(op);
             mark(2, s);
+            mark(12, s);
             ige::launch_m2l(op, prec);
             mark(3, s);
             ige::launch_m2l_reduce(op);
@@ -84,7 +86,7 @@ void apply_one(ige_op op, const double2 *x, double2 *y, int prec = IGE_F64)
         }
         if (prof) {
             if (!far)
-                for (int i : {0, 1, 2, 3, 4, 5, 6, 9, 10}) mark(i, s);
+                for (int i : {0, 1, 2, 3, 4, 5, 6, 9, 10, 12}) mark(i, s);
             op->prof_count++;
         }
         return;
@@ -102,6 +104,7 @@ void apply_one(ige_op op, const double2 *x, double2 *y, int prec = IGE_F64)
     ige::launch_spmv(op, x, y, s2, prof ? ev[11] : nullptr);
     mark(8, s2);
     IGE_HIP(hipEventRecord(op->ev_join, s2));
+    mark(12, s);
     ige::launch_m2l(op, prec);
     mark(3, s);
     ige::launch_m2l_reduce(op);
@@ -557,6 +560,7 @@ int ige_op_destroy(ige_op op)
             (void)hipStreamSynchronize(op->aux);
             (void)hipStreamDestroy(op->aux);
         }
+        if (op->gstream) (void)hipStreamDestroy(op->gstream);
         if (op->ev_fork) (void)hipEventDestroy(op->ev_fork);
         if (op->ev_join) (void)hipEventDestroy(op->ev_join);
         delete op;
@@ -646,7 +650,7 @@ int ige_op_stage_times(ige_op op, double *ms, int n)
     int cnt = 0;
     int rc = guard([&] {
         IGE_REQUIRE(op && ms, "null argument");
-        const int nst = 8;
+        const int nst = 9;
         for (int i = 0; i < std::min(n, nst); ++i) ms[i] = 0.0;
         const int64_t k = std::min<int64_t>(op->prof_count, ige_op_s::kProfSlots);
         if (k > 0) {
@@ -654,7 +658,7 @@ int ige_op_stage_times(ige_op op, double *ms, int n)
             IGE_HIP(hipStreamSynchronize(op->ctx->stream));
             IGE_HIP(hipStreamSynchronize(op->aux));
             // stage -> (begin event, end event); L2P = leaf part + gather part
-            const int pairs[8][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}, {7, 8}, {5, 6}, {7, 11}};
+            const int pairs[9][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}, {7, 8}, {5, 6}, {7, 11}, {12, 3}};
             for (int64_t sl = 0; sl < k; ++sl) {
                 hipEvent_t *ev = op->prof_ev.data() + sl * ige_op_s::kProfEv;
                 for (int i = 0; i < std::min(n, nst); ++i) {
@@ -695,19 +699,98 @@ void ensure_batched(ige_op op, int r)
 }  // namespace
 
 namespace {
-// y = A x for r device columns ([r][N]) in the given coupling precision
-void apply_dev(ige_op op, int r, const double2 *x, double2 *y, int prec)
+// A captured HIP graph of the operator body (every kernel of one apply between the
+// copy of x into the op's own input buffer and the copy of the result out of its
+// output buffer) for one column count and precision.  The first apply with a new
+// (r, prec) runs eagerly (it sizes every buffer and makes the one-time BF16 copies),
+// the second is captured, later ones replay it: one launch instead of one per kernel.
+// Valid while the op's buffers keep their size, i.e. within one solve.
+struct ApplyGraph {
+    int r = -1, prec = -1, eager = 0;
+    hipGraphExec_t exec = nullptr;
+    void reset()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        exec = nullptr;
+        eager = 0;
+    }
+    ~ApplyGraph() { reset(); }
+};
+
+bool graphs_enabled()
 {
+    const char *e = std::getenv("IGE_GRAPH");
+    return !e || std::string(e) != "0";
+}
+
+void run_graph(ige_op op, ApplyGraph *g, int r, int prec, const std::function<void()> &body)
+{
+    hipStream_t s = op->ctx->stream;
+    if (g->exec && g->r == r && g->prec == prec) {
+        IGE_HIP(hipGraphLaunch(g->exec, s));
+        return;
+    }
+    if (g->r != r || g->prec != prec) {
+        g->reset();
+        g->r = r;
+        g->prec = prec;
+    }
+    if (g->eager == 0) {
+        g->eager = 1;
+        body();
+        return;
+    }
+    if (!op->gstream) IGE_HIP(hipStreamCreateWithFlags(&op->gstream, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    IGE_HIP(hipStreamBeginCapture(op->gstream, hipStreamCaptureModeThreadLocal));
+    op->lst = op->gstream;
+    try {
+        body();
+    } catch (...) {
+        op->lst = nullptr;
+        (void)hipStreamEndCapture(op->gstream, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        throw;
+    }
+    op->lst = nullptr;
+    IGE_HIP(hipStreamEndCapture(op->gstream, &graph));
+    const hipError_t e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    IGE_HIP(e);
+    IGE_HIP(hipGraphLaunch(g->exec, s));
+}
+
+// y = A x for r device columns ([r][N]) in the given precision; with g, the operator
+// body runs as a captured graph (not while profiling)
+void apply_dev(ige_op op, int r, const double2 *x, double2 *y, int prec, ApplyGraph *g = nullptr)
+{
+    const bool graph = g && !op->profiling && graphs_enabled();
+    hipStream_t s = op->ctx->stream;
+    const int64_t N = op->D.N;
     if (r == 1 && prec <= IGE_F32) {
-        apply_one(op, x, y, prec);
+        if (!graph) {
+            apply_one(op, x, y, prec);
+            return;
+        }
+        ensure_staging(op);
+        IGE_HIP(hipMemcpyAsync(op->d_x.p, x, sizeof(double2) * N, hipMemcpyDeviceToDevice, s));
+        run_graph(op, g, r, prec, [&] { apply_one(op, op->d_x.p, op->d_y.p, prec); });
+        IGE_HIP(hipMemcpyAsync(y, op->d_y.p, sizeof(double2) * N, hipMemcpyDeviceToDevice, s));
         return;
     }
     ensure_batched(op, r);
-    hipEvent_t *ev = op->profiling
-                         ? op->prof_ev.data() + (size_t)(op->prof_count % ige_op_s::kProfSlots) * ige_op_s::kProfEv
-                         : nullptr;
-    ige::apply_batched(op, r, x, y, op->d_bxt.p, op->d_byt.p, ev, prec);
-    if (ev) op->prof_count++;
+    if (!graph) {
+        hipEvent_t *ev = op->profiling
+                             ? op->prof_ev.data() + (size_t)(op->prof_count % ige_op_s::kProfSlots) * ige_op_s::kProfEv
+                             : nullptr;
+        ige::apply_batched(op, r, x, y, op->d_bxt.p, op->d_byt.p, ev, prec);
+        if (ev) op->prof_count++;
+        return;
+    }
+    ige::batched_to_rows(op, r, x, op->d_bxt.p, s);
+    run_graph(op, g, r, prec,
+              [&] { ige::apply_batched(op, r, nullptr, nullptr, op->d_bxt.p, op->d_byt.p, nullptr, prec); });
+    ige::batched_to_cols(op, r, op->d_byt.p, y, s);
 }
 
 int apply_impl(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind, int prec)
@@ -830,6 +913,7 @@ void gmres_batched(ige_op op, int r, const double2 *B, double2 *X, const std::ve
         IGE_HIP(hipMemcpyAsync(dst, v.data(), sizeof(int) * r, hipMemcpyHostToDevice, s));
         IGE_HIP(hipStreamSynchronize(s));   // v leaves scope
     };
+    ApplyGraph ag;
     const std::vector<double> bnorm = norms(B);
     out.iters.assign(r, 0);
     out.relres_est.assign(r, 0.0);
@@ -840,7 +924,7 @@ void gmres_batched(ige_op op, int r, const double2 *B, double2 *X, const std::ve
         for (int c = 0; c < r; ++c) budget = budget || out.iters[c] < it_cap[c];
         if (!budget) return;   // every column used its iterations
         // V0 = B - A X
-        apply_dev(op, r, X, W, prec);
+        apply_dev(op, r, X, W, prec, &ag);
         ige::launch_axpby(op, (int64_t)r * N, make_double2(1, 0), B, make_double2(0, 0), V);
         ige::launch_axpby(op, (int64_t)r * N, make_double2(-1, 0), W, make_double2(1, 0), V);
         std::vector<double> beta = norms(V);
@@ -864,7 +948,7 @@ void gmres_batched(ige_op op, int r, const double2 *B, double2 *X, const std::ve
         upload_mask(run, op->d_grun.p);
         for (int jj = 0; jj < m; ++jj) {
             double2 *Vj = V + (size_t)jj * r * N, *Vj1 = V + (size_t)(jj + 1) * r * N;
-            apply_dev(op, r, Vj, Vj1, prec);
+            apply_dev(op, r, Vj, Vj1, prec, &ag);
             // Gram-Schmidt pass 1 on the running columns, pass 2 where it lost more than half
             ige::launch_gs_dots(s, gp, N, r, V, jj + 1, Vj1, op->d_grun.p, op->d_gspart.p, h1, hs, nb);
             ige::launch_gs_update(s, gp, N, r, V, jj + 1, h1, hs, -1.0, op->d_grun.p, Vj1, split, op->d_gnp.p);
@@ -986,13 +1070,46 @@ int ige_solve(ige_op op, int r, const ige_c64 *f, ige_c64 *x, int ptr_kind, cons
             // each inner solve is one GMRES cycle at most: the restart is an outer step with
             // the true FP64 residual, so a cycle never continues past the point where the
             // inner operator's rounding stops the true inner residual from decreasing
+            ApplyGraph ag64;
+            // inner precision in use; a refinement step whose FP64 residual contracts by
+            // less than 1/2 while the inner solve claimed at least twice as much is limited
+            // by the inner operator's error: its growing columns are undone and the inner
+            // precision moves one rung towards FP64 (split near field -> split coupling -> FP64)
+            int cur = opts->inner_prec;
+            std::vector<double> prev(r, 0.0), est(r, 0.0), undo(r, 0.0);
+            std::vector<int> lastcap(r, 0);
             for (int step = 0; step <= opts->maxit; ++step) {
-                apply_dev(op, r, X, op->d_r.p, IGE_F64);
+                apply_dev(op, r, X, op->d_r.p, IGE_F64, &ag64);
                 ige::launch_axpby(op, (int64_t)r * N, make_double2(1, 0), F, make_double2(-1, 0), op->d_r.p);
                 std::vector<double> rn(r);
                 ige::launch_norm2_b(op, r, op->d_r.p, op->d_red.p);
                 IGE_HIP(hipMemcpyAsync(rn.data(), op->d_red.p, sizeof(double) * r, hipMemcpyDeviceToHost, s));
                 IGE_HIP(hipStreamSynchronize(s));
+                if (cur != IGE_F64) {
+                    bool bad = false, back = false;
+                    for (int c = 0; c < r; ++c) {
+                        undo[c] = 0.0;
+                        if (lastcap[c] == 0 || prev[c] <= 0.0) continue;
+                        const double ratio = (fn[c] > 0 ? rn[c] / fn[c] : 0.0) / prev[c];
+                        if (ratio > 0.5 && ratio > 2.0 * est[c]) {
+                            bad = true;
+                            if (ratio > 1.0) {
+                                undo[c] = -1.0;
+                                back = true;
+                            }
+                        }
+                    }
+                    std::fill(lastcap.begin(), lastcap.end(), 0);
+                    if (bad) {
+                        cur = cur == IGE_BF16X3_ALL || cur == IGE_BF16 ? IGE_BF16X3 : IGE_F64;
+                        if (back) {   // x_c -= correction_c on the columns that got worse
+                            IGE_HIP(hipMemcpyAsync(op->d_scal.p, undo.data(), sizeof(double) * r, hipMemcpyHostToDevice, s));
+                            ige::launch_axpy_cols(op, r, op->d_scal.p, op->d_D.p, X);
+                            IGE_HIP(hipStreamSynchronize(s));
+                            continue;   // recompute the residual of the restored columns
+                        }
+                    }
+                }
                 bool any = false;
                 std::vector<int> cap(r);
                 std::vector<double> itol(r);
@@ -1009,11 +1126,14 @@ int ige_solve(ige_op op, int r, const ige_c64 *f, ige_c64 *x, int ptr_kind, cons
                 if (!any) break;
                 IGE_HIP(hipMemsetAsync(op->d_D.p, 0, sizeof(double2) * r * N, s));
                 // columns already converged get an inner budget of 0 and a zero correction
-                gmres_batched(op, r, op->d_r.p, op->d_D.p, itol, opts->restart, cap, opts->inner_prec, go);
+                gmres_batched(op, r, op->d_r.p, op->d_D.p, itol, opts->restart, cap, cur, go);
                 ige::launch_axpby(op, (int64_t)r * N, make_double2(1, 0), op->d_D.p, make_double2(1, 0), X);
                 for (int c = 0; c < r; ++c) {
                     iters[c] += go.iters[c];
                     if (cap[c] > 0) outer[c]++;
+                    prev[c] = relres[c];
+                    est[c] = go.relres_est[c];
+                    lastcap[c] = cap[c];
                 }
             }
         }

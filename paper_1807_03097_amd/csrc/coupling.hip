@@ -399,7 +399,7 @@ void store_coupling(ige_op op)
     const DevOp &o = op->view;
     const int64_t n = op->nfp * o.Q * o.Q;
     if (n == 0) return;
-    hipLaunchKernelGGL(k_g_store, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, op->ctx->stream, o, op->nfp,
+    hipLaunchKernelGGL(k_g_store, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, lstream(op), o, op->nfp,
                        op->d_fpair.p, op->d_G.p);
     IGE_HIP(hipGetLastError());
 }
@@ -409,7 +409,7 @@ void ensure_coupling32(ige_op op)
     const int64_t n = op->nfp * op->view.Q * op->view.Q;
     if (op->d_G32.p || n == 0) return;
     op->d_G32.alloc(n);
-    hipLaunchKernelGGL(k_g_to32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, op->ctx->stream, n, op->d_G.p,
+    hipLaunchKernelGGL(k_g_to32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, lstream(op), n, op->d_G.p,
                        op->d_G32.p);
     IGE_HIP(hipGetLastError());
 }
@@ -420,7 +420,7 @@ void m2l_t_launch(ige_op op, const TG *G)
 {
     const DevOp &o = op->view;
     const dim3 grid((unsigned)op->nfp), blk(256);
-    hipStream_t s = op->ctx->stream;
+    hipStream_t s = lstream(op);
     const double2 *src = op->d_src.p;
     double2 *part = op->d_gpart.p;
     switch ((o.Q + 31) / 32) {
@@ -445,7 +445,7 @@ void m2l_stored_one(ige_op op, int prec)
     }
 }
 
-void m2l_stored_reduce_one(ige_op op) { m2l_reduce_pass<1>(op, 1, 0, op->d_loc.p, op->ctx->stream); }
+void m2l_stored_reduce_one(ige_op op) { m2l_reduce_pass<1>(op, 1, 0, op->d_loc.p, lstream(op)); }
 
 int coupling_split() { return kSplit; }
 

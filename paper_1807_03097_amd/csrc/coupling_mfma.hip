@@ -336,7 +336,7 @@ void launch_mx_mt(ige_op op, int r, int MT, int ncol, const __bf16 *G, const __b
 
 }  // namespace
 
-void m2l_bf16(ige_op op, int r, int split, const double2 *src, hipStream_t s)
+void m2l_bf16(ige_op op, int r, int split, const double2 *src, hipStream_t s, hipEvent_t mid)
 {
     const DevOp &o = op->view;
     if (op->mwork.empty()) return;
@@ -353,6 +353,7 @@ void m2l_bf16(ige_op op, int r, int split, const double2 *src, hipStream_t s)
     hipLaunchKernelGGL(k_vb_prep, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s, o, op->NC, r, rc, nchunk, ncol,
                        Qp, split, src, op->d_vb.p);
     IGE_HIP(hipGetLastError());
+    if (mid) IGE_HIP(hipEventRecord(mid, s));
     if (split == 3) launch_mx_mt<3>(op, r, MT, ncol, op->d_Gb3.p, op->d_vb.p, s);
     else launch_mx_mt<1>(op, r, MT, ncol, op->d_Gb1.p, op->d_vb.p, s);
 }

@@ -1301,7 +1301,7 @@ void launch_element_data(ige_op op)
     const DevOp &o = op->view;
     const int64_t E = (int64_t)o.P * o.n * o.n;
     const int threads = 64;
-    hipStream_t s = op->ctx->stream;
+    hipStream_t s = lstream(op);
     switch (o.p) {
         case 1: hipLaunchKernelGGL(k_element_data<4>, dim3(E), dim3(threads), 0, s, o, op->d_eX.p, op->d_ePsi.p, op->d_ePsiF.p, op->d_eC.p); break;
         case 2: hipLaunchKernelGGL(k_element_data<12>, dim3(E), dim3(threads), 0, s, o, op->d_eX.p, op->d_ePsi.p, op->d_ePsiF.p, op->d_eC.p); break;
@@ -1314,7 +1314,7 @@ void launch_node_geometry(ige_op op)
 {
     const DevOp &o = op->view;
     const int64_t tot = (int64_t)op->NC * o.Q;
-    hipLaunchKernelGGL(k_node_geometry, dim3((tot + 255) / 256), dim3(256), 0, op->ctx->stream, o, op->NC,
+    hipLaunchKernelGGL(k_node_geometry, dim3((tot + 255) / 256), dim3(256), 0, lstream(op), o, op->NC,
                        op->d_nodeX.p, op->d_nodeT.p);
     IGE_LAUNCH_CHECK();
 }
@@ -1330,7 +1330,7 @@ template <int NL>
 void launch_near_regular_nl(ige_op op, dim3 grid, size_t shm, int sb)
 {
     const DevOp &o = op->view;
-    hipStream_t s = op->ctx->stream;
+    hipStream_t s = lstream(op);
     switch ((o.G2 + 15) / 16) {
         case 1: hipLaunchKernelGGL((k_near_regular<NL, 1>), grid, dim3(256), shm, s, o, sb); break;
         case 2: hipLaunchKernelGGL((k_near_regular<NL, 2>), grid, dim3(256), shm, s, o, sb); break;
@@ -1365,7 +1365,7 @@ void launch_near_singular(ige_op op)
 {
     const DevOp &o = op->view;
     if (op->nsing == 0) return;
-    hipStream_t s = op->ctx->stream;
+    hipStream_t s = lstream(op);
     switch (o.p) {
         case 1: hipLaunchKernelGGL(k_near_singular<1>, dim3(op->nsing), dim3(64), 0, s, o, op->d_sing.p); break;
         case 2: hipLaunchKernelGGL(k_near_singular<2>, dim3(op->nsing), dim3(64), 0, s, o, op->d_sing.p); break;
@@ -1380,7 +1380,7 @@ void launch_p2m(ige_op op, const double2 *x)
     const int nleaf = o.P * o.SL * o.SL;
     const int w1a = o.s + o.p, w2a = o.s + o.p - 1;
     const size_t shm = sizeof(double2) * (2 * w1a * w2a + 3 * (size_t)(w1a) * o.Q1);
-    hipLaunchKernelGGL(k_p2m, dim3(nleaf), dim3(256), shm, op->ctx->stream, o, x, op->d_mom.p, op->d_src.p);
+    hipLaunchKernelGGL(k_p2m, dim3(nleaf), dim3(256), shm, lstream(op), o, x, op->d_mom.p, op->d_src.p);
     IGE_LAUNCH_CHECK();
 }
 
@@ -1390,7 +1390,7 @@ void launch_m2m(ige_op op)
     const size_t shm = sizeof(double2) * 24 * o.Q;
     for (int lvl = o.L - 1; lvl >= 0; --lvl) {
         const int ncl = o.P << (2 * lvl);
-        hipLaunchKernelGGL(k_m2m, dim3(ncl), dim3(256), shm, op->ctx->stream, o, lvl, op->d_mom.p, op->d_src.p);
+        hipLaunchKernelGGL(k_m2m, dim3(ncl), dim3(256), shm, lstream(op), o, lvl, op->d_mom.p, op->d_src.p);
         IGE_LAUNCH_CHECK();
     }
 }
@@ -1413,10 +1413,10 @@ void launch_m2l(ige_op op, int prec)
     }
     if (prec == IGE_F32)
         hipLaunchKernelGGL(k_m2l<float>, dim3(op->work.size()), dim3(kM2LThreads), m2l_shared_bytes(o.Q),
-                           op->ctx->stream, o, op->d_work.p, op->d_partner.p, op->d_src.p, op->d_part.p);
+                           lstream(op), o, op->d_work.p, op->d_partner.p, op->d_src.p, op->d_part.p);
     else
         hipLaunchKernelGGL(k_m2l<double>, dim3(op->work.size()), dim3(kM2LThreads), m2l_shared_bytes(o.Q),
-                           op->ctx->stream, o, op->d_work.p, op->d_partner.p, op->d_src.p, op->d_part.p);
+                           lstream(op), o, op->d_work.p, op->d_partner.p, op->d_src.p, op->d_part.p);
     IGE_LAUNCH_CHECK();
 }
 
@@ -1427,7 +1427,7 @@ void launch_m2l_reduce(ige_op op)
         m2l_stored_reduce_one(op);
         return;
     }
-    hipLaunchKernelGGL(k_m2l_reduce, dim3(op->NC), dim3(128), 0, op->ctx->stream, o, op->d_wrk_of_tgt.p,
+    hipLaunchKernelGGL(k_m2l_reduce, dim3(op->NC), dim3(128), 0, lstream(op), o, op->d_wrk_of_tgt.p,
                        op->d_part.p, op->d_loc.p);
     IGE_LAUNCH_CHECK();
 }
@@ -1438,7 +1438,7 @@ void launch_l2l(ige_op op)
     const size_t shm = sizeof(double2) * 3 * o.Q;
     for (int lvl = 1; lvl <= o.L; ++lvl) {
         const int ncl = o.P << (2 * lvl);
-        hipLaunchKernelGGL(k_l2l, dim3(ncl), dim3(256), shm, op->ctx->stream, o, lvl, op->d_loc.p);
+        hipLaunchKernelGGL(k_l2l, dim3(ncl), dim3(256), shm, lstream(op), o, lvl, op->d_loc.p);
         IGE_LAUNCH_CHECK();
     }
 }
@@ -1482,21 +1482,21 @@ void launch_l2p_leaf(ige_op op)
     const DevOp &o = op->view;
     const int nleaf = o.P * o.SL * o.SL;
     const size_t shm = sizeof(double2) * 3 * (size_t)o.Q1 * o.rowlen;
-    hipLaunchKernelGGL(k_l2p_leaf, dim3(nleaf), dim3(256), shm, op->ctx->stream, o, op->d_loc.p, op->d_ybuf.p);
+    hipLaunchKernelGGL(k_l2p_leaf, dim3(nleaf), dim3(256), shm, lstream(op), o, op->d_loc.p, op->d_ybuf.p);
     IGE_LAUNCH_CHECK();
 }
 
 void launch_l2p_gather(ige_op op, double2 *y)
 {
     const DevOp &o = op->view;
-    hipLaunchKernelGGL(k_l2p_gather, dim3((o.N + 255) / 256), dim3(256), 0, op->ctx->stream, o, op->d_ybuf.p, y);
+    hipLaunchKernelGGL(k_l2p_gather, dim3((o.N + 255) / 256), dim3(256), 0, lstream(op), o, op->d_ybuf.p, y);
     IGE_LAUNCH_CHECK();
 }
 
 void launch_rhs_plane(ige_op op, const double *dir, double2 pol0, double2 pol1, double2 pol2, double2 *f)
 {
     const DevOp &o = op->view;
-    hipLaunchKernelGGL(k_rhs_plane, dim3((o.N + 127) / 128), dim3(128), 0, op->ctx->stream, o, dir[0], dir[1], dir[2],
+    hipLaunchKernelGGL(k_rhs_plane, dim3((o.N + 127) / 128), dim3(128), 0, lstream(op), o, dir[0], dir[1], dir[2],
                        pol0, pol1, pol2, f);
     IGE_LAUNCH_CHECK();
 }
@@ -1587,7 +1587,7 @@ void launch_potential(ige_op op, const double2 *w, int npts, const double *pts, 
 {
     const DevOp &o = op->view;
     const int64_t E = (int64_t)o.P * o.n * o.n;
-    hipStream_t s = op->ctx->stream;
+    hipStream_t s = lstream(op);
     switch (o.p) {
         case 1: hipLaunchKernelGGL(k_pot_sources<4>, dim3((unsigned)E), dim3(64), 0, s, o, w, src); break;
         case 2: hipLaunchKernelGGL(k_pot_sources<12>, dim3((unsigned)E), dim3(64), 0, s, o, w, src); break;

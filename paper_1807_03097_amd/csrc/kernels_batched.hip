@@ -22,6 +22,12 @@ __device__ inline double2 cmulb(double2 a, double2 b) { return make_double2(a.x 
 __device__ inline double2 caddb(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ inline double2 cscaleb(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
 
+__global__ void k_zero2(int64_t n, double2 *y)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = make_double2(0.0, 0.0);
+}
+
 // x [r][N] -> xt [N][r] and back
 __global__ void k_to_rows(int64_t N, int r, const double2 *x, double2 *xt)
 {
@@ -177,7 +183,9 @@ void near_batched(ige_op op, int r, const double2 *xt, double2 *yt, hipStream_t 
 {
     const DevOp &o = op->view;
     if (o.nblk == 0) {
-        IGE_HIP(hipMemsetAsync(yt, 0, sizeof(double2) * o.N * r, s));
+        const int64_t tot = (int64_t)o.N * r;
+        hipLaunchKernelGGL(k_zero2, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, tot, yt);
+        IGE_HIP(hipGetLastError());
         return;
     }
     switch (near_blk_u(o.nF)) {
@@ -594,15 +602,17 @@ void near_batched_mfma(ige_op op, int r, const double2 *xt, double2 *yt, hipStre
 void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, double2 *yt, hipEvent_t *ev, int prec)
 {
     const DevOp &o = op->view;
-    hipStream_t s = op->ctx->stream;
+    hipStream_t s = lstream(op);
     auto mark = [&](int i) {
         if (ev) IGE_HIP(hipEventRecord(ev[i], s));
     };
     const int64_t N = o.N;
     const int64_t tot = N * r;
     auto chunks = [&](int rb) { return (r + rb - 1) / rb; };
-    hipLaunchKernelGGL(k_to_rows, dim3((tot + 255) / 256), dim3(256), 0, s, N, r, x, xt);
-    IGE_HIP(hipGetLastError());
+    if (x) {   // x == nullptr: xt already holds the input (graph body)
+        hipLaunchKernelGGL(k_to_rows, dim3((tot + 255) / 256), dim3(256), 0, s, N, r, x, xt);
+        IGE_HIP(hipGetLastError());
+    }
     const bool far = !op->work.empty();
     mark(0);
     if (far) {
@@ -625,15 +635,17 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
         }
         mark(2);
         if (prec == IGE_BF16 || prec == IGE_BF16X3 || prec == IGE_BF16X3_ALL) {
-            m2l_bf16(op, r, prec == IGE_BF16 ? 1 : 3, op->d_bsrc.p, s);
+            m2l_bf16(op, r, prec == IGE_BF16 ? 1 : 3, op->d_bsrc.p, s, ev ? ev[12] : nullptr);
             mark(3);
             hipLaunchKernelGGL(k_m2l_reduce_b<float2>, dim3(op->NC), dim3(256), 0, s, o, r, op->d_mwrk_of_tgt.p,
                                op->d_bmpart.p, op->d_bloc.p);
             IGE_HIP(hipGetLastError());
         } else if (op->stored) {
+            mark(12);
             m2l_stored(op, r, prec, op->d_bsrc.p, op->d_bloc.p, s);
             mark(3);
         } else {
+            mark(12);
             {
                 const int TPG = (o.Q + kNTB - 1) / kNTB;
                 const int S = std::max(1, std::min(kM2LThreadsB / TPG, o.Q));
@@ -681,6 +693,7 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
         mark(6);
     } else {
         for (int i = 1; i <= 6; ++i) mark(i);
+        mark(12);
     }
     mark(7);
     if (prec == IGE_BF16X3_ALL) near_bf16(op, r, xt, yt, s);
@@ -694,7 +707,23 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
         IGE_HIP(hipGetLastError());
     }
     mark(10);
-    hipLaunchKernelGGL(k_to_cols, dim3((tot + 255) / 256), dim3(256), 0, s, N, r, yt, y);
+    if (y) {   // y == nullptr: the result stays in yt (graph body)
+        hipLaunchKernelGGL(k_to_cols, dim3((tot + 255) / 256), dim3(256), 0, s, N, r, yt, y);
+        IGE_HIP(hipGetLastError());
+    }
+}
+
+void batched_to_rows(ige_op op, int r, const double2 *x, double2 *xt, hipStream_t s)
+{
+    const int64_t tot = (int64_t)op->view.N * r;
+    hipLaunchKernelGGL(k_to_rows, dim3((tot + 255) / 256), dim3(256), 0, s, (int64_t)op->view.N, r, x, xt);
+    IGE_HIP(hipGetLastError());
+}
+
+void batched_to_cols(ige_op op, int r, const double2 *yt, double2 *y, hipStream_t s)
+{
+    const int64_t tot = (int64_t)op->view.N * r;
+    hipLaunchKernelGGL(k_to_cols, dim3((tot + 255) / 256), dim3(256), 0, s, (int64_t)op->view.N, r, yt, y);
     IGE_HIP(hipGetLastError());
 }
 

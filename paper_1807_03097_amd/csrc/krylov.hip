@@ -271,6 +271,19 @@ __global__ void k_scale_cols(int64_t n, const double *s, const double2 *x, doubl
     y[(size_t)c * n + i] = make_double2(sc * v.x, sc * v.y);
 }
 
+// y_c += s_c x_c (s per column, real)
+__global__ void k_axpy_cols(int64_t n, const double *s, const double2 *x, double2 *y)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (i >= n) return;
+    const double sc = s[c];
+    if (sc == 0.0) return;
+    const double2 v = x[(size_t)c * n + i];
+    double2 &t = y[(size_t)c * n + i];
+    t = make_double2(fma(sc, v.x, t.x), fma(sc, v.y, t.y));
+}
+
 int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 }  // namespace
@@ -339,6 +352,13 @@ void launch_axpby(ige_op op, int64_t n, double2 a, const double2 *x, double2 b, 
 void launch_norm2_b(ige_op op, int r, const double2 *x, double *out)
 {
     hipLaunchKernelGGL(k_norm2_b, dim3(r), dim3(256), 0, op->ctx->stream, (int64_t)op->view.N, x, out);
+    IGE_HIP(hipGetLastError());
+}
+
+void launch_axpy_cols(ige_op op, int r, const double *s, const double2 *x, double2 *y)
+{
+    const int64_t n = op->view.N;
+    hipLaunchKernelGGL(k_axpy_cols, dim3(cdiv(n, 256), r), dim3(256), 0, op->ctx->stream, n, s, x, y);
     IGE_HIP(hipGetLastError());
 }
 

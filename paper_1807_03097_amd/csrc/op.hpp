@@ -81,9 +81,11 @@ struct ige_op_s {
     double assemble_ms = 0.0;
     bool profiling = false;
     static constexpr int kProfSlots = 256;
-    static constexpr int kProfEv = 12;
+    static constexpr int kProfEv = 13;
     std::vector<hipEvent_t> prof_ev;   // [kProfSlots][kProfEv] stage boundary events
     hipStream_t aux = nullptr;         // second stream: near-field product
+    hipStream_t lst = nullptr;         // launch stream of the apply kernels (null: the context stream)
+    hipStream_t gstream = nullptr;     // stream on which apply graphs are captured
     bool overlap = true;               // near field concurrent with the far field
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int64_t prof_count = 0;
@@ -166,6 +168,9 @@ struct ige_op_s {
 
 namespace ige {
 
+// stream the apply kernels are launched on (a capture stream while a graph is recorded)
+inline hipStream_t lstream(const ige_op_s *op) { return op->lst ? op->lst : op->ctx->stream; }
+
 // assembly of geom's operator on ctx's device and stream (throws ige::Status)
 ige_op assemble_on(ige_ctx ctx, const ige_geom_s *geom, const ige_params &prm);
 // device bytes of an operator planned on the host plus a GMRES with this restart
@@ -194,7 +199,7 @@ void m2l_stored_one(ige_op op, int prec);
 void m2l_stored_reduce_one(ige_op op);
 // matrix-core coupling of r columns in BF16 (split 1) or split BF16 (split 3):
 // fields [NC][4][Q][r] -> partials per work item [mwork][4][Q][r] (d_bmpart)
-void m2l_bf16(ige_op op, int r, int split, const double2 *src, hipStream_t s);
+void m2l_bf16(ige_op op, int r, int split, const double2 *src, hipStream_t s, hipEvent_t mid = nullptr);
 void ensure_coupling_bf16(ige_op op, int split);
 // split-BF16 near-field product (yt = near part of A x, [N][r] layout)
 void plan_near_bf16(ige_op op, const std::vector<int32_t> &pair, const std::vector<int32_t> &leafdof, int nF);
@@ -235,7 +240,11 @@ void launch_gs_pack(hipStream_t s, int r, int k, const double2 *h1, const double
 void launch_axpby(ige_op op, int64_t n, double2 a, const double2 *x, double2 b, double2 *y);
 void launch_norm2_b(ige_op op, int r, const double2 *x, double *out);
 void launch_scale_cols(ige_op op, int r, const double *s, const double2 *x, double2 *y);
+void launch_axpy_cols(ige_op op, int r, const double *s, const double2 *x, double2 *y);
+// x == nullptr: the input is already in xt; y == nullptr: the result stays in yt
 void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, double2 *yt, hipEvent_t *ev, int prec);
+void batched_to_rows(ige_op op, int r, const double2 *x, double2 *xt, hipStream_t s);
+void batched_to_cols(ige_op op, int r, const double2 *yt, double2 *y, hipStream_t s);
 void launch_helmholtz_eval(hipStream_t s, int64_t n, double kappa, const double *r2, double2 *out, int prec);
 
 }  // namespace ige

@@ -296,6 +296,49 @@ def test_bf16_matrix_core_coupling(oracle_mod, ctx, case):
     op.close()
 
 
+@pytest.mark.parametrize("nrhs, prec", [(1, 0), (3, 0), (3, 3)], ids=["1col-f64", "3col-f64", "3col-splitbf16"])
+def test_solve_graph_replays_equal_eager(ctx, monkeypatch, nrhs, prec):
+    """GMRES with the apply captured as a HIP graph and replayed every iteration gives
+    bitwise the same iterates as the eager launches (every replay feeds the next)."""
+    from paper_1807_03097_amd import binding as B
+    geom = B.Geometry(ctx, _geom("sphere"))
+    op = B.Operator(geom, 2, 3, 8.0, 8, 1.6, 5, 5, 1)
+    dirs, pols = W.fibonacci_plane_waves(nrhs)
+    F = op.rhs_plane_wave(dirs, pols)
+    if nrhs == 1:
+        F = F[0]
+    kw = dict(tol=1e-8, restart=60, maxit=300)
+    if prec:
+        kw.update(refine=True, inner_prec=prec, inner_tol=1e-3)
+    monkeypatch.setenv("IGE_GRAPH", "0")
+    Xe, ste, rce = op.solve(F, **kw)
+    monkeypatch.setenv("IGE_GRAPH", "1")
+    Xg, stg, rcg = op.solve(F, **kw)
+    _say(f"  eager {[s[:3] for s in ste]}, graph {[s[:3] for s in stg]}")
+    assert rce == rcg and [s[:3] for s in ste] == [s[:3] for s in stg]
+    assert np.array_equal(Xe, Xg)
+    op.close()
+
+
+def test_refinement_escalates_inner_precision(ctx):
+    """Plain BF16 inner solves cannot reach 1e-10 alone (the inner operator's error
+    times the condition number is too large); the refined solve moves the inner
+    precision towards FP64 and meets the tolerance on the FP64 operator."""
+    from paper_1807_03097_amd import binding as B
+    geom = B.Geometry(ctx, _geom("sphere"))
+    op = B.Operator(geom, 2, 3, 8.0, 8, 1.6, 5, 5, 1)
+    dirs, pols = W.fibonacci_plane_waves(1)
+    F = op.rhs_plane_wave(dirs, pols)
+    X64, st64, rc = op.solve(F, tol=1e-10, restart=100, maxit=4000)
+    assert rc == 0
+    Xr, st, rc2 = op.solve(F, tol=1e-10, restart=100, maxit=12000, refine=True, inner_tol=1e-4,
+                           inner_prec=B.IGE_BF16)
+    _say(f"  FP64 iters {st64[0][0]}, BF16-start refined iters {st[0][0]} outer {st[0][1]} relres {st[0][2]:.2e}")
+    assert rc2 == 0 and st[0][2] <= 1.05e-10
+    assert _rel(Xr[0], X64[0]) <= 1e-6
+    op.close()
+
+
 @pytest.mark.parametrize("name, p, m, kappa", [("sphere", 2, 3, 8.0), ("torus", 1, 3, 3.0), ("jittered", 2, 2, 5.0)])
 def test_potential_matches_oracle(oracle_mod, ctx, name, p, m, kappa):
     """Scattered field e_s = V~ w at points off the surface (two columns)."""
