@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--inner-prec", type=int, default=3, choices=(0, 1, 2, 3, 4),
                     help="solve: precision of refined inner solves (as --prec)")
     ap.add_argument("--compare-fp64", action="store_true", help="solve: also solve in FP64 and report the difference")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the candidate tile shapes of the apply first and keep the fastest (ige_op_autotune)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (calibrates HBM byte counters)")
     ap.add_argument("--requests", type=int, default=32, help="serve: number of requests")
@@ -143,6 +145,12 @@ def run_solve(args):
     dirs, pols = W.fibonacci_plane_waves(args.nrhs)
     F = op.rhs_plane_wave(dirs, pols)
     log(f"N={op.N} near entries={op.info.near_nnz} far pairs={op.info.far_pairs} assembled in {t_asm:.2f} s")
+    tuned = {}
+    if args.autotune:
+        t2 = time.perf_counter()
+        for pr in sorted({0, args.inner_prec if args.refine else 0}):
+            tuned[str(pr)] = op.autotune(args.nrhs, pr)
+        log(f"autotuned {tuned} in {time.perf_counter() - t2:.2f} s")
     runs = []
     modes = [("refined" if args.refine else "fp64", args.refine)]
     if args.compare_fp64 and args.refine:
@@ -182,6 +190,7 @@ def run_solve(args):
         "assemble_s": t_asm,
         "runs": runs,
         "refined_vs_fp64_max_rel_diff": diff,
+        "autotuned": tuned or None,
     }
     print(json.dumps(out), flush=True)
     op.close()
@@ -304,6 +313,13 @@ def main():
     for _ in range(args.warmup):
         op.apply(x, y, prec=args.prec)
     torch.cuda.synchronize()
+    tuned = None
+    if args.autotune:
+        tuned = op.autotune(r, args.prec)
+        log(f"autotuned {tuned}")
+        for _ in range(args.warmup):
+            op.apply(x, y, prec=args.prec)
+        torch.cuda.synchronize()
 
     op.set_profiling(True)
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -439,6 +455,7 @@ def main():
         "roofline": roof,
         "roofline_isolated": roof_iso,
         "roofline_coupling": roof_cpl,
+        "autotuned": tuned,
         "stage_ms_isolated": st_iso,
         "cpu_baseline": cpu,
         "parity_sampled_rel_err": parity,

@@ -175,6 +175,23 @@ int ige_apply(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind);
  * bytes, Qn = slots per leaf rounded up to 32). */
 int ige_apply_prec(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind, int coupling_prec);
 
+/* Autotuner for the r-column apply in precision prec: times every candidate tile
+ * shape of the kernels that apply uses (coordinate descent, each candidate one
+ * warm-up and three timed applies on seeded N(0,1) + iN(0,1) columns, HIP events on
+ * the context stream) and keeps the fastest for later applies and solves with the
+ * same (r, prec).  Knobs, in choice[] order (-1: not used by this apply):
+ *   0 coupling column chunk of the BF16 matrix-core coupling (64, 128, 256 complex
+ *     columns, capped where registers would spill),
+ *   1 column tiles per wave of the split-BF16 near-field product (1, 2, 4),
+ *   2 column tiles per wave of the FP64 matrix-core near-field product (1, 2, 4),
+ *   3 columns per workgroup of the generated FP64/FP32 coupling (1, 2, 4; capped by
+ *     shared memory),
+ *   4 staging of the BF16 coupling blocks: 1 double-buffered (the next block loaded
+ *     step by step during the current product), 0 one buffer with the next block
+ *     prefetched into registers.
+ * Returns the number of timed configurations (>= 0) or an error status (< 0). */
+int ige_op_autotune(ige_op op, int r, int prec, int *choice, int nchoice);
+
 /* Stage profiling.  ige_op_set_profiling(op, 1) creates HIP events and clears the
  * record; every later single-column apply records its stage boundaries on the
  * context stream (no host synchronisation).  ige_op_stage_times synchronises the

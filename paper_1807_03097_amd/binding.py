@@ -90,6 +90,7 @@ _SIGS = {
     "ige_op_set_profiling": (C.c_int, [_V, C.c_int]),
     "ige_op_set_overlap": (C.c_int, [_V, C.c_int]),
     "ige_op_stage_times": (C.c_int, [_V, _V, C.c_int]),
+    "ige_op_autotune": (C.c_int, [_V, C.c_int, C.c_int, _V, C.c_int]),
     "ige_rhs_plane_wave": (C.c_int, [_V, C.c_int, _V, _V, _V, C.c_int]),
     "ige_solve": (C.c_int, [_V, C.c_int, _V, _V, C.c_int, C.POINTER(ige_solve_opts), _V]),
     "ige_helmholtz_eval": (C.c_int, [_V, C.c_int64, C.c_double, _V, _V, C.c_int]),
@@ -351,6 +352,14 @@ class Operator:
         out = np.zeros((r, len(points), 3), np.complex128)
         _check(_lib.ige_potential(self.h, r, _ptr(w), _kind(w), len(points), _ptr(points), _ptr(out)))
         return out[0] if w.ndim == 1 else out
+
+    def autotune(self, r, prec=IGE_F64):
+        """time the candidate tile shapes of the r-column apply and keep the fastest;
+        returns {knob: value} for the knobs that apply uses"""
+        ch = np.full(5, -1, np.int32)
+        _check(_lib.ige_op_autotune(self.h, int(r), int(prec), _ptr(ch), 5))
+        names = ("m2l_ncol", "near_bx_nt", "near_mfma_nt", "m2l_rb", "m2l_double_buffer")
+        return {n: int(v) for n, v in zip(names, ch) if v >= 0}
 
     def set_profiling(self, on=True):
         ige_op_set_profiling(self.h, on)

@@ -829,6 +829,87 @@ int ige_apply_prec(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind,
     return apply_impl(op, r, x, y, ptr_kind, coupling_prec);
 }
 
+int ige_op_autotune(ige_op op, int r, int prec, int *choice, int nchoice)
+{
+    int tried = 0;
+    int rc = guard([&] {
+        IGE_REQUIRE(op && r >= 1 && (choice || nchoice == 0), "bad autotune arguments");
+        IGE_REQUIRE(op->assembled, "operator was planned, not assembled");
+        IGE_REQUIRE(prec >= IGE_F64 && prec <= IGE_BF16X3_ALL, "bad precision");
+        set_device(op->ctx);
+        const int64_t N = op->D.N;
+        hipStream_t s = op->ctx->stream;
+        // seeded N(0,1) + i N(0,1) input columns
+        std::vector<double2> xh((size_t)r * N);
+        uint64_t st = 0x9e3779b97f4a7c15ull;
+        auto unif = [&] {
+            st ^= st << 13;
+            st ^= st >> 7;
+            st ^= st << 17;
+            return ((st >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+        };
+        for (auto &v : xh) {
+            const double a = std::sqrt(-2.0 * std::log(unif())), t = 6.283185307179586 * unif();
+            v = make_double2(a * std::cos(t), a * std::sin(t));
+        }
+        ige::DBuf<double2> dx, dy;
+        dx.upload(xh, s);
+        dy.alloc(xh.size());
+        hipEvent_t e0, e1;
+        IGE_HIP(hipEventCreate(&e0));
+        IGE_HIP(hipEventCreate(&e1));
+        auto time_apply = [&] {
+            apply_dev(op, r, dx.p, dy.p, prec);   // warm-up (sizes buffers for this choice)
+            IGE_HIP(hipEventRecord(e0, s));
+            for (int i = 0; i < 3; ++i) apply_dev(op, r, dx.p, dy.p, prec);
+            IGE_HIP(hipEventRecord(e1, s));
+            IGE_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            IGE_HIP(hipEventElapsedTime(&ms, e0, e1));
+            ++tried;
+            return ms / 3.0;
+        };
+        // coordinate descent over the knobs that the (r, prec) apply uses
+        const bool mx = r > 1 && prec >= IGE_BF16, near_bx = r > 1 && prec == IGE_BF16X3_ALL;
+        const bool near_mfma = r >= 8 && prec != IGE_BF16X3_ALL && ige::near_mfma_mtw_ok(op->view.nF, op->view.rc);
+        const bool gen = r > 1 && prec <= IGE_F32 && !op->stored && !op->work.empty();
+        const int split = prec == IGE_BF16 ? 1 : 3;
+        struct Knob {
+            bool on;
+            int id, key_prec;
+            std::vector<int> cand;
+        };
+        const bool mxon = mx && !op->mwork.empty();
+        const Knob knobs[ige::kTuneKnobs] = {{mxon, ige::kTuneM2lDb, split, {1, 0}},
+                                            {mxon, ige::kTuneM2lNcol, split, {64, 128, 256}},
+                                            {near_bx, ige::kTuneNearBxNt, 0, {1, 2, 4}},
+                                            {near_mfma, ige::kTuneNearMfmaNt, 0, {1, 2, 4}},
+                                            {gen, ige::kTuneM2lRb, prec, {1, 2, 4}}};
+        std::vector<int> chosen(ige::kTuneKnobs, -1);
+        for (const Knob &k : knobs) {
+            if (!k.on) continue;
+            const long long key = ige::tune_key(k.id, r, k.key_prec);
+            double best = 1e300;
+            int bv = k.cand[0];
+            for (int v : k.cand) {
+                op->tune[key] = v;
+                const double t = time_apply();
+                if (t < best) {
+                    best = t;
+                    bv = v;
+                }
+            }
+            op->tune[key] = bv;
+            chosen[k.id] = bv;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        IGE_HIP(hipStreamSynchronize(s));
+        for (int i = 0; i < std::min(nchoice, (int)ige::kTuneKnobs); ++i) choice[i] = chosen[i];
+    });
+    return rc == IGE_OK ? tried : rc;
+}
+
 int ige_rhs_plane_wave(ige_op op, int r, const double *dir, const ige_c64 *pol, ige_c64 *f, int ptr_kind)
 {
     return guard([&] {

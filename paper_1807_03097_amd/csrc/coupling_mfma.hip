@@ -256,6 +256,135 @@ __global__ __launch_bounds__(128 * WN) void k_m2l_mx(DevOp o, int r, int rc, int
     }
 }
 
+
+// The same product with the block staged in two shared-memory buffers: while the
+// waves multiply with block kp from one buffer, each reduction step loads a share of
+// block kp + 1 into registers and stores it into the other buffer after its products
+// (one barrier per partner, a few registers for the pieces in flight instead of the
+// whole next block), which leaves room for wider column chunks.
+template <int SPLIT, int MT, int WN, int NT>
+__global__ __launch_bounds__(128 * WN) void k_m2l_mxd(DevOp o, int r, int rc, int nchunk, int64_t nwork,
+                                                      const int32_t *order, const M2LWork *work,
+                                                      const int32_t *partner, const int32_t *gslot, const __bf16 *Gb,
+                                                      const __bf16 *Vb, float2 *part)
+{
+    constexpr int PL = SPLIT == 3 ? 2 : 1;
+    constexpr int QP = 16 * MT, K2 = 2 * QP, KS = K2 / 32, LD = K2 + 8;
+    constexpr int NTH = 128 * WN, NCOL = 16 * WN * NT;
+    constexpr int GCH = PL * QP * K2 / 8;           // 16-byte pieces of one block
+    constexpr int GV = (GCH + NTH - 1) / NTH;       // pieces per thread
+    constexpr int PPS = (GV + KS - 1) / KS;         // pieces per thread per reduction step
+    constexpr size_t BUF = (size_t)PL * QP * LD;    // one staging buffer
+    extern __shared__ __bf16 sG[];                  // [2][PL][QP][LD]
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv / WN, wn = wv % WN;
+    const int Q = o.Q;
+    const int64_t g = blockIdx.x;
+    const int64_t wo = (g / (8 * nchunk)) * 8 + g % 8;
+    const int ch = (int)((g / 8) % nchunk);
+    if (wo >= nwork) return;
+    const int64_t wi = order[wo];
+    const M2LWork wk = work[wi];
+    if (wk.beg >= wk.end) return;
+    const size_t gper = (size_t)PL * QP * K2, vper = (size_t)NCOL * K2;
+
+    auto s_piece = [&](__bf16 *buf, int e, uint4 v) {
+        const int pl = e / (QP * K2 / 8), rr = e % (QP * K2 / 8), row = rr / (K2 / 8), k8 = rr % (K2 / 8);
+        *reinterpret_cast<uint4 *>(buf + ((size_t)pl * QP + row) * LD + 8 * k8) = v;
+    };
+    auto b_load = [&](bf8 (&b)[NT][PL], int kp, int s) {
+        const __bf16 *Vs = Vb + ((size_t)partner[kp] * nchunk + ch) * PL * vper;
+        const int kk = 32 * s + 8 * (lane >> 4);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int n = 16 * (wn * NT + t) + (lane & 15);
+#pragma unroll
+            for (int pl = 0; pl < PL; ++pl)
+                b[t][pl] = *reinterpret_cast<const bf8 *>(Vs + (size_t)pl * vper + (size_t)n * K2 + kk);
+        }
+    };
+
+    f4 acc[MT][NT];
+#pragma unroll
+    for (int a = 0; a < MT; ++a)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[a][t] = f4{0.f, 0.f, 0.f, 0.f};
+
+    {   // first block straight into buffer 0
+        const __bf16 *Gp = Gb + (size_t)gslot[wk.beg] * gper;
+        for (int e = tid; e < GCH; e += NTH) s_piece(sG, e, *reinterpret_cast<const uint4 *>(Gp + (size_t)8 * e));
+    }
+    bf8 bcur[NT][PL], bnxt[NT][PL];
+    b_load(bcur, wk.beg, 0);
+    __syncthreads();
+    for (int kp = wk.beg; kp < wk.end; ++kp) {
+        const __bf16 *cur = sG + (size_t)((kp - wk.beg) & 1) * BUF;
+        __bf16 *nxt = sG + (size_t)(((kp - wk.beg) & 1) ^ 1) * BUF;
+        const bool more = kp + 1 < wk.end;
+        const __bf16 *Gn = more ? Gb + (size_t)gslot[kp + 1] * gper : Gb;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            // this step's share of the next block, in flight during the products
+            uint4 pc[PPS];
+#pragma unroll
+            for (int v = 0; v < PPS; ++v) {
+                const int e = tid + NTH * (s * PPS + v);
+                if (more && s * PPS + v < GV && e < GCH) pc[v] = *reinterpret_cast<const uint4 *>(Gn + (size_t)8 * e);
+            }
+            if (s + 1 < KS) b_load(bnxt, kp, s + 1);
+            else if (more) b_load(bnxt, kp + 1, 0);
+            const bool hi_half = 32 * s >= QP;
+            const int kk = 32 * s + 8 * (lane >> 4);
+            const int ksrc = wm == 0 ? kk : (hi_half ? kk - QP : kk + QP);
+            const bool neg = wm == 0 && hi_half;
+#pragma unroll
+            for (int a = 0; a < MT; ++a) {
+                const __bf16 *row = cur + (size_t)(16 * a + (lane & 15)) * LD + ksrc;
+                bf8 ah = *reinterpret_cast<const bf8 *>(row);
+                bf8 al;
+                if (SPLIT == 3) al = *reinterpret_cast<const bf8 *>(row + (size_t)QP * LD);
+                if (neg) {
+                    ah = neg_bf8(ah);
+                    if (SPLIT == 3) al = neg_bf8(al);
+                }
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    acc[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bcur[t][0], acc[a][t], 0, 0, 0);
+                    if (SPLIT == 3) {
+                        acc[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bcur[t][PL - 1], acc[a][t], 0, 0, 0);
+                        acc[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bcur[t][0], acc[a][t], 0, 0, 0);
+                    }
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < PPS; ++v) {
+                const int e = tid + NTH * (s * PPS + v);
+                if (more && s * PPS + v < GV && e < GCH) s_piece(nxt, e, pc[v]);
+            }
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int pl = 0; pl < PL; ++pl) bcur[t][pl] = bnxt[t][pl];
+        }
+        __syncthreads();   // the next block is complete and the current buffer is free
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int n = 16 * (wn * NT + t) + (lane & 15), f = n / rc, jc = n % rc;
+        const int col = ch * rc + jc;
+        if (f >= 4 || col >= r) continue;
+#pragma unroll
+        for (int a = 0; a < MT; ++a)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int m = 16 * a + 4 * (lane >> 4) + j;
+                if (m < Q) {
+                    float *dst = reinterpret_cast<float *>(part + (((size_t)wi * 4 + f) * Q + m) * r + col);
+                    dst[wm] = acc[a][t][j];
+                }
+            }
+    }
+}
+
 }  // namespace
 
 int coupling_qp(int Q) { return 32 * ((Q + 31) / 32); }
@@ -278,59 +407,78 @@ namespace {
 // columns per chunk (complex columns = 4 fields x right-hand sides): the smallest of
 // 16..256 holding all 4r columns, capped so that the accumulators, the prefetched
 // block and the streamed factor stay in registers (no spills)
-int m2l_ncol(int r, int MT, int split)
+// double-buffered staging: both buffers fit in shared memory (64 KB is the limit for
+// dynamic shared memory granted without asking; up to 160 KB after the attribute)
+bool m2l_db_fits(int MT, int split) { return (size_t)2 * (split == 3 ? 2 : 1) * 16 * MT * (32 * MT + 8) * 2 <= 160 * 1024; }
+
+// widest chunk (complex columns) without register spills; db: double-buffered kernel
+int m2l_ncol_cap(int MT, int split, bool db)
 {
-    const int cap = MT >= 8 ? (split == 3 ? 64 : 128) : (MT >= 6 ? 128 : 256);
+    if (db) return MT >= 8 ? 128 : (MT >= 6 && split == 3 ? 256 : 256);
+    return MT >= 8 ? (split == 3 ? 64 : 128) : (MT >= 6 ? 128 : 256);
+}
+
+// the smallest of 16..cap holding all 4r columns
+int m2l_ncol(int r, int cap)
+{
     int nc = 16;
     while (nc < 4 * r && nc < cap) nc *= 2;
     return nc;
 }
 
-template <int SPLIT, int MT, int WN, int NT>
+template <bool DB, int SPLIT, int MT, int WN, int NT>
 void launch_mx(ige_op op, int r, int rc, int nchunk, const __bf16 *G, const __bf16 *Vb, hipStream_t s)
 {
     const DevOp &o = op->view;
     const int64_t nw = (int64_t)op->mwork.size();
     const dim3 grid((unsigned)(((nw + 7) / 8) * 8 * nchunk)), blk(128 * WN);
     constexpr int PL = SPLIT == 3 ? 2 : 1, QP = 16 * MT;
-    const size_t shm = sizeof(__bf16) * PL * QP * (2 * QP + 8);
-    int lds_max = 0;
-    IGE_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, op->ctx->device));
-    IGE_REQUIRE(shm <= (size_t)lds_max, "coupling block does not fit in shared memory");
-    IGE_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_m2l_mx<SPLIT, MT, WN, NT>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-    hipLaunchKernelGGL((k_m2l_mx<SPLIT, MT, WN, NT>), grid, blk, shm, s, o, r, rc, nchunk, nw, op->d_morder.p,
-                       op->d_mwork.p, op->d_mpartner.p, op->d_gslot.p, G, Vb, op->d_bmpart.p);
+    constexpr size_t shm = sizeof(__bf16) * (DB ? 2 : 1) * PL * QP * (2 * QP + 8);
+    auto kern = DB ? &k_m2l_mxd<SPLIT, MT, WN, NT> : &k_m2l_mx<SPLIT, MT, WN, NT>;
+    static bool attr = false;   // the attribute is set once per kernel, before any graph capture
+    if (!attr) {
+        int lds_max = 0;
+        IGE_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, op->ctx->device));
+        IGE_REQUIRE(shm <= (size_t)lds_max, "coupling block does not fit in shared memory");
+        IGE_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)shm));
+        attr = true;
+    }
+    hipLaunchKernelGGL(kern, grid, blk, shm, s, o, r, rc, nchunk, nw, op->d_morder.p, op->d_mwork.p,
+                       op->d_mpartner.p, op->d_gslot.p, G, Vb, op->d_bmpart.p);
     IGE_HIP(hipGetLastError());
 }
 
-template <int SPLIT, int MT>
+template <bool DB, int SPLIT, int MT>
 void launch_mx_cols(ige_op op, int r, int ncol, const __bf16 *G, const __bf16 *Vb, hipStream_t s)
 {
     const int rc = ncol / 4, nchunk = (r + rc - 1) / rc;
     switch (ncol) {
-        case 16: launch_mx<SPLIT, MT, 1, 1>(op, r, rc, nchunk, G, Vb, s); break;
-        case 32: launch_mx<SPLIT, MT, 2, 1>(op, r, rc, nchunk, G, Vb, s); break;
-        case 64: launch_mx<SPLIT, MT, 4, 1>(op, r, rc, nchunk, G, Vb, s); break;
+        case 16: launch_mx<DB, SPLIT, MT, 1, 1>(op, r, rc, nchunk, G, Vb, s); break;
+        case 32: launch_mx<DB, SPLIT, MT, 2, 1>(op, r, rc, nchunk, G, Vb, s); break;
+        case 64: launch_mx<DB, SPLIT, MT, 4, 1>(op, r, rc, nchunk, G, Vb, s); break;
         case 128:
-            if constexpr (SPLIT == 1 || MT < 8) launch_mx<SPLIT, MT, 4, 2>(op, r, rc, nchunk, G, Vb, s);
+            if constexpr (DB || SPLIT == 1 || MT < 8) launch_mx<DB, SPLIT, MT, 4, 2>(op, r, rc, nchunk, G, Vb, s);
             else IGE_REQUIRE(false, "coupling chunk too wide for this interpolation degree");
             break;
         default:
-            if constexpr (MT <= 4) launch_mx<SPLIT, MT, 4, 4>(op, r, rc, nchunk, G, Vb, s);
+            if constexpr (MT <= 4 || (DB && MT <= 6)) launch_mx<DB, SPLIT, MT, 4, 4>(op, r, rc, nchunk, G, Vb, s);
             else IGE_REQUIRE(false, "coupling chunk too wide for this interpolation degree");
             break;
     }
 }
 
-template <int SPLIT>
+template <bool DB, int SPLIT>
 void launch_mx_mt(ige_op op, int r, int MT, int ncol, const __bf16 *G, const __bf16 *Vb, hipStream_t s)
 {
     switch (MT) {
-        case 2: launch_mx_cols<SPLIT, 2>(op, r, ncol, G, Vb, s); break;
-        case 4: launch_mx_cols<SPLIT, 4>(op, r, ncol, G, Vb, s); break;
-        case 6: launch_mx_cols<SPLIT, 6>(op, r, ncol, G, Vb, s); break;
-        default: launch_mx_cols<SPLIT, 8>(op, r, ncol, G, Vb, s); break;
+        case 2: launch_mx_cols<DB, SPLIT, 2>(op, r, ncol, G, Vb, s); break;
+        case 4: launch_mx_cols<DB, SPLIT, 4>(op, r, ncol, G, Vb, s); break;
+        case 6: launch_mx_cols<DB, SPLIT, 6>(op, r, ncol, G, Vb, s); break;
+        default:
+            if constexpr (!DB || SPLIT == 1) launch_mx_cols<DB, SPLIT, 8>(op, r, ncol, G, Vb, s);
+            else IGE_REQUIRE(false, "double-buffered coupling blocks do not fit in shared memory");
+            break;
     }
 }
 
@@ -343,7 +491,14 @@ void m2l_bf16(ige_op op, int r, int split, const double2 *src, hipStream_t s, hi
     ensure_coupling_bf16(op, split);
     const int Qp = coupling_qp(o.Q), K2 = 2 * Qp, MT = Qp / 16;
     IGE_REQUIRE(MT <= 8, "interpolation degree too large for the matrix-core coupling");
-    const int ncol = m2l_ncol(r, MT, split), rc = ncol / 4, nchunk = (r + rc - 1) / rc;
+    // staging (single or double buffer) and chunk width: tuned values if any, else
+    // double-buffered where it fits and the smallest chunk holding all columns
+    const bool db = m2l_db_fits(MT, split) && tune_get(op, kTuneM2lDb, r, split, 1) != 0;
+    const int cap = m2l_ncol_cap(MT, split, db);
+    int ncol = m2l_ncol(r, cap);
+    const int tuned = tune_get(op, kTuneM2lNcol, r, split, 0);
+    if (tuned >= 16 && (tuned & (tuned - 1)) == 0) ncol = std::min(tuned, cap);
+    const int rc = ncol / 4, nchunk = (r + rc - 1) / rc;
     const int planes = split == 3 ? 2 : 1;
     const size_t vbn = (size_t)op->NC * nchunk * planes * ncol * K2;
     if (op->d_vb.n < vbn) op->d_vb.alloc(vbn);
@@ -354,8 +509,13 @@ void m2l_bf16(ige_op op, int r, int split, const double2 *src, hipStream_t s, hi
                        Qp, split, src, op->d_vb.p);
     IGE_HIP(hipGetLastError());
     if (mid) IGE_HIP(hipEventRecord(mid, s));
-    if (split == 3) launch_mx_mt<3>(op, r, MT, ncol, op->d_Gb3.p, op->d_vb.p, s);
-    else launch_mx_mt<1>(op, r, MT, ncol, op->d_Gb1.p, op->d_vb.p, s);
+    if (db) {
+        if (split == 3) launch_mx_mt<true, 3>(op, r, MT, ncol, op->d_Gb3.p, op->d_vb.p, s);
+        else launch_mx_mt<true, 1>(op, r, MT, ncol, op->d_Gb1.p, op->d_vb.p, s);
+    } else {
+        if (split == 3) launch_mx_mt<false, 3>(op, r, MT, ncol, op->d_Gb3.p, op->d_vb.p, s);
+        else launch_mx_mt<false, 1>(op, r, MT, ncol, op->d_Gb1.p, op->d_vb.p, s);
+    }
 }
 
 }  // namespace ige

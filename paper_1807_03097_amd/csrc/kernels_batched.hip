@@ -651,7 +651,9 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
                 const int S = std::max(1, std::min(kM2LThreadsB / TPG, o.Q));
                 const size_t fixed = sizeof(double) * (3 * o.Q + 1);
                 const size_t per = std::max(sizeof(double2) * 4 * o.Q, sizeof(double2) * (size_t)S * o.Q);
-                const int rb = std::min(4, pick_rb(per, fixed));   // registers: 3 targets x 4 fields x rb columns
+                // registers: 3 targets x 4 fields x rb columns; a tuned value may only lower it
+                const int rbmax = std::min(4, pick_rb(per, fixed));
+                const int rb = std::min(rbmax, tune_get(op, kTuneM2lRb, r, prec, rbmax));
                 const dim3 grid(op->work.size(), chunks(rb)), blk(kM2LThreadsB);
                 const size_t shm = fixed + per * rb;
                 if (prec == IGE_F32) {
@@ -878,7 +880,7 @@ void near_batched_mfma(ige_op op, int r, const double2 *xt, double2 *yt, hipStre
     const size_t need = (size_t)o.nblk * o.nF * (1 + o.nch) * r;
     if (op->d_bnpart_r.n < need) op->d_bnpart_r.alloc(need);
     double2 *part = op->d_bnpart_r.p;
-    const int NT = r > 32 ? 4 : (r > 16 ? 2 : 1);
+    const int NT = tune_get(op, kTuneNearMfmaNt, r, 0, r > 32 ? 4 : (r > 16 ? 2 : 1));
     if (NT == 4) {
         launch_near_mfma<0, 4>(op, r, xt, part, s);
         launch_near_mfma<1, 4>(op, r, xt, part, s);

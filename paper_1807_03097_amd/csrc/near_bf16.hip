@@ -96,15 +96,16 @@ __global__ void k_xnb_prep(int64_t nleaf, int nF, int Qp, int r, int ncol, int n
     base[per + rem] = l;
 }
 
-template <int MTW, int NT>
-__global__ __launch_bounds__(256) void k_near_bx(int r, int nchunk, int Qp, int nF, int64_t nwork,
+template <int QP, int NT>
+__global__ __launch_bounds__(256) void k_near_bx(int r, int nchunk, int nF, int64_t nwork,
                                                  const int32_t *order, const M2LWork *work, const int32_t *partner,
                                                  const int32_t *aslot, const __bf16 *Ab, const __bf16 *Xb,
                                                  float2 *part)
 {
-    constexpr int NCOL = 16 * NT;
+    // QP: slots rounded up to 32; the reduction loop is unrolled so that the next
+    // step's loads can be issued ahead of the current step's products
+    constexpr int NCOL = 16 * NT, Qp = QP, K2 = 2 * QP, KS = QP / 32, MTT = QP / 16, MTW = (MTT + 3) / 4;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int K2 = 2 * Qp, KS = Qp / 32, MTT = Qp / 16;
     // the chunks of one work item share an XCD (consecutive ids go round-robin over 8)
     const int64_t g = blockIdx.x;
     const int64_t wo = (g / (8 * nchunk)) * 8 + g % 8;
@@ -124,6 +125,7 @@ __global__ __launch_bounds__(256) void k_near_bx(int r, int nchunk, int Qp, int 
     for (int kp = wk.beg; kp < wk.end; ++kp) {
         const __bf16 *As = Ab + (size_t)aslot[kp] * aper;
         const __bf16 *Xs = Xb + ((size_t)partner[kp] * nchunk + ch) * 2 * xper;
+#pragma unroll
         for (int s = 0; s < KS; ++s) {
             const int k = 32 * s + 8 * (lane >> 4);
             bf8 xr[NT][2], xi[NT][2];
@@ -274,25 +276,25 @@ void ensure_near_bf16(ige_op op)
 int near_bf16_ok(int nF) { return near_qp(nF) / 16 <= 4 * 4; }
 
 namespace {
-template <int MTW, int NT>
-void launch_bx(ige_op op, int r, int nchunk, int Qp, hipStream_t s)
+template <int QP, int NT>
+void launch_bx(ige_op op, int r, int nchunk, hipStream_t s)
 {
     const DevOp &o = op->view;
     const int64_t nw = op->nb_nwork;
     if (nw == 0) return;
     const dim3 grid((unsigned)(((nw + 7) / 8) * 8 * nchunk)), blk(256);
-    hipLaunchKernelGGL((k_near_bx<MTW, NT>), grid, blk, 0, s, r, nchunk, Qp, o.nF, nw, op->d_nborder.p,
-                       op->d_nbwork.p, op->d_nbpartner.p, op->d_nbslot.p, op->d_nb3.p, op->d_xnb.p, op->d_nbpart.p);
+    hipLaunchKernelGGL((k_near_bx<QP, NT>), grid, blk, 0, s, r, nchunk, o.nF, nw, op->d_nborder.p, op->d_nbwork.p,
+                       op->d_nbpartner.p, op->d_nbslot.p, op->d_nb3.p, op->d_xnb.p, op->d_nbpart.p);
     IGE_HIP(hipGetLastError());
 }
 
-template <int MTW>
-void launch_bx_nt(ige_op op, int r, int NT, int nchunk, int Qp, hipStream_t s)
+template <int QP>
+void launch_bx_nt(ige_op op, int r, int NT, int nchunk, hipStream_t s)
 {
     switch (NT) {
-        case 1: launch_bx<MTW, 1>(op, r, nchunk, Qp, s); break;
-        case 2: launch_bx<MTW, 2>(op, r, nchunk, Qp, s); break;
-        default: launch_bx<MTW, 4>(op, r, nchunk, Qp, s); break;
+        case 1: launch_bx<QP, 1>(op, r, nchunk, s); break;
+        case 2: launch_bx<QP, 2>(op, r, nchunk, s); break;
+        default: launch_bx<QP, 4>(op, r, nchunk, s); break;
     }
 }
 }  // namespace
@@ -302,8 +304,10 @@ void near_bf16(ige_op op, int r, const double2 *xt, double2 *yt, hipStream_t s)
     const DevOp &o = op->view;
     IGE_REQUIRE(near_bf16_ok(o.nF), "near-field blocks too large for the split-BF16 product");
     ensure_near_bf16(op);
-    const int Qp = near_qp(o.nF), MTT = Qp / 16, MTW = (MTT + 3) / 4;
-    const int NT = r > 32 ? 4 : (r > 16 ? 2 : 1), ncol = 16 * NT, nchunk = (r + ncol - 1) / ncol;
+    const int Qp = near_qp(o.nF);
+    int NT = tune_get(op, kTuneNearBxNt, r, 0, r > 32 ? 4 : (r > 16 ? 2 : 1));
+    if (NT != 1 && NT != 2) NT = 4;
+    const int ncol = 16 * NT, nchunk = (r + ncol - 1) / ncol;
     const int64_t nleaf = (int64_t)o.P * o.SL * o.SL;
     const size_t xn = (size_t)nleaf * nchunk * 2 * ncol * 2 * Qp;
     if (op->d_xnb.n < xn) op->d_xnb.alloc(xn);
@@ -313,11 +317,15 @@ void near_bf16(ige_op op, int r, const double2 *xt, double2 *yt, hipStream_t s)
     hipLaunchKernelGGL(k_xnb_prep, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, s, nleaf, o.nF, Qp, r, ncol,
                        nchunk, o.leafdof, xt, op->d_xnb.p);
     IGE_HIP(hipGetLastError());
-    switch (MTW) {
-        case 1: launch_bx_nt<1>(op, r, NT, nchunk, Qp, s); break;
-        case 2: launch_bx_nt<2>(op, r, NT, nchunk, Qp, s); break;
-        case 3: launch_bx_nt<3>(op, r, NT, nchunk, Qp, s); break;
-        default: launch_bx_nt<4>(op, r, NT, nchunk, Qp, s); break;
+    switch (Qp) {
+        case 32: launch_bx_nt<32>(op, r, NT, nchunk, s); break;
+        case 64: launch_bx_nt<64>(op, r, NT, nchunk, s); break;
+        case 96: launch_bx_nt<96>(op, r, NT, nchunk, s); break;
+        case 128: launch_bx_nt<128>(op, r, NT, nchunk, s); break;
+        case 160: launch_bx_nt<160>(op, r, NT, nchunk, s); break;
+        case 192: launch_bx_nt<192>(op, r, NT, nchunk, s); break;
+        case 224: launch_bx_nt<224>(op, r, NT, nchunk, s); break;
+        default: launch_bx_nt<256>(op, r, NT, nchunk, s); break;
     }
     const int64_t tot = (int64_t)o.N * r;
     hipLaunchKernelGGL(k_nb_gather, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, (int64_t)o.N, r,

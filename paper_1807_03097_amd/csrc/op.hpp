@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <complex>
+#include <map>
 #include <memory>
 #include <vector>
 
@@ -86,6 +87,7 @@ struct ige_op_s {
     hipStream_t aux = nullptr;         // second stream: near-field product
     hipStream_t lst = nullptr;         // launch stream of the apply kernels (null: the context stream)
     hipStream_t gstream = nullptr;     // stream on which apply graphs are captured
+    std::map<long long, int> tune;     // autotuned tile choices: (knob, columns, precision) -> value
     bool overlap = true;               // near field concurrent with the far field
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int64_t prof_count = 0;
@@ -168,6 +170,15 @@ struct ige_op_s {
 
 namespace ige {
 
+// autotuned tile choices (ige_op_autotune); absent keys take the built-in default
+enum TuneKnob { kTuneM2lNcol = 0, kTuneNearBxNt = 1, kTuneNearMfmaNt = 2, kTuneM2lRb = 3, kTuneM2lDb = 4, kTuneKnobs = 5 };
+inline long long tune_key(int knob, int r, int prec) { return ((long long)knob << 40) | ((long long)r << 8) | prec; }
+inline int tune_get(const ige_op_s *op, int knob, int r, int prec, int def)
+{
+    const auto it = op->tune.find(tune_key(knob, r, prec));
+    return it == op->tune.end() ? def : it->second;
+}
+
 // stream the apply kernels are launched on (a capture stream while a graph is recorded)
 inline hipStream_t lstream(const ige_op_s *op) { return op->lst ? op->lst : op->ctx->stream; }
 
@@ -210,7 +221,8 @@ void launch_m2l_reduce(ige_op op);
 void launch_l2l(ige_op op);
 // near-field product; records mid (if given) between the block pass and the reduction
 void launch_spmv(ige_op op, const double2 *x, double2 *y, hipStream_t st, hipEvent_t mid = nullptr);
-int near_blk_u(int nF);   // 64-column groups per block row (template choice)
+int near_blk_u(int nF);
+int near_mfma_mtw_ok(int nF, int rc);   // the FP64 matrix-core near product supports these blocks   // 64-column groups per block row (template choice)
 void launch_l2p_leaf(ige_op op);
 void launch_l2p_gather(ige_op op, double2 *y);
 // scattered field at npts points (device arrays; src: potential_source_doubles scratch)

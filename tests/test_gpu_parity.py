@@ -320,6 +320,24 @@ def test_solve_graph_replays_equal_eager(ctx, monkeypatch, nrhs, prec):
     op.close()
 
 
+@pytest.mark.parametrize("prec", [0, 3, 4], ids=["f64", "splitbf16", "splitbf16-near"])
+def test_autotune_keeps_results(ctx, prec):
+    """The autotuner only changes tile shapes (column chunking); every column's
+    arithmetic and its order stay the same, so applies before and after tuning agree
+    to rounding of the unchanged order (checked to 1e-13)."""
+    from paper_1807_03097_amd import binding as B
+    geom = B.Geometry(ctx, _geom("sphere"))
+    op = B.Operator(geom, 2, 3, 8.0, 8, 1.6, 5, 5, 1)
+    X = np.stack([W.random_coeffs(op.N, 200 + s) for s in range(20)])
+    y0 = op.apply(X, prec=prec)
+    ch = op.autotune(20, prec)
+    y1 = op.apply(X, prec=prec)
+    err = max(_rel(y1[c], y0[c]) for c in range(len(X)))
+    _say(f"  prec {prec}: chosen {ch}, max rel change {err:.1e}")
+    assert ch and err <= 1e-13
+    op.close()
+
+
 def test_refinement_escalates_inner_precision(ctx):
     """Plain BF16 inner solves cannot reach 1e-10 alone (the inner operator's error
     times the condition number is too large); the refined solve moves the inner
