@@ -892,6 +892,7 @@ int ige_op_autotune(ige_op op, int r, int prec, int *choice, int nchoice)
             double best = 1e300;
             int bv = k.cand[0];
             for (int v : k.cand) {
+                if (k.id == ige::kTuneM2lNcol && v > ige::m2l_ncol_limit(op, r, split)) continue;   // not usable
                 op->tune[key] = v;
                 const double t = time_apply();
                 if (t < best) {

@@ -108,6 +108,45 @@ __global__ void k_vb_prep(DevOp o, int NC, int r, int rc, int nchunk, int ncol, 
     }
 }
 
+// The same conversion through shared memory: a workgroup takes 32 nodes of one field
+// of one cluster and one column chunk, reads them along the columns (coalesced, the
+// layout of src) and writes each column's 32-node runs of Re and Im (contiguous in Vb).
+constexpr int kVbRows = 32;
+__global__ __launch_bounds__(256) void k_vb_prep_t(DevOp o, int r, int rc, int nchunk, int ncol, int Qp, int split,
+                                                   const double2 *src, __bf16 *Vb)
+{
+    __shared__ double2 tile[kVbRows][65];   // [node][column in chunk], rc <= 64
+    const int Q = o.Q, K2 = 2 * Qp, nrb = Qp / kVbRows;
+    int b = blockIdx.x;
+    const int rb = b % nrb;
+    b /= nrb;
+    const int f = b % 4;
+    b /= 4;
+    const int ch = b % nchunk, gc = b / nchunk;
+    const int m0 = rb * kVbRows;
+    for (int i = threadIdx.x; i < kVbRows * rc; i += blockDim.x) {
+        const int mm = i / rc, j = i % rc, col = ch * rc + j, m = m0 + mm;
+        tile[mm][j] = (m < Q && col < r) ? src[(((size_t)gc * 4 + f) * Q + m) * r + col] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    const int64_t per = (int64_t)ncol * K2;
+    __bf16 *base = Vb + ((size_t)gc * nchunk + ch) * (split == 3 ? 2 : 1) * per;
+    for (int i = threadIdx.x; i < rc * 2 * kVbRows; i += blockDim.x) {
+        const int j = i / (2 * kVbRows), h = (i / kVbRows) & 1, mm = i % kVbRows;
+        const double2 t = tile[mm][j];
+        const double v = h ? t.y : t.x;
+        const size_t at = (size_t)(f * rc + j) * K2 + h * Qp + m0 + mm;
+        if (split == 1) {
+            base[at] = (__bf16)(float)v;
+        } else {
+            __bf16 hi, lo;
+            split_bf16(v, hi, lo);
+            base[at] = hi;
+            base[per + at] = lo;
+        }
+    }
+}
+
 __device__ inline bf8 neg_bf8(bf8 x)
 {
     uint4 u = __builtin_bit_cast(uint4, x);
@@ -170,13 +209,17 @@ __global__ __launch_bounds__(128 * WN) void k_m2l_mx(DevOp o, int r, int rc, int
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[a][t] = f4{0.f, 0.f, 0.f, 0.f};
 
+    // loads stay branch-free so that the waits before the products count only the
+    // loads they need: piece indices are checked only when the pieces do not divide
+    // evenly, and the prefetch after the last partner re-reads the last block
+    constexpr bool GEVEN = GCH % NTH == 0;
     uint4 gpre[PREF ? GV : 1];
     if (PREF) {
         const __bf16 *Gp = Gb + (size_t)gslot[wk.beg] * gper;
 #pragma unroll
         for (int v = 0; v < GV; ++v) {
             const int e = tid + NTH * v;
-            if (e < GCH) gpre[v] = g_piece(Gp, e);
+            if (GEVEN || e < GCH) gpre[v] = g_piece(Gp, e);
         }
     }
     bf8 bcur[NT][PL], bnxt[NT][PL];
@@ -187,48 +230,60 @@ __global__ __launch_bounds__(128 * WN) void k_m2l_mx(DevOp o, int r, int rc, int
 #pragma unroll
             for (int v = 0; v < GV; ++v) {
                 const int e = tid + NTH * v;
-                if (e < GCH) s_piece(e, gpre[v]);
+                if (GEVEN || e < GCH) s_piece(e, gpre[v]);
             }
         } else {
             const __bf16 *Gp = Gb + (size_t)gslot[kp] * gper;
             for (int e = tid; e < GCH; e += NTH) s_piece(e, g_piece(Gp, e));
         }
         __syncthreads();
-        if (PREF && kp + 1 < wk.end) {
-            const __bf16 *Gp = Gb + (size_t)gslot[kp + 1] * gper;
+        const int kq = min(kp + 1, wk.end - 1);   // next partner (the last one again at the end)
+        if (PREF) {
+            const __bf16 *Gp = Gb + (size_t)gslot[kq] * gper;
 #pragma unroll
             for (int v = 0; v < GV; ++v) {
                 const int e = tid + NTH * v;
-                if (e < GCH) gpre[v] = g_piece(Gp, e);
+                if (GEVEN || e < GCH) gpre[v] = g_piece(Gp, e);
             }
         }
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
             if (s + 1 < KS) b_load(bnxt, kp, s + 1);
-            else if (kp + 1 < wk.end) b_load(bnxt, kp + 1, 0);
+            else b_load(bnxt, kq, 0);
             // left factor: real rows [Gr, -Gi], imaginary rows [Gi, Gr] of the stored [Gr | Gi]
             const bool hi_half = 32 * s >= QP;
             const int kk = 32 * s + 8 * (lane >> 4);
             const int ksrc = wm == 0 ? kk : (hi_half ? kk - QP : kk + QP);
             const bool neg = wm == 0 && hi_half;
+            // row tiles in pairs; the three split products go over the pair's 2 NT
+            // accumulators in turn, so consecutive instructions never share an accumulator
 #pragma unroll
-            for (int a = 0; a < MT; ++a) {
-                const __bf16 *row = sG + (size_t)(16 * a + (lane & 15)) * LD + ksrc;
-                bf8 ah = *reinterpret_cast<const bf8 *>(row);
-                bf8 al;
-                if (SPLIT == 3) al = *reinterpret_cast<const bf8 *>(row + (size_t)QP * LD);
-                if (neg) {
-                    ah = neg_bf8(ah);
-                    if (SPLIT == 3) al = neg_bf8(al);
-                }
+            for (int a0 = 0; a0 < MT; a0 += 2) {
+                constexpr int NA = 2;
+                bf8 ah[NA], al[NA];
 #pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    acc[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bcur[t][0], acc[a][t], 0, 0, 0);
-                    if (SPLIT == 3) {
-                        acc[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bcur[t][PL - 1], acc[a][t], 0, 0, 0);
-                        acc[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bcur[t][0], acc[a][t], 0, 0, 0);
+                for (int u = 0; u < NA; ++u) {
+                    if (a0 + u >= MT) break;
+                    const __bf16 *row = sG + (size_t)(16 * (a0 + u) + (lane & 15)) * LD + ksrc;
+                    ah[u] = *reinterpret_cast<const bf8 *>(row);
+                    if (SPLIT == 3) al[u] = *reinterpret_cast<const bf8 *>(row + (size_t)QP * LD);
+                    if (neg) {
+                        ah[u] = neg_bf8(ah[u]);
+                        if (SPLIT == 3) al[u] = neg_bf8(al[u]);
                     }
                 }
+#pragma unroll
+                for (int term = 0; term < (SPLIT == 3 ? 3 : 1); ++term)
+#pragma unroll
+                    for (int u = 0; u < NA; ++u) {
+                        if (a0 + u >= MT) break;
+#pragma unroll
+                        for (int t = 0; t < NT; ++t) {
+                            const bf8 &A = term == 2 ? al[u] : ah[u];
+                            const bf8 &Bv = term == 1 ? bcur[t][PL - 1] : bcur[t][0];
+                            acc[a0 + u][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, Bv, acc[a0 + u][t], 0, 0, 0);
+                        }
+                    }
             }
 #pragma unroll
             for (int t = 0; t < NT; ++t)
@@ -319,8 +374,10 @@ __global__ __launch_bounds__(128 * WN) void k_m2l_mxd(DevOp o, int r, int rc, in
     for (int kp = wk.beg; kp < wk.end; ++kp) {
         const __bf16 *cur = sG + (size_t)((kp - wk.beg) & 1) * BUF;
         __bf16 *nxt = sG + (size_t)(((kp - wk.beg) & 1) ^ 1) * BUF;
-        const bool more = kp + 1 < wk.end;
-        const __bf16 *Gn = more ? Gb + (size_t)gslot[kp + 1] * gper : Gb;
+        // next partner (the last one again at the end: branch-free loads, see above)
+        const int kq = min(kp + 1, wk.end - 1);
+        const __bf16 *Gn = Gb + (size_t)gslot[kq] * gper;
+        constexpr bool GEVEN = GCH % NTH == 0;
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
             // this step's share of the next block, in flight during the products
@@ -328,37 +385,48 @@ __global__ __launch_bounds__(128 * WN) void k_m2l_mxd(DevOp o, int r, int rc, in
 #pragma unroll
             for (int v = 0; v < PPS; ++v) {
                 const int e = tid + NTH * (s * PPS + v);
-                if (more && s * PPS + v < GV && e < GCH) pc[v] = *reinterpret_cast<const uint4 *>(Gn + (size_t)8 * e);
+                if (s * PPS + v < GV && (GEVEN || e < GCH)) pc[v] = *reinterpret_cast<const uint4 *>(Gn + (size_t)8 * e);
             }
             if (s + 1 < KS) b_load(bnxt, kp, s + 1);
-            else if (more) b_load(bnxt, kp + 1, 0);
+            else b_load(bnxt, kq, 0);
             const bool hi_half = 32 * s >= QP;
             const int kk = 32 * s + 8 * (lane >> 4);
             const int ksrc = wm == 0 ? kk : (hi_half ? kk - QP : kk + QP);
             const bool neg = wm == 0 && hi_half;
+            // row tiles in pairs; the three split products go over the pair's 2 NT
+            // accumulators in turn, so consecutive instructions never share an accumulator
 #pragma unroll
-            for (int a = 0; a < MT; ++a) {
-                const __bf16 *row = cur + (size_t)(16 * a + (lane & 15)) * LD + ksrc;
-                bf8 ah = *reinterpret_cast<const bf8 *>(row);
-                bf8 al;
-                if (SPLIT == 3) al = *reinterpret_cast<const bf8 *>(row + (size_t)QP * LD);
-                if (neg) {
-                    ah = neg_bf8(ah);
-                    if (SPLIT == 3) al = neg_bf8(al);
-                }
+            for (int a0 = 0; a0 < MT; a0 += 2) {
+                constexpr int NA = 2;
+                bf8 ah[NA], al[NA];
 #pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    acc[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bcur[t][0], acc[a][t], 0, 0, 0);
-                    if (SPLIT == 3) {
-                        acc[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bcur[t][PL - 1], acc[a][t], 0, 0, 0);
-                        acc[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bcur[t][0], acc[a][t], 0, 0, 0);
+                for (int u = 0; u < NA; ++u) {
+                    if (a0 + u >= MT) break;
+                    const __bf16 *row = cur + (size_t)(16 * (a0 + u) + (lane & 15)) * LD + ksrc;
+                    ah[u] = *reinterpret_cast<const bf8 *>(row);
+                    if (SPLIT == 3) al[u] = *reinterpret_cast<const bf8 *>(row + (size_t)QP * LD);
+                    if (neg) {
+                        ah[u] = neg_bf8(ah[u]);
+                        if (SPLIT == 3) al[u] = neg_bf8(al[u]);
                     }
                 }
+#pragma unroll
+                for (int term = 0; term < (SPLIT == 3 ? 3 : 1); ++term)
+#pragma unroll
+                    for (int u = 0; u < NA; ++u) {
+                        if (a0 + u >= MT) break;
+#pragma unroll
+                        for (int t = 0; t < NT; ++t) {
+                            const bf8 &A = term == 2 ? al[u] : ah[u];
+                            const bf8 &Bv = term == 1 ? bcur[t][PL - 1] : bcur[t][0];
+                            acc[a0 + u][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, Bv, acc[a0 + u][t], 0, 0, 0);
+                        }
+                    }
             }
 #pragma unroll
             for (int v = 0; v < PPS; ++v) {
                 const int e = tid + NTH * (s * PPS + v);
-                if (more && s * PPS + v < GV && e < GCH) s_piece(nxt, e, pc[v]);
+                if (s * PPS + v < GV && (GEVEN || e < GCH)) s_piece(nxt, e, pc[v]);
             }
 #pragma unroll
             for (int t = 0; t < NT; ++t)
@@ -414,7 +482,7 @@ bool m2l_db_fits(int MT, int split) { return (size_t)2 * (split == 3 ? 2 : 1) * 
 // widest chunk (complex columns) without register spills; db: double-buffered kernel
 int m2l_ncol_cap(int MT, int split, bool db)
 {
-    if (db) return MT >= 8 ? 128 : (MT >= 6 && split == 3 ? 256 : 256);
+    if (db) return MT >= 8 ? 128 : 256;
     return MT >= 8 ? (split == 3 ? 64 : 128) : (MT >= 6 ? 128 : 256);
 }
 
@@ -484,6 +552,13 @@ void launch_mx_mt(ige_op op, int r, int MT, int ncol, const __bf16 *G, const __b
 
 }  // namespace
 
+int m2l_ncol_limit(ige_op op, int r, int split)
+{
+    const int MT = coupling_qp(op->view.Q) / 16;
+    const bool db = m2l_db_fits(MT, split) && tune_get(op, kTuneM2lDb, r, split, 1) != 0;
+    return m2l_ncol_cap(MT, split, db);
+}
+
 void m2l_bf16(ige_op op, int r, int split, const double2 *src, hipStream_t s, hipEvent_t mid)
 {
     const DevOp &o = op->view;
@@ -504,9 +579,15 @@ void m2l_bf16(ige_op op, int r, int split, const double2 *src, hipStream_t s, hi
     if (op->d_vb.n < vbn) op->d_vb.alloc(vbn);
     const size_t pn = op->mwork.size() * 4 * (size_t)o.Q * r;
     if (op->d_bmpart.n < pn) op->d_bmpart.alloc(pn);
-    const int64_t nv = (int64_t)op->NC * nchunk * ncol * K2;
-    hipLaunchKernelGGL(k_vb_prep, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s, o, op->NC, r, rc, nchunk, ncol,
-                       Qp, split, src, op->d_vb.p);
+    if (rc <= 64) {   // every element of the chunk's right factor is written (zeros in the padding)
+        const int64_t nb = (int64_t)op->NC * nchunk * 4 * (Qp / kVbRows);
+        hipLaunchKernelGGL(k_vb_prep_t, dim3((unsigned)nb), dim3(256), 0, s, o, r, rc, nchunk, ncol, Qp, split, src,
+                           op->d_vb.p);
+    } else {
+        const int64_t nv = (int64_t)op->NC * nchunk * ncol * K2;
+        hipLaunchKernelGGL(k_vb_prep, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s, o, op->NC, r, rc, nchunk,
+                           ncol, Qp, split, src, op->d_vb.p);
+    }
     IGE_HIP(hipGetLastError());
     if (mid) IGE_HIP(hipEventRecord(mid, s));
     if (db) {

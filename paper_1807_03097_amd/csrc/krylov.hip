@@ -23,8 +23,8 @@ namespace ige {
 namespace {
 
 constexpr int kWave = 64;
-constexpr int kGsT = 8;      // entries per lane of the dot kernel: a chunk is 64 kGsT entries
-constexpr int kGsE = 2;      // entries per thread of the update kernel: a block covers 256 kGsE
+constexpr int kGsT = 16;     // entries per lane of the dot kernel: a chunk is 64 kGsT entries
+constexpr int kGsE = 4;      // entries per thread of the update kernel: a block covers 256 kGsE
 constexpr int kFillBlocks = 2048;
 
 __device__ inline double2 wave_sum(double2 v)
@@ -62,17 +62,23 @@ __global__ __launch_bounds__(256) void k_gs_dot(int64_t n, int r, const double2 
     }
     const size_t slot0 = (size_t)c * (k + 1);
     const int k0 = blockIdx.z * kgs, k1 = min(k, k0 + kgs);
+    // whole chunks load without bounds checks (all kGsT loads of a lane in flight)
+    const bool full = (int64_t)(ch + 1) * kWave * kGsT <= n;
     for (int kk = k0 + wv; kk < k1; kk += 4) {
-        const double2 *v = V + ((size_t)kk * r + c) * n;
+        const double2 *v = V + ((size_t)kk * r + c) * n + i0;
+        double2 vv[kGsT];
+        if (full) {
+#pragma unroll
+            for (int t = 0; t < kGsT; ++t) vv[t] = v[kWave * t];
+        } else {
+#pragma unroll
+            for (int t = 0; t < kGsT; ++t) vv[t] = i0 + kWave * t < n ? v[kWave * t] : make_double2(0.0, 0.0);
+        }
         double2 a = make_double2(0.0, 0.0);
 #pragma unroll
         for (int t = 0; t < kGsT; ++t) {
-            const int64_t i = i0 + (int64_t)kWave * t;
-            if (i < n) {
-                const double2 vv = v[i];
-                a.x = fma(vv.x, wl[t].x, fma(vv.y, wl[t].y, a.x));
-                a.y = fma(vv.x, wl[t].y, fma(-vv.y, wl[t].x, a.y));
-            }
+            a.x = fma(vv[t].x, wl[t].x, fma(vv[t].y, wl[t].y, a.x));
+            a.y = fma(vv[t].x, wl[t].y, fma(-vv[t].y, wl[t].x, a.y));
         }
         a = wave_sum(a);
         if (lane == 0) part[(slot0 + kk) * nchk + ch] = a;
@@ -126,8 +132,28 @@ __global__ __launch_bounds__(256) void k_gs_upd(int64_t n, int r, const double2 
 #pragma unroll
     for (int e = 0; e < kGsE; ++e) acc[e] = make_double2(0.0, 0.0);
     const double2 *hc = h + (size_t)c * hs;
-#pragma unroll 4
-    for (int kk = k0; kk < k1; ++kk) {
+    // whole blocks: four basis vectors at a time with every load in flight
+    const bool full = (int64_t)(blockIdx.x + 1) * 256 * kGsE <= n;
+    int kk = k0;
+    if (full)
+        for (; kk + 4 <= k1; kk += 4) {
+            double2 vv[4][kGsE], hh[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                hh[u] = hc[kk + u];
+                const double2 *v = V + ((size_t)(kk + u) * r + c) * n + i0;
+#pragma unroll
+                for (int e = 0; e < kGsE; ++e) vv[u][e] = v[256 * e];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int e = 0; e < kGsE; ++e) {
+                    acc[e].x = fma(vv[u][e].x, hh[u].x, fma(-vv[u][e].y, hh[u].y, acc[e].x));
+                    acc[e].y = fma(vv[u][e].x, hh[u].y, fma(vv[u][e].y, hh[u].x, acc[e].y));
+                }
+        }
+    for (; kk < k1; ++kk) {
         const double2 hh = hc[kk];
         const double2 *v = V + ((size_t)kk * r + c) * n;
 #pragma unroll

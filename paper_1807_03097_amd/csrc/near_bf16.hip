@@ -97,7 +97,7 @@ __global__ void k_xnb_prep(int64_t nleaf, int nF, int Qp, int r, int ncol, int n
 }
 
 template <int QP, int NT>
-__global__ __launch_bounds__(256) void k_near_bx(int r, int nchunk, int nF, int64_t nwork,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_near_bx(int r, int nchunk, int nF, int64_t nwork,
                                                  const int32_t *order, const M2LWork *work, const int32_t *partner,
                                                  const int32_t *aslot, const __bf16 *Ab, const __bf16 *Xb,
                                                  float2 *part)
@@ -138,34 +138,41 @@ __global__ __launch_bounds__(256) void k_near_bx(int r, int nchunk, int nF, int6
                     xi[t][pl] = *reinterpret_cast<const bf8 *>(xc + pl * xper + Qp);
                 }
             }
+            // every row tile of this step loaded before the products (no bounds branch
+            // when the tiles divide evenly over the four waves)
+            bf8 ba[MTW][2][2];
 #pragma unroll
             for (int a = 0; a < MTW; ++a) {
                 const int mt = wv * MTW + a;
-                if (mt >= MTT) break;   // uniform over the wave
+                if (MTT % 4 != 0 && mt >= MTT) break;   // uniform over the wave
                 const __bf16 *arow = As + (size_t)(16 * mt + (lane & 15)) * K2 + k;
-                bf8 br[2], bi[2], nb[2];
 #pragma unroll
                 for (int pl = 0; pl < 2; ++pl) {
-                    br[pl] = *reinterpret_cast<const bf8 *>(arow + pl * (size_t)Qp * K2);
-                    bi[pl] = *reinterpret_cast<const bf8 *>(arow + pl * (size_t)Qp * K2 + Qp);
-                    nb[pl] = neg8(bi[pl]);
+                    ba[a][0][pl] = *reinterpret_cast<const bf8 *>(arow + pl * (size_t)Qp * K2);
+                    ba[a][1][pl] = *reinterpret_cast<const bf8 *>(arow + pl * (size_t)Qp * K2 + Qp);
                 }
+            }
+            // Yr += Ar Xr - Ai Xi, Yi += Ai Xr + Ar Xi, each as three split products
+            // (hi.hi, hi.lo, lo.hi); the loop over (term, tile, column tile) puts
+            // MTW NT independent accumulators between two updates of the same one
 #pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    // Yr += Ar Xr - Ai Xi
-                    ar[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(br[0], xr[t][0], ar[a][t], 0, 0, 0);
-                    ar[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(br[0], xr[t][1], ar[a][t], 0, 0, 0);
-                    ar[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(br[1], xr[t][0], ar[a][t], 0, 0, 0);
-                    ar[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nb[0], xi[t][0], ar[a][t], 0, 0, 0);
-                    ar[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nb[0], xi[t][1], ar[a][t], 0, 0, 0);
-                    ar[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nb[1], xi[t][0], ar[a][t], 0, 0, 0);
-                    // Yi += Ai Xr + Ar Xi
-                    ai[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bi[0], xr[t][0], ai[a][t], 0, 0, 0);
-                    ai[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bi[0], xr[t][1], ai[a][t], 0, 0, 0);
-                    ai[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bi[1], xr[t][0], ai[a][t], 0, 0, 0);
-                    ai[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(br[0], xi[t][0], ai[a][t], 0, 0, 0);
-                    ai[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(br[0], xi[t][1], ai[a][t], 0, 0, 0);
-                    ai[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(br[1], xi[t][0], ai[a][t], 0, 0, 0);
+            for (int term = 0; term < 3; ++term) {
+                const int pa = term == 2 ? 1 : 0, px = term == 1 ? 1 : 0;
+#pragma unroll
+                for (int a = 0; a < MTW; ++a) {
+                    const int mt = wv * MTW + a;
+                    if (MTT % 4 != 0 && mt >= MTT) break;
+                    const bf8 br = ba[a][0][pa], bi = ba[a][1][pa], nb = neg8(bi);
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        ar[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(br, xr[t][px], ar[a][t], 0, 0, 0);
+                        ai[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bi, xr[t][px], ai[a][t], 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        ar[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nb, xi[t][px], ar[a][t], 0, 0, 0);
+                        ai[a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(br, xi[t][px], ai[a][t], 0, 0, 0);
+                    }
                 }
             }
         }
@@ -178,7 +185,7 @@ __global__ __launch_bounds__(256) void k_near_bx(int r, int nchunk, int nF, int6
 #pragma unroll
         for (int a = 0; a < MTW; ++a) {
             const int mt = wv * MTW + a;
-            if (mt >= MTT) break;
+            if (MTT % 4 != 0 && mt >= MTT) break;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int m = 16 * mt + 4 * (lane >> 4) + j;
@@ -307,6 +314,7 @@ void near_bf16(ige_op op, int r, const double2 *xt, double2 *yt, hipStream_t s)
     const int Qp = near_qp(o.nF);
     int NT = tune_get(op, kTuneNearBxNt, r, 0, r > 32 ? 4 : (r > 16 ? 2 : 1));
     if (NT != 1 && NT != 2) NT = 4;
+    if (Qp > 192 && NT == 4) NT = 2;   // four column tiles of the widest blocks would spill registers
     const int ncol = 16 * NT, nchunk = (r + ncol - 1) / ncol;
     const int64_t nleaf = (int64_t)o.P * o.SL * o.SL;
     const size_t xn = (size_t)nleaf * nchunk * 2 * ncol * 2 * Qp;

@@ -212,6 +212,8 @@ void m2l_stored_reduce_one(ige_op op);
 // fields [NC][4][Q][r] -> partials per work item [mwork][4][Q][r] (d_bmpart)
 void m2l_bf16(ige_op op, int r, int split, const double2 *src, hipStream_t s, hipEvent_t mid = nullptr);
 void ensure_coupling_bf16(ige_op op, int split);
+// widest usable coupling chunk (complex columns) for the current staging choice
+int m2l_ncol_limit(ige_op op, int r, int split);
 // split-BF16 near-field product (yt = near part of A x, [N][r] layout)
 void plan_near_bf16(ige_op op, const std::vector<int32_t> &pair, const std::vector<int32_t> &leafdof, int nF);
 void ensure_near_bf16(ige_op op);

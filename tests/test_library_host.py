@@ -57,6 +57,11 @@ def test_invalid_geometry_is_rejected():
     op = B.Operator(g, 1, 1, 1.0, plan_only=True)
     with pytest.raises(B.IgeError):
         op.apply(np.zeros(op.N, np.complex128))      # planned, not assembled
+    with pytest.raises(B.IgeError) as e:
+        op.autotune(4, B.IGE_BF16X3)                 # planned, not assembled
+    assert e.value.code == B.IGE_EINVAL
+    with pytest.raises(B.IgeError):
+        op.apply(np.zeros(op.N, np.complex128), prec=5)   # no such precision
 
 
 @pytest.mark.parametrize("geom,p,m,eta,d,q", [
