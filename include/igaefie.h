@@ -176,10 +176,12 @@ int ige_apply(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind);
 int ige_apply_prec(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind, int coupling_prec);
 
 /* Autotuner for the r-column apply in precision prec: times every candidate tile
- * shape of the kernels that apply uses (coordinate descent, each candidate one
- * warm-up and three timed applies on seeded N(0,1) + iN(0,1) columns, HIP events on
- * the context stream) and keeps the fastest for later applies and solves with the
- * same (r, prec).  Knobs, in choice[] order (-1: not used by this apply):
+ * shape of the kernels that apply uses (coordinate descent; each candidate in two
+ * rounds of one warm-up and three timed applies on seeded N(0,1) + iN(0,1) columns,
+ * HIP events on the context stream, the minimum kept) and keeps a candidate for
+ * later applies and solves with the same (r, prec) only when it beats the built-in
+ * default by more than 2 %.  Knobs, in choice[] order (-1: not used by this apply
+ * or the built-in rule kept, where the rule depends on r):
  *   0 coupling column chunk of the BF16 matrix-core coupling (64, 128, 256 complex
  *     columns, capped where registers would spill),
  *   1 column tiles per wave of the split-BF16 near-field product (1, 2, 4),

@@ -288,6 +288,7 @@ __global__ __launch_bounds__(256) void k_m2m_b(DevOp o, int lvl, int r, double2 
     const int gc = (int)o.lvl_off[lvl] + id;
     double2 *acc = sm2;               // [3 fields][Q][kRB]
     double2 *W = acc + 3 * Q * kRB;   // [Q1 (n2)][Q1 (m1)][kRB], one field of one child at a time
+    double2 *X = W + Q * kRB;         // the child's field, staged once (coalesced along columns)
     for (int i = threadIdx.x; i < 3 * Q * kRB; i += blockDim.x) acc[i] = make_double2(0, 0);
     for (int ch = 0; ch < 4; ++ch) {
         const int c1 = ch & 1, c2 = ch >> 1;
@@ -297,11 +298,14 @@ __global__ __launch_bounds__(256) void k_m2m_b(DevOp o, int lvl, int r, double2 
         for (int f = 0; f < 3; ++f) {
             __syncthreads();
             for (int i = threadIdx.x; i < Q * kRB; i += blockDim.x) {
+                const int c = i % kRB, q = i / kRB;
+                X[i] = c < nc ? cm[((size_t)f * Q + q) * r + c0 + c] : make_double2(0, 0);
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < Q * kRB; i += blockDim.x) {
                 const int c = i % kRB, nm = i / kRB, n2 = nm / Q1, m1 = nm % Q1;
                 double2 z = make_double2(0, 0);
-                if (c < nc)
-                    for (int n1 = 0; n1 < Q1; ++n1)
-                        z = caddb(z, cscaleb(Tu[n1 * Q1 + m1], cm[((size_t)f * Q + n2 * Q1 + n1) * r + c0 + c]));
+                for (int n1 = 0; n1 < Q1; ++n1) z = caddb(z, cscaleb(Tu[n1 * Q1 + m1], X[(n2 * Q1 + n1) * kRB + c]));
                 W[i] = z;
             }
             __syncthreads();
@@ -471,13 +475,17 @@ __global__ __launch_bounds__(256) void k_l2l_b(DevOp o, int lvl, int r, double2 
     const int c1 = k1 & 1, c2 = k2 & 1;
     const double *Tu = c1 ? o.T1 : o.T0, *Tv = c2 ? o.T1 : o.T0;
     const double2 *par = loc + (size_t)pgc * 3 * Q * r;
-    double2 *W = sm2;   // [3][Q1 (m2)][Q1 (n1)][kRB]
+    double2 *W = sm2;                 // [3][Q1 (m2)][Q1 (n1)][kRB]
+    double2 *X = W + 3 * Q * kRB;     // the parent's fields, staged once (coalesced along columns)
+    for (int i = threadIdx.x; i < 3 * Q * kRB; i += blockDim.x) {
+        const int c = i % kRB, t = i / kRB;
+        X[i] = c < nc ? par[(size_t)t * r + c0 + c] : make_double2(0, 0);
+    }
+    __syncthreads();
     for (int i = threadIdx.x; i < 3 * Q * kRB; i += blockDim.x) {
         const int c = i % kRB, t = i / kRB, f = t / Q, rem = t % Q, m2 = rem / Q1, n1 = rem % Q1;
         double2 z = make_double2(0, 0);
-        if (c < nc)
-            for (int m1 = 0; m1 < Q1; ++m1)
-                z = caddb(z, cscaleb(Tu[n1 * Q1 + m1], par[((size_t)f * Q + m2 * Q1 + m1) * r + c0 + c]));
+        for (int m1 = 0; m1 < Q1; ++m1) z = caddb(z, cscaleb(Tu[n1 * Q1 + m1], X[((f * Q) + m2 * Q1 + m1) * kRB + c]));
         W[i] = z;
     }
     __syncthreads();
@@ -626,7 +634,7 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
         }
         mark(1);
         {
-            const size_t per = sizeof(double2) * 4 * o.Q;
+            const size_t per = sizeof(double2) * 5 * o.Q;   // accumulators, intermediate, staged child
             const int rb = pick_rb(per);
             for (int lvl = o.L - 1; lvl >= 0; --lvl) {
                 IGE_RB_SWITCH(rb, k_m2m_b, dim3(o.P << (2 * lvl), chunks(rb)), dim3(256), per * rb, s, o, lvl, r,
@@ -678,7 +686,7 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
         }
         mark(4);
         {
-            const size_t per = sizeof(double2) * 3 * o.Q;
+            const size_t per = sizeof(double2) * 6 * o.Q;   // intermediate and staged parent
             const int rb = pick_rb(per);
             for (int lvl = 1; lvl <= o.L; ++lvl) {
                 IGE_RB_SWITCH(rb, k_l2l_b, dim3(o.P << (2 * lvl), chunks(rb)), dim3(256), per * rb, s, o, lvl, r,

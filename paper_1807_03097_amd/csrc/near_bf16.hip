@@ -102,10 +102,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                                                  const int32_t *aslot, const __bf16 *Ab, const __bf16 *Xb,
                                                  float2 *part)
 {
-    // QP: slots rounded up to 32; the reduction loop is unrolled so that the next
-    // step's loads can be issued ahead of the current step's products
+    // QP: slots rounded up to 32.  The right factor of each reduction step (all columns,
+    // 32 slots, re and im, both planes) is staged once per workgroup in shared memory,
+    // double-buffered: the next step's share is loaded during the current products and
+    // stored after them (one barrier per step).  The left factor rows of each wave are
+    // read straight from memory (no wave shares them).
     constexpr int NCOL = 16 * NT, Qp = QP, K2 = 2 * QP, KS = QP / 32, MTT = QP / 16, MTW = (MTT + 3) / 4;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    constexpr int LDX = 72;                    // staged column: 32 re + 32 im + padding
+    constexpr int XP = 2 * NCOL * 2 * 4;       // 16-byte pieces per step: planes, columns, re/im, 4
+    constexpr int XV = (XP + 255) / 256;       // pieces per thread
+    __shared__ __bf16 sX[2][2][NCOL][LDX];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     // the chunks of one work item share an XCD (consecutive ids go round-robin over 8)
     const int64_t g = blockIdx.x;
     const int64_t wo = (g / (8 * nchunk)) * 8 + g % 8;
@@ -114,6 +121,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const int64_t wi = order[wo];
     const M2LWork wk = work[wi];
     const size_t aper = (size_t)2 * Qp * K2, xper = (size_t)NCOL * K2;
+    auto xsrc = [&](int kp) { return Xb + ((size_t)partner[kp] * nchunk + ch) * 2 * xper; };
+    // piece e of step s: plane, column, re/im, quarter (quarters of one 64-byte run adjacent)
+    auto x_load = [&](const __bf16 *Xs, int s, int e) -> uint4 {
+        const int q = e & 3, h = (e >> 2) & 1, n = (e >> 3) % NCOL, pl = (e >> 3) / NCOL;
+        return *reinterpret_cast<const uint4 *>(Xs + pl * xper + (size_t)n * K2 + h * Qp + 32 * s + 8 * q);
+    };
+    auto x_store = [&](int buf, int e, uint4 v) {
+        const int q = e & 3, h = (e >> 2) & 1, n = (e >> 3) % NCOL, pl = (e >> 3) / NCOL;
+        *reinterpret_cast<uint4 *>(&sX[buf][pl][n][32 * h + 8 * q]) = v;
+    };
     f4 ar[MTW][NT], ai[MTW][NT];
 #pragma unroll
     for (int a = 0; a < MTW; ++a)
@@ -122,22 +139,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             ar[a][t] = f4{0.f, 0.f, 0.f, 0.f};
             ai[a][t] = f4{0.f, 0.f, 0.f, 0.f};
         }
+    {   // first step straight into buffer 0
+        const __bf16 *Xs = xsrc(wk.beg);
+#pragma unroll
+        for (int v = 0; v < XV; ++v) {
+            const int e = tid + 256 * v;
+            if (XP % 256 == 0 || e < XP) x_store(0, e, x_load(Xs, 0, e));
+        }
+    }
+    __syncthreads();
+    int buf = 0;
     for (int kp = wk.beg; kp < wk.end; ++kp) {
         const __bf16 *As = Ab + (size_t)aslot[kp] * aper;
-        const __bf16 *Xs = Xb + ((size_t)partner[kp] * nchunk + ch) * 2 * xper;
+        const __bf16 *Xs = xsrc(kp);
+        const __bf16 *Xn = xsrc(min(kp + 1, wk.end - 1));   // (the last partner again at the end)
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
-            const int k = 32 * s + 8 * (lane >> 4);
-            bf8 xr[NT][2], xi[NT][2];
+            // the next step's share of the right factor, in flight during the products
+            uint4 pc[XV];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const __bf16 *xc = Xs + (size_t)(16 * t + (lane & 15)) * K2 + k;
-#pragma unroll
-                for (int pl = 0; pl < 2; ++pl) {
-                    xr[t][pl] = *reinterpret_cast<const bf8 *>(xc + pl * xper);
-                    xi[t][pl] = *reinterpret_cast<const bf8 *>(xc + pl * xper + Qp);
-                }
+            for (int v = 0; v < XV; ++v) {
+                const int e = tid + 256 * v;
+                if (XP % 256 == 0 || e < XP) pc[v] = s + 1 < KS ? x_load(Xs, s + 1, e) : x_load(Xn, 0, e);
             }
+            const int k = 32 * s + 8 * (lane >> 4);
             // every row tile of this step loaded before the products (no bounds branch
             // when the tiles divide evenly over the four waves)
             bf8 ba[MTW][2][2];
@@ -152,6 +177,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                     ba[a][1][pl] = *reinterpret_cast<const bf8 *>(arow + pl * (size_t)Qp * K2 + Qp);
                 }
             }
+            bf8 xr[NT][2], xi[NT][2];
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int pl = 0; pl < 2; ++pl) {
+                    const __bf16 *xc = &sX[buf][pl][16 * t + (lane & 15)][8 * (lane >> 4)];
+                    xr[t][pl] = *reinterpret_cast<const bf8 *>(xc);
+                    xi[t][pl] = *reinterpret_cast<const bf8 *>(xc + 32);
+                }
             // Yr += Ar Xr - Ai Xi, Yi += Ai Xr + Ar Xi, each as three split products
             // (hi.hi, hi.lo, lo.hi); the loop over (term, tile, column tile) puts
             // MTW NT independent accumulators between two updates of the same one
@@ -175,6 +209,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                     }
                 }
             }
+#pragma unroll
+            for (int v = 0; v < XV; ++v) {
+                const int e = tid + 256 * v;
+                if (XP % 256 == 0 || e < XP) x_store(buf ^ 1, e, pc[v]);
+            }
+            __syncthreads();   // next step staged; this step's buffer is free
+            buf ^= 1;
         }
     }
     // lane holds D[4 (lane/16) + j][lane % 16] of each tile
@@ -314,7 +355,7 @@ void near_bf16(ige_op op, int r, const double2 *xt, double2 *yt, hipStream_t s)
     const int Qp = near_qp(o.nF);
     int NT = tune_get(op, kTuneNearBxNt, r, 0, r > 32 ? 4 : (r > 16 ? 2 : 1));
     if (NT != 1 && NT != 2) NT = 4;
-    if (Qp > 192 && NT == 4) NT = 2;   // four column tiles of the widest blocks would spill registers
+    if (NT == 4 && (Qp == 160 || Qp > 192)) NT = 2;   // four column tiles would spill registers there
     const int ncol = 16 * NT, nchunk = (r + ncol - 1) / ncol;
     const int64_t nleaf = (int64_t)o.P * o.SL * o.SL;
     const size_t xn = (size_t)nleaf * nchunk * 2 * ncol * 2 * Qp;
