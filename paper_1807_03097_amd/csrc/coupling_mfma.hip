@@ -28,6 +28,10 @@
 #include "device_math.hpp"
 #include "op.hpp"
 
+#ifndef IGE_GPAD
+#define IGE_GPAD 8   // padding (BF16 elements) of a staged block row in shared memory
+#endif
+
 namespace ige {
 
 namespace {
@@ -166,7 +170,7 @@ __global__ __launch_bounds__(128 * WN) void k_m2l_mx(DevOp o, int r, int rc, int
                                                      const __bf16 *Vb, float2 *part)
 {
     constexpr int PL = SPLIT == 3 ? 2 : 1;   // BF16 planes per factor
-    constexpr int QP = 16 * MT, K2 = 2 * QP, KS = K2 / 32, LD = K2 + 8;
+    constexpr int QP = 16 * MT, K2 = 2 * QP, KS = K2 / 32, LD = K2 + IGE_GPAD;
     constexpr int NTH = 128 * WN, NCOL = 16 * WN * NT;
     constexpr int GCH = PL * QP * K2 / 8;           // 16-byte pieces of one block
     constexpr int GV = (GCH + NTH - 1) / NTH;       // pieces per thread
@@ -324,7 +328,7 @@ __global__ __launch_bounds__(128 * WN) void k_m2l_mxd(DevOp o, int r, int rc, in
                                                       const __bf16 *Vb, float2 *part)
 {
     constexpr int PL = SPLIT == 3 ? 2 : 1;
-    constexpr int QP = 16 * MT, K2 = 2 * QP, KS = K2 / 32, LD = K2 + 8;
+    constexpr int QP = 16 * MT, K2 = 2 * QP, KS = K2 / 32, LD = K2 + IGE_GPAD;
     constexpr int NTH = 128 * WN, NCOL = 16 * WN * NT;
     constexpr int GCH = PL * QP * K2 / 8;           // 16-byte pieces of one block
     constexpr int GV = (GCH + NTH - 1) / NTH;       // pieces per thread
@@ -477,7 +481,7 @@ namespace {
 // block and the streamed factor stay in registers (no spills)
 // double-buffered staging: both buffers fit in shared memory (64 KB is the limit for
 // dynamic shared memory granted without asking; up to 160 KB after the attribute)
-bool m2l_db_fits(int MT, int split) { return (size_t)2 * (split == 3 ? 2 : 1) * 16 * MT * (32 * MT + 8) * 2 <= 160 * 1024; }
+bool m2l_db_fits(int MT, int split) { return (size_t)2 * (split == 3 ? 2 : 1) * 16 * MT * (32 * MT + IGE_GPAD) * 2 <= 160 * 1024; }
 
 // widest chunk (complex columns) without register spills; db: double-buffered kernel
 int m2l_ncol_cap(int MT, int split, bool db)
@@ -501,7 +505,7 @@ void launch_mx(ige_op op, int r, int rc, int nchunk, const __bf16 *G, const __bf
     const int64_t nw = (int64_t)op->mwork.size();
     const dim3 grid((unsigned)(((nw + 7) / 8) * 8 * nchunk)), blk(128 * WN);
     constexpr int PL = SPLIT == 3 ? 2 : 1, QP = 16 * MT;
-    constexpr size_t shm = sizeof(__bf16) * (DB ? 2 : 1) * PL * QP * (2 * QP + 8);
+    constexpr size_t shm = sizeof(__bf16) * (DB ? 2 : 1) * PL * QP * (2 * QP + IGE_GPAD);
     auto kern = DB ? &k_m2l_mxd<SPLIT, MT, WN, NT> : &k_m2l_mx<SPLIT, MT, WN, NT>;
     static bool attr = false;   // the attribute is set once per kernel, before any graph capture
     if (!attr) {
