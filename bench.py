@@ -341,9 +341,33 @@ def main():
     # roofline of the dominant kernel (durations from the timed region)
     traffic_ref = load_traffic(r)
 
+    def roofline_coupling(stage_ms):
+        """Matrix-core coupling (r > 1, BF16 precisions): issued BF16 matrix-core
+        operations of the real product [[Gr,-Gi],[Gi,Gr]] . [Re V; Im V] over padded
+        2Qp x 2Qp blocks and column chunks, over the kernel's own time."""
+        if args.prec < 2 or r == 1:
+            return None
+        Q = (q + 1) ** 2
+        Qp = 32 * ((Q + 31) // 32)
+        MT, split = Qp // 16, (1 if args.prec == 2 else 3)
+        cap = (64 if split == 3 else 128) if MT >= 8 else (128 if MT >= 6 else 256)
+        ncol = 16
+        while ncol < 4 * r and ncol < cap:
+            ncol *= 2
+        nchunk = -(-r // (ncol // 4))
+        issued = info.far_pairs * nchunk * 2.0 * (2 * Qp) * (2 * Qp) * ncol * split
+        useful = info.far_pairs * 8.0 * Q * Q * 4 * r
+        t_ms = stage_ms["m2l_kernel"]
+        ach = issued / (t_ms * 1e-3) / 1e12
+        return {"kernel": "k_m2l_mx", "bound": "mfma", "achieved": ach, "peak": BF16_MFMA_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": ach / BF16_MFMA_PEAK_TFLOPS, "traffic": None,
+                "useful_tflops": useful / (t_ms * 1e-3) / 1e12, "issued_flop": issued, "avg_ms": t_ms}
+
     def roofline(stage_ms):
         stages = {k: v for k, v in stage_ms.items() if k not in ("near_blk", "m2l_kernel")}
         dom = max(stages, key=stages.get)
+        if dom == "m2l" and args.prec >= 2 and r > 1:
+            return roofline_coupling(stage_ms)   # the BF16 matrix-core coupling kernel
         Q = (q + 1) ** 2
         if dom == "near_spmv" and r > 1:
             # many columns: matrix-core products over every ordered leaf pair (block and
@@ -385,30 +409,16 @@ def main():
                 "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
                 "node_pairs": int(entries), "avg_ms": stage_ms[dom]}
 
-    def roofline_coupling(stage_ms):
-        """Matrix-core coupling (r > 1, BF16 precisions): issued BF16 matrix-core
-        operations of the real product [[Gr,-Gi],[Gi,Gr]] . [Re V; Im V] over padded
-        2Qp x 2Qp blocks and column chunks, over the kernel's own time."""
-        if args.prec < 2 or r == 1:
-            return None
-        Q = (q + 1) ** 2
-        Qp = 32 * ((Q + 31) // 32)
-        MT, split = Qp // 16, (1 if args.prec == 2 else 3)
-        cap = (64 if split == 3 else 128) if MT >= 8 else (128 if MT >= 6 else 256)
-        ncol = 16
-        while ncol < 4 * r and ncol < cap:
-            ncol *= 2
-        nchunk = -(-r // (ncol // 4))
-        issued = info.far_pairs * nchunk * 2.0 * (2 * Qp) * (2 * Qp) * ncol * split
-        useful = info.far_pairs * 8.0 * Q * Q * 4 * r
-        t_ms = stage_ms["m2l_kernel"]
-        ach = issued / (t_ms * 1e-3) / 1e12
-        return {"kernel": "k_m2l_mx", "bound": "mfma", "achieved": ach, "peak": BF16_MFMA_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": ach / BF16_MFMA_PEAK_TFLOPS, "traffic": None,
-                "useful_tflops": useful / (t_ms * 1e-3) / 1e12, "issued_flop": issued, "avg_ms": t_ms}
-
     roof = roofline(st)
     roof_cpl = roofline_coupling(st)
+    # error of a reduced-precision apply against the FP64 apply of the same columns
+    err_fp64 = None
+    if args.prec != 0:
+        y64 = torch.empty_like(x)
+        op.apply(x, y64, prec=0)
+        torch.cuda.synchronize()
+        err_fp64 = float(torch.linalg.vector_norm(y - y64) / torch.linalg.vector_norm(y64))
+        log(f"relative error vs the FP64 apply: {err_fp64:.2e}")
     # the same kernels timed in isolation (stages in order on one stream)
     op.set_overlap(False)
     op.set_profiling(True)
@@ -455,6 +465,7 @@ def main():
         "roofline": roof,
         "roofline_isolated": roof_iso,
         "roofline_coupling": roof_cpl,
+        "rel_err_vs_fp64": err_fp64,
         "autotuned": tuned,
         "stage_ms_isolated": st_iso,
         "cpu_baseline": cpu,

@@ -137,3 +137,39 @@ def test_solution_alone_equals_solution_in_mix():
     for g in geoms.values():
         g.close()
     ctx.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("inner", [3, 4], ids=["split-coupling", "split-coupling-and-near"])
+def test_refined_requests_meet_the_fp64_tolerance(inner):
+    """Requests solved by FP64 refinement around lower-precision inner solves (several
+    at once) reach the tolerance on the FP64 operator and the FP64 solution."""
+    from paper_1807_03097_amd import binding as B
+    ctx = B.Context(0)
+    geoms = {n: _geom(B, ctx, n) for n in ("sphere", "torus", "jittered")}
+    reqs = REQS[:4]
+    ref = []
+    for (n, p, m, kap, q, eta, d, seed) in reqs:
+        op = B.Operator(geoms[n], p, m, kap, q, eta, 5, 5, d)
+        di, pol = _wave(seed)
+        x, st, rc = op.solve(op.rhs_plane_wave(di, pol)[0], tol=TOL, restart=300, maxit=3000)
+        assert rc == 0
+        ref.append(x)
+        op.close()
+    srv = B.Server(ctx, 3)
+    ts = []
+    for (n, p, m, kap, q, eta, d, seed) in reqs:
+        di, pol = _wave(seed)
+        ts.append(srv.submit(geoms[n], p, m, kap, di, pol, q=q, eta=eta, leaf_depth=d, tol=TOL, restart=300,
+                             maxit=6000, refine=True, inner_tol=1e-4, inner_prec=inner))
+    for k, t in enumerate(ts):
+        x, st = srv.result(t)
+        err = np.linalg.norm(x - ref[k]) / np.linalg.norm(ref[k])
+        print(f"request {k}: inner {inner} iters={st['iters']} relres={st['relres']:.1e} vs FP64 {err:.1e}",
+              flush=True)
+        assert st["rc"] == 0 and st["relres"] <= TOL * 1.05
+        assert err <= 1e-6
+    srv.close()
+    for g in geoms.values():
+        g.close()
+    ctx.close()
