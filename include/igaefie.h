@@ -190,7 +190,9 @@ int ige_apply_prec(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind,
  *     shared memory),
  *   4 staging of the BF16 coupling blocks: 1 double-buffered (the next block loaded
  *     step by step during the current product), 0 one buffer with the next block
- *     prefetched into registers.
+ *     prefetched into registers,
+ *   5 launch order of the BF16 coupling work items: 0 by decreasing partner count,
+ *     1 in cluster order with one contiguous part (equal partner counts) per XCD.
  * Returns the number of timed configurations (>= 0) or an error status (< 0). */
 int ige_op_autotune(ige_op op, int r, int prec, int *choice, int nchoice);
 

@@ -493,6 +493,30 @@ ige_op ige::assemble_on(ige_ctx ctx, const ige_geom_s *geom, const ige_params &p
                         return op->mwork[a].end - op->mwork[a].beg > op->mwork[b].end - op->mwork[b].beg;
                     });
                     op->d_morder.upload(morder, s);
+                    // alternative launch order: the work items in cluster order (neighbouring
+                    // targets share partners) cut into 8 contiguous parts of equal partner
+                    // counts, part x on XCD x (consecutive workgroups go round-robin over the
+                    // eight XCDs), so partners' right factors are reused in that XCD's L2
+                    {
+                        const size_t nw = op->mwork.size();
+                        int64_t total = 0;
+                        for (const auto &w : op->mwork) total += w.end - w.beg;
+                        std::vector<std::vector<int32_t>> parts(8);
+                        int64_t acc = 0;
+                        for (size_t w = 0; w < nw; ++w) {
+                            const int x = (int)std::min<int64_t>(7, total > 0 ? acc * 8 / total : 0);
+                            parts[x].push_back((int32_t)w);
+                            acc += op->mwork[w].end - op->mwork[w].beg;
+                        }
+                        std::vector<int32_t> sp;
+                        sp.reserve(nw + 8);
+                        size_t longest = 0;
+                        for (const auto &pt : parts) longest = std::max(longest, pt.size());
+                        for (size_t i = 0; i < longest; ++i)
+                            for (int x = 0; x < 8; ++x) sp.push_back(i < parts[x].size() ? parts[x][i] : -1);
+                        op->d_morder_sp.upload(sp, s);
+                        op->n_morder_sp = (int64_t)sp.size();
+                    }
                     op->d_mwork.upload(op->mwork, s);
                     op->d_mpartner.upload(mpart, s);
                     op->d_gslot.upload(gslot, s);
@@ -873,6 +897,7 @@ int ige_op_autotune(ige_op op, int r, int prec, int *choice, int nchoice)
         auto default_of = [&](int id) {
             switch (id) {
                 case ige::kTuneM2lDb: return 1;
+                case ige::kTuneM2lOrder: return 0;
                 case ige::kTuneM2lNcol: return -1;   // the smallest chunk holding all columns
                 case ige::kTuneNearBxNt:
                 case ige::kTuneNearMfmaNt: return r > 32 ? 4 : (r > 16 ? 2 : 1);
@@ -890,7 +915,8 @@ int ige_op_autotune(ige_op op, int r, int prec, int *choice, int nchoice)
             std::vector<int> cand;
         };
         const bool mxon = mx && !op->mwork.empty();
-        const Knob knobs[ige::kTuneKnobs] = {{mxon, ige::kTuneM2lDb, split, {1, 0}},
+        const Knob knobs[ige::kTuneKnobs] = {{mxon, ige::kTuneM2lOrder, split, {1}},
+                                            {mxon, ige::kTuneM2lDb, split, {1, 0}},
                                             {mxon, ige::kTuneM2lNcol, split, {64, 128, 256}},
                                             {near_bx, ige::kTuneNearBxNt, 0, {1, 2, 4}},
                                             {near_mfma, ige::kTuneNearMfmaNt, 0, {1, 2, 4}},

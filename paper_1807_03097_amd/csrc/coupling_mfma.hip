@@ -184,6 +184,7 @@ __global__ __launch_bounds__(128 * WN) void k_m2l_mx(DevOp o, int r, int rc, int
     const int ch = (int)((g / 8) % nchunk);
     if (wo >= nwork) return;
     const int64_t wi = order[wo];
+    if (wi < 0) return;   // padding slot of a launch order
     const M2LWork wk = work[wi];
     if (wk.beg >= wk.end) return;
     const size_t gper = (size_t)PL * QP * K2, vper = (size_t)NCOL * K2;
@@ -342,6 +343,7 @@ __global__ __launch_bounds__(128 * WN) void k_m2l_mxd(DevOp o, int r, int rc, in
     const int ch = (int)((g / 8) % nchunk);
     if (wo >= nwork) return;
     const int64_t wi = order[wo];
+    if (wi < 0) return;   // padding slot of a launch order
     const M2LWork wk = work[wi];
     if (wk.beg >= wk.end) return;
     const size_t gper = (size_t)PL * QP * K2, vper = (size_t)NCOL * K2;
@@ -502,7 +504,10 @@ template <bool DB, int SPLIT, int MT, int WN, int NT>
 void launch_mx(ige_op op, int r, int rc, int nchunk, const __bf16 *G, const __bf16 *Vb, hipStream_t s)
 {
     const DevOp &o = op->view;
-    const int64_t nw = (int64_t)op->mwork.size();
+    // launch order: decreasing partner count (default) or cluster order per XCD
+    const bool spatial = tune_get(op, kTuneM2lOrder, r, SPLIT, 0) == 1 && op->n_morder_sp > 0;
+    const int64_t nw = spatial ? op->n_morder_sp : (int64_t)op->mwork.size();
+    const int32_t *order = spatial ? op->d_morder_sp.p : op->d_morder.p;
     const dim3 grid((unsigned)(((nw + 7) / 8) * 8 * nchunk)), blk(128 * WN);
     constexpr int PL = SPLIT == 3 ? 2 : 1, QP = 16 * MT;
     constexpr size_t shm = sizeof(__bf16) * (DB ? 2 : 1) * PL * QP * (2 * QP + IGE_GPAD);
@@ -516,8 +521,8 @@ void launch_mx(ige_op op, int r, int rc, int nchunk, const __bf16 *G, const __bf
                                     (int)shm));
         attr = true;
     }
-    hipLaunchKernelGGL(kern, grid, blk, shm, s, o, r, rc, nchunk, nw, op->d_morder.p, op->d_mwork.p,
-                       op->d_mpartner.p, op->d_gslot.p, G, Vb, op->d_bmpart.p);
+    hipLaunchKernelGGL(kern, grid, blk, shm, s, o, r, rc, nchunk, nw, order, op->d_mwork.p, op->d_mpartner.p,
+                       op->d_gslot.p, G, Vb, op->d_bmpart.p);
     IGE_HIP(hipGetLastError());
 }
 

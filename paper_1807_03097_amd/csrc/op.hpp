@@ -135,6 +135,8 @@ struct ige_op_s {
     ige::DBuf<int32_t> d_mpartner, d_gslot, d_mwrk_of_tgt;
     ige::DBuf<float2> d_bmpart;          // matrix-core coupling partials [mwork][4][Q][r]
     ige::DBuf<int32_t> d_morder;         // work items by decreasing partner count
+    ige::DBuf<int32_t> d_morder_sp;      // work items in cluster order, one contiguous part per XCD (-1: none)
+    int64_t n_morder_sp = 0;
     // split-BF16 near-field product (inner solves): blocks per ordered leaf pair,
     // gathered right factors, work items (target leaf, partners), FP32 partials and
     // per-unknown reduction lists
@@ -171,7 +173,7 @@ struct ige_op_s {
 namespace ige {
 
 // autotuned tile choices (ige_op_autotune); absent keys take the built-in default
-enum TuneKnob { kTuneM2lNcol = 0, kTuneNearBxNt = 1, kTuneNearMfmaNt = 2, kTuneM2lRb = 3, kTuneM2lDb = 4, kTuneKnobs = 5 };
+enum TuneKnob { kTuneM2lNcol = 0, kTuneNearBxNt = 1, kTuneNearMfmaNt = 2, kTuneM2lRb = 3, kTuneM2lDb = 4, kTuneM2lOrder = 5, kTuneKnobs = 6 };
 inline long long tune_key(int knob, int r, int prec) { return ((long long)knob << 40) | ((long long)r << 8) | prec; }
 inline int tune_get(const ige_op_s *op, int knob, int r, int prec, int def)
 {
