@@ -33,6 +33,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
+FP64_MFMA_PEAK_TFLOPS = 78.6    # MI355X FP64 dense matrix cores
 BF16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix cores
 
 
@@ -341,16 +342,26 @@ def main():
     # roofline of the dominant kernel (durations from the timed region)
     traffic_ref = load_traffic(r)
 
+    Qc = (q + 1) ** 2
+    Qpc = 32 * ((Qc + 31) // 32)
+    # FP64 applies of 8 or more columns: coupling on the FP64 matrix cores (stored blocks)
+    f64mx = (args.prec == 0 and r >= 8 and Qpc <= 128 and info.far_pairs > 0
+             and os.environ.get("IGE_M2L_F64") != "generate")
+
     def roofline_coupling(stage_ms):
-        """Matrix-core coupling (r > 1, BF16 precisions): issued BF16 matrix-core
-        operations of the real product [[Gr,-Gi],[Gi,Gr]] . [Re V; Im V] over padded
-        2Qp x 2Qp blocks and column chunks, over the kernel's own time."""
-        if args.prec < 2 or r == 1:
+        """Matrix-core coupling (r > 1, BF16 precisions; FP64 with 8 or more columns):
+        issued matrix-core operations of the real product [[Gr,-Gi],[Gi,Gr]] . [Re V; Im V]
+        over padded 2Qp x 2Qp blocks and column chunks, over the kernel's own time."""
+        if not (f64mx or (args.prec >= 2 and r > 1)):
             return None
-        Q = (q + 1) ** 2
-        Qp = 32 * ((Q + 31) // 32)
-        MT, split = Qp // 16, (1 if args.prec == 2 else 3)
-        cap = (64 if split == 3 else 128) if MT >= 8 else (128 if MT >= 6 else 256)
+        Q, Qp = Qc, Qpc
+        MT = Qp // 16
+        if f64mx:
+            split, cap, kern, peak = 1, 128, "k_m2l_md", FP64_MFMA_PEAK_TFLOPS
+        else:
+            split = 1 if args.prec == 2 else 3
+            cap = (64 if split == 3 else 128) if MT >= 8 else (128 if MT >= 6 else 256)
+            kern, peak = "k_m2l_mx", BF16_MFMA_PEAK_TFLOPS
         ncol = 16
         while ncol < 4 * r and ncol < cap:
             ncol *= 2
@@ -359,15 +370,15 @@ def main():
         useful = info.far_pairs * 8.0 * Q * Q * 4 * r
         t_ms = stage_ms["m2l_kernel"]
         ach = issued / (t_ms * 1e-3) / 1e12
-        return {"kernel": "k_m2l_mx", "bound": "mfma", "achieved": ach, "peak": BF16_MFMA_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": ach / BF16_MFMA_PEAK_TFLOPS, "traffic": None,
+        return {"kernel": kern, "bound": "mfma", "achieved": ach, "peak": peak,
+                "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
                 "useful_tflops": useful / (t_ms * 1e-3) / 1e12, "issued_flop": issued, "avg_ms": t_ms}
 
     def roofline(stage_ms):
         stages = {k: v for k, v in stage_ms.items() if k not in ("near_blk", "m2l_kernel")}
         dom = max(stages, key=stages.get)
-        if dom == "m2l" and args.prec >= 2 and r > 1:
-            return roofline_coupling(stage_ms)   # the BF16 matrix-core coupling kernel
+        if dom == "m2l" and (f64mx or (args.prec >= 2 and r > 1)):
+            return roofline_coupling(stage_ms)   # the matrix-core coupling kernel
         Q = (q + 1) ** 2
         if dom == "near_spmv" and r > 1:
             # many columns: matrix-core products over every ordered leaf pair (block and
@@ -386,8 +397,8 @@ def main():
                         "issued_flop": issued, "avg_ms": t_ms}
             flops = info.near_leaf_pairs * nF * nF * 8.0 * r
             ach = flops / (t_ms * 1e-3) / 1e12
-            return {"kernel": "k_near_mfma", "bound": "mfma", "achieved": ach, "peak": FP64_VECTOR_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": ach / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+            return {"kernel": "k_near_mfma", "bound": "mfma", "achieved": ach, "peak": FP64_MFMA_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": ach / FP64_MFMA_PEAK_TFLOPS, "traffic": None,
                     "flop": flops, "avg_ms": t_ms}
         if dom == "near_spmv":
             # the block pass: stored block entries (16 B each) streamed once per pass

@@ -192,7 +192,10 @@ int ige_apply_prec(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind,
  *     step by step during the current product), 0 one buffer with the next block
  *     prefetched into registers,
  *   5 launch order of the BF16 coupling work items: 0 by decreasing partner count,
- *     1 in cluster order with one contiguous part (equal partner counts) per XCD.
+ *     1 in cluster order with one contiguous part (equal partner counts) per XCD,
+ *   6 coupling of the FP64 apply of 8 or more columns: 1 stored FP64 blocks on the
+ *     FP64 matrix cores (made on first use, 2 * pairs * Qp * 2Qp * 8 bytes, when that
+ *     leaves 8 GiB of device memory free), 0 the kernel evaluated per apply.
  * Returns the number of timed configurations (>= 0) or an error status (< 0). */
 int ige_op_autotune(ige_op op, int r, int prec, int *choice, int nchoice);
 

@@ -356,9 +356,10 @@ class Operator:
     def autotune(self, r, prec=IGE_F64):
         """time the candidate tile shapes of the r-column apply and keep the fastest;
         returns {knob: value} for the knobs that apply uses"""
-        ch = np.full(6, -1, np.int32)
-        _check(_lib.ige_op_autotune(self.h, int(r), int(prec), _ptr(ch), 6))
-        names = ("m2l_ncol", "near_bx_nt", "near_mfma_nt", "m2l_rb", "m2l_double_buffer", "m2l_order")
+        ch = np.full(7, -1, np.int32)
+        _check(_lib.ige_op_autotune(self.h, int(r), int(prec), _ptr(ch), 7))
+        names = ("m2l_ncol", "near_bx_nt", "near_mfma_nt", "m2l_rb", "m2l_double_buffer", "m2l_order",
+                 "m2l_f64_matrix_cores")
         return {n: int(v) for n, v in zip(names, ch) if v >= 0}
 
     def set_profiling(self, on=True):

@@ -456,6 +456,9 @@ ige_op ige::assemble_on(ige_ctx ctx, const ige_geom_s *geom, const ige_params &p
                 // per apply (IGE_M2L_ONE=generate)
                 op->m2l_generate_one = false;
                 if (const char *e = std::getenv("IGE_M2L_ONE")) op->m2l_generate_one = std::string(e) == "generate";
+                // many FP64 columns: stored blocks on the FP64 matrix cores (default) or
+                // evaluated per apply (IGE_M2L_F64=generate)
+                if (const char *e = std::getenv("IGE_M2L_F64")) op->f64mx_off = std::string(e) == "generate";
                 if (op->nfp > 0) {
                     op->d_fpair.upload(fpair, s);
                     // matrix-core coupling: per target, work items of up to 32 partners
@@ -612,6 +615,7 @@ int ige_op_info(ige_op op, ige_op_info_t *out)
         b += op->d_nodeX.bytes() + op->d_nodeT.bytes() + op->d_G.bytes() + op->d_G32.bytes() + op->d_gpart.bytes() + op->d_gtmp.bytes();
         b += op->d_fpair.bytes() + op->d_fred_ptr.bytes() + op->d_fred_idx.bytes();
         b += op->d_Gb1.bytes() + op->d_Gb3.bytes() + op->d_vb.bytes() + op->d_bmpart.bytes();
+        b += op->d_Gd.bytes() + op->d_vd.bytes() + op->d_bmpart64.bytes();
         b += op->d_nb3.bytes() + op->d_xnb.bytes() + op->d_nbpart.bytes() + op->d_nbwork.bytes();
         b += op->d_nbpartner.bytes() + op->d_nbslot.bytes() + op->d_nborder.bytes() + op->d_nbred_ptr.bytes();
         b += op->d_nbred_idx.bytes() + op->d_morder.bytes();
@@ -898,6 +902,7 @@ int ige_op_autotune(ige_op op, int r, int prec, int *choice, int nchoice)
             switch (id) {
                 case ige::kTuneM2lDb: return 1;
                 case ige::kTuneM2lOrder: return 0;
+                case ige::kTuneM2lF64: return 1;
                 case ige::kTuneM2lNcol: return -1;   // the smallest chunk holding all columns
                 case ige::kTuneNearBxNt:
                 case ige::kTuneNearMfmaNt: return r > 32 ? 4 : (r > 16 ? 2 : 1);
@@ -907,7 +912,10 @@ int ige_op_autotune(ige_op op, int r, int prec, int *choice, int nchoice)
         // coordinate descent over the knobs that the (r, prec) apply uses
         const bool mx = r > 1 && prec >= IGE_BF16, near_bx = r > 1 && prec == IGE_BF16X3_ALL;
         const bool near_mfma = r >= 8 && prec != IGE_BF16X3_ALL && ige::near_mfma_mtw_ok(op->view.nF, op->view.rc);
-        const bool gen = r > 1 && prec <= IGE_F32 && !op->stored && !op->work.empty();
+        // FP64 coupling on the matrix cores (default) against the generated kernel, whose
+        // columns per workgroup are tuned only where it is the default
+        const bool f64mx = prec == IGE_F64 && ige::m2l_f64mx_ok(op, r);
+        const bool gen = r > 1 && prec <= IGE_F32 && !op->stored && !op->work.empty() && !f64mx;
         const int split = prec == IGE_BF16 ? 1 : 3;
         struct Knob {
             bool on;
@@ -920,7 +928,8 @@ int ige_op_autotune(ige_op op, int r, int prec, int *choice, int nchoice)
                                             {mxon, ige::kTuneM2lNcol, split, {64, 128, 256}},
                                             {near_bx, ige::kTuneNearBxNt, 0, {1, 2, 4}},
                                             {near_mfma, ige::kTuneNearMfmaNt, 0, {1, 2, 4}},
-                                            {gen, ige::kTuneM2lRb, prec, {1, 2, 4}}};
+                                            {gen, ige::kTuneM2lRb, prec, {1, 2, 4}},
+                                            {f64mx, ige::kTuneM2lF64, IGE_F64, {0}}};
         // each candidate timed in two rounds (minimum kept); a candidate replaces the
         // default only when it is more than 2 % faster (the timings vary by about that)
         std::vector<int> chosen(ige::kTuneKnobs, -1);

@@ -459,6 +459,146 @@ __global__ __launch_bounds__(128 * WN) void k_m2l_mxd(DevOp o, int r, int rc, in
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// The same coupling in FP64 on the FP64 matrix cores (16x16x4: lane l supplies
+// A[l%16][l/16] and B[l/16][l%16]; accumulator register j of lane l holds
+// D[l/16 + 4j][l%16]), for many right-hand sides of the FP64 operator.  The blocks
+// are stored once in FP64 ([Gr | Gi] rows, both orientations); two instructions take
+// eight consecutive reduction indices, lane group g the pair 2g, 2g + 1, so that one
+// 16-byte load per lane feeds both.  Left factor rows straight from memory (the four
+// column waves of a half read the same rows, served by the caches).
+// ---------------------------------------------------------------------------
+typedef double dx4m __attribute__((ext_vector_type(4)));
+
+__global__ void k_gd_store(DevOp o, int64_t nfp, const int32_t *fpair, int Qp, double *Gd)
+{
+    const int Q = o.Q, K2 = 2 * Qp;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per = (int64_t)Qp * Qp;
+    if (t >= nfp * 2 * per) return;
+    const int64_t po = t / per;
+    const int rr = (int)(t % per), m = rr / Qp, mc = rr % Qp;
+    const int64_t pr = po / 2;
+    const int ori = (int)(po % 2);
+    const int ga = fpair[2 * pr + ori], gb = fpair[2 * pr + 1 - ori];
+    double2 g = make_double2(0.0, 0.0);
+    if (m < Q && mc < Q) {
+        const double *Xa = o.nodeX + (size_t)ga * 3 * Q, *Xb = o.nodeX + (size_t)gb * 3 * Q;
+        const double d0 = Xa[m] - Xb[mc], d1 = Xa[Q + m] - Xb[Q + mc], d2 = Xa[2 * Q + m] - Xb[2 * Q + mc];
+        g = dm::helmholtz_r2(o.kappa, fma(d0, d0, fma(d1, d1, d2 * d2)));
+    }
+    double *base = Gd + (size_t)po * Qp * K2;
+    base[(size_t)m * K2 + mc] = g.x;
+    base[(size_t)m * K2 + Qp + mc] = g.y;
+}
+
+// source fields [NC][4][Q][r] -> Vd[cluster][chunk][ncol][2Qp] (FP64), through shared memory
+__global__ __launch_bounds__(256) void k_vd_prep_t(DevOp o, int r, int rc, int nchunk, int ncol, int Qp,
+                                                   const double2 *src, double *Vd)
+{
+    __shared__ double2 tile[kVbRows][65];
+    const int Q = o.Q, K2 = 2 * Qp, nrb = Qp / kVbRows;
+    int b = blockIdx.x;
+    const int rb = b % nrb;
+    b /= nrb;
+    const int f = b % 4;
+    b /= 4;
+    const int ch = b % nchunk, gc = b / nchunk;
+    const int m0 = rb * kVbRows;
+    for (int i = threadIdx.x; i < kVbRows * rc; i += blockDim.x) {
+        const int mm = i / rc, j = i % rc, col = ch * rc + j, m = m0 + mm;
+        tile[mm][j] = (m < Q && col < r) ? src[(((size_t)gc * 4 + f) * Q + m) * r + col] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    double *base = Vd + ((size_t)gc * nchunk + ch) * (size_t)ncol * K2;
+    for (int i = threadIdx.x; i < rc * 2 * kVbRows; i += blockDim.x) {
+        const int j = i / (2 * kVbRows), h = (i / kVbRows) & 1, mm = i % kVbRows;
+        const double2 t = tile[mm][j];
+        base[(size_t)(f * rc + j) * K2 + h * Qp + m0 + mm] = h ? t.y : t.x;
+    }
+}
+
+template <int MT, int WN, int NT>
+__global__ __launch_bounds__(128 * WN) void k_m2l_md(DevOp o, int r, int rc, int nchunk, int64_t nwork,
+                                                     const int32_t *order, const M2LWork *work,
+                                                     const int32_t *partner, const int32_t *gslot, const double *Gd,
+                                                     const double *Vd, double2 *part)
+{
+    constexpr int QP = 16 * MT, K2 = 2 * QP, NCOL = 16 * WN * NT;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv / WN, wn = wv % WN;
+    const int Q = o.Q, gi = lane >> 4, li = lane & 15;
+    const int64_t g = blockIdx.x;
+    const int64_t wo = (g / (8 * nchunk)) * 8 + g % 8;
+    const int ch = (int)((g / 8) % nchunk);
+    if (wo >= nwork) return;
+    const int64_t wi = order[wo];
+    if (wi < 0) return;
+    const M2LWork wk = work[wi];
+    const size_t gper = (size_t)QP * K2, vper = (size_t)NCOL * K2;
+    dx4m acc[MT][NT];
+#pragma unroll
+    for (int a = 0; a < MT; ++a)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[a][t] = dx4m{0.0, 0.0, 0.0, 0.0};
+    // one step = eight reduction indices of one partner; the operands of the next step
+    // are loaded during the products of the current one
+    constexpr int KS = K2 / 8;
+    const int nstep = (wk.end - wk.beg) * KS;
+    double2 av[MT], bv[NT];
+    auto load = [&](int it) {
+        const int kp = wk.beg + it / KS, s8 = it % KS;
+        const double *Gp = Gd + (size_t)gslot[kp] * gper;
+        const double *Vs = Vd + ((size_t)partner[kp] * nchunk + ch) * vper;
+        const int kb = 8 * s8 + 2 * gi;
+        // real rows [Gr, -Gi], imaginary rows [Gi, Gr] of the stored [Gr | Gi]; kb and
+        // 8 s8 lie in the same half (QP is a multiple of 16)
+        const bool hi = 8 * s8 >= QP;
+        const int ksrc = wm == 0 ? kb : (hi ? kb - QP : kb + QP);
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+            bv[t] = *reinterpret_cast<const double2 *>(Vs + (size_t)(16 * (wn * NT + t) + li) * K2 + kb);
+#pragma unroll
+        for (int a = 0; a < MT; ++a)
+            av[a] = *reinterpret_cast<const double2 *>(Gp + (size_t)(16 * a + li) * K2 + ksrc);
+        return wm == 0 && hi;
+    };
+    bool neg = nstep > 0 ? load(0) : false;
+    for (int it = 0; it < nstep; ++it) {
+        double2 ca[MT], cb[NT];
+#pragma unroll
+        for (int a = 0; a < MT; ++a) ca[a] = neg ? make_double2(-av[a].x, -av[a].y) : av[a];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) cb[t] = bv[t];
+        if (it + 1 < nstep) neg = load(it + 1);
+#pragma unroll
+        for (int a = 0; a < MT; ++a)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[a][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[a].x, cb[t].x, acc[a][t], 0, 0, 0);
+#pragma unroll
+        for (int a = 0; a < MT; ++a)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[a][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[a].y, cb[t].y, acc[a][t], 0, 0, 0);
+    }
+    // lane holds D[lane/16 + 4 j][lane % 16] of each tile: node m, column n = f rc + jc
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int n = 16 * (wn * NT + t) + li, f = n / rc, jc = n % rc;
+        const int col = ch * rc + jc;
+        if (f >= 4 || col >= r) continue;
+#pragma unroll
+        for (int a = 0; a < MT; ++a)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int m = 16 * a + gi + 4 * j;
+                if (m < Q) {
+                    double *dst = reinterpret_cast<double *>(part + (((size_t)wi * 4 + f) * Q + m) * r + col);
+                    dst[wm] = acc[a][t][j];
+                }
+            }
+    }
+}
+
 }  // namespace
 
 int coupling_qp(int Q) { return 32 * ((Q + 31) / 32); }
@@ -605,6 +745,86 @@ void m2l_bf16(ige_op op, int r, int split, const double2 *src, hipStream_t s, hi
     } else {
         if (split == 3) launch_mx_mt<false, 3>(op, r, MT, ncol, op->d_Gb3.p, op->d_vb.p, s);
         else launch_mx_mt<false, 1>(op, r, MT, ncol, op->d_Gb1.p, op->d_vb.p, s);
+    }
+}
+
+
+namespace {
+template <int MT, int WN, int NT>
+void launch_md(ige_op op, int r, int rc, int nchunk, hipStream_t s)
+{
+    const DevOp &o = op->view;
+    const int64_t nw = (int64_t)op->mwork.size();
+    const dim3 grid((unsigned)(((nw + 7) / 8) * 8 * nchunk)), blk(128 * WN);
+    hipLaunchKernelGGL((k_m2l_md<MT, WN, NT>), grid, blk, 0, s, o, r, rc, nchunk, nw, op->d_morder.p, op->d_mwork.p,
+                       op->d_mpartner.p, op->d_gslot.p, op->d_Gd.p, op->d_vd.p, op->d_bmpart64.p);
+    IGE_HIP(hipGetLastError());
+}
+
+template <int MT>
+void launch_md_cols(ige_op op, int r, int ncol, hipStream_t s)
+{
+    const int rc = ncol / 4, nchunk = (r + rc - 1) / rc;
+    switch (ncol) {
+        case 16: launch_md<MT, 1, 1>(op, r, rc, nchunk, s); break;
+        case 32: launch_md<MT, 2, 1>(op, r, rc, nchunk, s); break;
+        case 64: launch_md<MT, 4, 1>(op, r, rc, nchunk, s); break;
+        default: launch_md<MT, 4, 2>(op, r, rc, nchunk, s); break;
+    }
+}
+}  // namespace
+
+void ensure_coupling_f64(ige_op op)
+{
+    if (op->d_Gd.p || op->nfp == 0) return;
+    const DevOp &o = op->view;
+    const int Qp = coupling_qp(o.Q);
+    op->d_Gd.alloc((size_t)op->nfp * 2 * Qp * 2 * Qp);
+    const int64_t n = op->nfp * 2 * (int64_t)Qp * Qp;
+    hipLaunchKernelGGL(k_gd_store, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, op->ctx->stream, o, op->nfp,
+                       op->d_fpair.p, Qp, op->d_Gd.p);
+    IGE_HIP(hipGetLastError());
+}
+
+bool m2l_f64mx_ok(ige_op op, int r)
+{
+    if (r < 8 || op->mwork.empty() || op->f64mx_off) return false;
+    const int Qp = coupling_qp(op->view.Q);
+    if (Qp > 128) return false;
+    if (op->gd_fit < 0) {   // decided once, at the first eligible apply (never under capture)
+        const size_t need = (size_t)op->nfp * 2 * Qp * 2 * Qp * sizeof(double);
+        size_t fr = 0, tot = 0;
+        IGE_HIP(hipMemGetInfo(&fr, &tot));
+        op->gd_fit = op->d_Gd.p || need + ((size_t)8 << 30) < fr ? 1 : 0;
+    }
+    return op->gd_fit == 1;
+}
+
+bool m2l_f64mx_use(ige_op op, int r) { return m2l_f64mx_ok(op, r) && tune_get(op, kTuneM2lF64, r, IGE_F64, 1) != 0; }
+
+void m2l_f64mx(ige_op op, int r, const double2 *src, hipStream_t s, hipEvent_t mid)
+{
+    const DevOp &o = op->view;
+    if (op->mwork.empty()) return;
+    ensure_coupling_f64(op);
+    const int Qp = coupling_qp(o.Q), K2 = 2 * Qp, MT = Qp / 16;
+    IGE_REQUIRE(MT <= 8, "interpolation degree too large for the matrix-core coupling");
+    int ncol = 16;
+    while (ncol < 4 * r && ncol < 128) ncol *= 2;
+    const int rc = ncol / 4, nchunk = (r + rc - 1) / rc;
+    const size_t vdn = (size_t)op->NC * nchunk * ncol * K2;
+    if (op->d_vd.n < vdn) op->d_vd.alloc(vdn);
+    const size_t pn = op->mwork.size() * 4 * (size_t)o.Q * r;
+    if (op->d_bmpart64.n < pn) op->d_bmpart64.alloc(pn);
+    const int64_t nb = (int64_t)op->NC * nchunk * 4 * (Qp / kVbRows);
+    hipLaunchKernelGGL(k_vd_prep_t, dim3((unsigned)nb), dim3(256), 0, s, o, r, rc, nchunk, ncol, Qp, src, op->d_vd.p);
+    IGE_HIP(hipGetLastError());
+    if (mid) IGE_HIP(hipEventRecord(mid, s));
+    switch (MT) {
+        case 2: launch_md_cols<2>(op, r, ncol, s); break;
+        case 4: launch_md_cols<4>(op, r, ncol, s); break;
+        case 6: launch_md_cols<6>(op, r, ncol, s); break;
+        default: launch_md_cols<8>(op, r, ncol, s); break;
     }
 }
 

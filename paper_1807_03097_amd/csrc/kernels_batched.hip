@@ -648,6 +648,12 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
             hipLaunchKernelGGL(k_m2l_reduce_b<float2>, dim3(op->NC), dim3(256), 0, s, o, r, op->d_mwrk_of_tgt.p,
                                op->d_bmpart.p, op->d_bloc.p);
             IGE_HIP(hipGetLastError());
+        } else if (prec == IGE_F64 && m2l_f64mx_use(op, r)) {
+            m2l_f64mx(op, r, op->d_bsrc.p, s, ev ? ev[12] : nullptr);
+            mark(3);
+            hipLaunchKernelGGL(k_m2l_reduce_b<double2>, dim3(op->NC), dim3(256), 0, s, o, r, op->d_mwrk_of_tgt.p,
+                               op->d_bmpart64.p, op->d_bloc.p);
+            IGE_HIP(hipGetLastError());
         } else if (op->stored) {
             mark(12);
             m2l_stored(op, r, prec, op->d_bsrc.p, op->d_bloc.p, s);

@@ -134,6 +134,10 @@ struct ige_op_s {
     ige::DBuf<ige::M2LWork> d_mwork;
     ige::DBuf<int32_t> d_mpartner, d_gslot, d_mwrk_of_tgt;
     ige::DBuf<float2> d_bmpart;          // matrix-core coupling partials [mwork][4][Q][r]
+    ige::DBuf<double> d_Gd, d_vd;       // FP64 matrix-core coupling: blocks, right factors
+    ige::DBuf<double2> d_bmpart64;      // FP64 matrix-core coupling partials [mwork][4][Q][r]
+    int gd_fit = -1;                    // FP64 blocks fit in device memory (-1: not yet decided)
+    bool f64mx_off = false;             // FP64 coupling of many columns generated per apply (IGE_M2L_F64=generate)
     ige::DBuf<int32_t> d_morder;         // work items by decreasing partner count
     ige::DBuf<int32_t> d_morder_sp;      // work items in cluster order, one contiguous part per XCD (-1: none)
     int64_t n_morder_sp = 0;
@@ -173,7 +177,7 @@ struct ige_op_s {
 namespace ige {
 
 // autotuned tile choices (ige_op_autotune); absent keys take the built-in default
-enum TuneKnob { kTuneM2lNcol = 0, kTuneNearBxNt = 1, kTuneNearMfmaNt = 2, kTuneM2lRb = 3, kTuneM2lDb = 4, kTuneM2lOrder = 5, kTuneKnobs = 6 };
+enum TuneKnob { kTuneM2lNcol = 0, kTuneNearBxNt = 1, kTuneNearMfmaNt = 2, kTuneM2lRb = 3, kTuneM2lDb = 4, kTuneM2lOrder = 5, kTuneM2lF64 = 6, kTuneKnobs = 7 };
 inline long long tune_key(int knob, int r, int prec) { return ((long long)knob << 40) | ((long long)r << 8) | prec; }
 inline int tune_get(const ige_op_s *op, int knob, int r, int prec, int def)
 {
@@ -214,6 +218,12 @@ void m2l_stored_reduce_one(ige_op op);
 // fields [NC][4][Q][r] -> partials per work item [mwork][4][Q][r] (d_bmpart)
 void m2l_bf16(ige_op op, int r, int split, const double2 *src, hipStream_t s, hipEvent_t mid = nullptr);
 void ensure_coupling_bf16(ige_op op, int split);
+// coupling of the FP64 operator on the FP64 matrix cores (many columns): partials d_bmpart64
+void ensure_coupling_f64(ige_op op);
+void m2l_f64mx(ige_op op, int r, const double2 *src, hipStream_t s, hipEvent_t mid = nullptr);
+// whether the FP64 apply of r columns can take (ok) and takes (use) the matrix-core coupling
+bool m2l_f64mx_ok(ige_op op, int r);
+bool m2l_f64mx_use(ige_op op, int r);
 // widest usable coupling chunk (complex columns) for the current staging choice
 int m2l_ncol_limit(ige_op op, int r, int split);
 // split-BF16 near-field product (yt = near part of A x, [N][r] layout)

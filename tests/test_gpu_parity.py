@@ -296,6 +296,37 @@ def test_bf16_matrix_core_coupling(oracle_mod, ctx, case):
     op.close()
 
 
+@pytest.mark.parametrize("case", [CASES[2], CASES[4], CASES[8], CASES[9]],
+                         ids=["sphere-d1", "torus-d1", "sphere-d0", "sphere-d3"])
+def test_fp64_matrix_core_coupling(oracle_mod, ctx, monkeypatch, case):
+    """FP64 applies of 8 or more columns take the coupling on the FP64 matrix cores
+    (stored FP64 blocks): equal to the oracle to the FP64 tolerance, and to single
+    columns and to the per-apply evaluated coupling up to summation order, for 8, 9
+    and 70 columns (one, one ragged, and several column chunks with a ragged last)."""
+    from paper_1807_03097_amd import binding as B
+    name, p, m, kappa, q, eta, d, g, gs = case
+    _say(f"case {case}")
+    pats = _geom(name)
+    geom = B.Geometry(ctx, pats)
+    op = B.Operator(geom, p, m, kappa, q, eta, g, gs, d)
+    monkeypatch.setenv("IGE_M2L_F64", "generate")
+    opg = B.Operator(geom, p, m, kappa, q, eta, g, gs, d)
+    monkeypatch.delenv("IGE_M2L_F64")
+    o = oracle_mod.Oracle(pats, p, m, kappa, g=g, gs=gs)
+    X70 = np.stack([W.random_coeffs(op.N, 300 + s) for s in range(70)])
+    for nc in (8, 9, 70):
+        X = X70[:nc].copy()
+        Y = op.apply(X)
+        Yg = opg.apply(X)
+        eg = max(_rel(Y[c], Yg[c]) for c in range(nc))
+        e1 = max(_rel(Y[c], op.apply(X[c].copy())) for c in (0, nc // 2, nc - 1))
+        eo = _rel(Y[nc - 1], o.fmm_apply(X[nc - 1], q, eta, d)) if nc < 70 else 0.0
+        _say(f"  {nc} columns: vs generated {eg:.2e}, vs single columns {e1:.2e}, last column vs oracle {eo:.2e}")
+        assert eg <= 1e-13 and e1 <= 1e-13 and eo <= TOL
+    opg.close()
+    op.close()
+
+
 @pytest.mark.parametrize("nrhs, prec", [(1, 0), (3, 0), (3, 3)], ids=["1col-f64", "3col-f64", "3col-splitbf16"])
 def test_solve_graph_replays_equal_eager(ctx, monkeypatch, nrhs, prec):
     """GMRES with the apply captured as a HIP graph and replayed every iteration gives
@@ -322,9 +353,9 @@ def test_solve_graph_replays_equal_eager(ctx, monkeypatch, nrhs, prec):
 
 @pytest.mark.parametrize("prec", [0, 3, 4], ids=["f64", "splitbf16", "splitbf16-near"])
 def test_autotune_keeps_results(ctx, prec):
-    """The autotuner only changes tile shapes (column chunking); every column's
-    arithmetic and its order stay the same, so applies before and after tuning agree
-    to rounding of the unchanged order (checked to 1e-13)."""
+    """The autotuner only changes tile shapes (column chunking), launch order and, for
+    FP64, which of two FP64 evaluations of the coupling runs; applies before and after
+    tuning agree to rounding (checked to 1e-13)."""
     from paper_1807_03097_amd import binding as B
     geom = B.Geometry(ctx, _geom("sphere"))
     op = B.Operator(geom, 2, 3, 8.0, 8, 1.6, 5, 5, 1)
