@@ -150,12 +150,15 @@ enum { IGE_F64 = 0, IGE_F32 = 1, IGE_BF16 = 2, IGE_BF16X3 = 3, IGE_BF16X3_ALL = 
 
 /* y = A x for r right-hand sides (A the compressed operator).  x, y: N*r complex.
  * r > 1 runs the batched kernels (columns in chunks, every kernel value and matrix
- * entry read or computed once per chunk). */
+ * entry read or computed once per chunk); r >= 8 applies the coupling on the FP64
+ * matrix cores (see ige_apply_prec, IGE_F64). */
 int ige_apply(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind);
 
 /* As ige_apply, with the coupling stage (interpolated-kernel values and their
- * products, a5) in the given precision:
- *   IGE_F64   FP64 (as ige_apply);
+ * products, M2L) in the given precision:
+ *   IGE_F64   FP64 (as ige_apply; with 8 or more columns the kernel matrices are
+ *             stored in FP64, both orientations, and applied on the FP64 matrix cores,
+ *             unless autotuned otherwise or IGE_M2L_F64=generate);
  *   IGE_F32   FP32 kernel values: evaluated and accumulated in FP32 when generated
  *             on the fly, an FP32 copy of the stored blocks with FP64 accumulation when
  *             stored; relative error about kappa * diam * 2^-23 on the far field;

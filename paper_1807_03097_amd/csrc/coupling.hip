@@ -1,4 +1,4 @@
-// Stored coupling blocks of the far field (a2/a5).
+// Stored coupling blocks of the far field (set-up and M2L).
 //
 // Every admissible cluster pair appears in both orders, and the interpolated
 // kernel matrix of (s, t) is the transpose of that of (t, s): G_ts[m][m'] =

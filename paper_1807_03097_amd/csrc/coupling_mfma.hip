@@ -1,4 +1,5 @@
-// Coupling stage (a5) on the BF16 matrix cores, for many right-hand sides.
+// Coupling stage (M2L) on the matrix cores, for many right-hand sides: BF16 and split
+// BF16 (below), and FP64 (the last kernels of this file).
 //
 // The kernel matrices G of the admissible pairs (the dense coupling blocks of the
 // interpolation-based FMM, Sec. 4) are stored once in BF16, in both orientations

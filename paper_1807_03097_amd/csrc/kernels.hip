@@ -1,19 +1,19 @@
-// HIP kernels of the igaefie library (gfx950, wave64).
+// HIP kernels of the igaefie library (gfx950, wave64), by step of the path:
 //
-//   a0  element_data / node_geometry : geometry from the rational Bezier form at the
-//       regular Gauss points of every element and at the Chebyshev nodes of every cluster
-//   a1  near_regular / near_singular : element-pair Galerkin quadrature of the near field,
-//       accumulated into dense blocks over leaf function slots (regular pairs on the
-//       FP64 matrix cores)
-//   a3  p2m   leaf moments, fused with the gather x_super = T x (1-D factors of T)
-//   a4  m2m   upward transfer of the moments (nested cluster bases)
-//   a5  m2l   coupling of admissible cluster pairs with the interpolated kernel
-//   a6  l2l   downward transfer
-//   a7  l2p   test-side moments, fused with the scatter T^T
-//   a8  near_blk + near_gather: near-field product over the stored blocks and their
-//       transposes, then a fixed-order sum per unknown
-//   a9  rhs   plane-wave right-hand side
-//   a10 GMRES vector kernels
+//   geometry   element_data / node_geometry : geometry from the rational Bezier form at
+//              the regular Gauss points of every element and at the Chebyshev nodes of
+//              every cluster
+//   near field near_regular / near_singular : element-pair Galerkin quadrature,
+//              accumulated into dense blocks over leaf function slots (regular pairs on
+//              the FP64 matrix cores)
+//   P2M        leaf moments, fused with the gather x_super = T x (1-D factors of T)
+//   M2M        upward transfer of the moments (nested cluster bases)
+//   M2L        coupling of admissible cluster pairs with the interpolated kernel
+//   L2L        downward transfer
+//   L2P        test-side moments, fused with the scatter T^T
+//   near product near_blk + near_gather: product with the stored blocks and their
+//              transposes, then a fixed-order sum per unknown
+//   rhs        plane-wave right-hand side
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

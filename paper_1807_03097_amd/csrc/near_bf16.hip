@@ -1,4 +1,4 @@
-// Near-field product (a8) in split BF16 on the matrix cores, for the inner solves
+// Near-field product in split BF16 on the matrix cores, for the inner solves
 // of the mixed-precision iterative refinement (the near-field blocks themselves are
 // assembled in FP64 by the Galerkin quadrature of Sec. 3; this is a lower-precision
 // copy of them for the inner operator only).
