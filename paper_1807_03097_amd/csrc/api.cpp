@@ -392,6 +392,18 @@ ige_op ige::assemble_on(ige_ctx ctx, const ige_geom_s *geom, const ige_params &p
             op->d_nodeX.alloc((size_t)op->NC * 3 * v.Q);
             op->d_nodeT.alloc((size_t)op->NC * 6 * v.Q);
             v.nodeX = op->d_nodeX.p; v.nodeT = op->d_nodeT.p;
+            {
+                // (cos, sin)(j pi/128), rounded from long double
+                static const std::vector<double2> tab = [] {
+                    std::vector<double2> t(256);
+                    const long double step = 3.14159265358979323846264338327950288L / 128.0L;
+                    for (int j = 0; j < 256; ++j)
+                        t[j] = make_double2((double)cosl(step * j), (double)sinl(step * j));
+                    return t;
+                }();
+                op->d_sctab.upload(tab, s);
+                v.sctab = op->d_sctab.p;
+            }
             ige::launch_node_geometry(op);
             // M2L work items: partners of each target in chunks
             // partners per M2L work item (tuning knob IGE_M2L_CHUNK, default 8)

@@ -12,6 +12,15 @@ __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x +
 __device__ inline double2 cscale(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
 __device__ inline float2 cmul(float2 a, float2 b) { return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
 __device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+// acc + a b as four fused multiply-adds (no separate product and sum)
+__device__ inline double2 cmac(double2 acc, double2 a, double2 b)
+{
+    return make_double2(fma(a.x, b.x, fma(-a.y, b.y, acc.x)), fma(a.x, b.y, fma(a.y, b.x, acc.y)));
+}
+__device__ inline float2 cmac(float2 acc, float2 a, float2 b)
+{
+    return make_float2(fmaf(a.x, b.x, fmaf(-a.y, b.y, acc.x)), fmaf(a.x, b.y, fmaf(a.y, b.x, acc.y)));
+}
 
 // FP64: 1/r by the hardware reciprocal square root and two Newton steps
 // y <- y (3/2 - r^2 y^2 / 2); sin and cos of kappa r by Cody-Waite reduction
@@ -62,6 +71,41 @@ __device__ inline double2 helmholtz_r2(double kappa, double r2)
     if ((q + 1) & 2) cs = -cs;
     const double f = kInv4Pi * y;
     return make_double2(cs * f, sn * f);
+}
+
+// The same kernel with a table-driven sine and cosine (angle addition): x = kappa r is
+// reduced by k = rint(x 128/pi) multiples of pi/128 (three-part split of pi/128, fused
+// multiply-adds), so |t| <= pi/256; sin t and cos t from their Taylor series to t^7 and
+// t^6 (truncation below 2e-20 relative); tab[k mod 256] = (cos, sin)(k pi/128) gives
+// cos x = C c - S s, sin x = S c + C s.  Valid for |kappa r| < 2^30.
+__device__ inline double2 helmholtz_r2_tab(double kappa, double r2, const double2 *tab)
+{
+    constexpr double kInvStep = 40.74366543152521;   // 128/pi
+    constexpr double kStep1 = 0.02454369260617026;   // pi/128 = kStep1 + kStep2 + kStep3
+    constexpr double kStep2 = 9.567553118338697e-19;
+    constexpr double kStep3 = -2.3396639138424529e-35;
+    constexpr double kInv4Pi = 0.07957747154594767;
+    double y = __builtin_amdgcn_rsq(r2);
+    const double hh = 0.5 * r2;
+    y = y * fma(-hh * y, y, 1.5);
+    y = y * fma(-hh * y, y, 1.5);
+    const double x = kappa * (r2 * y);
+    const double k = rint(x * kInvStep);
+    double t = fma(-k, kStep1, x);
+    t = fma(-k, kStep2, t);
+    t = fma(-k, kStep3, t);
+    const double2 cs = tab[(int)k & 255];
+    const double z = t * t;
+    double ps = -1.0 / 5040.0;                        // -1/7!
+    ps = fma(ps, z, 1.0 / 120.0);                     //  1/5!
+    ps = fma(ps, z, -1.0 / 6.0);                      // -1/3!
+    const double s = fma(t * z, ps, t);
+    double pc = -1.0 / 720.0;                         // -1/6!
+    pc = fma(pc, z, 1.0 / 24.0);                      //  1/4!
+    pc = fma(pc, z, -0.5);                            // -1/2!
+    const double c = fma(z, pc, 1.0);
+    const double f = kInv4Pi * y;
+    return make_double2(fma(cs.x, c, -cs.y * s) * f, fma(cs.y, c, cs.x * s) * f);
 }
 
 // FP32 counterpart (relative error about kappa r 2^-23 from the rounding of r):

@@ -910,6 +910,9 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l(DevOp o, const M2LWork *wor
     T *sX = reinterpret_cast<T *>(smd);                        // [3][Q]
     C *sV = reinterpret_cast<C *>(smd + (3 * Q * (int)sizeof(T) + 15) / 16 * 2);   // [4][Q], 16-B aligned after sX
     double2 *red = reinterpret_cast<double2 *>(smd);           // [S][Q][4] after the partner loop
+    __shared__ double2 sTab[256];                               // (cos, sin)(j pi/128), FP64 only
+    if constexpr (sizeof(T) == 8)
+        for (int i = tid; i < 256; i += kM2LThreads) sTab[i] = o.sctab[i];   // first use after a barrier
     const T kap = (T)o.kappa;
     T xt[kM2LNT][3];
     bool val[kM2LNT];
@@ -942,11 +945,13 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l(DevOp o, const M2LWork *wor
 #pragma unroll
                 for (int k = 0; k < kM2LNT; ++k) {
                     const T d0 = xt[k][0] - x0, d1 = xt[k][1] - x1, d2 = xt[k][2] - x2;
-                    const C G = dm::helmholtz_r2(kap, d0 * d0 + d1 * d1 + d2 * d2);
-                    acc[k][0] = dm::cadd(acc[k][0], dm::cmul(G, v0));
-                    acc[k][1] = dm::cadd(acc[k][1], dm::cmul(G, v1));
-                    acc[k][2] = dm::cadd(acc[k][2], dm::cmul(G, v2));
-                    acc[k][3] = dm::cadd(acc[k][3], dm::cmul(G, v3));
+                    C G;
+                    if constexpr (sizeof(T) == 8) G = dm::helmholtz_r2_tab(kap, fma(d0, d0, fma(d1, d1, d2 * d2)), sTab);
+                    else G = dm::helmholtz_r2(kap, fma(d0, d0, fma(d1, d1, d2 * d2)));
+                    acc[k][0] = dm::cmac(acc[k][0], G, v0);
+                    acc[k][1] = dm::cmac(acc[k][1], G, v1);
+                    acc[k][2] = dm::cmac(acc[k][2], G, v2);
+                    acc[k][3] = dm::cmac(acc[k][3], G, v3);
                 }
             }
         }

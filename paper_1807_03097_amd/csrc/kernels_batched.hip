@@ -362,6 +362,9 @@ __global__ __launch_bounds__(kM2LThreadsB) void k_m2l_b(DevOp o, int r, const M2
     T *sX = reinterpret_cast<T *>(smd);                        // [3][Q]
     C *sV = reinterpret_cast<C *>(smd + (3 * Q * (int)sizeof(T) + 15) / 16 * 2);   // [4][Q][kRB], after sX
     double2 *red = reinterpret_cast<double2 *>(smd);           // [S][Q][kRB] (one field at a time)
+    __shared__ double2 sTab[256];                               // (cos, sin)(j pi/128), FP64 only
+    if constexpr (sizeof(T) == 8)
+        for (int i = tid; i < 256; i += kM2LThreadsB) sTab[i] = o.sctab[i];   // first use after a barrier
     const T kap = (T)o.kappa;
     const double *Xt = o.nodeX + (size_t)wk.tgt * 3 * Q;
     T xt[kNTB][3];
@@ -401,7 +404,8 @@ __global__ __launch_bounds__(kM2LThreadsB) void k_m2l_b(DevOp o, int r, const M2
 #pragma unroll
                 for (int t = 0; t < kNTB; ++t) {
                     const T d0 = xt[t][0] - x0, d1 = xt[t][1] - x1, d2 = xt[t][2] - x2;
-                    G[t] = dm::helmholtz_r2(kap, d0 * d0 + d1 * d1 + d2 * d2);
+                    if constexpr (sizeof(T) == 8) G[t] = dm::helmholtz_r2_tab(kap, fma(d0, d0, fma(d1, d1, d2 * d2)), sTab);
+                    else G[t] = dm::helmholtz_r2(kap, fma(d0, d0, fma(d1, d1, d2 * d2)));
                 }
 #pragma unroll
                 for (int f = 0; f < 4; ++f) {
@@ -410,7 +414,7 @@ __global__ __launch_bounds__(kM2LThreadsB) void k_m2l_b(DevOp o, int r, const M2
                     for (int c = 0; c < kRB; ++c) {
                         const C v = vf[c];
 #pragma unroll
-                        for (int t = 0; t < kNTB; ++t) acc[t][f][c] = dm::cadd(acc[t][f][c], dm::cmul(G[t], v));
+                        for (int t = 0; t < kNTB; ++t) acc[t][f][c] = dm::cmac(acc[t][f][c], G[t], v);
                     }
                 }
             }

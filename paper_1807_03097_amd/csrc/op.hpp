@@ -55,6 +55,7 @@ struct DevOp {
     const int64_t *lvl_off;   // [L+2] first global cluster id of each level
     const double *nodeX;      // [NC][3][Q]
     const double *nodeT;      // [NC][6][Q]  d_uF (3), d_vF (3)
+    const double2 *sctab;     // [256] (cos, sin)(j pi/128), for the table-driven kernel evaluation
     const double *xn;         // [Q1] Chebyshev nodes
     const double *T0, *T1;    // [Q1][Q1]
     const double *Mp, *Mq, *Mdp;   // [SL][Q1][rowlen]
@@ -114,6 +115,7 @@ struct ige_op_s {
     ige::DBuf<double2> d_npart;        // near-field partial results [nslots]
     ige::DBuf<int64_t> d_lvl_off;
     ige::DBuf<double> d_nodeX, d_nodeT, d_xn, d_T0, d_T1, d_Mp, d_Mq, d_Mdp;
+    ige::DBuf<double2> d_sctab;
     ige::DBuf<int32_t> d_inc;
     ige::DBuf<ige::SingularPair> d_sing;
     ige::DBuf<ige::M2LWork> d_work;
