@@ -49,6 +49,19 @@ std::complex<double> cz(double2 a) { return {a.x, a.y}; }
 // the far-field pipeline (arithmetic bound) runs on the context stream; the L2P
 // gather joins both.  With profiling on, stage boundaries are recorded into one of
 // kProfSlots event sets on the stream each stage runs on (no host sync).
+// (cos, sin)(j pi/128), j < 256, rounded from long double: the table of the FP64
+// kernel evaluation in the coupling stage
+const std::vector<double2> &sincos_table()
+{
+    static const std::vector<double2> tab = [] {
+        std::vector<double2> t(256);
+        const long double step = 3.14159265358979323846264338327950288L / 128.0L;
+        for (int j = 0; j < 256; ++j) t[j] = make_double2((double)cosl(step * j), (double)sinl(step * j));
+        return t;
+    }();
+    return tab;
+}
+
 void apply_one(ige_op op, const double2 *x, double2 *y, int prec = IGE_F64)
 {
     hipStream_t s = ige::lstream(op), s2 = op->aux;
@@ -392,18 +405,8 @@ ige_op ige::assemble_on(ige_ctx ctx, const ige_geom_s *geom, const ige_params &p
             op->d_nodeX.alloc((size_t)op->NC * 3 * v.Q);
             op->d_nodeT.alloc((size_t)op->NC * 6 * v.Q);
             v.nodeX = op->d_nodeX.p; v.nodeT = op->d_nodeT.p;
-            {
-                // (cos, sin)(j pi/128), rounded from long double
-                static const std::vector<double2> tab = [] {
-                    std::vector<double2> t(256);
-                    const long double step = 3.14159265358979323846264338327950288L / 128.0L;
-                    for (int j = 0; j < 256; ++j)
-                        t[j] = make_double2((double)cosl(step * j), (double)sinl(step * j));
-                    return t;
-                }();
-                op->d_sctab.upload(tab, s);
-                v.sctab = op->d_sctab.p;
-            }
+            op->d_sctab.upload(sincos_table(), s);
+            v.sctab = op->d_sctab.p;
             ige::launch_node_geometry(op);
             // M2L work items: partners of each target in chunks
             // partners per M2L work item (tuning knob IGE_M2L_CHUNK, default 8)
@@ -1362,12 +1365,13 @@ int ige_helmholtz_eval(ige_ctx ctx, int64_t n, double kappa, const double *r2, i
         if (n == 0) return;
         set_device(ctx);
         DBuf<double> dr;
-        DBuf<double2> dout;
+        DBuf<double2> dout, dtab;
         dr.alloc(n);
         dout.alloc(n);
         IGE_HIP(hipMemcpyAsync(dr.p, r2, sizeof(double) * n, hipMemcpyHostToDevice, ctx->stream));
+        dtab.upload(sincos_table(), ctx->stream);
         IGE_REQUIRE(prec == IGE_F64 || prec == IGE_F32, "bad precision");
-        ige::launch_helmholtz_eval(ctx->stream, n, kappa, dr.p, dout.p, prec);
+        ige::launch_helmholtz_eval(ctx->stream, n, kappa, dr.p, dout.p, prec, dtab.p);
         IGE_HIP(hipMemcpyAsync(out, dout.p, sizeof(double2) * n, hipMemcpyDeviceToHost, ctx->stream));
         IGE_HIP(hipStreamSynchronize(ctx->stream));
     });

@@ -36,7 +36,7 @@ __global__ void k_g_store(DevOp o, int64_t nfp, const int32_t *fpair, double2 *G
     const double *Xt = o.nodeX + (size_t)fpair[2 * pr] * 3 * Q;
     const double *Xs = o.nodeX + (size_t)fpair[2 * pr + 1] * 3 * Q;
     const double d0 = Xt[m] - Xs[ms], d1 = Xt[Q + m] - Xs[Q + ms], d2 = Xt[2 * Q + m] - Xs[2 * Q + ms];
-    G[t] = dm::helmholtz_r2(o.kappa, fma(d0, d0, fma(d1, d1, d2 * d2)));
+    G[t] = dm::helmholtz_r2_tab(o.kappa, fma(d0, d0, fma(d1, d1, d2 * d2)), o.sctab);
 }
 
 __global__ void k_g_to32(int64_t n, const double2 *G, float2 *G32)

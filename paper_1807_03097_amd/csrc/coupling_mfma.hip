@@ -64,7 +64,7 @@ __global__ void k_gb_store(DevOp o, int64_t nfp, const int32_t *fpair, int Qp, i
     if (m < Q && mc < Q) {
         const double *Xa = o.nodeX + (size_t)ga * 3 * Q, *Xb = o.nodeX + (size_t)gb * 3 * Q;
         const double d0 = Xa[m] - Xb[mc], d1 = Xa[Q + m] - Xb[Q + mc], d2 = Xa[2 * Q + m] - Xb[2 * Q + mc];
-        g = dm::helmholtz_r2(o.kappa, fma(d0, d0, fma(d1, d1, d2 * d2)));
+        g = dm::helmholtz_r2_tab(o.kappa, fma(d0, d0, fma(d1, d1, d2 * d2)), o.sctab);
     }
     __bf16 *base = Gb + (size_t)po * (split == 3 ? 2 : 1) * Qp * K2;
     const size_t i_re = (size_t)m * K2 + mc, i_im = i_re + Qp;
@@ -487,7 +487,7 @@ __global__ void k_gd_store(DevOp o, int64_t nfp, const int32_t *fpair, int Qp, d
     if (m < Q && mc < Q) {
         const double *Xa = o.nodeX + (size_t)ga * 3 * Q, *Xb = o.nodeX + (size_t)gb * 3 * Q;
         const double d0 = Xa[m] - Xb[mc], d1 = Xa[Q + m] - Xb[Q + mc], d2 = Xa[2 * Q + m] - Xb[2 * Q + mc];
-        g = dm::helmholtz_r2(o.kappa, fma(d0, d0, fma(d1, d1, d2 * d2)));
+        g = dm::helmholtz_r2_tab(o.kappa, fma(d0, d0, fma(d1, d1, d2 * d2)), o.sctab);
     }
     double *base = Gd + (size_t)po * Qp * K2;
     base[(size_t)m * K2 + mc] = g.x;

@@ -1280,19 +1280,21 @@ __global__ void k_rhs_plane(DevOp o, double d0, double d1, double d2, double2 p0
     f[i] = acc;
 }
 
-__global__ void k_helmholtz_eval(int64_t n, double kappa, const double *r2, double2 *out, int prec)
+__global__ void k_helmholtz_eval(int64_t n, double kappa, const double *r2, double2 *out, int prec,
+                                 const double2 *sctab)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     if (prec == IGE_F32) out[i] = dm::to_d(dm::helmholtz_r2((float)kappa, (float)r2[i]));
-    else out[i] = dm::helmholtz_r2(kappa, r2[i]);
+    else out[i] = dm::helmholtz_r2_tab(kappa, r2[i], sctab);
 }
 
 }  // namespace
 
-void launch_helmholtz_eval(hipStream_t s, int64_t n, double kappa, const double *r2, double2 *out, int prec)
+void launch_helmholtz_eval(hipStream_t s, int64_t n, double kappa, const double *r2, double2 *out, int prec,
+                           const double2 *sctab)
 {
-    hipLaunchKernelGGL(k_helmholtz_eval, dim3((n + 255) / 256), dim3(256), 0, s, n, kappa, r2, out, prec);
+    hipLaunchKernelGGL(k_helmholtz_eval, dim3((n + 255) / 256), dim3(256), 0, s, n, kappa, r2, out, prec, sctab);
     IGE_HIP(hipGetLastError());
 }
 

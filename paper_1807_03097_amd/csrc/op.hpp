@@ -273,6 +273,7 @@ void launch_axpy_cols(ige_op op, int r, const double *s, const double2 *x, doubl
 void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, double2 *yt, hipEvent_t *ev, int prec);
 void batched_to_rows(ige_op op, int r, const double2 *x, double2 *xt, hipStream_t s);
 void batched_to_cols(ige_op op, int r, const double2 *yt, double2 *y, hipStream_t s);
-void launch_helmholtz_eval(hipStream_t s, int64_t n, double kappa, const double *r2, double2 *out, int prec);
+void launch_helmholtz_eval(hipStream_t s, int64_t n, double kappa, const double *r2, double2 *out, int prec,
+                           const double2 *sctab);
 
 }  // namespace ige
