@@ -322,7 +322,10 @@ def main():
             op.apply(x, y, prec=args.prec)
         torch.cuda.synchronize()
 
-    op.set_profiling(True)
+    # timed region: the boundaries of the block pass and of the coupling kernel only
+    # (four timing events per apply); the full stage breakdown comes from the
+    # isolated pass below
+    op.set_profiling(2)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -336,8 +339,9 @@ def main():
     ms_step = ev0.elapsed_time(ev1) / args.steps
     stages = op.stage_times()
     names = ["p2m", "m2m", "m2l", "m2l_reduce", "l2l", "near_spmv", "l2p", "near_blk", "m2l_kernel"]
-    st = {n: float(v) for n, v in zip(names, stages)}
-    log("stage ms: " + " ".join(f"{k}={v:.4f}" for k, v in st.items()) + f"  step={ms_step:.4f} ms wall/step={1e3 * wall / args.steps:.4f}")
+    st = {n: float(stages[names.index(n)]) for n in ("near_blk", "m2l_kernel")}
+    log("timed kernels ms: " + " ".join(f"{k}={v:.4f}" for k, v in st.items())
+        + f"  step={ms_step:.4f} ms wall/step={1e3 * wall / args.steps:.4f}")
 
     # roofline of the dominant kernel (durations from the timed region)
     traffic_ref = load_traffic(r)
@@ -375,8 +379,8 @@ def main():
                 "useful_tflops": useful / (t_ms * 1e-3) / 1e12, "issued_flop": issued, "avg_ms": t_ms}
 
     def roofline(stage_ms):
-        stages = {k: v for k, v in stage_ms.items() if k not in ("near_blk", "m2l_kernel")}
-        dom = max(stages, key=stages.get)
+        # the dominant kernel: the near-field block pass or the coupling kernel
+        dom = "near_spmv" if stage_ms["near_blk"] >= stage_ms["m2l_kernel"] else "m2l"
         if dom == "m2l" and (f64mx or (args.prec >= 2 and r > 1)):
             return roofline_coupling(stage_ms)   # the matrix-core coupling kernel
         Q = (q + 1) ** 2
@@ -415,10 +419,11 @@ def main():
         # multiply-adds per right-hand side (32 operations each)
         entries = info.far_pairs * Q * Q
         flops = entries * (14.0 + 32.0 * r)
-        achieved = flops / (stage_ms[dom] * 1e-3) / 1e12
-        return {"kernel": "k_" + dom, "bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+        t_ms = stage_ms["m2l_kernel"]
+        achieved = flops / (t_ms * 1e-3) / 1e12
+        return {"kernel": "k_m2l", "bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
-                "node_pairs": int(entries), "avg_ms": stage_ms[dom]}
+                "node_pairs": int(entries), "avg_ms": t_ms}
 
     roof = roofline(st)
     roof_cpl = roofline_coupling(st)
@@ -471,7 +476,7 @@ def main():
                    "n_dof": N, "nrhs": r, "eta": eta, "leaf_depth": d, "near_nnz": int(info.near_nnz),
                    "store_coupling": args.store_coupling,
                    "far_pairs": int(info.far_pairs), "parallelism": "single GPU"},
-        "stage_ms": st,
+        "timed_kernel_ms": st,
         "assemble_s": t_asm,
         "roofline": roof,
         "roofline_isolated": roof_iso,

@@ -202,15 +202,18 @@ int ige_apply_prec(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind,
  * Returns the number of timed configurations (>= 0) or an error status (< 0). */
 int ige_op_autotune(ige_op op, int r, int prec, int *choice, int nchoice);
 
-/* Stage profiling.  ige_op_set_profiling(op, 1) creates HIP events and clears the
- * record; every later single-column apply records its stage boundaries on the
- * context stream (no host synchronisation).  ige_op_stage_times synchronises the
- * stream and returns the average device time (ms) per stage over the last (up to
- * 256) recorded applies: 0 P2M, 1 M2M, 2 M2L, 3 M2L reduce, 4 L2L, 5 near-field
- * product (block pass and reduction), 6 L2P, 7 the block pass alone (the whole
- * near-field product for r > 1), 8 the coupling product alone (stage 2 without the
- * conversion of the source fields to the matrix-core operand layout).  n: capacity of
- * ms[]; returns the stage count (9). */
+/* Stage profiling.  ige_op_set_profiling(op, level) creates HIP events (timing only,
+ * no system-scope fence) and clears the record; every later apply outside solves
+ * records stage boundaries on the streams the stages run on (no host
+ * synchronisation): level 1 every boundary, level 2 only those of the block pass and
+ * of the coupling kernel (stages 7 and 8 below; the others read 0), for timing the
+ * dominant kernels at little cost; level 0 stops recording.  ige_op_stage_times
+ * synchronises the streams and returns the average device time (ms) per stage over
+ * the last (up to 256) recorded applies: 0 P2M, 1 M2M, 2 M2L, 3 M2L reduce, 4 L2L,
+ * 5 near-field product (block pass and reduction), 6 L2P, 7 the block pass alone (the
+ * whole near-field product for r > 1), 8 the coupling product alone (stage 2 without
+ * the conversion of the source fields to the matrix-core operand layout).  n:
+ * capacity of ms[]; returns the stage count (9). */
 int ige_op_set_profiling(ige_op op, int on);
 
 /* Scheduling knob: on (default) runs the near-field product on a second stream

@@ -363,7 +363,8 @@ class Operator:
         return {n: int(v) for n, v in zip(names, ch) if v >= 0}
 
     def set_profiling(self, on=True):
-        ige_op_set_profiling(self.h, on)
+        """on: True/1 every stage boundary, 2 the block pass and coupling kernel only, False/0 off"""
+        ige_op_set_profiling(self.h, int(on))
 
     def set_overlap(self, on=True):
         ige_op_set_overlap(self.h, on)

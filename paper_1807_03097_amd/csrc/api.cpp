@@ -69,7 +69,7 @@ void apply_one(ige_op op, const double2 *x, double2 *y, int prec = IGE_F64)
     hipEvent_t *ev = prof ? op->prof_ev.data() + (size_t)(op->prof_count % ige_op_s::kProfSlots) * ige_op_s::kProfEv
                           : nullptr;
     auto mark = [&](int i, hipStream_t st) {
-        if (prof) IGE_HIP(hipEventRecord(ev[i], st));
+        if (prof && ige::prof_records(op, i)) IGE_HIP(hipEventRecord(ev[i], st));
     };
     const bool far = !op->work.empty();
     if (!far || !op->overlap) {
@@ -559,8 +559,10 @@ ige_op ige::assemble_on(ige_ctx ctx, const ige_geom_s *geom, const ige_params &p
             op->d_part.alloc(std::max<size_t>(1, op->work.size()) * 4 * v.Q);
             if (op->stored) ige::store_coupling(op);
             IGE_HIP(hipStreamCreate(&op->aux));
-            IGE_HIP(hipEventCreateWithFlags(&op->ev_fork, hipEventDisableTiming));
-            IGE_HIP(hipEventCreateWithFlags(&op->ev_join, hipEventDisableTiming));
+            // fork/join between two streams of one device: no system-scope fence (the
+            // kernels' own releases and acquires order the device memory; 5 us per apply)
+            IGE_HIP(hipEventCreateWithFlags(&op->ev_fork, hipEventDisableTiming | hipEventDisableSystemFence));
+            IGE_HIP(hipEventCreateWithFlags(&op->ev_join, hipEventDisableTiming | hipEventDisableSystemFence));
             IGE_HIP(hipStreamSynchronize(s));
             int err = 0;
             IGE_HIP(hipMemcpy(&err, op->d_err.p, sizeof(int), hipMemcpyDeviceToHost));
@@ -673,9 +675,13 @@ int ige_op_set_profiling(ige_op op, int on)
         set_device(op->ctx);
         if (on && op->prof_ev.empty()) {
             op->prof_ev.assign((size_t)ige_op_s::kProfSlots * ige_op_s::kProfEv, nullptr);
-            for (auto &e : op->prof_ev) IGE_HIP(hipEventCreate(&e));
+            // timing only: no system-scope fence at each record (a fence writes back and
+            // invalidates the caches; the streams are synchronised before the read-out)
+            for (auto &e : op->prof_ev) IGE_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
         }
-        op->profiling = on != 0;
+        IGE_REQUIRE(on >= 0 && on <= 2, "profiling level must be 0, 1 or 2");
+        op->profiling = on;
+        if (on) op->prof_level_rec = on;
         op->prof_count = 0;
     });
 }
@@ -705,6 +711,7 @@ int ige_op_stage_times(ige_op op, double *ms, int n)
             for (int64_t sl = 0; sl < k; ++sl) {
                 hipEvent_t *ev = op->prof_ev.data() + sl * ige_op_s::kProfEv;
                 for (int i = 0; i < std::min(n, nst); ++i) {
+                    if (op->prof_level_rec == 2 && i != 7 && i != 8) continue;   // not recorded
                     float t = 0.f;
                     IGE_HIP(hipEventElapsedTime(&t, ev[pairs[i][0]], ev[pairs[i][1]]));
                     double v = t;

@@ -616,7 +616,7 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
     const DevOp &o = op->view;
     hipStream_t s = lstream(op);
     auto mark = [&](int i) {
-        if (ev) IGE_HIP(hipEventRecord(ev[i], s));
+        if (ev && prof_records(op, i)) IGE_HIP(hipEventRecord(ev[i], s));
     };
     const int64_t N = o.N;
     const int64_t tot = N * r;

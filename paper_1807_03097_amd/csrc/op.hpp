@@ -81,7 +81,8 @@ struct ige_op_s {
     int64_t nnz = 0;
     int64_t nsing = 0;
     double assemble_ms = 0.0;
-    bool profiling = false;
+    int profiling = 0;                 // 0 off, 1 every stage boundary, 2 the block pass and coupling kernel only
+    int prof_level_rec = 0;            // level of the recorded applies
     static constexpr int kProfSlots = 256;
     static constexpr int kProfEv = 13;
     std::vector<hipEvent_t> prof_ev;   // [kProfSlots][kProfEv] stage boundary events
@@ -189,6 +190,12 @@ inline int tune_get(const ige_op_s *op, int knob, int r, int prec, int def)
 
 // stream the apply kernels are launched on (a capture stream while a graph is recorded)
 inline hipStream_t lstream(const ige_op_s *op) { return op->lst ? op->lst : op->ctx->stream; }
+// whether a profiling event of the given index is recorded at the operator's level
+// (level 2 keeps only the boundaries of the block pass, 7-11, and of the coupling kernel, 12-3)
+inline bool prof_records(const ige_op_s *op, int i)
+{
+    return op->profiling == 1 || (op->profiling == 2 && (i == 3 || i == 7 || i == 11 || i == 12));
+}
 
 // assembly of geom's operator on ctx's device and stream (throws ige::Status)
 ige_op assemble_on(ige_ctx ctx, const ige_geom_s *geom, const ige_params &prm);
