@@ -926,8 +926,8 @@ int ige_op_autotune(ige_op op, int r, int prec, int *choice, int nchoice)
                 case ige::kTuneM2lOrder: return 0;
                 case ige::kTuneM2lF64: return 1;
                 case ige::kTuneM2lNcol: return -1;   // the smallest chunk holding all columns
-                case ige::kTuneNearBxNt:
-                case ige::kTuneNearMfmaNt: return r > 32 ? 4 : (r > 16 ? 2 : 1);
+                case ige::kTuneNearBxNt: return r > 32 ? 4 : (r > 16 ? 2 : 1);
+                case ige::kTuneNearMfmaNt: return r > 16 ? 2 : 1;
                 default: return -1;                   // the largest that fits
             }
         };

@@ -766,9 +766,13 @@ namespace {
 
 typedef double dx4b __attribute__((ext_vector_type(4)));
 
+constexpr int kNearMfmaMaxK = 1024;   // reduction length staged in shared memory (slots per leaf)
+constexpr int kNearMfmaPD = 2;        // reduction steps loaded ahead of the products
+
 template <int DIR, int NT, int MTW>
 __global__ __launch_bounds__(256) void k_near_mfma(DevOp o, int r, const double2 *xt, double2 *part)
 {
+    __shared__ int32_t skd[kNearMfmaMaxK];   // unknown of every reduction index (-1: none)
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int nF = o.nF;
     const int64_t b = blockIdx.x / o.nch;
@@ -782,36 +786,59 @@ __global__ __launch_bounds__(256) void k_near_mfma(DevOp o, int r, const double2
     const int nt = wv % NT, mstep = 4 / NT, mfirst = wv / NT;
     const int n = c0 + 16 * nt + (lane & 15);   // this lane's column (B operand and output)
     const bool nok = n < r;
+    const int nc = nok ? n : 0;
     const double2 *Bv = o.bval + (size_t)b * nF * nF;
     const int32_t *kdof = o.leafdof + (size_t)(DIR == 0 ? ls : lt) * nF + (DIR == 0 ? 0 : r0);
+    for (int i = threadIdx.x; i < K; i += blockDim.x) skd[i] = kdof[i];
+    __syncthreads();
     dx4b accr[MTW], acci[MTW];
 #pragma unroll
     for (int i = 0; i < MTW; ++i) {
         accr[i] = dx4b{0.0, 0.0, 0.0, 0.0};
         acci[i] = dx4b{0.0, 0.0, 0.0, 0.0};
     }
-    for (int s = 0; s < KS; ++s) {
+    // operands of reduction step s: every load from a clamped, valid address, zeroed
+    // where out of range (no branches around the loads, so they stay in flight)
+    auto load = [&](int s, double2 &xo, double2 (&ao)[MTW]) {
         const int k = 4 * s + (lane >> 4);   // reduction index supplied by this lane
-        double xr = 0.0, xi = 0.0;
-        if (k < K && nok) {
-            const int d = kdof[k];
-            if (d >= 0) {
-                const double2 v = xt[(size_t)d * r + n];
-                xr = v.x;
-                xi = v.y;
-            }
-        }
+        const int d = (k < K && nok) ? skd[min(k, K - 1)] : -1;
+        const double2 v = xt[(size_t)max(d, 0) * r + nc];
+        xo = d >= 0 ? v : make_double2(0.0, 0.0);
+        const int ka = min(k, K - 1);
 #pragma unroll
         for (int i = 0; i < MTW; ++i) {
             const int mt = mfirst + i * mstep;
-            if (mt >= MT) break;   // uniform over the wave
-            const int m = 16 * mt + (lane & 15), ka = 4 * s + (lane >> 4);
-            double2 a = make_double2(0.0, 0.0);
-            if (m < M && ka < K) a = DIR == 0 ? Bv[(size_t)(r0 + m) * nF + ka] : Bv[(size_t)(r0 + ka) * nF + m];
-            accr[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, xr, accr[i], 0, 0, 0);
-            accr[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, xi, accr[i], 0, 0, 0);
-            acci[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, xi, acci[i], 0, 0, 0);
-            acci[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, xr, acci[i], 0, 0, 0);
+            if (mt < MT) {   // uniform over the wave
+                const int m = 16 * mt + (lane & 15), mc = min(m, M - 1);
+                const double2 av = DIR == 0 ? Bv[(size_t)(r0 + mc) * nF + ka] : Bv[(size_t)(r0 + ka) * nF + mc];
+                ao[i] = (m < M && k < K) ? av : make_double2(0.0, 0.0);
+            }
+        }
+    };
+    double2 xb[kNearMfmaPD], ab[kNearMfmaPD][MTW];
+#pragma unroll
+    for (int d = 0; d < kNearMfmaPD; ++d)
+        if (d < KS) load(d, xb[d], ab[d]);
+    for (int s0 = 0; s0 < KS; s0 += kNearMfmaPD) {
+#pragma unroll
+        for (int d = 0; d < kNearMfmaPD; ++d) {
+            const int s = s0 + d;
+            if (s < KS) {   // uniform
+                const double xr = xb[d].x, xi = xb[d].y;
+                double2 a[MTW];
+#pragma unroll
+                for (int i = 0; i < MTW; ++i) a[i] = ab[d][i];
+                if (s + kNearMfmaPD < KS) load(s + kNearMfmaPD, xb[d], ab[d]);
+#pragma unroll
+                for (int i = 0; i < MTW; ++i) {
+                    if (mfirst + i * mstep < MT) {   // uniform over the wave
+                        accr[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, xr, accr[i], 0, 0, 0);
+                        accr[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[i].y, xi, accr[i], 0, 0, 0);
+                        acci[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, xi, acci[i], 0, 0, 0);
+                        acci[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, xr, acci[i], 0, 0, 0);
+                    }
+                }
+            }
         }
     }
     if (!nok) return;
@@ -884,6 +911,7 @@ void launch_near_mfma(ige_op op, int r, const double2 *xt, double2 *part, hipStr
 
 int near_mfma_mtw_ok(int nF, int rc)
 {
+    if (nF > kNearMfmaMaxK) return 0;
     for (int NT : {1, 2, 4})
         for (int M : {rc, nF}) {
             const int MT = (M + 15) / 16, ms = 4 / NT, w = (MT + ms - 1) / ms;
@@ -898,7 +926,7 @@ void near_batched_mfma(ige_op op, int r, const double2 *xt, double2 *yt, hipStre
     const size_t need = (size_t)o.nblk * o.nF * (1 + o.nch) * r;
     if (op->d_bnpart_r.n < need) op->d_bnpart_r.alloc(need);
     double2 *part = op->d_bnpart_r.p;
-    const int NT = tune_get(op, kTuneNearMfmaNt, r, 0, r > 32 ? 4 : (r > 16 ? 2 : 1));
+    const int NT = tune_get(op, kTuneNearMfmaNt, r, 0, r > 16 ? 2 : 1);
     if (NT == 4) {
         launch_near_mfma<0, 4>(op, r, xt, part, s);
         launch_near_mfma<1, 4>(op, r, xt, part, s);
