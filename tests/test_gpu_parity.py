@@ -327,6 +327,35 @@ def test_fp64_matrix_core_coupling(oracle_mod, ctx, monkeypatch, case):
     op.close()
 
 
+def test_stage_profiling_levels(ctx):
+    """Level 1 times every stage of a single-column apply (and of a batched one); level
+    2 only the block pass and the coupling kernel, the other stages reading 0; neither
+    changes the result."""
+    from paper_1807_03097_amd import binding as B
+    geom = B.Geometry(ctx, _geom("sphere"))
+    op = B.Operator(geom, 2, 3, 8.0, 8, 1.6, 5, 5, 1)
+    x = W.random_coeffs(op.N, 7)
+    y0 = op.apply(x)
+    X = np.stack([W.random_coeffs(op.N, 70 + s) for s in range(9)])
+    for level in (1, 2):
+        for xx in (x, X):
+            op.set_profiling(level)
+            y = op.apply(xx)
+            st = np.asarray(op.stage_times())
+            op.set_profiling(0)
+            _say(f"  level {level}, {xx.ndim} dims: {np.round(st * 1e3, 1)} us")
+            assert st[7] > 0 and st[8] > 0
+            if level == 1:
+                assert np.all(st[[0, 1, 2, 4, 5, 6]] > 0)
+            else:
+                assert np.all(st[:7] == 0)
+            if xx.ndim == 1:
+                assert _rel(y, y0) == 0.0
+    with pytest.raises(B.IgeError):
+        op.set_profiling(3)
+    op.close()
+
+
 @pytest.mark.parametrize("nrhs, prec", [(1, 0), (3, 0), (3, 3)], ids=["1col-f64", "3col-f64", "3col-splitbf16"])
 def test_solve_graph_replays_equal_eager(ctx, monkeypatch, nrhs, prec):
     """GMRES with the apply captured as a HIP graph and replayed every iteration gives
