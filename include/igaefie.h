@@ -241,7 +241,10 @@ typedef struct {
                         a step that reduces the FP64 residual by less than 1/2 while its
                         inner solve claimed twice as much is undone on the columns that
                         got worse and the inner precision moves towards FP64
-                        (IGE_BF16X3_ALL or IGE_BF16 -> IGE_BF16X3 -> IGE_F64) */
+                        (IGE_BF16X3_ALL or IGE_BF16 -> IGE_BF16X3 -> IGE_F64); with
+                        inner_tol >= 1e-5 the inner solves store their Krylov basis in
+                        FP32 (sums, the vector being orthogonalised and the correction
+                        in FP64; IGE_INNER_BASIS=fp64 keeps the basis in FP64) */
     double inner_tol;
     int inner_prec;  /* precision of the inner solves (IGE_F64 .. IGE_BF16X3_ALL) */
 } ige_solve_opts;

@@ -1027,14 +1027,22 @@ struct GmresOut {
 // precision prec, starting from X (device, [r][N], updated in place); each column
 // stops when its residual estimate reaches tol * ||B_c||.  it_cap: per-column
 // iteration budget.
+// b32: the Krylov basis stored in FP32 (inner solves of refinement); the vector being
+// orthogonalised, every sum and the solution stay FP64, and the operator is applied to
+// the FP64 basis vector before rounding
 void gmres_batched(ige_op op, int r, const double2 *B, double2 *X, const std::vector<double> &tol, int m,
                    const std::vector<int> &it_cap,
-                   int prec, GmresOut &out)
+                   int prec, GmresOut &out, bool b32 = false)
 {
     const int64_t N = op->D.N;
     hipStream_t s = op->ctx->stream;
     const size_t need = (size_t)(m + 1) * r * N;
-    if (op->d_V.n < need) op->d_V.alloc(need);
+    if (b32) {
+        if (op->d_V32.n < need) op->d_V32.alloc(need);
+        if (op->d_wcur.n < (size_t)r * N) op->d_wcur.alloc((size_t)r * N);
+    } else if (op->d_V.n < need) {
+        op->d_V.alloc(need);
+    }
     if (op->d_w.n < (size_t)r * N) op->d_w.alloc((size_t)r * N);
     const int hs = m + 2;
     const ige::GsPlan gp = ige::gs_plan(N, r, m);
@@ -1056,17 +1064,27 @@ void gmres_batched(ige_op op, int r, const double2 *B, double2 *X, const std::ve
     double2 *split = ige::gs_split_count(gp, N, r) ? op->d_gsplit.p : nullptr;
     double2 *h1 = op->d_h.p, *h2 = op->d_h.p + (size_t)r * hs;
     double *nb = op->d_gn.p, *nf = op->d_gn.p + r;
-    double2 *V = op->d_V.p, *W = op->d_w.p;
+    double2 *V = b32 ? nullptr : op->d_V.p, *W = op->d_w.p;
+    float2 *V32 = b32 ? op->d_V32.p : nullptr;
+    auto dots = [&](int k, const double2 *w, const int *gate, double2 *h, double *nbp) {
+        if (b32) ige::launch_gs_dots(s, gp, N, r, V32, k, w, gate, op->d_gspart.p, h, hs, nbp);
+        else ige::launch_gs_dots(s, gp, N, r, V, k, w, gate, op->d_gspart.p, h, hs, nbp);
+    };
+    auto update = [&](int k, const double2 *h, double sign, const int *gate, double2 *y, double *np) {
+        if (b32) ige::launch_gs_update(s, gp, N, r, V32, k, h, hs, sign, gate, y, split, np);
+        else ige::launch_gs_update(s, gp, N, r, V, k, h, hs, sign, gate, y, split, np);
+    };
+    // basis vector j scaled in place (x = y), with its FP32 copy in the FP32 basis
+    auto scale_basis = [&](int j, double2 *x) {
+        if (b32) ige::launch_scale_cols32(op, r, op->d_scal.p, x, x, V32 + (size_t)j * r * N);
+        else ige::launch_scale_cols(op, r, op->d_scal.p, x, x);
+    };
     auto norms = [&](const double2 *v) {
         std::vector<double> h(r);
         ige::launch_norm2_b(op, r, v, op->d_red.p);
         IGE_HIP(hipMemcpyAsync(h.data(), op->d_red.p, sizeof(double) * r, hipMemcpyDeviceToHost, s));
         IGE_HIP(hipStreamSynchronize(s));
         return h;
-    };
-    auto scale = [&](const std::vector<double> &sc, const double2 *x, double2 *y) {
-        IGE_HIP(hipMemcpyAsync(op->d_scal.p, sc.data(), sizeof(double) * r, hipMemcpyHostToDevice, s));
-        ige::launch_scale_cols(op, r, op->d_scal.p, x, y);
     };
     auto upload_mask = [&](const std::vector<char> &mk, int *dst) {
         std::vector<int> v(mk.begin(), mk.end());
@@ -1083,11 +1101,12 @@ void gmres_batched(ige_op op, int r, const double2 *B, double2 *X, const std::ve
         bool budget = false;
         for (int c = 0; c < r; ++c) budget = budget || out.iters[c] < it_cap[c];
         if (!budget) return;   // every column used its iterations
-        // V0 = B - A X
+        // V0 = B - A X (FP64; with the FP32 basis in the current-vector buffer)
         apply_dev(op, r, X, W, prec, &ag);
-        ige::launch_axpby(op, (int64_t)r * N, make_double2(1, 0), B, make_double2(0, 0), V);
-        ige::launch_axpby(op, (int64_t)r * N, make_double2(-1, 0), W, make_double2(1, 0), V);
-        std::vector<double> beta = norms(V);
+        double2 *cur = b32 ? op->d_wcur.p : V, *nxt = W;
+        ige::launch_axpby(op, (int64_t)r * N, make_double2(1, 0), B, make_double2(0, 0), cur);
+        ige::launch_axpby(op, (int64_t)r * N, make_double2(-1, 0), W, make_double2(1, 0), cur);
+        std::vector<double> beta = norms(cur);
         std::vector<char> act(r);
         int nact = 0;
         for (int c = 0; c < r; ++c) {
@@ -1098,7 +1117,9 @@ void gmres_batched(ige_op op, int r, const double2 *B, double2 *X, const std::ve
         if (nact == 0) return;
         std::vector<double> sc(r);
         for (int c = 0; c < r; ++c) sc[c] = act[c] ? 1.0 / beta[c] : 0.0;
-        scale(sc, V, V);
+        IGE_HIP(hipMemcpyAsync(op->d_scal.p, sc.data(), sizeof(double) * r, hipMemcpyHostToDevice, s));
+        scale_basis(0, cur);
+        IGE_HIP(hipStreamSynchronize(s));   // sc leaves scope
         std::vector<int> jdone(r, 0);
         for (int c = 0; c < r; ++c) {
             std::fill(g[c].begin(), g[c].end(), Cx(0));
@@ -1107,18 +1128,19 @@ void gmres_batched(ige_op op, int r, const double2 *B, double2 *X, const std::ve
         std::vector<char> run = act;
         upload_mask(run, op->d_grun.p);
         for (int jj = 0; jj < m; ++jj) {
-            double2 *Vj = V + (size_t)jj * r * N, *Vj1 = V + (size_t)(jj + 1) * r * N;
+            double2 *Vj = b32 ? cur : V + (size_t)jj * r * N, *Vj1 = b32 ? nxt : V + (size_t)(jj + 1) * r * N;
             apply_dev(op, r, Vj, Vj1, prec, &ag);
             // Gram-Schmidt pass 1 on the running columns, pass 2 where it lost more than half
-            ige::launch_gs_dots(s, gp, N, r, V, jj + 1, Vj1, op->d_grun.p, op->d_gspart.p, h1, hs, nb);
-            ige::launch_gs_update(s, gp, N, r, V, jj + 1, h1, hs, -1.0, op->d_grun.p, Vj1, split, op->d_gnp.p);
+            dots(jj + 1, Vj1, op->d_grun.p, h1, nb);
+            update(jj + 1, h1, -1.0, op->d_grun.p, Vj1, op->d_gnp.p);
             ige::launch_gs_norm(s, gp, r, op->d_gnp.p, op->d_grun.p, op->d_grun.p, nb, nf, op->d_scal.p,
                                 op->d_gflag.p);
-            ige::launch_gs_dots(s, gp, N, r, V, jj + 1, Vj1, op->d_gflag.p, op->d_gspart.p, h2, hs, nullptr);
-            ige::launch_gs_update(s, gp, N, r, V, jj + 1, h2, hs, -1.0, op->d_gflag.p, Vj1, split, op->d_gnp.p);
+            dots(jj + 1, Vj1, op->d_gflag.p, h2, nullptr);
+            update(jj + 1, h2, -1.0, op->d_gflag.p, Vj1, op->d_gnp.p);
             ige::launch_gs_norm(s, gp, r, op->d_gnp.p, op->d_gflag.p, op->d_grun.p, nullptr, nf, op->d_scal.p,
                                 nullptr);
-            ige::launch_scale_cols(op, r, op->d_scal.p, Vj1, Vj1);
+            scale_basis(jj + 1, Vj1);
+            if (b32) std::swap(cur, nxt);
             ige::launch_gs_pack(s, r, jj + 1, h1, h2, hs, nf, op->d_hpack.p);
             const double2 *hp = op->h_hpack.p;
             IGE_HIP(hipMemcpyAsync(op->h_hpack.p, op->d_hpack.p, sizeof(double2) * r * (jj + 2), hipMemcpyDeviceToHost,
@@ -1173,7 +1195,7 @@ void gmres_batched(ige_op op, int r, const double2 *B, double2 *X, const std::ve
         std::vector<char> upd(r);
         for (int c = 0; c < r; ++c) upd[c] = jdone[c] > 0;
         upload_mask(upd, op->d_gact.p);
-        if (kmax > 0) ige::launch_gs_update(s, gp, N, r, V, kmax, op->d_h.p, hs, 1.0, op->d_gact.p, X, split, nullptr);
+        if (kmax > 0) update(kmax, op->d_h.p, 1.0, op->d_gact.p, X, nullptr);
     }
 }
 }  // namespace
@@ -1236,6 +1258,11 @@ int ige_solve(ige_op op, int r, const ige_c64 *f, ige_c64 *x, int ptr_kind, cons
             // by the inner operator's error: its growing columns are undone and the inner
             // precision moves one rung towards FP64 (split near field -> split coupling -> FP64)
             int cur = opts->inner_prec;
+            // inner solves keep their Krylov basis in FP32 when they stop at a relative
+            // residual of 1e-5 or more (FP32 rounding of the basis, 6e-8, stays far below);
+            // IGE_INNER_BASIS=fp64 keeps it in FP64
+            const char *eb = std::getenv("IGE_INNER_BASIS");
+            const bool inner_b32 = (!eb || std::string(eb) != "fp64") && opts->inner_tol >= 1e-5;
             std::vector<double> prev(r, 0.0), est(r, 0.0), undo(r, 0.0);
             std::vector<int> lastcap(r, 0);
             for (int step = 0; step <= opts->maxit; ++step) {
@@ -1286,7 +1313,7 @@ int ige_solve(ige_op op, int r, const ige_c64 *f, ige_c64 *x, int ptr_kind, cons
                 if (!any) break;
                 IGE_HIP(hipMemsetAsync(op->d_D.p, 0, sizeof(double2) * r * N, s));
                 // columns already converged get an inner budget of 0 and a zero correction
-                gmres_batched(op, r, op->d_r.p, op->d_D.p, itol, opts->restart, cap, cur, go);
+                gmres_batched(op, r, op->d_r.p, op->d_D.p, itol, opts->restart, cap, cur, go, inner_b32);
                 ige::launch_axpby(op, (int64_t)r * N, make_double2(1, 0), op->d_D.p, make_double2(1, 0), X);
                 for (int c = 0; c < r; ++c) {
                     iters[c] += go.iters[c];

@@ -1,10 +1,14 @@
-// a10: vector kernels of the batched restarted complex GMRES that solves the
+// Vector kernels of the batched restarted complex GMRES that solves the
 // compressed EFIE system without preconditioner (Sec. 5).
 //
 // Layouts: the Krylov basis V is [k][r][n] (basis index, column, entry), vectors w
 // and X are [r][n].  Every reduction runs in a fixed order (per-wave sums over a
 // fixed shuffle tree, then partials summed in index order by a second kernel), so
 // an orthogonalisation step gives the same bits on every run.
+//
+// The basis is stored in FP64, or in FP32 for the inner solves of iterative
+// refinement (the Gram-Schmidt passes then read half the bytes; every sum, the
+// vector being orthogonalised and the solution stay FP64).
 //
 // Orthogonalisation is classical Gram-Schmidt with a selective second pass
 // (Daniel-Gragg-Kaufman-Stewart): after w' = w - V V^H w, the pass is repeated for
@@ -37,6 +41,13 @@ __device__ inline double2 wave_sum(double2 v)
     return v;
 }
 
+__device__ inline double2 ld2(const double2 *p) { return *p; }
+__device__ inline double2 ld2(const float2 *p)
+{
+    const float2 v = *p;
+    return make_double2(v.x, v.y);
+}
+
 __device__ inline double wave_sum(double v)
 {
 #pragma unroll
@@ -47,7 +58,8 @@ __device__ inline double wave_sum(double v)
 // part[(c (k+1) + kk) nchk + ch] = sum over chunk ch of conj(V[kk][c][i]) w_c[i] for
 // the basis indices kk of this block's group (blockIdx.z); slot kk = k holds |w_c|^2
 // over the chunk.  One wave per basis index, each wave holding the chunk of w.
-__global__ __launch_bounds__(256) void k_gs_dot(int64_t n, int r, const double2 *V, int k, int kgs, const double2 *w,
+template <typename VT>
+__global__ __launch_bounds__(256) void k_gs_dot(int64_t n, int r, const VT *V, int k, int kgs, const double2 *w,
                                                 const int *gate, double2 *part, int nchk)
 {
     const int c = blockIdx.y, ch = blockIdx.x, wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -65,14 +77,14 @@ __global__ __launch_bounds__(256) void k_gs_dot(int64_t n, int r, const double2 
     // whole chunks load without bounds checks (all kGsT loads of a lane in flight)
     const bool full = (int64_t)(ch + 1) * kWave * kGsT <= n;
     for (int kk = k0 + wv; kk < k1; kk += 4) {
-        const double2 *v = V + ((size_t)kk * r + c) * n + i0;
+        const VT *v = V + ((size_t)kk * r + c) * n + i0;
         double2 vv[kGsT];
         if (full) {
 #pragma unroll
-            for (int t = 0; t < kGsT; ++t) vv[t] = v[kWave * t];
+            for (int t = 0; t < kGsT; ++t) vv[t] = ld2(v + kWave * t);
         } else {
 #pragma unroll
-            for (int t = 0; t < kGsT; ++t) vv[t] = i0 + kWave * t < n ? v[kWave * t] : make_double2(0.0, 0.0);
+            for (int t = 0; t < kGsT; ++t) vv[t] = i0 + kWave * t < n ? ld2(v + kWave * t) : make_double2(0.0, 0.0);
         }
         double2 a = make_double2(0.0, 0.0);
 #pragma unroll
@@ -119,7 +131,8 @@ __global__ __launch_bounds__(256) void k_gs_sum(int r, int k, int nchk, const do
 // group (gridDim.z == 1) the result goes to y in place and the block's |y_c|^2 to
 // npart[c][block] (if npart); with several, group z writes its sum to
 // split[z][c][i] for k_gs_comb.
-__global__ __launch_bounds__(256) void k_gs_upd(int64_t n, int r, const double2 *V, int k, int kgs, const double2 *h,
+template <typename VT>
+__global__ __launch_bounds__(256) void k_gs_upd(int64_t n, int r, const VT *V, int k, int kgs, const double2 *h,
                                                 int hs, double sign, const int *gate, double2 *y, double2 *split,
                                                 double *npart, int nblk)
 {
@@ -141,9 +154,9 @@ __global__ __launch_bounds__(256) void k_gs_upd(int64_t n, int r, const double2 
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 hh[u] = hc[kk + u];
-                const double2 *v = V + ((size_t)(kk + u) * r + c) * n + i0;
+                const VT *v = V + ((size_t)(kk + u) * r + c) * n + i0;
 #pragma unroll
-                for (int e = 0; e < kGsE; ++e) vv[u][e] = v[256 * e];
+                for (int e = 0; e < kGsE; ++e) vv[u][e] = ld2(v + 256 * e);
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u)
@@ -155,12 +168,12 @@ __global__ __launch_bounds__(256) void k_gs_upd(int64_t n, int r, const double2 
         }
     for (; kk < k1; ++kk) {
         const double2 hh = hc[kk];
-        const double2 *v = V + ((size_t)kk * r + c) * n;
+        const VT *v = V + ((size_t)kk * r + c) * n;
 #pragma unroll
         for (int e = 0; e < kGsE; ++e) {
             const int64_t i = i0 + 256 * e;
             if (i < n) {
-                const double2 vv = v[i];
+                const double2 vv = ld2(v + i);
                 acc[e].x = fma(vv.x, hh.x, fma(-vv.y, hh.y, acc[e].x));
                 acc[e].y = fma(vv.x, hh.y, fma(vv.y, hh.x, acc[e].y));
             }
@@ -297,6 +310,19 @@ __global__ void k_scale_cols(int64_t n, const double *s, const double2 *x, doubl
     y[(size_t)c * n + i] = make_double2(sc * v.x, sc * v.y);
 }
 
+// y_c = s_c x_c and its FP32 copy v_c (s per column, real)
+__global__ void k_scale_cols32(int64_t n, const double *s, const double2 *x, double2 *y, float2 *v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (i >= n) return;
+    const double sc = s[c];
+    const double2 a = x[(size_t)c * n + i];
+    const double2 b = make_double2(sc * a.x, sc * a.y);
+    y[(size_t)c * n + i] = b;
+    v[(size_t)c * n + i] = make_float2((float)b.x, (float)b.y);
+}
+
 // y_c += s_c x_c (s per column, real)
 __global__ void k_axpy_cols(int64_t n, const double *s, const double2 *x, double2 *y)
 {
@@ -328,30 +354,58 @@ GsPlan gs_plan(int64_t n, int r, int kmax)
 size_t gs_part_count(const GsPlan &g, int r, int kmax) { return (size_t)r * (kmax + 1) * g.nchk; }
 size_t gs_split_count(const GsPlan &g, int64_t n, int r) { return g.upd_groups > 1 ? (size_t)g.upd_groups * r * n : 0; }
 
-void launch_gs_dots(hipStream_t s, const GsPlan &g, int64_t n, int r, const double2 *V, int k, const double2 *w,
-                    const int *gate, double2 *part, double2 *h, int hs, double *nb)
+namespace {
+template <typename VT>
+void gs_dots(hipStream_t s, const GsPlan &g, int64_t n, int r, const VT *V, int k, const double2 *w, const int *gate,
+             double2 *part, double2 *h, int hs, double *nb)
 {
     const int ng = std::max(1, std::min(g.dot_groups, cdiv(k, 4)));
     const int kgs = cdiv(k, ng);
-    hipLaunchKernelGGL(k_gs_dot, dim3(g.nchk, r, ng), dim3(256), 0, s, n, r, V, k, kgs, w, gate, part, g.nchk);
+    hipLaunchKernelGGL(k_gs_dot<VT>, dim3(g.nchk, r, ng), dim3(256), 0, s, n, r, V, k, kgs, w, gate, part, g.nchk);
     IGE_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_gs_sum, dim3(cdiv((int64_t)r * (k + 1), 4)), dim3(256), 0, s, r, k, g.nchk, part, gate, h, hs,
                        nb);
     IGE_HIP(hipGetLastError());
 }
 
-void launch_gs_update(hipStream_t s, const GsPlan &g, int64_t n, int r, const double2 *V, int k, const double2 *h,
-                      int hs, double sign, const int *gate, double2 *y, double2 *split, double *npart)
+template <typename VT>
+void gs_update(hipStream_t s, const GsPlan &g, int64_t n, int r, const VT *V, int k, const double2 *h, int hs,
+               double sign, const int *gate, double2 *y, double2 *split, double *npart)
 {
     const int ng = split ? std::max(1, std::min(g.upd_groups, cdiv(k, 8))) : 1;
     const int kgs = cdiv(k, ng);
-    hipLaunchKernelGGL(k_gs_upd, dim3(g.nblk, r, ng), dim3(256), 0, s, n, r, V, k, kgs, h, hs, sign, gate, y, split,
-                       npart, g.nblk);
+    hipLaunchKernelGGL(k_gs_upd<VT>, dim3(g.nblk, r, ng), dim3(256), 0, s, n, r, V, k, kgs, h, hs, sign, gate, y,
+                       split, npart, g.nblk);
     IGE_HIP(hipGetLastError());
     if (ng > 1) {
         hipLaunchKernelGGL(k_gs_comb, dim3(g.nblk, r), dim3(256), 0, s, n, r, ng, split, sign, gate, y, npart, g.nblk);
         IGE_HIP(hipGetLastError());
     }
+}
+}  // namespace
+
+void launch_gs_dots(hipStream_t s, const GsPlan &g, int64_t n, int r, const double2 *V, int k, const double2 *w,
+                    const int *gate, double2 *part, double2 *h, int hs, double *nb)
+{
+    gs_dots(s, g, n, r, V, k, w, gate, part, h, hs, nb);
+}
+
+void launch_gs_dots(hipStream_t s, const GsPlan &g, int64_t n, int r, const float2 *V, int k, const double2 *w,
+                    const int *gate, double2 *part, double2 *h, int hs, double *nb)
+{
+    gs_dots(s, g, n, r, V, k, w, gate, part, h, hs, nb);
+}
+
+void launch_gs_update(hipStream_t s, const GsPlan &g, int64_t n, int r, const double2 *V, int k, const double2 *h,
+                      int hs, double sign, const int *gate, double2 *y, double2 *split, double *npart)
+{
+    gs_update(s, g, n, r, V, k, h, hs, sign, gate, y, split, npart);
+}
+
+void launch_gs_update(hipStream_t s, const GsPlan &g, int64_t n, int r, const float2 *V, int k, const double2 *h,
+                      int hs, double sign, const int *gate, double2 *y, double2 *split, double *npart)
+{
+    gs_update(s, g, n, r, V, k, h, hs, sign, gate, y, split, npart);
 }
 
 void launch_gs_norm(hipStream_t s, const GsPlan &g, int r, const double *npart, const int *gate, const int *run,
@@ -385,6 +439,13 @@ void launch_axpy_cols(ige_op op, int r, const double *s, const double2 *x, doubl
 {
     const int64_t n = op->view.N;
     hipLaunchKernelGGL(k_axpy_cols, dim3(cdiv(n, 256), r), dim3(256), 0, op->ctx->stream, n, s, x, y);
+    IGE_HIP(hipGetLastError());
+}
+
+void launch_scale_cols32(ige_op op, int r, const double *s, const double2 *x, double2 *y, float2 *v)
+{
+    const int64_t n = op->view.N;
+    hipLaunchKernelGGL(k_scale_cols32, dim3(cdiv(n, 256), r), dim3(256), 0, op->ctx->stream, n, s, x, y, v);
     IGE_HIP(hipGetLastError());
 }
 

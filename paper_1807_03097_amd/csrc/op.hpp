@@ -167,6 +167,8 @@ struct ige_op_s {
     ige::DBuf<double2> d_bmom, d_bsrc, d_bpart, d_bloc, d_bybuf, d_bxt, d_byt, d_bx, d_by;
     // GMRES workspace
     ige::DBuf<double2> d_V, d_w, d_r, d_X, d_F, d_D;
+    ige::DBuf<float2> d_V32;           // FP32 Krylov basis of the inner solves of refinement
+    ige::DBuf<double2> d_wcur;         // FP64 current basis vectors (with the FP32 basis)
     ige::DBuf<double2> d_h;                          // [2][r][restart + 2] per-pass coefficients
     ige::DBuf<double> d_red, d_scal;
     ige::DBuf<double2> d_gspart, d_gsplit, d_hpack;  // Gram-Schmidt partials, split sums, packed column
@@ -266,6 +268,11 @@ void launch_gs_dots(hipStream_t s, const GsPlan &g, int64_t n, int r, const doub
 // y_c += sign V_c h_c for gate columns; npart (if given) gets per-block |y_c|^2
 void launch_gs_update(hipStream_t s, const GsPlan &g, int64_t n, int r, const double2 *V, int k, const double2 *h,
                       int hs, double sign, const int *gate, double2 *y, double2 *split, double *npart);
+// the same two passes over an FP32 basis (sums and w, y in FP64)
+void launch_gs_dots(hipStream_t s, const GsPlan &g, int64_t n, int r, const float2 *V, int k, const double2 *w,
+                    const int *gate, double2 *part, double2 *h, int hs, double *nb);
+void launch_gs_update(hipStream_t s, const GsPlan &g, int64_t n, int r, const float2 *V, int k, const double2 *h,
+                      int hs, double sign, const int *gate, double2 *y, double2 *split, double *npart);
 // nf = |y|^2 of gate columns; scal = 1/|y| for run columns (0 for the others);
 // flag (if given) = second Gram-Schmidt pass needed
 void launch_gs_norm(hipStream_t s, const GsPlan &g, int r, const double *npart, const int *gate, const int *run,
@@ -275,6 +282,8 @@ void launch_gs_pack(hipStream_t s, int r, int k, const double2 *h1, const double
 void launch_axpby(ige_op op, int64_t n, double2 a, const double2 *x, double2 b, double2 *y);
 void launch_norm2_b(ige_op op, int r, const double2 *x, double *out);
 void launch_scale_cols(ige_op op, int r, const double *s, const double2 *x, double2 *y);
+// y_c = s_c x_c and v_c = (FP32) y_c
+void launch_scale_cols32(ige_op op, int r, const double *s, const double2 *x, double2 *y, float2 *v);
 void launch_axpy_cols(ige_op op, int r, const double *s, const double2 *x, double2 *y);
 // x == nullptr: the input is already in xt; y == nullptr: the result stays in yt
 void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, double2 *yt, hipEvent_t *ev, int prec);
