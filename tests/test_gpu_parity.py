@@ -417,6 +417,37 @@ def test_refinement_escalates_inner_precision(ctx):
     op.close()
 
 
+@pytest.mark.parametrize("inner_tol", [1e-4, 1e-6], ids=["fp32-basis", "fp64-basis"])
+def test_inner_krylov_basis_precision(ctx, monkeypatch, inner_tol):
+    """Refined solves of 3 waves with the inner Krylov basis in FP32 (default for
+    inner_tol >= 1e-5) and in FP64 (IGE_INNER_BASIS=fp64, or a tighter inner_tol) both
+    meet the FP64 tolerance and agree with the FP64 solve to 1e-6."""
+    from paper_1807_03097_amd import binding as B
+    geom = B.Geometry(ctx, _geom("sphere"))
+    op = B.Operator(geom, 2, 3, 8.0, 8, 1.6, 5, 5, 1)
+    dirs, pols = W.fibonacci_plane_waves(3)
+    F = op.rhs_plane_wave(dirs, pols)
+    X64, st64, rc = op.solve(F, tol=1e-10, restart=100, maxit=4000)
+    assert rc == 0
+    res = {}
+    for basis in ("default", "fp64"):
+        if basis == "fp64":
+            monkeypatch.setenv("IGE_INNER_BASIS", "fp64")
+        Xr, st, rc2 = op.solve(F, tol=1e-10, restart=100, maxit=6000, refine=True, inner_tol=inner_tol,
+                               inner_prec=B.IGE_BF16X3)
+        monkeypatch.delenv("IGE_INNER_BASIS", raising=False)
+        assert rc2 == 0
+        for c in range(3):
+            _say(f"  {basis} basis, inner_tol {inner_tol}: col {c} iters {st[c][0]} outer {st[c][1]} "
+                 f"relres {st[c][2]:.2e}")
+            assert st[c][2] <= 1.05e-10
+            assert _rel(Xr[c], X64[c]) <= 1e-6
+        res[basis] = Xr
+    if inner_tol < 1e-5:   # both runs used the FP64 basis: identical
+        assert max(_rel(res["default"][c], res["fp64"][c]) for c in range(3)) == 0.0
+    op.close()
+
+
 @pytest.mark.parametrize("name, p, m, kappa", [("sphere", 2, 3, 8.0), ("torus", 1, 3, 3.0), ("jittered", 2, 2, 5.0)])
 def test_potential_matches_oracle(oracle_mod, ctx, name, p, m, kappa):
     """Scattered field e_s = V~ w at points off the surface (two columns)."""
