@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--kappa", type=float, default=8.0, help="solve: wavenumber")
     ap.add_argument("--q", type=int, default=8, help="solve: interpolation degree")
     ap.add_argument("--tol", type=float, default=1e-6, help="solve: relative residual")
+    ap.add_argument("--jitter", type=float, default=0.0,
+                    help="solve: standard deviation of the control-point jitter of the cube-sphere (0: none)")
+    ap.add_argument("--jitter-seed", type=int, default=7, help="solve: seed of the jitter")
     ap.add_argument("--restart", type=int, default=1500, help="solve: GMRES restart")
     ap.add_argument("--inner-prec", type=int, default=3, choices=(0, 1, 2, 3, 4),
                     help="solve: precision of refined inner solves (as --prec)")
@@ -139,7 +142,10 @@ def run_solve(args):
 
     torch.cuda.set_device(0)
     ctx = B.Context(0)
-    geom = B.Geometry(ctx, W.cube_sphere())
+    pats = W.cube_sphere()
+    if args.jitter > 0:
+        pats = W.jitter(pats, args.jitter, args.jitter_seed)
+    geom = B.Geometry(ctx, pats)
     t0 = time.perf_counter()
     op = B.Operator(geom, args.p, args.level, args.kappa, args.q, args.eta, 5, 5, args.leaf_depth)
     t_asm = time.perf_counter() - t0
@@ -185,7 +191,9 @@ def run_solve(args):
         "higher_is_better": True,
         "dtype": "f64" if not args.refine else f"f64 refinement around {prec_name}",
         "data": "synthetic",
-        "config": {"workload": f"cube-sphere, level {args.level}, p={args.p}, kappa={args.kappa}, q={args.q}, "
+        "config": {"workload": f"cube-sphere" + (f" jittered N(0,{args.jitter}^2) seed {args.jitter_seed}"
+                                                  if args.jitter > 0 else "")
+                               + f", level {args.level}, p={args.p}, kappa={args.kappa}, q={args.q}, "
                                f"eta={args.eta}, {args.nrhs} Fibonacci plane waves, GMRES tol {args.tol}, "
                                f"restart {args.restart}", "n_dof": op.N},
         "assemble_s": t_asm,

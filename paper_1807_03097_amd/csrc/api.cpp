@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <functional>
@@ -1027,6 +1028,16 @@ struct GmresOut {
 // precision prec, starting from X (device, [r][N], updated in place); each column
 // stops when its residual estimate reaches tol * ||B_c||.  it_cap: per-column
 // iteration budget.
+// progress lines on stderr (one per GMRES cycle and refinement step) with IGE_SOLVE_LOG=1
+bool solve_log()
+{
+    static const bool on = [] {
+        const char *e = std::getenv("IGE_SOLVE_LOG");
+        return e && std::atoi(e) != 0;
+    }();
+    return on;
+}
+
 // b32: the Krylov basis stored in FP32 (inner solves of refinement); the vector being
 // orthogonalised, every sum and the solution stay FP64, and the operator is applied to
 // the FP64 basis vector before rounding
@@ -1113,6 +1124,17 @@ void gmres_batched(ige_op op, int r, const double2 *B, double2 *X, const std::ve
             out.relres_est[c] = bnorm[c] > 0 ? beta[c] / bnorm[c] : 0.0;
             act[c] = bnorm[c] > 0 && out.relres_est[c] > tol[c] && out.iters[c] < it_cap[c];
             nact += act[c];
+        }
+        if (solve_log()) {
+            double worst = 0.0;
+            int itmax = 0;
+            for (int c = 0; c < r; ++c) {
+                worst = std::max(worst, out.relres_est[c]);
+                itmax = std::max(itmax, out.iters[c]);
+            }
+            std::fprintf(stderr, "[igaefie] gmres cycle: %d of %d columns active, iterations %d, max relres %.3e\n",
+                         nact, r, itmax, worst);
+            std::fflush(stderr);
         }
         if (nact == 0) return;
         std::vector<double> sc(r);
@@ -1311,6 +1333,17 @@ int ige_solve(ige_op op, int r, const ige_c64 *f, ige_c64 *x, int ptr_kind, cons
                     any = any || need;
                 }
                 if (!any) break;
+                if (solve_log()) {
+                    double worst = 0.0;
+                    int itmax = 0;
+                    for (int c = 0; c < r; ++c) {
+                        worst = std::max(worst, relres[c]);
+                        itmax = std::max(itmax, iters[c]);
+                    }
+                    std::fprintf(stderr, "[igaefie] refinement step: FP64 max relres %.3e, iterations %d, inner "
+                                         "precision %d\n", worst, itmax, cur);
+                    std::fflush(stderr);
+                }
                 IGE_HIP(hipMemsetAsync(op->d_D.p, 0, sizeof(double2) * r * N, s));
                 // columns already converged get an inner budget of 0 and a zero correction
                 gmres_batched(op, r, op->d_r.p, op->d_D.p, itol, opts->restart, cap, cur, go, inner_b32);
