@@ -48,9 +48,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=16, help="rows of the bounded oracle sample")
     ap.add_argument("--nrhs", type=int, default=1, help="right-hand sides per apply (batched kernels when > 1)")
-    ap.add_argument("--prec", type=int, default=0, choices=(0, 1, 2, 3, 4),
+    ap.add_argument("--prec", type=int, default=0, choices=(0, 1, 2, 3, 4, 5),
                     help="coupling precision: 0 FP64, 1 FP32, 2 BF16 matrix cores, 3 split BF16 (3 products), "
-                         "4 split BF16 coupling and near field")
+                         "4 split BF16 coupling and near field, 5 FP32 coupling and (one column) near field")
     ap.add_argument("--store-coupling", type=int, default=-1, choices=(-1, 0, 1),
                     help="coupling blocks: 1 stored, 0 evaluated per apply, -1 stored if they fit")
     ap.add_argument("--verbose", action="store_true")
@@ -63,7 +63,7 @@ def parse():
                     help="solve: standard deviation of the control-point jitter of the cube-sphere (0: none)")
     ap.add_argument("--jitter-seed", type=int, default=7, help="solve: seed of the jitter")
     ap.add_argument("--restart", type=int, default=1500, help="solve: GMRES restart")
-    ap.add_argument("--inner-prec", type=int, default=3, choices=(0, 1, 2, 3, 4),
+    ap.add_argument("--inner-prec", type=int, default=3, choices=(0, 1, 2, 3, 4, 5),
                     help="solve: precision of refined inner solves (as --prec)")
     ap.add_argument("--compare-fp64", action="store_true", help="solve: also solve in FP64 and report the difference")
     ap.add_argument("--autotune", action="store_true",
@@ -77,6 +77,10 @@ def parse():
     ap.add_argument("--refine", action="store_true",
                     help="serve / solve: FP64 refinement around solves with the --inner-prec coupling")
     return ap.parse_args()
+
+
+PREC_NAMES = ["f64", "f32 coupling", "bf16 coupling", "split-bf16 coupling", "split-bf16 coupling and near field",
+              "f32 coupling and near field"]
 
 
 def log(*a):
@@ -181,8 +185,7 @@ def run_solve(args):
         diff = max(float(np.linalg.norm(sols["refined"][c] - sols["fp64"][c]) / np.linalg.norm(sols["fp64"][c]))
                    for c in range(args.nrhs))
         log(f"refined vs FP64 solutions: max relative difference {diff:.2e}")
-    prec_name = ["f64", "f32 coupling", "bf16 coupling", "split-bf16 coupling",
-                 "split-bf16 coupling and near field"][args.inner_prec]
+    prec_name = PREC_NAMES[args.inner_prec]
     out = {
         "metric": "EFIE solves/s",
         "value": runs[0]["solves_per_s"],
@@ -254,8 +257,7 @@ def run_serving(args):
         "unit": "solves/s",
         "n_gpus": 1,
         "higher_is_better": True,
-        "dtype": "f64" if not args.refine else ["f64", "f32 coupling", "bf16 coupling", "split-bf16 coupling",
-                                                 "split-bf16 coupling and near field"][args.inner_prec] + " + f64 refinement",
+        "dtype": "f64" if not args.refine else PREC_NAMES[args.inner_prec] + " + f64 refinement",
         "data": "synthetic",
         "p50_latency_s": float(np.percentile(lat, 50)),
         "p99_latency_s": float(np.percentile(lat, 99)),
@@ -364,7 +366,7 @@ def main():
         """Matrix-core coupling (r > 1, BF16 precisions; FP64 with 8 or more columns):
         issued matrix-core operations of the real product [[Gr,-Gi],[Gi,Gr]] . [Re V; Im V]
         over padded 2Qp x 2Qp blocks and column chunks, over the kernel's own time."""
-        if not (f64mx or (args.prec >= 2 and r > 1)):
+        if not (f64mx or (args.prec in (2, 3, 4) and r > 1)):
             return None
         Q, Qp = Qc, Qpc
         MT = Qp // 16
@@ -389,7 +391,7 @@ def main():
     def roofline(stage_ms):
         # the dominant kernel: the near-field block pass or the coupling kernel
         dom = "near_spmv" if stage_ms["near_blk"] >= stage_ms["m2l_kernel"] else "m2l"
-        if dom == "m2l" and (f64mx or (args.prec >= 2 and r > 1)):
+        if dom == "m2l" and (f64mx or (args.prec in (2, 3, 4) and r > 1)):
             return roofline_coupling(stage_ms)   # the matrix-core coupling kernel
         Q = (q + 1) ** 2
         if dom == "near_spmv" and r > 1:
@@ -477,7 +479,8 @@ def main():
         "vs_baseline": None,
         "dtype": ["f64", "f64 (f32 coupling)", "f64 (bf16 matrix-core coupling)",
                   "f64 (split-bf16 matrix-core coupling)",
-                  "f64 moments/transfers (split-bf16 coupling and near field)"][args.prec],
+                  "f64 moments/transfers (split-bf16 coupling and near field)",
+                  "f64 moments/transfers (f32 coupling and near field)"][args.prec],
         "data": "synthetic",
         "config": {"workload": f"FMM matvec: 6-patch NURBS sphere, level {m}, p={p}, kappa={kappa}, q={q}, "
                                f"5x5 Gauss near field, x ~ N(0,1)+iN(0,1) seed 0",

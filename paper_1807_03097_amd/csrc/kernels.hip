@@ -1047,8 +1047,20 @@ __device__ inline double wave_sum(double v)
     return v;
 }
 
-template <int U>
-__global__ __launch_bounds__(256) void k_near_blk(DevOp o, const double2 *x, double2 *part)
+__device__ inline d2v ld_blk(const double2 *B, size_t i)
+{
+    return __builtin_nontemporal_load(reinterpret_cast<const d2v *>(B) + i);
+}
+__device__ inline d2v ld_blk(const float2 *B, size_t i)
+{
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    const f2v v = __builtin_nontemporal_load(reinterpret_cast<const f2v *>(B) + i);
+    return d2v{(double)v.x, (double)v.y};
+}
+
+// BT: block entries in FP64 (double2) or as an FP32 copy (float2), FP64 sums either way
+template <int U, typename BT>
+__global__ __launch_bounds__(256) void k_near_blk(DevOp o, const BT *bv, const double2 *x, double2 *part)
 {
     __shared__ double2 sxr[64 * U];
     __shared__ double2 syc[3][64 * U];
@@ -1071,7 +1083,7 @@ __global__ __launch_bounds__(256) void k_near_blk(DevOp o, const double2 *x, dou
         sxr[k] = d >= 0 ? x[d] : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    const d2v *B = reinterpret_cast<const d2v *>(o.bval) + (size_t)b * nF * nF;
+    const BT *B = bv + (size_t)b * nF * nF;
     int r = r0 + wv;
     // two rows per step: 2U independent streaming loads in flight per lane
     for (; r + 4 < r1; r += 8) {
@@ -1079,8 +1091,8 @@ __global__ __launch_bounds__(256) void k_near_blk(DevOp o, const double2 *x, dou
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int c = lane + 64 * u;
-            a0[u] = c < nF ? __builtin_nontemporal_load(B + (size_t)r * nF + c) : d2v{0.0, 0.0};
-            a1[u] = c < nF ? __builtin_nontemporal_load(B + (size_t)(r + 4) * nF + c) : d2v{0.0, 0.0};
+            a0[u] = c < nF ? ld_blk(B, (size_t)r * nF + c) : d2v{0.0, 0.0};
+            a1[u] = c < nF ? ld_blk(B, (size_t)(r + 4) * nF + c) : d2v{0.0, 0.0};
         }
         const double2 x0 = sxr[r - r0], x1 = sxr[r + 4 - r0];
         double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
@@ -1109,7 +1121,7 @@ __global__ __launch_bounds__(256) void k_near_blk(DevOp o, const double2 *x, dou
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int c = lane + 64 * u;
-            a0[u] = c < nF ? __builtin_nontemporal_load(B + (size_t)r * nF + c) : d2v{0.0, 0.0};
+            a0[u] = c < nF ? ld_blk(B, (size_t)r * nF + c) : d2v{0.0, 0.0};
         }
         const double2 x0 = sxr[r - r0];
         double re0 = 0.0, im0 = 0.0;
@@ -1458,7 +1470,44 @@ int near_blk_u(int nF)
     return 16;
 }
 
-void launch_spmv(ige_op op, const double2 *x, double2 *y, hipStream_t st, hipEvent_t mid)
+namespace {
+__global__ void k_to_f32(int64_t n, const double2 *a, float2 *b)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = make_float2((float)a[i].x, (float)a[i].y);
+}
+
+template <typename BT>
+void launch_near_blk(ige_op op, const BT *bv, const double2 *x, double2 *part, hipStream_t st)
+{
+    const DevOp &o = op->view;
+    const dim3 grid((unsigned)(o.nblk * o.nch)), blk(256);
+    switch (near_blk_u(o.nF)) {
+        case 1: hipLaunchKernelGGL((k_near_blk<1, BT>), grid, blk, 0, st, o, bv, x, part); break;
+        case 2: hipLaunchKernelGGL((k_near_blk<2, BT>), grid, blk, 0, st, o, bv, x, part); break;
+        case 3: hipLaunchKernelGGL((k_near_blk<3, BT>), grid, blk, 0, st, o, bv, x, part); break;
+        case 4: hipLaunchKernelGGL((k_near_blk<4, BT>), grid, blk, 0, st, o, bv, x, part); break;
+        case 6: hipLaunchKernelGGL((k_near_blk<6, BT>), grid, blk, 0, st, o, bv, x, part); break;
+        case 8: hipLaunchKernelGGL((k_near_blk<8, BT>), grid, blk, 0, st, o, bv, x, part); break;
+        case 12: hipLaunchKernelGGL((k_near_blk<12, BT>), grid, blk, 0, st, o, bv, x, part); break;
+        default: hipLaunchKernelGGL((k_near_blk<16, BT>), grid, blk, 0, st, o, bv, x, part); break;
+    }
+    IGE_LAUNCH_CHECK();
+}
+}  // namespace
+
+void ensure_near32(ige_op op)
+{
+    const DevOp &o = op->view;
+    if (op->d_bval32.p || o.nblk == 0) return;
+    const int64_t n = o.nblk * (int64_t)o.nF * o.nF;
+    op->d_bval32.alloc((size_t)n);
+    hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, lstream(op), n, o.bval,
+                       op->d_bval32.p);
+    IGE_LAUNCH_CHECK();
+}
+
+void launch_spmv(ige_op op, const double2 *x, double2 *y, hipStream_t st, hipEvent_t mid, bool near32)
 {
     const DevOp &o = op->view;
     if (o.nblk == 0) {
@@ -1466,19 +1515,13 @@ void launch_spmv(ige_op op, const double2 *x, double2 *y, hipStream_t st, hipEve
         if (mid) IGE_HIP(hipEventRecord(mid, st));
         return;
     }
-    const dim3 grid((unsigned)(o.nblk * o.nch)), blk(256);
     double2 *part = op->d_npart.p;
-    switch (near_blk_u(o.nF)) {
-        case 1: hipLaunchKernelGGL(k_near_blk<1>, grid, blk, 0, st, o, x, part); break;
-        case 2: hipLaunchKernelGGL(k_near_blk<2>, grid, blk, 0, st, o, x, part); break;
-        case 3: hipLaunchKernelGGL(k_near_blk<3>, grid, blk, 0, st, o, x, part); break;
-        case 4: hipLaunchKernelGGL(k_near_blk<4>, grid, blk, 0, st, o, x, part); break;
-        case 6: hipLaunchKernelGGL(k_near_blk<6>, grid, blk, 0, st, o, x, part); break;
-        case 8: hipLaunchKernelGGL(k_near_blk<8>, grid, blk, 0, st, o, x, part); break;
-        case 12: hipLaunchKernelGGL(k_near_blk<12>, grid, blk, 0, st, o, x, part); break;
-        default: hipLaunchKernelGGL(k_near_blk<16>, grid, blk, 0, st, o, x, part); break;
+    if (near32) {
+        IGE_REQUIRE(op->d_bval32.p, "FP32 near-field blocks not made");
+        launch_near_blk(op, (const float2 *)op->d_bval32.p, x, part, st);
+    } else {
+        launch_near_blk(op, (const double2 *)o.bval, x, part, st);
     }
-    IGE_LAUNCH_CHECK();
     if (mid) IGE_HIP(hipEventRecord(mid, st));
     hipLaunchKernelGGL(k_near_gather, dim3((unsigned)(((int64_t)o.N * 16 + 255) / 256)), dim3(256), 0, st, o.N, o.red_ptr, o.red_idx, part, y);
     IGE_LAUNCH_CHECK();

@@ -276,11 +276,13 @@ __global__ void k_gs_pack(int r, int k, const double2 *h1, const double2 *h2, in
     out[id] = v;
 }
 
+// y = a x + b y; with b = 0 the old y is not read (it may hold anything, NaN included)
 __global__ void k_axpby(int64_t n, double2 a, const double2 *x, double2 b, double2 *y)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    y[i] = dm::cadd(dm::cmul(a, x[i]), dm::cmul(b, y[i]));
+    const double2 ax = dm::cmul(a, x[i]);
+    y[i] = (b.x == 0.0 && b.y == 0.0) ? ax : dm::cadd(ax, dm::cmul(b, y[i]));
 }
 
 // out[c] = |x_c|, one block per column, fixed-order reduction

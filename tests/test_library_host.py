@@ -61,7 +61,7 @@ def test_invalid_geometry_is_rejected():
         op.autotune(4, B.IGE_BF16X3)                 # planned, not assembled
     assert e.value.code == B.IGE_EINVAL
     with pytest.raises(B.IgeError):
-        op.apply(np.zeros(op.N, np.complex128), prec=5)   # no such precision
+        op.apply(np.zeros(op.N, np.complex128), prec=6)   # no such precision
 
 
 @pytest.mark.parametrize("geom,p,m,eta,d,q", [
