@@ -53,40 +53,6 @@ __device__ inline d2v load_g(const float2 *p)
     return d2v{(double)v.x, (double)v.y};
 }
 
-// Sum V values over the 64 lanes of a wave by recursive halving: at each step a
-// lane keeps half of its values and adds the partner's copy of that half.  On exit
-// every lane holds the total of value index lane >> (6 - log2 V).
-template <int V>
-struct Halve {
-    static __device__ double run(const double *a, int lane, int off)
-    {
-        constexpr int H = V / 2;
-        double b[H];
-        const bool hi = (lane & off) != 0;
-#pragma unroll
-        for (int i = 0; i < H; ++i) {
-            const double send = hi ? a[i] : a[H + i];
-            const double keep = hi ? a[H + i] : a[i];
-            b[i] = keep + __shfl_xor(send, off, kWave);
-        }
-        return Halve<H>::run(b, lane, off >> 1);
-    }
-};
-template <>
-struct Halve<1> {
-    static __device__ double run(const double *a, int, int off)
-    {
-        double v = a[0];
-        for (; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
-        return v;
-    }
-};
-template <int V>
-constexpr int log2c()
-{
-    return V <= 1 ? 0 : 1 + log2c<V / 2>();
-}
-
 // One workgroup per stored pair; wave w takes the rows m = w, w + 4, ...; lanes own
 // the columns m' = lane + 64 u.  Row sums are reduced across the wave by halving;
 // column sums accumulate in registers and are combined over the waves in order.
@@ -155,8 +121,8 @@ __global__ __launch_bounds__(256) void k_m2l_g(DevOp o, int r, int c0, const int
                     a[2 * (f * RB + j)] = re;
                     a[2 * (f * RB + j) + 1] = im;
                 }
-            const double tot = Halve<NV>::run(a, lane, 32);
-            constexpr int SH = 6 - log2c<NV>();
+            const double tot = dm::Halve<NV>::run(a, lane, 32);
+            constexpr int SH = 6 - dm::log2c<NV>();
             if ((lane & ((1 << SH) - 1)) == 0) {
                 const int k = lane >> SH, comp = k & 1, fj = k >> 1, f = fj / RB, j = fj % RB;
                 prow[(((size_t)f * Q + m) * RB + j) * 2 + comp] = tot;
@@ -261,7 +227,7 @@ __global__ __launch_bounds__(256) void k_m2l_t(DevOp o, const int32_t *fpair, co
             }
             load_row(it + kDepth, gb[d]);
             // halving over offsets 16, 8, 4, then full steps 2, 1: value (lane >> 2) & 7
-            const double tot = Halve<8>::run(a, lane, 16);
+            const double tot = dm::Halve<8>::run(a, lane, 16);
             if (ok && (lane & 3) == 0) {
                 const int kk = (lane >> 2) & 7;
                 srow[kk >> 1][m][kk & 1] = tot;

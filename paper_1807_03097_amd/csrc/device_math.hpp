@@ -155,5 +155,39 @@ __device__ inline float2 to_c(double2 a, float) { return make_float2((float)a.x,
 __device__ inline double2 to_d(double2 a) { return a; }
 __device__ inline double2 to_d(float2 a) { return make_double2(a.x, a.y); }
 
+// Sum V values over the 64 lanes of a wave by recursive halving: at each step a
+// lane keeps half of its values and adds the partner's copy of that half.  On exit
+// every lane holds the total of value index lane >> (6 - log2 V).
+template <int V>
+struct Halve {
+    static __device__ double run(const double *a, int lane, int off)
+    {
+        constexpr int H = V / 2;
+        double b[H];
+        const bool hi = (lane & off) != 0;
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            const double send = hi ? a[i] : a[H + i];
+            const double keep = hi ? a[H + i] : a[i];
+            b[i] = keep + __shfl_xor(send, off, 64);
+        }
+        return Halve<H>::run(b, lane, off >> 1);
+    }
+};
+template <>
+struct Halve<1> {
+    static __device__ double run(const double *a, int, int off)
+    {
+        double v = a[0];
+        for (; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        return v;
+    }
+};
+template <int V>
+constexpr int log2c()
+{
+    return V <= 1 ? 0 : 1 + log2c<V / 2>();
+}
+
 }  // namespace dm
 }  // namespace ige

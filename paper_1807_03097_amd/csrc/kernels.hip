@@ -1047,16 +1047,20 @@ __device__ inline double wave_sum(double v)
     return v;
 }
 
+typedef float f2v __attribute__((ext_vector_type(2)));
+template <typename BT> struct BlkReg;   // register type of a loaded block entry
+template <> struct BlkReg<double2> { using type = d2v; };
+template <> struct BlkReg<float2> { using type = f2v; };
 __device__ inline d2v ld_blk(const double2 *B, size_t i)
 {
     return __builtin_nontemporal_load(reinterpret_cast<const d2v *>(B) + i);
 }
-__device__ inline d2v ld_blk(const float2 *B, size_t i)
+__device__ inline f2v ld_blk(const float2 *B, size_t i)
 {
-    typedef float f2v __attribute__((ext_vector_type(2)));
-    const f2v v = __builtin_nontemporal_load(reinterpret_cast<const f2v *>(B) + i);
-    return d2v{(double)v.x, (double)v.y};
+    return __builtin_nontemporal_load(reinterpret_cast<const f2v *>(B) + i);
 }
+__device__ inline d2v to_d2v(d2v v) { return v; }
+__device__ inline d2v to_d2v(f2v v) { return d2v{(double)v.x, (double)v.y}; }
 
 // BT: block entries in FP64 (double2) or as an FP32 copy (float2), FP64 sums either way
 template <int U, typename BT>
@@ -1085,56 +1089,58 @@ __global__ __launch_bounds__(256) void k_near_blk(DevOp o, const BT *bv, const d
     __syncthreads();
     const BT *B = bv + (size_t)b * nF * nF;
     int r = r0 + wv;
-    // two rows per step: 2U independent streaming loads in flight per lane
-    for (; r + 4 < r1; r += 8) {
-        d2v a0[U], a1[U];
+    // RS rows per step (r, r + 4, ...): RS U independent streaming loads in flight per lane
+    // (eight rows for the 8-byte FP32 entries, two for FP64)
+    constexpr int RS = sizeof(BT) == sizeof(double2) ? 2 : 8;
+    using LT = typename BlkReg<BT>::type;
+    // (the last step of a wave may hold fewer rows: the others load and add zeros)
+    for (; r < r1; r += 4 * RS) {
+        LT al[RS][U];   // entries as loaded, widened to FP64 at use
+#pragma unroll
+        for (int q = 0; q < RS; ++q)
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int c = lane + 64 * u;
+                al[q][u] = (c < nF && r + 4 * q < r1) ? ld_blk(B, (size_t)(r + 4 * q) * nF + c) : LT{0, 0};
+            }
+        double2 xq[RS];
+        double re[RS], im[RS];
+#pragma unroll
+        for (int q = 0; q < RS; ++q) {
+            xq[q] = r + 4 * q < r1 ? sxr[r + 4 * q - r0] : make_double2(0.0, 0.0);
+            re[q] = 0.0;
+            im[q] = 0.0;
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int c = lane + 64 * u;
-            a0[u] = c < nF ? ld_blk(B, (size_t)r * nF + c) : d2v{0.0, 0.0};
-            a1[u] = c < nF ? ld_blk(B, (size_t)(r + 4) * nF + c) : d2v{0.0, 0.0};
-        }
-        const double2 x0 = sxr[r - r0], x1 = sxr[r + 4 - r0];
-        double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
+            d2v a[RS];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            re0 = fma(a0[u].x, xc[u].x, fma(-a0[u].y, xc[u].y, re0));
-            im0 = fma(a0[u].x, xc[u].y, fma(a0[u].y, xc[u].x, im0));
-            re1 = fma(a1[u].x, xc[u].x, fma(-a1[u].y, xc[u].y, re1));
-            im1 = fma(a1[u].x, xc[u].y, fma(a1[u].y, xc[u].x, im1));
-            yc[u].x = fma(a0[u].x, x0.x, fma(-a0[u].y, x0.y, yc[u].x));
-            yc[u].y = fma(a0[u].x, x0.y, fma(a0[u].y, x0.x, yc[u].y));
-            yc[u].x = fma(a1[u].x, x1.x, fma(-a1[u].y, x1.y, yc[u].x));
-            yc[u].y = fma(a1[u].x, x1.y, fma(a1[u].y, x1.x, yc[u].y));
-        }
-        re0 = wave_sum(re0);
-        im0 = wave_sum(im0);
-        re1 = wave_sum(re1);
-        im1 = wave_sum(im1);
-        if (lane == 0) {
-            part[(size_t)b * nF + r] = make_double2(re0, im0);
-            part[(size_t)b * nF + r + 4] = make_double2(re1, im1);
-        }
-    }
-    for (; r < r1; r += 4) {
-        d2v a0[U];
+            for (int q = 0; q < RS; ++q) a[q] = to_d2v(al[q][u]);
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int c = lane + 64 * u;
-            a0[u] = c < nF ? ld_blk(B, (size_t)r * nF + c) : d2v{0.0, 0.0};
-        }
-        const double2 x0 = sxr[r - r0];
-        double re0 = 0.0, im0 = 0.0;
+            for (int q = 0; q < RS; ++q) {
+                re[q] = fma(a[q].x, xc[u].x, fma(-a[q].y, xc[u].y, re[q]));
+                im[q] = fma(a[q].x, xc[u].y, fma(a[q].y, xc[u].x, im[q]));
+            }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            re0 = fma(a0[u].x, xc[u].x, fma(-a0[u].y, xc[u].y, re0));
-            im0 = fma(a0[u].x, xc[u].y, fma(a0[u].y, xc[u].x, im0));
-            yc[u].x = fma(a0[u].x, x0.x, fma(-a0[u].y, x0.y, yc[u].x));
-            yc[u].y = fma(a0[u].x, x0.y, fma(a0[u].y, x0.x, yc[u].y));
+            for (int q = 0; q < RS; ++q) {
+                yc[u].x = fma(a[q].x, xq[q].x, fma(-a[q].y, xq[q].y, yc[u].x));
+                yc[u].y = fma(a[q].x, xq[q].y, fma(a[q].y, xq[q].x, yc[u].y));
+            }
         }
-        re0 = wave_sum(re0);
-        im0 = wave_sum(im0);
-        if (lane == 0) part[(size_t)b * nF + r] = make_double2(re0, im0);
+        // the 2 RS row sums over the wave by recursive halving (one value per lane group)
+        double v[2 * RS];
+#pragma unroll
+        for (int q = 0; q < RS; ++q) {
+            v[2 * q] = re[q];
+            v[2 * q + 1] = im[q];
+        }
+        const double tot = dm::Halve<2 * RS>::run(v, lane, 32);
+        constexpr int SH = 6 - dm::log2c<2 * RS>();
+        if ((lane & ((1 << SH) - 1)) == 0) {
+            const int k = lane >> SH;   // value 2 q + (0: real, 1: imaginary part)
+            if (r + 4 * (k >> 1) < r1)
+                reinterpret_cast<double *>(part)[2 * ((size_t)b * nF + r + 4 * (k >> 1)) + (k & 1)] = tot;
+        }
     }
     if (lt == ls) return;   // diagonal block: no transposed product (uniform branch)
     if (wv > 0)
