@@ -48,9 +48,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=16, help="rows of the bounded oracle sample")
     ap.add_argument("--nrhs", type=int, default=1, help="right-hand sides per apply (batched kernels when > 1)")
-    ap.add_argument("--prec", type=int, default=0, choices=(0, 1, 2, 3, 4, 5),
+    ap.add_argument("--prec", type=int, default=0, choices=(0, 1, 2, 3, 4),
                     help="coupling precision: 0 FP64, 1 FP32, 2 BF16 matrix cores, 3 split BF16 (3 products), "
-                         "4 split BF16 coupling and near field, 5 FP32 coupling and (one column) near field")
+                         "4 split BF16 coupling and near field")
     ap.add_argument("--store-coupling", type=int, default=-1, choices=(-1, 0, 1),
                     help="coupling blocks: 1 stored, 0 evaluated per apply, -1 stored if they fit")
     ap.add_argument("--verbose", action="store_true")
@@ -63,7 +63,7 @@ def parse():
                     help="solve: standard deviation of the control-point jitter of the cube-sphere (0: none)")
     ap.add_argument("--jitter-seed", type=int, default=7, help="solve: seed of the jitter")
     ap.add_argument("--restart", type=int, default=1500, help="solve: GMRES restart")
-    ap.add_argument("--inner-prec", type=int, default=3, choices=(0, 1, 2, 3, 4, 5),
+    ap.add_argument("--inner-prec", type=int, default=3, choices=(0, 1, 2, 3, 4),
                     help="solve: precision of refined inner solves (as --prec)")
     ap.add_argument("--compare-fp64", action="store_true", help="solve: also solve in FP64 and report the difference")
     ap.add_argument("--autotune", action="store_true",
@@ -79,8 +79,7 @@ def parse():
     return ap.parse_args()
 
 
-PREC_NAMES = ["f64", "f32 coupling", "bf16 coupling", "split-bf16 coupling", "split-bf16 coupling and near field",
-              "f32 coupling and near field"]
+PREC_NAMES = ["f64", "f32 coupling", "bf16 coupling", "split-bf16 coupling", "split-bf16 coupling and near field"]
 
 
 def log(*a):
@@ -479,8 +478,7 @@ def main():
         "vs_baseline": None,
         "dtype": ["f64", "f64 (f32 coupling)", "f64 (bf16 matrix-core coupling)",
                   "f64 (split-bf16 matrix-core coupling)",
-                  "f64 moments/transfers (split-bf16 coupling and near field)",
-                  "f64 moments/transfers (f32 coupling and near field)"][args.prec],
+                  "f64 moments/transfers (split-bf16 coupling and near field)"][args.prec],
         "data": "synthetic",
         "config": {"workload": f"FMM matvec: 6-patch NURBS sphere, level {m}, p={p}, kappa={kappa}, q={q}, "
                                f"5x5 Gauss near field, x ~ N(0,1)+iN(0,1) seed 0",

@@ -146,7 +146,7 @@ int ige_op_dofmap(ige_op op, int32_t *dof, int8_t *sgn);
  * cluster id on level l: patch*4^l + k2*2^l + k1.  Either pointer may be NULL. */
 int ige_op_partition(ige_op op, int32_t *far, int32_t *near);
 
-enum { IGE_F64 = 0, IGE_F32 = 1, IGE_BF16 = 2, IGE_BF16X3 = 3, IGE_BF16X3_ALL = 4, IGE_F32_ALL = 5 };
+enum { IGE_F64 = 0, IGE_F32 = 1, IGE_BF16 = 2, IGE_BF16X3 = 3, IGE_BF16X3_ALL = 4 };
 
 /* y = A x for r right-hand sides (A the compressed operator).  x, y: N*r complex.
  * r > 1 runs the batched kernels (columns in chunks, every kernel value and matrix
@@ -172,13 +172,8 @@ int ige_apply(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind);
  *             from a split-BF16 copy of the FP64-assembled near-field blocks (one block
  *             per ordered leaf pair) with FP32 accumulation; about 2^-16 on the whole
  *             product.  Meant as the inner operator of refined solves.
- *   IGE_F32_ALL  coupling as IGE_F32 and, for a single column, the near-field product
- *             from an FP32 copy of the FP64-assembled blocks (FP64 sums; half the
- *             bytes of the HBM-bound block pass); more columns keep the FP64 near
- *             field.  Meant as the inner operator of refined single-column solves.
- * Unless stated, near field, moments and transfers stay FP64.  The FP32 copies and the
- * BF16 blocks are made on first use (FP32 near field: 8 bytes per stored block entry;
- * BF16 coupling: 2 * pairs * Qp * 2Qp * 2 bytes per
+ * Unless stated, near field, moments and transfers stay FP64.  The FP32 copy and the
+ * BF16 blocks are made on first use (BF16 coupling: 2 * pairs * Qp * 2Qp * 2 bytes per
  * plane, Qp = Q rounded up to 32; split-BF16 near field: 2 * blocks * 2 * Qn * 2Qn * 2
  * bytes, Qn = slots per leaf rounded up to 32). */
 int ige_apply_prec(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind, int coupling_prec);

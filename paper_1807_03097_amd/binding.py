@@ -41,7 +41,7 @@ class ige_op_info_t(C.Structure):
                 ("assemble_ms", C.c_double)]
 
 
-IGE_F64, IGE_F32, IGE_BF16, IGE_BF16X3, IGE_BF16X3_ALL, IGE_F32_ALL = 0, 1, 2, 3, 4, 5
+IGE_F64, IGE_F32, IGE_BF16, IGE_BF16X3, IGE_BF16X3_ALL = 0, 1, 2, 3, 4
 
 
 class ige_solve_opts(C.Structure):

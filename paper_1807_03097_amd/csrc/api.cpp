@@ -63,10 +63,8 @@ const std::vector<double2> &sincos_table()
     return tab;
 }
 
-// near32: the near-field block pass reads the FP32 copy of the blocks
-void apply_one(ige_op op, const double2 *x, double2 *y, int prec = IGE_F64, bool near32 = false)
+void apply_one(ige_op op, const double2 *x, double2 *y, int prec = IGE_F64)
 {
-    if (near32) ige::ensure_near32(op);   // on the launch stream, before the fork
     hipStream_t s = ige::lstream(op), s2 = op->aux;
     const bool prof = op->profiling;
     hipEvent_t *ev = prof ? op->prof_ev.data() + (size_t)(op->prof_count % ige_op_s::kProfSlots) * ige_op_s::kProfEv
@@ -93,7 +91,7 @@ void apply_one(ige_op op, const double2 *x, double2 *y, int prec = IGE_F64, bool
             mark(6, s);
         }
         mark(7, s);
-        ige::launch_spmv(op, x, y, s, prof ? ev[11] : nullptr, near32);
+        ige::launch_spmv(op, x, y, s, prof ? ev[11] : nullptr);
         mark(8, s);
         if (far) {
             mark(9, s);
@@ -117,7 +115,7 @@ void apply_one(ige_op op, const double2 *x, double2 *y, int prec = IGE_F64, bool
     IGE_HIP(hipEventRecord(op->ev_fork, s));
     IGE_HIP(hipStreamWaitEvent(s2, op->ev_fork, 0));
     mark(7, s2);
-    ige::launch_spmv(op, x, y, s2, prof ? ev[11] : nullptr, near32);
+    ige::launch_spmv(op, x, y, s2, prof ? ev[11] : nullptr);
     mark(8, s2);
     IGE_HIP(hipEventRecord(op->ev_join, s2));
     mark(12, s);
@@ -635,7 +633,7 @@ int ige_op_info(ige_op op, ige_op_info_t *out)
         b += op->d_nodeX.bytes() + op->d_nodeT.bytes() + op->d_G.bytes() + op->d_G32.bytes() + op->d_gpart.bytes() + op->d_gtmp.bytes();
         b += op->d_fpair.bytes() + op->d_fred_ptr.bytes() + op->d_fred_idx.bytes();
         b += op->d_Gb1.bytes() + op->d_Gb3.bytes() + op->d_vb.bytes() + op->d_bmpart.bytes();
-        b += op->d_Gd.bytes() + op->d_vd.bytes() + op->d_bmpart64.bytes() + op->d_bval32.bytes();
+        b += op->d_Gd.bytes() + op->d_vd.bytes() + op->d_bmpart64.bytes();
         b += op->d_nb3.bytes() + op->d_xnb.bytes() + op->d_nbpart.bytes() + op->d_nbwork.bytes();
         b += op->d_nbpartner.bytes() + op->d_nbslot.bytes() + op->d_nborder.bytes() + op->d_nbred_ptr.bytes();
         b += op->d_nbred_idx.bytes() + op->d_morder.bytes();
@@ -820,18 +818,14 @@ void apply_dev(ige_op op, int r, const double2 *x, double2 *y, int prec, ApplyGr
     const bool graph = g && !op->profiling && graphs_enabled();
     hipStream_t s = op->ctx->stream;
     const int64_t N = op->D.N;
-    // IGE_F32_ALL: FP32 coupling, and FP32 near-field blocks for a single column
-    const int gkey = prec;   // graph key: the requested precision
-    const bool near32 = prec == IGE_F32_ALL && r == 1;
-    if (prec == IGE_F32_ALL) prec = IGE_F32;
     if (r == 1 && prec <= IGE_F32) {
         if (!graph) {
-            apply_one(op, x, y, prec, near32);
+            apply_one(op, x, y, prec);
             return;
         }
         ensure_staging(op);
         IGE_HIP(hipMemcpyAsync(op->d_x.p, x, sizeof(double2) * N, hipMemcpyDeviceToDevice, s));
-        run_graph(op, g, r, gkey, [&] { apply_one(op, op->d_x.p, op->d_y.p, prec, near32); });
+        run_graph(op, g, r, prec, [&] { apply_one(op, op->d_x.p, op->d_y.p, prec); });
         IGE_HIP(hipMemcpyAsync(y, op->d_y.p, sizeof(double2) * N, hipMemcpyDeviceToDevice, s));
         return;
     }
@@ -845,7 +839,7 @@ void apply_dev(ige_op op, int r, const double2 *x, double2 *y, int prec, ApplyGr
         return;
     }
     ige::batched_to_rows(op, r, x, op->d_bxt.p, s);
-    run_graph(op, g, r, gkey,
+    run_graph(op, g, r, prec,
               [&] { ige::apply_batched(op, r, nullptr, nullptr, op->d_bxt.p, op->d_byt.p, nullptr, prec); });
     ige::batched_to_cols(op, r, op->d_byt.p, y, s);
 }
@@ -856,7 +850,7 @@ int apply_impl(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind, int
         IGE_REQUIRE(op && x && y && r >= 1, "bad apply arguments");
         IGE_REQUIRE(op->assembled, "operator was planned, not assembled");
         IGE_REQUIRE(ptr_kind == IGE_HOST || ptr_kind == IGE_DEVICE, "bad ptr_kind");
-        IGE_REQUIRE(prec >= IGE_F64 && prec <= IGE_F32_ALL, "bad coupling precision");
+        IGE_REQUIRE(prec >= IGE_F64 && prec <= IGE_BF16X3_ALL, "bad coupling precision");
         set_device(op->ctx);
         const int64_t N = op->D.N;
         hipStream_t s = op->ctx->stream;
@@ -892,7 +886,7 @@ int ige_op_autotune(ige_op op, int r, int prec, int *choice, int nchoice)
     int rc = guard([&] {
         IGE_REQUIRE(op && r >= 1 && (choice || nchoice == 0), "bad autotune arguments");
         IGE_REQUIRE(op->assembled, "operator was planned, not assembled");
-        IGE_REQUIRE(prec >= IGE_F64 && prec <= IGE_F32_ALL, "bad precision");
+        IGE_REQUIRE(prec >= IGE_F64 && prec <= IGE_BF16X3_ALL, "bad precision");
         set_device(op->ctx);
         const int64_t N = op->D.N;
         hipStream_t s = op->ctx->stream;
@@ -939,12 +933,12 @@ int ige_op_autotune(ige_op op, int r, int prec, int *choice, int nchoice)
             }
         };
         // coordinate descent over the knobs that the (r, prec) apply uses
-        const bool mx = r > 1 && prec >= IGE_BF16 && prec <= IGE_BF16X3_ALL, near_bx = r > 1 && prec == IGE_BF16X3_ALL;
+        const bool mx = r > 1 && prec >= IGE_BF16, near_bx = r > 1 && prec == IGE_BF16X3_ALL;
         const bool near_mfma = r >= 8 && prec != IGE_BF16X3_ALL && ige::near_mfma_mtw_ok(op->view.nF, op->view.rc);
         // FP64 coupling on the matrix cores (default) against the generated kernel, whose
         // columns per workgroup are tuned only where it is the default
         const bool f64mx = prec == IGE_F64 && ige::m2l_f64mx_ok(op, r);
-        const bool gen = r > 1 && (prec <= IGE_F32 || prec == IGE_F32_ALL) && !op->stored && !op->work.empty() && !f64mx;
+        const bool gen = r > 1 && prec <= IGE_F32 && !op->stored && !op->work.empty() && !f64mx;
         const int split = prec == IGE_BF16 ? 1 : 3;
         struct Knob {
             bool on;
@@ -957,7 +951,7 @@ int ige_op_autotune(ige_op op, int r, int prec, int *choice, int nchoice)
                                             {mxon, ige::kTuneM2lNcol, split, {64, 128, 256}},
                                             {near_bx, ige::kTuneNearBxNt, 0, {1, 2, 4}},
                                             {near_mfma, ige::kTuneNearMfmaNt, 0, {1, 2, 4}},
-                                            {gen, ige::kTuneM2lRb, prec == IGE_F32_ALL ? IGE_F32 : prec, {1, 2, 4}},
+                                            {gen, ige::kTuneM2lRb, prec, {1, 2, 4}},
                                             {f64mx, ige::kTuneM2lF64, IGE_F64, {0}}};
         // each candidate timed in two rounds (minimum kept); a candidate replaces the
         // default only when it is more than 2 % faster (the timings vary by about that)
@@ -1238,7 +1232,7 @@ int ige_solve(ige_op op, int r, const ige_c64 *f, ige_c64 *x, int ptr_kind, cons
         IGE_REQUIRE(ptr_kind == IGE_HOST || ptr_kind == IGE_DEVICE, "bad ptr_kind");
         IGE_REQUIRE(opts->restart >= 1 && opts->maxit >= 0 && std::isfinite(opts->tol) && opts->tol >= 0.0,
                     "bad solve options");
-        IGE_REQUIRE(!opts->refine || (opts->inner_prec >= IGE_F64 && opts->inner_prec <= IGE_F32_ALL),
+        IGE_REQUIRE(!opts->refine || (opts->inner_prec >= IGE_F64 && opts->inner_prec <= IGE_BF16X3_ALL),
                     "bad inner precision");
         IGE_REQUIRE(!opts->refine || (std::isfinite(opts->inner_tol) && opts->inner_tol > 0.0 && opts->inner_tol < 1.0),
                     "inner_tol must be in (0, 1)");

@@ -1047,24 +1047,13 @@ __device__ inline double wave_sum(double v)
     return v;
 }
 
-typedef float f2v __attribute__((ext_vector_type(2)));
-template <typename BT> struct BlkReg;   // register type of a loaded block entry
-template <> struct BlkReg<double2> { using type = d2v; };
-template <> struct BlkReg<float2> { using type = f2v; };
 __device__ inline d2v ld_blk(const double2 *B, size_t i)
 {
     return __builtin_nontemporal_load(reinterpret_cast<const d2v *>(B) + i);
 }
-__device__ inline f2v ld_blk(const float2 *B, size_t i)
-{
-    return __builtin_nontemporal_load(reinterpret_cast<const f2v *>(B) + i);
-}
-__device__ inline d2v to_d2v(d2v v) { return v; }
-__device__ inline d2v to_d2v(f2v v) { return d2v{(double)v.x, (double)v.y}; }
 
-// BT: block entries in FP64 (double2) or as an FP32 copy (float2), FP64 sums either way
-template <int U, typename BT>
-__global__ __launch_bounds__(256) void k_near_blk(DevOp o, const BT *bv, const double2 *x, double2 *part)
+template <int U>
+__global__ __launch_bounds__(256) void k_near_blk(DevOp o, const double2 *x, double2 *part)
 {
     __shared__ double2 sxr[64 * U];
     __shared__ double2 syc[3][64 * U];
@@ -1087,21 +1076,19 @@ __global__ __launch_bounds__(256) void k_near_blk(DevOp o, const BT *bv, const d
         sxr[k] = d >= 0 ? x[d] : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    const BT *B = bv + (size_t)b * nF * nF;
+    const double2 *B = o.bval + (size_t)b * nF * nF;
     int r = r0 + wv;
-    // RS rows per step (r, r + 4, ...): RS U independent streaming loads in flight per lane
-    // (eight rows for the 8-byte FP32 entries, two for FP64)
-    constexpr int RS = sizeof(BT) == sizeof(double2) ? 2 : 8;
-    using LT = typename BlkReg<BT>::type;
-    // (the last step of a wave may hold fewer rows: the others load and add zeros)
+    // RS rows per step (r, r + 4, ...): RS U independent streaming loads in flight per
+    // lane; the last step of a wave may hold fewer rows (the others load and add zeros)
+    constexpr int RS = 2;
     for (; r < r1; r += 4 * RS) {
-        LT al[RS][U];   // entries as loaded, widened to FP64 at use
+        d2v al[RS][U];
 #pragma unroll
         for (int q = 0; q < RS; ++q)
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int c = lane + 64 * u;
-                al[q][u] = (c < nF && r + 4 * q < r1) ? ld_blk(B, (size_t)(r + 4 * q) * nF + c) : LT{0, 0};
+                al[q][u] = (c < nF && r + 4 * q < r1) ? ld_blk(B, (size_t)(r + 4 * q) * nF + c) : d2v{0.0, 0.0};
             }
         double2 xq[RS];
         double re[RS], im[RS];
@@ -1115,7 +1102,7 @@ __global__ __launch_bounds__(256) void k_near_blk(DevOp o, const BT *bv, const d
         for (int u = 0; u < U; ++u) {
             d2v a[RS];
 #pragma unroll
-            for (int q = 0; q < RS; ++q) a[q] = to_d2v(al[q][u]);
+            for (int q = 0; q < RS; ++q) a[q] = al[q][u];
 #pragma unroll
             for (int q = 0; q < RS; ++q) {
                 re[q] = fma(a[q].x, xc[u].x, fma(-a[q].y, xc[u].y, re[q]));
@@ -1476,44 +1463,7 @@ int near_blk_u(int nF)
     return 16;
 }
 
-namespace {
-__global__ void k_to_f32(int64_t n, const double2 *a, float2 *b)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) b[i] = make_float2((float)a[i].x, (float)a[i].y);
-}
-
-template <typename BT>
-void launch_near_blk(ige_op op, const BT *bv, const double2 *x, double2 *part, hipStream_t st)
-{
-    const DevOp &o = op->view;
-    const dim3 grid((unsigned)(o.nblk * o.nch)), blk(256);
-    switch (near_blk_u(o.nF)) {
-        case 1: hipLaunchKernelGGL((k_near_blk<1, BT>), grid, blk, 0, st, o, bv, x, part); break;
-        case 2: hipLaunchKernelGGL((k_near_blk<2, BT>), grid, blk, 0, st, o, bv, x, part); break;
-        case 3: hipLaunchKernelGGL((k_near_blk<3, BT>), grid, blk, 0, st, o, bv, x, part); break;
-        case 4: hipLaunchKernelGGL((k_near_blk<4, BT>), grid, blk, 0, st, o, bv, x, part); break;
-        case 6: hipLaunchKernelGGL((k_near_blk<6, BT>), grid, blk, 0, st, o, bv, x, part); break;
-        case 8: hipLaunchKernelGGL((k_near_blk<8, BT>), grid, blk, 0, st, o, bv, x, part); break;
-        case 12: hipLaunchKernelGGL((k_near_blk<12, BT>), grid, blk, 0, st, o, bv, x, part); break;
-        default: hipLaunchKernelGGL((k_near_blk<16, BT>), grid, blk, 0, st, o, bv, x, part); break;
-    }
-    IGE_LAUNCH_CHECK();
-}
-}  // namespace
-
-void ensure_near32(ige_op op)
-{
-    const DevOp &o = op->view;
-    if (op->d_bval32.p || o.nblk == 0) return;
-    const int64_t n = o.nblk * (int64_t)o.nF * o.nF;
-    op->d_bval32.alloc((size_t)n);
-    hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, lstream(op), n, o.bval,
-                       op->d_bval32.p);
-    IGE_LAUNCH_CHECK();
-}
-
-void launch_spmv(ige_op op, const double2 *x, double2 *y, hipStream_t st, hipEvent_t mid, bool near32)
+void launch_spmv(ige_op op, const double2 *x, double2 *y, hipStream_t st, hipEvent_t mid)
 {
     const DevOp &o = op->view;
     if (o.nblk == 0) {
@@ -1521,13 +1471,19 @@ void launch_spmv(ige_op op, const double2 *x, double2 *y, hipStream_t st, hipEve
         if (mid) IGE_HIP(hipEventRecord(mid, st));
         return;
     }
+    const dim3 grid((unsigned)(o.nblk * o.nch)), blk(256);
     double2 *part = op->d_npart.p;
-    if (near32) {
-        IGE_REQUIRE(op->d_bval32.p, "FP32 near-field blocks not made");
-        launch_near_blk(op, (const float2 *)op->d_bval32.p, x, part, st);
-    } else {
-        launch_near_blk(op, (const double2 *)o.bval, x, part, st);
+    switch (near_blk_u(o.nF)) {
+        case 1: hipLaunchKernelGGL(k_near_blk<1>, grid, blk, 0, st, o, x, part); break;
+        case 2: hipLaunchKernelGGL(k_near_blk<2>, grid, blk, 0, st, o, x, part); break;
+        case 3: hipLaunchKernelGGL(k_near_blk<3>, grid, blk, 0, st, o, x, part); break;
+        case 4: hipLaunchKernelGGL(k_near_blk<4>, grid, blk, 0, st, o, x, part); break;
+        case 6: hipLaunchKernelGGL(k_near_blk<6>, grid, blk, 0, st, o, x, part); break;
+        case 8: hipLaunchKernelGGL(k_near_blk<8>, grid, blk, 0, st, o, x, part); break;
+        case 12: hipLaunchKernelGGL(k_near_blk<12>, grid, blk, 0, st, o, x, part); break;
+        default: hipLaunchKernelGGL(k_near_blk<16>, grid, blk, 0, st, o, x, part); break;
     }
+    IGE_LAUNCH_CHECK();
     if (mid) IGE_HIP(hipEventRecord(mid, st));
     hipLaunchKernelGGL(k_near_gather, dim3((unsigned)(((int64_t)o.N * 16 + 255) / 256)), dim3(256), 0, st, o.N, o.red_ptr, o.red_idx, part, y);
     IGE_LAUNCH_CHECK();

@@ -139,7 +139,6 @@ struct ige_op_s {
     ige::DBuf<float2> d_bmpart;          // matrix-core coupling partials [mwork][4][Q][r]
     ige::DBuf<double> d_Gd, d_vd;       // FP64 matrix-core coupling: blocks, right factors
     ige::DBuf<double2> d_bmpart64;      // FP64 matrix-core coupling partials [mwork][4][Q][r]
-    ige::DBuf<float2> d_bval32;         // FP32 copy of the near-field blocks (IGE_F32_ALL)
     int gd_fit = -1;                    // FP64 blocks fit in device memory (-1: not yet decided)
     bool f64mx_off = false;             // FP64 coupling of many columns generated per apply (IGE_M2L_F64=generate)
     ige::DBuf<int32_t> d_morder;         // work items by decreasing partner count
@@ -246,10 +245,7 @@ void near_bf16(ige_op op, int r, const double2 *xt, double2 *yt, hipStream_t s);
 void launch_m2l_reduce(ige_op op);
 void launch_l2l(ige_op op);
 // near-field product; records mid (if given) between the block pass and the reduction
-void launch_spmv(ige_op op, const double2 *x, double2 *y, hipStream_t st, hipEvent_t mid = nullptr,
-                 bool near32 = false);
-// FP32 copy of the near-field blocks (made once, on the launch stream)
-void ensure_near32(ige_op op);
+void launch_spmv(ige_op op, const double2 *x, double2 *y, hipStream_t st, hipEvent_t mid = nullptr);
 int near_blk_u(int nF);
 int near_mfma_mtw_ok(int nF, int rc);   // the FP64 matrix-core near product supports these blocks   // 64-column groups per block row (template choice)
 void launch_l2p_leaf(ige_op op);

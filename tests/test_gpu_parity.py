@@ -417,38 +417,6 @@ def test_refinement_escalates_inner_precision(ctx):
     op.close()
 
 
-def test_fp32_near_field_single_column(oracle_mod, ctx):
-    """IGE_F32_ALL: FP32 coupling and, for one column, the near-field product from an
-    FP32 copy of the blocks: within FP32-level error of the oracle (and not FP64-exact);
-    several columns keep the FP64 near field (same result as IGE_F32); refined
-    single-column solves around it meet the FP64 tolerance and the FP64 solution."""
-    from paper_1807_03097_amd import binding as B
-    name, p, m, kappa, q, eta, d, g, gs = CASES[2]
-    pats = _geom(name)
-    geom = B.Geometry(ctx, pats)
-    op = B.Operator(geom, p, m, kappa, q, eta, g, gs, d)
-    x = W.random_coeffs(op.N, 0)
-    yo = oracle_mod.Oracle(pats, p, m, kappa, g=g, gs=gs).fmm_apply(x, q, eta, d)
-    y32 = op.apply(x, prec=B.IGE_F32)
-    yall = op.apply(x, prec=B.IGE_F32_ALL)
-    e32, eall = _rel(y32, yo), _rel(yall, yo)
-    X = np.stack([W.random_coeffs(op.N, 40 + s) for s in range(3)])
-    Y32 = op.apply(X, prec=B.IGE_F32)
-    Yall = op.apply(X, prec=B.IGE_F32_ALL)
-    _say(f"  FP32 coupling {e32:.2e}, FP32 coupling and near field {eall:.2e}")
-    assert 1e-12 < eall <= 1e-5 and eall != e32
-    assert max(_rel(Yall[c], Y32[c]) for c in range(3)) == 0.0
-    dirs, pols = W.fibonacci_plane_waves(1)
-    F = op.rhs_plane_wave(dirs, pols)
-    X64, st64, rc = op.solve(F, tol=1e-10, restart=100, maxit=4000)
-    Xr, st, rc2 = op.solve(F, tol=1e-10, restart=100, maxit=6000, refine=True, inner_tol=1e-4,
-                           inner_prec=B.IGE_F32_ALL)
-    _say(f"  FP64 iters {st64[0][0]}, refined iters {st[0][0]} outer {st[0][1]} relres {st[0][2]:.2e}")
-    assert rc == 0 and rc2 == 0 and st[0][2] <= 1.05e-10
-    assert _rel(Xr[0], X64[0]) <= 1e-6
-    op.close()
-
-
 @pytest.mark.parametrize("inner_tol", [1e-4, 1e-6], ids=["fp32-basis", "fp64-basis"])
 def test_inner_krylov_basis_precision(ctx, monkeypatch, inner_tol):
     """Refined solves of 3 waves with the inner Krylov basis in FP32 (default for
