@@ -286,35 +286,36 @@ __global__ __launch_bounds__(256) void k_m2m_b(DevOp o, int lvl, int r, double2 
     const int S = 1 << lvl, Q1 = o.Q1, Q = o.Q;
     const int j = id / (S * S), rr = id % (S * S), k2 = rr / S, k1 = rr % S;
     const int gc = (int)o.lvl_off[lvl] + id;
+    const int QR = Q * kRB;
     double2 *acc = sm2;               // [3 fields][Q][kRB]
-    double2 *W = acc + 3 * Q * kRB;   // [Q1 (n2)][Q1 (m1)][kRB], one field of one child at a time
-    double2 *X = W + Q * kRB;         // the child's field, staged once (coalesced along columns)
-    for (int i = threadIdx.x; i < 3 * Q * kRB; i += blockDim.x) acc[i] = make_double2(0, 0);
+    double2 *W = acc + 3 * QR;        // [3 fields][Q1 (n2)][Q1 (m1)][kRB] of one child
+    double2 *X = W + 3 * QR;          // the child's three fields, staged at once (coalesced along columns)
+    for (int i = threadIdx.x; i < 3 * QR; i += blockDim.x) acc[i] = make_double2(0, 0);
     for (int ch = 0; ch < 4; ++ch) {
         const int c1 = ch & 1, c2 = ch >> 1;
         const int cgc = (int)o.lvl_off[lvl + 1] + (j * 2 * S + 2 * k2 + c2) * 2 * S + 2 * k1 + c1;
         const double2 *cm = mom + (size_t)cgc * 3 * Q * r;
         const double *Tu = c1 ? o.T1 : o.T0, *Tv = c2 ? o.T1 : o.T0;
-        for (int f = 0; f < 3; ++f) {
-            __syncthreads();
-            for (int i = threadIdx.x; i < Q * kRB; i += blockDim.x) {
-                const int c = i % kRB, q = i / kRB;
-                X[i] = c < nc ? cm[((size_t)f * Q + q) * r + c0 + c] : make_double2(0, 0);
-            }
-            __syncthreads();
-            for (int i = threadIdx.x; i < Q * kRB; i += blockDim.x) {
-                const int c = i % kRB, nm = i / kRB, n2 = nm / Q1, m1 = nm % Q1;
-                double2 z = make_double2(0, 0);
-                for (int n1 = 0; n1 < Q1; ++n1) z = caddb(z, cscaleb(Tu[n1 * Q1 + m1], X[(n2 * Q1 + n1) * kRB + c]));
-                W[i] = z;
-            }
-            __syncthreads();
-            for (int i = threadIdx.x; i < Q * kRB; i += blockDim.x) {
-                const int c = i % kRB, mm = i / kRB, m2 = mm / Q1, m1 = mm % Q1;
-                double2 z = acc[(f * Q + mm) * kRB + c];
-                for (int n2 = 0; n2 < Q1; ++n2) z = caddb(z, cscaleb(Tv[n2 * Q1 + m2], W[(n2 * Q1 + m1) * kRB + c]));
-                acc[(f * Q + mm) * kRB + c] = z;
-            }
+        __syncthreads();
+        for (int i = threadIdx.x; i < 3 * QR; i += blockDim.x) {
+            const int c = i % kRB, t = i / kRB;   // t = f Q + q
+            X[i] = c < nc ? cm[(size_t)t * r + c0 + c] : make_double2(0, 0);
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < 3 * QR; i += blockDim.x) {
+            const int c = i % kRB, t = i / kRB, f = t / Q, nm = t % Q, n2 = nm / Q1, m1 = nm % Q1;
+            double2 z = make_double2(0, 0);
+            for (int n1 = 0; n1 < Q1; ++n1)
+                z = caddb(z, cscaleb(Tu[n1 * Q1 + m1], X[(f * Q + n2 * Q1 + n1) * kRB + c]));
+            W[i] = z;
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < 3 * QR; i += blockDim.x) {
+            const int c = i % kRB, t = i / kRB, f = t / Q, mm = t % Q, m2 = mm / Q1, m1 = mm % Q1;
+            double2 z = acc[i];
+            for (int n2 = 0; n2 < Q1; ++n2)
+                z = caddb(z, cscaleb(Tv[n2 * Q1 + m2], W[(f * Q + n2 * Q1 + m1) * kRB + c]));
+            acc[i] = z;
         }
     }
     __syncthreads();
@@ -638,7 +639,7 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
         }
         mark(1);
         {
-            const size_t per = sizeof(double2) * 5 * o.Q;   // accumulators, intermediate, staged child
+            const size_t per = sizeof(double2) * 9 * o.Q;   // accumulators, intermediate, staged child (3 fields each)
             const int rb = pick_rb(per);
             for (int lvl = o.L - 1; lvl >= 0; --lvl) {
                 IGE_RB_SWITCH(rb, k_m2m_b, dim3(o.P << (2 * lvl), chunks(rb)), dim3(256), per * rb, s, o, lvl, r,
