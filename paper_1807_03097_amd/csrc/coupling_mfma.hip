@@ -653,15 +653,17 @@ void launch_mx(ige_op op, int r, int rc, int nchunk, const __bf16 *G, const __bf
     constexpr int PL = SPLIT == 3 ? 2 : 1, QP = 16 * MT;
     constexpr size_t shm = sizeof(__bf16) * (DB ? 2 : 1) * PL * QP * (2 * QP + IGE_GPAD);
     auto kern = DB ? &k_m2l_mxd<SPLIT, MT, WN, NT> : &k_m2l_mx<SPLIT, MT, WN, NT>;
-    static bool attr = false;   // the attribute is set once per kernel, before any graph capture
-    if (!attr) {
+    // the attribute is set once per kernel (thread-safe static initialisation; a throw
+    // leaves it unset for the next call), before any graph capture
+    static const bool attr = [&] {
         int lds_max = 0;
         IGE_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, op->ctx->device));
         IGE_REQUIRE(shm <= (size_t)lds_max, "coupling block does not fit in shared memory");
         IGE_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)shm));
-        attr = true;
-    }
+        return true;
+    }();
+    (void)attr;
     hipLaunchKernelGGL(kern, grid, blk, shm, s, o, r, rc, nchunk, nw, order, op->d_mwork.p, op->d_mpartner.p,
                        op->d_gslot.p, G, Vb, op->d_bmpart.p);
     IGE_HIP(hipGetLastError());
