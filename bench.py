@@ -282,7 +282,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU (one operator per device); "
-                                   "multi-GPU sharding is described in DESIGN.md but not built"}))
+                                   "sharding over several GPUs is not built"}))
         sys.exit(2)
     if args.mode == "serve":
         run_serving(args)
