@@ -52,6 +52,7 @@ CASES = [
     ("multispan", 2, 3, 5.0, 6, 1.0, 1, 5, 5),    # NURBS input with interior knots
     ("sphere", 1, 3, 2.0, 3, 1.0, 0, 3, 6),       # leaf = element, low q
     ("sphere", 2, 3, 8.0, 8, 1.6, 3, 5, 5),       # leaf = patch: far field only between patches
+    ("sphere", 3, 3, 6.0, 6, 1.0, 1, 5, 5),       # cubic splines (24 local functions per element)
 ]
 
 
@@ -247,7 +248,8 @@ def test_fp32_coupling_apply_and_refined_solve(oracle_mod, ctx):
         assert _rel(Xir[c], X64[c]) <= 1e-6
 
 
-@pytest.mark.parametrize("case", [CASES[2], CASES[3], CASES[4]], ids=["sphere-m3-d1", "sphere-m4-d2", "torus-m3"])
+@pytest.mark.parametrize("case", [CASES[2], CASES[3], CASES[4], CASES[10]],
+                         ids=["sphere-m3-d1", "sphere-m4-d2", "torus-m3", "sphere-p3"])
 def test_bf16_matrix_core_coupling(oracle_mod, ctx, case):
     """Coupling on the BF16 matrix cores: plain BF16 within 2^-9-level error of the
     oracle, split BF16 (three products) within 2^-16-level error, one and several
