@@ -410,9 +410,14 @@ def main():
                         "issued_flop": issued, "avg_ms": t_ms}
             flops = info.near_leaf_pairs * nF * nF * 8.0 * r
             ach = flops / (t_ms * 1e-3) / 1e12
-            return {"kernel": "k_near_mfma", "bound": "mfma", "achieved": ach, "peak": FP64_MFMA_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": ach / FP64_MFMA_PEAK_TFLOPS, "traffic": None,
-                    "flop": flops, "avg_ms": t_ms}
+            out = {"kernel": "k_near_md" if r >= 56 else "k_near_mfma", "bound": "mfma", "achieved": ach,
+                   "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP64_MFMA_PEAK_TFLOPS,
+                   "traffic": None, "flop": flops, "avg_ms": t_ms}
+            if r >= 56:
+                # real products over the padded blocks: (2 Qn) x (2 Qn) by 64 columns per chunk
+                Qn = 32 * ((nF + 31) // 32)
+                out["issued_flop"] = info.near_leaf_pairs * (-(-r // 64)) * 2.0 * (2 * Qn) ** 2 * 64
+            return out
         if dom == "near_spmv":
             # the block pass: stored block entries (16 B each) streamed once per pass
             # of up to 4 columns, x read once per column

@@ -172,7 +172,11 @@ int ige_apply(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind);
  *             from a split-BF16 copy of the FP64-assembled near-field blocks (one block
  *             per ordered leaf pair) with FP32 accumulation; about 2^-16 on the whole
  *             product.  Meant as the inner operator of refined solves.
- * Unless stated, near field, moments and transfers stay FP64.  The FP32 copy and the
+ * Unless stated, near field, moments and transfers stay FP64.  The FP64 near field of
+ * 56 or more columns runs on the FP64 matrix cores from an FP64 copy of the blocks per
+ * ordered leaf pair (2 * blocks * Qn * 2Qn * 8 bytes, made on first use when 8 GiB of
+ * device memory stay free; IGE_NEAR_F64=blocks keeps the stored blocks and their
+ * transposes, as below 56 columns).  The FP32 copy and the
  * BF16 blocks are made on first use (BF16 coupling: 2 * pairs * Qp * 2Qp * 2 bytes per
  * plane, Qp = Q rounded up to 32; split-BF16 near field: 2 * blocks * 2 * Qn * 2Qn * 2
  * bytes, Qn = slots per leaf rounded up to 32). */
@@ -188,7 +192,8 @@ int ige_apply_prec(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind,
  *   0 coupling column chunk of the BF16 matrix-core coupling (64, 128, 256 complex
  *     columns, capped where registers would spill),
  *   1 column tiles per wave of the split-BF16 near-field product (1, 2, 4),
- *   2 column tiles per wave of the FP64 matrix-core near-field product (1, 2, 4),
+ *   2 column tiles per wave of the FP64 matrix-core near-field product of 8 to 55
+ *     columns (1, 2, 4),
  *   3 columns per workgroup of the generated FP64/FP32 coupling (1, 2, 4; capped by
  *     shared memory),
  *   4 staging of the BF16 coupling blocks: 1 double-buffered (the next block loaded

@@ -475,6 +475,9 @@ ige_op ige::assemble_on(ige_ctx ctx, const ige_geom_s *geom, const ige_params &p
                 // many FP64 columns: stored blocks on the FP64 matrix cores (default) or
                 // evaluated per apply (IGE_M2L_F64=generate)
                 if (const char *e = std::getenv("IGE_M2L_F64")) op->f64mx_off = std::string(e) == "generate";
+                // many FP64 columns: near field on ordered-pair FP64 blocks (default) or on
+                // the stored unordered blocks and their transposes (IGE_NEAR_F64=blocks)
+                if (const char *e = std::getenv("IGE_NEAR_F64")) op->near_md_off = std::string(e) == "blocks";
                 if (op->nfp > 0) {
                     op->d_fpair.upload(fpair, s);
                     // matrix-core coupling: per target, work items of up to 32 partners
@@ -634,6 +637,7 @@ int ige_op_info(ige_op op, ige_op_info_t *out)
         b += op->d_fpair.bytes() + op->d_fred_ptr.bytes() + op->d_fred_idx.bytes();
         b += op->d_Gb1.bytes() + op->d_Gb3.bytes() + op->d_vb.bytes() + op->d_bmpart.bytes();
         b += op->d_Gd.bytes() + op->d_vd.bytes() + op->d_bmpart64.bytes();
+        b += op->d_nd.bytes() + op->d_xnd.bytes() + op->d_ndpart.bytes();
         b += op->d_nb3.bytes() + op->d_xnb.bytes() + op->d_nbpart.bytes() + op->d_nbwork.bytes();
         b += op->d_nbpartner.bytes() + op->d_nbslot.bytes() + op->d_nborder.bytes() + op->d_nbred_ptr.bytes();
         b += op->d_nbred_idx.bytes() + op->d_morder.bytes();
@@ -934,7 +938,8 @@ int ige_op_autotune(ige_op op, int r, int prec, int *choice, int nchoice)
         };
         // coordinate descent over the knobs that the (r, prec) apply uses
         const bool mx = r > 1 && prec >= IGE_BF16, near_bx = r > 1 && prec == IGE_BF16X3_ALL;
-        const bool near_mfma = r >= 8 && prec != IGE_BF16X3_ALL && ige::near_mfma_mtw_ok(op->view.nF, op->view.rc);
+        const bool near_mfma = r >= 8 && prec != IGE_BF16X3_ALL && ige::near_mfma_mtw_ok(op->view.nF, op->view.rc) &&
+                               !ige::near_f64mx_ok(op, r);
         // FP64 coupling on the matrix cores (default) against the generated kernel, whose
         // columns per workgroup are tuned only where it is the default
         const bool f64mx = prec == IGE_F64 && ige::m2l_f64mx_ok(op, r);

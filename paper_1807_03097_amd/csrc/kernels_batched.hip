@@ -732,6 +732,7 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
     }
     mark(7);
     if (prec == IGE_BF16X3_ALL) near_bf16(op, r, xt, yt, s);
+    else if (near_f64mx_ok(op, r)) near_f64mx(op, r, xt, yt, s);
     else if (r >= 8 && near_mfma_mtw_ok(o.nF, o.rc)) near_batched_mfma(op, r, xt, yt, s);
     else near_batched(op, r, xt, yt, s);
     mark(11);

@@ -14,6 +14,10 @@
 // are folded into the blocks).  Work: one workgroup per (target leaf, up to 8
 // partners, chunk of 16 NT columns), wave w owning row tiles w MTW .. w MTW + MTW - 1;
 // partial results per work item (FP32) are summed per unknown in a fixed order.
+//
+// The FP64 operator of many columns uses the same ordered-pair blocks in FP64 on the
+// FP64 matrix cores (last part of this file): rows [Br, -Bi] and [Bi, Br] read from the
+// stored [Br | Bi] as one real product with [Re X; Im X], as in the FP64 coupling.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -252,6 +256,144 @@ __global__ void k_nb_gather(int64_t N, int r, const int64_t *ptr, const int32_t 
     yt[t] = make_double2(re, im);
 }
 
+// FP64 blocks Ad[2 b + ori][Qp][2 Qp] ([Re | Im] rows, ori as for Ab)
+__global__ void k_nd_store(const double2 *bval, int64_t nblk, int nF, int Qp, double *Ad)
+{
+    const int K2 = 2 * Qp;
+    const int64_t per = (int64_t)Qp * Qp;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * nblk * per) return;
+    const int64_t po = t / per;
+    const int rem = (int)(t % per), i = rem / Qp, j = rem % Qp;
+    const int64_t b = po / 2;
+    const int ori = (int)(po % 2);
+    double2 v = make_double2(0.0, 0.0);
+    if (i < nF && j < nF) v = ori == 0 ? bval[((size_t)b * nF + i) * nF + j] : bval[((size_t)b * nF + j) * nF + i];
+    double *base = Ad + (size_t)po * Qp * K2;
+    base[(size_t)i * K2 + j] = v.x;
+    base[(size_t)i * K2 + Qp + j] = v.y;
+}
+
+// Xd[leaf][chunk][ncol][2 Qp] FP64: column n of chunk ch is right-hand side ch ncol + n
+__global__ void k_xnd_prep(int64_t nleaf, int nF, int Qp, int r, int ncol, int nchunk, const int32_t *leafdof,
+                           const double2 *xt, double *Xd)
+{
+    const int K2 = 2 * Qp;
+    const int64_t per = (int64_t)ncol * K2;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nleaf * nchunk * per) return;
+    const int64_t lc = t / per;
+    const int rem = (int)(t % per), n = rem / K2, k = rem % K2;
+    const int64_t leaf = lc / nchunk;
+    const int ch = (int)(lc % nchunk), col = ch * ncol + n, j = k < Qp ? k : k - Qp;
+    double v = 0.0;
+    if (j < nF && col < r) {
+        const int d = leafdof[(size_t)leaf * nF + j];
+        if (d >= 0) {
+            const double2 x = xt[(size_t)d * r + col];
+            v = k < Qp ? x.x : x.y;
+        }
+    }
+    Xd[(size_t)lc * per + rem] = v;
+}
+
+// FP64 real product (16x16x4 FP64 instruction: lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; accumulator register j of lane l holds D[l/16 + 4j][l%16]).  Waves:
+// wm = 0 real rows, 1 imaginary rows; wr = row half (MTW row tiles each); wn = column
+// group of NT tiles.  Two instructions take eight consecutive reduction indices, lane
+// group g the pair 2g, 2g + 1 (one 16-byte load per lane feeds both); the operands of
+// the next step are loaded during the products of the current one.
+typedef double dx4n __attribute__((ext_vector_type(4)));
+template <int MTW, int WN, int NT>
+__global__ __launch_bounds__(256 * WN) void k_near_md(int r, int nchunk, int nF, int64_t nwork, const int32_t *order,
+                                                      const M2LWork *work, const int32_t *partner,
+                                                      const int32_t *aslot, const double *Ad, const double *Xd,
+                                                      double2 *part)
+{
+    constexpr int QP = 32 * MTW, K2 = 2 * QP, NCOL = 16 * WN * NT, KS = K2 / 8;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int wm = wv / (2 * WN), wr = (wv / WN) % 2, wn = wv % WN;
+    const int gi = lane >> 4, li = lane & 15;
+    const int64_t g = blockIdx.x;
+    const int64_t wo = (g / (8 * nchunk)) * 8 + g % 8;
+    const int ch = (int)((g / 8) % nchunk);
+    if (wo >= nwork) return;
+    const M2LWork wk = work[order[wo]];
+    const int64_t wi = order[wo];
+    const size_t aper = (size_t)QP * K2, xper = (size_t)NCOL * K2;
+    dx4n acc[MTW][NT];
+#pragma unroll
+    for (int a = 0; a < MTW; ++a)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[a][t] = dx4n{0.0, 0.0, 0.0, 0.0};
+    const int nstep = (wk.end - wk.beg) * KS;
+    double2 av[MTW], bv[NT];
+    auto load = [&](int it) {
+        const int kp = wk.beg + it / KS, s8 = it % KS;
+        const double *Ap = Ad + (size_t)aslot[kp] * aper;
+        const double *Xs = Xd + ((size_t)partner[kp] * nchunk + ch) * xper;
+        const int kb = 8 * s8 + 2 * gi;
+        // real rows [Br, -Bi], imaginary rows [Bi, Br] of the stored [Br | Bi]; kb and
+        // 8 s8 lie in the same half (QP is a multiple of 16)
+        const bool hi = 8 * s8 >= QP;
+        const int ksrc = wm == 0 ? kb : (hi ? kb - QP : kb + QP);
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+            bv[t] = *reinterpret_cast<const double2 *>(Xs + (size_t)(16 * (wn * NT + t) + li) * K2 + kb);
+#pragma unroll
+        for (int a = 0; a < MTW; ++a)
+            av[a] = *reinterpret_cast<const double2 *>(Ap + (size_t)(16 * (wr * MTW + a) + li) * K2 + ksrc);
+        return wm == 0 && hi;
+    };
+    bool neg = nstep > 0 ? load(0) : false;
+    for (int it = 0; it < nstep; ++it) {
+        double2 ca[MTW], cb[NT];
+#pragma unroll
+        for (int a = 0; a < MTW; ++a) ca[a] = neg ? make_double2(-av[a].x, -av[a].y) : av[a];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) cb[t] = bv[t];
+        if (it + 1 < nstep) neg = load(it + 1);
+#pragma unroll
+        for (int a = 0; a < MTW; ++a)
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+                acc[a][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[a].x, cb[t].x, acc[a][t], 0, 0, 0);
+#pragma unroll
+        for (int a = 0; a < MTW; ++a)
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+                acc[a][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[a].y, cb[t].y, acc[a][t], 0, 0, 0);
+    }
+    // lane holds D[lane/16 + 4 j][lane % 16] of each tile: slot m, column n
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int col = ch * NCOL + 16 * (wn * NT + t) + li;
+        if (col >= r) continue;
+#pragma unroll
+        for (int a = 0; a < MTW; ++a)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int m = 16 * (wr * MTW + a) + gi + 4 * j;
+                if (m < nF) reinterpret_cast<double *>(part + ((size_t)wi * nF + m) * r + col)[wm] = acc[a][t][j];
+            }
+    }
+}
+
+__global__ void k_nd_gather(int64_t N, int r, const int64_t *ptr, const int32_t *idx, const double2 *part, double2 *yt)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N * r) return;
+    const int64_t i = t / r;
+    const int c = (int)(t % r);
+    double re = 0.0, im = 0.0;
+    for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) {
+        const double2 v = part[(size_t)idx[k] * r + c];
+        re += v.x;
+        im += v.y;
+    }
+    yt[t] = make_double2(re, im);
+}
+
 int near_qp(int nF) { return 32 * ((nF + 31) / 32); }
 
 }  // namespace
@@ -379,6 +521,80 @@ void near_bf16(ige_op op, int r, const double2 *xt, double2 *yt, hipStream_t s)
     const int64_t tot = (int64_t)o.N * r;
     hipLaunchKernelGGL(k_nb_gather, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, (int64_t)o.N, r,
                        op->d_nbred_ptr.p, op->d_nbred_idx.p, op->d_nbpart.p, yt);
+    IGE_HIP(hipGetLastError());
+}
+
+
+// FP64 matrix-core near field for many columns: blocks made on first use when they
+// leave 8 GiB of device memory free.  Ordered pairs read each block twice (as itself
+// and as its transpose) where the unordered-block kernel reads it once for both
+// products, so they pay only once the products dominate: from 56 columns (measured
+// at 8, 16, 32 and 64 columns with chunks of 16, 32 and 64)
+bool near_f64mx_ok(ige_op op, int r)
+{
+    const DevOp &o = op->view;
+    if (r < 56 || o.nblk == 0 || op->near_md_off || near_qp(o.nF) > 256) return false;
+    if (op->nd_fit < 0) {   // decided once, at the first eligible apply (never under capture)
+        const int Qp = near_qp(o.nF);
+        const size_t need = (size_t)2 * o.nblk * Qp * 2 * Qp * sizeof(double);
+        size_t fr = 0, tot = 0;
+        IGE_HIP(hipMemGetInfo(&fr, &tot));
+        op->nd_fit = op->d_nd.p || need + ((size_t)8 << 30) < fr ? 1 : 0;
+    }
+    return op->nd_fit == 1;
+}
+
+namespace {
+// 64 columns per workgroup as two column waves of two tiles (one column wave of four
+// tiles, or four of one, measured no faster)
+template <int MTW>
+void launch_nd(ige_op op, int r, int nchunk, hipStream_t s)
+{
+    constexpr int WN = 2, NT = 2;
+    const DevOp &o = op->view;
+    const int64_t nw = op->nb_nwork;
+    if (nw == 0) return;
+    const dim3 grid((unsigned)(((nw + 7) / 8) * 8 * nchunk)), blk(256 * WN);
+    hipLaunchKernelGGL((k_near_md<MTW, WN, NT>), grid, blk, 0, s, r, nchunk, o.nF, nw, op->d_nborder.p,
+                       op->d_nbwork.p, op->d_nbpartner.p, op->d_nbslot.p, op->d_nd.p, op->d_xnd.p, op->d_ndpart.p);
+    IGE_HIP(hipGetLastError());
+}
+}  // namespace
+
+void near_f64mx(ige_op op, int r, const double2 *xt, double2 *yt, hipStream_t s)
+{
+    const DevOp &o = op->view;
+    const int Qp = near_qp(o.nF);
+    if (!op->d_nd.p) {
+        op->d_nd.alloc((size_t)2 * o.nblk * Qp * 2 * Qp);
+        const int64_t n = 2 * o.nblk * (int64_t)Qp * Qp;
+        hipLaunchKernelGGL(k_nd_store, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, o.bval, o.nblk, o.nF, Qp,
+                           op->d_nd.p);
+        IGE_HIP(hipGetLastError());
+    }
+    constexpr int ncol = 64;   // columns per workgroup
+    const int nchunk = (r + ncol - 1) / ncol;
+    const int64_t nleaf = (int64_t)o.P * o.SL * o.SL;
+    const size_t xn = (size_t)nleaf * nchunk * ncol * 2 * Qp;
+    if (op->d_xnd.n < xn) op->d_xnd.alloc(xn);
+    const size_t pn = (size_t)op->nb_nwork * o.nF * r;
+    if (op->d_ndpart.n < pn) op->d_ndpart.alloc(pn);
+    hipLaunchKernelGGL(k_xnd_prep, dim3((unsigned)(((int64_t)xn + 255) / 256)), dim3(256), 0, s, nleaf, o.nF, Qp, r,
+                       ncol, nchunk, o.leafdof, xt, op->d_xnd.p);
+    IGE_HIP(hipGetLastError());
+    switch (Qp / 32) {
+        case 1: launch_nd<1>(op, r, nchunk, s); break;
+        case 2: launch_nd<2>(op, r, nchunk, s); break;
+        case 3: launch_nd<3>(op, r, nchunk, s); break;
+        case 4: launch_nd<4>(op, r, nchunk, s); break;
+        case 5: launch_nd<5>(op, r, nchunk, s); break;
+        case 6: launch_nd<6>(op, r, nchunk, s); break;
+        case 7: launch_nd<7>(op, r, nchunk, s); break;
+        default: launch_nd<8>(op, r, nchunk, s); break;
+    }
+    const int64_t tot = (int64_t)o.N * r;
+    hipLaunchKernelGGL(k_nd_gather, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, (int64_t)o.N, r,
+                       op->d_nbred_ptr.p, op->d_nbred_idx.p, op->d_ndpart.p, yt);
     IGE_HIP(hipGetLastError());
 }
 

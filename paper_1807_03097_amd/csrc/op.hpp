@@ -139,6 +139,10 @@ struct ige_op_s {
     ige::DBuf<float2> d_bmpart;          // matrix-core coupling partials [mwork][4][Q][r]
     ige::DBuf<double> d_Gd, d_vd;       // FP64 matrix-core coupling: blocks, right factors
     ige::DBuf<double2> d_bmpart64;      // FP64 matrix-core coupling partials [mwork][4][Q][r]
+    ige::DBuf<double> d_nd, d_xnd;      // FP64 matrix-core near field: ordered-pair blocks, gathered right factors
+    ige::DBuf<double2> d_ndpart;        // its partials [near work items][nF][r]
+    int nd_fit = -1;                    // those blocks fit in device memory (-1: not yet decided)
+    bool near_md_off = false;           // IGE_NEAR_F64=blocks: the unordered-block kernel instead
     int gd_fit = -1;                    // FP64 blocks fit in device memory (-1: not yet decided)
     bool f64mx_off = false;             // FP64 coupling of many columns generated per apply (IGE_M2L_F64=generate)
     ige::DBuf<int32_t> d_morder;         // work items by decreasing partner count
@@ -242,6 +246,9 @@ void plan_near_bf16(ige_op op, const std::vector<int32_t> &pair, const std::vect
 void ensure_near_bf16(ige_op op);
 int near_bf16_ok(int nF);
 void near_bf16(ige_op op, int r, const double2 *xt, double2 *yt, hipStream_t s);
+// FP64 near field of r >= 56 columns on the FP64 matrix cores (ordered-pair FP64 blocks)
+bool near_f64mx_ok(ige_op op, int r);
+void near_f64mx(ige_op op, int r, const double2 *xt, double2 *yt, hipStream_t s);
 void launch_m2l_reduce(ige_op op);
 void launch_l2l(ige_op op);
 // near-field product; records mid (if given) between the block pass and the reduction

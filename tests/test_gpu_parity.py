@@ -329,6 +329,39 @@ def test_fp64_matrix_core_coupling(oracle_mod, ctx, monkeypatch, case):
     op.close()
 
 
+@pytest.mark.parametrize("case", [CASES[2], CASES[4], CASES[8], CASES[10]],
+                         ids=["sphere-m3-d1", "torus-m3", "sphere-d0", "sphere-p3"])
+def test_fp64_matrix_core_near_field(oracle_mod, ctx, monkeypatch, case):
+    """FP64 applies of 56 or more columns take the near field as FP64 matrix-core
+    products over ordered leaf pairs: equal to the unordered-block kernel and to
+    single columns up to summation order, and the first column to the oracle, for 56,
+    64 and 130 columns (one ragged chunk of 64, one full, three with a ragged last)."""
+    from paper_1807_03097_amd import binding as B
+    name, p, m, kappa, q, eta, d, g, gs = case
+    _say(f"case {case}")
+    pats = _geom(name)
+    geom = B.Geometry(ctx, pats)
+    op = B.Operator(geom, p, m, kappa, q, eta, g, gs, d)
+    monkeypatch.setenv("IGE_NEAR_F64", "blocks")
+    opb = B.Operator(geom, p, m, kappa, q, eta, g, gs, d)
+    monkeypatch.delenv("IGE_NEAR_F64")
+    o = oracle_mod.Oracle(pats, p, m, kappa, g=g, gs=gs)
+    XA = np.stack([W.random_coeffs(op.N, 500 + s) for s in range(130)])
+    yo = o.fmm_apply(XA[0], q, eta, d)
+    for nc in (56, 64, 130):
+        X = XA[:nc].copy()
+        Y = op.apply(X)
+        Yb = opb.apply(X)
+        eb = max(_rel(Y[c], Yb[c]) for c in range(nc))
+        e1 = max(_rel(Y[c], op.apply(X[c].copy())) for c in (0, nc // 2, nc - 1))
+        eo = _rel(Y[0], yo)
+        _say(f"  {nc} columns: vs unordered blocks {eb:.2e}, vs single columns {e1:.2e}, "
+             f"first column vs oracle {eo:.2e}")
+        assert eb <= 1e-13 and e1 <= 1e-13 and eo <= TOL
+    opb.close()
+    op.close()
+
+
 def test_stage_profiling_levels(ctx):
     """Level 1 times every stage of a single-column apply (and of a batched one); level
     2 only the block pass and the coupling kernel, the other stages reading 0; neither
