@@ -276,14 +276,16 @@ int ige_solve(ige_op op, int r, const ige_c64 *f, ige_c64 *x, int ptr_kind, cons
  * A server owns n_workers host threads, each with its own HIP stream on the device
  * of ctx, so the assembly and solve kernels of several requests share the device.
  * A request is one full solve: the operator of geom with the parameters prm
- * (assembled on the worker's stream, Sec. 3-4), the right-hand side of one plane
- * wave e_inc = pol exp(i kappa dir.x) (as ige_rhs_plane_wave), GMRES with opts
- * from x0 = 0 (as ige_solve), and the copy of the solution to host memory.
+ * (assembled on the worker's stream, Sec. 3-4), the right-hand sides of one or
+ * several plane waves e_inc = pol exp(i kappa dir.x) (as ige_rhs_plane_wave), GMRES
+ * with opts from x0 = 0 on all of them at once (as ige_solve), and the copy of the
+ * solutions to host memory.
  * Admission: requests wait in arrival order and start first-fit when their device
  * footprint (planned on the host at submission: near-field blocks, element and
- * cluster data, Krylov basis of opts.restart vectors) fits in hbm_budget next to
- * the running requests; the oldest waiting request is overtaken only during its
- * first second of waiting.  hbm_budget 0: 80 % of the free device memory.
+ * cluster data, Krylov bases of opts.restart vectors per wave, the copies of the
+ * blocks that the many-column kernels and the refinement precision make) fits in
+ * hbm_budget next to the running requests; the oldest waiting request is overtaken
+ * only during its first second of waiting.  hbm_budget 0: 80 % of the free device memory.
  * The caller keeps geom alive until its requests have finished.  Requests that
  * run concurrently share the device and do not synchronise with each other.
  * Timestamps are seconds since the server was created. */
@@ -297,15 +299,23 @@ typedef struct {
     size_t footprint;    /* planned device bytes used for admission */
     double t_submit, t_start, t_done;
     double assemble_s, solve_s;
+    int n_waves;         /* plane waves of the request; iters and relres are the largest over them */
 } ige_srv_stats;
 int ige_srv_create(ige_ctx ctx, int n_workers, size_t hbm_budget, ige_srv *out);
 /* Queue one request; returns at once with its ticket.  IGE_ENOMEM if its footprint
  * exceeds the budget, IGE_EINVAL on bad parameters. */
 int ige_srv_submit(ige_srv srv, ige_geom geom, const ige_params *prm, const double *dir, const ige_c64 *pol,
                    const ige_solve_opts *opts, int64_t *ticket);
+/* As ige_srv_submit for n_waves plane waves (1..4096): dir [n_waves][3], pol
+ * [n_waves][3] (host, copied), solved together as an n_waves-column system (the
+ * many-right-hand-side form of the scattering problem: one operator, several
+ * incident directions). */
+int ige_srv_submit_waves(ige_srv srv, ige_geom geom, const ige_params *prm, int n_waves, const double *dir,
+                         const ige_c64 *pol, const ige_solve_opts *opts, int64_t *ticket);
 int ige_srv_poll(ige_srv srv, int64_t ticket, ige_srv_stats *stats);   /* non-blocking */
 int ige_srv_wait(ige_srv srv, int64_t ticket, ige_srv_stats *stats);   /* blocks until finished */
-/* Copy a finished request's solution (n = its n_dof complex values) to host x. */
+/* Copy a finished request's solutions (n = n_waves * n_dof complex values, [n_waves][n_dof])
+ * to host x. */
 int ige_srv_result(ige_srv srv, int64_t ticket, ige_c64 *x, int64_t n);
 /* Finish every queued and running request, stop the workers, free everything. */
 int ige_srv_destroy(ige_srv srv);

@@ -57,7 +57,7 @@ class ige_srv_stats(C.Structure):
     _fields_ = [("state", C.c_int), ("rc", C.c_int), ("iters", C.c_int), ("relres", C.c_double),
                 ("n_dof", C.c_int64), ("footprint", C.c_size_t), ("t_submit", C.c_double),
                 ("t_start", C.c_double), ("t_done", C.c_double), ("assemble_s", C.c_double),
-                ("solve_s", C.c_double)]
+                ("solve_s", C.c_double), ("n_waves", C.c_int)]
 
 
 # One HIP runtime per process: torch ships its own libamdhip64 (same soname);
@@ -98,6 +98,8 @@ _SIGS = {
     "ige_srv_create": (C.c_int, [_V, C.c_int, C.c_size_t, C.POINTER(_V)]),
     "ige_srv_submit": (C.c_int, [_V, _V, C.POINTER(ige_params), _V, _V, C.POINTER(ige_solve_opts),
                                  C.POINTER(C.c_int64)]),
+    "ige_srv_submit_waves": (C.c_int, [_V, _V, C.POINTER(ige_params), C.c_int, _V, _V,
+                                       C.POINTER(ige_solve_opts), C.POINTER(C.c_int64)]),
     "ige_srv_poll": (C.c_int, [_V, C.c_int64, C.POINTER(ige_srv_stats)]),
     "ige_srv_wait": (C.c_int, [_V, C.c_int64, C.POINTER(ige_srv_stats)]),
     "ige_srv_result": (C.c_int, [_V, C.c_int64, _V, C.c_int64]),
@@ -388,6 +390,17 @@ def ige_srv_submit(srv, geom, prm, direction, pol, opts):
     return t.value
 
 
+def ige_srv_submit_waves(srv, geom, prm, directions, pols, opts):
+    d = np.ascontiguousarray(directions, np.float64).reshape(-1, 3)
+    pl = np.ascontiguousarray(pols, np.complex128).reshape(-1, 3)
+    if len(d) != len(pl):
+        raise ValueError("directions and polarisations differ in number")
+    t = C.c_int64()
+    _check(_lib.ige_srv_submit_waves(srv, geom, C.byref(prm), len(d), _ptr(d), _ptr(pl), C.byref(opts),
+                                     C.byref(t)))
+    return t.value
+
+
 def ige_srv_poll(srv, ticket):
     st = ige_srv_stats()
     _check(_lib.ige_srv_poll(srv, ticket, C.byref(st)))
@@ -427,7 +440,10 @@ class Server:
                inner_tol=1e-4, inner_prec=IGE_F32):
         prm = ige_params(p, level, kappa, q, eta, gauss_near, gauss_singular, leaf_depth, 0)
         opts = ige_solve_opts(tol, restart, maxit, int(refine), inner_tol, inner_prec)
-        t = ige_srv_submit(self.h, geom.h, prm, direction, pol, opts)
+        if np.ndim(direction) == 2:   # [W][3] directions and polarisations: one request of W waves
+            t = ige_srv_submit_waves(self.h, geom.h, prm, direction, pol, opts)
+        else:
+            t = ige_srv_submit(self.h, geom.h, prm, direction, pol, opts)
         self._geoms[t] = geom   # keep the geometry alive until the request is done
         return t
 
@@ -438,8 +454,10 @@ class Server:
         return _stats_dict(ige_srv_wait(self.h, ticket))
 
     def result(self, ticket):
+        """Solution [N] of a single-wave request submitted with one direction, else [W][N]."""
         st = self.wait(ticket)
-        return ige_srv_result(self.h, ticket, st["n_dof"]), st
+        x = ige_srv_result(self.h, ticket, st["n_waves"] * st["n_dof"])
+        return (x.reshape(st["n_waves"], st["n_dof"]) if st["n_waves"] > 1 else x), st
 
     def close(self):
         if self.h:

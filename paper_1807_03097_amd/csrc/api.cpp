@@ -264,7 +264,7 @@ void plan(ige_op op, const ige_geom_s *geom, ige::NearBlocks &A, std::vector<ige
 
 // device bytes an assembled operator and a single-column GMRES with the given
 // restart will hold (estimate from the host plan)
-size_t ige::planned_device_bytes(const ige_op_s *op, int restart)
+size_t ige::planned_device_bytes(const ige_op_s *op, int restart, int r, const ige_solve_opts *opts)
 {
     const ige::Discretisation &D = op->D;
     const int64_t E = (int64_t)D.P * D.n * D.n;
@@ -272,16 +272,32 @@ size_t ige::planned_device_bytes(const ige_op_s *op, int restart)
     const int Q = (op->prm.q + 1) * (op->prm.q + 1);
     const int s = op->T.s, W = s + p, nF = 2 * W * (W - 1);
     const int64_t nblk = nF > 0 ? op->nnz / ((int64_t)nF * nF) : 0;
+    const size_t R = (size_t)std::max(1, r);
+    const size_t nfp = op->T.far.size() / 2, Qp = 32 * (((size_t)Q + 31) / 32), Qn = 32 * (((size_t)nF + 31) / 32);
     size_t b = 0;
     b += (size_t)op->nnz * 16;                                   // near-field blocks
-    b += (size_t)nblk * nF * 3 * 16;                             // partial results (2 row chunks)
+    b += (size_t)nblk * nF * 3 * 16 * R;                         // partial results (2 row chunks)
     b += (size_t)E * (3 + 4 * nl) * G2 * 8 + (size_t)E * psi_fragment_doubles(nl, G2) * 8 + (size_t)E * 96;
-    b += (size_t)op->NC * Q * (9 * 8 + 11 * 16);                 // node data, moments, fields
-    b += (size_t)op->T.far.size() * 4 * Q * 16 / 4;              // coupling partials (chunks of partners)
-    b += (size_t)op->nsing * 24 + (size_t)D.N * 80;
-    b += ((size_t)restart + 1 + 8) * D.N * 16;                   // Krylov basis and work vectors
-    const ige::GsPlan gp = ige::gs_plan(D.N, 1, restart);
-    b += (ige::gs_part_count(gp, 1, restart) + ige::gs_split_count(gp, D.N, 1)) * 16;   // Gram-Schmidt scratch
+    b += (size_t)op->NC * Q * (9 * 8 + 11 * 16 * R);             // node data, moments, fields
+    b += (size_t)op->T.far.size() * 4 * Q * 16 / 4 * R;          // coupling partials (chunks of partners)
+    b += (size_t)op->nsing * 24 + (size_t)D.N * 80 * R;
+    b += ((size_t)restart + 1 + 8) * D.N * 16 * R;               // Krylov basis and work vectors
+    const ige::GsPlan gp = ige::gs_plan(D.N, (int)R, restart);
+    b += (ige::gs_part_count(gp, (int)R, restart) + ige::gs_split_count(gp, D.N, (int)R)) * 16;   // Gram-Schmidt scratch
+    // copies made on first use by the many-column kernels
+    if (R >= 8) b += nfp * 2 * Qp * 2 * Qp * 8;                  // FP64 coupling blocks
+    if (R >= 56) {                                               // ordered-pair FP64 near blocks, operands
+        b += (size_t)nblk * 2 * Qn * 2 * Qn * 8;
+        const size_t SL = s > 0 ? (size_t)D.n / s : 0;
+        b += (size_t)D.P * SL * SL * ((R + 63) / 64) * 64 * 2 * Qn * 8;
+    }
+    if (opts && opts->refine) {
+        const int ip = opts->inner_prec;
+        if (opts->inner_tol >= 1e-5) b += ((size_t)restart + 1) * D.N * 8 * R;   // FP32 inner basis
+        if (ip == IGE_F32) b += (size_t)op->T.far.size() * Q * Q * 8;           // FP32 coupling values
+        if (ip >= IGE_BF16) b += nfp * 2 * (ip == IGE_BF16 ? 1 : 2) * Qp * 2 * Qp * 2;
+        if (ip == IGE_BF16X3_ALL) b += (size_t)nblk * 2 * 2 * Qn * 2 * Qn * 2 + (size_t)nblk * nF * 8 * R;
+    }
     return b;
 }
 

@@ -206,7 +206,8 @@ inline bool prof_records(const ige_op_s *op, int i)
 // assembly of geom's operator on ctx's device and stream (throws ige::Status)
 ige_op assemble_on(ige_ctx ctx, const ige_geom_s *geom, const ige_params &prm);
 // device bytes of an operator planned on the host plus a GMRES with this restart
-size_t planned_device_bytes(const ige_op_s *op, int restart);
+// device bytes of an operator and an r-column solve with opts (NULL: FP64, no refinement)
+size_t planned_device_bytes(const ige_op_s *op, int restart, int r, const ige_solve_opts *opts);
 
 // assembly
 void launch_element_data(ige_op op);

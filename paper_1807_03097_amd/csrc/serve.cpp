@@ -1,13 +1,14 @@
 // Serving: many independent scattering solves (geometry, discretisation,
-// wavenumber and one incident plane wave each) on one device.
+// wavenumber and one or several incident plane waves each) on one device.
 //
 // A server owns n_workers host threads; each has its own context, i.e. its own HIP
 // stream, so the kernels of several requests share the device.  Requests wait in
 // arrival order and are admitted first-fit by their planned device footprint
 // against a memory budget; a request may overtake the oldest waiting one only while
 // that one has waited less than kMaxBypass seconds, which bounds its delay.  A
-// worker assembles the operator on its stream, forms the right-hand side, runs GMRES
-// and copies the solution to host memory, then frees the operator.
+// worker assembles the operator on its stream, forms the right-hand sides, runs GMRES
+// on all of them at once (the batched kernels from two waves on) and copies the
+// solutions to host memory, then frees the operator.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,8 +32,9 @@ struct SrvReq {
     int64_t ticket = 0;
     const ige_geom_s *geom = nullptr;
     ige_params prm{};
-    double dir[3] = {0, 0, 1};
-    ige_c64 pol[3] = {};
+    int nw = 1;                  // plane waves (right-hand sides)
+    std::vector<double> dir;     // [nw][3]
+    std::vector<ige_c64> pol;    // [nw][3]
     ige_solve_opts opts{};
     size_t footprint = 0;
     int64_t n_dof = 0;
@@ -91,16 +93,18 @@ struct ige_srv_s {
             const double t1 = now();
             r->assemble_s = t1 - t0;
             const int64_t N = op->D.N;
-            std::vector<ige_c64> f((size_t)N);
-            r->x.assign((size_t)N, ige_c64{0.0, 0.0});
-            int rc = ige_rhs_plane_wave(op, 1, r->dir, r->pol, f.data(), IGE_HOST);
+            std::vector<ige_c64> f((size_t)N * r->nw);
+            r->x.assign((size_t)N * r->nw, ige_c64{0.0, 0.0});
+            int rc = ige_rhs_plane_wave(op, r->nw, r->dir.data(), r->pol.data(), f.data(), IGE_HOST);
             if (rc != IGE_OK) throw ige::Status{rc, ige_last_error()};
-            ige_solve_stats st{};
-            rc = ige_solve(op, 1, f.data(), r->x.data(), IGE_HOST, &r->opts, &st);
+            std::vector<ige_solve_stats> st((size_t)r->nw);
+            rc = ige_solve(op, r->nw, f.data(), r->x.data(), IGE_HOST, &r->opts, st.data());
             if (rc != IGE_OK && rc != IGE_ENOTCONV) throw ige::Status{rc, ige_last_error()};
             r->rc = rc;
-            r->iters = st.iters;
-            r->relres = st.relres;
+            for (const auto &c : st) {   // the slowest wave
+                r->iters = std::max(r->iters, c.iters);
+                r->relres = std::max(r->relres, c.relres);
+            }
             r->solve_s = now() - t1;
         } catch (const ige::Status &e) {
             r->rc = e.code;
@@ -161,6 +165,7 @@ void fill_stats(const SrvReq &r, ige_srv_stats *st)
     st->t_done = r.t_done;
     st->assemble_s = r.assemble_s;
     st->solve_s = r.solve_s;
+    st->n_waves = r.nw;
 }
 
 template <typename F>
@@ -208,22 +213,28 @@ int ige_srv_create(ige_ctx ctx, int n_workers, size_t hbm_budget, ige_srv *out)
 int ige_srv_submit(ige_srv srv, ige_geom geom, const ige_params *prm, const double *dir, const ige_c64 *pol,
                    const ige_solve_opts *opts, int64_t *ticket)
 {
+    return ige_srv_submit_waves(srv, geom, prm, 1, dir, pol, opts, ticket);
+}
+
+int ige_srv_submit_waves(ige_srv srv, ige_geom geom, const ige_params *prm, int n_waves, const double *dir,
+                         const ige_c64 *pol, const ige_solve_opts *opts, int64_t *ticket)
+{
     return srv_guard([&] {
         IGE_REQUIRE(srv && geom && prm && dir && pol && opts && ticket, "null argument");
         IGE_REQUIRE(opts->restart >= 1 && opts->maxit >= 0, "bad solve options");
+        IGE_REQUIRE(n_waves >= 1 && n_waves <= 4096, "n_waves must be 1..4096");
         auto r = std::make_unique<SrvReq>();
         r->geom = geom;
         r->prm = *prm;
-        for (int k = 0; k < 3; ++k) {
-            r->dir[k] = dir[k];
-            r->pol[k] = pol[k];
-        }
+        r->nw = n_waves;
+        r->dir.assign(dir, dir + 3 * (size_t)n_waves);
+        r->pol.assign(pol, pol + 3 * (size_t)n_waves);
         r->opts = *opts;
         // footprint from the host plan of the operator
         ige_op planned = nullptr;
         int rc = ige_op_plan(geom, prm, &planned);
         if (rc != IGE_OK) throw ige::Status{rc, ige_last_error()};
-        r->footprint = ige::planned_device_bytes(planned, opts->restart);
+        r->footprint = ige::planned_device_bytes(planned, opts->restart, n_waves, opts);
         r->n_dof = planned->D.N;
         ige_op_destroy(planned);
         std::lock_guard<std::mutex> lk(srv->mu);

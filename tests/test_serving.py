@@ -173,3 +173,50 @@ def test_refined_requests_meet_the_fp64_tolerance(inner):
     for g in geoms.values():
         g.close()
     ctx.close()
+
+
+@pytest.mark.gpu
+def test_multi_wave_requests_match_direct_solves():
+    """Requests of several plane waves (one operator, all waves solved together, the
+    batched kernels from two waves and the matrix-core ones from eight) equal direct
+    solves of the same columns, beside single-wave requests; a refined nine-wave
+    request (split-BF16 coupling and near field inside) reaches the FP64 tolerance and
+    the FP64 solution; the planned footprint grows with the waves."""
+    from paper_1807_03097_amd import binding as B
+    ctx = B.Context(0)
+    geoms = {n: _geom(B, ctx, n) for n in ("sphere", "torus", "jittered")}
+    cases = [(REQS[2], 3, False), (REQS[3], 9, False), (REQS[4], 2, False), (REQS[2], 9, True)]
+    ref = []
+    for (n, p, m, kap, q, eta, d, seed), nw, _ in cases:
+        op = B.Operator(geoms[n], p, m, kap, q, eta, 5, 5, d)
+        dirs, pols = W.random_plane_waves(nw, seed)
+        X, st, rc = op.solve(op.rhs_plane_wave(dirs, pols), tol=TOL, restart=300, maxit=3000)
+        assert rc == 0
+        ref.append(X)
+        op.close()
+    srv = B.Server(ctx, 3)
+    ts, singles = [], []
+    for ((n, p, m, kap, q, eta, d, seed), nw, refine) in cases:
+        dirs, pols = W.random_plane_waves(nw, seed)
+        ts.append(srv.submit(geoms[n], p, m, kap, dirs, pols, q=q, eta=eta, leaf_depth=d, tol=TOL, restart=300,
+                             maxit=6000, refine=refine, inner_tol=1e-4, inner_prec=B.IGE_BF16X3_ALL))
+        di, pol = _wave(seed)
+        singles.append(srv.submit(geoms[n], p, m, kap, di, pol, q=q, eta=eta, leaf_depth=d, tol=TOL, restart=300))
+    fp = {}
+    for k, (t, (rq, nw, refine)) in enumerate(zip(ts, cases)):
+        X, st = srv.result(t)
+        assert st["n_waves"] == nw and X.shape == (nw, st["n_dof"])
+        err = max(np.linalg.norm(X[c] - ref[k][c]) / np.linalg.norm(ref[k][c]) for c in range(nw))
+        print(f"request {k}: {nw} waves refine={refine} iters={st['iters']} relres={st['relres']:.1e} "
+              f"vs direct {err:.1e} footprint {st['footprint'] / 2**20:.0f} MiB", flush=True)
+        assert st["rc"] == 0 and st["relres"] <= TOL * 1.05
+        assert err <= (1e-6 if refine else _agree(TOL))
+        fp[(rq[0], rq[2], nw, refine)] = st["footprint"]
+    for t in singles:
+        x1, s1 = srv.result(t)
+        assert s1["rc"] == 0 and s1["n_waves"] == 1 and x1.shape == (s1["n_dof"],)
+    srv.close()
+    assert fp[("sphere", 3, 9, True)] > fp[("sphere", 3, 3, False)]
+    for g in geoms.values():
+        g.close()
+    ctx.close()
