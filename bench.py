@@ -396,9 +396,10 @@ def main():
                 "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
                 "useful_tflops": useful / (t_ms * 1e-3) / 1e12, "issued_flop": issued, "avg_ms": t_ms}
 
-    def roofline(stage_ms):
+    def roofline(stage_ms, dom=None):
         # the dominant kernel: the near-field block pass or the coupling kernel
-        dom = "near_spmv" if stage_ms["near_blk"] >= stage_ms["m2l_kernel"] else "m2l"
+        if dom is None:
+            dom = "near_spmv" if stage_ms["near_blk"] >= stage_ms["m2l_kernel"] else "m2l"
         if dom == "m2l" and (f64mx or (args.prec in (2, 3, 4) and r > 1)):
             return roofline_coupling(stage_ms)   # the matrix-core coupling kernel
         Q = (q + 1) ** 2
@@ -468,6 +469,8 @@ def main():
     op.set_profiling(False)
     op.set_overlap(True)
     roof_iso = roofline(st_iso)
+    # the near-field product alone on the device (stages in order on one stream)
+    roof_near_iso = roofline(st_iso, dom="near_spmv")
     log("isolated stage ms: " + " ".join(f"{k}={v:.4f}" for k, v in st_iso.items()))
 
     # parity spot check against the oracle (sampled rows) + CPU baseline
@@ -503,6 +506,7 @@ def main():
         "assemble_s": t_asm,
         "roofline": roof,
         "roofline_isolated": roof_iso,
+        "roofline_near_isolated": roof_near_iso,
         "roofline_coupling": roof_cpl,
         "rel_err_vs_fp64": err_fp64,
         "autotuned": tuned,
