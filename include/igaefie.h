@@ -111,9 +111,10 @@ typedef struct {
 } ige_params;
 
 /* Assemble the operator on the device: element and cluster-node geometry, the
- * near-field Galerkin entries (element-pair quadrature, accumulated in the glued
- * basis as a CSR matrix), the far-field partition and the moment and transfer
- * tables.  Synchronous. */
+ * near-field Galerkin entries (element-pair quadrature, summed in a fixed order into
+ * dense blocks over the leaf function slots of each near leaf pair, glued basis),
+ * the far-field partition and the moment and transfer tables.  Synchronous.  The
+ * result does not depend on timing: the same inputs give the same bits. */
 int ige_op_assemble(ige_geom geom, const ige_params *params, ige_op *out);
 int ige_op_destroy(ige_op op);
 
@@ -145,6 +146,15 @@ int ige_op_dofmap(ige_op op, int32_t *dof, int8_t *sgn);
  *   near [near_leaf_pairs][2] (target leaf cluster, source leaf cluster)
  * cluster id on level l: patch*4^l + k2*2^l + k1.  Either pointer may be NULL. */
 int ige_op_partition(ige_op op, int32_t *far, int32_t *near);
+
+/* Copy the assembled near-field blocks (the exact Galerkin entries of the
+ * non-admissible leaf pairs, Sec. 4.2) to host memory: one dense nF x nF complex
+ * block per unordered near leaf pair in the order of ige_op_partition's near list
+ * with target <= source, rows over the target leaf's function slots, signs of the
+ * glued unknowns folded in, zero rows and columns where a slot holds no unknown.
+ * n must equal near_nnz of ige_op_info.  Synchronous.  The assembly sums every entry
+ * in a fixed order, so two assemblies of the same operator give the same bits. */
+int ige_op_near_blocks(ige_op op, ige_c64 *out, int64_t n);
 
 enum { IGE_F64 = 0, IGE_F32 = 1, IGE_BF16 = 2, IGE_BF16X3 = 3, IGE_BF16X3_ALL = 4 };
 

@@ -85,6 +85,7 @@ _SIGS = {
     "ige_op_info": (C.c_int, [_V, C.POINTER(ige_op_info_t)]),
     "ige_op_dofmap": (C.c_int, [_V, _V, _V]),
     "ige_op_partition": (C.c_int, [_V, _V, _V]),
+    "ige_op_near_blocks": (C.c_int, [_V, _V, C.c_int64]),
     "ige_apply": (C.c_int, [_V, C.c_int, _V, _V, C.c_int]),
     "ige_apply_prec": (C.c_int, [_V, C.c_int, _V, _V, C.c_int, C.c_int]),
     "ige_op_set_profiling": (C.c_int, [_V, C.c_int]),
@@ -317,6 +318,12 @@ class Operator:
         near = np.zeros((int(self.info.near_leaf_pairs), 2), np.int32)
         ige_op_partition(self.h, far, near)
         return {"L": int(self.info.leaf_level), "far": far, "near": near}
+
+    def near_blocks(self):
+        """the stored near-field blocks as a flat complex array of near_nnz entries"""
+        out = np.zeros(int(self.info.near_nnz), np.complex128)
+        _check(_lib.ige_op_near_blocks(self.h, _ptr(out), len(out)))
+        return out
 
     def apply(self, x, y=None, prec=IGE_F64):
         """y = A x; x numpy (host) or torch (device) of shape (N,) or (r, N)."""

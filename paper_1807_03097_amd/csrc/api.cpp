@@ -281,6 +281,7 @@ size_t ige::planned_device_bytes(const ige_op_s *op, int restart, int r, const i
     b += (size_t)op->NC * Q * (9 * 8 + 11 * 16 * R);             // node data, moments, fields
     b += (size_t)op->T.far.size() * 4 * Q * 16 / 4 * R;          // coupling partials (chunks of partners)
     b += (size_t)op->nsing * 24 + (size_t)D.N * 80 * R;
+    b += (size_t)op->nsing * nl * nl * 16 + (size_t)nblk * s * s * 4;   // singular pair blocks (assembly)
     b += ((size_t)restart + 1 + 8) * D.N * 16 * R;               // Krylov basis and work vectors
     const ige::GsPlan gp = ige::gs_plan(D.N, (int)R, restart);
     b += (ige::gs_part_count(gp, (int)R, restart) + ige::gs_split_count(gp, D.N, (int)R)) * 16;   // Gram-Schmidt scratch
@@ -406,8 +407,29 @@ ige_op ige::assemble_on(ige_ctx ctx, const ige_geom_s *geom, const ige_params &p
             v.bpair = op->d_bpair.p; v.bval = op->d_bval.p; v.leafdof = op->d_leafdof.p; v.leafsgn = op->d_leafsgn.p;
             v.red_ptr = op->d_red_ptr.p; v.red_idx = op->d_red_idx.p;
             op->d_sing.upload(sing, s);
-            ige::launch_near_regular(op);
+            {
+                // range of singular pairs per (block, test element of the target leaf):
+                // the list is ordered by block, then test element (row major in the leaf)
+                const int s2 = T.s * T.s;
+                std::vector<int32_t> sptr((size_t)A.nblk() * s2 + 1, 0);
+                int64_t prev = -1;
+                for (size_t k = 0; k < sing.size(); ++k) {
+                    const int64_t e = sing[k].e;
+                    const int e1 = (int)(e % D.n), e2 = (int)((e / D.n) % D.n);
+                    const int64_t key = (int64_t)sing[k].blk * s2 + (e2 % T.s) * T.s + (e1 % T.s);
+                    IGE_REQUIRE(key >= prev, "singular pairs not ordered by block and test element");
+                    prev = key;
+                    sptr[key + 1]++;
+                }
+                for (size_t i = 1; i < sptr.size(); ++i) sptr[i] += sptr[i - 1];
+                op->d_sing_ptr.upload(sptr, s);
+            }
+            op->d_sblk.alloc(std::max<size_t>(1, (size_t)op->nsing * v.nl * v.nl));
+            v.sing = op->d_sing.p; v.sing_ptr = op->d_sing_ptr.p; v.sblk = op->d_sblk.p;
+            // singular element pairs into their own slots, then the regular pairs and those
+            // slots summed into the blocks in a fixed order (colour by colour)
             ige::launch_near_singular(op);
+            ige::launch_near_regular(op);
             // cluster tree and far field
             op->d_lvl_off.upload(op->lvl_off, s);
             v.lvl_off = op->d_lvl_off.p;
@@ -587,6 +609,8 @@ ige_op ige::assemble_on(ige_ctx ctx, const ige_geom_s *geom, const ige_params &p
             int err = 0;
             IGE_HIP(hipMemcpy(&err, op->d_err.p, sizeof(int), hipMemcpyDeviceToHost));
             IGE_REQUIRE(err == 0, "near-field assembly produced entries outside the leaf function slots");
+            op->d_sblk.release();
+            v.sblk = nullptr;
         } catch (...) {
             delete op;
             throw;
@@ -685,6 +709,18 @@ int ige_op_partition(ige_op op, int32_t *far, int32_t *near)
         if (near)
             for (size_t i = 0; i < op->T.near.size(); ++i)
                 for (int k = 0; k < 2; ++k) near[2 * i + k] = op->T.near[i][k];
+    });
+}
+
+int ige_op_near_blocks(ige_op op, ige_c64 *out, int64_t n)
+{
+    return guard([&] {
+        IGE_REQUIRE(op && out, "null argument");
+        IGE_REQUIRE(op->assembled, "operator was planned, not assembled");
+        IGE_REQUIRE(n == op->nnz, "n must equal near_nnz");
+        set_device(op->ctx);
+        IGE_HIP(hipStreamSynchronize(op->ctx->stream));
+        if (n > 0) IGE_HIP(hipMemcpy(out, op->d_bval.p, sizeof(double2) * (size_t)n, hipMemcpyDeviceToHost));
     });
 }
 

@@ -319,29 +319,6 @@ __device__ inline void local_dof(const DevOp &o, int j, int e1, int e2, int l, i
     sg = (double)o.sgn[off];
 }
 
-// leaf cluster of element (j, e1, e2) and the leaf-local slot of its local function l
-__device__ inline int leaf_of(const DevOp &o, int j, int e1, int e2)
-{
-    return (j * o.SL + e2 / o.s) * o.SL + e1 / o.s;
-}
-__device__ inline int elem_slot(const DevOp &o, int e1, int e2, int l)
-{
-    int a, t1, t2;
-    local_index(o.p, l, a, t1, t2);
-    return leaf_slot(o.W, a, e1 % o.s + t1, e2 % o.s + t2);
-}
-
-// block entry B_b[kr][kc] += s_r s_c v (signs of the glued unknowns folded in)
-__device__ inline void blk_add(const DevOp &o, int64_t b, int lt, int ls, int kr, int kc, double2 v)
-{
-    const int nF = o.nF;
-    const double sg = (double)o.leafsgn[(size_t)lt * nF + kr] * (double)o.leafsgn[(size_t)ls * nF + kc];
-    if (sg == 0.0) return;   // slot without an unknown
-    double *dst = reinterpret_cast<double *>(o.bval + ((size_t)b * nF + kr) * nF + kc);
-    atomicAdd(dst, sg * v.x);
-    atomicAdd(dst + 1, sg * v.y);
-}
-
 // FP64 matrix-core instruction 16x16x4: lane l supplies A[l % 16][l / 16] and
 // B[l / 16][l % 16]; accumulator register j of lane l holds D[l / 16 + 4 j][l % 16].
 // Operand order: for step t a lane supplies the entry with quadrature index
@@ -435,28 +412,43 @@ __device__ inline bool share_corner(const DevOp &o, int64_t e, int64_t f)
 // The accumulator layout of the first product (row lane/16 + 4 j) is the operand
 // layout of the second when its reduction slots are ordered by frag_q.
 // A workgroup takes one block, one test element e of the target leaf and a square
-// of sb x sb trial elements of the source leaf (one wave per trial element at a
-// time); the block rows of e are summed in shared memory, then added to the block.
+// of sb x sb trial elements of the source leaf.  The four waves take the trial
+// elements four at a time; their element-pair blocks are added to the block rows of
+// e in shared memory one wave after the other (trial elements in ascending order),
+// then the element pairs of e that share a corner with a trial element of the square
+// (computed before by k_near_singular) in list order.  Every sum therefore has a
+// fixed order.
+// Launched once per colour: the test elements of a launch are p + 1 apart in both
+// directions (no glued function in common, so no block row in common), and with
+// several trial squares per leaf the squares of a launch are two apart (sb >= p: no
+// column in common).  Each block entry thus has at most one writer per launch, and
+// the launches run in a fixed order on one stream: the assembled blocks are the same
+// bits on every run.
 // ---------------------------------------------------------------------------
 template <int NL, int QT>
-__global__ __launch_bounds__(256) void k_near_regular(DevOp o, int sb)
+__device__ __forceinline__ void near_regular_body(const DevOp &o, int sb, int ce1, int ce2, int cs1, int cs2, int sstep)
 {
     constexpr int LT = (NL + 15) / 16, T = 4 * QT;
-    extern __shared__ double2 sacc[];                 // [NL][2 Wsb^2]
+    extern __shared__ double2 sacc[];                 // [NL][2 Wsb^2], then [4][NL][NL] staging
     __shared__ double sXe[3][16 * QT];                // test element points (zero padded)
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int s = o.s, s2 = s * s, nsb = s / sb, Wsb = sb + o.p, nslot = 2 * Wsb * Wsb;
+    const int s = o.s, nsb = s / sb, Wsb = sb + o.p, nslot = 2 * Wsb * Wsb, P1 = o.p + 1;
+    double2 *sstage = sacc + NL * nslot;
+    // test elements and trial squares of this colour
+    const int n1 = (s - ce1 + P1 - 1) / P1, n2 = (s - ce2 + P1 - 1) / P1;
+    const int m1 = (nsb - cs1 + sstep - 1) / sstep, m2 = (nsb - cs2 + sstep - 1) / sstep;
     int64_t blk = blockIdx.x;
-    const int sub = (int)(blk % (nsb * nsb));
-    blk /= nsb * nsb;
-    const int ti = (int)(blk % s2);
-    const int64_t b = blk / s2;
+    const int sub = (int)(blk % (m1 * m2));
+    blk /= m1 * m2;
+    const int tc = (int)(blk % (n1 * n2));
+    const int64_t b = blk / (n1 * n2);
     const int lt = o.bpair[2 * b], ls = o.bpair[2 * b + 1];
     const int SL = o.SL;
     const int jt = lt / (SL * SL), jr = lt % (SL * SL), js = ls / (SL * SL), jsr = ls % (SL * SL);
-    const int tl1 = ti % s, tl2 = ti / s;                       // e inside its leaf
+    const int tl1 = ce1 + P1 * (tc % n1), tl2 = ce2 + P1 * (tc / n1);   // e inside its leaf
+    const int ti = tl2 * s + tl1;
     const int te1 = (jr % SL) * s + tl1, te2 = (jr / SL) * s + tl2;
-    const int sl1 = (sub % nsb) * sb, sl2 = (sub / nsb) * sb;   // trial square inside its leaf
+    const int sl1 = (cs1 + sstep * (sub % m1)) * sb, sl2 = (cs2 + sstep * (sub / m1)) * sb;   // trial square
     const int fx0 = (jsr % SL) * s + sl1, fy0 = (jsr / SL) * s + sl2;
     const int64_t e = ((int64_t)jt * o.n + te2) * o.n + te1;
     const int G2 = o.G2;
@@ -479,98 +471,142 @@ __global__ __launch_bounds__(256) void k_near_regular(DevOp o, int sb)
                     pa[c][u][t] = Fe[((c * LT + u) * T + t) * 64 + lane] * (c == 3 ? -ik2 : 1.0);
     }
     __syncthreads();
-    for (int fi = wv; fi < sb * sb; fi += 4) {
+    const int nfe = sb * sb, nround = (nfe + 3) / 4;
+    for (int rd = 0; rd < nround; ++rd) {
+        const int fi = 4 * rd + wv;
         const int fe1 = fx0 + fi % sb, fe2 = fy0 + fi / sb;
         const int64_t f = ((int64_t)js * o.n + fe2) * o.n + fe1;
-        if (share_corner(o, e, f)) continue;   // handled by the singular kernel
-        // kernel values as operand A: row q' = 16 qt + lane % 16, slot q = frag_q(t, lane)
-        double kre[QT][T], kim[QT][T];
-#pragma unroll
-        for (int qt = 0; qt < QT; ++qt) {
-            const int qb = 16 * qt + (lane & 15);
-            const bool okb = qb < G2;
-            double xb0 = 0.0, xb1 = 0.0, xb2 = 0.0;
-            if (okb) {
-                xb0 = o.eX[(f * 3 + 0) * G2 + qb];
-                xb1 = o.eX[(f * 3 + 1) * G2 + qb];
-                xb2 = o.eX[(f * 3 + 2) * G2 + qb];
-            }
-#pragma unroll
-            for (int t = 0; t < T; ++t) {
-                const int qa = frag_q(t, lane);
-                double2 K = make_double2(0.0, 0.0);
-                if (okb && qa < G2) {
-                    const double d0 = sXe[0][qa] - xb0, d1 = sXe[1][qa] - xb1, d2 = sXe[2][qa] - xb2;
-                    K = dm::helmholtz_r2(o.kappa, fma(d0, d0, fma(d1, d1, d2 * d2)));
-                }
-                kre[qt][t] = K.x;
-                kim[qt][t] = K.y;
-            }
-        }
+        // wave-uniform: trial element exists and shares no corner with e (those pairs
+        // come from the singular kernel)
+        const bool act = fi < nfe && !share_corner(o, e, f);
         dx4 br[LT][LT], bi[LT][LT];
+        if (act) {
 #pragma unroll
-        for (int u = 0; u < LT; ++u)
+            for (int u = 0; u < LT; ++u)
 #pragma unroll
-            for (int v = 0; v < LT; ++v) {
-                br[u][v] = dx4{0.0, 0.0, 0.0, 0.0};
-                bi[u][v] = dx4{0.0, 0.0, 0.0, 0.0};
-            }
-        const double *Ff = o.ePsiF + (size_t)f * FE;
+                for (int v = 0; v < LT; ++v) {
+                    br[u][v] = dx4{0.0, 0.0, 0.0, 0.0};
+                    bi[u][v] = dx4{0.0, 0.0, 0.0, 0.0};
+                }
+            // kernel values as operand A: row q' = 16 qt + lane % 16, slot q = frag_q(t, lane)
+            double kre[QT][T], kim[QT][T];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            dx4 yr[QT][LT], yi[QT][LT];
-#pragma unroll
-            for (int qt = 0; qt < QT; ++qt)
-#pragma unroll
-                for (int u = 0; u < LT; ++u) {
-                    yr[qt][u] = dx4{0.0, 0.0, 0.0, 0.0};
-                    yi[qt][u] = dx4{0.0, 0.0, 0.0, 0.0};
+            for (int qt = 0; qt < QT; ++qt) {
+                const int qb = 16 * qt + (lane & 15);
+                const bool okb = qb < G2;
+                double xb0 = 0.0, xb1 = 0.0, xb2 = 0.0;
+                if (okb) {
+                    xb0 = o.eX[(f * 3 + 0) * G2 + qb];
+                    xb1 = o.eX[(f * 3 + 1) * G2 + qb];
+                    xb2 = o.eX[(f * 3 + 2) * G2 + qb];
                 }
 #pragma unroll
-            for (int t = 0; t < T; ++t)
+                for (int t = 0; t < T; ++t) {
+                    const int qa = frag_q(t, lane);
+                    double2 K = make_double2(0.0, 0.0);
+                    if (okb && qa < G2) {
+                        const double d0 = sXe[0][qa] - xb0, d1 = sXe[1][qa] - xb1, d2 = sXe[2][qa] - xb2;
+                        K = dm::helmholtz_r2(o.kappa, fma(d0, d0, fma(d1, d1, d2 * d2)));
+                    }
+                    kre[qt][t] = K.x;
+                    kim[qt][t] = K.y;
+                }
+            }
+            const double *Ff = o.ePsiF + (size_t)f * FE;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                dx4 yr[QT][LT], yi[QT][LT];
 #pragma unroll
                 for (int qt = 0; qt < QT; ++qt)
 #pragma unroll
                     for (int u = 0; u < LT; ++u) {
-                        yr[qt][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(kre[qt][t], pa[c][u][t], yr[qt][u], 0, 0, 0);
-                        yi[qt][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(kim[qt][t], pa[c][u][t], yi[qt][u], 0, 0, 0);
+                        yr[qt][u] = dx4{0.0, 0.0, 0.0, 0.0};
+                        yi[qt][u] = dx4{0.0, 0.0, 0.0, 0.0};
                     }
 #pragma unroll
-            for (int v = 0; v < LT; ++v)
+                for (int t = 0; t < T; ++t)
 #pragma unroll
-                for (int qt = 0; qt < QT; ++qt)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const double pb = Ff[((c * LT + v) * T + 4 * qt + j) * 64 + lane];
+                    for (int qt = 0; qt < QT; ++qt)
 #pragma unroll
                         for (int u = 0; u < LT; ++u) {
-                            br[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(yr[qt][u][j], pb, br[u][v], 0, 0, 0);
-                            bi[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(yi[qt][u][j], pb, bi[u][v], 0, 0, 0);
+                            yr[qt][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(kre[qt][t], pa[c][u][t], yr[qt][u], 0, 0, 0);
+                            yi[qt][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(kim[qt][t], pa[c][u][t], yi[qt][u], 0, 0, 0);
                         }
-                    }
+#pragma unroll
+                for (int v = 0; v < LT; ++v)
+#pragma unroll
+                    for (int qt = 0; qt < QT; ++qt)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const double pb = Ff[((c * LT + v) * T + 4 * qt + j) * 64 + lane];
+#pragma unroll
+                            for (int u = 0; u < LT; ++u) {
+                                br[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(yr[qt][u][j], pb, br[u][v], 0, 0, 0);
+                                bi[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(yi[qt][u][j], pb, bi[u][v], 0, 0, 0);
+                            }
+                        }
+            }
         }
-        // rows l = 16 u + lane / 16 + 4 j, columns l' = 16 v + lane % 16
+        // rows l = 16 u + lane / 16 + 4 j, columns l' = 16 v + lane % 16 into this wave's
+        // staging block, then the four staged blocks are added in wave order
+        double2 *stg = sstage + (size_t)wv * NL * NL;
+        if (act) {
 #pragma unroll
-        for (int v = 0; v < LT; ++v) {
-            const int lb = 16 * v + (lane & 15);
-            if (lb >= NL) continue;
-            int a, t1, t2;
-            local_index(o.p, lb, a, t1, t2);
-            const int slot = a * Wsb * Wsb + (fe2 - fy0 + t2) * Wsb + (fe1 - fx0 + t1);
+            for (int v = 0; v < LT; ++v) {
+                const int lb = 16 * v + (lane & 15);
 #pragma unroll
-            for (int u = 0; u < LT; ++u)
+                for (int u = 0; u < LT; ++u)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int l = 16 * u + (lane >> 4) + 4 * j;
-                    if (l < NL) {
-                        atomicAdd(&sacc[l * nslot + slot].x, br[u][v][j]);
-                        atomicAdd(&sacc[l * nslot + slot].y, bi[u][v][j]);
+                    for (int j = 0; j < 4; ++j) {
+                        const int l = 16 * u + (lane >> 4) + 4 * j;
+                        if (l < NL && lb < NL) stg[l * NL + lb] = make_double2(br[u][v][j], bi[u][v][j]);
                     }
+            }
+        }
+        __syncthreads();
+        for (int w = 0; w < 4; ++w) {
+            const int fw = 4 * rd + w;
+            // uniform over the workgroup: whether wave w computed a pair this round
+            const bool aw = fw < nfe && !share_corner(o, e, ((int64_t)js * o.n + fy0 + fw / sb) * o.n + fx0 + fw % sb);
+            if (aw) {
+                const int q1 = fw % sb, q2 = fw / sb;
+                const double2 *sw = sstage + (size_t)w * NL * NL;
+                for (int i = threadIdx.x; i < NL * NL; i += blockDim.x) {
+                    const int l = i / NL, lb = i % NL;
+                    int a, t1, t2;
+                    local_index(o.p, lb, a, t1, t2);
+                    const int slot = a * Wsb * Wsb + (q2 + t2) * Wsb + (q1 + t1);
+                    const double2 v = sw[i];
+                    double2 &acc = sacc[l * nslot + slot];
+                    acc.x += v.x;
+                    acc.y += v.y;
                 }
+            }
+            __syncthreads();
         }
     }
-    __syncthreads();
-    const int W = o.W;
+    // element pairs of e with a shared corner whose trial element lies in the square
+    const int kb = o.sing_ptr[b * (int64_t)(s * s) + ti], ke = o.sing_ptr[b * (int64_t)(s * s) + ti + 1];
+    for (int k = kb; k < ke; ++k) {
+        const int64_t f = o.sing[k].f;
+        int jf, f1, f2;
+        elem_of(o, f, jf, f1, f2);
+        const int q1 = f1 - fx0, q2 = f2 - fy0;
+        if (q1 < 0 || q1 >= sb || q2 < 0 || q2 >= sb) continue;   // uniform over the workgroup
+        const double2 *P = o.sblk + (size_t)k * NL * NL;
+        for (int i = threadIdx.x; i < NL * NL; i += blockDim.x) {
+            const int l = i / NL, lb = i % NL;
+            int a, t1, t2;
+            local_index(o.p, lb, a, t1, t2);
+            const int slot = a * Wsb * Wsb + (q2 + t2) * Wsb + (q1 + t1);
+            const double2 v = P[i];
+            double2 &acc = sacc[l * nslot + slot];
+            acc.x += v.x;
+            acc.y += v.y;
+        }
+        __syncthreads();
+    }
+    const int W = o.W, nF = o.nF;
     for (int i = threadIdx.x; i < NL * nslot; i += blockDim.x) {
         const double2 v = sacc[i];
         if (v.x == 0.0 && v.y == 0.0) continue;
@@ -585,13 +621,36 @@ __global__ __launch_bounds__(256) void k_near_regular(DevOp o, int sb)
         int ar, t1, t2;
         local_index(o.p, l, ar, t1, t2);
         const int kr = leaf_slot(W, ar, tl1 + t1, tl2 + t2);
-        blk_add(o, b, lt, ls, kr, kc, v);
+        // signs of the glued unknowns folded in; slots without an unknown are skipped
+        const double sg = (double)o.leafsgn[(size_t)lt * nF + kr] * (double)o.leafsgn[(size_t)ls * nF + kc];
+        if (sg == 0.0) continue;
+        double2 *dst = o.bval + ((size_t)b * nF + kr) * nF + kc;   // the only writer in this launch
+        double2 cur = *dst;
+        cur.x += sg * v.x;
+        cur.y += sg * v.y;
+        *dst = cur;
     }
+}
+
+// the small rules (one or two 16-point tiles, up to 12 local functions) fit two
+// workgroups per CU without spilling; the others take all registers of one
+template <int NL, int QT>
+__global__ __launch_bounds__(256) void k_near_regular(DevOp o, int sb, int ce1, int ce2, int cs1, int cs2, int sstep)
+{
+    near_regular_body<NL, QT>(o, sb, ce1, ce2, cs1, cs2, sstep);
+}
+template <int NL, int QT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_near_regular_o2(DevOp o, int sb, int ce1,
+                                                                                                   int ce2, int cs1, int cs2,
+                                                                                                   int sstep)
+{
+    near_regular_body<NL, QT>(o, sb, ce1, ce2, cs1, cs2, sstep);
 }
 
 // ---------------------------------------------------------------------------
 // a1: element pairs sharing a corner (relative-coordinate / Duffy sub-rules),
-// one wavefront per pair; rows of the block are produced in chunks of RCH.
+// one wavefront per pair; each pair's NL x NL block is written to its own slot of a
+// scratch array (no accumulation here).
 // ---------------------------------------------------------------------------
 __device__ inline void frame_map(int code, double c1, double c2, double &x, double &y)
 {
@@ -737,8 +796,9 @@ __global__ __launch_bounds__(64) void k_near_singular(DevOp o, const SingularPai
                 }
         }
     }
-    // lane holds B[16 u + lane/16 + 4 j][16 v + lane % 16]
-    const int la = leaf_of(o, ja, a1, a2), lb_ = leaf_of(o, jb, b1, b2);
+    // lane holds B[16 u + lane/16 + 4 j][16 v + lane % 16]; the element-pair block goes
+    // to its own slot, added to the near-field block by k_near_regular in list order
+    double2 *dst = o.sblk + (size_t)blockIdx.x * NL * NL;
 #pragma unroll
     for (int u = 0; u < LT; ++u)
 #pragma unroll
@@ -746,9 +806,7 @@ __global__ __launch_bounds__(64) void k_near_singular(DevOp o, const SingularPai
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int l = 16 * u + (lane >> 4) + 4 * j, lb = 16 * v + (lane & 15);
-                if (l < NL && lb < NL)
-                    blk_add(o, sp.blk, la, lb_, elem_slot(o, a1, a2, l), elem_slot(o, b1, b2, lb),
-                            make_double2(br[u][v][j], bi[u][v][j]));
+                if (l < NL && lb < NL) dst[l * NL + lb] = make_double2(br[u][v][j], bi[u][v][j]);
             }
 }
 
@@ -1339,38 +1397,69 @@ size_t psi_fragment_doubles(int nl, int G2)
 
 namespace {
 template <int NL>
-void launch_near_regular_nl(ige_op op, dim3 grid, size_t shm, int sb)
+void launch_near_regular_nl(ige_op op, dim3 grid, size_t shm, int sb, int ce1, int ce2, int cs1, int cs2, int sstep)
 {
     const DevOp &o = op->view;
     hipStream_t s = lstream(op);
     switch ((o.G2 + 15) / 16) {
-        case 1: hipLaunchKernelGGL((k_near_regular<NL, 1>), grid, dim3(256), shm, s, o, sb); break;
-        case 2: hipLaunchKernelGGL((k_near_regular<NL, 2>), grid, dim3(256), shm, s, o, sb); break;
-        case 3: hipLaunchKernelGGL((k_near_regular<NL, 3>), grid, dim3(256), shm, s, o, sb); break;
-        default: hipLaunchKernelGGL((k_near_regular<NL, 4>), grid, dim3(256), shm, s, o, sb); break;
+        case 1:
+            if constexpr (NL <= 12) hipLaunchKernelGGL((k_near_regular_o2<NL, 1>), grid, dim3(256), shm, s, o, sb, ce1, ce2, cs1, cs2, sstep);
+            else hipLaunchKernelGGL((k_near_regular<NL, 1>), grid, dim3(256), shm, s, o, sb, ce1, ce2, cs1, cs2, sstep);
+            break;
+        case 2:
+            if constexpr (NL <= 12) hipLaunchKernelGGL((k_near_regular_o2<NL, 2>), grid, dim3(256), shm, s, o, sb, ce1, ce2, cs1, cs2, sstep);
+            else hipLaunchKernelGGL((k_near_regular<NL, 2>), grid, dim3(256), shm, s, o, sb, ce1, ce2, cs1, cs2, sstep);
+            break;
+        case 3: hipLaunchKernelGGL((k_near_regular<NL, 3>), grid, dim3(256), shm, s, o, sb, ce1, ce2, cs1, cs2, sstep); break;
+        default: hipLaunchKernelGGL((k_near_regular<NL, 4>), grid, dim3(256), shm, s, o, sb, ce1, ce2, cs1, cs2, sstep); break;
     }
 }
 }  // namespace
+
+// shared memory of k_near_regular: block rows of the test element over a trial
+// square of sb x sb elements, and four staged element-pair blocks
+size_t near_regular_shm(int sb, int p, int nl)
+{
+    return sizeof(double2) * ((size_t)nl * 2 * (sb + p) * (sb + p) + (size_t)4 * nl * nl);
+}
+
+int near_regular_sb(int s, int p, int nl)
+{
+    // trial squares of sb x sb elements: the largest power of two <= s that fits in
+    // 64 KB of shared memory
+    int sb = s;
+    while (sb > 1 && near_regular_shm(sb, p, nl) > 64 * 1024) sb /= 2;
+    return sb;
+}
 
 void launch_near_regular(ige_op op)
 {
     const DevOp &o = op->view;
     if (o.nblk == 0) return;
     IGE_REQUIRE(o.G2 <= 64, "regular near-field rule limited to 8 x 8 points");
-    // trial squares of sb x sb elements: the largest power of two <= s whose block
-    // rows fit in 48 KB of shared memory
-    int sb = o.s;
-    auto shm_of = [&](int q) { return sizeof(double2) * o.nl * 2 * (size_t)(q + o.p) * (q + o.p); };
-    while (sb > 1 && shm_of(sb) > 48 * 1024) sb /= 2;
+    const int sb = near_regular_sb(o.s, o.p, o.nl);
     const int nsb = o.s / sb;
-    const dim3 grid((unsigned)(o.nblk * o.s * o.s * nsb * nsb));
-    const size_t shm = shm_of(sb);
-    switch (o.p) {
-        case 1: launch_near_regular_nl<4>(op, grid, shm, sb); break;
-        case 2: launch_near_regular_nl<12>(op, grid, shm, sb); break;
-        default: launch_near_regular_nl<24>(op, grid, shm, sb); break;
-    }
-    IGE_LAUNCH_CHECK();
+    // colours: test elements p + 1 apart (a glued function spans at most p + 1
+    // elements per direction); with several trial squares per leaf, squares whose gap
+    // of (sstep - 1) sb elements is at least p
+    const int P1 = o.p + 1, sstep = nsb > 1 ? 1 + (o.p + sb - 1) / sb : 1;
+    const size_t shm = near_regular_shm(sb, o.p, o.nl);
+    for (int ce2 = 0; ce2 < std::min(P1, o.s); ++ce2)
+        for (int ce1 = 0; ce1 < std::min(P1, o.s); ++ce1)
+            for (int cs2 = 0; cs2 < std::min(sstep, nsb); ++cs2)
+                for (int cs1 = 0; cs1 < std::min(sstep, nsb); ++cs1) {
+                    const int64_t n1 = (o.s - ce1 + P1 - 1) / P1, n2 = (o.s - ce2 + P1 - 1) / P1;
+                    const int64_t m1 = (nsb - cs1 + sstep - 1) / sstep, m2 = (nsb - cs2 + sstep - 1) / sstep;
+                    const int64_t nwg = o.nblk * n1 * n2 * m1 * m2;
+                    if (nwg == 0) continue;
+                    const dim3 grid((unsigned)nwg);
+                    switch (o.p) {
+                        case 1: launch_near_regular_nl<4>(op, grid, shm, sb, ce1, ce2, cs1, cs2, sstep); break;
+                        case 2: launch_near_regular_nl<12>(op, grid, shm, sb, ce1, ce2, cs1, cs2, sstep); break;
+                        default: launch_near_regular_nl<24>(op, grid, shm, sb, ce1, ce2, cs1, cs2, sstep); break;
+                    }
+                    IGE_LAUNCH_CHECK();
+                }
 }
 
 void launch_near_singular(ige_op op)

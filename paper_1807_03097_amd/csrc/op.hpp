@@ -51,6 +51,12 @@ struct DevOp {
     const int8_t *leafsgn;    // [nleaf][nF]
     const int64_t *red_ptr;   // [N+1]
     const int32_t *red_idx;
+    // element pairs with a shared corner: the list, their blocks [nsing][nl][nl]
+    // (assembly scratch) and per (block, test element of the target leaf) the range of
+    // list entries [nblk][s^2 + 1]
+    const SingularPair *sing;
+    double2 *sblk;
+    const int32_t *sing_ptr;
     // cluster tree
     const int64_t *lvl_off;   // [L+2] first global cluster id of each level
     const double *nodeX;      // [NC][3][Q]
@@ -119,6 +125,8 @@ struct ige_op_s {
     ige::DBuf<double2> d_sctab;
     ige::DBuf<int32_t> d_inc;
     ige::DBuf<ige::SingularPair> d_sing;
+    ige::DBuf<double2> d_sblk;           // singular element-pair blocks (assembly only)
+    ige::DBuf<int32_t> d_sing_ptr;
     ige::DBuf<ige::M2LWork> d_work;
     ige::DBuf<int32_t> d_partner;       // source global cluster id per work entry
     ige::DBuf<int32_t> d_wrk_of_tgt;
@@ -213,6 +221,7 @@ size_t planned_device_bytes(const ige_op_s *op, int restart, int r, const ige_so
 void launch_element_data(ige_op op);
 void launch_node_geometry(ige_op op);
 void launch_near_regular(ige_op op);
+int near_regular_sb(int s, int p, int nl);
 // doubles of matrix-core operand data per element (see k_element_data)
 size_t psi_fragment_doubles(int nl, int G2);
 void launch_near_singular(ige_op op);

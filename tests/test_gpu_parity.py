@@ -541,3 +541,46 @@ def test_c2_full_size_sampled_rows(oracle_mod, ctx):
     err = _rel(y[rows], yo)
     _say(f"  C2 N={op.N} nnz={op.info.near_nnz} far={op.info.far_pairs} sampled rel.err={err:.2e}")
     assert err <= TOL
+
+
+# Assembly cases for the colour launches of the near-field quadrature: trial squares
+# smaller than the leaf (p = 3 with 8 x 8-element leaves: squares of 2 x 2, three
+# apart; p = 2 with 16 x 16-element leaves: squares of 8 x 8, two apart), and the
+# single-square cases of every degree.
+ASSEMBLY_CASES = [
+    ("sphere", 1, 3, 3.0, 6, 1.0, 1, 5, 5),
+    ("sphere", 2, 3, 5.0, 6, 1.0, 1, 5, 5),
+    ("torus", 2, 2, 6.0, 6, 1.0, 1, 5, 5),
+    ("sphere", 3, 3, 6.0, 6, 1.6, 3, 5, 4),
+    ("sphere", 2, 4, 8.0, 8, 1.6, 4, 5, 5),
+]
+
+
+@pytest.mark.parametrize("case", ASSEMBLY_CASES,
+                         ids=[f"{c[0]}-p{c[1]}-m{c[2]}-d{c[6]}" for c in ASSEMBLY_CASES])
+def test_assembly_is_bitwise_reproducible(oracle_mod, ctx, case):
+    """Two assemblies of the same operator give the same near-field blocks bit for
+    bit (every element-pair contribution is summed in a fixed order), hence the same
+    applies; the operator matches the oracle (Sec. 4.1 quadrature, Sec. 4.2 FMM)."""
+    from paper_1807_03097_amd import binding as B
+    name, p, m, kappa, q, eta, d, g, gs = case
+    _say(f"case {case}")
+    pats = _geom(name)
+    geom = B.Geometry(ctx, pats)
+    op1 = B.Operator(geom, p, m, kappa, q, eta, g, gs, d)
+    op2 = B.Operator(geom, p, m, kappa, q, eta, g, gs, d)
+    b1, b2 = op1.near_blocks(), op2.near_blocks()
+    assert b1.shape == b2.shape and np.count_nonzero(b1) > 0
+    assert np.array_equal(b1.view(np.uint64), b2.view(np.uint64))
+    x = W.random_coeffs(op1.N, 0)
+    y1, y2 = op1.apply(x), op2.apply(x)
+    assert np.array_equal(y1.view(np.uint64), y2.view(np.uint64))
+    X = np.stack([W.random_coeffs(op1.N, s) for s in range(1, 10)])
+    assert np.array_equal(op1.apply(X).view(np.uint64), op2.apply(X).view(np.uint64))
+    o = oracle_mod.Oracle(pats, p, m, kappa, g=g, gs=gs)
+    yo = o.fmm_apply(x, q, eta, d)
+    err = _rel(y1, yo)
+    _say(f"  N={op1.N} blocks={op1.info.near_leaf_pairs} sing={op1.info.singular_pairs} err={err:.2e}")
+    assert err <= TOL
+    op1.close()
+    op2.close()
