@@ -338,6 +338,18 @@ int ige_srv_destroy(ige_srv srv);
  * host memory.  Synchronous; uses temporary device memory (E * g^2 * 88 bytes). */
 int ige_potential(ige_op op, int r, const ige_c64 *w, int ptr_kind, int npts, const double *points, ige_c64 *E);
 
+/* ige_potential for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same kernels
+ * and results, with the per-element source data in a fixed device array of the
+ * library (64 MiB per device, held until the process ends) instead of temporary
+ * memory.  w [r][N], points [npts][3] and E [r][npts][3] are device memory of the
+ * context's device; the call is ordered on the context's stream and returns before
+ * the work completes; it calls no hipMalloc/hipFree and makes no host copy (points
+ * are not checked for NaN).  IGE_EINVAL if the operator's source data,
+ * elements * g^2 * 88 bytes, exceed 64 MiB.  Calls that overlap on one device (two
+ * streams, or two host threads) race on that array. */
+int ige_potential_noalloc(ige_op op, int r, const ige_c64 *w, int npts, const double *points, ige_c64 *E);
+
 /* Diagnostic: evaluate on the context's device the Helmholtz kernel
  * G_k(r) = e^{ikr}/(4 pi r) (Sec. 2.2, eq. (eq:HelmholtzGreen)) exactly as the
  * coupling stage does in precision prec (IGE_F64: reciprocal square root with two

@@ -96,6 +96,7 @@ _SIGS = {
     "ige_solve": (C.c_int, [_V, C.c_int, _V, _V, C.c_int, C.POINTER(ige_solve_opts), _V]),
     "ige_helmholtz_eval": (C.c_int, [_V, C.c_int64, C.c_double, _V, _V, C.c_int]),
     "ige_potential": (C.c_int, [_V, C.c_int, _V, C.c_int, C.c_int, _V, _V]),
+    "ige_potential_noalloc": (C.c_int, [_V, C.c_int, _V, C.c_int, _V, _V]),
     "ige_srv_create": (C.c_int, [_V, C.c_int, C.c_size_t, C.POINTER(_V)]),
     "ige_srv_submit": (C.c_int, [_V, _V, C.POINTER(ige_params), _V, _V, C.POINTER(ige_solve_opts),
                                  C.POINTER(C.c_int64)]),
@@ -361,6 +362,15 @@ class Operator:
         out = np.zeros((r, len(points), 3), np.complex128)
         _check(_lib.ige_potential(self.h, r, _ptr(w), _kind(w), len(points), _ptr(points), _ptr(out)))
         return out[0] if w.ndim == 1 else out
+
+    def potential_noalloc(self, w, points, out):
+        """ige_potential_noalloc: w [N] or [r][N], points [npts][3] (float64) and out
+        [npts][3] or [r][npts][3] (complex128), all torch tensors on the context's
+        device; ordered on the context's stream"""
+        r = 1 if w.ndim == 1 else w.shape[0]
+        npts = points.shape[0]
+        _check(_lib.ige_potential_noalloc(self.h, r, _ptr(w), npts, _ptr(points), _ptr(out)))
+        return out
 
     def autotune(self, r, prec=IGE_F64):
         """time the candidate tile shapes of the r-column apply and keep the fastest;

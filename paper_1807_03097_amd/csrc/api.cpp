@@ -169,6 +169,7 @@ int ige_ctx_create(int device, void *hip_stream, ige_ctx *out)
         c->device = device;
         try {
             IGE_HIP(hipSetDevice(device));
+            ige::potential_scratch_init(device);
             if (hip_stream) {
                 c->stream = (hipStream_t)hip_stream;
             } else {
@@ -1476,6 +1477,28 @@ int ige_potential(ige_op op, int r, const ige_c64 *w, int ptr_kind, int npts, co
                                        hipMemcpyDeviceToHost, s));
         }
         IGE_HIP(hipStreamSynchronize(s));
+    });
+}
+
+int ige_potential_noalloc(ige_op op, int r, const ige_c64 *w, int npts, const double *points, ige_c64 *E)
+{
+    return guard([&] {
+        IGE_REQUIRE(op && w && r >= 1 && npts >= 0 && (npts == 0 || (points && E)), "bad potential arguments");
+        IGE_REQUIRE(op->assembled, "operator was planned, not assembled");
+        const size_t need = ige::potential_source_doubles(op);
+        const size_t cap = ige::potential_scratch_doubles();
+        if (need > cap)
+            throw ige::Status{IGE_EINVAL, "operator too large for the fixed potential scratch: " +
+                                              std::to_string(need * 8) + " bytes of source data > " +
+                                              std::to_string(cap * 8)};
+        set_device(op->ctx);
+        double *scr = ige::potential_scratch(op->ctx->device);
+        IGE_REQUIRE(scr != nullptr, "potential scratch not set up on this device");
+        const int64_t N = op->D.N;
+        const double2 *W = reinterpret_cast<const double2 *>(w);
+        double2 *out = reinterpret_cast<double2 *>(E);
+        for (int c = 0; c < r; ++c)
+            ige::launch_potential(op, W + (size_t)c * N, npts, points, out + (size_t)c * 3 * npts, scr);
     });
 }
 

@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
+#include <vector>
 
 #include "device_math.hpp"
 #include "op.hpp"
@@ -1681,6 +1683,40 @@ __global__ __launch_bounds__(256) void k_potential(int64_t nsrc, double kappa, c
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// Fixed device scratch of ige_potential_noalloc: the per-element source data of the
+// potential (kPotStride doubles per Gauss point of every element), at most
+// kPotScratchDoubles doubles (64 MiB).  Every device the library runs on holds its
+// own copy until the process ends.  Host code never passes the symbol itself: its
+// device address is looked up once per device (potential_scratch_init, with that
+// device current) and kept per device ordinal.
+// ---------------------------------------------------------------------------
+constexpr size_t kPotScratchDoubles = (size_t)8 << 20;
+static __device__ __align__(256) double scratch[kPotScratchDoubles];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<double *> g_scratch_ptr;   // device address of scratch per device ordinal
+}  // namespace
+
+void potential_scratch_init(int device)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= device) g_scratch_ptr.resize((size_t)device + 1, nullptr);
+    if (g_scratch_ptr[device]) return;
+    void *ptr = nullptr;
+    IGE_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[device] = static_cast<double *>(ptr);
+}
+
+double *potential_scratch(int device)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return device >= 0 && device < (int)g_scratch_ptr.size() ? g_scratch_ptr[device] : nullptr;
+}
+
+size_t potential_scratch_doubles() { return kPotScratchDoubles; }
 
 size_t potential_source_doubles(ige_op op) { return (size_t)op->view.P * op->view.n * op->view.n * op->view.G2 * kPotStride; }
 

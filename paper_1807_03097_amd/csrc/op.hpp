@@ -270,6 +270,11 @@ void launch_l2p_gather(ige_op op, double2 *y);
 // scattered field at npts points (device arrays; src: potential_source_doubles scratch)
 size_t potential_source_doubles(ige_op op);
 void launch_potential(ige_op op, const double2 *w, int npts, const double *pts, double2 *out, double *src);
+// fixed scratch of the allocation-free potential: address lookup (once per device, with
+// that device current), the device address (nullptr before the lookup), capacity
+void potential_scratch_init(int device);
+double *potential_scratch(int device);
+size_t potential_scratch_doubles();
 void launch_rhs_plane(ige_op op, const double *dir, double2 pol0, double2 pol1, double2 pol2, double2 *f);
 // GMRES vector kernels (V: [k][r][n], vectors [r][n]; gate/run/flag: per-column int masks)
 struct GsPlan {
