@@ -46,7 +46,9 @@ def parse():
     ap.add_argument("--leaf-depth", type=int, default=3)
     ap.add_argument("--level", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=16, help="rows of the bounded oracle sample")
+    ap.add_argument("--cpu-rows", type=int, default=64, help="rows of the larger bounded oracle sample")
+    ap.add_argument("--no-solve", action="store_true",
+                    help="matvec mode: skip the batched-solve leg (level 6, kappa 16, 64 plane waves)")
     ap.add_argument("--nrhs", type=int, default=1, help="right-hand sides per apply (batched kernels when > 1)")
     ap.add_argument("--prec", type=int, default=0, choices=(0, 1, 2, 3, 4),
                     help="coupling precision: 0 FP64, 1 FP32, 2 BF16 matrix cores, 3 split BF16 (3 products), "
@@ -89,33 +91,72 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def load_traffic(r):
-    """HBM bytes per launch of the block pass from the committed counter summary,
-    valid only while the kernel source is the one the counters were taken on."""
+def load_traffic(r, kernel):
+    """HBM bytes per launch of the near-field product from the committed counter
+    summary, valid only while the source file of that kernel is the one the counters
+    were taken on."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_near_blk_sphere_l5_p2_traffic.json")
-    src = os.path.join(ROOT, "paper_1807_03097_amd", "csrc", "kernels.hip")
-    if r != 1 or not os.path.exists(path):
+    files = {"k_near_cmp": ("k_near_cmp_sphere_l5_p2_traffic.json", "near_once.hip"),
+             "k_near_blk": ("k_near_blk_sphere_l5_p2_traffic.json", "kernels.hip")}
+    if r != 1 or kernel not in files:
+        return None
+    path = os.path.join(ROOT, "profiles", files[kernel][0])
+    src = os.path.join(ROOT, "paper_1807_03097_amd", "csrc", files[kernel][1])
+    if not os.path.exists(path):
         return None
     ref = json.load(open(path))
     h = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    return ref["traffic_bytes"] if ref.get("kernels_hip_sha256") == h else None
+    return ref["traffic_bytes"] if ref.get("source_sha256", ref.get("kernels_hip_sha256")) == h else None
+
+
+def host_cpu():
+    """model, physical cores and thread settings of the host (CPU baseline disclosure)"""
+    model, phys = None, set()
+    try:
+        cur = {}
+        for line in open("/proc/cpuinfo"):
+            if ":" not in line:
+                if cur:
+                    phys.add((cur.get("physical id"), cur.get("core id")))
+                cur = {}
+                continue
+            k, v = [t.strip() for t in line.split(":", 1)]
+            cur[k] = v
+            if k == "model name" and model is None:
+                model = v
+        if cur:
+            phys.add((cur.get("physical id"), cur.get("core id")))
+    except OSError:
+        pass
+    return {"model": model, "physical_cores": len(phys) or None, "logical_cpus": os.cpu_count(),
+            "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS"), "OMP_PROC_BIND": os.environ.get("OMP_PROC_BIND")}
 
 
 def cpu_baseline(pats, p, m, kappa, q, eta, d, x, rows):
-    """The oracle, as it stands, on a bounded sample of rows of the same operator."""
+    """The oracle, as it stands, on a bounded sample of the same operator: complete
+    rows of A_q x for two sample sizes, the fixed cost (the whole-mesh moment pass)
+    and the cost per row fitted to them, and the full apply extrapolated to N rows."""
     import numpy as np
     from oracle import oracle as O
 
     o = O.Oracle(pats, p, m, kappa, g=5, gs=5)
     tree = o.block_tree(eta, d)
-    sel = np.unique(np.linspace(0, o.N - 1, rows).astype(int))
-    t0 = time.perf_counter()
-    y = o.fmm_apply(x, q, eta, d, rows=sel, tree=tree)
-    dt = time.perf_counter() - t0
-    return {"value": len(sel) / dt, "unit": "DOF/s", "cores": int(O.lib().or_num_threads()), "kind": "oracle",
-            "sample": f"{len(sel)} evenly spaced rows of the same A_q x (complete rows incl. the fixed "
-                      f"whole-mesh moment pass), {dt:.1f} s"}, sel, y
+    times, ys = [], []
+    for nr in (max(1, rows // 4), rows):
+        sel = np.unique(np.linspace(0, o.N - 1, nr).astype(int))
+        t0 = time.perf_counter()
+        y = o.fmm_apply(x, q, eta, d, rows=sel, tree=tree)
+        times.append((len(sel), time.perf_counter() - t0))
+        ys.append((sel, y))
+    (n1, t1), (n2, t2) = times
+    per_row = max((t2 - t1) / (n2 - n1), 1e-12)
+    fixed = max(t1 - n1 * per_row, 0.0)
+    t_full = fixed + o.N * per_row
+    return {"value": o.N / t_full, "unit": "DOF/s", "cores": int(O.lib().or_num_threads()), "kind": "oracle",
+            "sample": f"complete rows of the same A_q x: {n1} rows in {t1:.2f} s and {n2} rows in {t2:.2f} s; "
+                      f"fixed cost {fixed:.2f} s + {per_row * 1e3:.1f} ms per row, extrapolated to the "
+                      f"{o.N} rows of one apply ({t_full:.0f} s)",
+            "extrapolated": True, "host": host_cpu()}, ys[-1][0], ys[-1][1]
 
 
 def serve_requests(n, seed, waves=1, sphere_only=False):
@@ -213,6 +254,59 @@ def run_solve(args):
     op.close()
     geom.close()
     ctx.close()
+
+
+def solve_leg(level=6, kappa=16.0, nrhs=64, tol=1e-6, restart=300, inner_prec=4, eta=1.6, d=3):
+    """The batched-solve configuration: cube-sphere, level 6, p = 2, kappa = 16, q = 8,
+    64 Fibonacci plane waves (theta polarisation), GMRES to a relative residual of 1e-6,
+    refined (FP64 residuals around split-BF16 inner solves) and plain FP64; solves/s of
+    both, the true FP64 residuals, the difference of the two solutions and the residual
+    of that difference (at most the sum of the two residuals: the tolerance-aware bound
+    on solutions that agree only to about tol * cond(A))."""
+    import numpy as np
+
+    from paper_1807_03097_amd import binding as B
+    from paper_1807_03097_amd import workloads as W
+
+    ctx = B.Context(0)
+    geom = B.Geometry(ctx, W.cube_sphere())
+    t0 = time.perf_counter()
+    op = B.Operator(geom, 2, level, kappa, 8, eta, 5, 5, d)
+    t_asm = time.perf_counter() - t0
+    dirs, pols = W.fibonacci_plane_waves(nrhs)
+    F = op.rhs_plane_wave(dirs, pols)
+    t1 = time.perf_counter()
+    tuned = {str(pr): op.autotune(nrhs, pr) for pr in (0, inner_prec)}
+    t_tune = time.perf_counter() - t1
+    runs, sols = {}, {}
+    for name, refine in (("refined", True), ("fp64", False)):
+        t2 = time.perf_counter()
+        X, st, rc = op.solve(F, tol=tol, restart=restart, maxit=6000, refine=refine, inner_tol=1e-4,
+                             inner_prec=inner_prec)
+        dt = time.perf_counter() - t2
+        sols[name] = X
+        runs[name] = {"seconds": dt, "solves_per_s": nrhs / dt, "rc": rc, "iters_max": max(c[0] for c in st),
+                      "relres_fp64_max": max(c[2] for c in st)}
+        log(f"solve leg {name}: {dt:.2f} s ({nrhs / dt:.2f} solves/s), iterations <= {runs[name]['iters_max']}, "
+            f"max FP64 relres {runs[name]['relres_fp64_max']:.2e}")
+    Dx = sols["refined"] - sols["fp64"]
+    AD = op.apply(np.ascontiguousarray(Dx))
+    diff = max(float(np.linalg.norm(Dx[c]) / np.linalg.norm(sols["fp64"][c])) for c in range(nrhs))
+    res_diff = max(float(np.linalg.norm(AD[c]) / np.linalg.norm(F[c])) for c in range(nrhs))
+    bound = runs["refined"]["relres_fp64_max"] + runs["fp64"]["relres_fp64_max"]
+    log(f"solve leg: refined vs FP64 solutions {diff:.2e}; residual of the difference {res_diff:.2e} "
+        f"(bound {bound:.2e}); implied cond(A) >= {diff / max(res_diff, 1e-300):.0f}")
+    out = {"workload": f"cube-sphere level {level}, p=2, N={op.N}, kappa={kappa}, q=8, eta={eta}, d={d}, "
+                       f"{nrhs} Fibonacci plane waves, GMRES tol {tol}, restart {restart}, "
+                       f"refined inner precision {PREC_NAMES[inner_prec]}",
+           "assemble_s": t_asm, "autotune_s": t_tune, "autotuned": tuned, "refined": runs["refined"],
+           "fp64": runs["fp64"], "speedup_refined_over_fp64": runs["fp64"]["seconds"] / runs["refined"]["seconds"],
+           "refined_vs_fp64_max_rel_diff": diff, "residual_of_difference_max": res_diff,
+           "residual_bound": bound, "difference_within_bound": bool(res_diff <= 1.01 * bound)}
+    op.close()
+    geom.close()
+    ctx.close()
+    return out
 
 
 def run_serving(args):
@@ -362,7 +456,8 @@ def main():
         + f"  step={ms_step:.4f} ms wall/step={1e3 * wall / args.steps:.4f}")
 
     # roofline of the dominant kernel (durations from the timed region)
-    traffic_ref = load_traffic(r)
+    near_once = r == 1 and info.near_distinct > 0 and os.environ.get("IGE_NEAR_COMPACT", "1") != "0"
+    traffic_ref = load_traffic(r, "k_near_cmp" if near_once else "k_near_blk")
 
     Qc = (q + 1) ** 2
     Qpc = 32 * ((Qc + 31) // 32)
@@ -428,6 +523,17 @@ def main():
                 Qn = 32 * ((nF + 31) // 32)
                 out["issued_flop"] = info.near_leaf_pairs * (-(-r // 64)) * 2.0 * (2 * Qn) ** 2 * 64
             return out
+        if dom == "near_spmv" and near_once:
+            # the method's bytes: every distinct entry of the symmetric near-field matrix
+            # (16 B) once, x read and y written once
+            alg = info.near_distinct * 16 + 2 * N * 16
+            t_ms = stage_ms["near_blk"]
+            achieved = alg / (t_ms * 1e-3) / 1e9
+            return {"kernel": "k_near_cmp", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_ref,
+                    "traffic_over_algorithmic": None if traffic_ref is None else traffic_ref / alg,
+                    "algorithmic_bytes": int(alg), "near_distinct_entries": int(info.near_distinct),
+                    "avg_ms": t_ms}
         if dom == "near_spmv":
             # the block pass: stored block entries (16 B each) streamed once per pass
             # of up to 4 columns, x read once per column
@@ -482,6 +588,13 @@ def main():
         parity = float(np.linalg.norm(yh[sel] - yo) / np.linalg.norm(yo))
         log(f"cpu baseline {cpu['value']:.1f} DOF/s on {cpu['cores']} threads; sampled rel.err vs oracle {parity:.2e}")
 
+    solve = None
+    if not args.no_solve and args.level == 5 and r == 1 and args.prec == 0:
+        op.close()
+        geom.close()
+        ctx.close()
+        op = geom = ctx = None
+        solve = solve_leg()
     out = {
         "metric": "EFIE FMM matvec DOF/s",
         "value": N * r / (ms_step * 1e-3),
@@ -513,11 +626,12 @@ def main():
         "stage_ms_isolated": st_iso,
         "cpu_baseline": cpu,
         "parity_sampled_rel_err": parity,
+        "solve_c3": solve,
     }
     print(json.dumps(out), flush=True)
-    op.close()
-    geom.close()
-    ctx.close()
+    for h in (op, geom, ctx):
+        if h is not None:
+            h.close()
 
 
 if __name__ == "__main__":

@@ -127,13 +127,16 @@ int ige_op_plan(ige_geom geom, const ige_params *params, ige_op *out);
 typedef struct {
     int64_t n_dof;          /* N glued unknowns */
     int64_t n_elements;     /* P 4^m */
-    int64_t near_nnz;       /* stored near-field entries */
+    int64_t near_nnz;       /* stored near-field entries of the leaf-pair blocks */
     int64_t far_pairs;      /* admissible (ordered) cluster pairs */
     int64_t near_leaf_pairs;
     int64_t singular_pairs; /* element pairs that share a corner */
     int32_t leaf_level, q;
     int64_t device_bytes;   /* device memory held by the operator */
     double assemble_ms;     /* wall time of ige_op_assemble */
+    int64_t near_distinct;  /* distinct entries of the symmetric near-field matrix in the
+                               glued basis (i <= j): the values the product of one column
+                               streams (each once) */
 } ige_op_info_t;
 int ige_op_info(ige_op op, ige_op_info_t *out);
 

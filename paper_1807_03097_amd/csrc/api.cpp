@@ -251,6 +251,12 @@ void plan(ige_op op, const ige_geom_s *geom, ige::NearBlocks &A, std::vector<ige
     if (const char *e = std::getenv("IGE_NEAR_CHUNKS")) nch = std::max(1, std::min(64, std::atoi(e)));
     ige::build_near_blocks(A, op->D, op->T, nch);
     op->nnz = A.nblk() * A.nF * A.nF;
+    // rows per work item of the once-per-entry product (tuning knob IGE_NEAR_ROWS,
+    // default 128, at most 128)
+    int nrows = 128;
+    if (const char *e = std::getenv("IGE_NEAR_ROWS")) nrows = std::max(8, std::min(128, std::atoi(e)));
+    ige::build_near_compact(op->cmp, op->D, op->T, A, nrows);
+    if (const char *e = std::getenv("IGE_NEAR_RS")) op->cmp_rs = std::atoi(e) == 4 ? 4 : 2;
     std::vector<double> corners;
     ige::build_singular_pairs(sing, corners, geom->G, op->D, op->T, A);
     op->nsing = (int64_t)sing.size();
@@ -277,6 +283,11 @@ size_t ige::planned_device_bytes(const ige_op_s *op, int restart, int r, const i
     const size_t nfp = op->T.far.size() / 2, Qp = 32 * (((size_t)Q + 31) / 32), Qn = 32 * (((size_t)nF + 31) / 32);
     size_t b = 0;
     b += (size_t)op->nnz * 16;                                   // near-field blocks
+    {   // the near field once per distinct entry, its lists and partial results
+        const ige::NearCompact &C = op->cmp;
+        b += (size_t)C.nval * 16 + (size_t)C.npart * 16 + C.idx.size() * 4 + C.red_idx.size() * 4 +
+             C.red_ptr.size() * 8 + C.occ.size() * 4 + C.wsub.size() * 40;
+    }
     b += (size_t)nblk * nF * 3 * 16 * R;                         // partial results (2 row chunks)
     b += (size_t)E * (3 + 4 * nl) * G2 * 8 + (size_t)E * psi_fragment_doubles(nl, G2) * 8 + (size_t)E * 96;
     b += (size_t)op->NC * Q * (9 * 8 + 11 * 16 * R);             // node data, moments, fields
@@ -431,6 +442,47 @@ ige_op ige::assemble_on(ige_ctx ctx, const ige_geom_s *geom, const ige_params &p
             // slots summed into the blocks in a fixed order (colour by colour)
             ige::launch_near_singular(op);
             ige::launch_near_regular(op);
+            // the same near field once per distinct entry, for the product of one column
+            // (IGE_NEAR_COMPACT=0 keeps the leaf-pair blocks for it)
+            {
+                const ige::NearCompact &C = op->cmp;
+                bool on = C.nsub() > 0 && C.maxn <= ige::near_cmp_max();
+                if (const char *e = std::getenv("IGE_NEAR_COMPACT")) on = on && std::atoi(e) != 0;
+                op->cmp_on = on;
+                if (on) {
+                    std::vector<int4> wk(C.wsub.size());
+                    for (size_t w = 0; w < wk.size(); ++w) wk[w] = make_int4(C.wsub[w], C.wr0[w], C.wr1[w], 0);
+                    op->d_cnr.upload(C.nr, s);
+                    op->d_cnc.upload(C.nc, s);
+                    op->d_cld.upload(C.ld, s);
+                    op->d_csym.upload(C.sym, s);
+                    op->d_cvoff.upload(C.val, s);
+                    op->d_clst.upload(C.lst, s);
+                    op->d_cidx.upload(C.idx, s);
+                    op->d_cwork.upload(wk, s);
+                    op->d_cwpart.upload(C.wpart, s);
+                    op->d_corder.upload(C.worder, s);
+                    op->d_cred_ptr.upload(C.red_ptr, s);
+                    op->d_cred_idx.upload(C.red_idx, s);
+                    op->d_cocc_ptr.upload(C.occ_ptr, s);
+                    op->d_cocc.upload(C.occ, s);
+                    op->d_cnp_ptr.upload(C.np_ptr, s);
+                    op->d_cnp_leaf.upload(C.np_leaf, s);
+                    op->d_cnp_code.upload(C.np_code, s);
+                    op->d_cval.alloc(std::max<int64_t>(1, C.nval));
+                    op->d_cpart.alloc(std::max<int64_t>(1, C.npart));
+                    ige::NearCmpView &cv = op->cview;
+                    cv.nsub = C.nsub();
+                    cv.nwork = (int64_t)C.wsub.size();
+                    cv.nr = op->d_cnr.p; cv.nc = op->d_cnc.p; cv.ld = op->d_cld.p; cv.sym = op->d_csym.p;
+                    cv.val_off = op->d_cvoff.p; cv.lst = op->d_clst.p; cv.idx = op->d_cidx.p;
+                    cv.val = op->d_cval.p; cv.work = op->d_cwork.p; cv.wpart = op->d_cwpart.p;
+                    cv.order = op->d_corder.p;
+                    cv.occ_ptr = op->d_cocc_ptr.p; cv.occ = op->d_cocc.p;
+                    cv.np_ptr = op->d_cnp_ptr.p; cv.np_leaf = op->d_cnp_leaf.p; cv.np_code = op->d_cnp_code.p;
+                    ige::launch_near_merge(op);
+                }
+            }
             // cluster tree and far field
             op->d_lvl_off.upload(op->lvl_off, s);
             v.lvl_off = op->d_lvl_off.p;
@@ -664,6 +716,7 @@ int ige_op_info(ige_op op, ige_op_info_t *out)
         r.n_dof = op->D.N;
         r.n_elements = (int64_t)op->D.P * op->D.n * op->D.n;
         r.near_nnz = op->nnz;
+        r.near_distinct = op->cmp.distinct;
         r.far_pairs = (int64_t)op->T.far.size();
         r.near_leaf_pairs = (int64_t)op->T.near.size();
         r.singular_pairs = op->nsing;
@@ -685,6 +738,10 @@ int ige_op_info(ige_op op, ige_op_info_t *out)
         b += op->d_Mp.bytes() * 3 + op->d_inc.bytes() + op->d_sing.bytes() + op->d_work.bytes();
         b += op->d_partner.bytes() + op->d_mom.bytes() + op->d_src.bytes() + op->d_loc.bytes() + op->d_part.bytes();
         b += op->d_x.bytes() + op->d_y.bytes() + op->d_V.bytes() + op->d_w.bytes() + op->d_r.bytes();
+        b += op->d_cnr.bytes() + op->d_cnc.bytes() + op->d_cld.bytes() + op->d_cidx.bytes() + op->d_corder.bytes() + op->d_cred_idx.bytes();
+        b += op->d_cocc_ptr.bytes() + op->d_cocc.bytes() + op->d_cnp_ptr.bytes() + op->d_cnp_leaf.bytes();
+        b += op->d_cnp_code.bytes() + op->d_csym.bytes() + op->d_cvoff.bytes() + op->d_clst.bytes();
+        b += op->d_cwpart.bytes() + op->d_cred_ptr.bytes() + op->d_cwork.bytes() + op->d_cval.bytes() + op->d_cpart.bytes();
         r.device_bytes = (int64_t)b;
         r.assemble_ms = op->assemble_ms;
         *out = r;

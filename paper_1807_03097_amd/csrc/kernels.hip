@@ -1562,6 +1562,15 @@ void launch_spmv(ige_op op, const double2 *x, double2 *y, hipStream_t st, hipEve
         if (mid) IGE_HIP(hipEventRecord(mid, st));
         return;
     }
+    if (op->cmp_on) {
+        double2 *part = op->d_cpart.p;
+        launch_near_once(op, x, part, st);
+        if (mid) IGE_HIP(hipEventRecord(mid, st));
+        hipLaunchKernelGGL(k_near_gather, dim3((unsigned)(((int64_t)o.N * 16 + 255) / 256)), dim3(256), 0, st, o.N,
+                           op->d_cred_ptr.p, op->d_cred_idx.p, part, y);
+        IGE_LAUNCH_CHECK();
+        return;
+    }
     const dim3 grid((unsigned)(o.nblk * o.nch)), blk(256);
     double2 *part = op->d_npart.p;
     switch (near_blk_u(o.nF)) {

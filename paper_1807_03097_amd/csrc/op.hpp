@@ -70,6 +70,20 @@ struct DevOp {
     int *err;                 // assembly consistency counter (entries outside the pattern)
 };
 
+// Device view of the near field stored once per distinct entry (NearCompact).
+struct NearCmpView {
+    int64_t nsub, nwork;
+    const int32_t *nr, *nc, *ld;
+    const int8_t *sym;
+    const int64_t *val_off, *lst;
+    const int32_t *idx;
+    double2 *val;
+    const int4 *work;          // (rectangle, r0, r1, 0)
+    const int64_t *wpart;      // first partial result of each work item
+    const int32_t *order;      // launch order of the work items
+    const int32_t *occ_ptr, *occ, *np_ptr, *np_leaf, *np_code;
+};
+
 struct M2LWork {
     int32_t tgt;      // global cluster id
     int32_t beg, end; // range in the partner array
@@ -120,6 +134,16 @@ struct ige_op_s {
     ige::DBuf<int64_t> d_red_ptr;
     ige::DBuf<double2> d_bval;
     ige::DBuf<double2> d_npart;        // near-field partial results [nslots]
+    // near field stored once per distinct entry (product of one column)
+    ige::NearCompact cmp;
+    bool cmp_on = false;
+    int cmp_rs = 2;                      // rows per step of its product (2 or 4)
+    ige::NearCmpView cview{};
+    ige::DBuf<int32_t> d_cnr, d_cnc, d_cld, d_cidx, d_corder, d_cred_idx, d_cocc_ptr, d_cocc, d_cnp_ptr, d_cnp_leaf, d_cnp_code;
+    ige::DBuf<int8_t> d_csym;
+    ige::DBuf<int64_t> d_cvoff, d_clst, d_cwpart, d_cred_ptr;
+    ige::DBuf<int4> d_cwork;
+    ige::DBuf<double2> d_cval, d_cpart;
     ige::DBuf<int64_t> d_lvl_off;
     ige::DBuf<double> d_nodeX, d_nodeT, d_xn, d_T0, d_T1, d_Mp, d_Mq, d_Mdp;
     ige::DBuf<double2> d_sctab;
@@ -225,6 +249,12 @@ int near_regular_sb(int s, int p, int nl);
 // doubles of matrix-core operand data per element (see k_element_data)
 size_t psi_fragment_doubles(int nl, int G2);
 void launch_near_singular(ige_op op);
+// values of the once-per-entry near field from the leaf-pair blocks (fixed order)
+void launch_near_merge(ige_op op);
+// largest rectangle side the once-per-entry product supports
+int near_cmp_max();
+// its row and column sums into part (one column)
+void launch_near_once(ige_op op, const double2 *x, double2 *part, hipStream_t st);
 // apply pieces (one right-hand side)
 void launch_p2m(ige_op op, const double2 *x);
 void launch_m2m(ige_op op);

@@ -567,6 +567,189 @@ void build_near_blocks(NearBlocks &B, const Discretisation &D, const Partition &
 }
 
 // ---------------------------------------------------------------------------
+// near field stored once per distinct entry (owner blocks split into dense rectangles)
+// ---------------------------------------------------------------------------
+void build_near_compact(NearCompact &C, const Discretisation &D, const Partition &T, const NearBlocks &B,
+                        int rows_per_item)
+{
+    C = NearCompact{};
+    const int p = D.p, n = D.n, nb = D.nb, s = T.s, SL = 1 << T.L, nF = B.nF;
+    const int nleaf = D.P * SL * SL;
+    const int64_t N = D.N;
+    // owner leaf of every unknown: leaf of the last element of its support at its first
+    // incarnation in canonical order
+    std::vector<int32_t> own((size_t)N, -1);
+    for (int j = 0; j < D.P; ++j)
+        for (int a = 0; a < 2; ++a) {
+            const int n1 = a == 0 ? n + p : n + p - 1, n2 = a == 0 ? n + p - 1 : n + p;
+            for (int i2 = 0; i2 < n2; ++i2)
+                for (int i1 = 0; i1 < n1; ++i1) {
+                    const int32_t g = D.dof[(((size_t)j * 2 + a) * nb + i2) * nb + i1];
+                    if (g < 0 || own[g] >= 0) continue;
+                    const int e1 = std::min(i1, n - 1), e2 = std::min(i2, n - 1);
+                    own[g] = (j * SL + e2 / s) * SL + e1 / s;
+                }
+        }
+    for (int64_t i = 0; i < N; ++i) IGE_REQUIRE(own[i] >= 0, "unknown without an owner leaf");
+    // per leaf: its slot unknowns grouped by owner, (owner, sorted unknowns)
+    std::vector<std::vector<std::pair<int32_t, std::vector<int32_t>>>> grp((size_t)nleaf);
+    for (int t = 0; t < nleaf; ++t) {
+        std::map<int32_t, std::vector<int32_t>> m;
+        for (int k = 0; k < nF; ++k) {
+            const int32_t g = B.leafdof[(size_t)t * nF + k];
+            if (g >= 0) m[own[g]].push_back(g);
+        }
+        for (auto &kv : m) {
+            std::sort(kv.second.begin(), kv.second.end());
+            kv.second.erase(std::unique(kv.second.begin(), kv.second.end()), kv.second.end());
+            grp[t].emplace_back(kv.first, std::move(kv.second));
+        }
+    }
+    auto slice = [&](int leaf, int32_t owner) -> const std::vector<int32_t> & {
+        for (const auto &g : grp[leaf])
+            if (g.first == owner) return g.second;
+        throw Status{IGE_EINVAL, "internal: owner slice not found"};
+    };
+    // off-diagonal owner blocks: for every row, the leaves that give it columns;
+    // diagonal owner blocks: their unknowns
+    std::map<std::pair<int32_t, int32_t>, std::map<int32_t, std::vector<int32_t>>> off;
+    std::map<int32_t, std::vector<int32_t>> diag;
+    for (int64_t b = 0; b < B.nblk(); ++b) {
+        const int t = B.pair[2 * b], u = B.pair[2 * b + 1];
+        for (const auto &gt : grp[t])
+            for (const auto &gu : grp[u]) {
+                const int32_t Tt = gt.first, Su = gu.first;
+                if (Tt == Su) {
+                    auto &dv = diag[Tt];
+                    dv.insert(dv.end(), gt.second.begin(), gt.second.end());
+                    dv.insert(dv.end(), gu.second.begin(), gu.second.end());
+                } else if (Tt < Su) {
+                    auto &rows = off[{Tt, Su}];
+                    for (int32_t i : gt.second) rows[i].push_back(u);
+                } else {
+                    auto &rows = off[{Su, Tt}];
+                    for (int32_t i : gu.second) rows[i].push_back(t);
+                }
+            }
+    }
+    auto add_sub = [&](const std::vector<int32_t> &rows, const std::vector<int32_t> &cols, bool sq) {
+        C.nr.push_back((int32_t)rows.size());
+        C.nc.push_back((int32_t)cols.size());
+        C.sym.push_back(sq ? 1 : 0);
+        const int32_t ld = (int32_t)((cols.size() + 3) / 4 * 4);
+        C.nval = (C.nval + 15) / 16 * 16;
+        C.val.push_back(C.nval);
+        C.ld.push_back(ld);
+        C.lst.push_back((int64_t)C.idx.size());
+        C.idx.insert(C.idx.end(), rows.begin(), rows.end());
+        C.idx.insert(C.idx.end(), cols.begin(), cols.end());
+        C.nval += (int64_t)rows.size() * ld;
+        C.distinct += sq ? (int64_t)rows.size() * ((int64_t)rows.size() + 1) / 2
+                         : (int64_t)rows.size() * (int64_t)cols.size();
+        C.maxn = std::max(C.maxn, (int)std::max(rows.size(), cols.size()));
+    };
+    // in owner order: the diagonal square of T, then its off-diagonal blocks (T, S > T)
+    auto it = off.begin();
+    for (int32_t Tt = 0; Tt < nleaf; ++Tt) {
+        auto dt = diag.find(Tt);
+        if (dt != diag.end()) {
+            auto &v = dt->second;
+            std::sort(v.begin(), v.end());
+            v.erase(std::unique(v.begin(), v.end()), v.end());
+            add_sub(v, v, true);
+        }
+        for (; it != off.end() && it->first.first == Tt; ++it) {
+            const int32_t Su = it->first.second;
+            // rows with the same set of column leaves form one rectangle
+            std::map<std::vector<int32_t>, std::vector<int32_t>> byset;
+            for (auto &rv : it->second) {
+                auto &ls = rv.second;
+                std::sort(ls.begin(), ls.end());
+                ls.erase(std::unique(ls.begin(), ls.end()), ls.end());
+                byset[ls].push_back(rv.first);
+            }
+            for (auto &kv : byset) {
+                std::vector<int32_t> cols;
+                for (int32_t leaf : kv.first) {
+                    const auto &sl = slice(leaf, Su);
+                    cols.insert(cols.end(), sl.begin(), sl.end());
+                }
+                std::sort(cols.begin(), cols.end());
+                cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+                add_sub(kv.second, cols, false);
+            }
+        }
+    }
+    IGE_REQUIRE(C.idx.size() < ((size_t)1 << 31), "near field too large for 32-bit index lists");
+    // work items and partial results
+    const int RI = std::max(1, rows_per_item);
+    for (int64_t k = 0; k < C.nsub(); ++k)
+        for (int r0 = 0; r0 < C.nr[k]; r0 += RI) {
+            const int r1 = std::min(C.nr[k], r0 + RI);
+            C.wsub.push_back((int32_t)k);
+            C.wr0.push_back(r0);
+            C.wr1.push_back(r1);
+            C.wpart.push_back(C.npart);
+            C.npart += (r1 - r0) + C.nc[k];
+        }
+    IGE_REQUIRE(C.npart < ((int64_t)1 << 31), "near field too large for 32-bit partial indices");
+    // launch order: the work items of at most 128 columns, then the wider ones (two
+    // launches with different lane tiling), each largest first
+    C.worder.resize(C.wsub.size());
+    std::iota(C.worder.begin(), C.worder.end(), 0);
+    std::stable_sort(C.worder.begin(), C.worder.end(), [&](int32_t a, int32_t b) {
+        const bool na = C.nc[C.wsub[a]] <= 128, nb = C.nc[C.wsub[b]] <= 128;
+        if (na != nb) return na;
+        return (int64_t)(C.wr1[a] - C.wr0[a]) * C.nc[C.wsub[a]] > (int64_t)(C.wr1[b] - C.wr0[b]) * C.nc[C.wsub[b]];
+    });
+    C.nnarrow = 0;
+    while (C.nnarrow < (int64_t)C.worder.size() && C.nc[C.wsub[C.worder[C.nnarrow]]] <= 128) ++C.nnarrow;
+    // per unknown its partial results in ascending order
+    std::vector<int64_t> cnt((size_t)N + 1, 0);
+    auto visit = [&](auto &&emit) {
+        for (size_t w = 0; w < C.wsub.size(); ++w) {
+            const int k = C.wsub[w];
+            const int32_t *rows = &C.idx[C.lst[k]], *cols = rows + C.nr[k];
+            for (int r = C.wr0[w]; r < C.wr1[w]; ++r) emit(rows[r], C.wpart[w] + (r - C.wr0[w]));
+            for (int c = 0; c < C.nc[k]; ++c) emit(cols[c], C.wpart[w] + (C.wr1[w] - C.wr0[w]) + c);
+        }
+    };
+    visit([&](int32_t g, int64_t) { cnt[g + 1]++; });
+    for (int64_t i = 0; i < N; ++i) cnt[i + 1] += cnt[i];
+    C.red_ptr = cnt;
+    C.red_idx.assign(cnt[N], 0);
+    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+    visit([&](int32_t g, int64_t slot) { C.red_idx[fill[g]++] = (int32_t)slot; });
+    // merge tables
+    std::vector<int32_t> oc((size_t)N + 1, 0);
+    for (size_t q = 0; q < B.leafdof.size(); ++q)
+        if (B.leafdof[q] >= 0) oc[B.leafdof[q] + 1]++;
+    for (int64_t i = 0; i < N; ++i) oc[i + 1] += oc[i];
+    C.occ_ptr = oc;
+    C.occ.assign(oc[N], 0);
+    {
+        std::vector<int32_t> f(oc.begin(), oc.end() - 1);
+        for (size_t q = 0; q < B.leafdof.size(); ++q)
+            if (B.leafdof[q] >= 0) C.occ[f[B.leafdof[q]]++] = (int32_t)q;   // ascending in q
+    }
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> nbr((size_t)nleaf);
+    for (int64_t b = 0; b < B.nblk(); ++b) {
+        const int t = B.pair[2 * b], u = B.pair[2 * b + 1];
+        nbr[t].push_back({u, (int32_t)(2 * b)});
+        if (u != t) nbr[u].push_back({t, (int32_t)(2 * b + 1)});
+    }
+    C.np_ptr.assign((size_t)nleaf + 1, 0);
+    for (int t = 0; t < nleaf; ++t) {
+        std::sort(nbr[t].begin(), nbr[t].end());
+        C.np_ptr[t + 1] = C.np_ptr[t] + (int32_t)nbr[t].size();
+        for (const auto &e : nbr[t]) {
+            C.np_leaf.push_back(e.first);
+            C.np_code.push_back(e.second);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // singular element pairs (shared corner) with their reference frames
 // ---------------------------------------------------------------------------
 namespace {

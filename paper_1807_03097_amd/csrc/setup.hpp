@@ -83,6 +83,44 @@ __host__ __device__ inline int leaf_slot(int W, int a, int i1, int i2)
 }
 void build_near_blocks(NearBlocks &B, const Discretisation &D, const Partition &T, int nch);
 
+// The same near-field matrix stored once per distinct entry (used by the product of
+// one column).  Every glued unknown is owned by one leaf (the leaf of the last element
+// of its support, at its first incarnation).  An entry (i, j) lives in the owner block
+// (own(i), own(j)) if own(i) <= own(j), else as (j, i) in (own(j), own(i)) (the matrix
+// is complex symmetric).  An off-diagonal owner block is split into dense
+// rectangles: its rows grouped by the set of source leaves whose slots give their
+// columns, each group times the union of those columns, so every stored entry is a
+// distinct nonzero.  A diagonal owner block is one dense square over its unknowns, of
+// which the product reads the upper triangle.  The values are summed from the leaf-pair
+// blocks (k_near_merge) in a fixed order.
+struct NearCompact {
+    std::vector<int32_t> nr, nc;       // [nsub] rows, columns of each rectangle
+    std::vector<int8_t> sym;           // [nsub] 1: diagonal square (upper triangle used)
+    std::vector<int64_t> val;          // [nsub] first value (row-major nr x ld, 256-byte aligned)
+    std::vector<int32_t> ld;           // [nsub] row stride: nc rounded up to 4 (64-byte rows)
+    std::vector<int64_t> lst;          // [nsub] first entry in idx: nr rows then nc columns
+    std::vector<int32_t> idx;          // glued unknowns
+    int64_t nval = 0;                  // stored values (full squares, padded rows)
+    int64_t distinct = 0;              // distinct entries (upper triangles of the squares)
+    int maxn = 0;                      // largest nr or nc
+    // work items of the product: rows [r0, r1) of one rectangle; partial results at
+    // part[w]: (r1 - r0) row sums, then nc column sums
+    std::vector<int32_t> wsub, wr0, wr1;
+    std::vector<int64_t> wpart;
+    std::vector<int32_t> worder;       // launch order of the work items
+    int64_t nnarrow = 0;               // leading work items of at most 128 columns
+    int64_t npart = 0;
+    std::vector<int64_t> red_ptr;      // [N+1] partial results of every unknown, ascending
+    std::vector<int32_t> red_idx;
+    // merge tables: leaf slots holding each unknown (leaf * nF + slot), ascending, and
+    // per leaf its near partners (both orders) with code = 2 * block + (leaf > partner)
+    std::vector<int32_t> occ_ptr, occ;
+    std::vector<int32_t> np_ptr, np_leaf, np_code;
+    int64_t nsub() const { return (int64_t)nr.size(); }
+};
+void build_near_compact(NearCompact &C, const Discretisation &D, const Partition &T, const NearBlocks &B,
+                        int rows_per_item);
+
 // singular element pairs inside the near field: (test element, trial element,
 // kind 1 identical / 2 edge / 3 vertex, frame code test, frame code trial)
 // Only pairs whose leaf pair is stored (leaf(e) <= leaf(f)) are kept; blk is the

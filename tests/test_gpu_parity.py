@@ -526,21 +526,69 @@ def test_plane_wave_scattering_against_mie(ctx):
 
 
 def test_c2_full_size_sampled_rows(oracle_mod, ctx):
-    """Matvec configuration: sphere, level 5, p = 2, kappa = 8, q = 8, 5x5 Gauss, x seed 0,
-    as timed by the benchmark; rows sampled evenly, computed one by one by the oracle."""
+    """Matvec configuration as the benchmark times it: sphere, level 5, p = 2,
+    kappa = 8, q = 8, eta = 1.6, leaf depth 3, 5x5 Gauss, x seed 0.  On the 48 rows of
+    tests/golden/c2_dense_rows.json: the HIP FMM equals the oracle's FMM (computed row
+    by row) to 1e-12 and the stored dense Galerkin rows to 1e-6."""
+    import json
+    import os
     from paper_1807_03097_amd import binding as B
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c2_dense_rows.json")))
+    rows = np.array(g["rows"])
+    yd = np.array(g["re"]) + 1j * np.array(g["im"])
     pats = W.cube_sphere()
     geom = B.Geometry(ctx, pats)
-    eta, d = 1.6, 2
+    eta, d = 1.6, 3
     op = B.Operator(geom, 2, 5, 8.0, 8, eta, 5, 5, d)
     x = W.random_coeffs(op.N, 0)
     y = op.apply(x)
-    rows = np.unique(np.linspace(0, op.N - 1, 20).astype(int))
     o = oracle_mod.Oracle(pats, 2, 5, 8.0, g=5, gs=5)
     yo = o.fmm_apply(x, 8, eta, d, rows=rows)
     err = _rel(y[rows], yo)
-    _say(f"  C2 N={op.N} nnz={op.info.near_nnz} far={op.info.far_pairs} sampled rel.err={err:.2e}")
-    assert err <= TOL
+    errd = _rel(y[rows], yd)
+    _say(f"  C2 N={op.N} distinct near entries={op.info.near_distinct} far={op.info.far_pairs} "
+         f"vs oracle FMM {err:.2e}, vs dense rows {errd:.2e}")
+    assert err <= TOL and errd <= 1e-6
+    op.close()
+
+
+HIGHQ_CASES = [
+    # geometry, p, m, kappa, q, eta, leaf depth, g, gs: q = 10 (121 nodes, matrix-core
+    # tiles of 128) at kappa 16 and 40
+    ("sphere", 2, 4, 16.0, 10, 1.6, 2, 5, 5),
+    ("sphere", 2, 4, 40.0, 10, 1.6, 2, 5, 5),
+    ("jittered", 2, 3, 16.0, 10, 1.0, 1, 5, 5),
+]
+
+
+@pytest.mark.parametrize("case", HIGHQ_CASES, ids=[f"{c[0]}-m{c[2]}-k{int(c[3])}-q{c[4]}" for c in HIGHQ_CASES])
+def test_high_q_and_kappa_match_oracle(oracle_mod, ctx, case):
+    """q = 10 and kappa = 16, 40 against the oracle: FP64 one column and batched
+    (generated coupling) to 1e-12, the FP64 matrix-core coupling of 16 columns to
+    1e-12, BF16 within (1e-6, 1e-2] and split BF16 within (1e-12, 2e-4]."""
+    from paper_1807_03097_amd import binding as B
+    name, p, m, kappa, q, eta, d, g, gs = case
+    _say(f"case {case}")
+    pats = _geom(name)
+    geom = B.Geometry(ctx, pats)
+    op = B.Operator(geom, p, m, kappa, q, eta, g, gs, d)
+    x = W.random_coeffs(op.N, 0)
+    yo = oracle_mod.Oracle(pats, p, m, kappa, g=g, gs=gs).fmm_apply(x, q, eta, d)
+    y1 = op.apply(x)
+    X = np.stack([x] + [W.random_coeffs(op.N, s) for s in range(1, 16)])
+    Y4 = op.apply(X[:4].copy())
+    Y16 = op.apply(X)
+    e1, e4, e16 = _rel(y1, yo), _rel(Y4[0], yo), _rel(Y16[0], yo)
+    e16c = max(_rel(Y16[c], Y4[c]) for c in range(4))
+    _say(f"  N={op.N} far={op.info.far_pairs}: 1 column {e1:.1e}, 4 columns {e4:.1e}, 16 columns (matrix cores) "
+         f"{e16:.1e} (vs 4 columns {e16c:.1e})")
+    assert e1 <= TOL and e4 <= TOL and e16 <= TOL and e16c <= 1e-13
+    for prec, lo, hi in ((B.IGE_BF16, 1e-6, 1e-2), (B.IGE_BF16X3, 1e-12, 2e-4)):
+        Yp = op.apply(X, prec=prec)
+        ep = _rel(Yp[0], yo)
+        _say(f"  prec {prec}: {ep:.1e}")
+        assert lo < ep <= hi
+    op.close()
 
 
 # Assembly cases for the colour launches of the near-field quadrature: trial squares
@@ -584,3 +632,39 @@ def test_assembly_is_bitwise_reproducible(oracle_mod, ctx, case):
     assert err <= TOL
     op1.close()
     op2.close()
+
+
+NEAR_ONCE_CASES = [CASES[0], CASES[2], CASES[4], CASES[5], CASES[7], CASES[9], CASES[10], ASSEMBLY_CASES[3]]
+
+
+@pytest.mark.parametrize("case", NEAR_ONCE_CASES,
+                         ids=[f"{c[0]}-p{c[1]}-m{c[2]}-eta{c[5]}-d{c[6]}" for c in NEAR_ONCE_CASES])
+def test_near_once_per_entry_equals_leaf_pair_blocks(oracle_mod, ctx, case, monkeypatch):
+    """The one-column near-field product over the distinct entries of the symmetric
+    matrix (owner blocks, upper triangles of the diagonal squares) equals the product
+    over the leaf-pair blocks and their transposes up to summation order, and the
+    whole apply matches the oracle."""
+    from paper_1807_03097_amd import binding as B
+    name, p, m, kappa, q, eta, d, g, gs = case
+    _say(f"case {case}")
+    pats = _geom(name)
+    geom = B.Geometry(ctx, pats)
+    monkeypatch.setenv("IGE_NEAR_COMPACT", "0")
+    op0 = B.Operator(geom, p, m, kappa, q, eta, g, gs, d)
+    monkeypatch.delenv("IGE_NEAR_COMPACT")
+    op1 = B.Operator(geom, p, m, kappa, q, eta, g, gs, d)
+    ys0, ys1 = [], []
+    for seed in range(3):
+        x = W.random_coeffs(op1.N, seed)
+        ys0.append(op0.apply(x))
+        ys1.append(op1.apply(x))
+    err = max(_rel(a, b) for a, b in zip(ys1, ys0))
+    x = W.random_coeffs(op1.N, 0)
+    dd = d if d >= 0 else int(np.ceil(np.log2((q + 1) / (p + 1)) - 1e-12))
+    yo = oracle_mod.Oracle(pats, p, m, kappa, g=g, gs=gs).fmm_apply(x, q, eta, dd)
+    erro = _rel(ys1[0], yo)
+    _say(f"  distinct {op1.info.near_distinct} of {op1.info.near_nnz} block entries; vs blocks {err:.1e}, "
+         f"vs oracle {erro:.1e}")
+    assert err <= 1e-14 and erro <= TOL
+    op0.close()
+    op1.close()

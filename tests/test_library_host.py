@@ -87,3 +87,38 @@ def test_plan_matches_oracle(oracle_mod, geom, p, m, eta, d, q):
     assert pt["L"] == tr["L"]
     assert np.array_equal(pt["far"], tr["far"])
     assert np.array_equal(pt["near"], tr["near"])
+
+
+@pytest.mark.parametrize("geom,p,m,eta,d", [
+    ("sphere", 2, 3, 1.6, 1), ("torus", 1, 3, 1.0, 1), ("sphere", 3, 3, 1.0, 2), ("sphere", 1, 2, 0.0, -1),
+])
+def test_near_distinct_entries_match_oracle_pattern(oracle_mod, geom, p, m, eta, d):
+    """The near field stored once per entry holds exactly the distinct entries
+    (i <= j) of the near-field pattern: glued unknowns i, j whose supports meet the
+    leaves of a near leaf pair, counted here from the oracle's own unknown table and
+    block tree (Sec. 4.2, eq. (eq::superspace) supports)."""
+    from paper_1807_03097_amd import binding as B
+    pats = {"sphere": W.cube_sphere, "torus": W.torus}[geom]()
+    ctx = B.Context(-1)
+    g = B.Geometry(ctx, pats)
+    op = B.Operator(g, p, m, 4.0, 6, eta, leaf_depth=d, plan_only=True)
+    o = oracle_mod.Oracle(pats, p, m, 4.0, g=2)
+    dd = d if d >= 0 else int(np.ceil(np.log2(7 / (p + 1)) - 1e-12))
+    tr = o.block_tree(eta, dd)
+    L, n = tr["L"], 1 << m
+    s, SL = n >> L, 1 << L
+    # unknowns whose support meets each leaf
+    sets = [set() for _ in range(o.P * SL * SL)]
+    J, A, I2, I1 = np.nonzero(o.dof >= 0)
+    for j, a, i2, i1 in zip(J, A, I2, I1):
+        pu, pv = (p, p - 1) if a == 0 else (p - 1, p)
+        for e2 in range(max(0, i2 - pv), min(n, i2 + 1)):
+            for e1 in range(max(0, i1 - pu), min(n, i1 + 1)):
+                sets[(j * SL + e2 // s) * SL + e1 // s].add(int(o.dof[j, a, i2, i1]))
+    keys = set()
+    for t, u in tr["near"]:
+        I = np.array(sorted(sets[t])); Jv = np.array(sorted(sets[u]))
+        ii, jj = np.meshgrid(I, Jv, indexing="ij")
+        keys.update((np.minimum(ii, jj).ravel() * o.N + np.maximum(ii, jj).ravel()).tolist())
+    assert op.info.near_distinct == len(keys)
+    assert op.info.near_distinct < op.info.near_nnz or eta == 0.0
