@@ -85,7 +85,7 @@ int ige_geom_create(ige_ctx ctx, int n_patches, const int *degree, const int *n_
 int ige_geom_destroy(ige_geom geom);
 
 /* Discretisation and compression parameters.
- *   p             spline degree of S^1 (Sec. 3.2: S^{p,p-1} x S^{p-1,p}), 1..3
+ *   p             spline degree of S^1 (Sec. 3.2: S^{p,p-1} x S^{p-1,p}), 1..4
  *   level         m: 2^m x 2^m elements per patch (Sec. 4.1), 0..10
  *   kappa         wavenumber > 0
  *   q             interpolation degree (q+1 Chebyshev nodes per direction), 1..11

@@ -226,7 +226,7 @@ namespace {
 
 void check_params(const ige_params &P)
 {
-    IGE_REQUIRE(P.p >= 1 && P.p <= ige::kMaxP, "p must be 1..3");
+    IGE_REQUIRE(P.p >= 1 && P.p <= ige::kMaxP, "p must be 1..4");
     IGE_REQUIRE(P.level >= 0 && P.level <= 10, "level must be 0..10");
     IGE_REQUIRE(std::isfinite(P.kappa) && P.kappa > 0.0, "kappa must be positive");
     IGE_REQUIRE(P.q >= 1 && P.q <= 11, "q must be 1..11");

@@ -12,7 +12,7 @@
 namespace ige {
 
 constexpr int kMaxGeomDeg = 8;   // NURBS degree of the input patches
-constexpr int kMaxP = 3;         // discretisation degree p
+constexpr int kMaxP = 4;         // discretisation degree p
 constexpr int kMaxNl = 2 * kMaxP * (kMaxP + 1);   // local glued functions per element
 constexpr int kMaxQ1 = 16;       // q + 1
 constexpr int kMaxG = 8;         // regular Gauss points per direction

@@ -404,6 +404,10 @@ __device__ inline bool share_corner(const DevOp &o, int64_t e, int64_t f)
     return false;
 }
 
+// row tiles of test functions per workgroup of k_near_regular: all up to 24 local
+// functions, one 16-row tile for more (p = 4: 40 functions, three workgroups)
+constexpr int near_regular_lr(int nl) { return nl <= 24 ? (nl + 15) / 16 : 1; }
+
 // ---------------------------------------------------------------------------
 // a1: regular element pairs (no shared corner).  With S = (1, 1, 1, -kappa^-2) and
 // the weights folded into Psi,
@@ -427,19 +431,25 @@ __device__ inline bool share_corner(const DevOp &o, int64_t e, int64_t f)
 // the launches run in a fixed order on one stream: the assembled blocks are the same
 // bits on every run.
 // ---------------------------------------------------------------------------
-template <int NL, int QT>
+template <int NL, int QT, int LR>
 __device__ __forceinline__ void near_regular_body(const DevOp &o, int sb, int ce1, int ce2, int cs1, int cs2, int sstep)
 {
-    constexpr int LT = (NL + 15) / 16, T = 4 * QT;
-    extern __shared__ double2 sacc[];                 // [NL][2 Wsb^2], then [4][NL][NL] staging
+    // LR of the LT 16-row tiles of test functions per workgroup (LR = LT: all rows;
+    // otherwise the rows are split over LT / LR workgroups, for the larger degrees)
+    constexpr int LT = (NL + 15) / 16, T = 4 * QT, NRT = LT / LR;
+    constexpr int NR = LR == LT ? NL : 16 * LR;       // test-function rows of this workgroup
+    extern __shared__ double2 sacc[];                 // [NR][2 Wsb^2], then [4][NR][NL] staging
     __shared__ double sXe[3][16 * QT];                // test element points (zero padded)
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int s = o.s, nsb = s / sb, Wsb = sb + o.p, nslot = 2 * Wsb * Wsb, P1 = o.p + 1;
-    double2 *sstage = sacc + NL * nslot;
+    double2 *sstage = sacc + NR * nslot;
     // test elements and trial squares of this colour
     const int n1 = (s - ce1 + P1 - 1) / P1, n2 = (s - ce2 + P1 - 1) / P1;
     const int m1 = (nsb - cs1 + sstep - 1) / sstep, m2 = (nsb - cs2 + sstep - 1) / sstep;
     int64_t blk = blockIdx.x;
+    const int u0 = LR * (int)(blk % NRT);             // first row tile
+    blk /= NRT;
+    const int l0 = 16 * u0;                           // first test function
     const int sub = (int)(blk % (m1 * m2));
     blk /= m1 * m2;
     const int tc = (int)(blk % (n1 * n2));
@@ -454,23 +464,23 @@ __device__ __forceinline__ void near_regular_body(const DevOp &o, int sb, int ce
     const int fx0 = (jsr % SL) * s + sl1, fy0 = (jsr / SL) * s + sl2;
     const int64_t e = ((int64_t)jt * o.n + te2) * o.n + te1;
     const int G2 = o.G2;
-    for (int i = threadIdx.x; i < NL * nslot; i += blockDim.x) sacc[i] = make_double2(0.0, 0.0);
+    for (int i = threadIdx.x; i < NR * nslot; i += blockDim.x) sacc[i] = make_double2(0.0, 0.0);
     for (int i = threadIdx.x; i < 3 * 16 * QT; i += blockDim.x) {
         const int d = i / (16 * QT), q = i % (16 * QT);
         sXe[d][q] = q < G2 ? o.eX[(e * 3 + d) * G2 + q] : 0.0;
     }
     constexpr size_t FE = (size_t)4 * LT * T * 64;
     const double ik2 = 1.0 / (o.kappa * o.kappa);
-    double pa[4][LT][T];
+    double pa[4][LR][T];
     {
         const double *Fe = o.ePsiF + (size_t)e * FE;
 #pragma unroll
         for (int c = 0; c < 4; ++c)
 #pragma unroll
-            for (int u = 0; u < LT; ++u)
+            for (int u = 0; u < LR; ++u)
 #pragma unroll
                 for (int t = 0; t < T; ++t)
-                    pa[c][u][t] = Fe[((c * LT + u) * T + t) * 64 + lane] * (c == 3 ? -ik2 : 1.0);
+                    pa[c][u][t] = Fe[((c * LT + u0 + u) * T + t) * 64 + lane] * (c == 3 ? -ik2 : 1.0);
     }
     __syncthreads();
     const int nfe = sb * sb, nround = (nfe + 3) / 4;
@@ -481,10 +491,10 @@ __device__ __forceinline__ void near_regular_body(const DevOp &o, int sb, int ce
         // wave-uniform: trial element exists and shares no corner with e (those pairs
         // come from the singular kernel)
         const bool act = fi < nfe && !share_corner(o, e, f);
-        dx4 br[LT][LT], bi[LT][LT];
+        dx4 br[LR][LT], bi[LR][LT];
         if (act) {
 #pragma unroll
-            for (int u = 0; u < LT; ++u)
+            for (int u = 0; u < LR; ++u)
 #pragma unroll
                 for (int v = 0; v < LT; ++v) {
                     br[u][v] = dx4{0.0, 0.0, 0.0, 0.0};
@@ -517,11 +527,11 @@ __device__ __forceinline__ void near_regular_body(const DevOp &o, int sb, int ce
             const double *Ff = o.ePsiF + (size_t)f * FE;
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                dx4 yr[QT][LT], yi[QT][LT];
+                dx4 yr[QT][LR], yi[QT][LR];
 #pragma unroll
                 for (int qt = 0; qt < QT; ++qt)
 #pragma unroll
-                    for (int u = 0; u < LT; ++u) {
+                    for (int u = 0; u < LR; ++u) {
                         yr[qt][u] = dx4{0.0, 0.0, 0.0, 0.0};
                         yi[qt][u] = dx4{0.0, 0.0, 0.0, 0.0};
                     }
@@ -530,7 +540,7 @@ __device__ __forceinline__ void near_regular_body(const DevOp &o, int sb, int ce
 #pragma unroll
                     for (int qt = 0; qt < QT; ++qt)
 #pragma unroll
-                        for (int u = 0; u < LT; ++u) {
+                        for (int u = 0; u < LR; ++u) {
                             yr[qt][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(kre[qt][t], pa[c][u][t], yr[qt][u], 0, 0, 0);
                             yi[qt][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(kim[qt][t], pa[c][u][t], yi[qt][u], 0, 0, 0);
                         }
@@ -542,7 +552,7 @@ __device__ __forceinline__ void near_regular_body(const DevOp &o, int sb, int ce
                         for (int j = 0; j < 4; ++j) {
                             const double pb = Ff[((c * LT + v) * T + 4 * qt + j) * 64 + lane];
 #pragma unroll
-                            for (int u = 0; u < LT; ++u) {
+                            for (int u = 0; u < LR; ++u) {
                                 br[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(yr[qt][u][j], pb, br[u][v], 0, 0, 0);
                                 bi[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(yi[qt][u][j], pb, bi[u][v], 0, 0, 0);
                             }
@@ -551,17 +561,17 @@ __device__ __forceinline__ void near_regular_body(const DevOp &o, int sb, int ce
         }
         // rows l = 16 u + lane / 16 + 4 j, columns l' = 16 v + lane % 16 into this wave's
         // staging block, then the four staged blocks are added in wave order
-        double2 *stg = sstage + (size_t)wv * NL * NL;
+        double2 *stg = sstage + (size_t)wv * NR * NL;
         if (act) {
 #pragma unroll
             for (int v = 0; v < LT; ++v) {
                 const int lb = 16 * v + (lane & 15);
 #pragma unroll
-                for (int u = 0; u < LT; ++u)
+                for (int u = 0; u < LR; ++u)
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
-                        const int l = 16 * u + (lane >> 4) + 4 * j;
-                        if (l < NL && lb < NL) stg[l * NL + lb] = make_double2(br[u][v][j], bi[u][v][j]);
+                        const int lr = 16 * u + (lane >> 4) + 4 * j;   // row of this workgroup
+                        if (l0 + lr < NL && lb < NL) stg[lr * NL + lb] = make_double2(br[u][v][j], bi[u][v][j]);
                     }
             }
         }
@@ -572,9 +582,10 @@ __device__ __forceinline__ void near_regular_body(const DevOp &o, int sb, int ce
             const bool aw = fw < nfe && !share_corner(o, e, ((int64_t)js * o.n + fy0 + fw / sb) * o.n + fx0 + fw % sb);
             if (aw) {
                 const int q1 = fw % sb, q2 = fw / sb;
-                const double2 *sw = sstage + (size_t)w * NL * NL;
-                for (int i = threadIdx.x; i < NL * NL; i += blockDim.x) {
+                const double2 *sw = sstage + (size_t)w * NR * NL;
+                for (int i = threadIdx.x; i < NR * NL; i += blockDim.x) {
                     const int l = i / NL, lb = i % NL;
+                    if (l0 + l >= NL) continue;
                     int a, t1, t2;
                     local_index(o.p, lb, a, t1, t2);
                     const int slot = a * Wsb * Wsb + (q2 + t2) * Wsb + (q1 + t1);
@@ -595,9 +606,10 @@ __device__ __forceinline__ void near_regular_body(const DevOp &o, int sb, int ce
         elem_of(o, f, jf, f1, f2);
         const int q1 = f1 - fx0, q2 = f2 - fy0;
         if (q1 < 0 || q1 >= sb || q2 < 0 || q2 >= sb) continue;   // uniform over the workgroup
-        const double2 *P = o.sblk + (size_t)k * NL * NL;
-        for (int i = threadIdx.x; i < NL * NL; i += blockDim.x) {
+        const double2 *P = o.sblk + (size_t)k * NL * NL + (size_t)l0 * NL;
+        for (int i = threadIdx.x; i < NR * NL; i += blockDim.x) {
             const int l = i / NL, lb = i % NL;
+            if (l0 + l >= NL) continue;
             int a, t1, t2;
             local_index(o.p, lb, a, t1, t2);
             const int slot = a * Wsb * Wsb + (q2 + t2) * Wsb + (q1 + t1);
@@ -609,10 +621,11 @@ __device__ __forceinline__ void near_regular_body(const DevOp &o, int sb, int ce
         __syncthreads();
     }
     const int W = o.W, nF = o.nF;
-    for (int i = threadIdx.x; i < NL * nslot; i += blockDim.x) {
+    for (int i = threadIdx.x; i < NR * nslot; i += blockDim.x) {
         const double2 v = sacc[i];
         if (v.x == 0.0 && v.y == 0.0) continue;
-        const int l = i / nslot, sl = i % nslot;
+        const int l = l0 + i / nslot, sl = i % nslot;
+        if (l >= NL) continue;
         const int a = sl / (Wsb * Wsb), r = sl % (Wsb * Wsb);
         const int i1 = sl1 + r % Wsb, i2 = sl2 + r / Wsb;
         if (i1 >= (a == 0 ? W : W - 1) || i2 >= (a == 0 ? W - 1 : W)) {
@@ -639,14 +652,14 @@ __device__ __forceinline__ void near_regular_body(const DevOp &o, int sb, int ce
 template <int NL, int QT>
 __global__ __launch_bounds__(256) void k_near_regular(DevOp o, int sb, int ce1, int ce2, int cs1, int cs2, int sstep)
 {
-    near_regular_body<NL, QT>(o, sb, ce1, ce2, cs1, cs2, sstep);
+    near_regular_body<NL, QT, near_regular_lr(NL)>(o, sb, ce1, ce2, cs1, cs2, sstep);
 }
 template <int NL, int QT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_near_regular_o2(DevOp o, int sb, int ce1,
                                                                                                    int ce2, int cs1, int cs2,
                                                                                                    int sstep)
 {
-    near_regular_body<NL, QT>(o, sb, ce1, ce2, cs1, cs2, sstep);
+    near_regular_body<NL, QT, near_regular_lr(NL)>(o, sb, ce1, ce2, cs1, cs2, sstep);
 }
 
 // ---------------------------------------------------------------------------
@@ -720,7 +733,8 @@ __device__ inline void singular_point(const DevOp &o, int kind, int idx, double 
 template <int P>
 __global__ __launch_bounds__(64) void k_near_singular(DevOp o, const SingularPair *list)
 {
-    constexpr int NL = 2 * P * (P + 1), LT = (NL + 15) / 16, NB = 32;
+    // points per batch: 32 (16 for p = 4, whose 40 local functions would not fit)
+    constexpr int NL = 2 * P * (P + 1), LT = (NL + 15) / 16, NB = P >= 4 ? 16 : 32;
     __shared__ double sPa[NB][NL][4];
     __shared__ double sPb[NB][NL][4];
     __shared__ double2 sK[NB];
@@ -747,7 +761,7 @@ __global__ __launch_bounds__(64) void k_near_singular(DevOp o, const SingularPai
         const int pt = p0 + qi;
         double X[3] = {0.0, 0.0, 0.0}, wt = 0.0;
         __syncthreads();   // the previous batch has been consumed
-        if (pt < npts) {
+        if (pt < npts && qi < NB) {
             double s1, s2, t1, t2;
             singular_point(o, sp.kind, pt, s1, s2, t1, t2, wt);
             double xa, ya, xb, yb;
@@ -770,7 +784,7 @@ __global__ __launch_bounds__(64) void k_near_singular(DevOp o, const SingularPai
             }
         }
         __syncthreads();
-        if (half == 0) {
+        if (half == 0 && qi < NB) {
             double2 K = make_double2(0.0, 0.0);
             if (pt < npts) {
                 const double d0 = X[0] - sX[qi][0], d1 = X[1] - sX[qi][1], d2 = X[2] - sX[qi][2];
@@ -1377,7 +1391,8 @@ void launch_element_data(ige_op op)
     switch (o.p) {
         case 1: hipLaunchKernelGGL(k_element_data<4>, dim3(E), dim3(threads), 0, s, o, op->d_eX.p, op->d_ePsi.p, op->d_ePsiF.p, op->d_eC.p); break;
         case 2: hipLaunchKernelGGL(k_element_data<12>, dim3(E), dim3(threads), 0, s, o, op->d_eX.p, op->d_ePsi.p, op->d_ePsiF.p, op->d_eC.p); break;
-        default: hipLaunchKernelGGL(k_element_data<24>, dim3(E), dim3(threads), 0, s, o, op->d_eX.p, op->d_ePsi.p, op->d_ePsiF.p, op->d_eC.p); break;
+        case 3: hipLaunchKernelGGL(k_element_data<24>, dim3(E), dim3(threads), 0, s, o, op->d_eX.p, op->d_ePsi.p, op->d_ePsiF.p, op->d_eC.p); break;
+        default: hipLaunchKernelGGL(k_element_data<40>, dim3(E), dim3(threads), 0, s, o, op->d_eX.p, op->d_ePsi.p, op->d_ePsiF.p, op->d_eC.p); break;
     }
     IGE_LAUNCH_CHECK();
 }
@@ -1422,7 +1437,8 @@ void launch_near_regular_nl(ige_op op, dim3 grid, size_t shm, int sb, int ce1, i
 // square of sb x sb elements, and four staged element-pair blocks
 size_t near_regular_shm(int sb, int p, int nl)
 {
-    return sizeof(double2) * ((size_t)nl * 2 * (sb + p) * (sb + p) + (size_t)4 * nl * nl);
+    const size_t nr = nl <= 24 ? nl : 16 * near_regular_lr(nl);   // rows per workgroup
+    return sizeof(double2) * (nr * 2 * (sb + p) * (sb + p) + (size_t)4 * nr * nl);
 }
 
 int near_regular_sb(int s, int p, int nl)
@@ -1452,13 +1468,16 @@ void launch_near_regular(ige_op op)
                 for (int cs1 = 0; cs1 < std::min(sstep, nsb); ++cs1) {
                     const int64_t n1 = (o.s - ce1 + P1 - 1) / P1, n2 = (o.s - ce2 + P1 - 1) / P1;
                     const int64_t m1 = (nsb - cs1 + sstep - 1) / sstep, m2 = (nsb - cs2 + sstep - 1) / sstep;
-                    const int64_t nwg = o.nblk * n1 * n2 * m1 * m2;
+                    const int LT = (o.nl + 15) / 16;
+                    const int64_t nrt = LT / near_regular_lr(o.nl);   // row-tile workgroups per element
+                    const int64_t nwg = o.nblk * n1 * n2 * m1 * m2 * nrt;
                     if (nwg == 0) continue;
                     const dim3 grid((unsigned)nwg);
                     switch (o.p) {
                         case 1: launch_near_regular_nl<4>(op, grid, shm, sb, ce1, ce2, cs1, cs2, sstep); break;
                         case 2: launch_near_regular_nl<12>(op, grid, shm, sb, ce1, ce2, cs1, cs2, sstep); break;
-                        default: launch_near_regular_nl<24>(op, grid, shm, sb, ce1, ce2, cs1, cs2, sstep); break;
+                        case 3: launch_near_regular_nl<24>(op, grid, shm, sb, ce1, ce2, cs1, cs2, sstep); break;
+                        default: launch_near_regular_nl<40>(op, grid, shm, sb, ce1, ce2, cs1, cs2, sstep); break;
                     }
                     IGE_LAUNCH_CHECK();
                 }
@@ -1472,7 +1491,8 @@ void launch_near_singular(ige_op op)
     switch (o.p) {
         case 1: hipLaunchKernelGGL(k_near_singular<1>, dim3(op->nsing), dim3(64), 0, s, o, op->d_sing.p); break;
         case 2: hipLaunchKernelGGL(k_near_singular<2>, dim3(op->nsing), dim3(64), 0, s, o, op->d_sing.p); break;
-        default: hipLaunchKernelGGL(k_near_singular<3>, dim3(op->nsing), dim3(64), 0, s, o, op->d_sing.p); break;
+        case 3: hipLaunchKernelGGL(k_near_singular<3>, dim3(op->nsing), dim3(64), 0, s, o, op->d_sing.p); break;
+        default: hipLaunchKernelGGL(k_near_singular<4>, dim3(op->nsing), dim3(64), 0, s, o, op->d_sing.p); break;
     }
     IGE_LAUNCH_CHECK();
 }
@@ -1737,7 +1757,8 @@ void launch_potential(ige_op op, const double2 *w, int npts, const double *pts, 
     switch (o.p) {
         case 1: hipLaunchKernelGGL(k_pot_sources<4>, dim3((unsigned)E), dim3(64), 0, s, o, w, src); break;
         case 2: hipLaunchKernelGGL(k_pot_sources<12>, dim3((unsigned)E), dim3(64), 0, s, o, w, src); break;
-        default: hipLaunchKernelGGL(k_pot_sources<24>, dim3((unsigned)E), dim3(64), 0, s, o, w, src); break;
+        case 3: hipLaunchKernelGGL(k_pot_sources<24>, dim3((unsigned)E), dim3(64), 0, s, o, w, src); break;
+        default: hipLaunchKernelGGL(k_pot_sources<40>, dim3((unsigned)E), dim3(64), 0, s, o, w, src); break;
     }
     IGE_HIP(hipGetLastError());
     if (npts > 0) {

@@ -343,7 +343,7 @@ void extraction_1d(int deg, int n, std::vector<double> &ext)
 
 void build_discretisation(Discretisation &D, const Geometry &G, int p, int m)
 {
-    IGE_REQUIRE(p >= 1 && p <= kMaxP, "p must be 1..3");
+    IGE_REQUIRE(p >= 1 && p <= kMaxP, "p must be 1..4");
     IGE_REQUIRE(m >= 0 && m <= 10, "level must be 0..10");
     D.P = G.P; D.p = p; D.m = m; D.n = 1 << m; D.nb = D.n + p;
     const int n = D.n, nb = D.nb;

@@ -53,6 +53,8 @@ CASES = [
     ("sphere", 1, 3, 2.0, 3, 1.0, 0, 3, 6),       # leaf = element, low q
     ("sphere", 2, 3, 8.0, 8, 1.6, 3, 5, 5),       # leaf = patch: far field only between patches
     ("sphere", 3, 3, 6.0, 6, 1.0, 1, 5, 5),       # cubic splines (24 local functions per element)
+    ("sphere", 4, 2, 4.0, 8, 1.0, 1, 5, 5),       # quartic splines (40 local functions per element)
+    ("jittered", 4, 3, 6.0, 8, 1.6, 1, 5, 5),
 ]
 
 
@@ -248,8 +250,8 @@ def test_fp32_coupling_apply_and_refined_solve(oracle_mod, ctx):
         assert _rel(Xir[c], X64[c]) <= 1e-6
 
 
-@pytest.mark.parametrize("case", [CASES[2], CASES[3], CASES[4], CASES[10]],
-                         ids=["sphere-m3-d1", "sphere-m4-d2", "torus-m3", "sphere-p3"])
+@pytest.mark.parametrize("case", [CASES[2], CASES[3], CASES[4], CASES[10], CASES[12]],
+                         ids=["sphere-m3-d1", "sphere-m4-d2", "torus-m3", "sphere-p3", "jittered-p4"])
 def test_bf16_matrix_core_coupling(oracle_mod, ctx, case):
     """Coupling on the BF16 matrix cores: plain BF16 within 2^-9-level error of the
     oracle, split BF16 (three products) within 2^-16-level error, one and several
@@ -601,6 +603,7 @@ ASSEMBLY_CASES = [
     ("torus", 2, 2, 6.0, 6, 1.0, 1, 5, 5),
     ("sphere", 3, 3, 6.0, 6, 1.6, 3, 5, 4),
     ("sphere", 2, 4, 8.0, 8, 1.6, 4, 5, 5),
+    ("sphere", 4, 3, 6.0, 8, 1.6, 2, 5, 4),
 ]
 
 
@@ -634,7 +637,8 @@ def test_assembly_is_bitwise_reproducible(oracle_mod, ctx, case):
     op2.close()
 
 
-NEAR_ONCE_CASES = [CASES[0], CASES[2], CASES[4], CASES[5], CASES[7], CASES[9], CASES[10], ASSEMBLY_CASES[3]]
+NEAR_ONCE_CASES = [CASES[0], CASES[2], CASES[4], CASES[5], CASES[7], CASES[9], CASES[10], CASES[12],
+                   ASSEMBLY_CASES[3], ASSEMBLY_CASES[5]]
 
 
 @pytest.mark.parametrize("case", NEAR_ONCE_CASES,
@@ -668,3 +672,26 @@ def test_near_once_per_entry_equals_leaf_pair_blocks(oracle_mod, ctx, case, monk
     assert err <= 1e-14 and erro <= TOL
     op0.close()
     op1.close()
+
+
+def test_quartic_dense_solve_matches_lapack(oracle_mod, ctx):
+    """p = 4 (the paper's Table 1, last column: N = 300 at level 1): the dense operator
+    (eta = 0) against the oracle's matrix, and a plane-wave GMRES solve against LAPACK
+    within tol * cond(A)."""
+    from paper_1807_03097_amd import binding as B
+    pats = W.cube_sphere()
+    geom = B.Geometry(ctx, pats)
+    op = B.Operator(geom, 4, 1, 1.0, 8, 0.0, 5, 5, -1)
+    assert op.N == 300
+    o = oracle_mod.Oracle(pats, 4, 1, 1.0)
+    A = o.dense_matrix()
+    Ag = op.apply(np.eye(op.N, dtype=np.complex128)).T
+    assert np.max(np.abs(Ag - A)) <= TOL * np.max(np.abs(A))
+    f = op.rhs_plane_wave([[0.0, 0.0, 1.0]], [[1.0, 0.0, 0.0]])[0]
+    fo = o.rhs_plane_wave([0, 0, 1], [1, 0, 0])
+    assert _rel(f, fo) <= TOL
+    x, st, rc = op.solve(f, tol=1e-10, restart=400, maxit=4000)
+    assert rc == 0
+    xl = np.linalg.solve(A, fo)
+    _say(f"  p=4 N={op.N}: GMRES iterations {st[0][0]}, relres {st[0][2]:.1e}, vs LAPACK {_rel(x, xl):.1e}")
+    assert _rel(x, xl) <= 1e-10 * np.linalg.cond(A)
