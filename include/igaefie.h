@@ -100,7 +100,12 @@ int ige_geom_destroy(ige_geom geom);
  *                 at assembly and stored, one Q x Q complex block per unordered
  *                 cluster pair (G of (s, t) is the transpose of G of (t, s)); every
  *                 apply then streams them (Q^2 * 16 bytes per pair).  0 or -1: G is
- *                 evaluated in every apply (the default: measured faster). */
+ *                 evaluated in every apply (the default: measured faster).
+ *   kappa_cap     0: the admissibility condition of the paper (eq:admissibility), which
+ *                 does not involve kappa; > 0: a block is admissible only if also
+ *                 kappa * max diam <= kappa_cap (coarse clusters many wavelengths
+ *                 wide are refined further, so the fixed q keeps its accuracy at high
+ *                 kappa; more, smaller far blocks). */
 typedef struct {
     int p, level;
     double kappa;
@@ -108,6 +113,7 @@ typedef struct {
     double eta;
     int gauss_near, gauss_singular, leaf_depth;
     int store_coupling;
+    double kappa_cap;
 } ige_params;
 
 /* Assemble the operator on the device: element and cluster-node geometry, the

@@ -367,10 +367,12 @@ class Oracle:
                     rad[cid] = np.max(np.linalg.norm(blk - c, axis=1))
         return cen, rad
 
-    def block_tree(self, eta: float, d: int):
+    def block_tree(self, eta: float, d: int, kappa_cap: float = 0.0):
         """Algorithm 1 started from all ordered patch pairs; returns the far field
         (level, target, source) and the near leaf pairs (target, source) with cluster
-        ids j*4^l + k2*2^l + k1, each list sorted."""
+        ids j*4^l + k2*2^l + k1, each list sorted.  kappa_cap > 0 adds the condition
+        kappa * diam <= kappa_cap to the admissibility test (not in the paper: an
+        option for high wavenumbers, where the paper's condition ignores kappa)."""
         L = self.leaf_level(d)
         balls = [self.bounding_balls(l) for l in range(L + 1)]
         tgt, src = np.meshgrid(np.arange(self.P), np.arange(self.P), indexing="ij")
@@ -382,6 +384,8 @@ class Oracle:
             dist = np.linalg.norm(cen[tgt] - cen[src], axis=1) - rad[tgt] - rad[src]
             diam = 2.0 * np.maximum(rad[tgt], rad[src])
             adm = (dist > 0) & (diam <= eta * dist * (1.0 - ADM_MARGIN))
+            if kappa_cap > 0:
+                adm &= self.kappa * diam <= kappa_cap * (1.0 - ADM_MARGIN)
             far.append(np.stack([np.full(adm.sum(), l), tgt[adm], src[adm]], axis=1))
             tn, sn = tgt[~adm], src[~adm]
             if l == L:

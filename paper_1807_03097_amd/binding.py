@@ -31,7 +31,7 @@ class IgeError(RuntimeError):
 class ige_params(C.Structure):
     _fields_ = [("p", C.c_int), ("level", C.c_int), ("kappa", C.c_double), ("q", C.c_int), ("eta", C.c_double),
                 ("gauss_near", C.c_int), ("gauss_singular", C.c_int), ("leaf_depth", C.c_int),
-                ("store_coupling", C.c_int)]
+                ("store_coupling", C.c_int), ("kappa_cap", C.c_double)]
 
 
 class ige_op_info_t(C.Structure):
@@ -282,9 +282,10 @@ class Geometry:
 class Operator:
     def __init__(self, geom: Geometry, p: int, level: int, kappa: float, q: int = 8, eta: float = 1.0,
                  gauss_near: int = 5, gauss_singular: int = 5, leaf_depth: int = -1, plan_only: bool = False,
-                 store_coupling: int = -1):
+                 store_coupling: int = -1, kappa_cap: float = 0.0):
         self.geom = geom
-        self.prm = ige_params(p, level, kappa, q, eta, gauss_near, gauss_singular, leaf_depth, store_coupling)
+        self.prm = ige_params(p, level, kappa, q, eta, gauss_near, gauss_singular, leaf_depth, store_coupling,
+                              kappa_cap)
         self.h = ige_op_plan(geom.h, self.prm) if plan_only else ige_op_assemble(geom.h, self.prm)
         self.info = ige_op_info(self.h)
         self.N = int(self.info.n_dof)
@@ -454,8 +455,8 @@ class Server:
 
     def submit(self, geom: Geometry, p, level, kappa, direction, pol, q=8, eta=1.0, leaf_depth=-1,
                gauss_near=5, gauss_singular=5, tol=1e-6, restart=1500, maxit=10000, refine=False,
-               inner_tol=1e-4, inner_prec=IGE_F32):
-        prm = ige_params(p, level, kappa, q, eta, gauss_near, gauss_singular, leaf_depth, 0)
+               inner_tol=1e-4, inner_prec=IGE_F32, kappa_cap=0.0):
+        prm = ige_params(p, level, kappa, q, eta, gauss_near, gauss_singular, leaf_depth, 0, kappa_cap)
         opts = ige_solve_opts(tol, restart, maxit, int(refine), inner_tol, inner_prec)
         if np.ndim(direction) == 2:   # [W][3] directions and polarisations: one request of W waves
             t = ige_srv_submit_waves(self.h, geom.h, prm, direction, pol, opts)

@@ -19,14 +19,27 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    objdir = os.path.join(HERE, "_build")
+# host-code sanitizer variants (the device code is compiled as usual): used by the CPU
+# tests of the host planning, never loaded by the GPU path
+SANITIZE = {
+    "asan": ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"],
+    "tsan": ["-Xarch_host", "-fsanitize=thread", "-Xarch_host", "-fno-omit-frame-pointer"],
+}
+
+
+def build(verbose: bool = False, variant: str | None = None) -> str:
+    """Compile the library; variant "asan" or "tsan" builds a host-sanitized copy
+    _build_<variant>/libigaefie_<variant>.so instead of libigaefie.so."""
+    extra = SANITIZE[variant] if variant else []
+    objdir = os.path.join(HERE, "_build" + (f"_{variant}" if variant else ""))
+    target = os.path.join(objdir, f"libigaefie_{variant}.so") if variant else OUT
     os.makedirs(objdir, exist_ok=True)
     objs = []
     procs = []
     for src in SOURCES:
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
-        cmd = [HIPCC, "-x", "hip", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC, "-x", "hip", *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
@@ -40,11 +53,11 @@ def build(verbose: bool = False) -> str:
             failed.append(src)
     if failed:
         raise RuntimeError("hipcc failed for " + ", ".join(failed))
-    tmp = OUT + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fopenmp", "-o", tmp, *objs]
+    tmp = target + ".tmp"
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fopenmp", *extra, "-o", tmp, *objs]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, OUT)
-    return OUT
+    os.replace(tmp, target)
+    return target
 
 
 if __name__ == "__main__":

@@ -35,6 +35,9 @@ int guard(F &&f)
     } catch (const std::exception &e) {
         g_err = e.what();
         return IGE_EINVAL;
+    } catch (...) {
+        g_err = "unknown exception";
+        return IGE_EINVAL;
     }
 }
 
@@ -235,6 +238,7 @@ void check_params(const ige_params &P)
     IGE_REQUIRE(P.gauss_singular >= 1 && P.gauss_singular <= ige::kMaxGs, "gauss_singular must be 1..12");
     IGE_REQUIRE(P.leaf_depth >= -1 && P.leaf_depth <= 10, "leaf_depth must be -1..10");
     IGE_REQUIRE(P.store_coupling >= -1 && P.store_coupling <= 1, "store_coupling must be -1, 0 or 1");
+    IGE_REQUIRE(std::isfinite(P.kappa_cap) && P.kappa_cap >= 0.0, "kappa_cap must be >= 0");
 }
 
 // host part: unknowns, trees, near pattern, singular pairs, far tables
@@ -244,7 +248,7 @@ void plan(ige_op op, const ige_geom_s *geom, ige::NearBlocks &A, std::vector<ige
     int d = P.leaf_depth;
     if (d < 0) d = std::max(0, (int)std::ceil(std::log2((P.q + 1.0) / (P.p + 1.0)) - 1e-12));
     ige::build_discretisation(op->D, geom->G, P.p, P.level);
-    ige::build_partition(op->T, geom->G, op->D, P.eta, d);
+    ige::build_partition(op->T, geom->G, op->D, P.eta, d, P.kappa, P.kappa_cap);
     ige::build_far_tables(op->F, op->D, op->T, P.q);
     // row chunks per near-field block (tuning knob IGE_NEAR_CHUNKS, default 2)
     int nch = 2;

@@ -112,6 +112,13 @@ struct ige_srv_s {
         } catch (const std::bad_alloc &) {
             r->rc = IGE_ENOMEM;
             r->err = "host allocation failed";
+        } catch (const std::exception &e) {
+            r->rc = IGE_EINVAL;
+            r->err = std::string("request failed: ") + e.what();
+        } catch (...) {
+            // nothing may escape a worker thread (that would end the process)
+            r->rc = IGE_EINVAL;
+            r->err = "request failed with an unknown exception";
         }
         if (op) ige_op_destroy(op);
     }
@@ -131,7 +138,7 @@ struct ige_srv_s {
                 r->t_start = now();
             }
             if (rc == IGE_OK) {
-                run(r, wctx);
+                run(r, wctx);   // reports every failure in r (catches all exceptions)
             } else {
                 r->rc = rc;
                 r->err = "worker context creation failed";
@@ -180,6 +187,12 @@ int srv_guard(F &&f)
     } catch (const std::bad_alloc &) {
         ige::set_error("host allocation failed");
         return IGE_ENOMEM;
+    } catch (const std::exception &e) {
+        ige::set_error(e.what());
+        return IGE_EINVAL;
+    } catch (...) {
+        ige::set_error("unknown exception");
+        return IGE_EINVAL;
     }
 }
 

@@ -449,7 +449,8 @@ Balls level_balls(const Geometry &G, int n, int lvl, const std::vector<double> &
 
 }  // namespace
 
-void build_partition(Partition &T, const Geometry &G, const Discretisation &D, double eta, int leaf_depth)
+void build_partition(Partition &T, const Geometry &G, const Discretisation &D, double eta, int leaf_depth, double kappa,
+                     double kappa_cap)
 {
     const int n = D.n;
     T.L = std::max(0, D.m - leaf_depth);
@@ -471,7 +472,9 @@ void build_partition(Partition &T, const Geometry &G, const Discretisation &D, d
             const int t = pr.first, u = pr.second;
             const double dist = dist3(&B.c[(size_t)t * 3], &B.c[(size_t)u * 3]) - B.r[t] - B.r[u];
             const double diam = 2.0 * std::max(B.r[t], B.r[u]);
-            const bool adm = eta > 0.0 && dist > 0.0 && diam <= eta * dist * margin;
+            // optional wavenumber cap: admissible only if also kappa * diam <= kappa_cap
+            const bool adm = eta > 0.0 && dist > 0.0 && diam <= eta * dist * margin &&
+                             (kappa_cap <= 0.0 || kappa * diam <= kappa_cap * margin);
             if (adm) {
                 T.far.push_back({l, t, u});
             } else if (l == T.L) {

@@ -54,7 +54,10 @@ struct Partition {
     std::vector<std::array<int32_t, 2>> near;   // (target leaf, source leaf), sorted
 };
 
-void build_partition(Partition &T, const Geometry &G, const Discretisation &D, double eta, int leaf_depth);
+// Algorithm 1 from all ordered patch pairs with the admissibility condition
+// max diam <= eta dist; kappa_cap > 0 adds kappa * max diam <= kappa_cap
+void build_partition(Partition &T, const Geometry &G, const Discretisation &D, double eta, int leaf_depth, double kappa,
+                     double kappa_cap);
 
 // Near field as dense blocks over leaf function slots.  The functions whose
 // support meets a leaf cluster (2^d x 2^d elements, degree p) are numbered by a

@@ -695,3 +695,50 @@ def test_quartic_dense_solve_matches_lapack(oracle_mod, ctx):
     xl = np.linalg.solve(A, fo)
     _say(f"  p=4 N={op.N}: GMRES iterations {st[0][0]}, relres {st[0][2]:.1e}, vs LAPACK {_rel(x, xl):.1e}")
     assert _rel(x, xl) <= 1e-10 * np.linalg.cond(A)
+
+
+def test_kappa_cap_operator_matches_oracle(oracle_mod, ctx):
+    """The wavenumber cap of the admissibility condition (kappa * diam <= 8): same
+    partition as the oracle's and the same operator to 1e-12, one and four columns."""
+    from paper_1807_03097_amd import binding as B
+    pats = W.cube_sphere()
+    geom = B.Geometry(ctx, pats)
+    op = B.Operator(geom, 2, 4, 16.0, 8, 1.6, 5, 5, 1, kappa_cap=8.0)
+    o = oracle_mod.Oracle(pats, 2, 4, 16.0, g=5, gs=5)
+    tr = o.block_tree(1.6, 1, kappa_cap=8.0)
+    pt = op.partition()
+    assert np.array_equal(pt["far"], tr["far"]) and np.array_equal(pt["near"], tr["near"])
+    assert op.info.far_pairs > 0 and op.info.far_pairs > len(o.block_tree(1.6, 1)["far"])
+    X = np.stack([W.random_coeffs(op.N, s) for s in range(4)])
+    yo = o.fmm_apply(X[0], 8, 1.6, 1, tree=tr)
+    e1, e4 = _rel(op.apply(X[0].copy()), yo), _rel(op.apply(X)[0], yo)
+    _say(f"  far {op.info.far_pairs}: {e1:.1e} (1 column), {e4:.1e} (4 columns)")
+    assert e1 <= TOL and e4 <= TOL
+    op.close()
+
+
+@pytest.mark.parametrize("name", ["c3", "c5"])
+def test_high_kappa_rows_match_dense_with_kappa_cap(oracle_mod, ctx, name):
+    """Level 6, kappa = 16, q = 8 and the jittered level-7 sphere at kappa = 40, q = 11,
+    both with the wavenumber cap (kappa * diam <= 8 and <= 12): the HIP FMM equals the
+    oracle's FMM to 1e-12 and the dense Galerkin rows of tests/golden to 1e-6."""
+    import json
+    import os
+    from paper_1807_03097_amd import binding as B
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", f"{name}_dense_rows.json")))
+    rows = np.array(g["rows"])
+    yd = np.array(g["re"]) + 1j * np.array(g["im"])
+    cf = g["config"]
+    q, cap = (8, 8.0) if name == "c3" else (11, 12.0)
+    pats = W.cube_sphere() if name == "c3" else W.jitter(W.cube_sphere(), 0.02, 7)
+    geom = B.Geometry(ctx, pats)
+    op = B.Operator(geom, 2, cf["level"], cf["kappa"], q, 1.6, 5, 5, 3, kappa_cap=cap)
+    assert op.N == cf["n_dof"]
+    x = W.random_coeffs(op.N, 0)
+    y = op.apply(x)
+    o = oracle_mod.Oracle(pats, 2, cf["level"], cf["kappa"], g=5, gs=5)
+    yo = o.fmm_apply(x, q, 1.6, 3, rows=rows, tree=o.block_tree(1.6, 3, kappa_cap=cap))
+    err, errd = _rel(y[rows], yo), _rel(y[rows], yd)
+    _say(f"  {name}: N={op.N} far={op.info.far_pairs} vs oracle FMM {err:.1e}, vs dense {errd:.1e}")
+    assert err <= TOL and errd <= 1e-6
+    op.close()

@@ -64,6 +64,22 @@ def test_invalid_geometry_is_rejected():
         op.apply(np.zeros(op.N, np.complex128), prec=6)   # no such precision
 
 
+def test_plan_with_kappa_cap_matches_oracle(oracle_mod):
+    """The wavenumber cap of the admissibility condition gives the oracle's partition."""
+    from paper_1807_03097_amd import binding as B
+    pats = W.cube_sphere()
+    ctx = B.Context(-1)
+    g = B.Geometry(ctx, pats)
+    o = oracle_mod.Oracle(pats, 2, 4, 16.0, g=2)
+    for cap in (6.0, 8.0, 12.0):
+        op = B.Operator(g, 2, 4, 16.0, 8, 1.6, leaf_depth=2, plan_only=True, kappa_cap=cap)
+        tr = o.block_tree(1.6, 2, kappa_cap=cap)
+        pt = op.partition()
+        assert np.array_equal(pt["far"], tr["far"]) and np.array_equal(pt["near"], tr["near"])
+    with pytest.raises(B.IgeError):
+        B.Operator(g, 2, 4, 16.0, 8, 1.6, leaf_depth=2, plan_only=True, kappa_cap=-1.0)
+
+
 @pytest.mark.parametrize("geom,p,m,eta,d,q", [
     ("sphere", 1, 2, 0.0, -1, 8), ("sphere", 2, 3, 1.6, 1, 8), ("sphere", 2, 5, 1.0, 2, 8),
     ("torus", 2, 4, 1.0, 2, 6), ("cube", 1, 4, 0.7, 1, 4), ("jittered", 2, 4, 1.0, 2, 8),

@@ -451,7 +451,7 @@ def test_c2_fmm_matches_dense_rows(oracle_mod):
     sampled rows (Theorem (thm::mutlipole): the compression error decays exponentially
     in q), for leaf depth 3 (the benchmark's) and the default depth 2; q = 4 misses the
     bar, so the rows can tell.  The dense rows are stored in tests/golden/c2_dense_rows.json,
-    written by tests/golden/make_c2_dense_rows.py from the oracle alone."""
+    written by tests/golden/make_dense_rows.py from the oracle alone."""
     import json
     import os
     g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c2_dense_rows.json")))
@@ -467,6 +467,59 @@ def test_c2_fmm_matches_dense_rows(oracle_mod):
     print(errs)
     assert errs[(8, 3)] <= 1e-6 and errs[(8, 2)] <= 1e-6
     assert errs[(4, 3)] > 1e-6
+
+
+def _dense_rows(name):
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", f"{name}_dense_rows.json")))
+    return g, np.array(g["rows"]), np.array(g["re"]) + 1j * np.array(g["im"])
+
+
+@pytest.mark.slow
+def test_high_kappa_accuracy_needs_kappa_cap(oracle_mod):
+    """The admissibility condition (eq:admissibility) does not involve kappa, so at a
+    fixed q the compression error grows with kappa * diam of the coarse clusters.  On
+    sampled dense rows (tests/golden/c3_, c5_dense_rows.json, written from the oracle
+    alone): level 6, kappa = 16, q = 8, eta = 1.6 misses 1e-6 with the paper's condition
+    and meets it with kappa * diam <= 8; the jittered level-7 sphere at kappa = 40
+    loses three digits at q = 10 and meets 1e-6 with q = 11 and kappa * diam <= 12."""
+    res = {}
+    for name, jit, cases in (("c3", None, ((8, 0.0), (8, 8.0))), ("c5", (0.02, 7), ((10, 0.0), (11, 12.0)))):
+        g, rows, yd = _dense_rows(name)
+        pats = W.cube_sphere() if jit is None else W.jitter(W.cube_sphere(), *jit)
+        cf = g["config"]
+        o = oracle_mod.Oracle(pats, 2, cf["level"], cf["kappa"], g=5, gs=5)
+        assert o.N == cf["n_dof"]
+        x = W.random_coeffs(o.N, 0)
+        for q, cap in cases:
+            tr = o.block_tree(1.6, 3, kappa_cap=cap)
+            y = o.fmm_apply(x, q, 1.6, 3, rows=rows, tree=tr)
+            res[(name, q, cap)] = np.linalg.norm(y - yd) / np.linalg.norm(yd)
+    print(res)
+    assert res[("c3", 8, 0.0)] > 1e-5 and res[("c3", 8, 8.0)] <= 1e-6
+    assert res[("c5", 10, 0.0)] > 1e-4 and res[("c5", 11, 12.0)] <= 1e-6
+
+
+def test_kappa_cap_only_refines_the_partition(oracle_mod):
+    """kappa_cap > 0 keeps Algorithm 1's structure: the far blocks still satisfy
+    eq. (eq:admissibility), additionally kappa * diam <= kappa_cap, and with a cap
+    above every cluster's kappa * diam the partition is the paper's."""
+    o = oracle_mod.Oracle(W.cube_sphere(), 2, 5, 16.0, g=2)
+    base = o.block_tree(1.6, 2)
+    same = o.block_tree(1.6, 2, kappa_cap=1e6)
+    assert np.array_equal(base["far"], same["far"]) and np.array_equal(base["near"], same["near"])
+    cap = o.block_tree(1.6, 2, kappa_cap=8.0)
+    assert len(cap["far"]) > len(base["far"])
+    # blocks the cap refines end as far blocks or near pairs of the leaf level
+    bn = set(map(tuple, base["near"]))
+    assert bn <= set(map(tuple, cap["near"]))
+    for lvl in range(cap["L"] + 1):
+        cen, rad = o.bounding_balls(lvl)
+        sel = cap["far"][cap["far"][:, 0] == lvl]
+        if len(sel):
+            diam = 2 * np.maximum(rad[sel[:, 1]], rad[sel[:, 2]])
+            assert np.all(16.0 * diam <= 8.0)
 
 
 def test_fmm_error_decays_geometrically_in_q(oracle_mod):
