@@ -77,10 +77,23 @@ typedef struct {
     double kappa;
     int g, gs;                 /* regular / singular Gauss orders */
     int kernel;                /* 0 Helmholtz, 1 polynomial test kernel */
+    int scalar;                /* 1: scalar single layer (patchwise tensor B-splines of degree p,
+                                  A_ij = int int G phi_j phi_i, Sec. 4.2), 0: the EFIE */
     double gx[MAXG], gw[MAXG], sx[MAXG], sw[MAXG];
     double scale;              /* geometry size for vertex matching */
     int nthreads;
 } ctx_t;
+
+static int nloc(const void *cv)
+{
+    const ctx_t *c = (const ctx_t *)cv;
+    return c->scalar ? (c->p + 1) * (c->p + 1) : 2 * c->p * (c->p + 1);
+}
+static double dcoef(const void *cv)
+{
+    const ctx_t *c = (const ctx_t *)cv;
+    return c->scalar ? 1.0 : -1.0 / (c->kappa * c->kappa);
+}
 
 /* ------------------------------------------------------------------------- */
 /* Gauss-Legendre rule on [0,1] by Newton iteration on the Legendre recurrence */
@@ -337,6 +350,12 @@ void or_destroy(void *h)
  * NURBS map, on the unit sphere) are scaled onto the circumscribed cube, and the
  * bilinear face through them is projected radially.  For the six-patch cube-sphere
  * this is the analytic cube-sphere map, with the same corners and orientation. */
+int or_set_scalar(void *h)
+{
+    ((ctx_t *)h)->scalar = 1;
+    return 0;
+}
+
 int or_set_exact_sphere(void *h)
 {
     ctx_t *c = (ctx_t *)h;
@@ -370,7 +389,7 @@ int or_geom_eval(void *h, int j, int npts, const double *uv, double *out /* [npt
 /* Local function order on element (e1,e2): component 0 (u-flux, degree (p,p-1)):
  * i2 = e2..e2+p-1 (major), i1 = e1..e1+p (minor); then component 1 (degree (p-1,p)):
  * i2 = e2..e2+p, i1 = e1..e1+p-1. */
-static int nloc_of(int p) { return 2 * p * (p + 1); }
+
 
 typedef struct {
     int nl;
@@ -382,6 +401,18 @@ typedef struct {
 static void local_map(const ctx_t *c, int j, int e1, int e2, locmap_t *L)
 {
     int p = c->p, nb = c->nb, k = 0;
+    if (c->scalar) {   /* tensor B-splines b_{e1+t1}(u) b_{e2+t2}(v), t2 major */
+        for (int t2 = 0; t2 <= p; ++t2)
+            for (int t1 = 0; t1 <= p; ++t1) {
+                size_t o = (((size_t)j * 2) * nb + (e2 + t2)) * nb + (e1 + t1);
+                L->idx[k] = c->dof[o];
+                L->sg[k] = 1.0;
+                L->comp[k] = 0;
+                ++k;
+            }
+        L->nl = k;
+        return;
+    }
     for (int a = 0; a < 2; ++a) {
         int r1 = (a == 0) ? p + 1 : p, r2 = (a == 0) ? p : p + 1;
         for (int t2 = 0; t2 < r2; ++t2)
@@ -426,6 +457,17 @@ static void point_values(const ctx_t *c, int j, int e1, int e2, double u, double
     double bpv[MAXDEG + 1], dpv[MAXDEG + 1], bqv[MAXDEG + 1], dqv[MAXDEG + 1];
     element_pieces(c, e1, e2, u, v, bpu, dpu, bqu, dqu, bpv, dpv, bqv, dqv);
     int k = 0;
+    if (c->scalar) {   /* value times the surface element |d_uF x d_vF| in D, no field part */
+        double nx = Fu[1] * Fv[2] - Fu[2] * Fv[1], ny = Fu[2] * Fv[0] - Fu[0] * Fv[2], nz = Fu[0] * Fv[1] - Fu[1] * Fv[0];
+        double J = sqrt(nx * nx + ny * ny + nz * nz);
+        for (int t2 = 0; t2 <= p; ++t2)
+            for (int t1 = 0; t1 <= p; ++t1) {
+                pv->Phi[k][0] = pv->Phi[k][1] = pv->Phi[k][2] = 0.0;
+                pv->D[k] = bpu[t1] * bpv[t2] * J;
+                ++k;
+            }
+        return;
+    }
     for (int t2 = 0; t2 < p; ++t2)            /* component 0: b^p(u) b^{p-1}(v) */
         for (int t1 = 0; t1 <= p; ++t1) {
             double val = bpu[t1] * bqv[t2];
@@ -555,11 +597,11 @@ typedef struct {
 static void accum_point(const ctx_t *c, const pointval_t *A, const pointval_t *B, double w, int nl, cplx *blk)
 {
     cplx kv = kernel_eval(c, A->X, B->X) * w;
-    double ik2 = 1.0 / (c->kappa * c->kappa);
+    double cd = dcoef(c);
     for (int l = 0; l < nl; ++l) {
         for (int lp = 0; lp < nl; ++lp) {
             double g = A->Phi[l][0] * B->Phi[lp][0] + A->Phi[l][1] * B->Phi[lp][1] + A->Phi[l][2] * B->Phi[lp][2]
-                       - ik2 * A->D[l] * B->D[lp];
+                       + cd * A->D[l] * B->D[lp];
             blk[l * nl + lp] += kv * g;
         }
     }
@@ -570,7 +612,7 @@ static void accum_point(const ctx_t *c, const pointval_t *A, const pointval_t *B
 static void pair_regular(const ctx_t *c, const pointval_t *TA, const pointval_t *TB, int nq, const double *wq,
                          int nl, cplx *blk)
 {
-    double ik2 = 1.0 / (c->kappa * c->kappa);
+    double cd = dcoef(c);
     cplx Z[MAXLOC][4];
     for (int q = 0; q < nq; ++q) {
         for (int l = 0; l < nl; ++l) Z[l][0] = Z[l][1] = Z[l][2] = Z[l][3] = 0.0;
@@ -586,7 +628,7 @@ static void pair_regular(const ctx_t *c, const pointval_t *TA, const pointval_t 
         for (int l = 0; l < nl; ++l)
             for (int lp = 0; lp < nl; ++lp)
                 blk[l * nl + lp] += wq[q] * (TA[q].Phi[l][0] * Z[lp][0] + TA[q].Phi[l][1] * Z[lp][1] +
-                                             TA[q].Phi[l][2] * Z[lp][2] - ik2 * TA[q].D[l] * Z[lp][3]);
+                                             TA[q].Phi[l][2] * Z[lp][2] + cd * TA[q].D[l] * Z[lp][3]);
     }
 }
 
@@ -695,7 +737,7 @@ static void pair_vertex(const ctx_t *c, const elem_t *E, const elem_t *Ep, const
 static void element_pair(const ctx_t *c, const elem_t *E, const elem_t *Ep, const pointval_t *TA,
                          const pointval_t *TB, const double *wq, double CA[4][3], double CB[4][3], cplx *blk)
 {
-    int nl = nloc_of(c->p);
+    int nl = nloc(c);
     memset(blk, 0, sizeof(cplx) * nl * nl);
     int ti[4], si[4];
     int ns = shared_corners(c, CA, CB, ti, si);
@@ -724,7 +766,7 @@ static void element_pair(const ctx_t *c, const elem_t *E, const elem_t *Ep, cons
 int or_element_pair(void *h, int j, int e1, int e2, int jp, int f1, int f2, double *blk_out)
 {
     ctx_t *c = (ctx_t *)h;
-    int ng = c->g * c->g, nl = nloc_of(c->p);
+    int ng = c->g * c->g, nl = nloc(c);
     pointval_t *TA = (pointval_t *)malloc(sizeof(pointval_t) * ng);
     pointval_t *TB = (pointval_t *)malloc(sizeof(pointval_t) * ng);
     double *wq = (double *)malloc(sizeof(double) * ng);
@@ -784,7 +826,7 @@ static void ecache_free(ecache_t *ec) { free(ec->T); free(ec->w); free(ec->C); }
 int or_dense_matrix(void *h, double *Aout)
 {
     ctx_t *c = (ctx_t *)h;
-    int n = c->n, E = c->P * n * n, nl = nloc_of(c->p), ng = c->g * c->g;
+    int n = c->n, E = c->P * n * n, nl = nloc(c), ng = c->g * c->g;
     ecache_t ec;
     ecache_build(c, &ec, NULL);
     cplx *A = (cplx *)Aout;
@@ -824,7 +866,7 @@ int or_dense_matrix(void *h, double *Aout)
 int or_dense_apply(void *h, const double *xin, double *yout, const uint8_t *tmask)
 {
     ctx_t *c = (ctx_t *)h;
-    int n = c->n, E = c->P * n * n, nl = nloc_of(c->p), ng = c->g * c->g;
+    int n = c->n, E = c->P * n * n, nl = nloc(c), ng = c->g * c->g;
     const cplx *x = (const cplx *)xin;
     ecache_t ec;
     ecache_build(c, &ec, NULL);
@@ -898,10 +940,25 @@ static void field_eval(const ctx_t *c, int kind, const double *par, const double
     }
 }
 
+/* scalar Dirichlet data g for the single layer (V w = g):
+ * kind 2: point source G(x - x0) = e^{i kappa r} / (4 pi r)   (par = x0[3])
+ * kind 3: plane wave exp(i kappa dir.x)                       (par = dir[3])
+ * kind 4: the constant 1 */
+static cplx scalar_field(const ctx_t *c, int kind, const double *par, const double *x)
+{
+    if (kind == 2) {
+        double rv[3] = {x[0] - par[0], x[1] - par[1], x[2] - par[2]};
+        double r = sqrt(rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2]);
+        return cexp(I * c->kappa * r) / (4.0 * M_PI * r);
+    }
+    if (kind == 3) return cexp(I * c->kappa * (par[0] * x[0] + par[1] * x[1] + par[2] * x[2]));
+    return 1.0;
+}
+
 int or_rhs(void *h, int kind, const double *par, double *fout)
 {
     ctx_t *c = (ctx_t *)h;
-    int n = c->n, E = c->P * n * n, nl = nloc_of(c->p), ng = c->g * c->g;
+    int n = c->n, E = c->P * n * n, nl = nloc(c), ng = c->g * c->g;
     cplx *f = (cplx *)fout;
     memset(f, 0, sizeof(cplx) * c->N);
     for (int e = 0; e < E; ++e) {   /* serial: small */
@@ -914,6 +971,11 @@ int or_rhs(void *h, int kind, const double *par, double *fout)
             for (int a = 0; a < c->g; ++a) {
                 point_values(c, j, e1, e2, (e1 + c->gx[a]) * h1, (e2 + c->gx[b]) * h1, &T);
                 double w = c->gw[a] * c->gw[b] * h1 * h1;
+                if (c->scalar) {   /* f_i = int g phi_i dsigma (the surface element is in D) */
+                    cplx g = scalar_field(c, kind, par, T.X);
+                    for (int l = 0; l < nl; ++l) f[L.idx[l]] += w * g * T.D[l];
+                    continue;
+                }
                 cplx Ein[3];
                 field_eval(c, kind, par, T.X, Ein);
                 for (int l = 0; l < nl; ++l)
@@ -938,7 +1000,7 @@ int or_field(void *h, int kind, const double *par, int npts, const double *x, do
 int or_potential(void *h, const double *win, int npts, const double *x, double *Eout)
 {
     ctx_t *c = (ctx_t *)h;
-    int n = c->n, E = c->P * n * n, nl = nloc_of(c->p);
+    int n = c->n, E = c->P * n * n, nl = nloc(c);
     const cplx *w = (const cplx *)win;
     cplx *out = (cplx *)Eout;
     double k = c->kappa, h1 = 1.0 / n;
@@ -964,6 +1026,10 @@ int or_potential(void *h, const double *win, int npts, const double *x, double *
                     double rv[3] = {xp[0] - T.X[0], xp[1] - T.X[1], xp[2] - T.X[2]};
                     double rr = sqrt(rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2]);
                     cplx G = cexp(I * k * rr) / (4.0 * M_PI * rr);
+                    if (c->scalar) {   /* u(x) = int G(x - y) w(y) dsigma: value in acc[0] */
+                        acc[0] += wt * G * dv;
+                        continue;
+                    }
                     cplx dG = G * (I * k * rr - 1.0) / (rr * rr);     /* grad_x G = (x-y) dG */
                     for (int d = 0; d < 3; ++d) acc[d] += wt * (G * W[d] + dG * rv[d] * dv / (k * k));
                 }
@@ -1002,6 +1068,14 @@ int or_lagrange(int q, int npts, const double *s, double *L)
     return 0;
 }
 
+/* |d_uF x d_vF| from a node record (F, d_uF, d_vF) */
+static double surf_elem(const double *g9)
+{
+    const double *Fu = g9 + 3, *Fv = g9 + 6;
+    double nx = Fu[1] * Fv[2] - Fu[2] * Fv[1], ny = Fu[2] * Fv[0] - Fu[0] * Fv[2], nz = Fu[0] * Fv[1] - Fu[1] * Fv[0];
+    return sqrt(nx * nx + ny * ny + nz * nz);
+}
+
 /* cluster id (patch j, level l, k1, k2) -> offset within level: j*4^l + k2*2^l + k1 */
 typedef struct {
     int j, lvl, k1, k2;
@@ -1037,7 +1111,7 @@ int or_fmm_apply(void *h, int q, int L, int nfar, const int32_t *far_lvl, const 
 {
     ctx_t *c = (ctx_t *)h;
     if (q < 1 || q > MAXQ || L < 0 || L > c->m) return -1;
-    int n = c->n, E = c->P * n * n, nl = nloc_of(c->p), ng = c->g * c->g, p = c->p;
+    int n = c->n, E = c->P * n * n, nl = nloc(c), ng = c->g * c->g, p = c->p;
     int Q1 = q + 1, Q = Q1 * Q1;
     double hh = 1.0 / n, ik2 = 1.0 / (c->kappa * c->kappa);
     const cplx *x = (const cplx *)xin;
@@ -1070,6 +1144,19 @@ int or_fmm_apply(void *h, int q, int L, int nfar, const int32_t *far_lvl, const 
                 element_pieces(c, e1, e2, u, v, bpu, dpu, bqu, dqu, bpv, dpv, bqv, dqv);
                 cplx x0 = 0, x1 = 0, dv = 0;
                 int k = 0;
+                if (c->scalar) {   /* the parameter-space function x_h (no surface element) */
+                    for (int t2 = 0; t2 <= p; ++t2)
+                        for (int t1 = 0; t1 <= p; ++t1, ++k) {
+                            double val = bpu[t1] * bpv[t2];
+                            tv[(((size_t)e * nmq + g) * nl + k) * 2] = 0.0;
+                            tv[(((size_t)e * nmq + g) * nl + k) * 2 + 1] = val;
+                            dv += x[Lm.idx[k]] * val;
+                        }
+                    xv[((size_t)e * nmq + g) * 3 + 0] = 0;
+                    xv[((size_t)e * nmq + g) * 3 + 1] = 0;
+                    xv[((size_t)e * nmq + g) * 3 + 2] = dv;
+                    continue;
+                }
                 for (int t2 = 0; t2 < p; ++t2)
                     for (int t1 = 0; t1 <= p; ++t1, ++k) {
                         double val = bpu[t1] * bqv[t2], dd = dpu[t1] * bqv[t2];
@@ -1166,6 +1253,14 @@ int or_fmm_apply(void *h, int q, int L, int nfar, const int32_t *far_lvl, const 
             for (int mt = 0; mt < Q; ++mt) {
                 const double *xt = Gt + mt * 9;
                 for (int ms = 0; ms < Q; ++ms) K[ms] = kernel_eval(c, xt, Gs + ms * 9);
+                if (c->scalar) {
+                    /* scalar localized kernel G(x_m, x'_m') |J(x_m)| |J'(x'_m')| on the moments */
+                    double Jt = surf_elem(xt);
+                    cplx s = 0;
+                    for (int ms = 0; ms < Q; ++ms) s += K[ms] * surf_elem(Gs + ms * 9) * Ms[ms * 3 + 2];
+                    tl[mt * 3 + 2] += Jt * s;
+                    continue;
+                }
                 for (int a = 0; a < 2; ++a) {
                     const double *da = xt + 3 + 3 * a;
                     cplx s = 0;
@@ -1323,7 +1418,7 @@ int or_num_threads(void)
 int or_div_integrals(void *h, double *out)
 {
     ctx_t *c = (ctx_t *)h;
-    int n = c->n, E = c->P * n * n, nl = nloc_of(c->p);
+    int n = c->n, E = c->P * n * n, nl = nloc(c);
     double hh = 1.0 / n;
     memset(out, 0, sizeof(double) * c->N);
     for (int e = 0; e < E; ++e) {

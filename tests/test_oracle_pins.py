@@ -625,3 +625,70 @@ def test_mie_density_converges_at_rate_p(oracle_mod, p, lo, hi):
     print(f"p={p}: errors {errs}, ratios {ratios}")
     assert errs[0] < 0.5
     assert all(lo <= r <= hi for r in ratios)
+
+
+# ---------------------------------------------------------------------------
+# scalar single layer (Sec. 4.2: the matrices int int G phi_j phi_i the
+# interpolation-based FMM was built for)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kappa", [0.5, 2.0])
+def test_scalar_single_layer_constant_density(oracle_mod, kappa):
+    """On the unit sphere (exact map) the single layer maps the constant density to
+    lambda_0 = i kappa j_0(kappa) h_0(kappa) = sin(kappa) e^{i kappa} / kappa times
+    the constant, and the splines reproduce constants: A 1 = lambda_0 (int phi_i dsigma)_i
+    up to quadrature; the matrix is complex symmetric."""
+    lam = np.sin(kappa) * np.exp(1j * kappa) / kappa
+    for p, m, bar in ((1, 2, 1e-7), (2, 2, 1e-7), (2, 3, 1e-8)):
+        o = oracle_mod.Oracle(W.cube_sphere(), p, m, kappa, g=6, gs=6, exact_sphere=True, scalar=True)
+        assert o.N == 6 * (2 ** m + p) ** 2
+        A = o.dense_matrix()
+        b = o.rhs_scalar("one")
+        err = np.linalg.norm(A @ np.ones(o.N) - lam * b) / np.linalg.norm(lam * b)
+        assert err <= bar, (p, m, err)
+        assert np.abs(A - A.T).max() <= 1e-14 * np.abs(A).max()
+        assert np.abs(A - A.conj().T).max() > 1e-6 * np.abs(A).max()
+
+
+def test_scalar_exterior_dirichlet_point_source(oracle_mod):
+    """Exterior Dirichlet problem with the data of a point source inside the NURBS
+    sphere: u = S w with V w = G(. - x0) on Gamma reproduces G(x - x0) outside; the
+    error at r = 3 falls under refinement."""
+    x0, kappa = np.array([0.1, 0.2, -0.15]), 2.0
+    pts = oracle_mod.fibonacci_sphere(40, 3.0)
+    d = np.linalg.norm(pts - x0, axis=1)
+    ref = np.exp(1j * kappa * d) / (4 * np.pi * d)
+    for p in (1, 2):
+        errs = []
+        for m in (1, 2, 3):
+            o = oracle_mod.Oracle(W.cube_sphere(), p, m, kappa, g=5, gs=5, scalar=True)
+            w = np.linalg.solve(o.dense_matrix(), o.rhs_scalar("point", x0))
+            errs.append(np.abs(o.potential_scalar(w, pts) - ref).max() / np.abs(ref).max())
+        assert errs[0] > errs[1] > errs[2] and errs[2] < 1e-5, (p, errs)
+
+
+def test_scalar_fmm_pins(oracle_mod):
+    """The K_2-only FMM of the scalar single layer: nothing admissible gives the dense
+    operator; a polynomial test kernel on flat patches is interpolated exactly (pins
+    the scalar moments and the surface elements at the nodes); the error decays with q;
+    the compressed operator stays complex symmetric."""
+    o = oracle_mod.Oracle(W.cube_sphere(), 2, 2, 4.0, scalar=True)
+    x = W.random_coeffs(o.N, 0)
+    tr0 = o.block_tree(1e-8, 1)
+    assert np.linalg.norm(o.fmm_apply(x, 6, 1e-8, 1, tree=tr0) - o.dense_apply(x)) <= 1e-14 * np.linalg.norm(o.dense_apply(x))
+    for p, m, d, q in ((2, 2, 0, 5), (1, 3, 1, 4)):
+        oc = oracle_mod.Oracle(W.flat_cube(), p, m, 3.0, g=8, gs=8, kernel=1, scalar=True)
+        tr = oc.block_tree(1.6, d)
+        assert len(tr["far"]) > 0
+        xc = W.random_coeffs(oc.N, 2)
+        yd = oc.dense_apply(xc)
+        assert np.linalg.norm(oc.fmm_apply(xc, q, 1.6, d, tree=tr) - yd) <= 1e-12 * np.linalg.norm(yd)
+        assert np.linalg.norm(oc.fmm_apply(xc, 2, 1.6, d, tree=tr) - yd) > 1e-8 * np.linalg.norm(yd)
+    o3 = oracle_mod.Oracle(W.cube_sphere(), 2, 3, 8.0, scalar=True)
+    x3 = W.random_coeffs(o3.N, 0)
+    yd = o3.dense_apply(x3)
+    tr = o3.block_tree(1.0, 1)
+    errs = [np.linalg.norm(o3.fmm_apply(x3, q, 1.0, 1, tree=tr) - yd) / np.linalg.norm(yd) for q in (2, 4, 6, 8)]
+    assert errs[0] > errs[1] > errs[2] > errs[3] and errs[3] < 1e-8, errs
+    z = W.random_coeffs(o3.N, 4)
+    a, b = z @ o3.fmm_apply(x3, 6, 1.0, 1, tree=tr), x3 @ o3.fmm_apply(z, 6, 1.0, 1, tree=tr)
+    assert abs(a - b) <= 1e-13 * abs(a)
