@@ -76,9 +76,15 @@ def parse():
     ap.add_argument("--rate", type=float, default=20.0, help="serve: mean arrivals per second")
     ap.add_argument("--workers", type=int, default=4, help="serve: concurrent requests (one stream each)")
     ap.add_argument("--sphere-only", action="store_true", help="serve: every request on the sphere")
+    ap.add_argument("--same-object", action="store_true",
+                    help="serve: every request on the object, level, degree and kappa of the first one "
+                         "(a stream of incident directions on one scatterer)")
     ap.add_argument("--waves", type=int, default=1,
                     help="serve: plane waves per request, solved together (solves/s counts waves)")
     ap.add_argument("--maxit", type=int, default=3000, help="serve: GMRES iteration cap per request")
+    ap.add_argument("--srv-restart", type=int, default=300, help="serve: GMRES restart of every request")
+    ap.add_argument("--max-merge", type=int, default=64,
+                    help="serve: plane waves of waiting requests on one operator solved together (1: no merging)")
     ap.add_argument("--refine", action="store_true",
                     help="serve / solve: FP64 refinement around solves with the --inner-prec coupling")
     return ap.parse_args()
@@ -319,13 +325,18 @@ def run_serving(args):
     torch.cuda.set_device(0)
     ctx = B.Context(0)
     reqs = serve_requests(args.requests, 4, args.waves, args.sphere_only)
-    # one wave: a long restart (the basis is one column); several: 300, as the batched solves
-    restart = 1500 if args.waves == 1 else 300
+    restart = args.srv_restart
+    if args.same_object:
+        for rq in reqs[1:]:
+            rq.update({k: reqs[0][k] for k in ("geo", "jitter_seed", "m", "p", "kappa")})
     geoms = []
-    for rq in reqs:
+    for k, rq in enumerate(reqs):
+        if args.same_object and k > 0:
+            geoms.append(geoms[0])
+            continue
         base = W.cube_sphere() if rq["geo"] == "sphere" else W.torus()
         geoms.append(B.Geometry(ctx, W.jitter(base, 0.01, rq["jitter_seed"])))
-    srv = B.Server(ctx, args.workers)
+    srv = B.Server(ctx, args.workers, max_merge=args.max_merge)
     t0 = time.perf_counter()
     arrival, tickets = [], []
     t_next = 0.0
@@ -351,7 +362,7 @@ def run_serving(args):
     for k, (rq, st) in enumerate(zip(reqs, stats)):
         log(f"req {k:3d} {rq['geo']:6s} m={rq['m']} p={rq['p']} kappa={rq['kappa']:5.2f} N={st['n_dof']:6d} "
             f"iters={st['iters']:5d} relres={st['relres']:.1e} rc={st['rc']} asm={st['assemble_s']:.3f}s "
-            f"solve={st['solve_s']:.3f}s latency={lat[k]:.3f}s")
+            f"solve={st['solve_s']:.3f}s latency={lat[k]:.3f}s merged={st['merged']} reused={st['reused']}")
     out = {
         "metric": "EFIE serving solves/s",
         "value": len(done) * args.waves / span,
@@ -367,16 +378,22 @@ def run_serving(args):
         "requests": len(stats),
         "span_s": span,
         "config": {"workload": f"{len(reqs)} solves, exponential arrivals at {args.rate}/s (seed 4); "
+                               + ("one object (the first request's: " + f"{reqs[0]['geo']} m={reqs[0]['m']} "
+                                  f"p={reqs[0]['p']} kappa={reqs[0]['kappa']:.2f}), random plane waves; "
+                                  if args.same_object else "")
                                + ("sphere" if args.sphere_only else "sphere or torus") + ", control-point jitter N(0, 0.01^2), m in 3..6, p in 1..2, kappa in [1, 20], "
                                f"q=8, eta={args.eta}, {args.waves} plane wave(s) per request, GMRES tol 1e-6, "
                                f"restart {restart}, maxit {args.maxit}",
-                   "workers": args.workers, "refine": bool(args.refine), "waves_per_request": args.waves},
+                   "workers": args.workers, "refine": bool(args.refine), "waves_per_request": args.waves,
+                   "max_merge": args.max_merge, "same_object": bool(args.same_object)},
+        "merged_requests": int(sum(1 for st in stats if st["merged"] > 1)),
+        "reused_operator": int(sum(1 for st in stats if st["reused"])),
         "requests_s": len(done) / span,
         "total_iters": int(sum(st["iters"] for st in stats)),
         "total_dof": int(sum(st["n_dof"] for st in stats)),
     }
     print(json.dumps(out), flush=True)
-    for g in geoms:
+    for g in set(geoms):
         g.close()
     ctx.close()
 

@@ -64,7 +64,9 @@ const char *ige_version(void);
  * host-only context that can create geometries and plan operators (ige_op_plan)
  * but not assemble or apply them; it makes no HIP call.
  * hip_stream: a hipStream_t to order all work on, or NULL for a stream the context
- * creates and owns.  One context per host thread. */
+ * creates and owns.  One context per host thread.
+ * ige_ctx_destroy: IGE_EINVAL while geometries, operators or servers made on the
+ * context are not yet destroyed (they use its device and stream). */
 int ige_ctx_create(int device, void *hip_stream, ige_ctx *out);
 int ige_ctx_destroy(ige_ctx ctx);
 
@@ -105,7 +107,17 @@ int ige_geom_destroy(ige_geom geom);
  *                 does not involve kappa; > 0: a block is admissible only if also
  *                 kappa * max diam <= kappa_cap (coarse clusters many wavelengths
  *                 wide are refined further, so the fixed q keeps its accuracy at high
- *                 kappa; more, smaller far blocks). */
+ *                 kappa; more, smaller far blocks).
+ *   kind          IGE_OP_EFIE (0): the EFIE matrix above on S^1;
+ *                 IGE_OP_SCALAR (1): the scalar Helmholtz single layer
+ *                     A_ij = int int G_k(x-y) phi_j(y) phi_i(x) dsigma dsigma
+ *                 on the patchwise tensor B-splines of degree p (Sec. 3.2 with the
+ *                 scalar space in place of S^1: (2^m + p)^2 functions per patch, no
+ *                 continuity across patches, unknowns ordered patch, i2, i1), compressed
+ *                 with the K_2 block alone (eq:FMMlr with the surface elements inside
+ *                 the localized kernel).  The scalar operator applies and solves in FP64
+ *                 only; refinement, autotuning, plane-wave fields and serving refuse it. */
+enum { IGE_OP_EFIE = 0, IGE_OP_SCALAR = 1 };
 typedef struct {
     int p, level;
     double kappa;
@@ -114,6 +126,7 @@ typedef struct {
     int gauss_near, gauss_singular, leaf_depth;
     int store_coupling;
     double kappa_cap;
+    int kind;
 } ige_params;
 
 /* Assemble the operator on the device: element and cluster-node geometry, the
@@ -253,6 +266,16 @@ int ige_op_stage_times(ige_op op, double *ms, int n);
  * current w with e_s = V~ w (eq:ESLP). */
 int ige_rhs_plane_wave(ige_op op, int r, const double *dir, const ige_c64 *pol, ige_c64 *f, int ptr_kind);
 
+/* Right-hand side of the scalar single layer (kind IGE_OP_SCALAR), the Galerkin
+ * moments f_i = int_Gamma g phi_i dsigma of r Dirichlet data g (Sec. 2.2: V u = g
+ * with the element quadrature of the near field, g x g points per element):
+ *   kind IGE_RHS_PLANE: g(x) = exp(i kappa a.x), a a unit direction;
+ *   kind IGE_RHS_POINT: g(x) = G_k(x - a), a point source at a (off the surface).
+ * a [r][3] (host); f: N*r complex in ptr_kind memory.  IGE_EINVAL on the EFIE
+ * operator, a bad kind or non-finite a. */
+enum { IGE_RHS_PLANE = 0, IGE_RHS_POINT = 1 };
+int ige_rhs_scalar(ige_op op, int r, int kind, const double *a, ige_c64 *f, int ptr_kind);
+
 typedef struct {
     double tol;      /* stop at ||f - A x|| <= tol ||f|| (relative, FP64 operator, x0 as passed) */
     int restart;     /* Krylov basis size before restart (>= 1) */
@@ -291,7 +314,7 @@ typedef struct {
 int ige_solve(ige_op op, int r, const ige_c64 *f, ige_c64 *x, int ptr_kind, const ige_solve_opts *opts,
               ige_solve_stats *stats);
 
-/* ---- Serving: many independent scattering solves on one device --------------
+/* ---- Serving: scattering solves as they arrive, on one device ----------------
  * A server owns n_workers host threads, each with its own HIP stream on the device
  * of ctx, so the assembly and solve kernels of several requests share the device.
  * A request is one full solve: the operator of geom with the parameters prm
@@ -303,10 +326,19 @@ int ige_solve(ige_op op, int r, const ige_c64 *f, ige_c64 *x, int ptr_kind, cons
  * footprint (planned on the host at submission: near-field blocks, element and
  * cluster data, Krylov bases of opts.restart vectors per wave, the copies of the
  * blocks that the many-column kernels and the refinement precision make) fits in
- * hbm_budget next to the running requests; the oldest waiting request is overtaken
- * only during its first second of waiting.  hbm_budget 0: 80 % of the free device memory.
- * The caller keeps geom alive until its requests have finished.  Requests that
- * run concurrently share the device and do not synchronise with each other.
+ * hbm_budget next to the running requests and the resident operators; the oldest
+ * waiting request is overtaken only during its first second of waiting.
+ * hbm_budget 0: 80 % of the free device memory.
+ * Continuous batching: a worker that takes a request also takes the waiting requests
+ * on the same operator (same geom handle and prm) with the same opts, up to
+ * max_merge plane waves in all (ige_srv_set_merge, default 64), and solves all their
+ * waves as one many-column system (results as for a direct ige_solve of those
+ * columns together); a request solved alone gives the same bits as a direct solve.
+ * Residency: a worker keeps the assembled operator of its last solve on the device
+ * and prefers waiting requests on it (no second assembly); resident operators count
+ * in the budget and are freed when a waiting request needs their memory.
+ * The caller keeps geom alive until its requests have finished.  Requests that run
+ * concurrently share the device and do not synchronise with each other.
  * Timestamps are seconds since the server was created. */
 typedef struct ige_srv_s *ige_srv;
 typedef struct {
@@ -319,6 +351,8 @@ typedef struct {
     double t_submit, t_start, t_done;
     double assemble_s, solve_s;
     int n_waves;         /* plane waves of the request; iters and relres are the largest over them */
+    int merged;          /* requests solved together in its solve (1: alone) */
+    int reused;          /* 1: ran on an operator already resident on the device */
 } ige_srv_stats;
 int ige_srv_create(ige_ctx ctx, int n_workers, size_t hbm_budget, ige_srv *out);
 /* Queue one request; returns at once with its ticket.  IGE_ENOMEM if its footprint
@@ -331,6 +365,9 @@ int ige_srv_submit(ige_srv srv, ige_geom geom, const ige_params *prm, const doub
  * incident directions). */
 int ige_srv_submit_waves(ige_srv srv, ige_geom geom, const ige_params *prm, int n_waves, const double *dir,
                          const ige_c64 *pol, const ige_solve_opts *opts, int64_t *ticket);
+/* Largest number of plane waves solved together by merging waiting requests on one
+ * operator (1: no merging).  Applies to requests submitted afterwards. */
+int ige_srv_set_merge(ige_srv srv, int max_waves);
 int ige_srv_poll(ige_srv srv, int64_t ticket, ige_srv_stats *stats);   /* non-blocking */
 int ige_srv_wait(ige_srv srv, int64_t ticket, ige_srv_stats *stats);   /* blocks until finished */
 /* Copy a finished request's solutions (n = n_waves * n_dof complex values, [n_waves][n_dof])
@@ -344,7 +381,10 @@ int ige_srv_destroy(ige_srv srv);
  *   e_s(x) = int G(x-y) w(y) + kappa^-2 grad_x int G(x-y) div w(y) dsigma(y),
  * each element integrated with the g x g Gauss rule of the near field, so points
  * should stay a few element sizes away from the surface.  E: [r][npts][3] complex,
- * host memory.  Synchronous; uses temporary device memory (E * g^2 * 88 bytes). */
+ * host memory.  Synchronous; uses temporary device memory (E * g^2 * 88 bytes).
+ * On the scalar single layer (kind IGE_OP_SCALAR) component 0 of each point holds
+ * the single layer potential u(x) = int G(x-y) w(y) dsigma(y) and components 1, 2
+ * are zero. */
 int ige_potential(ige_op op, int r, const ige_c64 *w, int ptr_kind, int npts, const double *points, ige_c64 *E);
 
 /* ige_potential for callers that cannot allocate device memory (code under HIP graph

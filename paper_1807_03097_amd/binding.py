@@ -12,6 +12,7 @@ from __future__ import annotations
 import ctypes as C
 import os
 import sys
+import weakref
 
 import numpy as np
 
@@ -31,7 +32,7 @@ class IgeError(RuntimeError):
 class ige_params(C.Structure):
     _fields_ = [("p", C.c_int), ("level", C.c_int), ("kappa", C.c_double), ("q", C.c_int), ("eta", C.c_double),
                 ("gauss_near", C.c_int), ("gauss_singular", C.c_int), ("leaf_depth", C.c_int),
-                ("store_coupling", C.c_int), ("kappa_cap", C.c_double)]
+                ("store_coupling", C.c_int), ("kappa_cap", C.c_double), ("kind", C.c_int)]
 
 
 class ige_op_info_t(C.Structure):
@@ -42,6 +43,8 @@ class ige_op_info_t(C.Structure):
 
 
 IGE_F64, IGE_F32, IGE_BF16, IGE_BF16X3, IGE_BF16X3_ALL = 0, 1, 2, 3, 4
+IGE_OP_EFIE, IGE_OP_SCALAR = 0, 1
+IGE_RHS_PLANE, IGE_RHS_POINT = 0, 1
 
 
 class ige_solve_opts(C.Structure):
@@ -57,7 +60,7 @@ class ige_srv_stats(C.Structure):
     _fields_ = [("state", C.c_int), ("rc", C.c_int), ("iters", C.c_int), ("relres", C.c_double),
                 ("n_dof", C.c_int64), ("footprint", C.c_size_t), ("t_submit", C.c_double),
                 ("t_start", C.c_double), ("t_done", C.c_double), ("assemble_s", C.c_double),
-                ("solve_s", C.c_double), ("n_waves", C.c_int)]
+                ("solve_s", C.c_double), ("n_waves", C.c_int), ("merged", C.c_int), ("reused", C.c_int)]
 
 
 # One HIP runtime per process: torch ships its own libamdhip64 (same soname);
@@ -93,6 +96,7 @@ _SIGS = {
     "ige_op_stage_times": (C.c_int, [_V, _V, C.c_int]),
     "ige_op_autotune": (C.c_int, [_V, C.c_int, C.c_int, _V, C.c_int]),
     "ige_rhs_plane_wave": (C.c_int, [_V, C.c_int, _V, _V, _V, C.c_int]),
+    "ige_rhs_scalar": (C.c_int, [_V, C.c_int, C.c_int, _V, _V, C.c_int]),
     "ige_solve": (C.c_int, [_V, C.c_int, _V, _V, C.c_int, C.POINTER(ige_solve_opts), _V]),
     "ige_helmholtz_eval": (C.c_int, [_V, C.c_int64, C.c_double, _V, _V, C.c_int]),
     "ige_potential": (C.c_int, [_V, C.c_int, _V, C.c_int, C.c_int, _V, _V]),
@@ -102,6 +106,7 @@ _SIGS = {
                                  C.POINTER(C.c_int64)]),
     "ige_srv_submit_waves": (C.c_int, [_V, _V, C.POINTER(ige_params), C.c_int, _V, _V,
                                        C.POINTER(ige_solve_opts), C.POINTER(C.c_int64)]),
+    "ige_srv_set_merge": (C.c_int, [_V, C.c_int]),
     "ige_srv_poll": (C.c_int, [_V, C.c_int64, C.POINTER(ige_srv_stats)]),
     "ige_srv_wait": (C.c_int, [_V, C.c_int64, C.POINTER(ige_srv_stats)]),
     "ige_srv_result": (C.c_int, [_V, C.c_int64, _V, C.c_int64]),
@@ -222,6 +227,11 @@ def ige_rhs_plane_wave(op, r, dirs, pols, f, ptr_kind):
     _check(_lib.ige_rhs_plane_wave(op, r, _ptr(dirs), _ptr(pols), _ptr(f), ptr_kind))
 
 
+def ige_rhs_scalar(op, r, kind, a, f, ptr_kind):
+    a = np.ascontiguousarray(a, np.float64)
+    _check(_lib.ige_rhs_scalar(op, r, kind, _ptr(a), _ptr(f), ptr_kind))
+
+
 def ige_solve(op, r, f, x, ptr_kind, opts: ige_solve_opts, stats=None):
     arr = (ige_solve_stats * r)() if stats is None else stats
     rc = _lib.ige_solve(op, r, _ptr(f), _ptr(x), ptr_kind, C.byref(opts), C.cast(arr, _V))
@@ -244,9 +254,17 @@ class Context:
     def __init__(self, device: int = 0, stream=None):
         self.device = device
         self.h = ige_ctx_create(device, stream)
+        self._deps = weakref.WeakSet()   # geometries, operators and servers made on it
 
     def close(self):
+        """Destroy the context; servers, operators and geometries still open on it are
+        closed first (the library refuses to destroy a context that has any)."""
         if self.h:
+            deps = list(self._deps)
+            for kind in (Server, Operator, Geometry):
+                for d in deps:
+                    if isinstance(d, kind):
+                        d.close()
             ige_ctx_destroy(self.h)
             self.h = None
 
@@ -264,6 +282,7 @@ class Geometry:
         from . import workloads
         self.ctx = ctx
         self.h = ige_geom_create(ctx.h, *workloads.pack(patches))
+        ctx._deps.add(self)
 
     def close(self):
         if self.h:
@@ -282,11 +301,12 @@ class Geometry:
 class Operator:
     def __init__(self, geom: Geometry, p: int, level: int, kappa: float, q: int = 8, eta: float = 1.0,
                  gauss_near: int = 5, gauss_singular: int = 5, leaf_depth: int = -1, plan_only: bool = False,
-                 store_coupling: int = -1, kappa_cap: float = 0.0):
+                 store_coupling: int = -1, kappa_cap: float = 0.0, kind: int = IGE_OP_EFIE):
         self.geom = geom
         self.prm = ige_params(p, level, kappa, q, eta, gauss_near, gauss_singular, leaf_depth, store_coupling,
-                              kappa_cap)
+                              kappa_cap, kind)
         self.h = ige_op_plan(geom.h, self.prm) if plan_only else ige_op_assemble(geom.h, self.prm)
+        geom.ctx._deps.add(self)
         self.info = ige_op_info(self.h)
         self.N = int(self.info.n_dof)
         self.p, self.level = p, level
@@ -344,6 +364,16 @@ class Operator:
         if out is None:
             out = np.zeros((r, self.N), np.complex128)
         ige_rhs_plane_wave(self.h, r, dirs, np.atleast_2d(pols), out, _kind(out))
+        return out
+
+    def rhs_scalar(self, kind, a, out=None):
+        """scalar single layer data moments: kind IGE_RHS_PLANE (a: directions) or
+        IGE_RHS_POINT (a: source points), a of shape (3,) or (r, 3)"""
+        a = np.atleast_2d(np.asarray(a, np.float64))
+        r = a.shape[0]
+        if out is None:
+            out = np.zeros((r, self.N), np.complex128)
+        ige_rhs_scalar(self.h, r, int(kind), a, out, _kind(out))
         return out
 
     def solve(self, f, x0=None, tol=1e-8, restart=1500, maxit=10000, refine=False, inner_tol=1e-4,
@@ -448,15 +478,18 @@ def _stats_dict(st):
 class Server:
     """Queue of independent scattering solves on one device (see ige_srv_create)."""
 
-    def __init__(self, ctx: Context, n_workers: int = 4, hbm_budget: int = 0):
+    def __init__(self, ctx: Context, n_workers: int = 4, hbm_budget: int = 0, max_merge: int | None = None):
         self.ctx = ctx
         self.h = ige_srv_create(ctx.h, n_workers, hbm_budget)
+        ctx._deps.add(self)
         self._geoms = {}
+        if max_merge is not None:
+            _check(_lib.ige_srv_set_merge(self.h, int(max_merge)))
 
     def submit(self, geom: Geometry, p, level, kappa, direction, pol, q=8, eta=1.0, leaf_depth=-1,
                gauss_near=5, gauss_singular=5, tol=1e-6, restart=1500, maxit=10000, refine=False,
-               inner_tol=1e-4, inner_prec=IGE_F32, kappa_cap=0.0):
-        prm = ige_params(p, level, kappa, q, eta, gauss_near, gauss_singular, leaf_depth, 0, kappa_cap)
+               inner_tol=1e-4, inner_prec=IGE_F32, kappa_cap=0.0, kind=IGE_OP_EFIE):
+        prm = ige_params(p, level, kappa, q, eta, gauss_near, gauss_singular, leaf_depth, 0, kappa_cap, kind)
         opts = ige_solve_opts(tol, restart, maxit, int(refine), inner_tol, inner_prec)
         if np.ndim(direction) == 2:   # [W][3] directions and polarisations: one request of W waves
             t = ige_srv_submit_waves(self.h, geom.h, prm, direction, pol, opts)

@@ -43,7 +43,13 @@ int guard(F &&f)
 
 using ige::DBuf;
 
-void set_device(ige_ctx ctx) { IGE_HIP(hipSetDevice(ctx->device)); }
+// the device of ctx, with the calling thread's last-error state cleared: an error left
+// by unrelated code on this thread must not be taken for a failed launch of ours
+void set_device(ige_ctx ctx)
+{
+    IGE_HIP(hipSetDevice(ctx->device));
+    (void)hipGetLastError();
+}
 
 double2 c2(std::complex<double> z) { return make_double2(z.real(), z.imag()); }
 std::complex<double> cz(double2 a) { return {a.x, a.y}; }
@@ -191,6 +197,7 @@ int ige_ctx_destroy(ige_ctx ctx)
 {
     return guard([&] {
         if (!ctx) return;
+        IGE_REQUIRE(ctx->users.load() == 0, "the context still has geometries, operators or servers: destroy them first");
         if (ctx->device < 0) {
             delete ctx;
             return;
@@ -216,13 +223,18 @@ int ige_geom_create(ige_ctx ctx, int n_patches, const int *degree, const int *n_
             delete g;
             throw;
         }
+        ctx->users++;
         *out = g;
     });
 }
 
 int ige_geom_destroy(ige_geom geom)
 {
-    return guard([&] { delete geom; });
+    return guard([&] {
+        if (!geom) return;
+        geom->ctx->users--;
+        delete geom;
+    });
 }
 
 namespace {
@@ -239,6 +251,7 @@ void check_params(const ige_params &P)
     IGE_REQUIRE(P.leaf_depth >= -1 && P.leaf_depth <= 10, "leaf_depth must be -1..10");
     IGE_REQUIRE(P.store_coupling >= -1 && P.store_coupling <= 1, "store_coupling must be -1, 0 or 1");
     IGE_REQUIRE(std::isfinite(P.kappa_cap) && P.kappa_cap >= 0.0, "kappa_cap must be >= 0");
+    IGE_REQUIRE(P.kind == IGE_OP_EFIE || P.kind == IGE_OP_SCALAR, "kind must be IGE_OP_EFIE or IGE_OP_SCALAR");
 }
 
 // host part: unknowns, trees, near pattern, singular pairs, far tables
@@ -247,7 +260,7 @@ void plan(ige_op op, const ige_geom_s *geom, ige::NearBlocks &A, std::vector<ige
     const ige_params &P = op->prm;
     int d = P.leaf_depth;
     if (d < 0) d = std::max(0, (int)std::ceil(std::log2((P.q + 1.0) / (P.p + 1.0)) - 1e-12));
-    ige::build_discretisation(op->D, geom->G, P.p, P.level);
+    ige::build_discretisation(op->D, geom->G, P.p, P.level, P.kind == IGE_OP_SCALAR ? 1 : 0);
     ige::build_partition(op->T, geom->G, op->D, P.eta, d, P.kappa, P.kappa_cap);
     ige::build_far_tables(op->F, op->D, op->T, P.q);
     // row chunks per near-field block (tuning knob IGE_NEAR_CHUNKS, default 2)
@@ -279,9 +292,9 @@ size_t ige::planned_device_bytes(const ige_op_s *op, int restart, int r, const i
 {
     const ige::Discretisation &D = op->D;
     const int64_t E = (int64_t)D.P * D.n * D.n;
-    const int p = D.p, nl = 2 * p * (p + 1), g = op->prm.gauss_near, G2 = g * g;
+    const int p = D.p, nl = D.scalar ? (p + 1) * (p + 1) : 2 * p * (p + 1), g = op->prm.gauss_near, G2 = g * g;
     const int Q = (op->prm.q + 1) * (op->prm.q + 1);
-    const int s = op->T.s, W = s + p, nF = 2 * W * (W - 1);
+    const int s = op->T.s, W = s + p, nF = D.scalar ? W * W : 2 * W * (W - 1);
     const int64_t nblk = nF > 0 ? op->nnz / ((int64_t)nF * nF) : 0;
     const size_t R = (size_t)std::max(1, r);
     const size_t nfp = op->T.far.size() / 2, Qp = 32 * (((size_t)Q + 31) / 32), Qn = 32 * (((size_t)nF + 31) / 32);
@@ -340,6 +353,7 @@ int ige_op_plan(ige_geom geom, const ige_params *prm, ige_op *out)
         }
         op->assemble_ms =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        op->ctx->users++;
         *out = op;
     });
 }
@@ -369,7 +383,11 @@ ige_op ige::assemble_on(ige_ctx ctx, const ige_geom_s *geom, const ige_params &p
             const auto &T = op->T;
             const auto &F = op->F;
             ige::DevOp &v = op->view;
-            v.P = D.P; v.p = D.p; v.m = D.m; v.n = D.n; v.nb = D.nb; v.N = D.N; v.nl = 2 * D.p * (D.p + 1);
+            v.P = D.P; v.p = D.p; v.m = D.m; v.n = D.n; v.nb = D.nb; v.N = D.N;
+            v.scalar = D.scalar;
+            v.nl = D.scalar ? (D.p + 1) * (D.p + 1) : 2 * D.p * (D.p + 1);
+            // factor of the value / divergence term: 1 (scalar), -kappa^-2 (EFIE)
+            v.cdiv = D.scalar ? 1.0 : -1.0 / (P.kappa * P.kappa);
             v.L = T.L; v.s = T.s; v.SL = 1 << T.L;
             v.q = P.q; v.Q1 = P.q + 1; v.Q = v.Q1 * v.Q1;
             v.g = P.gauss_near; v.G2 = v.g * v.g; v.gs = P.gauss_singular;
@@ -674,6 +692,7 @@ ige_op ige::assemble_on(ige_ctx ctx, const ige_geom_s *geom, const ige_params &p
         }
         op->assemble_ms =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        ctx->users++;
         result = op;
     }
     return result;
@@ -693,6 +712,7 @@ int ige_op_destroy(ige_op op)
 {
     return guard([&] {
         if (!op) return;
+        op->ctx->users--;
         if (!op->assembled) {
             delete op;
             return;
@@ -936,15 +956,20 @@ void apply_dev(ige_op op, int r, const double2 *x, double2 *y, int prec, ApplyGr
     const bool graph = g && !op->profiling && graphs_enabled();
     hipStream_t s = op->ctx->stream;
     const int64_t N = op->D.N;
-    if (r == 1 && prec <= IGE_F32) {
-        if (!graph) {
-            apply_one(op, x, y, prec);
-            return;
+    // the scalar single layer runs column by column on the single-vector kernels
+    if ((r == 1 && prec <= IGE_F32) || op->view.scalar) {
+        for (int c = 0; c < r; ++c) {
+            const double2 *xc = x + (size_t)c * N;
+            double2 *yc = y + (size_t)c * N;
+            if (!graph) {
+                apply_one(op, xc, yc, prec);
+                continue;
+            }
+            ensure_staging(op);
+            IGE_HIP(hipMemcpyAsync(op->d_x.p, xc, sizeof(double2) * N, hipMemcpyDeviceToDevice, s));
+            run_graph(op, g, 1, prec, [&] { apply_one(op, op->d_x.p, op->d_y.p, prec); });
+            IGE_HIP(hipMemcpyAsync(yc, op->d_y.p, sizeof(double2) * N, hipMemcpyDeviceToDevice, s));
         }
-        ensure_staging(op);
-        IGE_HIP(hipMemcpyAsync(op->d_x.p, x, sizeof(double2) * N, hipMemcpyDeviceToDevice, s));
-        run_graph(op, g, r, prec, [&] { apply_one(op, op->d_x.p, op->d_y.p, prec); });
-        IGE_HIP(hipMemcpyAsync(y, op->d_y.p, sizeof(double2) * N, hipMemcpyDeviceToDevice, s));
         return;
     }
     ensure_batched(op, r);
@@ -969,6 +994,7 @@ int apply_impl(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind, int
         IGE_REQUIRE(op->assembled, "operator was planned, not assembled");
         IGE_REQUIRE(ptr_kind == IGE_HOST || ptr_kind == IGE_DEVICE, "bad ptr_kind");
         IGE_REQUIRE(prec >= IGE_F64 && prec <= IGE_BF16X3_ALL, "bad coupling precision");
+        IGE_REQUIRE(!op->view.scalar || prec == IGE_F64, "the scalar single layer applies in FP64 only");
         set_device(op->ctx);
         const int64_t N = op->D.N;
         hipStream_t s = op->ctx->stream;
@@ -1005,6 +1031,7 @@ int ige_op_autotune(ige_op op, int r, int prec, int *choice, int nchoice)
         IGE_REQUIRE(op && r >= 1 && (choice || nchoice == 0), "bad autotune arguments");
         IGE_REQUIRE(op->assembled, "operator was planned, not assembled");
         IGE_REQUIRE(prec >= IGE_F64 && prec <= IGE_BF16X3_ALL, "bad precision");
+        IGE_REQUIRE(!op->view.scalar, "autotuning covers the EFIE operator only");
         set_device(op->ctx);
         const int64_t N = op->D.N;
         hipStream_t s = op->ctx->stream;
@@ -1109,11 +1136,38 @@ int ige_op_autotune(ige_op op, int r, int prec, int *choice, int nchoice)
     return rc == IGE_OK ? tried : rc;
 }
 
+int ige_rhs_scalar(ige_op op, int r, int kind, const double *a, ige_c64 *f, int ptr_kind)
+{
+    return guard([&] {
+        IGE_REQUIRE(op && a && f && r >= 1, "bad rhs arguments");
+        IGE_REQUIRE(op->assembled, "operator was planned, not assembled");
+        IGE_REQUIRE(op->view.scalar, "the operator is not the scalar single layer");
+        IGE_REQUIRE(kind == IGE_RHS_PLANE || kind == IGE_RHS_POINT, "kind must be IGE_RHS_PLANE or IGE_RHS_POINT");
+        IGE_REQUIRE(ptr_kind == IGE_HOST || ptr_kind == IGE_DEVICE, "bad ptr_kind");
+        set_device(op->ctx);
+        const int64_t N = op->D.N;
+        hipStream_t s = op->ctx->stream;
+        if (ptr_kind == IGE_HOST) ensure_staging(op);
+        for (int c = 0; c < r; ++c) {
+            const double *ac = a + 3 * c;
+            IGE_REQUIRE(std::isfinite(ac[0]) && std::isfinite(ac[1]) && std::isfinite(ac[2]), "a must be finite");
+            double2 *fc = reinterpret_cast<double2 *>(f) + (size_t)c * N;
+            double2 *dst = (ptr_kind == IGE_HOST) ? op->d_y.p : fc;
+            ige::launch_rhs_scalar(op, kind, ac, dst);
+            if (ptr_kind == IGE_HOST) {
+                IGE_HIP(hipMemcpyAsync(fc, op->d_y.p, sizeof(double2) * N, hipMemcpyDeviceToHost, s));
+                IGE_HIP(hipStreamSynchronize(s));
+            }
+        }
+    });
+}
+
 int ige_rhs_plane_wave(ige_op op, int r, const double *dir, const ige_c64 *pol, ige_c64 *f, int ptr_kind)
 {
     return guard([&] {
         IGE_REQUIRE(op && dir && pol && f && r >= 1, "bad rhs arguments");
         IGE_REQUIRE(op->assembled, "operator was planned, not assembled");
+        IGE_REQUIRE(!op->view.scalar, "the operator is the scalar single layer: use ige_rhs_scalar");
         IGE_REQUIRE(ptr_kind == IGE_HOST || ptr_kind == IGE_DEVICE, "bad ptr_kind");
         set_device(op->ctx);
         const int64_t N = op->D.N;
@@ -1355,6 +1409,7 @@ int ige_solve(ige_op op, int r, const ige_c64 *f, ige_c64 *x, int ptr_kind, cons
                     "bad inner precision");
         IGE_REQUIRE(!opts->refine || (std::isfinite(opts->inner_tol) && opts->inner_tol > 0.0 && opts->inner_tol < 1.0),
                     "inner_tol must be in (0, 1)");
+        IGE_REQUIRE(!op->view.scalar || !opts->refine, "the scalar single layer solves in FP64 only (no refinement)");
         set_device(op->ctx);
         const auto t0 = std::chrono::steady_clock::now();
         const int64_t N = op->D.N;

@@ -205,9 +205,17 @@ __device__ inline void geom_eval(const GeomView &g, int j, double u, double v, d
     else geom_eval_generic(g, j, u, v, X, Xu, Xv);
 }
 
-// local glued function l of an element: (component, t1, t2)
-__device__ inline void local_index(int p, int l, int &a, int &t1, int &t2)
+// local function l of an element: (component, t1, t2); the scalar operator has the
+// (p+1)^2 tensor B-splines, t2 major, in component 0
+__device__ inline void local_index(const DevOp &o, int l, int &a, int &t1, int &t2)
 {
+    const int p = o.p;
+    if (o.scalar) {
+        a = 0;
+        t2 = l / (p + 1);
+        t1 = l % (p + 1);
+        return;
+    }
     const int n0 = p * (p + 1);
     if (l < n0) {
         a = 0;
@@ -221,7 +229,15 @@ __device__ inline void local_index(int p, int l, int &a, int &t1, int &t2)
     }
 }
 
+// surface element |d_uF x d_vF|
+__device__ inline double surf_elem(const double Fu[3], const double Fv[3])
+{
+    const double nx = Fu[1] * Fv[2] - Fu[2] * Fv[1], ny = Fu[2] * Fv[0] - Fu[0] * Fv[2], nz = Fu[0] * Fv[1] - Fu[1] * Fv[0];
+    return sqrt(fma(nx, nx, fma(ny, ny, nz * nz)));
+}
+
 // values of the local functions at element-local (x, y): Phi (3) and div, unsigned
+// (scalar operator: Phi = 0 and the value times the surface element in place of div)
 template <int NL>
 __device__ inline void local_values(const DevOp &o, int e1, int e2, double x, double y, const double Fu[3],
                                     const double Fv[3], double Phi[NL][3], double Dv[NL])
@@ -229,11 +245,21 @@ __device__ inline void local_values(const DevOp &o, int e1, int e2, double x, do
     double Pu[kMaxP + 1], dPu[kMaxP + 1], Qu[kMaxP + 1], Pv[kMaxP + 1], dPv[kMaxP + 1], Qv[kMaxP + 1];
     spline_pieces(o, e1, x, Pu, dPu, Qu);
     spline_pieces(o, e2, y, Pv, dPv, Qv);
-    const int p = o.p;
+    if (o.scalar) {   // value times the surface element, no field part
+        const double J = surf_elem(Fu, Fv);
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+            int a, t1, t2;
+            local_index(o, l, a, t1, t2);
+            Phi[l][0] = Phi[l][1] = Phi[l][2] = 0.0;
+            Dv[l] = Pu[t1] * Pv[t2] * J;
+        }
+        return;
+    }
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
         int a, t1, t2;
-        local_index(p, l, a, t1, t2);
+        local_index(o, l, a, t1, t2);
         double val, div;
         if (a == 0) {
             val = Pu[t1] * Qv[t2];
@@ -258,11 +284,21 @@ __device__ inline void local_values_lds(const DevOp &o, int e1, int e2, double x
     double Pu[kMaxP + 1], dPu[kMaxP + 1], Qu[kMaxP + 1], Pv[kMaxP + 1], dPv[kMaxP + 1], Qv[kMaxP + 1];
     spline_pieces(o, e1, x, Pu, dPu, Qu);
     spline_pieces(o, e2, y, Pv, dPv, Qv);
-    const int p = o.p;
+    if (o.scalar) {
+        const double J = surf_elem(Fu, Fv);
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+            int a, t1, t2;
+            local_index(o, l, a, t1, t2);
+            dst[l][0] = dst[l][1] = dst[l][2] = 0.0;
+            dst[l][3] = cdiv * Pu[t1] * Pv[t2] * J;
+        }
+        return;
+    }
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
         int a, t1, t2;
-        local_index(p, l, a, t1, t2);
+        local_index(o, l, a, t1, t2);
         double val, div;
         if (a == 0) {
             val = Pu[t1] * Qv[t2];
@@ -280,7 +316,7 @@ __device__ inline void local_values_lds(const DevOp &o, int e1, int e2, double x
 }
 
 // (Phi_l, cdiv * div_l) for the NL = 2P(P+1) local functions, into rows of shared memory
-template <int P>
+template <int P, bool SC = false>
 __device__ inline void local_values_lds_t(const DevOp &o, int e1, int e2, double x, double y, const double Fu[3],
                                           const double Fv[3], double cdiv, double (*dst)[4])
 {
@@ -288,6 +324,15 @@ __device__ inline void local_values_lds_t(const DevOp &o, int e1, int e2, double
     double Pu[P + 1], dPu[P + 1], Qu[P], Pv[P + 1], dPv[P + 1], Qv[P];
     spline_pieces_t<P>(o, e1, x, Pu, dPu, Qu);
     spline_pieces_t<P>(o, e2, y, Pv, dPv, Qv);
+    if constexpr (SC) {   // scalar: (p+1)^2 tensor B-splines, value times |J| in slot 3
+        const double J = surf_elem(Fu, Fv);
+#pragma unroll
+        for (int l = 0; l < (P + 1) * (P + 1); ++l) {
+            dst[l][0] = dst[l][1] = dst[l][2] = 0.0;
+            dst[l][3] = cdiv * Pu[l % (P + 1)] * Pv[l / (P + 1)] * J;
+        }
+        return;
+    }
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
         const bool a0 = l < P * (P + 1);
@@ -315,7 +360,7 @@ __device__ inline void elem_of(const DevOp &o, int64_t e, int &j, int &e1, int &
 __device__ inline void local_dof(const DevOp &o, int j, int e1, int e2, int l, int &idx, double &sg)
 {
     int a, t1, t2;
-    local_index(o.p, l, a, t1, t2);
+    local_index(o, l, a, t1, t2);
     const size_t off = (((size_t)j * 2 + a) * o.nb + (e2 + t2)) * o.nb + (e1 + t1);
     idx = o.dof[off];
     sg = (double)o.sgn[off];
@@ -470,7 +515,6 @@ __device__ __forceinline__ void near_regular_body(const DevOp &o, int sb, int ce
         sXe[d][q] = q < G2 ? o.eX[(e * 3 + d) * G2 + q] : 0.0;
     }
     constexpr size_t FE = (size_t)4 * LT * T * 64;
-    const double ik2 = 1.0 / (o.kappa * o.kappa);
     double pa[4][LR][T];
     {
         const double *Fe = o.ePsiF + (size_t)e * FE;
@@ -480,7 +524,7 @@ __device__ __forceinline__ void near_regular_body(const DevOp &o, int sb, int ce
             for (int u = 0; u < LR; ++u)
 #pragma unroll
                 for (int t = 0; t < T; ++t)
-                    pa[c][u][t] = Fe[((c * LT + u0 + u) * T + t) * 64 + lane] * (c == 3 ? -ik2 : 1.0);
+                    pa[c][u][t] = Fe[((c * LT + u0 + u) * T + t) * 64 + lane] * (c == 3 ? o.cdiv : 1.0);
     }
     __syncthreads();
     const int nfe = sb * sb, nround = (nfe + 3) / 4;
@@ -587,7 +631,7 @@ __device__ __forceinline__ void near_regular_body(const DevOp &o, int sb, int ce
                     const int l = i / NL, lb = i % NL;
                     if (l0 + l >= NL) continue;
                     int a, t1, t2;
-                    local_index(o.p, lb, a, t1, t2);
+                    local_index(o, lb, a, t1, t2);
                     const int slot = a * Wsb * Wsb + (q2 + t2) * Wsb + (q1 + t1);
                     const double2 v = sw[i];
                     double2 &acc = sacc[l * nslot + slot];
@@ -611,7 +655,7 @@ __device__ __forceinline__ void near_regular_body(const DevOp &o, int sb, int ce
             const int l = i / NL, lb = i % NL;
             if (l0 + l >= NL) continue;
             int a, t1, t2;
-            local_index(o.p, lb, a, t1, t2);
+            local_index(o, lb, a, t1, t2);
             const int slot = a * Wsb * Wsb + (q2 + t2) * Wsb + (q1 + t1);
             const double2 v = P[i];
             double2 &acc = sacc[l * nslot + slot];
@@ -628,13 +672,13 @@ __device__ __forceinline__ void near_regular_body(const DevOp &o, int sb, int ce
         if (l >= NL) continue;
         const int a = sl / (Wsb * Wsb), r = sl % (Wsb * Wsb);
         const int i1 = sl1 + r % Wsb, i2 = sl2 + r / Wsb;
-        if (i1 >= (a == 0 ? W : W - 1) || i2 >= (a == 0 ? W - 1 : W)) {
+        if (i1 >= (a == 0 ? W : W - 1) || i2 >= ((a == 0 && !o.scalar) ? W - 1 : W)) {
             atomicAdd(o.err, 1);
             continue;
         }
         const int kc = leaf_slot(W, a, i1, i2);
         int ar, t1, t2;
-        local_index(o.p, l, ar, t1, t2);
+        local_index(o, l, ar, t1, t2);
         const int kr = leaf_slot(W, ar, tl1 + t1, tl2 + t2);
         // signs of the glued unknowns folded in; slots without an unknown are skipped
         const double sg = (double)o.leafsgn[(size_t)lt * nF + kr] * (double)o.leafsgn[(size_t)ls * nF + kc];
@@ -730,11 +774,13 @@ __device__ inline void singular_point(const DevOp &o, int kind, int idx, double 
 //   B[l][l'] += sum_q K_q sum_c Psi_a[q][l][c] Psi_b[q][l'][c]
 // runs on the FP64 matrix cores with the four components c as the reduction slots
 // of one instruction per point (K_q = weight * kernel folded into the test side).
-template <int P>
+template <int P, bool SC = false>
 __global__ __launch_bounds__(64) void k_near_singular(DevOp o, const SingularPair *list)
 {
-    // points per batch: 32 (16 for p = 4, whose 40 local functions would not fit)
-    constexpr int NL = 2 * P * (P + 1), LT = (NL + 15) / 16, NB = P >= 4 ? 16 : 32;
+    // points per batch: 32 (16 for p = 4, whose 40 local functions would not fit);
+    // SC: the scalar operator's (p+1)^2 local functions
+    constexpr int NL = SC ? (P + 1) * (P + 1) : 2 * P * (P + 1), LT = (NL + 15) / 16;
+    constexpr int NB = (SC ? 2 * P * (P + 1) : NL) > 24 ? 16 : 32;
     __shared__ double sPa[NB][NL][4];
     __shared__ double sPb[NB][NL][4];
     __shared__ double2 sK[NB];
@@ -747,7 +793,7 @@ __global__ __launch_bounds__(64) void k_near_singular(DevOp o, const SingularPai
     const int gs = o.gs, g4 = gs * gs * gs * gs;
     const int nsub = sp.kind == 1 ? 8 : (sp.kind == 2 ? 6 : 4);
     const int npts = nsub * g4;
-    const double ik2 = 1.0 / (o.kappa * o.kappa), h4 = o.h * o.h * o.h * o.h;
+    const double h4 = o.h * o.h * o.h * o.h;
     dx4 br[LT][LT], bi[LT][LT];
 #pragma unroll
     for (int u = 0; u < LT; ++u)
@@ -774,10 +820,10 @@ __global__ __launch_bounds__(64) void k_near_singular(DevOp o, const SingularPai
             double Fu[3], Fv[3];
             if (half == 0) {
                 geom_eval(o.geo, ja, (a1 + xa) * o.h, (a2 + ya) * o.h, X, Fu, Fv);
-                local_values_lds_t<P>(o, a1, a2, xa, ya, Fu, Fv, -ik2, sPa[qi]);
+                local_values_lds_t<P, SC>(o, a1, a2, xa, ya, Fu, Fv, o.cdiv, sPa[qi]);
             } else {
                 geom_eval(o.geo, jb, (b1 + xb) * o.h, (b2 + yb) * o.h, X, Fu, Fv);
-                local_values_lds_t<P>(o, b1, b2, xb, yb, Fu, Fv, 1.0, sPb[qi]);
+                local_values_lds_t<P, SC>(o, b1, b2, xb, yb, Fu, Fv, 1.0, sPb[qi]);
                 sX[qi][0] = X[0];
                 sX[qi][1] = X[1];
                 sX[qi][2] = X[2];
@@ -900,6 +946,47 @@ __global__ __launch_bounds__(256) void k_p2m(DevOp o, const double2 *x, double2 
     }
 }
 
+// scalar single layer: leaf moments d = (M_p (x) M_p) c of the tensor B-spline
+// coefficients over the leaf's W x W window (fields 0 and 1 stay zero), and the source
+// values |J(x_m)| d at the nodes
+__global__ __launch_bounds__(256) void k_p2m_sc(DevOp o, const double2 *x, double2 *mom, double2 *src)
+{
+    extern __shared__ double2 sm2[];
+    const int id = blockIdx.x;
+    const int SL = o.SL, s = o.s, p = o.p, Q1 = o.Q1, Q = o.Q, RL = o.rowlen, W = s + p;
+    const int j = id / (SL * SL), r = id % (SL * SL), k2 = r / SL, k1 = r % SL;
+    const int gc = (int)o.lvl_off[o.L] + id;
+    double2 *X = sm2;           // [W (i2)][W (i1)]
+    double2 *Z = X + W * W;     // [W (i2)][Q1 (m1)]
+    for (int i = threadIdx.x; i < W * W; i += blockDim.x) {
+        const int i2 = i / W, i1 = i % W;
+        X[i] = x[o.dof[((size_t)j * 2 * o.nb + (k2 * s + i2)) * o.nb + (k1 * s + i1)]];
+    }
+    __syncthreads();
+    const double *Mpu = o.Mp + (size_t)k1 * Q1 * RL, *Mpv = o.Mp + (size_t)k2 * Q1 * RL;
+    for (int i = threadIdx.x; i < W * Q1; i += blockDim.x) {
+        const int i2 = i / Q1, m1 = i % Q1;
+        double2 z = make_double2(0, 0);
+        for (int i1 = 0; i1 < W; ++i1) z = cadd(z, cscale(Mpu[m1 * RL + i1], X[i2 * W + i1]));
+        Z[i] = z;
+    }
+    __syncthreads();
+    for (int mm = threadIdx.x; mm < Q; mm += blockDim.x) {
+        const int m2 = mm / Q1, m1 = mm % Q1;
+        double2 d = make_double2(0, 0);
+        for (int i2 = 0; i2 < W; ++i2) d = cadd(d, cscale(Mpv[m2 * RL + i2], Z[i2 * Q1 + m1]));
+        double2 *M = mom + (size_t)gc * 3 * Q;
+        M[mm] = make_double2(0, 0);
+        M[Q + mm] = make_double2(0, 0);
+        M[2 * Q + mm] = d;
+        const double *T = o.nodeT + (size_t)gc * 6 * Q;
+        const double Fu[3] = {T[mm], T[Q + mm], T[2 * Q + mm]}, Fv[3] = {T[3 * Q + mm], T[4 * Q + mm], T[5 * Q + mm]};
+        double2 *S = src + (size_t)gc * 4 * Q;
+        for (int k = 0; k < 3; ++k) S[k * Q + mm] = make_double2(0, 0);
+        S[3 * Q + mm] = cscale(surf_elem(Fu, Fv), d);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // a4: M2M, parents on level lvl from children on lvl+1
 // parent[m2][m1] = sum_c sum_{n1,n2} T_c1[n1][m1] T_c2[n2][m2] child_c[n2][n1]
@@ -952,7 +1039,12 @@ __global__ __launch_bounds__(256) void k_m2m(DevOp o, int lvl, double2 *mom, dou
         const double *T = o.nodeT + (size_t)gc * 6 * Q;
         double2 *Sv = src + (size_t)gc * 4 * Q;
         for (int k = 0; k < 3; ++k) Sv[k * Q + mm] = cadd(cscale(T[k * Q + mm], s1), cscale(T[(3 + k) * Q + mm], s2v));
-        Sv[3 * Q + mm] = d;
+        if (o.scalar) {   // scalar: the moments times the surface element at the node
+            const double Fu[3] = {T[mm], T[Q + mm], T[2 * Q + mm]}, Fv[3] = {T[3 * Q + mm], T[4 * Q + mm], T[5 * Q + mm]};
+            Sv[3 * Q + mm] = cscale(surf_elem(Fu, Fv), d);
+        } else {
+            Sv[3 * Q + mm] = d;
+        }
     }
 }
 
@@ -1065,6 +1157,13 @@ __global__ void k_m2l_reduce(DevOp o, const int32_t *wrk_of_tgt, const double2 *
             t2 = cadd(t2, cscale(T[(3 + k) * Q + mm], u[k]));
         }
         double2 *L = loc + (size_t)gc * 3 * Q;
+        if (o.scalar) {   // scalar: t = |J(x_m)| u (the localized kernel's target surface element)
+            const double Fu[3] = {T[mm], T[Q + mm], T[2 * Q + mm]}, Fv[3] = {T[3 * Q + mm], T[4 * Q + mm], T[5 * Q + mm]};
+            L[mm] = make_double2(0, 0);
+            L[Q + mm] = make_double2(0, 0);
+            L[2 * Q + mm] = cscale(surf_elem(Fu, Fv), u[3]);
+            continue;
+        }
         L[mm] = t1;
         L[Q + mm] = t2;
         L[2 * Q + mm] = cscale(-ik2, u[3]);
@@ -1295,6 +1394,35 @@ __global__ __launch_bounds__(256) void k_l2p_leaf(DevOp o, const double2 *loc, d
     }
 }
 
+// scalar single layer: Y[i2][i1] = sum (M_p (x) M_p)^T t^d over the leaf's W x W window
+// (component 0 of the leaf's result rows)
+__global__ __launch_bounds__(256) void k_l2p_leaf_sc(DevOp o, const double2 *loc, double2 *ybuf)
+{
+    extern __shared__ double2 sm2[];
+    const int id = blockIdx.x;
+    const int SL = o.SL, s = o.s, p = o.p, Q1 = o.Q1, Q = o.Q, RL = o.rowlen, W = s + p;
+    const int r = id % (SL * SL), k2 = r / SL, k1 = r % SL;
+    const int gc = (int)o.lvl_off[o.L] + id;
+    const double2 *t = loc + (size_t)gc * 3 * Q + 2 * Q;
+    const double *Mpu = o.Mp + (size_t)k1 * Q1 * RL, *Mpv = o.Mp + (size_t)k2 * Q1 * RL;
+    double2 *Wm = sm2;   // [Q1 (m2)][W (i1)]
+    for (int i = threadIdx.x; i < Q1 * W; i += blockDim.x) {
+        const int m2 = i / W, i1 = i % W;
+        double2 a = make_double2(0, 0);
+        for (int m1 = 0; m1 < Q1; ++m1) a = cadd(a, cscale(Mpu[m1 * RL + i1], t[m2 * Q1 + m1]));
+        Wm[i] = a;
+    }
+    __syncthreads();
+    double2 *Y = ybuf + (size_t)id * 2 * RL * RL;
+    for (int i = threadIdx.x; i < RL * RL; i += blockDim.x) {
+        const int i2 = i / RL, i1 = i % RL;
+        double2 v = make_double2(0, 0);
+        if (i2 < W && i1 < W)
+            for (int m2 = 0; m2 < Q1; ++m2) v = cadd(v, cscale(Mpv[m2 * RL + i2], Wm[m2 * W + i1]));
+        Y[i] = v;
+    }
+}
+
 __global__ void k_l2p_gather(DevOp o, const double2 *ybuf, double2 *y)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1307,7 +1435,7 @@ __global__ void k_l2p_gather(DevOp o, const double2 *ybuf, double2 *y)
         if (j < 0) continue;
         const int a = in[1], i1 = in[2], i2 = in[3];
         const double sg = (double)in[4];
-        const int du = (a == 0) ? p : p - 1, dv = (a == 0) ? p - 1 : p;
+        const int du = (a == 0) ? p : p - 1, dv = (a == 0 && !o.scalar) ? p - 1 : p;
         const int k1b = max(0, i1 - du) / s, k1e = min(n - 1, i1) / s;
         const int k2b = max(0, i2 - dv) / s, k2e = min(n - 1, i2) / s;
         for (int k2 = k2b; k2 <= k2e; ++k2)
@@ -1359,6 +1487,38 @@ __global__ void k_rhs_plane(DevOp o, double d0, double d1, double d2, double2 p0
     f[i] = acc;
 }
 
+// scalar single layer right-hand side f_i = int g phi_i dsigma, one thread per unknown:
+// kind 0 plane wave g = exp(i kappa a.x), kind 1 point source g = G(x - a)
+__global__ void k_rhs_scalar(DevOp o, int kind, double a0, double a1, double a2, double2 *f)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= o.N) return;
+    const int p = o.p, n = o.n, G2 = o.G2, NL = o.nl;
+    const int32_t *in = o.inc + (size_t)i * 2 * 5;
+    const int j = in[0], i1 = in[2], i2 = in[3];
+    double2 acc = make_double2(0, 0);
+    for (int e2 = max(0, i2 - p); e2 <= min(n - 1, i2); ++e2)
+        for (int e1 = max(0, i1 - p); e1 <= min(n - 1, i1); ++e1) {
+            const int l = (i2 - e2) * (p + 1) + (i1 - e1);
+            const int64_t e = ((int64_t)j * n + e2) * n + e1;
+            const double *X = o.eX + e * 3 * G2;
+            const double *Ps = o.ePsi + (e * 4 + 3) * NL * G2 + (size_t)l * G2;   // weight * value * |J|
+            for (int q = 0; q < G2; ++q) {
+                double2 g;
+                if (kind == 0) {
+                    double sn, cs;
+                    sincos(o.kappa * (a0 * X[q] + a1 * X[G2 + q] + a2 * X[2 * G2 + q]), &sn, &cs);
+                    g = make_double2(cs, sn);
+                } else {
+                    const double d0 = X[q] - a0, d1 = X[G2 + q] - a1, d2 = X[2 * G2 + q] - a2;
+                    g = helmholtz(o.kappa, sqrt(d0 * d0 + d1 * d1 + d2 * d2));
+                }
+                acc = cadd(acc, cscale(Ps[q], g));
+            }
+        }
+    f[i] = acc;
+}
+
 __global__ void k_helmholtz_eval(int64_t n, double kappa, const double *r2, double2 *out, int prec,
                                  const double2 *sctab)
 {
@@ -1388,12 +1548,17 @@ void launch_element_data(ige_op op)
     const int64_t E = (int64_t)o.P * o.n * o.n;
     const int threads = 64;
     hipStream_t s = lstream(op);
-    switch (o.p) {
-        case 1: hipLaunchKernelGGL(k_element_data<4>, dim3(E), dim3(threads), 0, s, o, op->d_eX.p, op->d_ePsi.p, op->d_ePsiF.p, op->d_eC.p); break;
-        case 2: hipLaunchKernelGGL(k_element_data<12>, dim3(E), dim3(threads), 0, s, o, op->d_eX.p, op->d_ePsi.p, op->d_ePsiF.p, op->d_eC.p); break;
-        case 3: hipLaunchKernelGGL(k_element_data<24>, dim3(E), dim3(threads), 0, s, o, op->d_eX.p, op->d_ePsi.p, op->d_ePsiF.p, op->d_eC.p); break;
-        default: hipLaunchKernelGGL(k_element_data<40>, dim3(E), dim3(threads), 0, s, o, op->d_eX.p, op->d_ePsi.p, op->d_ePsiF.p, op->d_eC.p); break;
+#define IGE_ED(NLV) hipLaunchKernelGGL(k_element_data<NLV>, dim3(E), dim3(threads), 0, s, o, op->d_eX.p, op->d_ePsi.p, op->d_ePsiF.p, op->d_eC.p)
+    switch (o.nl) {
+        case 4: IGE_ED(4); break;
+        case 9: IGE_ED(9); break;
+        case 12: IGE_ED(12); break;
+        case 16: IGE_ED(16); break;
+        case 24: IGE_ED(24); break;
+        case 25: IGE_ED(25); break;
+        default: IGE_ED(40); break;
     }
+#undef IGE_ED
     IGE_LAUNCH_CHECK();
 }
 
@@ -1473,10 +1638,13 @@ void launch_near_regular(ige_op op)
                     const int64_t nwg = o.nblk * n1 * n2 * m1 * m2 * nrt;
                     if (nwg == 0) continue;
                     const dim3 grid((unsigned)nwg);
-                    switch (o.p) {
-                        case 1: launch_near_regular_nl<4>(op, grid, shm, sb, ce1, ce2, cs1, cs2, sstep); break;
-                        case 2: launch_near_regular_nl<12>(op, grid, shm, sb, ce1, ce2, cs1, cs2, sstep); break;
-                        case 3: launch_near_regular_nl<24>(op, grid, shm, sb, ce1, ce2, cs1, cs2, sstep); break;
+                    switch (o.nl) {
+                        case 4: launch_near_regular_nl<4>(op, grid, shm, sb, ce1, ce2, cs1, cs2, sstep); break;
+                        case 9: launch_near_regular_nl<9>(op, grid, shm, sb, ce1, ce2, cs1, cs2, sstep); break;
+                        case 12: launch_near_regular_nl<12>(op, grid, shm, sb, ce1, ce2, cs1, cs2, sstep); break;
+                        case 16: launch_near_regular_nl<16>(op, grid, shm, sb, ce1, ce2, cs1, cs2, sstep); break;
+                        case 24: launch_near_regular_nl<24>(op, grid, shm, sb, ce1, ce2, cs1, cs2, sstep); break;
+                        case 25: launch_near_regular_nl<25>(op, grid, shm, sb, ce1, ce2, cs1, cs2, sstep); break;
                         default: launch_near_regular_nl<40>(op, grid, shm, sb, ce1, ce2, cs1, cs2, sstep); break;
                     }
                     IGE_LAUNCH_CHECK();
@@ -1488,11 +1656,20 @@ void launch_near_singular(ige_op op)
     const DevOp &o = op->view;
     if (op->nsing == 0) return;
     hipStream_t s = lstream(op);
-    switch (o.p) {
-        case 1: hipLaunchKernelGGL(k_near_singular<1>, dim3(op->nsing), dim3(64), 0, s, o, op->d_sing.p); break;
-        case 2: hipLaunchKernelGGL(k_near_singular<2>, dim3(op->nsing), dim3(64), 0, s, o, op->d_sing.p); break;
-        case 3: hipLaunchKernelGGL(k_near_singular<3>, dim3(op->nsing), dim3(64), 0, s, o, op->d_sing.p); break;
-        default: hipLaunchKernelGGL(k_near_singular<4>, dim3(op->nsing), dim3(64), 0, s, o, op->d_sing.p); break;
+    if (o.scalar) {
+        switch (o.p) {
+            case 1: hipLaunchKernelGGL((k_near_singular<1, true>), dim3(op->nsing), dim3(64), 0, s, o, op->d_sing.p); break;
+            case 2: hipLaunchKernelGGL((k_near_singular<2, true>), dim3(op->nsing), dim3(64), 0, s, o, op->d_sing.p); break;
+            case 3: hipLaunchKernelGGL((k_near_singular<3, true>), dim3(op->nsing), dim3(64), 0, s, o, op->d_sing.p); break;
+            default: hipLaunchKernelGGL((k_near_singular<4, true>), dim3(op->nsing), dim3(64), 0, s, o, op->d_sing.p); break;
+        }
+    } else {
+        switch (o.p) {
+            case 1: hipLaunchKernelGGL(k_near_singular<1>, dim3(op->nsing), dim3(64), 0, s, o, op->d_sing.p); break;
+            case 2: hipLaunchKernelGGL(k_near_singular<2>, dim3(op->nsing), dim3(64), 0, s, o, op->d_sing.p); break;
+            case 3: hipLaunchKernelGGL(k_near_singular<3>, dim3(op->nsing), dim3(64), 0, s, o, op->d_sing.p); break;
+            default: hipLaunchKernelGGL(k_near_singular<4>, dim3(op->nsing), dim3(64), 0, s, o, op->d_sing.p); break;
+        }
     }
     IGE_LAUNCH_CHECK();
 }
@@ -1501,6 +1678,13 @@ void launch_p2m(ige_op op, const double2 *x)
 {
     const DevOp &o = op->view;
     const int nleaf = o.P * o.SL * o.SL;
+    if (o.scalar) {
+        const size_t W = o.s + o.p;
+        const size_t shm = sizeof(double2) * (W * W + W * o.Q1);
+        hipLaunchKernelGGL(k_p2m_sc, dim3(nleaf), dim3(256), shm, lstream(op), o, x, op->d_mom.p, op->d_src.p);
+        IGE_LAUNCH_CHECK();
+        return;
+    }
     const int w1a = o.s + o.p, w2a = o.s + o.p - 1;
     const size_t shm = sizeof(double2) * (2 * w1a * w2a + 3 * (size_t)(w1a) * o.Q1);
     hipLaunchKernelGGL(k_p2m, dim3(nleaf), dim3(256), shm, lstream(op), o, x, op->d_mom.p, op->d_src.p);
@@ -1613,6 +1797,12 @@ void launch_l2p_leaf(ige_op op)
 {
     const DevOp &o = op->view;
     const int nleaf = o.P * o.SL * o.SL;
+    if (o.scalar) {
+        const size_t shm = sizeof(double2) * (size_t)o.Q1 * (o.s + o.p);
+        hipLaunchKernelGGL(k_l2p_leaf_sc, dim3(nleaf), dim3(256), shm, lstream(op), o, op->d_loc.p, op->d_ybuf.p);
+        IGE_LAUNCH_CHECK();
+        return;
+    }
     const size_t shm = sizeof(double2) * 3 * (size_t)o.Q1 * o.rowlen;
     hipLaunchKernelGGL(k_l2p_leaf, dim3(nleaf), dim3(256), shm, lstream(op), o, op->d_loc.p, op->d_ybuf.p);
     IGE_LAUNCH_CHECK();
@@ -1622,6 +1812,13 @@ void launch_l2p_gather(ige_op op, double2 *y)
 {
     const DevOp &o = op->view;
     hipLaunchKernelGGL(k_l2p_gather, dim3((o.N + 255) / 256), dim3(256), 0, lstream(op), o, op->d_ybuf.p, y);
+    IGE_LAUNCH_CHECK();
+}
+
+void launch_rhs_scalar(ige_op op, int kind, const double *a, double2 *f)
+{
+    const DevOp &o = op->view;
+    hipLaunchKernelGGL(k_rhs_scalar, dim3((o.N + 255) / 256), dim3(256), 0, lstream(op), o, kind, a[0], a[1], a[2], f);
     IGE_LAUNCH_CHECK();
 }
 
@@ -1677,8 +1874,9 @@ __global__ void k_pot_sources(DevOp o, const double2 *w, double *src)
 
 // one workgroup per target point; threads take every 256th source point, then a
 // fixed tree over the workgroup
+// scalar: the single layer potential u(x) = int G(x - y) w(y) dsigma into component 0
 __global__ __launch_bounds__(256) void k_potential(int64_t nsrc, double kappa, const double *src, const double *pts,
-                                                   double2 *out)
+                                                   double2 *out, int scalar)
 {
     __shared__ double red[6][256];
     const int t = blockIdx.x;
@@ -1691,6 +1889,12 @@ __global__ __launch_bounds__(256) void k_potential(int64_t nsrc, double kappa, c
         const double rr2 = fma(rv[0], rv[0], fma(rv[1], rv[1], rv[2] * rv[2]));
         const double kr = kappa * sqrt(rr2);
         const double2 G = dm::helmholtz_r2(kappa, rr2);
+        if (scalar) {
+            const double2 v = cmul(G, make_double2(s[9], s[10]));
+            acc[0] += v.x;
+            acc[1] += v.y;
+            continue;
+        }
         // grad_x G = (x - y) G (i kappa r - 1) / r^2, times kappa^-2 and D
         const double2 dG = make_double2((-G.x - kr * G.y) / rr2, (kr * G.x - G.y) / rr2);
         const double2 dgD = cscale(ik2, cmul(dG, make_double2(s[9], s[10])));
@@ -1754,15 +1958,18 @@ void launch_potential(ige_op op, const double2 *w, int npts, const double *pts, 
     const DevOp &o = op->view;
     const int64_t E = (int64_t)o.P * o.n * o.n;
     hipStream_t s = lstream(op);
-    switch (o.p) {
-        case 1: hipLaunchKernelGGL(k_pot_sources<4>, dim3((unsigned)E), dim3(64), 0, s, o, w, src); break;
-        case 2: hipLaunchKernelGGL(k_pot_sources<12>, dim3((unsigned)E), dim3(64), 0, s, o, w, src); break;
-        case 3: hipLaunchKernelGGL(k_pot_sources<24>, dim3((unsigned)E), dim3(64), 0, s, o, w, src); break;
+    switch (o.nl) {
+        case 4: hipLaunchKernelGGL(k_pot_sources<4>, dim3((unsigned)E), dim3(64), 0, s, o, w, src); break;
+        case 9: hipLaunchKernelGGL(k_pot_sources<9>, dim3((unsigned)E), dim3(64), 0, s, o, w, src); break;
+        case 12: hipLaunchKernelGGL(k_pot_sources<12>, dim3((unsigned)E), dim3(64), 0, s, o, w, src); break;
+        case 16: hipLaunchKernelGGL(k_pot_sources<16>, dim3((unsigned)E), dim3(64), 0, s, o, w, src); break;
+        case 24: hipLaunchKernelGGL(k_pot_sources<24>, dim3((unsigned)E), dim3(64), 0, s, o, w, src); break;
+        case 25: hipLaunchKernelGGL(k_pot_sources<25>, dim3((unsigned)E), dim3(64), 0, s, o, w, src); break;
         default: hipLaunchKernelGGL(k_pot_sources<40>, dim3((unsigned)E), dim3(64), 0, s, o, w, src); break;
     }
     IGE_HIP(hipGetLastError());
     if (npts > 0) {
-        hipLaunchKernelGGL(k_potential, dim3(npts), dim3(256), 0, s, E * o.G2, o.kappa, src, pts, out);
+        hipLaunchKernelGGL(k_potential, dim3(npts), dim3(256), 0, s, E * o.G2, o.kappa, src, pts, out, o.scalar);
         IGE_HIP(hipGetLastError());
     }
 }

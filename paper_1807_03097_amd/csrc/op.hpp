@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <complex>
 #include <map>
 #include <memory>
@@ -16,6 +17,9 @@ struct ige_ctx_s {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    // geometries, operators and servers made on this context and not yet destroyed:
+    // they use its device and stream, so the context outlives them
+    std::atomic<int> users{0};
 };
 
 struct ige_geom_s {
@@ -30,6 +34,8 @@ using cd = double2;   // complex double as (re, im)
 // Device view of the operator, passed by value to kernels.
 struct DevOp {
     int P, p, m, n, nb, N, nl, L, s, SL;   // SL = 2^L leaf clusters per patch side
+    int scalar;                // 1: scalar single layer (one component: value times |J| in slot 3)
+    double cdiv;               // factor of the slot-3 term: -kappa^-2 (EFIE divergence), 1 (scalar)
     int q, Q1, Q, g, G2, gs;
     double kappa, h, scale_tol;
     GeomView geo;
@@ -305,6 +311,8 @@ void launch_potential(ige_op op, const double2 *w, int npts, const double *pts, 
 void potential_scratch_init(int device);
 double *potential_scratch(int device);
 size_t potential_scratch_doubles();
+// scalar single layer right-hand side (kind 0 plane wave of direction a, 1 point source at a)
+void launch_rhs_scalar(ige_op op, int kind, const double *a, double2 *f);
 void launch_rhs_plane(ige_op op, const double *dir, double2 pol0, double2 pol1, double2 pol2, double2 *f);
 // GMRES vector kernels (V: [k][r][n], vectors [r][n]; gate/run/flag: per-column int masks)
 struct GsPlan {

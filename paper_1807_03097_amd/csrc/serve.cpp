@@ -1,19 +1,27 @@
-// Serving: many independent scattering solves (geometry, discretisation,
-// wavenumber and one or several incident plane waves each) on one device.
+// Serving: many scattering solves (geometry, discretisation, wavenumber and one or
+// several incident plane waves each) on one device, as they arrive.
 //
 // A server owns n_workers host threads; each has its own context, i.e. its own HIP
 // stream, so the kernels of several requests share the device.  Requests wait in
 // arrival order and are admitted first-fit by their planned device footprint
 // against a memory budget; a request may overtake the oldest waiting one only while
-// that one has waited less than kMaxBypass seconds, which bounds its delay.  A
-// worker assembles the operator on its stream, forms the right-hand sides, runs GMRES
-// on all of them at once (the batched kernels from two waves on) and copies the
-// solutions to host memory, then frees the operator.
+// that one has waited less than kMaxBypass seconds, which bounds its delay.
+//
+// Continuous batching: when a worker takes a request, the other waiting requests on
+// the same operator (same geometry handle, parameters and solve options) join it, up
+// to max_merge plane waves in all, and all their waves are solved together as one
+// many-column system (every kernel value and block entry is read once per column
+// chunk); the solutions are split back per request.  A worker keeps the operator of
+// its last request resident on the device (cluster trees, near-field blocks, moment
+// tables and its Krylov workspace) and prefers waiting requests on that operator, so
+// a stream of requests on one object is assembled once.  Resident operators count
+// against the budget and are freed when a waiting request needs their memory.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstring>
 #include <deque>
 #include <map>
 #include <memory>
@@ -27,6 +35,7 @@
 namespace {
 
 constexpr double kMaxBypass = 1.0;   // seconds
+constexpr int kMergeDefault = 64;    // plane waves of one merged solve
 
 struct SrvReq {
     int64_t ticket = 0;
@@ -36,7 +45,9 @@ struct SrvReq {
     std::vector<double> dir;     // [nw][3]
     std::vector<ige_c64> pol;    // [nw][3]
     ige_solve_opts opts{};
-    size_t footprint = 0;
+    size_t footprint = 0;        // planned device bytes of this request alone
+    size_t fp_merged = 0;        // planned device bytes of a merged solve of max_merge waves
+    size_t fp_operator = 0;      // of which the assembled operator (resident between requests)
     int64_t n_dof = 0;
     int state = 0;   // 0 queued, 1 running, 2 finished
     int rc = 0;
@@ -44,7 +55,26 @@ struct SrvReq {
     int iters = 0;
     double relres = 0.0;
     double t_submit = 0.0, t_start = 0.0, t_done = 0.0, assemble_s = 0.0, solve_s = 0.0;
+    int merged = 1;              // requests solved together with this one (itself included)
+    bool reused = false;         // ran on a resident operator (no assembly)
     std::vector<ige_c64> x;
+};
+
+bool same_operator(const SrvReq &a, const SrvReq &b)
+{
+    return a.geom == b.geom && std::memcmp(&a.prm, &b.prm, sizeof(ige_params)) == 0;
+}
+bool same_solve(const SrvReq &a, const SrvReq &b)
+{
+    return same_operator(a, b) && std::memcmp(&a.opts, &b.opts, sizeof(ige_solve_opts)) == 0;
+}
+
+// the operator a worker keeps resident after its last request
+struct Resident {
+    ige_op op = nullptr;
+    const ige_geom_s *geom = nullptr;
+    ige_params prm{};
+    size_t bytes = 0;            // counted in the server's in_use
 };
 
 }  // namespace
@@ -53,12 +83,14 @@ struct ige_srv_s {
     ige_ctx parent = nullptr;
     int device = 0;
     size_t budget = 0, in_use = 0;
+    int max_merge = kMergeDefault;
     std::chrono::steady_clock::time_point origin;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<SrvReq *> queue;
     std::map<int64_t, std::unique_ptr<SrvReq>> all;
     std::vector<std::thread> workers;
+    std::vector<Resident> resident;   // per worker
     int64_t next_ticket = 1;
     bool stop = false;
 
@@ -67,91 +99,244 @@ struct ige_srv_s {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - origin).count();
     }
 
-    // first request (arrival order) that fits next to the running ones; the oldest
-    // one is overtaken only while it has waited less than kMaxBypass
-    SrvReq *pick()
+    // bytes a group led by r needs beyond what worker w already holds for it
+    size_t need(const SrvReq *r, int w, bool merged) const
     {
-        if (queue.empty()) return nullptr;
-        const double t = now();
-        for (auto it = queue.begin(); it != queue.end(); ++it) {
-            if (in_use + (*it)->footprint <= budget) {
-                SrvReq *r = *it;
-                queue.erase(it);
-                return r;
-            }
-            if (it == queue.begin() && t - (*it)->t_submit >= kMaxBypass) return nullptr;
-        }
-        return nullptr;
+        const size_t fp = merged ? r->fp_merged : r->footprint;
+        const Resident &R = resident[w];
+        const bool hit = R.op && R.geom == r->geom && std::memcmp(&R.prm, &r->prm, sizeof(ige_params)) == 0;
+        return hit ? fp - std::min(fp, std::min(R.bytes, r->fp_operator)) : fp;
     }
 
-    void run(SrvReq *r, ige_ctx wctx)
+    // Worker w picks its next group (called with mu held): a waiting request on its
+    // resident operator first, else the first request (arrival order) that fits next to
+    // the running ones, the oldest one overtaken only while it has waited less than
+    // kMaxBypass.  Requests with the same operator and solve options join the group.
+    // A resident operator that is not needed is dropped (to *drop, freed by the caller
+    // outside the lock) when the oldest waiting request does not fit.
+    std::vector<SrvReq *> pick(int w, ige_op *drop)
     {
+        std::vector<SrvReq *> grp;
+        if (queue.empty()) return grp;
+        const double t = now();
+        Resident &R = resident[w];
+        auto fits = [&](const SrvReq *r, bool merged) {
+            const size_t own = (R.op && !(R.geom == r->geom && std::memcmp(&R.prm, &r->prm, sizeof(ige_params)) == 0))
+                                   ? R.bytes : 0;   // an unrelated resident operator is dropped on start
+            return in_use - own + need(r, w, merged) <= budget;
+        };
+        auto it = queue.end();
+        if (R.op && t - queue.front()->t_submit < kMaxBypass)
+            for (auto jt = queue.begin(); jt != queue.end(); ++jt)
+                if ((*jt)->geom == R.geom && std::memcmp(&(*jt)->prm, &R.prm, sizeof(ige_params)) == 0 &&
+                    fits(*jt, false)) {
+                    it = jt;
+                    break;
+                }
+        if (it == queue.end())
+            for (auto jt = queue.begin(); jt != queue.end(); ++jt) {
+                if (fits(*jt, false)) {
+                    it = jt;
+                    break;
+                }
+                if (jt == queue.begin() && t - (*jt)->t_submit >= kMaxBypass) break;
+            }
+        if (it == queue.end()) {
+            // the oldest request waits for memory: give back this worker's resident operator
+            if (R.op) {
+                in_use -= R.bytes;
+                *drop = R.op;
+                R = Resident{};
+                cv_work.notify_all();   // the others may free theirs too
+            }
+            return grp;
+        }
+        SrvReq *lead = *it;
+        queue.erase(it);
+        grp.push_back(lead);
+        // requests on the same operator with the same options join, while a solve of
+        // max_merge waves still fits
+        int waves = lead->nw;
+        if (max_merge > 1 && fits(lead, true))
+            for (auto jt = queue.begin(); jt != queue.end();) {
+                if (same_solve(**jt, *lead) && waves + (*jt)->nw <= max_merge) {
+                    waves += (*jt)->nw;
+                    grp.push_back(*jt);
+                    jt = queue.erase(jt);
+                } else {
+                    ++jt;
+                }
+            }
+        return grp;
+    }
+
+    // Solve a group on the worker's context: assemble (or reuse the resident operator),
+    // right-hand sides of all waves, one GMRES on all columns, results split per request.
+    // Every failure is reported in the requests (all exceptions caught).
+    void run(std::vector<SrvReq *> &grp, ige_ctx wctx, int w, ige_op &keep)
+    {
+        SrvReq *lead = grp[0];
         const double t0 = now();
         ige_op op = nullptr;
+        std::string err;
+        int rc = IGE_OK;
         try {
-            op = ige::assemble_on(wctx, r->geom, r->prm);
-            const double t1 = now();
-            r->assemble_s = t1 - t0;
-            const int64_t N = op->D.N;
-            std::vector<ige_c64> f((size_t)N * r->nw);
-            r->x.assign((size_t)N * r->nw, ige_c64{0.0, 0.0});
-            int rc = ige_rhs_plane_wave(op, r->nw, r->dir.data(), r->pol.data(), f.data(), IGE_HOST);
-            if (rc != IGE_OK) throw ige::Status{rc, ige_last_error()};
-            std::vector<ige_solve_stats> st((size_t)r->nw);
-            rc = ige_solve(op, r->nw, f.data(), r->x.data(), IGE_HOST, &r->opts, st.data());
-            if (rc != IGE_OK && rc != IGE_ENOTCONV) throw ige::Status{rc, ige_last_error()};
-            r->rc = rc;
-            for (const auto &c : st) {   // the slowest wave
-                r->iters = std::max(r->iters, c.iters);
-                r->relres = std::max(r->relres, c.relres);
+            Resident &R = resident[w];
+            if (R.op && R.geom == lead->geom && std::memcmp(&R.prm, &lead->prm, sizeof(ige_params)) == 0) {
+                op = R.op;   // already counted: its bytes move into the group's footprint
+                for (auto *r : grp) r->reused = true;
+            } else {
+                op = ige::assemble_on(wctx, lead->geom, lead->prm);
             }
-            r->solve_s = now() - t1;
+            const double t1 = now();
+            int nw = 0;
+            for (auto *r : grp) nw += r->nw;
+            const int64_t N = op->D.N;
+            std::vector<double> dir;
+            std::vector<ige_c64> pol;
+            for (auto *r : grp) {
+                dir.insert(dir.end(), r->dir.begin(), r->dir.end());
+                pol.insert(pol.end(), r->pol.begin(), r->pol.end());
+            }
+            std::vector<ige_c64> f((size_t)N * nw), x((size_t)N * nw, ige_c64{0.0, 0.0});
+            int rr = ige_rhs_plane_wave(op, nw, dir.data(), pol.data(), f.data(), IGE_HOST);
+            if (rr != IGE_OK) throw ige::Status{rr, ige_last_error()};
+            std::vector<ige_solve_stats> st((size_t)nw);
+            rr = ige_solve(op, nw, f.data(), x.data(), IGE_HOST, &lead->opts, st.data());
+            if (rr != IGE_OK && rr != IGE_ENOTCONV) throw ige::Status{rr, ige_last_error()};
+            const double t2 = now();
+            int c0 = 0;
+            for (auto *r : grp) {
+                r->x.assign(x.begin() + (size_t)c0 * N, x.begin() + (size_t)(c0 + r->nw) * N);
+                bool conv = true;
+                for (int c = c0; c < c0 + r->nw; ++c) {   // the slowest wave of the request
+                    r->iters = std::max(r->iters, st[c].iters);
+                    r->relres = std::max(r->relres, st[c].relres);
+                    conv = conv && st[c].relres <= lead->opts.tol;
+                }
+                r->rc = (rr == IGE_ENOTCONV && !conv) ? IGE_ENOTCONV : IGE_OK;
+                r->assemble_s = r->reused ? 0.0 : t1 - t0;
+                r->solve_s = t2 - t1;
+                r->merged = (int)grp.size();
+                c0 += r->nw;
+            }
+            keep = op;
+            return;
         } catch (const ige::Status &e) {
-            r->rc = e.code;
-            r->err = e.msg;
+            rc = e.code;
+            err = e.msg;
         } catch (const std::bad_alloc &) {
-            r->rc = IGE_ENOMEM;
-            r->err = "host allocation failed";
+            rc = IGE_ENOMEM;
+            err = "host allocation failed";
         } catch (const std::exception &e) {
-            r->rc = IGE_EINVAL;
-            r->err = std::string("request failed: ") + e.what();
+            rc = IGE_EINVAL;
+            err = std::string("request failed: ") + e.what();
         } catch (...) {
             // nothing may escape a worker thread (that would end the process)
-            r->rc = IGE_EINVAL;
-            r->err = "request failed with an unknown exception";
+            rc = IGE_EINVAL;
+            err = "request failed with an unknown exception";
         }
-        if (op) ige_op_destroy(op);
+        for (auto *r : grp) {
+            r->rc = rc;
+            r->err = err;
+        }
+        keep = op;   // kept only if it is healthy (see worker_main)
     }
 
-    void worker_main()
+    void worker_main(int w)
     {
         ige_ctx wctx = nullptr;
-        const int rc = ige_ctx_create(device, nullptr, &wctx);
+        const int crc = ige_ctx_create(device, nullptr, &wctx);
         for (;;) {
-            SrvReq *r = nullptr;
+            std::vector<SrvReq *> grp;
+            ige_op drop = nullptr, old = nullptr;
+            size_t held = 0;
             {
                 std::unique_lock<std::mutex> lk(mu);
-                cv_work.wait(lk, [&] { return (r = pick()) != nullptr || (stop && queue.empty()); });
-                if (!r) break;
-                in_use += r->footprint;
-                r->state = 1;
-                r->t_start = now();
+                cv_work.wait(lk, [&] {
+                    if (drop) return true;   // free it outside the lock first
+                    grp = pick(w, &drop);
+                    return !grp.empty() || (stop && queue.empty());
+                });
+                if (!grp.empty()) {
+                    Resident &R = resident[w];
+                    const bool hit = R.op && R.geom == grp[0]->geom &&
+                                     std::memcmp(&R.prm, &grp[0]->prm, sizeof(ige_params)) == 0;
+                    if (R.op && !hit) {   // an unrelated resident operator makes room
+                        in_use -= R.bytes;
+                        old = R.op;
+                        R = Resident{};
+                    }
+                    held = grp.size() > 1 ? grp[0]->fp_merged : grp[0]->footprint;
+                    if (hit) {   // its resident bytes become part of the group's footprint
+                        in_use -= R.bytes;
+                        R.bytes = 0;
+                    }
+                    in_use += held;
+                    const double t = now();
+                    for (auto *r : grp) {
+                        r->state = 1;
+                        r->t_start = t;
+                    }
+                }
             }
-            if (rc == IGE_OK) {
-                run(r, wctx);   // reports every failure in r (catches all exceptions)
+            if (drop) ige_op_destroy(drop);
+            if (old) ige_op_destroy(old);
+            if (grp.empty()) {
+                if (drop) continue;
+                break;   // stopping and nothing waits
+            }
+            ige_op keep = nullptr;
+            if (crc == IGE_OK) {
+                run(grp, wctx, w, keep);
             } else {
-                r->rc = rc;
-                r->err = "worker context creation failed";
+                for (auto *r : grp) {
+                    r->rc = crc;
+                    r->err = "worker context creation failed";
+                }
             }
+            // keep the operator resident if the solve went through, else free it
+            const bool healthy = keep && (grp[0]->rc == IGE_OK || grp[0]->rc == IGE_ENOTCONV);
+            size_t bytes = 0;
+            if (healthy) {
+                ige_op_info_t info{};
+                if (ige_op_info(keep, &info) == IGE_OK) bytes = (size_t)info.device_bytes;
+            }
+            ige_op freed = nullptr;
             {
                 std::lock_guard<std::mutex> lk(mu);
-                in_use -= r->footprint;
-                r->t_done = now();
-                r->state = 2;
+                in_use -= held;
+                Resident &R = resident[w];
+                if (healthy && !stop) {
+                    R.op = keep;
+                    R.geom = grp[0]->geom;
+                    R.prm = grp[0]->prm;
+                    R.bytes = bytes;
+                    in_use += bytes;
+                } else {
+                    if (R.op == keep) R = Resident{};
+                    freed = keep;
+                }
+                const double t = now();
+                for (auto *r : grp) {
+                    r->t_done = t;
+                    r->state = 2;
+                }
             }
+            if (freed) ige_op_destroy(freed);
             cv_done.notify_all();
             cv_work.notify_all();
         }
+        ige_op last = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            if (resident[w].op) {
+                in_use -= resident[w].bytes;
+                last = resident[w].op;
+                resident[w] = Resident{};
+            }
+        }
+        if (last) ige_op_destroy(last);
         if (wctx) ige_ctx_destroy(wctx);
     }
 };
@@ -173,6 +358,8 @@ void fill_stats(const SrvReq &r, ige_srv_stats *st)
     st->assemble_s = r.assemble_s;
     st->solve_s = r.solve_s;
     st->n_waves = r.nw;
+    st->merged = r.merged;
+    st->reused = r.reused ? 1 : 0;
 }
 
 template <typename F>
@@ -217,8 +404,10 @@ int ige_srv_create(ige_ctx ctx, int n_workers, size_t hbm_budget, ige_srv *out)
         }
         srv->budget = hbm_budget;
         srv->origin = std::chrono::steady_clock::now();
+        srv->resident.resize(n_workers);
         ige_srv_s *s = srv.get();
-        for (int i = 0; i < n_workers; ++i) s->workers.emplace_back([s] { s->worker_main(); });
+        for (int i = 0; i < n_workers; ++i) s->workers.emplace_back([s, i] { s->worker_main(i); });
+        ctx->users++;
         *out = srv.release();
     });
 }
@@ -236,6 +425,7 @@ int ige_srv_submit_waves(ige_srv srv, ige_geom geom, const ige_params *prm, int 
         IGE_REQUIRE(srv && geom && prm && dir && pol && opts && ticket, "null argument");
         IGE_REQUIRE(opts->restart >= 1 && opts->maxit >= 0, "bad solve options");
         IGE_REQUIRE(n_waves >= 1 && n_waves <= 4096, "n_waves must be 1..4096");
+        IGE_REQUIRE(prm->kind == IGE_OP_EFIE, "serving solves plane-wave scattering with the EFIE operator only");
         auto r = std::make_unique<SrvReq>();
         r->geom = geom;
         r->prm = *prm;
@@ -247,7 +437,14 @@ int ige_srv_submit_waves(ige_srv srv, ige_geom geom, const ige_params *prm, int 
         ige_op planned = nullptr;
         int rc = ige_op_plan(geom, prm, &planned);
         if (rc != IGE_OK) throw ige::Status{rc, ige_last_error()};
+        int mm = kMergeDefault;
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            mm = srv->max_merge;
+        }
         r->footprint = ige::planned_device_bytes(planned, opts->restart, n_waves, opts);
+        r->fp_merged = ige::planned_device_bytes(planned, opts->restart, std::max(n_waves, mm), opts);
+        r->fp_operator = ige::planned_device_bytes(planned, 0, 1, nullptr);
         r->n_dof = planned->D.N;
         ige_op_destroy(planned);
         std::lock_guard<std::mutex> lk(srv->mu);
@@ -259,7 +456,17 @@ int ige_srv_submit_waves(ige_srv srv, ige_geom geom, const ige_params *prm, int 
         *ticket = r->ticket;
         srv->queue.push_back(r.get());
         srv->all[r->ticket] = std::move(r);
-        srv->cv_work.notify_one();
+        srv->cv_work.notify_all();
+    });
+}
+
+int ige_srv_set_merge(ige_srv srv, int max_waves)
+{
+    return srv_guard([&] {
+        IGE_REQUIRE(srv, "null server");
+        IGE_REQUIRE(max_waves >= 1 && max_waves <= 4096, "max_waves must be 1..4096");
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->max_merge = max_waves;
     });
 }
 
@@ -312,6 +519,7 @@ int ige_srv_destroy(ige_srv srv)
         }
         srv->cv_work.notify_all();
         for (auto &t : srv->workers) t.join();
+        srv->parent->users--;
         delete srv;
     });
 }

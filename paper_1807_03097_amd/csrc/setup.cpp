@@ -341,15 +341,35 @@ void extraction_1d(int deg, int n, std::vector<double> &ext)
 
 }  // namespace
 
-void build_discretisation(Discretisation &D, const Geometry &G, int p, int m)
+void build_discretisation(Discretisation &D, const Geometry &G, int p, int m, int scalar)
 {
     IGE_REQUIRE(p >= 1 && p <= kMaxP, "p must be 1..4");
     IGE_REQUIRE(m >= 0 && m <= 10, "level must be 0..10");
     D.P = G.P; D.p = p; D.m = m; D.n = 1 << m; D.nb = D.n + p;
+    D.scalar = scalar;
     const int n = D.n, nb = D.nb;
     D.dof.assign((size_t)D.P * 2 * nb * nb, -1);
     D.sgn.assign((size_t)D.P * 2 * nb * nb, 0);
     auto at = [&](int j, int a, int i2, int i1) { return (((size_t)j * 2 + a) * nb + i2) * nb + i1; };
+    if (scalar) {
+        // scalar single layer: the (n+p)^2 tensor B-splines of degree p of every patch,
+        // numbered patch, i2, i1, in slot 0 of the table (the density space needs no
+        // continuity across patches)
+        int N = 0;
+        D.inc.clear();
+        for (int j = 0; j < D.P; ++j)
+            for (int i2 = 0; i2 < nb; ++i2)
+                for (int i1 = 0; i1 < nb; ++i1) {
+                    D.dof[at(j, 0, i2, i1)] = N++;
+                    D.sgn[at(j, 0, i2, i1)] = 1;
+                    D.inc.push_back({j, 0, i1, i2, 1});
+                    D.inc.push_back({-1, 0, 0, 0, 0});
+                }
+        D.N = N;
+        extraction_1d(p, n, D.ext_p);
+        extraction_1d(p - 1, n, D.ext_q);
+        return;
+    }
     // outward conormal side of each edge: -1 for u=0 / v=0, +1 for u=1 / v=1
     const int side[4] = {-1, +1, +1, -1};
     int N = 0;
@@ -508,7 +528,8 @@ void build_near_blocks(NearBlocks &B, const Discretisation &D, const Partition &
     const int p = D.p, nb = D.nb, s = T.s, S = 1 << T.L;
     const int W = s + p;
     B.W = W;
-    B.nF = 2 * W * (W - 1);
+    // slots: EFIE W (W-1) per flux component; scalar W x W functions (slot i2 W + i1)
+    B.nF = D.scalar ? W * W : 2 * W * (W - 1);
     IGE_REQUIRE(B.nF <= kMaxLeafSlots, "leaf clusters too large for the near-field blocks (lower leaf_depth)");
     const int nF = B.nF;
     const size_t nleaf = (size_t)D.P * S * S;
@@ -518,8 +539,8 @@ void build_near_blocks(NearBlocks &B, const Discretisation &D, const Partition &
         for (int k2 = 0; k2 < S; ++k2)
             for (int k1 = 0; k1 < S; ++k1) {
                 const size_t lid = ((size_t)j * S + k2) * S + k1;
-                for (int a = 0; a < 2; ++a) {
-                    const int w1 = (a == 0) ? W : W - 1, w2 = (a == 0) ? W - 1 : W;
+                for (int a = 0; a < (D.scalar ? 1 : 2); ++a) {
+                    const int w1 = (a == 0) ? W : W - 1, w2 = (a == 0 && !D.scalar) ? W - 1 : W;
                     for (int i2 = 0; i2 < w2; ++i2)
                         for (int i1 = 0; i1 < w1; ++i1) {
                             const size_t off = (((size_t)j * 2 + a) * nb + k2 * s + i2) * nb + k1 * s + i1;
@@ -583,8 +604,8 @@ void build_near_compact(NearCompact &C, const Discretisation &D, const Partition
     // incarnation in canonical order
     std::vector<int32_t> own((size_t)N, -1);
     for (int j = 0; j < D.P; ++j)
-        for (int a = 0; a < 2; ++a) {
-            const int n1 = a == 0 ? n + p : n + p - 1, n2 = a == 0 ? n + p - 1 : n + p;
+        for (int a = 0; a < (D.scalar ? 1 : 2); ++a) {
+            const int n1 = a == 0 ? n + p : n + p - 1, n2 = (a == 0 && !D.scalar) ? n + p - 1 : n + p;
             for (int i2 = 0; i2 < n2; ++i2)
                 for (int i1 = 0; i1 < n1; ++i1) {
                     const int32_t g = D.dof[(((size_t)j * 2 + a) * nb + i2) * nb + i1];

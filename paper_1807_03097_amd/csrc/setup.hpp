@@ -35,6 +35,7 @@ void lagrange_bary(int q, const double *xn, double s, double *L);
 
 struct Discretisation {
     int P, p, m, n, nb, N;
+    int scalar = 0;             // 1: scalar single layer (tensor B-splines of degree p per patch, not glued)
     std::vector<int32_t> dof;   // [P][2][nb][nb]
     std::vector<int8_t> sgn;
     // per unknown up to two incarnations (patch, comp, i1, i2, sign); patch -1 = none
@@ -45,7 +46,7 @@ struct Discretisation {
     std::vector<double> ext_p, ext_q;
 };
 
-void build_discretisation(Discretisation &D, const Geometry &G, int p, int m);
+void build_discretisation(Discretisation &D, const Geometry &G, int p, int m, int scalar = 0);
 
 struct Partition {
     int L = 0;                    // leaf level

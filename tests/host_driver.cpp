@@ -61,16 +61,17 @@ int g_fail = 0;
     } while (0)
 
 // plan one operator and read everything a planned operator answers
-void plan_one(ige_geom geom, int p, int level, double kappa, int q, double eta, int d, double cap, int P)
+void plan_one(ige_geom geom, int p, int level, double kappa, int q, double eta, int d, double cap, int P,
+              int kind = IGE_OP_EFIE)
 {
-    ige_params prm{p, level, kappa, q, eta, 5, 5, d, 0, cap};
+    ige_params prm{p, level, kappa, q, eta, 5, 5, d, 0, cap, kind};
     ige_op op = nullptr;
     CHECK(ige_op_plan(geom, &prm, &op) == IGE_OK);
     if (!op) return;
     ige_op_info_t info{};
     CHECK(ige_op_info(op, &info) == IGE_OK);
     const int64_t n = (int64_t)1 << level, nb = n + p;
-    CHECK(info.n_dof == 2 * (int64_t)P * (n + p - 1) * (n + p - 1));
+    CHECK(info.n_dof == (kind == IGE_OP_SCALAR ? (int64_t)P * nb * nb : 2 * (int64_t)P * (n + p - 1) * (n + p - 1)));
     CHECK(info.near_distinct > 0 && info.near_distinct <= info.n_dof * (info.n_dof + 1) / 2);
     std::vector<int32_t> dof((size_t)P * 2 * nb * nb), far((size_t)3 * info.far_pairs + 1),
         near((size_t)2 * info.near_leaf_pairs + 1);
@@ -98,6 +99,9 @@ void error_paths(ige_geom geom)
     CHECK(std::string(ige_last_error()).find("kappa") != std::string::npos);
     ige_params bad3{2, 2, 1.0, 8, 1.0, 5, 5, -1, 0, -2.0};
     CHECK(ige_op_plan(geom, &bad3, &op) == IGE_EINVAL);
+    ige_params bad4{2, 2, 1.0, 8, 1.0, 5, 5, -1, 0, 0.0, 7};
+    CHECK(ige_op_plan(geom, &bad4, &op) == IGE_EINVAL);
+    CHECK(std::string(ige_last_error()).find("kind") != std::string::npos);
     CHECK(ige_op_plan(nullptr, &bad, &op) == IGE_EINVAL);
     ige_params ok{1, 1, 1.0, 4, 1.0, 5, 5, -1, 0, 0.0};
     CHECK(ige_op_plan(geom, &ok, &op) == IGE_OK);   // success clears the error text
@@ -116,6 +120,7 @@ void worker(const GeomData *gd, ige_geom shared, int id)
         const int p = 1 + (id + k) % 4;
         plan_one(own, p, 2 + (id + k) % 2, 2.0 + id, 6, 1.0, 1, 0.0, gd->P);
         plan_one(shared, 1 + (id + k + 1) % 3, 3, 8.0, 8, 1.6, 1 + k % 2, (k == 2) ? 8.0 : 0.0, gd->P);
+        plan_one(own, 1 + (id + k) % 4, 3, 4.0, 6, 1.0, 1, 0.0, gd->P, IGE_OP_SCALAR);
         error_paths(own);
     }
     CHECK(ige_geom_destroy(own) == IGE_OK);
@@ -157,6 +162,8 @@ int main(int argc, char **argv)
     std::vector<std::thread> th;
     for (int i = 0; i < nt; ++i) th.emplace_back(worker, &gd, geom, i);
     for (auto &t : th) t.join();
+    // a context outlives what was made on it
+    CHECK(ige_ctx_destroy(ctx) == IGE_EINVAL);
     CHECK(ige_geom_destroy(geom) == IGE_OK);
     CHECK(ige_ctx_destroy(ctx) == IGE_OK);
     if (g_fail) {

@@ -138,3 +138,38 @@ def test_near_distinct_entries_match_oracle_pattern(oracle_mod, geom, p, m, eta,
         keys.update((np.minimum(ii, jj).ravel() * o.N + np.maximum(ii, jj).ravel()).tolist())
     assert op.info.near_distinct == len(keys)
     assert op.info.near_distinct < op.info.near_nnz or eta == 0.0
+
+
+@pytest.mark.parametrize("p,m,eta,d", [(1, 3, 1.0, 1), (2, 3, 1.6, 1), (4, 2, 1.0, 1)])
+def test_scalar_plan_matches_oracle(oracle_mod, p, m, eta, d):
+    """The scalar single layer (kind IGE_OP_SCALAR): unknown table, partition and the
+    count of distinct near-field entries equal the oracle's (tensor B-splines of degree
+    p on every patch, supports of p + 1 elements per direction)."""
+    from paper_1807_03097_amd import binding as B
+    pats = W.cube_sphere()
+    ctx = B.Context(-1)
+    g = B.Geometry(ctx, pats)
+    op = B.Operator(g, p, m, 4.0, 6, eta, leaf_depth=d, plan_only=True, kind=B.IGE_OP_SCALAR)
+    o = oracle_mod.Oracle(pats, p, m, 4.0, g=2, scalar=True)
+    assert op.N == o.N == len(pats) * ((1 << m) + p) ** 2
+    dof, sgn = op.dofmap()
+    assert np.array_equal(dof, o.dof) and np.array_equal(sgn, o.sgn)
+    tr = o.block_tree(eta, d)
+    pt = op.partition()
+    assert np.array_equal(pt["far"], tr["far"]) and np.array_equal(pt["near"], tr["near"])
+    L, n = tr["L"], 1 << m
+    s, SL = n >> L, 1 << L
+    sets = [set() for _ in range(o.P * SL * SL)]
+    J, _, I2, I1 = np.nonzero(o.dof >= 0)
+    for j, i2, i1 in zip(J, I2, I1):
+        for e2 in range(max(0, i2 - p), min(n, i2 + 1)):
+            for e1 in range(max(0, i1 - p), min(n, i1 + 1)):
+                sets[(j * SL + e2 // s) * SL + e1 // s].add(int(o.dof[j, 0, i2, i1]))
+    keys = set()
+    for t, u in tr["near"]:
+        I = np.array(sorted(sets[t])); Jv = np.array(sorted(sets[u]))
+        ii, jj = np.meshgrid(I, Jv, indexing="ij")
+        keys.update((np.minimum(ii, jj).ravel() * o.N + np.maximum(ii, jj).ravel()).tolist())
+    assert op.info.near_distinct == len(keys)
+    with pytest.raises(B.IgeError):
+        B.Operator(g, p, m, 4.0, 6, eta, leaf_depth=d, plan_only=True, kind=2)

@@ -219,3 +219,61 @@ def test_multi_wave_requests_match_direct_solves():
     for g in geoms.values():
         g.close()
     ctx.close()
+
+
+@pytest.mark.gpu
+def test_waiting_requests_on_one_operator_are_merged_and_the_operator_stays_resident():
+    """Continuous batching: single-wave requests on the same object that wait behind a
+    running one are solved together as one many-column system; each meets the FP64
+    tolerance and agrees with its direct solve within the tolerance-aware bound (the
+    residual of the difference is at most the sum of the two residuals).  A later
+    request on the same object runs on the resident operator (no assembly) and equals
+    its direct solve bit for bit."""
+    from paper_1807_03097_amd import binding as B
+    ctx = B.Context(0)
+    geoms = {n: _geom(B, ctx, n) for n in ("sphere", "torus")}
+    n, p, m, kap, q, eta, d, _ = REQS[2]
+    seeds = [21, 22, 23, 24, 25]
+    op = B.Operator(geoms[n], p, m, kap, q, eta, 5, 5, d)
+    direct = {}
+    for sd in seeds:
+        di, pol = _wave(sd)
+        f = op.rhs_plane_wave(di, pol)[0]
+        x, st, rc = op.solve(f, tol=TOL, restart=300, maxit=3000)
+        assert rc == 0
+        direct[sd] = (x, f)
+    srv = B.Server(ctx, 1, max_merge=8)
+    # a blocker on another object keeps the single worker busy while the others queue
+    nb, pb, mb, kb, qb, eb, db, sb = REQS[4]
+    db_, pol_ = _wave(sb)
+    tb = srv.submit(geoms[nb], pb, mb, kb, db_, pol_, q=qb, eta=eb, leaf_depth=db, tol=TOL, restart=300, maxit=3000)
+    ts = []
+    for sd in seeds[:4]:
+        di, pol = _wave(sd)
+        ts.append(srv.submit(geoms[n], p, m, kap, di, pol, q=q, eta=eta, leaf_depth=d, tol=TOL, restart=300,
+                             maxit=3000))
+    srv.wait(tb)
+    for sd, t in zip(seeds[:4], ts):
+        x, st = srv.result(t)
+        xd, f = direct[sd]
+        dx = x - xd
+        res_diff = np.linalg.norm(op.apply(dx)) / np.linalg.norm(f)
+        print(f"seed {sd}: merged {st['merged']} reused {st['reused']} iters {st['iters']} relres {st['relres']:.1e} "
+              f"vs direct {np.linalg.norm(dx) / np.linalg.norm(xd):.1e}, residual of the difference {res_diff:.1e}",
+              flush=True)
+        assert st["rc"] == 0 and st["relres"] <= TOL * 1.05
+        assert res_diff <= 2.1 * TOL
+    stats = [srv.wait(t) for t in ts]
+    assert max(s["merged"] for s in stats) >= 2
+    # the same object again, alone: resident operator, same bits as the direct solve
+    di, pol = _wave(seeds[4])
+    t5 = srv.submit(geoms[n], p, m, kap, di, pol, q=q, eta=eta, leaf_depth=d, tol=TOL, restart=300, maxit=3000)
+    x5, s5 = srv.result(t5)
+    print(f"resident: reused {s5['reused']} assemble {s5['assemble_s']:.3f} s merged {s5['merged']}", flush=True)
+    assert s5["reused"] == 1 and s5["assemble_s"] == 0.0 and s5["merged"] == 1
+    assert _same(x5, direct[seeds[4]][0])
+    srv.close()
+    op.close()
+    for g in geoms.values():
+        g.close()
+    ctx.close()
