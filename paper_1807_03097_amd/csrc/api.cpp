@@ -897,10 +897,17 @@ namespace {
 struct ApplyGraph {
     int r = -1, prec = -1, eager = 0;
     hipGraphExec_t exec = nullptr;
+    hipStream_t launched = nullptr;   // stream of the last launch of exec
+    // an executable graph is destroyed only after its launches have completed (also when
+    // a solve unwinds from an error with a launch still in flight)
     void reset()
     {
-        if (exec) (void)hipGraphExecDestroy(exec);
+        if (exec) {
+            if (launched) (void)hipStreamSynchronize(launched);
+            (void)hipGraphExecDestroy(exec);
+        }
         exec = nullptr;
+        launched = nullptr;
         eager = 0;
     }
     ~ApplyGraph() { reset(); }
@@ -916,6 +923,7 @@ void run_graph(ige_op op, ApplyGraph *g, int r, int prec, const std::function<vo
 {
     hipStream_t s = op->ctx->stream;
     if (g->exec && g->r == r && g->prec == prec) {
+        g->launched = s;
         IGE_HIP(hipGraphLaunch(g->exec, s));
         return;
     }
@@ -946,6 +954,7 @@ void run_graph(ige_op op, ApplyGraph *g, int r, int prec, const std::function<vo
     const hipError_t e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     IGE_HIP(e);
+    g->launched = s;
     IGE_HIP(hipGraphLaunch(g->exec, s));
 }
 
