@@ -50,6 +50,7 @@ typedef double complex cplx;
 
 #define MAXDEG 4          /* max discretisation degree p */
 #define MAXQ 16           /* max interpolation degree q */
+#define MAXLEV 10         /* max cluster-tree level */
 #define MAXLOC 40         /* max local glued functions on one element: 2 p (p+1), p <= 4 */
 #define MAXG 24           /* max Gauss points per direction */
 
@@ -1105,23 +1106,32 @@ static clu_t clu_of(int lvl, int id)
  * tmask: optional per-element mask of test elements to evaluate (rows touched only
  * by masked elements are complete).
  */
-int or_fmm_apply(void *h, int q, int L, int nfar, const int32_t *far_lvl, const int32_t *far_tgt,
+/* qlev[l]: interpolation degree of the clusters of level l = 0..L (the same degree on
+ * every level is the method of Sec. 4.2; a degree per level is the variable-order form,
+ * each level's moments and node geometry taken directly with its own degree) */
+int or_fmm_apply(void *h, const int32_t *qlev, int L, int nfar, const int32_t *far_lvl, const int32_t *far_tgt,
                  const int32_t *far_src, int nnear, const int32_t *near_tgt, const int32_t *near_src,
                  const double *xin, double *yout, const uint8_t *tmask)
 {
     ctx_t *c = (ctx_t *)h;
-    if (q < 1 || q > MAXQ || L < 0 || L > c->m) return -1;
+    if (!qlev || L < 0 || L > c->m) return -1;
+    int qmax = 0;
+    for (int l = 0; l <= L; ++l) {
+        if (qlev[l] < 1 || qlev[l] > MAXQ) return -1;
+        if (qlev[l] > qmax) qmax = qlev[l];
+    }
     int n = c->n, E = c->P * n * n, nl = nloc(c), ng = c->g * c->g, p = c->p;
-    int Q1 = q + 1, Q = Q1 * Q1;
+    /* per-cluster storage with the largest node count; level l uses its first Q_l */
+    int Q = (qmax + 1) * (qmax + 1);
     double hh = 1.0 / n, ik2 = 1.0 / (c->kappa * c->kappa);
     const cplx *x = (const cplx *)xin;
     cplx *y = (cplx *)yout;
     memset(y, 0, sizeof(cplx) * c->N);
-    double xn[MAXQ + 1];
-    cheb_nodes(q, xn);
+    double xnl[MAXLEV + 1][MAXQ + 1];
+    for (int l = 0; l <= L; ++l) cheb_nodes(qlev[l], xnl[l]);
 
-    /* Gauss rule exact for degree q + p per direction (moment integrals) */
-    int nm = (q + p + 2) / 2 + 1;
+    /* Gauss rule exact for degree qmax + p per direction (moment integrals) */
+    int nm = (qmax + p + 2) / 2 + 1;
     double mx[MAXG], mw[MAXG];
     or_gauss_legendre(nm, mx, mw);
     int nmq = nm * nm;
@@ -1192,6 +1202,8 @@ int or_fmm_apply(void *h, int q, int L, int nfar, const int32_t *far_lvl, const 
         int s = 1 << l, sub = n / s;   /* elements per cluster side */
         double H = 1.0 / s;
         long ncl = (long)c->P * s * s;
+        const int q = qlev[l], Q1 = q + 1;
+        const double *xn = xnl[l];
 #pragma omp parallel for schedule(dynamic, 4)
         for (long id = 0; id < ncl; ++id) {
             clu_t cl = clu_of(l, (int)id);
@@ -1246,18 +1258,19 @@ int or_fmm_apply(void *h, int q, int L, int nfar, const int32_t *far_lvl, const 
             int l = far_lvl[f];
             size_t ti = lvoff[l] + far_tgt[f], si = lvoff[l] + far_src[f];
             if (!tneed[ti]) continue;
+            const int Ql = (qlev[l] + 1) * (qlev[l] + 1);   /* nodes of this level */
             const double *Gt = geo + ti * Q * 9, *Gs = geo + si * Q * 9;
             const cplx *Ms = mom + si * Q * 3;
             cplx *tl = (cplx *)malloc(sizeof(cplx) * Q * 3);
             memset(tl, 0, sizeof(cplx) * Q * 3);
-            for (int mt = 0; mt < Q; ++mt) {
+            for (int mt = 0; mt < Ql; ++mt) {
                 const double *xt = Gt + mt * 9;
-                for (int ms = 0; ms < Q; ++ms) K[ms] = kernel_eval(c, xt, Gs + ms * 9);
+                for (int ms = 0; ms < Ql; ++ms) K[ms] = kernel_eval(c, xt, Gs + ms * 9);
                 if (c->scalar) {
                     /* scalar localized kernel G(x_m, x'_m') |J(x_m)| |J'(x'_m')| on the moments */
                     double Jt = surf_elem(xt);
                     cplx s = 0;
-                    for (int ms = 0; ms < Q; ++ms) s += K[ms] * surf_elem(Gs + ms * 9) * Ms[ms * 3 + 2];
+                    for (int ms = 0; ms < Ql; ++ms) s += K[ms] * surf_elem(Gs + ms * 9) * Ms[ms * 3 + 2];
                     tl[mt * 3 + 2] += Jt * s;
                     continue;
                 }
@@ -1265,7 +1278,7 @@ int or_fmm_apply(void *h, int q, int L, int nfar, const int32_t *far_lvl, const 
                     const double *da = xt + 3 + 3 * a;
                     cplx s = 0;
                     for (int b = 0; b < 2; ++b)
-                        for (int ms = 0; ms < Q; ++ms) {
+                        for (int ms = 0; ms < Ql; ++ms) {
                             const double *db = Gs + ms * 9 + 3 + 3 * b;
                             cplx K1 = K[ms] * (da[0] * db[0] + da[1] * db[1] + da[2] * db[2]);
                             s += K1 * Ms[ms * 3 + b];
@@ -1273,7 +1286,7 @@ int or_fmm_apply(void *h, int q, int L, int nfar, const int32_t *far_lvl, const 
                     tl[mt * 3 + a] += s;
                 }
                 cplx s = 0;
-                for (int ms = 0; ms < Q; ++ms) s += -ik2 * K[ms] * Ms[ms * 3 + 2];
+                for (int ms = 0; ms < Ql; ++ms) s += -ik2 * K[ms] * Ms[ms * 3 + 2];
                 tl[mt * 3 + 2] += s;
             }
             cplx *dst = loc + ti * Q * 3;
@@ -1344,6 +1357,8 @@ int or_fmm_apply(void *h, int q, int L, int nfar, const int32_t *far_lvl, const 
                 int s = 1 << l, sub = n / s;
                 double H = 1.0 / s;
                 int k1 = e1 / sub, k2 = e2 / sub;
+                const int q = qlev[l], Q1 = q + 1;
+                const double *xn = xnl[l];
                 const cplx *T = loc + (lvoff[l] + (size_t)j * s * s + k2 * s + k1) * Q * 3;
                 for (int b = 0; b < nm; ++b)
                     for (int a = 0; a < nm; ++a) {

@@ -70,7 +70,7 @@ def lib():
             "or_field": [P, C.c_int, P, C.c_int, P, P],
             "or_potential": [P, P, C.c_int, P, P],
             "or_lagrange": [C.c_int, C.c_int, P, P],
-            "or_fmm_apply": [P, C.c_int, C.c_int, C.c_int, P, P, P, C.c_int, P, P, P, P, P],
+            "or_fmm_apply": [P, P, C.c_int, C.c_int, P, P, P, C.c_int, P, P, P, P, P],
             "or_field_param": [P, P, C.c_int, C.c_int, P, P],
             "or_div_integrals": [P, P],
         }.items():
@@ -446,7 +446,10 @@ class Oracle:
         return {"L": L, "far": farr, "near": near}
 
     # ---- FMM --------------------------------------------------------------------
-    def fmm_apply(self, x, q: int, eta: float, d: int, rows=None, tree=None):
+    def fmm_apply(self, x, q, eta: float, d: int, rows=None, tree=None):
+        """The compressed operator of Sec. 4.2 applied to x.  q: the interpolation
+        degree, or one degree per cluster-tree level 0..L (entries beyond L are
+        ignored; an entry 0 takes the last positive one before it)."""
         if tree is None:
             tree = self.block_tree(eta, d)
         far, near = tree["far"], tree["near"]
@@ -458,10 +461,26 @@ class Oracle:
         x = np.ascontiguousarray(x, np.complex128)
         y = np.zeros(self.N, np.complex128)
         mask = None if rows is None else self.support_elements(rows)
-        rc = lib().or_fmm_apply(self._h, q, tree["L"], len(fl), _p(fl), _p(ft), _p(fs), len(nt), _p(nt), _p(ns),
-                                _p(x), _p(y), _p(mask))
+        qlev = level_degrees(q, tree["L"])
+        rc = lib().or_fmm_apply(self._h, _p(qlev), tree["L"], len(fl), _p(fl), _p(ft), _p(fs), len(nt), _p(nt),
+                                _p(ns), _p(x), _p(y), _p(mask))
         assert rc == 0
         return y if rows is None else y[np.asarray(rows)]
+
+
+def level_degrees(q, L: int):
+    """Interpolation degree of every cluster-tree level 0..L as an int32 array: q an
+    int (the same degree on every level) or a sequence per level, where 0 repeats the
+    degree of the level before (level 0 must be given)."""
+    if np.ndim(q) == 0:
+        return np.full(L + 1, int(q), np.int32)
+    qs = [int(v) for v in q] + [0] * (L + 1)
+    out = np.zeros(L + 1, np.int32)
+    for l in range(L + 1):
+        out[l] = qs[l] if qs[l] > 0 else (out[l - 1] if l > 0 else 0)
+    if out.min() < 1:
+        raise ValueError("level 0 needs a positive degree")
+    return out
 
 
 # ---------------------------------------------------------------------------

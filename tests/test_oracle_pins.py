@@ -477,15 +477,19 @@ def _dense_rows(name):
 
 
 @pytest.mark.slow
-def test_high_kappa_accuracy_needs_kappa_cap(oracle_mod):
+def test_high_kappa_accuracy_needs_kappa_cap_or_level_degrees(oracle_mod):
     """The admissibility condition (eq:admissibility) does not involve kappa, so at a
     fixed q the compression error grows with kappa * diam of the coarse clusters.  On
     sampled dense rows (tests/golden/c3_, c5_dense_rows.json, written from the oracle
     alone): level 6, kappa = 16, q = 8, eta = 1.6 misses 1e-6 with the paper's condition
-    and meets it with kappa * diam <= 8; the jittered level-7 sphere at kappa = 40
-    loses three digits at q = 10 and meets 1e-6 with q = 11 and kappa * diam <= 12."""
+    and meets it with kappa * diam <= 8, or, on the same partition, with degrees that
+    grow with kappa * diam (degree_rule: 14, 10, 8 on levels 1..3).  The jittered
+    level-7 sphere at kappa = 40 loses three digits at q = 10 and meets 1e-6 with q = 11
+    and kappa * diam <= 12; its level-1 blocks would need degrees beyond 15, so there the
+    rule runs with kappa_cap = 2 (15 - 5) = 20 and gives 11, 10 on levels 3, 4."""
     res = {}
-    for name, jit, cases in (("c3", None, ((8, 0.0), (8, 8.0))), ("c5", (0.02, 7), ((10, 0.0), (11, 12.0)))):
+    for name, jit, cases, rcap in (("c3", None, ((8, 0.0), (8, 8.0)), 0.0),
+                                   ("c5", (0.02, 7), ((10, 0.0), (11, 12.0)), 20.0)):
         g, rows, yd = _dense_rows(name)
         pats = W.cube_sphere() if jit is None else W.jitter(W.cube_sphere(), *jit)
         cf = g["config"]
@@ -496,9 +500,56 @@ def test_high_kappa_accuracy_needs_kappa_cap(oracle_mod):
             tr = o.block_tree(1.6, 3, kappa_cap=cap)
             y = o.fmm_apply(x, q, 1.6, 3, rows=rows, tree=tr)
             res[(name, q, cap)] = np.linalg.norm(y - yd) / np.linalg.norm(yd)
+        tr = o.block_tree(1.6, 3, kappa_cap=rcap)
+        ql = degree_rule(o, tr, cf["kappa"], cases[0][0])
+        y = o.fmm_apply(x, ql, 1.6, 3, rows=rows, tree=tr)
+        res[(name, "rule")] = (ql, np.linalg.norm(y - yd) / np.linalg.norm(yd))
     print(res)
     assert res[("c3", 8, 0.0)] > 1e-5 and res[("c3", 8, 8.0)] <= 1e-6
     assert res[("c5", 10, 0.0)] > 1e-4 and res[("c5", 11, 12.0)] <= 1e-6
+    assert res[("c3", "rule")][0] == [8, 14, 10, 8] and res[("c3", "rule")][1] <= 1e-6
+    assert res[("c5", "rule")][0][3:] == [11, 10] and res[("c5", "rule")][1] <= 1e-6
+
+
+def degree_rule(o, tree, kappa, q, qmax=15, extra=5):
+    """Interpolation degree per level from the oscillation of the kernel over the
+    clusters: q_l = min(qmax, max(q, ceil(kappa * diam_l / 2) + extra)) on levels with far
+    blocks (diam_l the largest bounding-ball diameter of the level), q elsewhere."""
+    nfar = np.bincount(tree["far"][:, 0], minlength=tree["L"] + 1) if len(tree["far"]) else np.zeros(tree["L"] + 1)
+    out = []
+    for lvl in range(tree["L"] + 1):
+        if nfar[lvl] == 0:
+            out.append(q)
+            continue
+        _, rad = o.bounding_balls(lvl)
+        out.append(int(min(qmax, max(q, np.ceil(kappa * 2 * rad.max() / 2) + extra))))
+    return out
+
+
+def test_level_degrees_pin_each_level(oracle_mod):
+    """A degree per cluster-tree level (the variable-order form of Sec. 4.2): with the
+    polynomial test kernel on flat patches every level whose far blocks are interpolated
+    with degree >= 4 is exact, whatever the others get, so the compressed operator equals
+    the dense one for any such choice; degree 2 on a level is visible exactly when that
+    level has far blocks (level 0 has none here).  This pins that each level's moments,
+    nodes and test-side expansions use that level's own degree."""
+    o = oracle_mod.Oracle(W.flat_cube(), 1, 3, 3.0, g=8, gs=8, kernel=1)
+    tr = o.block_tree(1.6, 1)
+    nfar = np.bincount(tr["far"][:, 0], minlength=tr["L"] + 1)
+    assert tr["L"] == 2 and nfar[0] == 0 and np.all(nfar[1:] > 0)
+    x = W.random_coeffs(o.N, 2)
+    yd = o.dense_apply(x)
+    y5 = o.fmm_apply(x, 5, 1.6, 1, tree=tr)
+    # (the oracle sums its far field with atomic adds: equal up to summation order)
+    assert np.linalg.norm(o.fmm_apply(x, [5, 5, 5], 1.6, 1, tree=tr) - y5) <= 1e-14 * np.linalg.norm(y5)
+    for q in ([4, 5, 6], [7, 6, 4], [2, 5, 5], [11, 4, 9]):
+        y = o.fmm_apply(x, q, 1.6, 1, tree=tr)
+        assert np.linalg.norm(y - yd) <= 1e-12 * np.linalg.norm(yd), q
+    for lvl in (1, 2):
+        q = [5, 5, 5]
+        q[lvl] = 2
+        y = o.fmm_apply(x, q, 1.6, 1, tree=tr)
+        assert np.linalg.norm(y - yd) > 1e-6 * np.linalg.norm(yd), q
 
 
 def test_kappa_cap_only_refines_the_partition(oracle_mod):
