@@ -116,7 +116,17 @@ int ige_geom_destroy(ige_geom geom);
  *                 continuity across patches, unknowns ordered patch, i2, i1), compressed
  *                 with the K_2 block alone (eq:FMMlr with the surface elements inside
  *                 the localized kernel).  The scalar operator applies and solves in FP64
- *                 only; refinement, autotuning, plane-wave fields and serving refuse it. */
+ *                 only; refinement, autotuning, plane-wave fields and serving refuse it.
+ *   q_level       interpolation degree per cluster-tree level l = 0..10 (0: q), 1..15:
+ *                 the far blocks of level l are interpolated with q_level[l] + 1 nodes
+ *                 per direction (the variable-order form of Sec. 4.2; the paper uses one
+ *                 q).  Degrees that grow with kappa * diam of the level's clusters keep
+ *                 the accuracy at high kappa without refining the partition; a rule is
+ *                 q_l = min(15, max(q, ceil(kappa diam_l / 2) + 5)) on the levels with far
+ *                 blocks, with diam_l from ige_op_info of the planned operator.  With
+ *                 degrees that differ between levels the operator applies in FP64 or
+ *                 FP32 (ige_apply_prec IGE_F32) only, column by column; stored coupling
+ *                 blocks, the matrix-core precisions and autotuning refuse it. */
 enum { IGE_OP_EFIE = 0, IGE_OP_SCALAR = 1 };
 typedef struct {
     int p, level;
@@ -127,6 +137,7 @@ typedef struct {
     int store_coupling;
     double kappa_cap;
     int kind;
+    int q_level[11];
 } ige_params;
 
 /* Assemble the operator on the device: element and cluster-node geometry, the
@@ -156,6 +167,9 @@ typedef struct {
     int64_t near_distinct;  /* distinct entries of the symmetric near-field matrix in the
                                glued basis (i <= j): the values the product of one column
                                streams (each once) */
+    int32_t q_level[11];    /* interpolation degree of each level 0..leaf_level (0 beyond) */
+    double level_diam[11];  /* largest bounding-ball diameter of the clusters of each level
+                               0..leaf_level (0 beyond) */
 } ige_op_info_t;
 int ige_op_info(ige_op op, ige_op_info_t *out);
 

@@ -32,14 +32,16 @@ class IgeError(RuntimeError):
 class ige_params(C.Structure):
     _fields_ = [("p", C.c_int), ("level", C.c_int), ("kappa", C.c_double), ("q", C.c_int), ("eta", C.c_double),
                 ("gauss_near", C.c_int), ("gauss_singular", C.c_int), ("leaf_depth", C.c_int),
-                ("store_coupling", C.c_int), ("kappa_cap", C.c_double), ("kind", C.c_int)]
+                ("store_coupling", C.c_int), ("kappa_cap", C.c_double), ("kind", C.c_int),
+                ("q_level", C.c_int * 11)]
 
 
 class ige_op_info_t(C.Structure):
     _fields_ = [("n_dof", C.c_int64), ("n_elements", C.c_int64), ("near_nnz", C.c_int64),
                 ("far_pairs", C.c_int64), ("near_leaf_pairs", C.c_int64), ("singular_pairs", C.c_int64),
                 ("leaf_level", C.c_int32), ("q", C.c_int32), ("device_bytes", C.c_int64),
-                ("assemble_ms", C.c_double), ("near_distinct", C.c_int64)]
+                ("assemble_ms", C.c_double), ("near_distinct", C.c_int64), ("q_level", C.c_int32 * 11),
+                ("level_diam", C.c_double * 11)]
 
 
 IGE_F64, IGE_F32, IGE_BF16, IGE_BF16X3, IGE_BF16X3_ALL = 0, 1, 2, 3, 4
@@ -298,13 +300,40 @@ class Geometry:
             pass
 
 
+def _levels(q_level):
+    """ige_params.q_level from a sequence of per-level degrees (0: the base q)"""
+    arr = (C.c_int * 11)()
+    if q_level is not None:
+        ql = [int(v) for v in q_level]
+        if len(ql) > 11:
+            raise ValueError("at most 11 levels")
+        for i, v in enumerate(ql):
+            arr[i] = v
+    return arr
+
+
+def degree_rule(info, kappa: float, q: int, far_levels, qmax: int = 15, extra: int = 5):
+    """Interpolation degree per level that grows with the oscillation of the kernel
+    over the level's clusters: q_l = min(qmax, max(q, ceil(kappa diam_l / 2) + extra))
+    on the levels that have far blocks (far_levels), q elsewhere; diam_l from the
+    operator info (ige_op_info of a planned operator)."""
+    import math
+    out = []
+    for lvl in range(int(info.leaf_level) + 1):
+        if lvl in far_levels:
+            out.append(int(min(qmax, max(q, math.ceil(kappa * info.level_diam[lvl] / 2) + extra))))
+        else:
+            out.append(int(q))
+    return out
+
+
 class Operator:
     def __init__(self, geom: Geometry, p: int, level: int, kappa: float, q: int = 8, eta: float = 1.0,
                  gauss_near: int = 5, gauss_singular: int = 5, leaf_depth: int = -1, plan_only: bool = False,
-                 store_coupling: int = -1, kappa_cap: float = 0.0, kind: int = IGE_OP_EFIE):
+                 store_coupling: int = -1, kappa_cap: float = 0.0, kind: int = IGE_OP_EFIE, q_level=None):
         self.geom = geom
         self.prm = ige_params(p, level, kappa, q, eta, gauss_near, gauss_singular, leaf_depth, store_coupling,
-                              kappa_cap, kind)
+                              kappa_cap, kind, _levels(q_level))
         self.h = ige_op_plan(geom.h, self.prm) if plan_only else ige_op_assemble(geom.h, self.prm)
         geom.ctx._deps.add(self)
         self.info = ige_op_info(self.h)
@@ -334,6 +363,13 @@ class Operator:
 
     def geom_patches(self):
         return int(self.info.n_elements) >> (2 * self.level)
+
+    def q_levels(self):
+        """interpolation degree of each level 0..leaf level"""
+        return [int(self.info.q_level[l]) for l in range(int(self.info.leaf_level) + 1)]
+
+    def level_diameters(self):
+        return [float(self.info.level_diam[l]) for l in range(int(self.info.leaf_level) + 1)]
 
     def partition(self):
         far = np.zeros((int(self.info.far_pairs), 3), np.int32)
@@ -488,8 +524,9 @@ class Server:
 
     def submit(self, geom: Geometry, p, level, kappa, direction, pol, q=8, eta=1.0, leaf_depth=-1,
                gauss_near=5, gauss_singular=5, tol=1e-6, restart=1500, maxit=10000, refine=False,
-               inner_tol=1e-4, inner_prec=IGE_F32, kappa_cap=0.0, kind=IGE_OP_EFIE):
-        prm = ige_params(p, level, kappa, q, eta, gauss_near, gauss_singular, leaf_depth, 0, kappa_cap, kind)
+               inner_tol=1e-4, inner_prec=IGE_F32, kappa_cap=0.0, kind=IGE_OP_EFIE, q_level=None):
+        prm = ige_params(p, level, kappa, q, eta, gauss_near, gauss_singular, leaf_depth, 0, kappa_cap, kind,
+                         _levels(q_level))
         opts = ige_solve_opts(tol, restart, maxit, int(refine), inner_tol, inner_prec)
         if np.ndim(direction) == 2:   # [W][3] directions and polarisations: one request of W waves
             t = ige_srv_submit_waves(self.h, geom.h, prm, direction, pol, opts)

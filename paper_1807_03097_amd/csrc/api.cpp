@@ -252,6 +252,8 @@ void check_params(const ige_params &P)
     IGE_REQUIRE(P.store_coupling >= -1 && P.store_coupling <= 1, "store_coupling must be -1, 0 or 1");
     IGE_REQUIRE(std::isfinite(P.kappa_cap) && P.kappa_cap >= 0.0, "kappa_cap must be >= 0");
     IGE_REQUIRE(P.kind == IGE_OP_EFIE || P.kind == IGE_OP_SCALAR, "kind must be IGE_OP_EFIE or IGE_OP_SCALAR");
+    for (int l = 0; l < 11; ++l)
+        IGE_REQUIRE(P.q_level[l] >= 0 && P.q_level[l] <= 15, "q_level entries must be 0 (q) or 1..15");
 }
 
 // host part: unknowns, trees, near pattern, singular pairs, far tables
@@ -262,7 +264,10 @@ void plan(ige_op op, const ige_geom_s *geom, ige::NearBlocks &A, std::vector<ige
     if (d < 0) d = std::max(0, (int)std::ceil(std::log2((P.q + 1.0) / (P.p + 1.0)) - 1e-12));
     ige::build_discretisation(op->D, geom->G, P.p, P.level, P.kind == IGE_OP_SCALAR ? 1 : 0);
     ige::build_partition(op->T, geom->G, op->D, P.eta, d, P.kappa, P.kappa_cap);
-    ige::build_far_tables(op->F, op->D, op->T, P.q);
+    std::vector<int> ql((size_t)op->T.L + 1);
+    for (int l = 0; l <= op->T.L; ++l) ql[l] = P.q_level[l] > 0 ? P.q_level[l] : P.q;
+    ige::build_far_tables(op->F, op->D, op->T, ql);
+    IGE_REQUIRE(!op->F.varq || P.store_coupling != 1, "stored coupling blocks need one interpolation degree on all levels");
     // row chunks per near-field block (tuning knob IGE_NEAR_CHUNKS, default 2)
     int nch = 2;
     if (const char *e = std::getenv("IGE_NEAR_CHUNKS")) nch = std::max(1, std::min(64, std::atoi(e)));
@@ -293,7 +298,7 @@ size_t ige::planned_device_bytes(const ige_op_s *op, int restart, int r, const i
     const ige::Discretisation &D = op->D;
     const int64_t E = (int64_t)D.P * D.n * D.n;
     const int p = D.p, nl = D.scalar ? (p + 1) * (p + 1) : 2 * p * (p + 1), g = op->prm.gauss_near, G2 = g * g;
-    const int Q = (op->prm.q + 1) * (op->prm.q + 1);
+    const int Q = op->F.Q1 * op->F.Q1;
     const int s = op->T.s, W = s + p, nF = D.scalar ? W * W : 2 * W * (W - 1);
     const int64_t nblk = nF > 0 ? op->nnz / ((int64_t)nF * nF) : 0;
     const size_t R = (size_t)std::max(1, r);
@@ -389,7 +394,9 @@ ige_op ige::assemble_on(ige_ctx ctx, const ige_geom_s *geom, const ige_params &p
             // factor of the value / divergence term: 1 (scalar), -kappa^-2 (EFIE)
             v.cdiv = D.scalar ? 1.0 : -1.0 / (P.kappa * P.kappa);
             v.L = T.L; v.s = T.s; v.SL = 1 << T.L;
-            v.q = P.q; v.Q1 = P.q + 1; v.Q = v.Q1 * v.Q1;
+            v.q = F.q; v.Q1 = F.Q1; v.Q = v.Q1 * v.Q1;
+            v.varq = F.varq ? 1 : 0;
+            for (int l = 0; l < ige::kMaxLev; ++l) v.ql[l] = l <= T.L ? F.ql[l] : F.q;
             v.g = P.gauss_near; v.G2 = v.g * v.g; v.gs = P.gauss_singular;
             v.kappa = P.kappa; v.h = 1.0 / D.n; v.scale_tol = 1e-9 * geom->G.scale;
             v.rowlen = F.rowlen;
@@ -515,6 +522,9 @@ ige_op ige::assemble_on(ige_ctx ctx, const ige_geom_s *geom, const ige_params &p
             op->d_Mq.upload(F.Mq, s);
             op->d_Mdp.upload(F.Mdp, s);
             v.xn = op->d_xn.p; v.T0 = op->d_T0.p; v.T1 = op->d_T1.p;
+            op->d_xnl.upload(F.xnl, s);
+            op->d_Rl.upload(F.R, s);
+            v.xnl = op->d_xnl.p; v.Rl = op->d_Rl.p;
             v.Mp = op->d_Mp.p; v.Mq = op->d_Mq.p; v.Mdp = op->d_Mdp.p;
             op->d_nodeX.alloc((size_t)op->NC * 3 * v.Q);
             op->d_nodeT.alloc((size_t)op->NC * 6 * v.Q);
@@ -745,7 +755,11 @@ int ige_op_info(ige_op op, ige_op_info_t *out)
         r.near_leaf_pairs = (int64_t)op->T.near.size();
         r.singular_pairs = op->nsing;
         r.leaf_level = op->T.L;
-        r.q = op->prm.q;
+        r.q = op->F.q;
+        for (int l = 0; l <= op->T.L && l < 11; ++l) {
+            r.q_level[l] = op->F.ql[l];
+            r.level_diam[l] = op->T.diam[l];
+        }
         size_t b = 0;
         b += op->d_hdr.bytes() + op->d_brk.bytes() + op->d_cp.bytes() + op->d_dof.bytes() + op->d_sgn.bytes();
         b += op->d_ext_p.bytes() + op->d_ext_q.bytes() + op->d_eX.bytes() + op->d_ePsi.bytes() + op->d_eC.bytes();
@@ -958,6 +972,10 @@ void run_graph(ige_op op, ApplyGraph *g, int r, int prec, const std::function<vo
     IGE_HIP(hipGraphLaunch(g->exec, s));
 }
 
+// degrees that differ between levels (or beyond 11) are implemented by the
+// single-vector FP64/FP32 kernels only
+bool single_vector_only(const ige_op_s *op) { return op->F.varq || op->F.q > 11; }
+
 // y = A x for r device columns ([r][N]) in the given precision; with g, the operator
 // body runs as a captured graph (not while profiling)
 void apply_dev(ige_op op, int r, const double2 *x, double2 *y, int prec, ApplyGraph *g = nullptr)
@@ -965,8 +983,9 @@ void apply_dev(ige_op op, int r, const double2 *x, double2 *y, int prec, ApplyGr
     const bool graph = g && !op->profiling && graphs_enabled();
     hipStream_t s = op->ctx->stream;
     const int64_t N = op->D.N;
-    // the scalar single layer runs column by column on the single-vector kernels
-    if ((r == 1 && prec <= IGE_F32) || op->view.scalar) {
+    // the scalar single layer and operators with a degree per level run column by
+    // column on the single-vector kernels
+    if ((r == 1 && prec <= IGE_F32) || op->view.scalar || single_vector_only(op)) {
         for (int c = 0; c < r; ++c) {
             const double2 *xc = x + (size_t)c * N;
             double2 *yc = y + (size_t)c * N;
@@ -1004,6 +1023,8 @@ int apply_impl(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind, int
         IGE_REQUIRE(ptr_kind == IGE_HOST || ptr_kind == IGE_DEVICE, "bad ptr_kind");
         IGE_REQUIRE(prec >= IGE_F64 && prec <= IGE_BF16X3_ALL, "bad coupling precision");
         IGE_REQUIRE(!op->view.scalar || prec == IGE_F64, "the scalar single layer applies in FP64 only");
+        IGE_REQUIRE(!single_vector_only(op) || prec <= IGE_F32,
+                    "an operator with a degree per level applies in FP64 or FP32 only");
         set_device(op->ctx);
         const int64_t N = op->D.N;
         hipStream_t s = op->ctx->stream;
@@ -1040,7 +1061,8 @@ int ige_op_autotune(ige_op op, int r, int prec, int *choice, int nchoice)
         IGE_REQUIRE(op && r >= 1 && (choice || nchoice == 0), "bad autotune arguments");
         IGE_REQUIRE(op->assembled, "operator was planned, not assembled");
         IGE_REQUIRE(prec >= IGE_F64 && prec <= IGE_BF16X3_ALL, "bad precision");
-        IGE_REQUIRE(!op->view.scalar, "autotuning covers the EFIE operator only");
+        IGE_REQUIRE(!op->view.scalar && !single_vector_only(op),
+                    "autotuning covers the EFIE operator with one interpolation degree only");
         set_device(op->ctx);
         const int64_t N = op->D.N;
         hipStream_t s = op->ctx->stream;
@@ -1419,6 +1441,8 @@ int ige_solve(ige_op op, int r, const ige_c64 *f, ige_c64 *x, int ptr_kind, cons
         IGE_REQUIRE(!opts->refine || (std::isfinite(opts->inner_tol) && opts->inner_tol > 0.0 && opts->inner_tol < 1.0),
                     "inner_tol must be in (0, 1)");
         IGE_REQUIRE(!op->view.scalar || !opts->refine, "the scalar single layer solves in FP64 only (no refinement)");
+        IGE_REQUIRE(!single_vector_only(op) || !opts->refine || opts->inner_prec <= IGE_F32,
+                    "an operator with a degree per level refines with FP32 inner solves only");
         set_device(op->ctx);
         const auto t0 = std::chrono::steady_clock::now();
         const int64_t N = op->D.N;

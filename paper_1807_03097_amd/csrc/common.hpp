@@ -15,6 +15,7 @@ constexpr int kMaxGeomDeg = 8;   // NURBS degree of the input patches
 constexpr int kMaxP = 4;         // discretisation degree p
 constexpr int kMaxNl = 2 * kMaxP * (kMaxP + 1);   // local glued functions per element
 constexpr int kMaxQ1 = 16;       // q + 1
+constexpr int kMaxLev = 11;      // cluster-tree levels 0..10
 constexpr int kMaxG = 8;         // regular Gauss points per direction
 constexpr int kMaxGs = 12;       // singular sub-rule points per variable
 

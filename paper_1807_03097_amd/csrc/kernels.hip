@@ -427,10 +427,14 @@ __global__ void k_node_geometry(DevOp o, int NC, double *nodeX, double *nodeT)
     const int id = gc - (int)o.lvl_off[lvl];
     const int S = 1 << lvl;
     const int j = id / (S * S), r = id % (S * S), k2 = r / S, k1 = r % S;
-    const int m1 = mm % o.Q1, m2 = mm / o.Q1;
+    // the nodes of the level's degree (stored with the stride of the largest degree)
+    const int Q1l = o.ql[lvl] + 1;
+    if (mm >= Q1l * Q1l) return;
+    const int m1 = mm % Q1l, m2 = mm / Q1l;
+    const double *xn = o.xnl + (size_t)lvl * kMaxQ1;
     const double H = 1.0 / S;
     double X[3], Fu[3], Fv[3];
-    bezier_eval(o.geo, j, (k1 + o.xn[m1]) * H, (k2 + o.xn[m2]) * H, X, Fu, Fv);
+    bezier_eval(o.geo, j, (k1 + xn[m1]) * H, (k2 + xn[m2]) * H, X, Fu, Fv);
     for (int d = 0; d < 3; ++d) {
         nodeX[((size_t)gc * 3 + d) * o.Q + mm] = X[d];
         nodeT[((size_t)gc * 6 + d) * o.Q + mm] = Fu[d];
@@ -1048,6 +1052,74 @@ __global__ __launch_bounds__(256) void k_m2m(DevOp o, int lvl, double2 *mom, dou
     }
 }
 
+// Levels of a smaller interpolation degree q_l (variable order): their moments are the
+// exact restriction of the degree-q moments, m_l = (R_l (x) R_l)^T m with
+// R_l[n][m] = L^{q_l}_m(x^q_n), turned into the source fields at the level's own nodes;
+// the coupling's local expansions go back through R_l (x) R_l before L2L.
+__global__ __launch_bounds__(256) void k_restrict(DevOp o, int lvl, const double2 *mom, double2 *src)
+{
+    extern __shared__ double2 sm2[];
+    const int gc = (int)o.lvl_off[lvl] + blockIdx.x;
+    const int Q1h = o.Q1, Qs = o.Q, Q1l = o.ql[lvl] + 1, Ql = Q1l * Q1l;
+    const double *R = o.Rl + (size_t)lvl * Q1h * Q1h;   // [n][m], m < Q1l
+    double2 *M = sm2;               // [3][Qs]
+    double2 *Z = M + 3 * Qs;        // [3][Q1h (n2)][Q1l (m1)]
+    for (int i = threadIdx.x; i < 3 * Qs; i += blockDim.x) M[i] = mom[(size_t)gc * 3 * Qs + i];
+    __syncthreads();
+    for (int i = threadIdx.x; i < 3 * Q1h * Q1l; i += blockDim.x) {
+        const int f = i / (Q1h * Q1l), r = i % (Q1h * Q1l), n2 = r / Q1l, m1 = r % Q1l;
+        double2 z = make_double2(0, 0);
+        for (int n1 = 0; n1 < Q1h; ++n1) z = cadd(z, cscale(R[n1 * Q1h + m1], M[f * Qs + n2 * Q1h + n1]));
+        Z[i] = z;
+    }
+    __syncthreads();
+    const double *T = o.nodeT + (size_t)gc * 6 * Qs;
+    double2 *Sv = src + (size_t)gc * 4 * Qs;
+    for (int mm = threadIdx.x; mm < Ql; mm += blockDim.x) {
+        const int m2 = mm / Q1l, m1 = mm % Q1l;
+        double2 sf[3];
+        for (int f = 0; f < 3; ++f) {
+            double2 v = make_double2(0, 0);
+            for (int n2 = 0; n2 < Q1h; ++n2) v = cadd(v, cscale(R[n2 * Q1h + m2], Z[(f * Q1h + n2) * Q1l + m1]));
+            sf[f] = v;
+        }
+        const double Fu[3] = {T[mm], T[Qs + mm], T[2 * Qs + mm]}, Fv[3] = {T[3 * Qs + mm], T[4 * Qs + mm], T[5 * Qs + mm]};
+        if (o.scalar) {
+            for (int k = 0; k < 3; ++k) Sv[k * Qs + mm] = make_double2(0, 0);
+            Sv[3 * Qs + mm] = cscale(surf_elem(Fu, Fv), sf[2]);
+        } else {
+            for (int k = 0; k < 3; ++k) Sv[k * Qs + mm] = cadd(cscale(Fu[k], sf[0]), cscale(Fv[k], sf[1]));
+            Sv[3 * Qs + mm] = sf[2];
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_lift(DevOp o, int lvl, double2 *loc)
+{
+    extern __shared__ double2 sm2[];
+    const int gc = (int)o.lvl_off[lvl] + blockIdx.x;
+    const int Q1h = o.Q1, Qs = o.Q, Q1l = o.ql[lvl] + 1, Ql = Q1l * Q1l;
+    const double *R = o.Rl + (size_t)lvl * Q1h * Q1h;
+    double2 *A = sm2;               // [3][Ql]
+    double2 *Y = A + 3 * Ql;        // [3][Q1l (m2)][Q1h (n1)]
+    double2 *Lc = loc + (size_t)gc * 3 * Qs;
+    for (int i = threadIdx.x; i < 3 * Ql; i += blockDim.x) A[i] = Lc[(i / Ql) * Qs + i % Ql];
+    __syncthreads();
+    for (int i = threadIdx.x; i < 3 * Q1l * Q1h; i += blockDim.x) {
+        const int f = i / (Q1l * Q1h), r = i % (Q1l * Q1h), m2 = r / Q1h, n1 = r % Q1h;
+        double2 y = make_double2(0, 0);
+        for (int m1 = 0; m1 < Q1l; ++m1) y = cadd(y, cscale(R[n1 * Q1h + m1], A[f * Ql + m2 * Q1l + m1]));
+        Y[i] = y;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 3 * Qs; i += blockDim.x) {
+        const int f = i / Qs, nn = i % Qs, n2 = nn / Q1h, n1 = nn % Q1h;
+        double2 v = make_double2(0, 0);
+        for (int m2 = 0; m2 < Q1l; ++m2) v = cadd(v, cscale(R[n2 * Q1h + m2], Y[(f * Q1l + m2) * Q1h + n1]));
+        Lc[i] = v;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // a5: M2L. Work item = (target cluster, range of far partners).  The localized
 // kernel is interpolated in both parameter squares:
@@ -1066,7 +1138,12 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l(DevOp o, const M2LWork *wor
     using C = typename dm::cplx_of<T>::type;
     extern __shared__ double smd[];
     const M2LWork wk = work[blockIdx.x];
-    const int Q = o.Q;
+    // nodes of the target's level (the partners are on the same level); per-cluster
+    // arrays keep the stride Qs of the largest degree
+    const int Qs = o.Q;
+    int lvw = 0;
+    while (lvw < o.L && wk.tgt >= o.lvl_off[lvw + 1]) ++lvw;
+    const int Q = (o.ql[lvw] + 1) * (o.ql[lvw] + 1);
     const int TPG = (Q + kM2LNT - 1) / kM2LNT;
     const int S = min(kM2LThreads / TPG, Q);
     const int SP = (Q + S - 1) / S;
@@ -1083,15 +1160,15 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l(DevOp o, const M2LWork *wor
     T xt[kM2LNT][3];
     bool val[kM2LNT];
     C acc[kM2LNT][4];
-    const double *Xt = o.nodeX + (size_t)wk.tgt * 3 * Q;
+    const double *Xt = o.nodeX + (size_t)wk.tgt * 3 * Qs;
 #pragma unroll
     for (int k = 0; k < kM2LNT; ++k) {
         const int mm = mt + k * TPG;
         val[k] = active && mm < Q;
         const int mc = val[k] ? mm : 0;
         xt[k][0] = (T)Xt[mc];
-        xt[k][1] = (T)Xt[Q + mc];
-        xt[k][2] = (T)Xt[2 * Q + mc];
+        xt[k][1] = (T)Xt[Qs + mc];
+        xt[k][2] = (T)Xt[2 * Qs + mc];
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[k][j] = C{0, 0};
     }
@@ -1099,10 +1176,10 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l(DevOp o, const M2LWork *wor
     for (int kp = wk.beg; kp < wk.end; ++kp) {
         const int sc = partner[kp];
         __syncthreads();
-        const double *Xs = o.nodeX + (size_t)sc * 3 * Q;
-        const double2 *Vs = src + (size_t)sc * 4 * Q;
-        for (int i = tid; i < 3 * Q; i += kM2LThreads) sX[i] = (T)Xs[i];
-        for (int i = tid; i < 4 * Q; i += kM2LThreads) sV[i] = dm::to_c(Vs[i], T(0));
+        const double *Xs = o.nodeX + (size_t)sc * 3 * Qs;
+        const double2 *Vs = src + (size_t)sc * 4 * Qs;
+        for (int i = tid; i < 3 * Q; i += kM2LThreads) sX[i] = (T)Xs[(i / Q) * Qs + i % Q];
+        for (int i = tid; i < 4 * Q; i += kM2LThreads) sV[i] = dm::to_c(Vs[(i / Q) * Qs + i % Q], T(0));
         __syncthreads();
         if (active) {
             for (int ms = mb; ms < me; ++ms) {
@@ -1135,7 +1212,7 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l(DevOp o, const M2LWork *wor
         const int j = i / Q, mm = i % Q;
         double2 v = make_double2(0, 0);
         for (int q2 = 0; q2 < S; ++q2) v = cadd(v, red[((size_t)q2 * Q + mm) * 4 + j]);
-        part[(size_t)blockIdx.x * 4 * Q + i] = v;
+        part[((size_t)blockIdx.x * 4 + j) * Qs + mm] = v;
     }
 }
 
@@ -1143,30 +1220,33 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l(DevOp o, const M2LWork *wor
 // test-side fields t^a = d_aF . u_xyz, t^d = -kappa^-2 u_d
 __global__ void k_m2l_reduce(DevOp o, const int32_t *wrk_of_tgt, const double2 *part, double2 *loc)
 {
-    const int gc = blockIdx.x, Q = o.Q;
+    const int gc = blockIdx.x, Qs = o.Q;
+    int lvl = 0;
+    while (lvl < o.L && gc >= o.lvl_off[lvl + 1]) ++lvl;
+    const int Q = (o.ql[lvl] + 1) * (o.ql[lvl] + 1);   // nodes of the level (stride Qs)
     const int b = wrk_of_tgt[gc], e = wrk_of_tgt[gc + 1];
     const double ik2 = 1.0 / (o.kappa * o.kappa);
     for (int mm = threadIdx.x; mm < Q; mm += blockDim.x) {
         double2 u[4] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
         for (int w = b; w < e; ++w)
-            for (int k = 0; k < 4; ++k) u[k] = cadd(u[k], part[((size_t)w * 4 + k) * Q + mm]);
-        const double *T = o.nodeT + (size_t)gc * 6 * Q;
+            for (int k = 0; k < 4; ++k) u[k] = cadd(u[k], part[((size_t)w * 4 + k) * Qs + mm]);
+        const double *T = o.nodeT + (size_t)gc * 6 * Qs;
         double2 t1 = make_double2(0, 0), t2 = make_double2(0, 0);
         for (int k = 0; k < 3; ++k) {
-            t1 = cadd(t1, cscale(T[k * Q + mm], u[k]));
-            t2 = cadd(t2, cscale(T[(3 + k) * Q + mm], u[k]));
+            t1 = cadd(t1, cscale(T[k * Qs + mm], u[k]));
+            t2 = cadd(t2, cscale(T[(3 + k) * Qs + mm], u[k]));
         }
-        double2 *L = loc + (size_t)gc * 3 * Q;
+        double2 *L = loc + (size_t)gc * 3 * Qs;
         if (o.scalar) {   // scalar: t = |J(x_m)| u (the localized kernel's target surface element)
-            const double Fu[3] = {T[mm], T[Q + mm], T[2 * Q + mm]}, Fv[3] = {T[3 * Q + mm], T[4 * Q + mm], T[5 * Q + mm]};
+            const double Fu[3] = {T[mm], T[Qs + mm], T[2 * Qs + mm]}, Fv[3] = {T[3 * Qs + mm], T[4 * Qs + mm], T[5 * Qs + mm]};
             L[mm] = make_double2(0, 0);
-            L[Q + mm] = make_double2(0, 0);
-            L[2 * Q + mm] = cscale(surf_elem(Fu, Fv), u[3]);
+            L[Qs + mm] = make_double2(0, 0);
+            L[2 * Qs + mm] = cscale(surf_elem(Fu, Fv), u[3]);
             continue;
         }
         L[mm] = t1;
-        L[Q + mm] = t2;
-        L[2 * Q + mm] = cscale(-ik2, u[3]);
+        L[Qs + mm] = t2;
+        L[2 * Qs + mm] = cscale(-ik2, u[3]);
     }
 }
 
@@ -1695,11 +1775,36 @@ void launch_m2m(ige_op op)
 {
     const DevOp &o = op->view;
     const size_t shm = sizeof(double2) * 24 * o.Q;
+    lds_attr_once(reinterpret_cast<const void *>(&k_m2m), shm);
     for (int lvl = o.L - 1; lvl >= 0; --lvl) {
         const int ncl = o.P << (2 * lvl);
         hipLaunchKernelGGL(k_m2m, dim3(ncl), dim3(256), shm, lstream(op), o, lvl, op->d_mom.p, op->d_src.p);
         IGE_LAUNCH_CHECK();
     }
+    if (!o.varq) return;
+    // levels of a smaller degree: source fields from the restricted moments
+    for (int lvl = 0; lvl <= o.L; ++lvl) {
+        const int Q1l = o.ql[lvl] + 1;
+        if (Q1l == o.Q1) continue;
+        const size_t sh = sizeof(double2) * (3 * (size_t)o.Q + 3 * (size_t)o.Q1 * Q1l);
+        hipLaunchKernelGGL(k_restrict, dim3(o.P << (2 * lvl)), dim3(256), sh, lstream(op), o, lvl, op->d_mom.p,
+                           op->d_src.p);
+        IGE_LAUNCH_CHECK();
+    }
+}
+
+// dynamic shared memory above the 64 KB granted without asking (degrees 12..15 of the
+// transfer kernels): the kernel's limit is raised once, before any graph capture
+void lds_attr_once(const void *kern, size_t shm)
+{
+    if (shm <= (size_t)64 * 1024) return;
+    static std::mutex mu;
+    static std::map<const void *, size_t> done;
+    std::lock_guard<std::mutex> lk(mu);
+    size_t &have = done[kern];
+    if (have >= shm) return;
+    IGE_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    have = shm;
 }
 
 size_t m2l_shared_bytes(int Q)
@@ -1718,12 +1823,17 @@ void launch_m2l(ige_op op, int prec)
         m2l_stored_one(op, prec);
         return;
     }
-    if (prec == IGE_F32)
-        hipLaunchKernelGGL(k_m2l<float>, dim3(op->work.size()), dim3(kM2LThreads), m2l_shared_bytes(o.Q),
-                           lstream(op), o, op->d_work.p, op->d_partner.p, op->d_src.p, op->d_part.p);
-    else
-        hipLaunchKernelGGL(k_m2l<double>, dim3(op->work.size()), dim3(kM2LThreads), m2l_shared_bytes(o.Q),
-                           lstream(op), o, op->d_work.p, op->d_partner.p, op->d_src.p, op->d_part.p);
+    size_t shm = m2l_shared_bytes(o.Q);   // the largest over the levels' node counts
+    for (int lvl = 0; lvl <= o.L; ++lvl) shm = std::max(shm, m2l_shared_bytes((o.ql[lvl] + 1) * (o.ql[lvl] + 1)));
+    if (prec == IGE_F32) {
+        lds_attr_once(reinterpret_cast<const void *>(&k_m2l<float>), shm);
+        hipLaunchKernelGGL(k_m2l<float>, dim3(op->work.size()), dim3(kM2LThreads), shm, lstream(op), o,
+                           op->d_work.p, op->d_partner.p, op->d_src.p, op->d_part.p);
+    } else {
+        lds_attr_once(reinterpret_cast<const void *>(&k_m2l<double>), shm);
+        hipLaunchKernelGGL(k_m2l<double>, dim3(op->work.size()), dim3(kM2LThreads), shm, lstream(op), o,
+                           op->d_work.p, op->d_partner.p, op->d_src.p, op->d_part.p);
+    }
     IGE_LAUNCH_CHECK();
 }
 
@@ -1737,6 +1847,15 @@ void launch_m2l_reduce(ige_op op)
     hipLaunchKernelGGL(k_m2l_reduce, dim3(op->NC), dim3(128), 0, lstream(op), o, op->d_wrk_of_tgt.p,
                        op->d_part.p, op->d_loc.p);
     IGE_LAUNCH_CHECK();
+    if (!o.varq) return;
+    // levels of a smaller degree: local expansions back to the degree-q nodes
+    for (int lvl = 0; lvl <= o.L; ++lvl) {
+        const int Q1l = o.ql[lvl] + 1;
+        if (Q1l == o.Q1) continue;
+        const size_t sh = sizeof(double2) * (3 * (size_t)Q1l * Q1l + 3 * (size_t)Q1l * o.Q1);
+        hipLaunchKernelGGL(k_lift, dim3(o.P << (2 * lvl)), dim3(256), sh, lstream(op), o, lvl, op->d_loc.p);
+        IGE_LAUNCH_CHECK();
+    }
 }
 
 void launch_l2l(ige_op op)

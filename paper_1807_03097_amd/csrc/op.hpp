@@ -68,7 +68,12 @@ struct DevOp {
     const double *nodeX;      // [NC][3][Q]
     const double *nodeT;      // [NC][6][Q]  d_uF (3), d_vF (3)
     const double2 *sctab;     // [256] (cos, sin)(j pi/128), for the table-driven kernel evaluation
-    const double *xn;         // [Q1] Chebyshev nodes
+    const double *xn;         // [Q1] Chebyshev nodes of degree q (the largest level degree)
+    // degree per level (variable order): varq = 1 when some level's degree ql[l] < q;
+    // its nodes xnl [L+1][kMaxQ1] and the restriction Rl [L+1][Q1][Q1] from degree q
+    int varq;
+    int ql[kMaxLev];
+    const double *xnl, *Rl;
     const double *T0, *T1;    // [Q1][Q1]
     const double *Mp, *Mq, *Mdp;   // [SL][Q1][rowlen]
     int rowlen;
@@ -151,7 +156,7 @@ struct ige_op_s {
     ige::DBuf<int4> d_cwork;
     ige::DBuf<double2> d_cval, d_cpart;
     ige::DBuf<int64_t> d_lvl_off;
-    ige::DBuf<double> d_nodeX, d_nodeT, d_xn, d_T0, d_T1, d_Mp, d_Mq, d_Mdp;
+    ige::DBuf<double> d_nodeX, d_nodeT, d_xn, d_T0, d_T1, d_Mp, d_Mq, d_Mdp, d_xnl, d_Rl;
     ige::DBuf<double2> d_sctab;
     ige::DBuf<int32_t> d_inc;
     ige::DBuf<ige::SingularPair> d_sing;
@@ -311,6 +316,8 @@ void launch_potential(ige_op op, const double2 *w, int npts, const double *pts, 
 void potential_scratch_init(int device);
 double *potential_scratch(int device);
 size_t potential_scratch_doubles();
+// raise a kernel's dynamic shared-memory limit above 64 KB once per process
+void lds_attr_once(const void *kern, size_t shm);
 // scalar single layer right-hand side (kind 0 plane wave of direction a, 1 point source at a)
 void launch_rhs_scalar(ige_op op, int kind, const double *a, double2 *f);
 void launch_rhs_plane(ige_op op, const double *dir, double2 pol0, double2 pol1, double2 pol2, double2 *f);

@@ -484,8 +484,10 @@ void build_partition(Partition &T, const Geometry &G, const Discretisation &D, d
     std::vector<std::pair<int32_t, int32_t>> cand;
     for (int a = 0; a < G.P; ++a)
         for (int b = 0; b < G.P; ++b) cand.push_back({a, b});
+    T.diam.assign((size_t)T.L + 1, 0.0);
     for (int l = 0; l <= T.L; ++l) {
         const Balls B = level_balls(G, n, l, V);
+        for (double r : B.r) T.diam[l] = std::max(T.diam[l], 2.0 * r);
         const int s = 1 << l;
         std::vector<std::pair<int32_t, int32_t>> next;
         for (auto &pr : cand) {
@@ -864,16 +866,35 @@ void build_singular_pairs(std::vector<SingularPair> &S, std::vector<double> &cor
 // ---------------------------------------------------------------------------
 // far-field tables: 1-D cluster moments of the splines and transfer matrices
 // ---------------------------------------------------------------------------
-void build_far_tables(FarTables &F, const Discretisation &D, const Partition &T, int q)
+void build_far_tables(FarTables &F, const Discretisation &D, const Partition &T, const std::vector<int> &ql)
 {
-    IGE_REQUIRE(q >= 1 && q + 1 <= kMaxQ1, "q must be 1..15");
+    IGE_REQUIRE((int)ql.size() == T.L + 1, "one interpolation degree per level");
+    int q = 0;
+    for (int v : ql) {
+        IGE_REQUIRE(v >= 1 && v + 1 <= kMaxQ1, "interpolation degrees must be 1..15");
+        q = std::max(q, v);
+    }
     const int p = D.p, n = D.n, s = T.s, S = 1 << T.L;
     const double h = 1.0 / n, H = 1.0 / S;
     F.q = q;
     F.Q1 = q + 1;
     F.rowlen = s + p;
+    F.ql = ql;
+    F.varq = false;
+    for (int v : ql) F.varq = F.varq || v != q;
     F.xn.resize(q + 1);
     chebyshev01(q, F.xn.data());
+    // per level: its nodes, and the restriction from the degree-q nodes
+    F.xnl.assign((size_t)(T.L + 1) * kMaxQ1, 0.0);
+    F.R.assign((size_t)(T.L + 1) * F.Q1 * F.Q1, 0.0);
+    for (int l = 0; l <= T.L; ++l) {
+        chebyshev01(ql[l], &F.xnl[(size_t)l * kMaxQ1]);
+        for (int nn = 0; nn <= q; ++nn) {
+            double Lm[kMaxQ1];
+            lagrange_bary(ql[l], &F.xnl[(size_t)l * kMaxQ1], F.xn[nn], Lm);
+            for (int mm = 0; mm <= ql[l]; ++mm) F.R[((size_t)l * F.Q1 + nn) * F.Q1 + mm] = Lm[mm];
+        }
+    }
     const int ng = (q + p) / 2 + 1;    // exact for the degree q + p moment integrands
     std::vector<double> gx(ng), gw(ng);
     gauss_legendre01(ng, gx.data(), gw.data());

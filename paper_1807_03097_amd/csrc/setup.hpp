@@ -53,6 +53,7 @@ struct Partition {
     int s = 1;                    // elements per leaf cluster side
     std::vector<std::array<int32_t, 3>> far;    // (level, target, source), sorted
     std::vector<std::array<int32_t, 2>> near;   // (target leaf, source leaf), sorted
+    std::vector<double> diam;                   // [L+1] largest bounding-ball diameter per level
 };
 
 // Algorithm 1 from all ordered patch pairs with the admissibility condition
@@ -139,12 +140,21 @@ void build_singular_pairs(std::vector<SingularPair> &S, std::vector<double> &cor
                           const Discretisation &D, const Partition &T, const NearBlocks &B);
 
 // 1-D moment tables of the leaf clusters and transfer matrices
+// q: the largest degree of the levels; the upward and downward passes (moments of
+// the leaves, M2M, L2L, L2P) run in it on every level.  A level l of smaller degree
+// q_l takes its moments by the exact restriction R_l[n][m] = L^{q_l}_m(x^q_n) of the
+// degree-q moments (a degree-q_l Lagrange polynomial is reproduced by degree-q
+// interpolation) and gives its local expansions back through R_l^T.
 struct FarTables {
     int q, Q1, rowlen;            // rowlen = s + p
+    bool varq = false;            // some level's degree differs from q
+    std::vector<int> ql;               // [L+1] degree of each level
     std::vector<double> Mp, Mq, Mdp;   // [2^L][Q1][rowlen]
     std::vector<double> T0, T1;        // [Q1][Q1]: T_c[n][m] = L_m((x_n + c)/2)
     std::vector<double> xn;            // nodes
+    std::vector<double> xnl;           // [L+1][kMaxQ1] nodes of each level's degree
+    std::vector<double> R;             // [L+1][Q1][Q1] restriction (columns m <= q_l used)
 };
-void build_far_tables(FarTables &F, const Discretisation &D, const Partition &T, int q);
+void build_far_tables(FarTables &F, const Discretisation &D, const Partition &T, const std::vector<int> &ql);
 
 }  // namespace ige

@@ -742,3 +742,110 @@ def test_high_kappa_rows_match_dense_with_kappa_cap(oracle_mod, ctx, name):
     _say(f"  {name}: N={op.N} far={op.info.far_pairs} vs oracle FMM {err:.1e}, vs dense {errd:.1e}")
     assert err <= TOL and errd <= 1e-6
     op.close()
+
+
+LQ_CASES = [
+    # geometry, p, m, kappa, eta, leaf depth, degree per level, scalar
+    ("sphere", 2, 4, 8.0, 1.0, 1, [8, 10, 9, 6], False),    # larger and smaller than the leaf degree
+    ("torus", 1, 3, 4.0, 1.0, 1, [4, 13, 5], False),       # degree 13: transfer kernels above 64 KB of LDS
+    ("jittered", 3, 3, 6.0, 1.0, 1, [6, 7, 9], False),
+    ("sphere", 2, 3, 8.0, 1.0, 1, [6, 9, 7], True),         # scalar single layer
+]
+
+
+@pytest.mark.parametrize("case", LQ_CASES, ids=[f"{c[0]}-p{c[1]}-m{c[2]}-q{'.'.join(map(str, c[6]))}"
+                                                + ("-scalar" if c[7] else "") for c in LQ_CASES])
+def test_level_degrees_match_oracle(oracle_mod, ctx, case):
+    """A degree per cluster-tree level: the restriction of the largest degree's moments
+    to each level's nodes and the lift of its local expansions give the oracle's
+    operator (moments taken directly per level) to 1e-12; several columns are applied
+    column by column (bitwise the single-column result) and FP32 stays within 1e-5."""
+    from paper_1807_03097_amd import binding as B
+    name, p, m, kappa, eta, d, ql, scalar = case
+    _say(f"case {case}")
+    pats = _geom(name)
+    geom = B.Geometry(ctx, pats)
+    kind = B.IGE_OP_SCALAR if scalar else B.IGE_OP_EFIE
+    op = B.Operator(geom, p, m, kappa, 8, eta, 5, 5, d, kind=kind, q_level=ql)
+    assert op.q_levels() == ql
+    o = oracle_mod.Oracle(pats, p, m, kappa, g=5, gs=5, scalar=scalar)
+    x = W.random_coeffs(op.N, 0)
+    y = op.apply(x)
+    yo = o.fmm_apply(x, ql, eta, d)
+    err = _rel(y, yo)
+    nfar = np.bincount(op.partition()["far"][:, 0], minlength=len(ql)).tolist()
+    _say(f"  N={op.N} far per level {nfar} err={err:.2e}")
+    assert err <= TOL
+    X = np.stack([x, W.random_coeffs(op.N, 1), W.random_coeffs(op.N, 2)])
+    Y = op.apply(X)
+    assert np.array_equal(Y[0], y) and _rel(Y[2], o.fmm_apply(X[2], ql, eta, d)) <= TOL
+    if not scalar:
+        e32 = _rel(op.apply(x, prec=B.IGE_F32), yo)
+        assert 1e-12 < e32 <= 1e-5
+    op.close()
+
+
+def test_level_degrees_refusals_and_refined_solve(oracle_mod, ctx):
+    """Operators with a degree per level refuse the matrix-core precisions, stored
+    coupling blocks and autotuning; FP64 refinement around FP32 inner solves reaches
+    the tolerance on the FP64 operator."""
+    from paper_1807_03097_amd import binding as B
+    pats = W.cube_sphere()
+    geom = B.Geometry(ctx, pats)
+    ql = [8, 10, 9, 6]
+    with pytest.raises(B.IgeError):
+        B.Operator(geom, 2, 4, 8.0, 8, 1.0, 5, 5, 1, store_coupling=1, q_level=ql)
+    with pytest.raises(B.IgeError):
+        B.Operator(geom, 2, 4, 8.0, 8, 1.0, 5, 5, 1, q_level=[8, 16])
+    op = B.Operator(geom, 2, 4, 8.0, 8, 1.0, 5, 5, 1, q_level=ql)
+    x = W.random_coeffs(op.N, 0)
+    for prec in (B.IGE_BF16, B.IGE_BF16X3, B.IGE_BF16X3_ALL):
+        with pytest.raises(B.IgeError):
+            op.apply(x, prec=prec)
+    with pytest.raises(B.IgeError):
+        op.autotune(2)
+    f = op.rhs_plane_wave([[0.0, 0.0, 1.0]], [[1.0, 0.0, 0.0]])[0]
+    with pytest.raises(B.IgeError):
+        op.solve(f, refine=True, inner_prec=B.IGE_BF16X3)
+    xs, st, rc = op.solve(f, tol=1e-8, restart=300, maxit=3000)
+    xr, sr, rcr = op.solve(f, tol=1e-8, restart=300, maxit=3000, refine=True, inner_prec=B.IGE_F32)
+    _say(f"  FP64 iters {st[0][0]} relres {st[0][2]:.1e}; refined iters {sr[0][0]} relres {sr[0][2]:.1e}")
+    assert rc == 0 and rcr == 0 and sr[0][2] <= 1e-8 * 1.05
+    # the refined solution's true residual on the FP64 operator; the two solutions differ
+    # by at most about tol * cond(A)
+    assert _rel(op.apply(xr), f) <= 1.05e-8
+    assert _rel(xr, xs) <= 1e-4
+    op.close()
+
+
+@pytest.mark.parametrize("name", ["c3", "c5"])
+def test_high_kappa_rows_match_dense_with_level_degrees(oracle_mod, ctx, name):
+    """Level 6, kappa = 16 on the paper's partition and the jittered level-7 sphere at
+    kappa = 40 with kappa_cap = 20, both with degrees from the kappa * diam rule of the
+    binding (degree_rule, levels with far blocks only): the HIP FMM equals the oracle's
+    FMM with the same degrees to 1e-12 and the dense Galerkin rows of tests/golden to
+    1e-6."""
+    import json
+    import os
+    from paper_1807_03097_amd import binding as B
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", f"{name}_dense_rows.json")))
+    rows = np.array(g["rows"])
+    yd = np.array(g["re"]) + 1j * np.array(g["im"])
+    cf = g["config"]
+    q, cap = (8, 0.0) if name == "c3" else (10, 20.0)
+    pats = W.cube_sphere() if name == "c3" else W.jitter(W.cube_sphere(), 0.02, 7)
+    geom = B.Geometry(ctx, pats)
+    plan = B.Operator(geom, 2, cf["level"], cf["kappa"], q, 1.6, 5, 5, 3, kappa_cap=cap, plan_only=True)
+    far_levels = set(plan.partition()["far"][:, 0].tolist())
+    ql = B.degree_rule(plan.info, cf["kappa"], q, far_levels)
+    plan.close()
+    op = B.Operator(geom, 2, cf["level"], cf["kappa"], q, 1.6, 5, 5, 3, kappa_cap=cap, q_level=ql)
+    assert op.N == cf["n_dof"]
+    x = W.random_coeffs(op.N, 0)
+    y = op.apply(x)
+    o = oracle_mod.Oracle(pats, 2, cf["level"], cf["kappa"], g=5, gs=5)
+    yo = o.fmm_apply(x, ql, 1.6, 3, rows=rows, tree=o.block_tree(1.6, 3, kappa_cap=cap))
+    err, errd = _rel(y[rows], yo), _rel(y[rows], yd)
+    _say(f"  {name}: degrees {ql} far={op.info.far_pairs} vs oracle FMM {err:.1e}, vs dense {errd:.1e}")
+    assert err <= TOL and errd <= 1e-6
+    op.close()

@@ -173,3 +173,29 @@ def test_scalar_plan_matches_oracle(oracle_mod, p, m, eta, d):
     assert op.info.near_distinct == len(keys)
     with pytest.raises(B.IgeError):
         B.Operator(g, p, m, 4.0, 6, eta, leaf_depth=d, plan_only=True, kind=2)
+
+
+def test_level_degrees_plan_and_diameters_match_oracle(oracle_mod):
+    """q_level: the partition does not depend on the degrees, the info reports each
+    level's degree and the largest bounding-ball diameter of its clusters (the
+    oracle's balls, to rounding), the binding's degree rule gives the oracle-pinned
+    degrees at level 6 / kappa 16, and out-of-range degrees are refused."""
+    from paper_1807_03097_amd import binding as B
+    pats = W.cube_sphere()
+    ctx = B.Context(-1)
+    g = B.Geometry(ctx, pats)
+    op0 = B.Operator(g, 2, 4, 8.0, 8, 1.0, leaf_depth=1, plan_only=True)
+    op = B.Operator(g, 2, 4, 8.0, 8, 1.0, leaf_depth=1, plan_only=True, q_level=[8, 10, 0, 6])
+    assert op.q_levels() == [8, 10, 8, 6] and op.info.q == 10 and op0.q_levels() == [8, 8, 8, 8]
+    p0, p1 = op0.partition(), op.partition()
+    assert np.array_equal(p0["far"], p1["far"]) and np.array_equal(p0["near"], p1["near"])
+    o = oracle_mod.Oracle(pats, 2, 4, 8.0, g=2)
+    for lvl, dm in enumerate(op.level_diameters()):
+        _, rad = o.bounding_balls(lvl)
+        assert abs(dm - 2 * rad.max()) <= 1e-12 * dm
+    c3 = B.Operator(g, 2, 6, 16.0, 8, 1.6, leaf_depth=3, plan_only=True)
+    far_levels = set(c3.partition()["far"][:, 0].tolist())
+    assert B.degree_rule(c3.info, 16.0, 8, far_levels) == [8, 14, 10, 8]
+    for bad in ([16], [-1], [0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 20]):
+        with pytest.raises(B.IgeError):
+            B.Operator(g, 2, 4, 8.0, 8, 1.0, leaf_depth=1, plan_only=True, q_level=bad)
