@@ -72,6 +72,11 @@ def parse():
                     help="time the candidate tile shapes of the apply first and keep the fastest (ige_op_autotune)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (calibrates HBM byte counters)")
+    ap.add_argument("--kappa-cap", type=float, default=0.0,
+                    help="matvec/solve: admissible blocks also need kappa * diam <= this (0: the paper's condition)")
+    ap.add_argument("--q-level", type=str, default="",
+                    help="matvec: interpolation degree per cluster-tree level, comma separated (0: --q); "
+                         "'rule' takes the kappa * diam rule of the binding on the levels with far blocks")
     ap.add_argument("--requests", type=int, default=32, help="serve: number of requests")
     ap.add_argument("--rate", type=float, default=20.0, help="serve: mean arrivals per second")
     ap.add_argument("--workers", type=int, default=4, help="serve: concurrent requests (one stream each)")
@@ -416,7 +421,7 @@ def main():
     from paper_1807_03097_amd import binding as B
     from paper_1807_03097_amd import workloads as W
 
-    p, m, kappa, q, eta, d = 2, args.level, args.kappa, 8, args.eta, args.leaf_depth
+    p, m, kappa, q, eta, d = 2, args.level, args.kappa, args.q, args.eta, args.leaf_depth
     pats = W.cube_sphere()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -429,10 +434,21 @@ def main():
         del src_buf, dst_buf
     ctx = B.Context(0, stream.cuda_stream)
     geom = B.Geometry(ctx, pats)
+    q_level = None
+    if args.q_level == "rule":
+        plan = B.Operator(geom, p, m, kappa, q, eta, 5, 5, d, kappa_cap=args.kappa_cap, plan_only=True)
+        q_level = B.degree_rule(plan.info, kappa, q, set(plan.partition()["far"][:, 0].tolist()))
+        plan.close()
+    elif args.q_level:
+        q_level = [int(v) for v in args.q_level.split(",")]
     t0 = time.perf_counter()
-    op = B.Operator(geom, p, m, kappa, q, eta, 5, 5, d, store_coupling=args.store_coupling)
+    op = B.Operator(geom, p, m, kappa, q, eta, 5, 5, d, store_coupling=args.store_coupling,
+                    kappa_cap=args.kappa_cap, q_level=q_level)
     t_asm = time.perf_counter() - t0
     info = op.info
+    far_per_level = np.bincount(op.partition()["far"][:, 0], minlength=info.leaf_level + 1).tolist() \
+        if info.far_pairs else [0] * (info.leaf_level + 1)
+    q_used = op.q_levels()
     N = op.N
     log(f"assembled N={N} nnz={info.near_nnz} far={info.far_pairs} near_leaf={info.near_leaf_pairs} "
         f"L={info.leaf_level} in {t_asm:.2f} s")
@@ -564,7 +580,7 @@ def main():
         # M2L: per interpolation-node pair the kernel G(|x - x'|) (distance 8,
         # sqrt/rcp/sin/cos 4, scaling 2 FP64 operations) and four complex
         # multiply-adds per right-hand side (32 operations each)
-        entries = info.far_pairs * Q * Q
+        entries = sum(nf * (ql + 1) ** 4 for nf, ql in zip(far_per_level, q_used))
         flops = entries * (14.0 + 32.0 * r)
         t_ms = stage_ms["m2l_kernel"]
         achieved = flops / (t_ms * 1e-3) / 1e12
@@ -630,8 +646,9 @@ def main():
         "config": {"workload": f"FMM matvec: 6-patch NURBS sphere, level {m}, p={p}, kappa={kappa}, q={q}, "
                                f"5x5 Gauss near field, x ~ N(0,1)+iN(0,1) seed 0",
                    "n_dof": N, "nrhs": r, "eta": eta, "leaf_depth": d, "near_nnz": int(info.near_nnz),
-                   "store_coupling": args.store_coupling,
-                   "far_pairs": int(info.far_pairs), "parallelism": "single GPU"},
+                   "store_coupling": args.store_coupling, "kappa_cap": args.kappa_cap, "q_level": q_used,
+                   "far_pairs": int(info.far_pairs), "far_pairs_per_level": far_per_level,
+                   "parallelism": "single GPU"},
         "timed_kernel_ms": st,
         "assemble_s": t_asm,
         "roofline": roof,
