@@ -279,6 +279,7 @@ void plan(ige_op op, const ige_geom_s *geom, ige::NearBlocks &A, std::vector<ige
     if (const char *e = std::getenv("IGE_NEAR_ROWS")) nrows = std::max(8, std::min(128, std::atoi(e)));
     ige::build_near_compact(op->cmp, op->D, op->T, A, nrows);
     if (const char *e = std::getenv("IGE_NEAR_RS")) op->cmp_rs = std::atoi(e) == 4 ? 4 : 2;
+    if (const char *e = std::getenv("IGE_NEAR_PRIO")) op->near_prio = std::max(0, std::min(3, std::atoi(e)));
     std::vector<double> corners;
     ige::build_singular_pairs(sing, corners, geom->G, op->D, op->T, A);
     op->nsing = (int64_t)sing.size();
@@ -594,6 +595,7 @@ ige_op ige::assemble_on(ige_ctx ctx, const ige_geom_s *geom, const ige_params &p
                 // single column with stored blocks: streamed (default) or evaluated
                 // per apply (IGE_M2L_ONE=generate)
                 op->m2l_generate_one = false;
+                if (const char *e = std::getenv("IGE_M2L_LDS_KB")) op->m2l_lds = (size_t)std::max(0, std::min(150, std::atoi(e))) * 1024;
                 if (const char *e = std::getenv("IGE_M2L_ONE")) op->m2l_generate_one = std::string(e) == "generate";
                 // many FP64 columns: stored blocks on the FP64 matrix cores (default) or
                 // evaluated per apply (IGE_M2L_F64=generate)

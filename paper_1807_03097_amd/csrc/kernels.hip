@@ -1825,6 +1825,7 @@ void launch_m2l(ige_op op, int prec)
     }
     size_t shm = m2l_shared_bytes(o.Q);   // the largest over the levels' node counts
     for (int lvl = 0; lvl <= o.L; ++lvl) shm = std::max(shm, m2l_shared_bytes((o.ql[lvl] + 1) * (o.ql[lvl] + 1)));
+    shm = std::max(shm, op->m2l_lds);
     if (prec == IGE_F32) {
         lds_attr_once(reinterpret_cast<const void *>(&k_m2l<float>), shm);
         hipLaunchKernelGGL(k_m2l<float>, dim3(op->work.size()), dim3(kM2LThreads), shm, lstream(op), o,

@@ -122,10 +122,16 @@ __device__ __forceinline__ void near_cmp_item(const NearCmpView &v, int w, const
 // Work items of at most 128 columns take two column groups of 64 per lane; the wider
 // ones U of them, in a second launch (obase: first item of the launch in the order).
 template <int U, int RS>
-__global__ __launch_bounds__(256) void k_near_cmp(NearCmpView v, int64_t obase, const double2 *x, double2 *part)
+__global__ __launch_bounds__(256) void k_near_cmp(NearCmpView v, int64_t obase, const double2 *x, double2 *part,
+                                                  int prio)
 {
     __shared__ double2 sxr[kCmpRows];
     __shared__ double2 syc[3][256];
+    // issue priority of these waves over others resident on the same SIMD (the
+    // coupling kernel runs beside this one)
+    if (prio == 1) __builtin_amdgcn_s_setprio(1);
+    else if (prio == 2) __builtin_amdgcn_s_setprio(2);
+    else if (prio == 3) __builtin_amdgcn_s_setprio(3);
     near_cmp_item<U, RS>(v, v.order[obase + blockIdx.x], x, part, sxr, syc);
 }
 
@@ -191,15 +197,17 @@ void launch_near_once(ige_op op, const double2 *x, double2 *part, hipStream_t st
     const NearCmpView &v = op->cview;
     const dim3 blk(256);
     const int64_t na = op->cmp.nnarrow, nw = v.nwork - na;
+    const int pr = op->near_prio;
     if (na > 0) {
-        if (op->cmp_rs == 4) hipLaunchKernelGGL((k_near_cmp<2, 4>), dim3((unsigned)na), blk, 0, st, v, (int64_t)0, x, part);
-        else hipLaunchKernelGGL((k_near_cmp<2, 2>), dim3((unsigned)na), blk, 0, st, v, (int64_t)0, x, part);
+        if (op->cmp_rs == 4)
+            hipLaunchKernelGGL((k_near_cmp<2, 4>), dim3((unsigned)na), blk, 0, st, v, (int64_t)0, x, part, pr);
+        else hipLaunchKernelGGL((k_near_cmp<2, 2>), dim3((unsigned)na), blk, 0, st, v, (int64_t)0, x, part, pr);
         IGE_HIP(hipGetLastError());
     }
     if (nw > 0) {
         const dim3 grid((unsigned)nw);
-        if ((op->cmp.maxn + 63) / 64 <= 3) hipLaunchKernelGGL((k_near_cmp<3, 2>), grid, blk, 0, st, v, na, x, part);
-        else hipLaunchKernelGGL((k_near_cmp<4, 2>), grid, blk, 0, st, v, na, x, part);
+        if ((op->cmp.maxn + 63) / 64 <= 3) hipLaunchKernelGGL((k_near_cmp<3, 2>), grid, blk, 0, st, v, na, x, part, pr);
+        else hipLaunchKernelGGL((k_near_cmp<4, 2>), grid, blk, 0, st, v, na, x, part, pr);
         IGE_HIP(hipGetLastError());
     }
 }

@@ -131,6 +131,13 @@ struct ige_op_s {
     // stored coupling blocks (one per unordered far pair)
     bool stored = false;
     bool m2l_generate_one = true;   // single column: evaluate the kernel per apply even when stored
+    // shared memory per workgroup of the generated single-column coupling (0: what it
+    // needs); more limits its workgroups per CU and leaves registers to the near field
+    size_t m2l_lds = 0;
+    // wave issue priority of the once-per-entry near-field product (0..3): 1 lets its
+    // loads issue ahead of the coupling kernel's arithmetic on shared SIMDs (C2 apply
+    // 0.208 against 0.218 ms on one device)
+    int near_prio = 1;
     int64_t nfp = 0;
 
     // device buffers
