@@ -207,8 +207,17 @@ def run_solve(args):
     if args.jitter > 0:
         pats = W.jitter(pats, args.jitter, args.jitter_seed)
     geom = B.Geometry(ctx, pats)
+    q_level = None
+    if args.q_level == "rule":
+        plan = B.Operator(geom, args.p, args.level, args.kappa, args.q, args.eta, 5, 5, args.leaf_depth,
+                          kappa_cap=args.kappa_cap, plan_only=True)
+        q_level = B.degree_rule(plan.info, args.kappa, args.q, set(plan.partition()["far"][:, 0].tolist()))
+        plan.close()
+    elif args.q_level:
+        q_level = [int(v) for v in args.q_level.split(",")]
     t0 = time.perf_counter()
-    op = B.Operator(geom, args.p, args.level, args.kappa, args.q, args.eta, 5, 5, args.leaf_depth)
+    op = B.Operator(geom, args.p, args.level, args.kappa, args.q, args.eta, 5, 5, args.leaf_depth,
+                    kappa_cap=args.kappa_cap, q_level=q_level)
     t_asm = time.perf_counter() - t0
     dirs, pols = W.fibonacci_plane_waves(args.nrhs)
     F = op.rhs_plane_wave(dirs, pols)
@@ -255,7 +264,8 @@ def run_solve(args):
                                                   if args.jitter > 0 else "")
                                + f", level {args.level}, p={args.p}, kappa={args.kappa}, q={args.q}, "
                                f"eta={args.eta}, {args.nrhs} Fibonacci plane waves, GMRES tol {args.tol}, "
-                               f"restart {args.restart}", "n_dof": op.N},
+                               f"restart {args.restart}", "n_dof": op.N, "kappa_cap": args.kappa_cap,
+                   "q_level": op.q_levels(), "far_pairs": int(op.info.far_pairs)},
         "assemble_s": t_asm,
         "runs": runs,
         "refined_vs_fp64_max_rel_diff": diff,

@@ -1402,6 +1402,14 @@ void gmres_batched(ige_op op, int r, const double2 *B, double2 *X, const std::ve
                 }
                 nrun += run[c];
             }
+            if (solve_log() && (jj + 1) % 250 == 0) {   // progress inside long cycles
+                double worst = 0.0;
+                for (int c = 0; c < r; ++c)
+                    if (run[c]) worst = std::max(worst, out.relres_est[c]);
+                std::fprintf(stderr, "[igaefie] gmres: %d iterations into the cycle, %d columns running, max relres %.3e\n",
+                             jj + 1, nrun, worst);
+                std::fflush(stderr);
+            }
             if (nrun == 0) break;
             if (changed) upload_mask(run, op->d_grun.p);
         }
