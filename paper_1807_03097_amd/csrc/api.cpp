@@ -1249,7 +1249,7 @@ bool solve_log()
 // the FP64 basis vector before rounding
 void gmres_batched(ige_op op, int r, const double2 *B, double2 *X, const std::vector<double> &tol, int m,
                    const std::vector<int> &it_cap,
-                   int prec, GmresOut &out, bool b32 = false)
+                   int prec, GmresOut &out, bool b32 = false, ApplyGraph *gkeep = nullptr)
 {
     const int64_t N = op->D.N;
     hipStream_t s = op->ctx->stream;
@@ -1308,7 +1308,10 @@ void gmres_batched(ige_op op, int r, const double2 *B, double2 *X, const std::ve
         IGE_HIP(hipMemcpyAsync(dst, v.data(), sizeof(int) * r, hipMemcpyHostToDevice, s));
         IGE_HIP(hipStreamSynchronize(s));   // v leaves scope
     };
-    ApplyGraph ag;
+    // the apply graph (captured once, replayed): the caller's when given, so that the
+    // inner solves of successive refinement steps reuse one graph
+    ApplyGraph local;
+    ApplyGraph &ag = gkeep ? *gkeep : local;
     const std::vector<double> bnorm = norms(B);
     out.iters.assign(r, 0);
     out.relres_est.assign(r, 0.0);
@@ -1491,7 +1494,7 @@ int ige_solve(ige_op op, int r, const ige_c64 *f, ige_c64 *x, int ptr_kind, cons
             // each inner solve is one GMRES cycle at most: the restart is an outer step with
             // the true FP64 residual, so a cycle never continues past the point where the
             // inner operator's rounding stops the true inner residual from decreasing
-            ApplyGraph ag64;
+            ApplyGraph ag64, ag_inner;
             // inner precision in use; a refinement step whose FP64 residual contracts by
             // less than 1/2 while the inner solve claimed at least twice as much is limited
             // by the inner operator's error: its growing columns are undone and the inner
@@ -1563,7 +1566,7 @@ int ige_solve(ige_op op, int r, const ige_c64 *f, ige_c64 *x, int ptr_kind, cons
                 }
                 IGE_HIP(hipMemsetAsync(op->d_D.p, 0, sizeof(double2) * r * N, s));
                 // columns already converged get an inner budget of 0 and a zero correction
-                gmres_batched(op, r, op->d_r.p, op->d_D.p, itol, opts->restart, cap, cur, go, inner_b32);
+                gmres_batched(op, r, op->d_r.p, op->d_D.p, itol, opts->restart, cap, cur, go, inner_b32, &ag_inner);
                 ige::launch_axpby(op, (int64_t)r * N, make_double2(1, 0), op->d_D.p, make_double2(1, 0), X);
                 for (int c = 0; c < r; ++c) {
                     iters[c] += go.iters[c];
