@@ -849,3 +849,42 @@ def test_high_kappa_rows_match_dense_with_level_degrees(oracle_mod, ctx, name):
     _say(f"  {name}: degrees {ql} far={op.info.far_pairs} vs oracle FMM {err:.1e}, vs dense {errd:.1e}")
     assert err <= TOL and errd <= 1e-6
     op.close()
+
+
+def test_edge_and_degenerate_cases(oracle_mod, ctx):
+    """Degenerate inputs through the C ABI: zero columns are refused; a zero density
+    gives exactly zero (product, right-hand side of zero polarisation, solve, potential);
+    an empty point set is accepted; the scalar operator with one element per patch and
+    an operator whose only far level is level 0 (leaf = patch) with its own degree match
+    the oracle; a leaf level below a level of larger degree keeps parity."""
+    from paper_1807_03097_amd import binding as B
+    pats = W.cube_sphere()
+    geom = B.Geometry(ctx, pats)
+    op = B.Operator(geom, 2, 3, 6.0, 6, 1.0, 5, 5, 1)
+    with pytest.raises(B.IgeError) as e:
+        op.apply(np.zeros((0, op.N), np.complex128))
+    assert e.value.code == B.IGE_EINVAL
+    z = np.zeros(op.N, np.complex128)
+    assert np.array_equal(op.apply(z), z)
+    f0 = op.rhs_plane_wave([[0.0, 0.0, 1.0]], [[0.0, 0.0, 0.0]])[0]
+    assert np.array_equal(f0, z)
+    x0, st, rc = op.solve(f0, tol=1e-8)
+    assert rc == 0 and st[0][0] == 0 and np.array_equal(x0, z)
+    assert op.potential(W.random_coeffs(op.N, 0), np.zeros((0, 3))).shape == (0, 3)
+    assert np.array_equal(op.potential(z, [[0.0, 0.0, 3.0]]), np.zeros((1, 3), np.complex128))
+    op.close()
+    # scalar single layer with one element per patch
+    sc = B.Operator(geom, 2, 0, 2.0, 4, 1.0, 5, 5, 0, kind=B.IGE_OP_SCALAR)
+    o = oracle_mod.Oracle(pats, 2, 0, 2.0, g=5, gs=5, scalar=True)
+    x = W.random_coeffs(sc.N, 1)
+    assert sc.N == 6 * 9 and _rel(sc.apply(x), o.fmm_apply(x, 4, 1.0, 0)) <= TOL
+    sc.close()
+    # leaf = patch (leaf depth 3 at level 3): far blocks between opposite patches only
+    # (eta = 12: their balls are 0.16 apart), on level 0, with a degree of its own
+    ol = oracle_mod.Oracle(pats, 2, 3, 8.0, g=5, gs=5)
+    for ql in ([9], [9, 0, 0, 0]):
+        lq = B.Operator(geom, 2, 3, 8.0, 6, 12.0, 5, 5, 3, q_level=ql)
+        assert lq.info.leaf_level == 0 and lq.q_levels() == [9] and lq.info.far_pairs == 6
+        x = W.random_coeffs(lq.N, 2)
+        assert _rel(lq.apply(x), ol.fmm_apply(x, [9], 12.0, 3)) <= TOL
+        lq.close()
