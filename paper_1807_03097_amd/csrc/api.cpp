@@ -280,6 +280,7 @@ void plan(ige_op op, const ige_geom_s *geom, ige::NearBlocks &A, std::vector<ige
     ige::build_near_compact(op->cmp, op->D, op->T, A, nrows);
     if (const char *e = std::getenv("IGE_NEAR_RS")) op->cmp_rs = std::atoi(e) == 4 ? 4 : 2;
     if (const char *e = std::getenv("IGE_NEAR_PRIO")) op->near_prio = std::max(0, std::min(3, std::atoi(e)));
+    if (const char *e = std::getenv("IGE_M2L_RM")) op->m2l_rm = std::atoi(e) != 0;
     std::vector<double> corners;
     ige::build_singular_pairs(sing, corners, geom->G, op->D, op->T, A);
     op->nsing = (int64_t)sing.size();

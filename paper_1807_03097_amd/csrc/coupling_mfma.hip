@@ -600,6 +600,145 @@ __global__ __launch_bounds__(128 * WN) void k_m2l_md(DevOp o, int r, int rc, int
     }
 }
 
+// The double-buffered product with the real and the imaginary row tiles of a column
+// tile in the same wave: WN waves of NT column tiles each, no two waves loading the
+// same right-factor fragments (the kernel above loads each twice, once per row half),
+// at the price of twice the left-factor reads from shared memory.
+template <int SPLIT, int MT, int WN, int NT>
+__global__ __launch_bounds__(64 * WN) void k_m2l_mxr(DevOp o, int r, int rc, int nchunk, int64_t nwork,
+                                                     const int32_t *order, const M2LWork *work,
+                                                     const int32_t *partner, const int32_t *gslot, const __bf16 *Gb,
+                                                     const __bf16 *Vb, float2 *part)
+{
+    constexpr int PL = SPLIT == 3 ? 2 : 1;
+    constexpr int QP = 16 * MT, K2 = 2 * QP, KS = K2 / 32, LD = K2 + IGE_GPAD;
+    constexpr int NTH = 64 * WN, NCOL = 16 * WN * NT;
+    constexpr int GCH = PL * QP * K2 / 8;           // 16-byte pieces of one block
+    constexpr int GV = (GCH + NTH - 1) / NTH;       // pieces per thread
+    constexpr int PPS = (GV + KS - 1) / KS;         // pieces per thread per reduction step
+    constexpr size_t BUF = (size_t)PL * QP * LD;    // one staging buffer
+    extern __shared__ __bf16 sG[];                  // [2][PL][QP][LD]
+    const int tid = threadIdx.x, lane = tid & 63, wn = tid >> 6;
+    const int Q = o.Q;
+    const int64_t g = blockIdx.x;
+    const int64_t wo = (g / (8 * nchunk)) * 8 + g % 8;
+    const int ch = (int)((g / 8) % nchunk);
+    if (wo >= nwork) return;
+    const int64_t wi = order[wo];
+    if (wi < 0) return;   // padding slot of a launch order
+    const M2LWork wk = work[wi];
+    if (wk.beg >= wk.end) return;
+    const size_t gper = (size_t)PL * QP * K2, vper = (size_t)NCOL * K2;
+
+    auto s_piece = [&](__bf16 *buf, int e, uint4 v) {
+        const int pl = e / (QP * K2 / 8), rr = e % (QP * K2 / 8), row = rr / (K2 / 8), k8 = rr % (K2 / 8);
+        *reinterpret_cast<uint4 *>(buf + ((size_t)pl * QP + row) * LD + 8 * k8) = v;
+    };
+    auto b_load = [&](bf8 (&b)[NT][PL], int kp, int s) {
+        const __bf16 *Vs = Vb + ((size_t)partner[kp] * nchunk + ch) * PL * vper;
+        const int kk = 32 * s + 8 * (lane >> 4);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int n = 16 * (wn * NT + t) + (lane & 15);
+#pragma unroll
+            for (int pl = 0; pl < PL; ++pl)
+                b[t][pl] = *reinterpret_cast<const bf8 *>(Vs + (size_t)pl * vper + (size_t)n * K2 + kk);
+        }
+    };
+
+    f4 acc[2][MT][NT];   // [real rows, imaginary rows]
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int a = 0; a < MT; ++a)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[h][a][t] = f4{0.f, 0.f, 0.f, 0.f};
+
+    {   // first block straight into buffer 0
+        const __bf16 *Gp = Gb + (size_t)gslot[wk.beg] * gper;
+        for (int e = tid; e < GCH; e += NTH) s_piece(sG, e, *reinterpret_cast<const uint4 *>(Gp + (size_t)8 * e));
+    }
+    bf8 bcur[NT][PL], bnxt[NT][PL];
+    b_load(bcur, wk.beg, 0);
+    __syncthreads();
+    for (int kp = wk.beg; kp < wk.end; ++kp) {
+        const __bf16 *cur = sG + (size_t)((kp - wk.beg) & 1) * BUF;
+        __bf16 *nxt = sG + (size_t)(((kp - wk.beg) & 1) ^ 1) * BUF;
+        const int kq = min(kp + 1, wk.end - 1);
+        const __bf16 *Gn = Gb + (size_t)gslot[kq] * gper;
+        constexpr bool GEVEN = GCH % NTH == 0;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            uint4 pc[PPS];
+#pragma unroll
+            for (int v = 0; v < PPS; ++v) {
+                const int e = tid + NTH * (s * PPS + v);
+                if (s * PPS + v < GV && (GEVEN || e < GCH)) pc[v] = *reinterpret_cast<const uint4 *>(Gn + (size_t)8 * e);
+            }
+            if (s + 1 < KS) b_load(bnxt, kp, s + 1);
+            else b_load(bnxt, kq, 0);
+            const bool hi_half = 32 * s >= QP;
+            const int kk = 32 * s + 8 * (lane >> 4);
+            // real rows [Gr, -Gi]: columns kk of the stored [Gr | Gi] row, negated in the
+            // upper half; imaginary rows [Gi, Gr]: the halves swapped
+            const int ksrc[2] = {kk, hi_half ? kk - QP : kk + QP};
+#pragma unroll
+            for (int a = 0; a < MT; ++a) {
+                bf8 ah[2], al[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const __bf16 *row = cur + (size_t)(16 * a + (lane & 15)) * LD + ksrc[h];
+                    ah[h] = *reinterpret_cast<const bf8 *>(row);
+                    if (SPLIT == 3) al[h] = *reinterpret_cast<const bf8 *>(row + (size_t)QP * LD);
+                }
+                if (hi_half) {
+                    ah[0] = neg_bf8(ah[0]);
+                    if (SPLIT == 3) al[0] = neg_bf8(al[0]);
+                }
+                // the split products go over the tile's 2 NT accumulators in turn, so
+                // consecutive instructions never share an accumulator
+#pragma unroll
+                for (int term = 0; term < (SPLIT == 3 ? 3 : 1); ++term)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+#pragma unroll
+                        for (int t = 0; t < NT; ++t) {
+                            const bf8 &A = term == 2 ? al[h] : ah[h];
+                            const bf8 &Bv = term == 1 ? bcur[t][PL - 1] : bcur[t][0];
+                            acc[h][a][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, Bv, acc[h][a][t], 0, 0, 0);
+                        }
+            }
+#pragma unroll
+            for (int v = 0; v < PPS; ++v) {
+                const int e = tid + NTH * (s * PPS + v);
+                if (s * PPS + v < GV && (GEVEN || e < GCH)) s_piece(nxt, e, pc[v]);
+            }
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int pl = 0; pl < PL; ++pl) bcur[t][pl] = bnxt[t][pl];
+        }
+        __syncthreads();   // the next block is complete and the current buffer is free
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int n = 16 * (wn * NT + t) + (lane & 15), f = n / rc, jc = n % rc;
+        const int col = ch * rc + jc;
+        if (f >= 4 || col >= r) continue;
+#pragma unroll
+        for (int a = 0; a < MT; ++a)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int m = 16 * a + 4 * (lane >> 4) + j;
+                if (m < Q) {
+                    float *dst = reinterpret_cast<float *>(part + (((size_t)wi * 4 + f) * Q + m) * r + col);
+                    dst[0] = acc[0][a][t][j];
+                    dst[1] = acc[1][a][t][j];
+                }
+            }
+    }
+}
+
 }  // namespace
 
 int coupling_qp(int Q) { return 32 * ((Q + 31) / 32); }
@@ -669,10 +808,47 @@ void launch_mx(ige_op op, int r, int rc, int nchunk, const __bf16 *G, const __bf
     IGE_HIP(hipGetLastError());
 }
 
+// the rows-merged kernel (k_m2l_mxr): WN waves of NT column tiles
+template <int SPLIT, int MT, int WN, int NT>
+void launch_mxr(ige_op op, int r, int rc, int nchunk, const __bf16 *G, const __bf16 *Vb, hipStream_t s)
+{
+    const DevOp &o = op->view;
+    const bool spatial = tune_get(op, kTuneM2lOrder, r, SPLIT, 0) == 1 && op->n_morder_sp > 0;
+    const int64_t nw = spatial ? op->n_morder_sp : (int64_t)op->mwork.size();
+    const int32_t *order = spatial ? op->d_morder_sp.p : op->d_morder.p;
+    const dim3 grid((unsigned)(((nw + 7) / 8) * 8 * nchunk)), blk(64 * WN);
+    constexpr int PL = SPLIT == 3 ? 2 : 1, QP = 16 * MT;
+    constexpr size_t shm = sizeof(__bf16) * 2 * PL * QP * (2 * QP + IGE_GPAD);
+    auto kern = &k_m2l_mxr<SPLIT, MT, WN, NT>;
+    static const bool attr = [&] {
+        int lds_max = 0;
+        IGE_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, op->ctx->device));
+        IGE_REQUIRE(shm <= (size_t)lds_max, "coupling block does not fit in shared memory");
+        IGE_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)shm));
+        return true;
+    }();
+    (void)attr;
+    hipLaunchKernelGGL(kern, grid, blk, shm, s, o, r, rc, nchunk, nw, order, op->d_mwork.p, op->d_mpartner.p,
+                       op->d_gslot.p, G, Vb, op->d_bmpart.p);
+    IGE_HIP(hipGetLastError());
+}
+
 template <bool DB, int SPLIT, int MT>
 void launch_mx_cols(ige_op op, int r, int ncol, const __bf16 *G, const __bf16 *Vb, hipStream_t s)
 {
     const int rc = ncol / 4, nchunk = (r + rc - 1) / rc;
+    // wide double-buffered chunks: the rows-merged kernel (IGE_M2L_RM=0 keeps the other)
+    if constexpr (DB) {
+        if (op->m2l_rm && ncol == 256 && MT <= 6) {
+            launch_mxr<SPLIT, MT, 8, 2>(op, r, rc, nchunk, G, Vb, s);
+            return;
+        }
+        if (op->m2l_rm && ncol == 128) {
+            launch_mxr<SPLIT, MT, 8, 1>(op, r, rc, nchunk, G, Vb, s);
+            return;
+        }
+    }
     switch (ncol) {
         case 16: launch_mx<DB, SPLIT, MT, 1, 1>(op, r, rc, nchunk, G, Vb, s); break;
         case 32: launch_mx<DB, SPLIT, MT, 2, 1>(op, r, rc, nchunk, G, Vb, s); break;

@@ -138,6 +138,9 @@ struct ige_op_s {
     // loads issue ahead of the coupling kernel's arithmetic on shared SIMDs (C2 apply
     // 0.208 against 0.218 ms on one device)
     int near_prio = 1;
+    // BF16 coupling of wide column chunks: real and imaginary row tiles in one wave
+    // (IGE_M2L_RM, default 1)
+    bool m2l_rm = true;
     int64_t nfp = 0;
 
     // device buffers
