@@ -67,6 +67,7 @@ def parse():
     ap.add_argument("--restart", type=int, default=1500, help="solve: GMRES restart")
     ap.add_argument("--inner-prec", type=int, default=3, choices=(0, 1, 2, 3, 4),
                     help="solve: precision of refined inner solves (as --prec)")
+    ap.add_argument("--inner-tol", type=float, default=1e-4, help="solve: relative residual of the inner solves")
     ap.add_argument("--compare-fp64", action="store_true", help="solve: also solve in FP64 and report the difference")
     ap.add_argument("--autotune", action="store_true",
                     help="time the candidate tile shapes of the apply first and keep the fastest (ige_op_autotune)")
@@ -237,7 +238,7 @@ def run_solve(args):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         X, st, rc = op.solve(F, tol=args.tol, restart=args.restart, maxit=args.maxit, refine=refine,
-                             inner_tol=1e-4, inner_prec=args.inner_prec)
+                             inner_tol=args.inner_tol, inner_prec=args.inner_prec)
         dt = time.perf_counter() - t1
         sols[name] = X
         iters = [s_[0] for s_ in st]
