@@ -530,6 +530,9 @@ ige_op ige::assemble_on(ige_ctx ctx, const ige_geom_s *geom, const ige_params &p
             v.Mp = op->d_Mp.p; v.Mq = op->d_Mq.p; v.Mdp = op->d_Mdp.p;
             op->d_nodeX.alloc((size_t)op->NC * 3 * v.Q);
             op->d_nodeT.alloc((size_t)op->NC * 6 * v.Q);
+            // levels of a smaller degree fill only the first (q_l + 1)^2 entries of a field
+            IGE_HIP(hipMemsetAsync(op->d_nodeX.p, 0, op->d_nodeX.bytes(), s));
+            IGE_HIP(hipMemsetAsync(op->d_nodeT.p, 0, op->d_nodeT.bytes(), s));
             v.nodeX = op->d_nodeX.p; v.nodeT = op->d_nodeT.p;
             op->d_sctab.upload(sincos_table(), s);
             v.sctab = op->d_sctab.p;
