@@ -526,6 +526,8 @@ def main():
         ncol = 16
         while ncol < 4 * r and ncol < cap:
             ncol *= 2
+        if not f64mx and ncol >= 128 and os.environ.get("IGE_M2L_RM", "1") != "0":
+            kern = "k_m2l_mxr"   # wide chunks: real and imaginary row tiles in one wave
         nchunk = -(-r // (ncol // 4))
         issued = info.far_pairs * nchunk * 2.0 * (2 * Qp) * (2 * Qp) * ncol * split
         useful = info.far_pairs * 8.0 * Q * Q * 4 * r
@@ -601,6 +603,21 @@ def main():
 
     roof = roofline(st)
     roof_cpl = roofline_coupling(st)
+
+    def measured(rf):
+        """the same fraction against the device's achievable peak (the library's probes)"""
+        if rf is None:
+            return rf
+        m = None
+        if rf["bound"] == "hbm":
+            m = peaks["hbm_GBps"]
+        elif rf["bound"] == "mfma":
+            m = peaks["f64_mfma_TFLOPs"] if rf["kernel"] in ("k_m2l_md", "k_near_md", "k_near_mfma") \
+                else peaks["bf16_mfma_TFLOPs"]
+        rf["peak_measured"] = m
+        rf["frac_of_measured"] = None if m is None else rf["achieved"] / m
+        return rf
+
     # error of a reduced-precision apply against the FP64 apply of the same columns
     err_fp64 = None
     if args.prec != 0:
@@ -618,9 +635,16 @@ def main():
     st_iso = {n: float(v) for n, v in zip(names, op.stage_times())}
     op.set_profiling(False)
     op.set_overlap(True)
-    roof_iso = roofline(st_iso)
+    # achievable peaks of this device (the library's own copy and matrix-core probes),
+    # taken after the timed and the isolated passes so that they cannot disturb them
+    peaks = {"hbm_GBps": B.ige_peak_probe(ctx.h, B.IGE_PROBE_HBM),
+             "bf16_mfma_TFLOPs": B.ige_peak_probe(ctx.h, B.IGE_PROBE_MFMA_BF16),
+             "f64_mfma_TFLOPs": B.ige_peak_probe(ctx.h, B.IGE_PROBE_MFMA_F64)}
+    log("measured peaks: " + " ".join(f"{k}={v:.1f}" for k, v in peaks.items()))
+    roof, roof_cpl = measured(roof), measured(roof_cpl)
+    roof_iso = measured(roofline(st_iso))
     # the near-field product alone on the device (stages in order on one stream)
-    roof_near_iso = roofline(st_iso, dom="near_spmv")
+    roof_near_iso = measured(roofline(st_iso, dom="near_spmv"))
     log("isolated stage ms: " + " ".join(f"{k}={v:.4f}" for k, v in st_iso.items()))
 
     # parity spot check against the oracle (sampled rows) + CPU baseline
@@ -662,6 +686,8 @@ def main():
                    "parallelism": "single GPU"},
         "timed_kernel_ms": st,
         "assemble_s": t_asm,
+        "superspace_dof_per_s": 2 * len(pats) * ((1 << m) + p) * ((1 << m) + p - 1) * r / (ms_step * 1e-3),
+        "peaks_measured": peaks,
         "roofline": roof,
         "roofline_isolated": roof_iso,
         "roofline_near_isolated": roof_near_iso,

@@ -413,6 +413,17 @@ int ige_potential(ige_op op, int r, const ige_c64 *w, int ptr_kind, int npts, co
  * streams, or two host threads) race on that array. */
 int ige_potential_noalloc(ige_op op, int r, const ige_c64 *w, int npts, const double *points, ige_c64 *E);
 
+/* Achievable peaks of the context's device, measured by the library's own probe
+ * kernels (diagnostic; the benchmarks report roofline fractions against these beside
+ * the published figures).  Synchronous; allocates 2 GiB for the copy probe.
+ *   IGE_PROBE_HBM:       a grid-stride copy of 1 GiB, *value = GB/s (bytes read + written);
+ *   IGE_PROBE_MFMA_BF16: register-only 16x16x32 BF16 matrix-core products (16 independent
+ *                        chains per wave, four waves per SIMD on every CU), *value = TFLOP/s;
+ *   IGE_PROBE_MFMA_F64:  the same with the 16x16x4 FP64 product (8 chains per wave).
+ * Best of 5 timed launches after one warm-up. */
+enum { IGE_PROBE_HBM = 0, IGE_PROBE_MFMA_BF16 = 1, IGE_PROBE_MFMA_F64 = 2 };
+int ige_peak_probe(ige_ctx ctx, int kind, double *value);
+
 /* Diagnostic: evaluate on the context's device the Helmholtz kernel
  * G_k(r) = e^{ikr}/(4 pi r) (Sec. 2.2, eq. (eq:HelmholtzGreen)) exactly as the
  * coupling stage does in precision prec (IGE_F64: reciprocal square root with two

@@ -46,6 +46,7 @@ class ige_op_info_t(C.Structure):
 
 IGE_F64, IGE_F32, IGE_BF16, IGE_BF16X3, IGE_BF16X3_ALL = 0, 1, 2, 3, 4
 IGE_OP_EFIE, IGE_OP_SCALAR = 0, 1
+IGE_PROBE_HBM, IGE_PROBE_MFMA_BF16, IGE_PROBE_MFMA_F64 = 0, 1, 2
 IGE_RHS_PLANE, IGE_RHS_POINT = 0, 1
 
 
@@ -101,6 +102,7 @@ _SIGS = {
     "ige_rhs_scalar": (C.c_int, [_V, C.c_int, C.c_int, _V, _V, C.c_int]),
     "ige_solve": (C.c_int, [_V, C.c_int, _V, _V, C.c_int, C.POINTER(ige_solve_opts), _V]),
     "ige_helmholtz_eval": (C.c_int, [_V, C.c_int64, C.c_double, _V, _V, C.c_int]),
+    "ige_peak_probe": (C.c_int, [_V, C.c_int, C.POINTER(C.c_double)]),
     "ige_potential": (C.c_int, [_V, C.c_int, _V, C.c_int, C.c_int, _V, _V]),
     "ige_potential_noalloc": (C.c_int, [_V, C.c_int, _V, C.c_int, _V, _V]),
     "ige_srv_create": (C.c_int, [_V, C.c_int, C.c_size_t, C.POINTER(_V)]),
@@ -227,6 +229,13 @@ def ige_rhs_plane_wave(op, r, dirs, pols, f, ptr_kind):
     dirs = np.ascontiguousarray(dirs, np.float64)
     pols = np.ascontiguousarray(pols, np.complex128)
     _check(_lib.ige_rhs_plane_wave(op, r, _ptr(dirs), _ptr(pols), _ptr(f), ptr_kind))
+
+
+def ige_peak_probe(ctx, kind):
+    """achievable device peak: GB/s (IGE_PROBE_HBM) or TFLOP/s (the matrix-core kinds)"""
+    v = C.c_double(0.0)
+    _check(_lib.ige_peak_probe(ctx, int(kind), C.byref(v)))
+    return v.value
 
 
 def ige_rhs_scalar(op, r, kind, a, f, ptr_kind):

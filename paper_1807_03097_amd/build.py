@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libigaefie.so")
-SOURCES = ["setup.cpp", "api.cpp", "kernels.hip", "kernels_batched.hip", "coupling.hip", "coupling_mfma.hip", "krylov.hip", "near_bf16.hip", "near_once.hip", "serve.cpp"]
+SOURCES = ["setup.cpp", "api.cpp", "kernels.hip", "kernels_batched.hip", "coupling.hip", "coupling_mfma.hip", "krylov.hip", "near_bf16.hip", "near_once.hip", "probe.hip", "serve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

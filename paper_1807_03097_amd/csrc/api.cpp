@@ -279,7 +279,7 @@ void plan(ige_op op, const ige_geom_s *geom, ige::NearBlocks &A, std::vector<ige
     if (const char *e = std::getenv("IGE_NEAR_ROWS")) nrows = std::max(8, std::min(128, std::atoi(e)));
     ige::build_near_compact(op->cmp, op->D, op->T, A, nrows);
     if (const char *e = std::getenv("IGE_NEAR_RS")) op->cmp_rs = std::atoi(e) == 4 ? 4 : 2;
-    if (const char *e = std::getenv("IGE_NEAR_PRIO")) op->near_prio = std::max(0, std::min(3, std::atoi(e)));
+    if (const char *e = std::getenv("IGE_NEAR_PRIO")) op->near_prio = std::max(0, std::min(1, std::atoi(e)));
     if (const char *e = std::getenv("IGE_M2L_RM")) op->m2l_rm = std::atoi(e) != 0;
     std::vector<double> corners;
     ige::build_singular_pairs(sing, corners, geom->G, op->D, op->T, A);
@@ -1665,6 +1665,17 @@ int ige_potential_noalloc(ige_op op, int r, const ige_c64 *w, int npts, const do
         double2 *out = reinterpret_cast<double2 *>(E);
         for (int c = 0; c < r; ++c)
             ige::launch_potential(op, W + (size_t)c * N, npts, points, out + (size_t)c * 3 * npts, scr);
+    });
+}
+
+int ige_peak_probe(ige_ctx ctx, int kind, double *value)
+{
+    return guard([&] {
+        IGE_REQUIRE(ctx && value, "null argument");
+        IGE_REQUIRE(ctx->device >= 0, "the probe needs a device context");
+        IGE_REQUIRE(kind >= IGE_PROBE_HBM && kind <= IGE_PROBE_MFMA_F64, "bad probe kind");
+        set_device(ctx);
+        *value = ige::peak_probe(ctx->stream, kind);
     });
 }
 

@@ -33,7 +33,7 @@ __device__ inline d2v ld_once(const double2 *B, size_t i)
 // ---------------------------------------------------------------------------
 constexpr int kCmpRows = 128;   // largest rows per work item (host: rows_per_item)
 
-template <int U, int RS>
+template <int U, int RS, int PRIO>
 __device__ __forceinline__ void near_cmp_item(const NearCmpView &v, int w, const double2 *x, double2 *part,
                                               double2 *sxr, double2 (*syc)[256])
 {
@@ -54,6 +54,7 @@ __device__ __forceinline__ void near_cmp_item(const NearCmpView &v, int w, const
     }
     for (int q = threadIdx.x; q < r1 - r0; q += blockDim.x) sxr[q] = x[rows[r0 + q]];
     __syncthreads();
+    if constexpr (PRIO > 0) __builtin_amdgcn_s_setprio(PRIO);
     for (int r = r0 + wv; r < r1; r += 4 * RS) {
         d2v al[RS][U];
 #pragma unroll
@@ -121,18 +122,15 @@ __device__ __forceinline__ void near_cmp_item(const NearCmpView &v, int w, const
 
 // Work items of at most 128 columns take two column groups of 64 per lane; the wider
 // ones U of them, in a second launch (obase: first item of the launch in the order).
-template <int U, int RS>
-__global__ __launch_bounds__(256) void k_near_cmp(NearCmpView v, int64_t obase, const double2 *x, double2 *part,
-                                                  int prio)
+template <int U, int RS, int PRIO>
+__global__ __launch_bounds__(256) void k_near_cmp(NearCmpView v, int64_t obase, const double2 *x, double2 *part)
 {
     __shared__ double2 sxr[kCmpRows];
     __shared__ double2 syc[3][256];
     // issue priority of these waves over others resident on the same SIMD (the
-    // coupling kernel runs beside this one)
-    if (prio == 1) __builtin_amdgcn_s_setprio(1);
-    else if (prio == 2) __builtin_amdgcn_s_setprio(2);
-    else if (prio == 3) __builtin_amdgcn_s_setprio(3);
-    near_cmp_item<U, RS>(v, v.order[obase + blockIdx.x], x, part, sxr, syc);
+    // coupling kernel runs beside this one); a compile-time choice, so the kernel's
+    // registers are those of the plain form
+    near_cmp_item<U, RS, PRIO>(v, v.order[obase + blockIdx.x], x, part, sxr, syc);
 }
 
 // Values of the once-per-entry near field: entry (i, j) is the sum over the leaf
@@ -197,17 +195,27 @@ void launch_near_once(ige_op op, const double2 *x, double2 *part, hipStream_t st
     const NearCmpView &v = op->cview;
     const dim3 blk(256);
     const int64_t na = op->cmp.nnarrow, nw = v.nwork - na;
-    const int pr = op->near_prio;
+    const bool pr = op->near_prio > 0;
     if (na > 0) {
-        if (op->cmp_rs == 4)
-            hipLaunchKernelGGL((k_near_cmp<2, 4>), dim3((unsigned)na), blk, 0, st, v, (int64_t)0, x, part, pr);
-        else hipLaunchKernelGGL((k_near_cmp<2, 2>), dim3((unsigned)na), blk, 0, st, v, (int64_t)0, x, part, pr);
+        const dim3 grid((unsigned)na);
+        if (op->cmp_rs == 4) {
+            if (pr) hipLaunchKernelGGL((k_near_cmp<2, 4, 1>), grid, blk, 0, st, v, (int64_t)0, x, part);
+            else hipLaunchKernelGGL((k_near_cmp<2, 4, 0>), grid, blk, 0, st, v, (int64_t)0, x, part);
+        } else {
+            if (pr) hipLaunchKernelGGL((k_near_cmp<2, 2, 1>), grid, blk, 0, st, v, (int64_t)0, x, part);
+            else hipLaunchKernelGGL((k_near_cmp<2, 2, 0>), grid, blk, 0, st, v, (int64_t)0, x, part);
+        }
         IGE_HIP(hipGetLastError());
     }
     if (nw > 0) {
         const dim3 grid((unsigned)nw);
-        if ((op->cmp.maxn + 63) / 64 <= 3) hipLaunchKernelGGL((k_near_cmp<3, 2>), grid, blk, 0, st, v, na, x, part, pr);
-        else hipLaunchKernelGGL((k_near_cmp<4, 2>), grid, blk, 0, st, v, na, x, part, pr);
+        if ((op->cmp.maxn + 63) / 64 <= 3) {
+            if (pr) hipLaunchKernelGGL((k_near_cmp<3, 2, 1>), grid, blk, 0, st, v, na, x, part);
+            else hipLaunchKernelGGL((k_near_cmp<3, 2, 0>), grid, blk, 0, st, v, na, x, part);
+        } else {
+            if (pr) hipLaunchKernelGGL((k_near_cmp<4, 2, 1>), grid, blk, 0, st, v, na, x, part);
+            else hipLaunchKernelGGL((k_near_cmp<4, 2, 0>), grid, blk, 0, st, v, na, x, part);
+        }
         IGE_HIP(hipGetLastError());
     }
 }

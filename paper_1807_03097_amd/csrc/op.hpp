@@ -134,10 +134,10 @@ struct ige_op_s {
     // shared memory per workgroup of the generated single-column coupling (0: what it
     // needs); more limits its workgroups per CU and leaves registers to the near field
     size_t m2l_lds = 0;
-    // wave issue priority of the once-per-entry near-field product (0..3): 1 lets its
-    // loads issue ahead of the coupling kernel's arithmetic on shared SIMDs (C2 apply
-    // 0.208 against 0.218 ms on one device)
-    int near_prio = 1;
+    // wave issue priority of the once-per-entry near-field product (0 or 1, the latter
+    // ahead of the coupling kernel's waves on shared SIMDs; measured: no gain per apply,
+    // and slower alone, so 0)
+    int near_prio = 0;
     // BF16 coupling of wide column chunks: real and imaginary row tiles in one wave
     // (IGE_M2L_RM, default 1)
     bool m2l_rm = true;
@@ -326,6 +326,9 @@ void launch_potential(ige_op op, const double2 *w, int npts, const double *pts, 
 void potential_scratch_init(int device);
 double *potential_scratch(int device);
 size_t potential_scratch_doubles();
+// achievable peak of the device on stream s: kind 0 HBM copy (GB/s), 1 BF16 matrix
+// cores (TFLOP/s), 2 FP64 matrix cores (TFLOP/s)
+double peak_probe(hipStream_t s, int kind);
 // raise a kernel's dynamic shared-memory limit above 64 KB once per process
 void lds_attr_once(const void *kern, size_t shm);
 // scalar single layer right-hand side (kind 0 plane wave of direction a, 1 point source at a)

@@ -888,3 +888,19 @@ def test_edge_and_degenerate_cases(oracle_mod, ctx):
         x = W.random_coeffs(lq.N, 2)
         assert _rel(lq.apply(x), ol.fmm_apply(x, [9], 12.0, 3)) <= TOL
         lq.close()
+
+
+def test_peak_probes_are_plausible(ctx):
+    """The library's own probes of the device's achievable peaks lie below the published
+    figures (HBM 8 TB/s, dense BF16 2.5 PFLOP/s, FP64 matrix cores 78.6 TFLOP/s, with 10 %
+    allowance for clocks above the nominal one) and well above a tenth of them."""
+    from paper_1807_03097_amd import binding as B
+    hbm = B.ige_peak_probe(ctx.h, B.IGE_PROBE_HBM)
+    bf16 = B.ige_peak_probe(ctx.h, B.IGE_PROBE_MFMA_BF16)
+    f64 = B.ige_peak_probe(ctx.h, B.IGE_PROBE_MFMA_F64)
+    _say(f"  measured peaks: HBM {hbm:.0f} GB/s, BF16 {bf16:.0f} TFLOP/s, FP64 matrix cores {f64:.1f} TFLOP/s")
+    assert 800.0 < hbm <= 8000.0 * 1.1
+    assert 250.0 < bf16 <= 2500.0 * 1.1
+    assert 7.86 < f64 <= 78.6 * 1.1
+    with pytest.raises(B.IgeError):
+        B.ige_peak_probe(ctx.h, 7)
