@@ -28,9 +28,18 @@ SANITIZE = {
 }
 
 
-def build(verbose: bool = False, variant: str | None = None) -> str:
+def _newest_input(src: str) -> float:
+    """latest modification time of a source and of every header it may include"""
+    hdrs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
+    inc = os.path.join(os.path.dirname(HERE), "include")
+    hdrs += [os.path.join(inc, f) for f in os.listdir(inc) if f.endswith(".h")]
+    return max(os.path.getmtime(p) for p in [src, *hdrs, __file__])
+
+
+def build(verbose: bool = False, variant: str | None = None, incremental: bool = False) -> str:
     """Compile the library; variant "asan" or "tsan" builds a host-sanitized copy
-    _build_<variant>/libigaefie_<variant>.so instead of libigaefie.so."""
+    _build_<variant>/libigaefie_<variant>.so instead of libigaefie.so.  incremental:
+    keep object files newer than their source, every header and this script."""
     extra = SANITIZE[variant] if variant else []
     objdir = os.path.join(HERE, "_build" + (f"_{variant}" if variant else ""))
     target = os.path.join(objdir, f"libigaefie_{variant}.so") if variant else OUT
@@ -39,11 +48,14 @@ def build(verbose: bool = False, variant: str | None = None) -> str:
     procs = []
     for src in SOURCES:
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
-        cmd = [HIPCC, "-x", "hip", *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
+        objs.append(obj)
+        spath = os.path.join(CSRC, src)
+        if incremental and os.path.exists(obj) and os.path.getmtime(obj) > _newest_input(spath):
+            continue
+        cmd = [HIPCC, "-x", "hip", *FLAGS, *extra, "-c", spath, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
-        objs.append(obj)
     failed = []
     for src, p in procs:
         out, _ = p.communicate()

@@ -39,7 +39,7 @@ def _write_geom(path, patches):
 @pytest.mark.parametrize("variant", ["asan", "tsan"])
 def test_host_code_under_sanitizers(tmp_path, variant):
     from paper_1807_03097_amd import build as B
-    lib = B.build(variant=variant)
+    lib = B.build(variant=variant, incremental=True)   # objects older than their inputs are rebuilt
     libdir = os.path.dirname(lib)
     exe = str(tmp_path / f"host_driver_{variant}")
     cmd = [CLANGXX, "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", *DRIVER_FLAGS[variant], "-o", exe,
