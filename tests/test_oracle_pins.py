@@ -433,7 +433,7 @@ def test_fmm_kernel_swap_is_exact(oracle_mod):
     moment matrices, the K_1^(a,b) geometry factors, the K_2 divergence term and the
     gluing together (eq:FMMlr)."""
     for p, m, d, q in ((2, 2, 0, 5), (1, 3, 1, 4)):
-        o = oracle_mod.Oracle(W.flat_cube(), p, m, 3.0, g=8, gs=8, kernel=1)
+        o = oracle_mod.Oracle(W.flat_cube(), p, m, 3.0, g=5, gs=5, kernel=1)
         tr = o.block_tree(1.6, d)
         assert len(tr["far"]) > 0
         x = W.random_coeffs(o.N, 2)
@@ -533,7 +533,7 @@ def test_level_degrees_pin_each_level(oracle_mod):
     the dense one for any such choice; degree 2 on a level is visible exactly when that
     level has far blocks (level 0 has none here).  This pins that each level's moments,
     nodes and test-side expansions use that level's own degree."""
-    o = oracle_mod.Oracle(W.flat_cube(), 1, 3, 3.0, g=8, gs=8, kernel=1)
+    o = oracle_mod.Oracle(W.flat_cube(), 1, 3, 3.0, g=4, gs=4, kernel=1)
     tr = o.block_tree(1.6, 1)
     nfar = np.bincount(tr["far"][:, 0], minlength=tr["L"] + 1)
     assert tr["L"] == 2 and nfar[0] == 0 and np.all(nfar[1:] > 0)
@@ -727,7 +727,7 @@ def test_scalar_fmm_pins(oracle_mod):
     tr0 = o.block_tree(1e-8, 1)
     assert np.linalg.norm(o.fmm_apply(x, 6, 1e-8, 1, tree=tr0) - o.dense_apply(x)) <= 1e-14 * np.linalg.norm(o.dense_apply(x))
     for p, m, d, q in ((2, 2, 0, 5), (1, 3, 1, 4)):
-        oc = oracle_mod.Oracle(W.flat_cube(), p, m, 3.0, g=8, gs=8, kernel=1, scalar=True)
+        oc = oracle_mod.Oracle(W.flat_cube(), p, m, 3.0, g=5, gs=5, kernel=1, scalar=True)
         tr = oc.block_tree(1.6, d)
         assert len(tr["far"]) > 0
         xc = W.random_coeffs(oc.N, 2)
