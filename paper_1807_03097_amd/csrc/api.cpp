@@ -114,6 +114,36 @@ void apply_one(ige_op op, const double2 *x, double2 *y, int prec = IGE_F64)
         }
         return;
     }
+    if (op->near_first) {
+        // the near-field product beside the short upward pass only; the coupling stage
+        // then has the device to itself
+        mark(0, s);
+        IGE_HIP(hipEventRecord(op->ev_fork, s));
+        IGE_HIP(hipStreamWaitEvent(s2, op->ev_fork, 0));
+        mark(7, s2);
+        ige::launch_spmv(op, x, y, s2, prof ? ev[11] : nullptr);
+        mark(8, s2);
+        IGE_HIP(hipEventRecord(op->ev_join, s2));
+        ige::launch_p2m(op, x);
+        mark(1, s);
+        ige::launch_m2m(op);
+        mark(2, s);
+        IGE_HIP(hipStreamWaitEvent(s, op->ev_join, 0));
+        mark(12, s);
+        ige::launch_m2l(op, prec);
+        mark(3, s);
+        ige::launch_m2l_reduce(op);
+        mark(4, s);
+        ige::launch_l2l(op);
+        mark(5, s);
+        ige::launch_l2p_leaf(op);
+        mark(6, s);
+        mark(9, s);
+        ige::launch_l2p_gather(op, y);
+        mark(10, s);
+        if (prof) op->prof_count++;
+        return;
+    }
     // the small upward-pass kernels go first; the near-field product then shares
     // the device with the long coupling stage
     mark(0, s);
@@ -543,6 +573,7 @@ ige_op ige::assemble_on(ige_ctx ctx, const ige_geom_s *geom, const ige_params &p
             if (const char *e = std::getenv("IGE_M2L_CHUNK")) CH = std::max(1, std::min(64, std::atoi(e)));
             op->overlap = true;
             if (const char *e = std::getenv("IGE_OVERLAP")) op->overlap = std::atoi(e) != 0;
+            if (const char *e = std::getenv("IGE_NEAR_FIRST")) op->near_first = std::atoi(e) != 0;
             std::vector<int32_t> partner;
             op->wrk_of_tgt.assign(op->NC + 1, 0);
             {
