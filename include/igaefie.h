@@ -115,8 +115,9 @@ int ige_geom_destroy(ige_geom geom);
  *                 scalar space in place of S^1: (2^m + p)^2 functions per patch, no
  *                 continuity across patches, unknowns ordered patch, i2, i1), compressed
  *                 with the K_2 block alone (eq:FMMlr with the surface elements inside
- *                 the localized kernel).  The scalar operator applies and solves in FP64
- *                 only; refinement, autotuning, plane-wave fields and serving refuse it.
+ *                 the localized kernel).  The scalar operator takes every apply
+ *                 precision, refinement and autotuning like the EFIE one; plane-wave
+ *                 fields (ige_rhs_plane_wave) and serving refuse it.
  *   q_level       interpolation degree per cluster-tree level l = 0..10 (0: q), 1..15:
  *                 the far blocks of level l are interpolated with q_level[l] + 1 nodes
  *                 per direction (the variable-order form of Sec. 4.2; the paper uses one

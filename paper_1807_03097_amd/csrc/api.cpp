@@ -1020,9 +1020,9 @@ void apply_dev(ige_op op, int r, const double2 *x, double2 *y, int prec, ApplyGr
     const bool graph = g && !op->profiling && graphs_enabled();
     hipStream_t s = op->ctx->stream;
     const int64_t N = op->D.N;
-    // the scalar single layer and operators with a degree per level run column by
-    // column on the single-vector kernels
-    if ((r == 1 && prec <= IGE_F32) || op->view.scalar || single_vector_only(op)) {
+    // operators with a degree per level run column by column on the single-vector
+    // kernels
+    if ((r == 1 && prec <= IGE_F32) || single_vector_only(op)) {
         for (int c = 0; c < r; ++c) {
             const double2 *xc = x + (size_t)c * N;
             double2 *yc = y + (size_t)c * N;
@@ -1059,7 +1059,6 @@ int apply_impl(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind, int
         IGE_REQUIRE(op->assembled, "operator was planned, not assembled");
         IGE_REQUIRE(ptr_kind == IGE_HOST || ptr_kind == IGE_DEVICE, "bad ptr_kind");
         IGE_REQUIRE(prec >= IGE_F64 && prec <= IGE_BF16X3_ALL, "bad coupling precision");
-        IGE_REQUIRE(!op->view.scalar || prec == IGE_F64, "the scalar single layer applies in FP64 only");
         IGE_REQUIRE(!single_vector_only(op) || prec <= IGE_F32,
                     "an operator with a degree per level applies in FP64 or FP32 only");
         set_device(op->ctx);
@@ -1098,8 +1097,7 @@ int ige_op_autotune(ige_op op, int r, int prec, int *choice, int nchoice)
         IGE_REQUIRE(op && r >= 1 && (choice || nchoice == 0), "bad autotune arguments");
         IGE_REQUIRE(op->assembled, "operator was planned, not assembled");
         IGE_REQUIRE(prec >= IGE_F64 && prec <= IGE_BF16X3_ALL, "bad precision");
-        IGE_REQUIRE(!op->view.scalar && !single_vector_only(op),
-                    "autotuning covers the EFIE operator with one interpolation degree only");
+        IGE_REQUIRE(!single_vector_only(op), "autotuning covers operators with one interpolation degree only");
         set_device(op->ctx);
         const int64_t N = op->D.N;
         hipStream_t s = op->ctx->stream;
@@ -1488,7 +1486,6 @@ int ige_solve(ige_op op, int r, const ige_c64 *f, ige_c64 *x, int ptr_kind, cons
                     "bad inner precision");
         IGE_REQUIRE(!opts->refine || (std::isfinite(opts->inner_tol) && opts->inner_tol > 0.0 && opts->inner_tol < 1.0),
                     "inner_tol must be in (0, 1)");
-        IGE_REQUIRE(!op->view.scalar || !opts->refine, "the scalar single layer solves in FP64 only (no refinement)");
         IGE_REQUIRE(!single_vector_only(op) || !opts->refine || opts->inner_prec <= IGE_F32,
                     "an operator with a degree per level refines with FP32 inner solves only");
         set_device(op->ctx);

@@ -312,6 +312,14 @@ __global__ void k_m2l_reduce_g(DevOp o, int r, int c0, const double2 *tmp, doubl
             t2 = make_double2(t2.x + T[(3 + k) * Q + mm] * u[k].x, t2.y + T[(3 + k) * Q + mm] * u[k].y);
         }
         double2 *L = loc + (size_t)gc * 3 * Q * r;
+        if (o.scalar) {   // scalar: |J(x_m)| u (the target's surface element)
+            const double Fu[3] = {T[mm], T[Q + mm], T[2 * Q + mm]}, Fv[3] = {T[3 * Q + mm], T[4 * Q + mm], T[5 * Q + mm]};
+            const double J = dm::surf_elem(Fu, Fv);
+            L[((size_t)0 * Q + mm) * r + c0 + j] = make_double2(0, 0);
+            L[((size_t)1 * Q + mm) * r + c0 + j] = make_double2(0, 0);
+            L[((size_t)2 * Q + mm) * r + c0 + j] = make_double2(J * u[3].x, J * u[3].y);
+            continue;
+        }
         L[((size_t)0 * Q + mm) * r + c0 + j] = t1;
         L[((size_t)1 * Q + mm) * r + c0 + j] = t2;
         L[((size_t)2 * Q + mm) * r + c0 + j] = make_double2(-ik2 * u[3].x, -ik2 * u[3].y);

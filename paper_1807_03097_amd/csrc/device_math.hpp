@@ -13,6 +13,12 @@ __device__ inline double2 cscale(double s, double2 a) { return make_double2(s * 
 __device__ inline float2 cmul(float2 a, float2 b) { return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
 __device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 // acc + a b as four fused multiply-adds (no separate product and sum)
+// surface element |d_uF x d_vF|
+__device__ inline double surf_elem(const double Fu[3], const double Fv[3])
+{
+    const double nx = Fu[1] * Fv[2] - Fu[2] * Fv[1], ny = Fu[2] * Fv[0] - Fu[0] * Fv[2], nz = Fu[0] * Fv[1] - Fu[1] * Fv[0];
+    return sqrt(fma(nx, nx, fma(ny, ny, nz * nz)));
+}
 __device__ inline double2 cmac(double2 acc, double2 a, double2 b)
 {
     return make_double2(fma(a.x, b.x, fma(-a.y, b.y, acc.x)), fma(a.x, b.y, fma(a.y, b.x, acc.y)));

@@ -34,6 +34,7 @@ __device__ __constant__ double kInv4Pi = 0.07957747154594767;   // 1/(4 pi)
 __device__ inline double2 cmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
 __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ inline double2 cscale(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
+using dm::surf_elem;
 
 // Helmholtz kernel e^{i k r} / (4 pi r) (library sincos, correctly rounded sqrt):
 // used by the assembly kernels
@@ -227,13 +228,6 @@ __device__ inline void local_index(const DevOp &o, int l, int &a, int &t1, int &
         t2 = r / p;
         t1 = r % p;
     }
-}
-
-// surface element |d_uF x d_vF|
-__device__ inline double surf_elem(const double Fu[3], const double Fv[3])
-{
-    const double nx = Fu[1] * Fv[2] - Fu[2] * Fv[1], ny = Fu[2] * Fv[0] - Fu[0] * Fv[2], nz = Fu[0] * Fv[1] - Fu[1] * Fv[0];
-    return sqrt(fma(nx, nx, fma(ny, ny, nz * nz)));
 }
 
 // values of the local functions at element-local (x, y): Phi (3) and div, unsigned

@@ -275,6 +275,52 @@ __global__ __launch_bounds__(256) void k_p2m_b(DevOp o, int r, const double2 *xt
     }
 }
 
+// scalar single layer, kRB columns: leaf moments d = (M_p (x) M_p) c of the tensor
+// B-spline coefficients over the leaf's W x W window (fields 0 and 1 zero) and the
+// source values |J(x_m)| d at the nodes
+template <int kRB>
+__global__ __launch_bounds__(256) void k_p2m_sc_b(DevOp o, int r, const double2 *xt, double2 *mom, double2 *src)
+{
+    extern __shared__ double2 sm2[];
+    const int id = blockIdx.x;
+    const int c0 = blockIdx.y * kRB, nc = min(kRB, r - c0);
+    const int SL = o.SL, s = o.s, p = o.p, Q1 = o.Q1, Q = o.Q, RL = o.rowlen, W = s + p;
+    const int j = id / (SL * SL), rr = id % (SL * SL), k2 = rr / SL, k1 = rr % SL;
+    const int gc = (int)o.lvl_off[o.L] + id;
+    double2 *X = sm2;                  // [W (i2)][W (i1)][kRB]
+    double2 *Z = X + W * W * kRB;      // [W (i2)][Q1 (m1)][kRB]
+    for (int i = threadIdx.x; i < W * W * kRB; i += blockDim.x) {
+        const int c = i % kRB, t = i / kRB, i2 = t / W, i1 = t % W;
+        const size_t off = ((size_t)j * 2 * o.nb + (k2 * s + i2)) * o.nb + (k1 * s + i1);
+        X[i] = c < nc ? xt[(size_t)o.dof[off] * r + c0 + c] : make_double2(0, 0);
+    }
+    __syncthreads();
+    const double *Mpu = o.Mp + (size_t)k1 * Q1 * RL, *Mpv = o.Mp + (size_t)k2 * Q1 * RL;
+    for (int i = threadIdx.x; i < W * Q1 * kRB; i += blockDim.x) {
+        const int c = i % kRB, t = i / kRB, i2 = t / Q1, m1 = t % Q1;
+        double2 z = make_double2(0, 0);
+        for (int i1 = 0; i1 < W; ++i1) z = caddb(z, cscaleb(Mpu[m1 * RL + i1], X[(i2 * W + i1) * kRB + c]));
+        Z[i] = z;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < Q * kRB; i += blockDim.x) {
+        const int c = i % kRB, mm = i / kRB, m2 = mm / Q1, m1 = mm % Q1;
+        if (c >= nc) continue;
+        double2 d = make_double2(0, 0);
+        for (int i2 = 0; i2 < W; ++i2) d = caddb(d, cscaleb(Mpv[m2 * RL + i2], Z[(i2 * Q1 + m1) * kRB + c]));
+        const size_t col = c0 + c;
+        double2 *M = mom + (size_t)gc * 3 * Q * r;
+        M[((size_t)0 * Q + mm) * r + col] = make_double2(0, 0);
+        M[((size_t)1 * Q + mm) * r + col] = make_double2(0, 0);
+        M[((size_t)2 * Q + mm) * r + col] = d;
+        const double *T = o.nodeT + (size_t)gc * 6 * Q;
+        const double Fu[3] = {T[mm], T[Q + mm], T[2 * Q + mm]}, Fv[3] = {T[3 * Q + mm], T[4 * Q + mm], T[5 * Q + mm]};
+        double2 *S = src + (size_t)gc * 4 * Q * r;
+        for (int k = 0; k < 3; ++k) S[((size_t)k * Q + mm) * r + col] = make_double2(0, 0);
+        S[((size_t)3 * Q + mm) * r + col] = cscaleb(dm::surf_elem(Fu, Fv), d);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // M2M, kRB columns
 // ---------------------------------------------------------------------------
@@ -333,7 +379,12 @@ __global__ __launch_bounds__(256) void k_m2m_b(DevOp o, int lvl, int r, double2 
         double2 *Sv = src + (size_t)gc * 4 * Q * r;
         for (int k = 0; k < 3; ++k)
             Sv[((size_t)k * Q + mm) * r + col] = caddb(cscaleb(T[k * Q + mm], s1), cscaleb(T[(3 + k) * Q + mm], s2v));
-        Sv[((size_t)3 * Q + mm) * r + col] = d;
+        if (o.scalar) {   // scalar: the moments times the surface element at the node
+            const double Fu[3] = {T[mm], T[Q + mm], T[2 * Q + mm]}, Fv[3] = {T[3 * Q + mm], T[4 * Q + mm], T[5 * Q + mm]};
+            Sv[((size_t)3 * Q + mm) * r + col] = cscaleb(dm::surf_elem(Fu, Fv), d);
+        } else {
+            Sv[((size_t)3 * Q + mm) * r + col] = d;
+        }
     }
 }
 
@@ -461,6 +512,13 @@ __global__ void k_m2l_reduce_b(DevOp o, int r, const int32_t *wrk_of_tgt, const 
             t2 = caddb(t2, cscaleb(T[(3 + k) * Q + mm], u[k]));
         }
         double2 *L = loc + (size_t)gc * 3 * Q * r;
+        if (o.scalar) {   // scalar: |J(x_m)| u (the target's surface element)
+            const double Fu[3] = {T[mm], T[Q + mm], T[2 * Q + mm]}, Fv[3] = {T[3 * Q + mm], T[4 * Q + mm], T[5 * Q + mm]};
+            L[((size_t)0 * Q + mm) * r + c] = make_double2(0, 0);
+            L[((size_t)1 * Q + mm) * r + c] = make_double2(0, 0);
+            L[((size_t)2 * Q + mm) * r + c] = cscaleb(dm::surf_elem(Fu, Fv), u[3]);
+            continue;
+        }
         L[((size_t)0 * Q + mm) * r + c] = t1;
         L[((size_t)1 * Q + mm) * r + c] = t2;
         L[((size_t)2 * Q + mm) * r + c] = cscaleb(-ik2, u[3]);
@@ -557,6 +615,39 @@ __global__ __launch_bounds__(256) void k_l2p_leaf_b(DevOp o, int r, const double
     }
 }
 
+// scalar single layer, kRB columns: Y[i2][i1] = sum (M_p (x) M_p)^T t^d over the
+// leaf's W x W window (channel 0 of the leaf's result rows; channel 1 zero)
+template <int kRB>
+__global__ __launch_bounds__(256) void k_l2p_leaf_sc_b(DevOp o, int r, const double2 *loc, double2 *ybuf)
+{
+    extern __shared__ double2 sm2[];
+    const int id = blockIdx.x;
+    const int c0 = blockIdx.y * kRB, nc = min(kRB, r - c0);
+    const int SL = o.SL, s = o.s, p = o.p, Q1 = o.Q1, Q = o.Q, RL = o.rowlen, W = s + p;
+    const int rr = id % (SL * SL), k2 = rr / SL, k1 = rr % SL;
+    const int gc = (int)o.lvl_off[o.L] + id;
+    const double2 *t = loc + ((size_t)gc * 3 + 2) * Q * r;
+    const double *Mpu = o.Mp + (size_t)k1 * Q1 * RL, *Mpv = o.Mp + (size_t)k2 * Q1 * RL;
+    double2 *Wm = sm2;   // [Q1 (m2)][W (i1)][kRB]
+    for (int i = threadIdx.x; i < Q1 * W * kRB; i += blockDim.x) {
+        const int c = i % kRB, tt = i / kRB, m2 = tt / W, i1 = tt % W;
+        double2 a = make_double2(0, 0);
+        if (c < nc)
+            for (int m1 = 0; m1 < Q1; ++m1) a = caddb(a, cscaleb(Mpu[m1 * RL + i1], t[(size_t)(m2 * Q1 + m1) * r + c0 + c]));
+        Wm[i] = a;
+    }
+    __syncthreads();
+    double2 *Y = ybuf + (size_t)id * 2 * RL * RL * r;
+    for (int i = threadIdx.x; i < 2 * RL * RL * kRB; i += blockDim.x) {
+        const int c = i % kRB, tt = i / kRB, ch = tt / (RL * RL), rem = tt % (RL * RL), i2 = rem / RL, i1 = rem % RL;
+        if (c >= nc) continue;
+        double2 v = make_double2(0, 0);
+        if (ch == 0 && i2 < W && i1 < W)
+            for (int m2 = 0; m2 < Q1; ++m2) v = caddb(v, cscaleb(Mpv[m2 * RL + i2], Wm[(m2 * W + i1) * kRB + c]));
+        Y[(size_t)tt * r + c0 + c] = v;
+    }
+}
+
 __global__ void k_l2p_gather_b(DevOp o, int r, const double2 *ybuf, double2 *yt)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -570,7 +661,7 @@ __global__ void k_l2p_gather_b(DevOp o, int r, const double2 *ybuf, double2 *yt)
         if (j < 0) continue;
         const int a = in[1], i1 = in[2], i2 = in[3];
         const double sg = (double)in[4];
-        const int du = (a == 0) ? p : p - 1, dv = (a == 0) ? p - 1 : p;
+        const int du = (a == 0) ? p : p - 1, dv = (a == 0 && !o.scalar) ? p - 1 : p;
         const int k1b = max(0, i1 - du) / s, k1e = min(n - 1, i1) / s;
         const int k2b = max(0, i2 - dv) / s, k2e = min(n - 1, i2) / s;
         for (int k2 = k2b; k2 <= k2e; ++k2)
@@ -645,7 +736,12 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
     if (far) {
         const int nleaf = o.P * o.SL * o.SL;
         const size_t w1a = o.s + o.p;
-        {
+        if (o.scalar) {
+            const size_t per = sizeof(double2) * (w1a * w1a + w1a * o.Q1);
+            const int rb = pick_rb(per);
+            IGE_RB_SWITCH(rb, k_p2m_sc_b, dim3(nleaf, chunks(rb)), dim3(256), per * rb, s, o, r, xt, op->d_bmom.p,
+                          op->d_bsrc.p);
+        } else {
             const size_t per = sizeof(double2) * (2 * w1a * w1a + 3 * w1a * o.Q1);
             const int rb = pick_rb(per);
             IGE_RB_SWITCH(rb, k_p2m_b, dim3(nleaf, chunks(rb)), dim3(256), per * rb, s, o, r, xt, op->d_bmom.p,
@@ -719,7 +815,12 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
             }
         }
         mark(5);
-        {
+        if (o.scalar) {
+            const size_t per = sizeof(double2) * (size_t)o.Q1 * w1a;
+            const int rb = pick_rb(per);
+            IGE_RB_SWITCH(rb, k_l2p_leaf_sc_b, dim3(nleaf, chunks(rb)), dim3(256), per * rb, s, o, r, op->d_bloc.p,
+                          op->d_bybuf.p);
+        } else {
             const size_t per = sizeof(double2) * 3 * (size_t)o.Q1 * o.rowlen;
             const int rb = pick_rb(per);
             IGE_RB_SWITCH(rb, k_l2p_leaf_b, dim3(nleaf, chunks(rb)), dim3(256), per * rb, s, o, r, op->d_bloc.p,
