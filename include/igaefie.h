@@ -125,9 +125,11 @@ int ige_geom_destroy(ige_geom geom);
  *                 the accuracy at high kappa without refining the partition; a rule is
  *                 q_l = min(15, max(q, ceil(kappa diam_l / 2) + 5)) on the levels with far
  *                 blocks, with diam_l from ige_op_info of the planned operator.  With
- *                 degrees that differ between levels the operator applies in FP64 or
- *                 FP32 (ige_apply_prec IGE_F32) only, column by column; stored coupling
- *                 blocks, the matrix-core precisions and autotuning refuse it. */
+ *                 degrees that differ between levels (and with one degree above 10) the
+ *                 operator couples on the generated FP64/FP32 kernels, one and many
+ *                 columns, each level's blocks of its own size in one launch: the BF16
+ *                 precisions (apply, autotuning, refinement inner solves) and stored
+ *                 coupling blocks refuse it with IGE_EINVAL. */
 enum { IGE_OP_EFIE = 0, IGE_OP_SCALAR = 1 };
 typedef struct {
     int p, level;

@@ -574,6 +574,7 @@ ige_op ige::assemble_on(ige_ctx ctx, const ige_geom_s *geom, const ige_params &p
             op->overlap = true;
             if (const char *e = std::getenv("IGE_OVERLAP")) op->overlap = std::atoi(e) != 0;
             if (const char *e = std::getenv("IGE_NEAR_FIRST")) op->near_first = std::atoi(e) != 0;
+            op->lfar = T.far.empty() ? T.L + 1 : T.far.front()[0];   // far pairs sorted by level
             std::vector<int32_t> partner;
             op->wrk_of_tgt.assign(op->NC + 1, 0);
             {
@@ -718,6 +719,9 @@ ige_op ige::assemble_on(ige_ctx ctx, const ige_geom_s *geom, const ige_params &p
             op->d_wrk_of_tgt.upload(op->wrk_of_tgt, s);
             op->d_mom.alloc((size_t)op->NC * 3 * v.Q);
             op->d_src.alloc((size_t)op->NC * 4 * v.Q);
+            // source fields of the levels above the coarsest far level are never written
+            // (the upward pass stops there) but the matrix-core coupling stages them
+            IGE_HIP(hipMemsetAsync(op->d_src.p, 0, op->d_src.bytes(), s));
             op->d_loc.alloc((size_t)op->NC * 3 * v.Q);
             op->d_ybuf.alloc((size_t)D.P * v.SL * v.SL * 2 * F.rowlen * F.rowlen);
             op->d_part.alloc(std::max<size_t>(1, op->work.size()) * 4 * v.Q);
@@ -928,6 +932,7 @@ void ensure_batched(ige_op op, int r)
     const size_t Q = v.Q;
     op->d_bmom.alloc((size_t)op->NC * 3 * Q * r);
     op->d_bsrc.alloc((size_t)op->NC * 4 * Q * r);
+    IGE_HIP(hipMemsetAsync(op->d_bsrc.p, 0, op->d_bsrc.bytes(), op->ctx->stream));   // as d_src
     op->d_bloc.alloc((size_t)op->NC * 3 * Q * r);
     op->d_bpart.alloc(std::max<size_t>(1, op->work.size()) * 4 * Q * r);
     op->d_bybuf.alloc((size_t)v.P * v.SL * v.SL * 2 * v.rowlen * v.rowlen * r);
@@ -1009,9 +1014,10 @@ void run_graph(ige_op op, ApplyGraph *g, int r, int prec, const std::function<vo
     IGE_HIP(hipGraphLaunch(g->exec, s));
 }
 
-// degrees that differ between levels (or beyond 11) are implemented by the
-// single-vector FP64/FP32 kernels only
-bool single_vector_only(const ige_op_s *op) { return op->F.varq || op->F.q > 11; }
+// the matrix-core couplings (BF16, and FP64 on the matrix cores) hold one padded block
+// size of at most 128 nodes: one degree on all levels, at most 10; other operators
+// couple on the generated FP64/FP32 kernels, whose blocks may differ per level
+bool mx_coupling_ok(const ige_op_s *op) { return !op->F.varq && op->F.q <= 10; }
 
 // y = A x for r device columns ([r][N]) in the given precision; with g, the operator
 // body runs as a captured graph (not while profiling)
@@ -1020,9 +1026,7 @@ void apply_dev(ige_op op, int r, const double2 *x, double2 *y, int prec, ApplyGr
     const bool graph = g && !op->profiling && graphs_enabled();
     hipStream_t s = op->ctx->stream;
     const int64_t N = op->D.N;
-    // operators with a degree per level run column by column on the single-vector
-    // kernels
-    if ((r == 1 && prec <= IGE_F32) || single_vector_only(op)) {
+    if (r == 1 && prec <= IGE_F32) {
         for (int c = 0; c < r; ++c) {
             const double2 *xc = x + (size_t)c * N;
             double2 *yc = y + (size_t)c * N;
@@ -1059,8 +1063,8 @@ int apply_impl(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind, int
         IGE_REQUIRE(op->assembled, "operator was planned, not assembled");
         IGE_REQUIRE(ptr_kind == IGE_HOST || ptr_kind == IGE_DEVICE, "bad ptr_kind");
         IGE_REQUIRE(prec >= IGE_F64 && prec <= IGE_BF16X3_ALL, "bad coupling precision");
-        IGE_REQUIRE(!single_vector_only(op) || prec <= IGE_F32,
-                    "an operator with a degree per level applies in FP64 or FP32 only");
+        IGE_REQUIRE(prec <= IGE_F32 || mx_coupling_ok(op),
+                    "the BF16 couplings need one interpolation degree on all levels, at most 10");
         set_device(op->ctx);
         const int64_t N = op->D.N;
         hipStream_t s = op->ctx->stream;
@@ -1097,7 +1101,8 @@ int ige_op_autotune(ige_op op, int r, int prec, int *choice, int nchoice)
         IGE_REQUIRE(op && r >= 1 && (choice || nchoice == 0), "bad autotune arguments");
         IGE_REQUIRE(op->assembled, "operator was planned, not assembled");
         IGE_REQUIRE(prec >= IGE_F64 && prec <= IGE_BF16X3_ALL, "bad precision");
-        IGE_REQUIRE(!single_vector_only(op), "autotuning covers operators with one interpolation degree only");
+        IGE_REQUIRE(prec <= IGE_F32 || mx_coupling_ok(op),
+                    "the BF16 couplings need one interpolation degree on all levels, at most 10");
         set_device(op->ctx);
         const int64_t N = op->D.N;
         hipStream_t s = op->ctx->stream;
@@ -1486,8 +1491,8 @@ int ige_solve(ige_op op, int r, const ige_c64 *f, ige_c64 *x, int ptr_kind, cons
                     "bad inner precision");
         IGE_REQUIRE(!opts->refine || (std::isfinite(opts->inner_tol) && opts->inner_tol > 0.0 && opts->inner_tol < 1.0),
                     "inner_tol must be in (0, 1)");
-        IGE_REQUIRE(!single_vector_only(op) || !opts->refine || opts->inner_prec <= IGE_F32,
-                    "an operator with a degree per level refines with FP32 inner solves only");
+        IGE_REQUIRE(!opts->refine || opts->inner_prec <= IGE_F32 || mx_coupling_ok(op),
+                    "the BF16 couplings need one interpolation degree on all levels, at most 10");
         set_device(op->ctx);
         const auto t0 = std::chrono::steady_clock::now();
         const int64_t N = op->D.N;

@@ -967,7 +967,7 @@ void ensure_coupling_f64(ige_op op)
 
 bool m2l_f64mx_ok(ige_op op, int r)
 {
-    if (r < 8 || op->mwork.empty() || op->f64mx_off) return false;
+    if (r < 8 || op->mwork.empty() || op->f64mx_off || op->view.varq) return false;
     const int Qp = coupling_qp(op->view.Q);
     if (Qp > 128) return false;
     if (op->gd_fit < 0) {   // decided once, at the first eligible apply (never under capture)

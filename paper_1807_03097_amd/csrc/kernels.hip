@@ -1770,14 +1770,15 @@ void launch_m2m(ige_op op)
     const DevOp &o = op->view;
     const size_t shm = sizeof(double2) * 24 * o.Q;
     lds_attr_once(reinterpret_cast<const void *>(&k_m2m), shm);
-    for (int lvl = o.L - 1; lvl >= 0; --lvl) {
+    // parents down to the coarsest level with far pairs (coarser moments are unused)
+    for (int lvl = o.L - 1; lvl >= std::max(0, op->lfar); --lvl) {
         const int ncl = o.P << (2 * lvl);
         hipLaunchKernelGGL(k_m2m, dim3(ncl), dim3(256), shm, lstream(op), o, lvl, op->d_mom.p, op->d_src.p);
         IGE_LAUNCH_CHECK();
     }
     if (!o.varq) return;
     // levels of a smaller degree: source fields from the restricted moments
-    for (int lvl = 0; lvl <= o.L; ++lvl) {
+    for (int lvl = std::max(0, op->lfar); lvl <= o.L; ++lvl) {
         const int Q1l = o.ql[lvl] + 1;
         if (Q1l == o.Q1) continue;
         const size_t sh = sizeof(double2) * (3 * (size_t)o.Q + 3 * (size_t)o.Q1 * Q1l);
@@ -1844,7 +1845,7 @@ void launch_m2l_reduce(ige_op op)
     IGE_LAUNCH_CHECK();
     if (!o.varq) return;
     // levels of a smaller degree: local expansions back to the degree-q nodes
-    for (int lvl = 0; lvl <= o.L; ++lvl) {
+    for (int lvl = std::max(0, op->lfar); lvl <= o.L; ++lvl) {
         const int Q1l = o.ql[lvl] + 1;
         if (Q1l == o.Q1) continue;
         const size_t sh = sizeof(double2) * (3 * (size_t)Q1l * Q1l + 3 * (size_t)Q1l * o.Q1);
@@ -1857,7 +1858,8 @@ void launch_l2l(ige_op op)
 {
     const DevOp &o = op->view;
     const size_t shm = sizeof(double2) * 3 * o.Q;
-    for (int lvl = 1; lvl <= o.L; ++lvl) {
+    // children below the coarsest level with far pairs (the expansions above it are zero)
+    for (int lvl = std::max(1, op->lfar + 1); lvl <= o.L; ++lvl) {
         const int ncl = o.P << (2 * lvl);
         hipLaunchKernelGGL(k_l2l, dim3(ncl), dim3(256), shm, lstream(op), o, lvl, op->d_loc.p);
         IGE_LAUNCH_CHECK();

@@ -405,7 +405,12 @@ __global__ __launch_bounds__(kM2LThreadsB) void k_m2l_b(DevOp o, int r, const M2
     extern __shared__ double smd[];
     const M2LWork wk = work[blockIdx.x];
     const int c0 = blockIdx.y * kRB, nc = min(kRB, r - c0);
-    const int Q = o.Q;
+    // nodes of the target's level (the partners are on the same level); the cluster
+    // arrays keep the stride Qs of the largest degree
+    const int Qs = o.Q;
+    int lvw = 0;
+    while (lvw < o.L && wk.tgt >= o.lvl_off[lvw + 1]) ++lvw;
+    const int Q = (o.ql[lvw] + 1) * (o.ql[lvw] + 1);
     const int TPG = (Q + kNTB - 1) / kNTB;
     const int S = max(1, min(kM2LThreadsB / TPG, Q));
     const int SP = (Q + S - 1) / S;
@@ -419,7 +424,7 @@ __global__ __launch_bounds__(kM2LThreadsB) void k_m2l_b(DevOp o, int r, const M2
     if constexpr (sizeof(T) == 8)
         for (int i = tid; i < 256; i += kM2LThreadsB) sTab[i] = o.sctab[i];   // first use after a barrier
     const T kap = (T)o.kappa;
-    const double *Xt = o.nodeX + (size_t)wk.tgt * 3 * Q;
+    const double *Xt = o.nodeX + (size_t)wk.tgt * 3 * Qs;
     T xt[kNTB][3];
     bool val[kNTB];
 #pragma unroll
@@ -428,8 +433,8 @@ __global__ __launch_bounds__(kM2LThreadsB) void k_m2l_b(DevOp o, int r, const M2
         val[t] = active && mm < Q;
         const int mc = val[t] ? mm : 0;
         xt[t][0] = (T)Xt[mc];
-        xt[t][1] = (T)Xt[Q + mc];
-        xt[t][2] = (T)Xt[2 * Q + mc];
+        xt[t][1] = (T)Xt[Qs + mc];
+        xt[t][2] = (T)Xt[2 * Qs + mc];
     }
     C acc[kNTB][4][kRB];
 #pragma unroll
@@ -442,12 +447,12 @@ __global__ __launch_bounds__(kM2LThreadsB) void k_m2l_b(DevOp o, int r, const M2
     for (int kp = wk.beg; kp < wk.end; ++kp) {
         const int sc = partner[kp];
         __syncthreads();
-        const double *Xs = o.nodeX + (size_t)sc * 3 * Q;
-        const double2 *Vs = src + (size_t)sc * 4 * Q * r;
-        for (int i = tid; i < 3 * Q; i += kM2LThreadsB) sX[i] = (T)Xs[i];
+        const double *Xs = o.nodeX + (size_t)sc * 3 * Qs;
+        const double2 *Vs = src + (size_t)sc * 4 * Qs * r;
+        for (int i = tid; i < 3 * Q; i += kM2LThreadsB) sX[i] = (T)Xs[(i / Q) * Qs + i % Q];
         for (int i = tid; i < 4 * Q * kRB; i += kM2LThreadsB) {
             const int c = i % kRB, fm = i / kRB;
-            sV[i] = c < nc ? dm::to_c(Vs[(size_t)fm * r + c0 + c], T(0)) : C{0, 0};
+            sV[i] = c < nc ? dm::to_c(Vs[((size_t)(fm / Q) * Qs + fm % Q) * r + c0 + c], T(0)) : C{0, 0};
         }
         __syncthreads();
         if (active) {
@@ -486,7 +491,7 @@ __global__ __launch_bounds__(kM2LThreadsB) void k_m2l_b(DevOp o, int r, const M2
             if (c >= nc) continue;
             double2 v = make_double2(0, 0);
             for (int q2 = 0; q2 < S; ++q2) v = caddb(v, red[((size_t)q2 * Q + mm) * kRB + c]);
-            part[(((size_t)blockIdx.x * 4 + f) * Q + mm) * r + c0 + c] = v;
+            part[(((size_t)blockIdx.x * 4 + f) * Qs + mm) * r + c0 + c] = v;
         }
     }
 }
@@ -497,31 +502,117 @@ __device__ inline double2 to_d2(float2 v) { return make_double2(v.x, v.y); }
 template <typename PT>
 __global__ void k_m2l_reduce_b(DevOp o, int r, const int32_t *wrk_of_tgt, const PT *part, double2 *loc)
 {
-    const int gc = blockIdx.x, Q = o.Q;
+    const int gc = blockIdx.x, Qs = o.Q;
+    int lvl = 0;
+    while (lvl < o.L && gc >= o.lvl_off[lvl + 1]) ++lvl;
+    const int Q = (o.ql[lvl] + 1) * (o.ql[lvl] + 1);   // nodes of the level (stride Qs)
     const int b = wrk_of_tgt[gc], e = wrk_of_tgt[gc + 1];
     const double ik2 = 1.0 / (o.kappa * o.kappa);
     for (int t = threadIdx.x; t < Q * r; t += blockDim.x) {
         const int mm = t / r, c = t % r;
         double2 u[4] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
         for (int w = b; w < e; ++w)
-            for (int k = 0; k < 4; ++k) u[k] = caddb(u[k], to_d2(part[(((size_t)w * 4 + k) * Q + mm) * r + c]));
-        const double *T = o.nodeT + (size_t)gc * 6 * Q;
+            for (int k = 0; k < 4; ++k) u[k] = caddb(u[k], to_d2(part[(((size_t)w * 4 + k) * Qs + mm) * r + c]));
+        const double *T = o.nodeT + (size_t)gc * 6 * Qs;
         double2 t1 = make_double2(0, 0), t2 = make_double2(0, 0);
         for (int k = 0; k < 3; ++k) {
-            t1 = caddb(t1, cscaleb(T[k * Q + mm], u[k]));
-            t2 = caddb(t2, cscaleb(T[(3 + k) * Q + mm], u[k]));
+            t1 = caddb(t1, cscaleb(T[k * Qs + mm], u[k]));
+            t2 = caddb(t2, cscaleb(T[(3 + k) * Qs + mm], u[k]));
         }
-        double2 *L = loc + (size_t)gc * 3 * Q * r;
+        double2 *L = loc + (size_t)gc * 3 * Qs * r;
         if (o.scalar) {   // scalar: |J(x_m)| u (the target's surface element)
-            const double Fu[3] = {T[mm], T[Q + mm], T[2 * Q + mm]}, Fv[3] = {T[3 * Q + mm], T[4 * Q + mm], T[5 * Q + mm]};
-            L[((size_t)0 * Q + mm) * r + c] = make_double2(0, 0);
-            L[((size_t)1 * Q + mm) * r + c] = make_double2(0, 0);
-            L[((size_t)2 * Q + mm) * r + c] = cscaleb(dm::surf_elem(Fu, Fv), u[3]);
+            const double Fu[3] = {T[mm], T[Qs + mm], T[2 * Qs + mm]}, Fv[3] = {T[3 * Qs + mm], T[4 * Qs + mm], T[5 * Qs + mm]};
+            L[((size_t)0 * Qs + mm) * r + c] = make_double2(0, 0);
+            L[((size_t)1 * Qs + mm) * r + c] = make_double2(0, 0);
+            L[((size_t)2 * Qs + mm) * r + c] = cscaleb(dm::surf_elem(Fu, Fv), u[3]);
             continue;
         }
-        L[((size_t)0 * Q + mm) * r + c] = t1;
-        L[((size_t)1 * Q + mm) * r + c] = t2;
-        L[((size_t)2 * Q + mm) * r + c] = cscaleb(-ik2, u[3]);
+        L[((size_t)0 * Qs + mm) * r + c] = t1;
+        L[((size_t)1 * Qs + mm) * r + c] = t2;
+        L[((size_t)2 * Qs + mm) * r + c] = cscaleb(-ik2, u[3]);
+    }
+}
+
+// Levels of a smaller degree q_l, kRB columns: source fields at the level's nodes from
+// the exact restriction m_l = (R_l (x) R_l)^T m of the degree-q moments
+// (R_l[n][m] = L^{q_l}_m(x^q_n)), and local expansions back through R_l (x) R_l.
+template <int kRB>
+__global__ __launch_bounds__(256) void k_restrict_b(DevOp o, int lvl, int r, const double2 *mom, double2 *src)
+{
+    extern __shared__ double2 sm2[];
+    const int gc = (int)o.lvl_off[lvl] + blockIdx.x;
+    const int c0 = blockIdx.y * kRB, nc = min(kRB, r - c0);
+    const int Q1h = o.Q1, Qs = o.Q, Q1l = o.ql[lvl] + 1, Ql = Q1l * Q1l;
+    const double *R = o.Rl + (size_t)lvl * Q1h * Q1h;   // [n][m], m < Q1l
+    double2 *M = sm2;                       // [3][Qs][kRB]
+    double2 *Z = M + 3 * Qs * kRB;          // [3][Q1h (n2)][Q1l (m1)][kRB]
+    const double2 *Mg = mom + (size_t)gc * 3 * Qs * r;
+    for (int i = threadIdx.x; i < 3 * Qs * kRB; i += blockDim.x) {
+        const int c = i % kRB, t = i / kRB;
+        M[i] = c < nc ? Mg[(size_t)t * r + c0 + c] : make_double2(0, 0);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 3 * Q1h * Q1l * kRB; i += blockDim.x) {
+        const int c = i % kRB, t = i / kRB, f = t / (Q1h * Q1l), rm = t % (Q1h * Q1l), n2 = rm / Q1l, m1 = rm % Q1l;
+        double2 z = make_double2(0, 0);
+        for (int n1 = 0; n1 < Q1h; ++n1) z = caddb(z, cscaleb(R[n1 * Q1h + m1], M[(f * Qs + n2 * Q1h + n1) * kRB + c]));
+        Z[i] = z;
+    }
+    __syncthreads();
+    const double *T = o.nodeT + (size_t)gc * 6 * Qs;
+    double2 *Sv = src + (size_t)gc * 4 * Qs * r;
+    for (int i = threadIdx.x; i < Ql * kRB; i += blockDim.x) {
+        const int c = i % kRB, mm = i / kRB, m2 = mm / Q1l, m1 = mm % Q1l;
+        if (c >= nc) continue;
+        double2 sf[3];
+        for (int f = 0; f < 3; ++f) {
+            double2 v = make_double2(0, 0);
+            for (int n2 = 0; n2 < Q1h; ++n2)
+                v = caddb(v, cscaleb(R[n2 * Q1h + m2], Z[((f * Q1h + n2) * Q1l + m1) * kRB + c]));
+            sf[f] = v;
+        }
+        const double Fu[3] = {T[mm], T[Qs + mm], T[2 * Qs + mm]}, Fv[3] = {T[3 * Qs + mm], T[4 * Qs + mm], T[5 * Qs + mm]};
+        const size_t col = c0 + c;
+        if (o.scalar) {
+            for (int k = 0; k < 3; ++k) Sv[((size_t)k * Qs + mm) * r + col] = make_double2(0, 0);
+            Sv[((size_t)3 * Qs + mm) * r + col] = cscaleb(dm::surf_elem(Fu, Fv), sf[2]);
+        } else {
+            for (int k = 0; k < 3; ++k)
+                Sv[((size_t)k * Qs + mm) * r + col] = caddb(cscaleb(Fu[k], sf[0]), cscaleb(Fv[k], sf[1]));
+            Sv[((size_t)3 * Qs + mm) * r + col] = sf[2];
+        }
+    }
+}
+
+template <int kRB>
+__global__ __launch_bounds__(256) void k_lift_b(DevOp o, int lvl, int r, double2 *loc)
+{
+    extern __shared__ double2 sm2[];
+    const int gc = (int)o.lvl_off[lvl] + blockIdx.x;
+    const int c0 = blockIdx.y * kRB, nc = min(kRB, r - c0);
+    const int Q1h = o.Q1, Qs = o.Q, Q1l = o.ql[lvl] + 1, Ql = Q1l * Q1l;
+    const double *R = o.Rl + (size_t)lvl * Q1h * Q1h;
+    double2 *A = sm2;                       // [3][Ql][kRB]
+    double2 *Y = A + 3 * Ql * kRB;          // [3][Q1l (m2)][Q1h (n1)][kRB]
+    double2 *Lc = loc + (size_t)gc * 3 * Qs * r;
+    for (int i = threadIdx.x; i < 3 * Ql * kRB; i += blockDim.x) {
+        const int c = i % kRB, t = i / kRB;
+        A[i] = c < nc ? Lc[((size_t)(t / Ql) * Qs + t % Ql) * r + c0 + c] : make_double2(0, 0);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 3 * Q1l * Q1h * kRB; i += blockDim.x) {
+        const int c = i % kRB, t = i / kRB, f = t / (Q1l * Q1h), rm = t % (Q1l * Q1h), m2 = rm / Q1h, n1 = rm % Q1h;
+        double2 y = make_double2(0, 0);
+        for (int m1 = 0; m1 < Q1l; ++m1) y = caddb(y, cscaleb(R[n1 * Q1h + m1], A[(f * Ql + m2 * Q1l + m1) * kRB + c]));
+        Y[i] = y;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 3 * Qs * kRB; i += blockDim.x) {
+        const int c = i % kRB, t = i / kRB, f = t / Qs, nn = t % Qs, n2 = nn / Q1h, n1 = nn % Q1h;
+        if (c >= nc) continue;
+        double2 v = make_double2(0, 0);
+        for (int m2 = 0; m2 < Q1l; ++m2) v = caddb(v, cscaleb(R[n2 * Q1h + m2], Y[((f * Q1l + m2) * Q1h + n1) * kRB + c]));
+        Lc[(size_t)t * r + c0 + c] = v;
     }
 }
 
@@ -751,11 +842,20 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
         {
             const size_t per = sizeof(double2) * 9 * o.Q;   // accumulators, intermediate, staged child (3 fields each)
             const int rb = pick_rb(per);
-            for (int lvl = o.L - 1; lvl >= 0; --lvl) {
+            for (int lvl = o.L - 1; lvl >= std::max(0, op->lfar); --lvl) {   // as the single-column pass
                 IGE_RB_SWITCH(rb, k_m2m_b, dim3(o.P << (2 * lvl), chunks(rb)), dim3(256), per * rb, s, o, lvl, r,
                               op->d_bmom.p, op->d_bsrc.p);
             }
         }
+        if (o.varq)   // levels of a smaller degree: source fields from the restricted moments
+            for (int lvl = std::max(0, op->lfar); lvl <= o.L; ++lvl) {
+                const size_t Q1l = o.ql[lvl] + 1;
+                if ((int)Q1l == o.Q1) continue;
+                const size_t per = sizeof(double2) * (3 * (size_t)o.Q + 3 * (size_t)o.Q1 * Q1l);
+                const int rb = pick_rb(per);
+                IGE_RB_SWITCH(rb, k_restrict_b, dim3(o.P << (2 * lvl), chunks(rb)), dim3(256), per * rb, s, o, lvl, r,
+                              op->d_bmom.p, op->d_bsrc.p);
+            }
         mark(2);
         if (prec == IGE_BF16 || prec == IGE_BF16X3 || prec == IGE_BF16X3_ALL) {
             m2l_bf16(op, r, prec == IGE_BF16 ? 1 : 3, op->d_bsrc.p, s, ev ? ev[12] : nullptr);
@@ -776,10 +876,15 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
         } else {
             mark(12);
             {
-                const int TPG = (o.Q + kNTB - 1) / kNTB;
-                const int S = std::max(1, std::min(kM2LThreadsB / TPG, o.Q));
+                // shared memory for the largest of the levels' node counts
+                size_t per = 0;
+                for (int lvl = std::max(0, op->lfar); lvl <= o.L; ++lvl) {
+                    const int Ql = (o.ql[lvl] + 1) * (o.ql[lvl] + 1);
+                    const int TPG = (Ql + kNTB - 1) / kNTB;
+                    const int S = std::max(1, std::min(kM2LThreadsB / TPG, Ql));
+                    per = std::max(per, std::max(sizeof(double2) * 4 * Ql, sizeof(double2) * (size_t)S * Ql));
+                }
                 const size_t fixed = sizeof(double) * (3 * o.Q + 1);
-                const size_t per = std::max(sizeof(double2) * 4 * o.Q, sizeof(double2) * (size_t)S * o.Q);
                 // registers: 3 targets x 4 fields x rb columns; a tuned value may only lower it
                 const int rbmax = std::min(4, pick_rb(per, fixed, kLdsMax));
                 const int rb = std::min(rbmax, tune_get(op, kTuneM2lRb, r, prec, rbmax));
@@ -805,11 +910,20 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
                                op->d_bloc.p);
             IGE_HIP(hipGetLastError());
         }
+        if (o.varq)   // levels of a smaller degree: local expansions back to the degree-q nodes
+            for (int lvl = std::max(0, op->lfar); lvl <= o.L; ++lvl) {
+                const size_t Q1l = o.ql[lvl] + 1;
+                if ((int)Q1l == o.Q1) continue;
+                const size_t per = sizeof(double2) * (3 * Q1l * Q1l + 3 * Q1l * (size_t)o.Q1);
+                const int rb = pick_rb(per);
+                IGE_RB_SWITCH(rb, k_lift_b, dim3(o.P << (2 * lvl), chunks(rb)), dim3(256), per * rb, s, o, lvl, r,
+                              op->d_bloc.p);
+            }
         mark(4);
         {
             const size_t per = sizeof(double2) * 6 * o.Q;   // intermediate and staged parent
             const int rb = pick_rb(per);
-            for (int lvl = 1; lvl <= o.L; ++lvl) {
+            for (int lvl = std::max(1, op->lfar + 1); lvl <= o.L; ++lvl) {
                 IGE_RB_SWITCH(rb, k_l2l_b, dim3(o.P << (2 * lvl), chunks(rb)), dim3(256), per * rb, s, o, lvl, r,
                               op->d_bloc.p);
             }

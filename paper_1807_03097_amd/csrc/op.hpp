@@ -122,6 +122,9 @@ struct ige_op_s {
     hipStream_t gstream = nullptr;     // stream on which apply graphs are captured
     std::map<long long, int> tune;     // autotuned tile choices: (knob, columns, precision) -> value
     bool overlap = true;               // near field concurrent with the far field
+    // coarsest level with far pairs (L + 1 if none): the upward pass stops there and
+    // the downward pass starts there, since coarser moments and expansions are unused
+    int lfar = 0;
     bool near_first = false;           // overlap: near field beside the upward pass only, then the coupling alone
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int64_t prof_count = 0;

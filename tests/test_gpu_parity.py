@@ -758,8 +758,10 @@ LQ_CASES = [
 def test_level_degrees_match_oracle(oracle_mod, ctx, case):
     """A degree per cluster-tree level: the restriction of the largest degree's moments
     to each level's nodes and the lift of its local expansions give the oracle's
-    operator (moments taken directly per level) to 1e-12; several columns are applied
-    column by column (bitwise the single-column result) and FP32 stays within 1e-5."""
+    operator (moments taken directly per level) to 1e-12; several columns (3, 11 and 70:
+    the many-column kernels with coupling blocks of each level's size in one launch, a
+    ragged column chunk) equal single columns to 1e-13 and the oracle to 1e-12; FP32
+    stays within 1e-5 on one and on several columns."""
     from paper_1807_03097_amd import binding as B
     name, p, m, kappa, eta, d, ql, scalar = case
     _say(f"case {case}")
@@ -778,17 +780,29 @@ def test_level_degrees_match_oracle(oracle_mod, ctx, case):
     assert err <= TOL
     X = np.stack([x, W.random_coeffs(op.N, 1), W.random_coeffs(op.N, 2)])
     Y = op.apply(X)
-    assert np.array_equal(Y[0], y) and _rel(Y[2], o.fmm_apply(X[2], ql, eta, d)) <= TOL
-    if not scalar:
-        e32 = _rel(op.apply(x, prec=B.IGE_F32), yo)
-        assert 1e-12 < e32 <= 1e-5
+    assert _rel(Y[0], y) <= 1e-13 and _rel(Y[2], o.fmm_apply(X[2], ql, eta, d)) <= TOL
+    X70 = np.stack([x] + [W.random_coeffs(op.N, 10 + c) for c in range(69)])
+    y69 = op.apply(X70[69].copy())
+    for nc in (11, 70):
+        Y = op.apply(X70[:nc].copy())
+        e1 = max(_rel(Y[0], y), _rel(Y[nc - 1], op.apply(X70[nc - 1].copy())))
+        _say(f"  {nc} columns: vs single columns {e1:.1e}")
+        assert e1 <= 1e-13 and _rel(Y[0], yo) <= TOL
+    assert _rel(Y[69], y69) <= 1e-13
+    e32 = _rel(op.apply(x, prec=B.IGE_F32), yo)
+    Y32 = op.apply(X70[:11].copy(), prec=B.IGE_F32)
+    e32b = max(_rel(Y32[c], op.apply(X70[c].copy())) for c in (0, 5, 10))
+    _say(f"  FP32: one column {e32:.1e}, 11 columns {e32b:.1e}")
+    assert 1e-12 < e32 <= 1e-5 and e32b <= 1e-5
     op.close()
 
 
 def test_level_degrees_refusals_and_refined_solve(oracle_mod, ctx):
-    """Operators with a degree per level refuse the matrix-core precisions, stored
-    coupling blocks and autotuning; FP64 refinement around FP32 inner solves reaches
-    the tolerance on the FP64 operator."""
+    """Operators with a degree per level (and those of one degree above 10) refuse the
+    BF16 couplings (applies, autotuning, refinement inner solves) and stored coupling
+    blocks; FP64 autotuning keeps the results to 1e-13; FP64 refinement around FP32
+    inner solves of one and of three waves reaches the tolerance on the FP64
+    operator."""
     from paper_1807_03097_amd import binding as B
     pats = W.cube_sphere()
     geom = B.Geometry(ctx, pats)
@@ -799,12 +813,24 @@ def test_level_degrees_refusals_and_refined_solve(oracle_mod, ctx):
         B.Operator(geom, 2, 4, 8.0, 8, 1.0, 5, 5, 1, q_level=[8, 16])
     op = B.Operator(geom, 2, 4, 8.0, 8, 1.0, 5, 5, 1, q_level=ql)
     x = W.random_coeffs(op.N, 0)
-    for prec in (B.IGE_BF16, B.IGE_BF16X3, B.IGE_BF16X3_ALL):
+    q11 = B.Operator(geom, 2, 3, 8.0, 11, 1.0, 5, 5, 1)
+    for o_ in (op, q11):
+        for prec in (B.IGE_BF16, B.IGE_BF16X3, B.IGE_BF16X3_ALL):
+            with pytest.raises(B.IgeError) as e:
+                o_.apply(W.random_coeffs(o_.N, 0), prec=prec)
+            assert e.value.code == B.IGE_EINVAL
         with pytest.raises(B.IgeError):
-            op.apply(x, prec=prec)
-    with pytest.raises(B.IgeError):
-        op.autotune(2)
-    f = op.rhs_plane_wave([[0.0, 0.0, 1.0]], [[1.0, 0.0, 0.0]])[0]
+            o_.autotune(4, B.IGE_BF16X3)
+    q11.close()
+    X = np.stack([W.random_coeffs(op.N, 40 + c) for c in range(8)])
+    y0 = op.apply(X)
+    ch = op.autotune(8)
+    d = max(_rel(a, b) for a, b in zip(op.apply(X), y0))
+    _say(f"  autotune FP64: {ch}, max change {d:.1e}")
+    assert d <= 1e-13
+    F = op.rhs_plane_wave([[0.0, 0.0, 1.0], [0.0, 1.0, 0.0], [1.0, 0.0, 0.0]],
+                          [[1.0, 0.0, 0.0], [0.0, 0.0, 1.0], [0.0, 1.0, 0.0]])
+    f = F[0]
     with pytest.raises(B.IgeError):
         op.solve(f, refine=True, inner_prec=B.IGE_BF16X3)
     xs, st, rc = op.solve(f, tol=1e-8, restart=300, maxit=3000)
@@ -815,6 +841,14 @@ def test_level_degrees_refusals_and_refined_solve(oracle_mod, ctx):
     # by at most about tol * cond(A)
     assert _rel(op.apply(xr), f) <= 1.05e-8
     assert _rel(xr, xs) <= 1e-4
+    # three waves: the many-column kernels inside the FP64 and FP32 Krylov iterations
+    X3, s3, rc3 = op.solve(F, tol=1e-8, restart=300, maxit=3000, refine=True, inner_prec=B.IGE_F32)
+    assert rc3 == 0
+    R = op.apply(X3)
+    for c in range(3):
+        _say(f"  wave {c}: refined iters {s3[c][0]} relres {s3[c][2]:.1e}")
+        assert _rel(R[c], F[c]) <= 1.05e-8
+    assert _rel(X3[0], xs) <= 1e-4
     op.close()
 
 
@@ -846,8 +880,12 @@ def test_high_kappa_rows_match_dense_with_level_degrees(oracle_mod, ctx, name):
     o = oracle_mod.Oracle(pats, 2, cf["level"], cf["kappa"], g=5, gs=5)
     yo = o.fmm_apply(x, ql, 1.6, 3, rows=rows, tree=o.block_tree(1.6, 3, kappa_cap=cap))
     err, errd = _rel(y[rows], yo), _rel(y[rows], yd)
-    _say(f"  {name}: degrees {ql} far={op.info.far_pairs} vs oracle FMM {err:.1e}, vs dense {errd:.1e}")
-    assert err <= TOL and errd <= 1e-6
+    # the same product among 4 columns of the many-column kernels (the full-size shape)
+    Y = op.apply(np.stack([x] + [W.random_coeffs(op.N, c) for c in (1, 2, 3)]))
+    eb = _rel(Y[0], y)
+    _say(f"  {name}: degrees {ql} far={op.info.far_pairs} vs oracle FMM {err:.1e}, vs dense {errd:.1e}, "
+         f"4 columns vs one {eb:.1e}")
+    assert err <= TOL and errd <= 1e-6 and eb <= 1e-13
     op.close()
 
 
