@@ -59,14 +59,14 @@ std::complex<double> cz(double2 a) { return {a.x, a.y}; }
 // the far-field pipeline (arithmetic bound) runs on the context stream; the L2P
 // gather joins both.  With profiling on, stage boundaries are recorded into one of
 // kProfSlots event sets on the stream each stage runs on (no host sync).
-// (cos, sin)(j pi/128), j < 256, rounded from long double: the table of the FP64
+// (cos, sin)(j pi/128) / (4 pi), j < 256, rounded from long double: the table of the FP64
 // kernel evaluation in the coupling stage
 const std::vector<double2> &sincos_table()
 {
     static const std::vector<double2> tab = [] {
         std::vector<double2> t(256);
-        const long double step = 3.14159265358979323846264338327950288L / 128.0L;
-        for (int j = 0; j < 256; ++j) t[j] = make_double2((double)cosl(step * j), (double)sinl(step * j));
+        const long double pi = 3.14159265358979323846264338327950288L, step = pi / 128.0L, f = 0.25L / pi;
+        for (int j = 0; j < 256; ++j) t[j] = make_double2((double)(f * cosl(step * j)), (double)(f * sinl(step * j)));
         return t;
     }();
     return tab;

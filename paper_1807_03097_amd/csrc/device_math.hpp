@@ -82,19 +82,20 @@ __device__ inline double2 helmholtz_r2(double kappa, double r2)
 // The same kernel with a table-driven sine and cosine (angle addition): x = kappa r is
 // reduced by k = rint(x 128/pi) multiples of pi/128 (three-part split of pi/128, fused
 // multiply-adds), so |t| <= pi/256; sin t and cos t from their Taylor series to t^7 and
-// t^6 (truncation below 2e-20 relative); tab[k mod 256] = (cos, sin)(k pi/128) gives
-// cos x = C c - S s, sin x = S c + C s.  Valid for |kappa r| < 2^30.
+// t^6 (truncation below 2e-20 relative); tab[k mod 256] = (cos, sin)(k pi/128) / (4 pi)
+// gives e^{ix} / (4 pi) = (C c - S s, S c + C s).  1/r from the hardware reciprocal
+// square root y0 and one third-order step y = y0 (1 + e/2 + 3e^2/8), e = 1 - r^2 y0^2
+// (the next term, 5e^3/16, is below 1e-21 for the hardware estimate's |e| < 1e-7).
+// Valid for |kappa r| < 2^30.
 __device__ inline double2 helmholtz_r2_tab(double kappa, double r2, const double2 *tab)
 {
     constexpr double kInvStep = 40.74366543152521;   // 128/pi
     constexpr double kStep1 = 0.02454369260617026;   // pi/128 = kStep1 + kStep2 + kStep3
     constexpr double kStep2 = 9.567553118338697e-19;
     constexpr double kStep3 = -2.3396639138424529e-35;
-    constexpr double kInv4Pi = 0.07957747154594767;
-    double y = __builtin_amdgcn_rsq(r2);
-    const double hh = 0.5 * r2;
-    y = y * fma(-hh * y, y, 1.5);
-    y = y * fma(-hh * y, y, 1.5);
+    const double y0 = __builtin_amdgcn_rsq(r2);
+    const double e = fma(-(r2 * y0), y0, 1.0);
+    const double y = fma(e * y0, fma(e, 0.375, 0.5), y0);
     const double x = kappa * (r2 * y);
     const double k = rint(x * kInvStep);
     double t = fma(-k, kStep1, x);
@@ -110,8 +111,7 @@ __device__ inline double2 helmholtz_r2_tab(double kappa, double r2, const double
     pc = fma(pc, z, 1.0 / 24.0);                      //  1/4!
     pc = fma(pc, z, -0.5);                            // -1/2!
     const double c = fma(z, pc, 1.0);
-    const double f = kInv4Pi * y;
-    return make_double2(fma(cs.x, c, -cs.y * s) * f, fma(cs.y, c, cs.x * s) * f);
+    return make_double2(fma(cs.x, c, -cs.y * s) * y, fma(cs.y, c, cs.x * s) * y);
 }
 
 // FP32 counterpart (relative error about kappa r 2^-23 from the rounding of r):

@@ -1144,9 +1144,10 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l(DevOp o, const M2LWork *wor
     const int tid = threadIdx.x;
     const int mt = tid % TPG, sp = tid / TPG;
     const bool active = sp < S;
-    T *sX = reinterpret_cast<T *>(smd);                        // [3][Q]
-    C *sV = reinterpret_cast<C *>(smd + (3 * Q * (int)sizeof(T) + 15) / 16 * 2);   // [4][Q], 16-B aligned after sX
-    double2 *red = reinterpret_cast<double2 *>(smd);           // [S][Q][4] after the partner loop
+    // node-major staging, so one address (and immediate offsets) reaches a node's data
+    T *sX = reinterpret_cast<T *>(smd);                        // [Q][4]: x, y, z, unused
+    C *sV = reinterpret_cast<C *>(smd + (4 * Q * (int)sizeof(T) + 15) / 16 * 2);   // [Q][4], 16-B aligned after sX
+    double2 *red = reinterpret_cast<double2 *>(smd);           // [S][Q][2] after the partner loop
     __shared__ double2 sTab[256];                               // (cos, sin)(j pi/128), FP64 only
     if constexpr (sizeof(T) == 8)
         for (int i = tid; i < 256; i += kM2LThreads) sTab[i] = o.sctab[i];   // first use after a barrier
@@ -1172,13 +1173,13 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l(DevOp o, const M2LWork *wor
         __syncthreads();
         const double *Xs = o.nodeX + (size_t)sc * 3 * Qs;
         const double2 *Vs = src + (size_t)sc * 4 * Qs;
-        for (int i = tid; i < 3 * Q; i += kM2LThreads) sX[i] = (T)Xs[(i / Q) * Qs + i % Q];
-        for (int i = tid; i < 4 * Q; i += kM2LThreads) sV[i] = dm::to_c(Vs[(i / Q) * Qs + i % Q], T(0));
+        for (int i = tid; i < 3 * Q; i += kM2LThreads) sX[(i % Q) * 4 + i / Q] = (T)Xs[(i / Q) * Qs + i % Q];
+        for (int i = tid; i < 4 * Q; i += kM2LThreads) sV[(i % Q) * 4 + i / Q] = dm::to_c(Vs[(i / Q) * Qs + i % Q], T(0));
         __syncthreads();
         if (active) {
             for (int ms = mb; ms < me; ++ms) {
-                const T x0 = sX[ms], x1 = sX[Q + ms], x2 = sX[2 * Q + ms];
-                const C v0 = sV[ms], v1 = sV[Q + ms], v2 = sV[2 * Q + ms], v3 = sV[3 * Q + ms];
+                const T x0 = sX[4 * ms], x1 = sX[4 * ms + 1], x2 = sX[4 * ms + 2];
+                const C v0 = sV[4 * ms], v1 = sV[4 * ms + 1], v2 = sV[4 * ms + 2], v3 = sV[4 * ms + 3];
 #pragma unroll
                 for (int k = 0; k < kM2LNT; ++k) {
                     const T d0 = xt[k][0] - x0, d1 = xt[k][1] - x1, d2 = xt[k][2] - x2;
@@ -1193,20 +1194,25 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l(DevOp o, const M2LWork *wor
             }
         }
     }
-    __syncthreads();
+    // the source parts summed in a fixed order, two fields at a time (half the
+    // shared memory of all four: one more workgroup per CU)
 #pragma unroll
-    for (int k = 0; k < kM2LNT; ++k)
-        if (val[k]) {
-            const int mm = mt + k * TPG;
+    for (int hf = 0; hf < 2; ++hf) {
+        __syncthreads();
 #pragma unroll
-            for (int j = 0; j < 4; ++j) red[((size_t)sp * Q + mm) * 4 + j] = dm::to_d(acc[k][j]);
+        for (int k = 0; k < kM2LNT; ++k)
+            if (val[k]) {
+                const int mm = mt + k * TPG;
+#pragma unroll
+                for (int j = 0; j < 2; ++j) red[((size_t)sp * Q + mm) * 2 + j] = dm::to_d(acc[k][2 * hf + j]);
+            }
+        __syncthreads();
+        for (int i = tid; i < 2 * Q; i += kM2LThreads) {
+            const int j = i / Q, mm = i % Q;
+            double2 v = make_double2(0, 0);
+            for (int q2 = 0; q2 < S; ++q2) v = cadd(v, red[((size_t)q2 * Q + mm) * 2 + j]);
+            part[((size_t)blockIdx.x * 4 + 2 * hf + j) * Qs + mm] = v;
         }
-    __syncthreads();
-    for (int i = tid; i < 4 * Q; i += kM2LThreads) {
-        const int j = i / Q, mm = i % Q;
-        double2 v = make_double2(0, 0);
-        for (int q2 = 0; q2 < S; ++q2) v = cadd(v, red[((size_t)q2 * Q + mm) * 4 + j]);
-        part[((size_t)blockIdx.x * 4 + j) * Qs + mm] = v;
     }
 }
 
@@ -1806,8 +1812,8 @@ size_t m2l_shared_bytes(int Q)
 {
     const int TPG = (Q + kM2LNT - 1) / kM2LNT;
     const int S = std::min(kM2LThreads / TPG, Q);
-    // [3][Q] positions (16-byte aligned end) + [4][Q] complex, or the reduction
-    return std::max(sizeof(double) * (3 * Q + 1) + sizeof(double2) * 4 * Q, sizeof(double2) * 4 * (size_t)Q * S);
+    // [Q][4] positions + [Q][4] complex, or the reduction of two fields
+    return std::max(sizeof(double) * 4 * Q + sizeof(double2) * 4 * Q, sizeof(double2) * 2 * (size_t)Q * S);
 }
 
 void launch_m2l(ige_op op, int prec)

@@ -67,7 +67,7 @@ struct DevOp {
     const int64_t *lvl_off;   // [L+2] first global cluster id of each level
     const double *nodeX;      // [NC][3][Q]
     const double *nodeT;      // [NC][6][Q]  d_uF (3), d_vF (3)
-    const double2 *sctab;     // [256] (cos, sin)(j pi/128), for the table-driven kernel evaluation
+    const double2 *sctab;     // [256] (cos, sin)(j pi/128) / (4 pi), for the table-driven kernel evaluation
     const double *xn;         // [Q1] Chebyshev nodes of degree q (the largest level degree)
     // degree per level (variable order): varq = 1 when some level's degree ql[l] < q;
     // its nodes xnl [L+1][kMaxQ1] and the restriction Rl [L+1][Q1][Q1] from degree q
