@@ -48,6 +48,41 @@ __global__ void k_to_cols(int64_t N, int r, const double2 *yt, double2 *y)
     y[t] = yt[i * r + c];
 }
 
+// the same through a 32 x 32 tile in LDS, so that both the loads and the stores run
+// along contiguous memory (the direct kernels above stride one side by N or r);
+// blocks of 256 threads over (N / 32, r / 32) tiles; TO_ROWS: x [r][N] -> xt [N][r]
+constexpr int kTT = 32;
+template <bool TO_ROWS>
+__global__ __launch_bounds__(256) void k_transpose_t(int64_t N, int r, const double2 *in, double2 *out)
+{
+    __shared__ double2 tile[kTT][kTT + 1];
+    const int64_t i0 = (int64_t)blockIdx.x * kTT;
+    const int c0 = blockIdx.y * kTT, tx = threadIdx.x % kTT, ty = threadIdx.x / kTT;
+    for (int k = ty; k < kTT; k += 256 / kTT) {
+        if (TO_ROWS) {   // column c0 + k of x, entries i0 + tx
+            const int c = c0 + k;
+            const int64_t i = i0 + tx;
+            if (c < r && i < N) tile[k][tx] = in[(size_t)c * N + i];
+        } else {         // entry i0 + k of yt, columns c0 + tx
+            const int c = c0 + tx;
+            const int64_t i = i0 + k;
+            if (c < r && i < N) tile[tx][k] = in[(size_t)i * r + c];
+        }
+    }
+    __syncthreads();
+    for (int k = ty; k < kTT; k += 256 / kTT) {
+        if (TO_ROWS) {   // entry i0 + k of xt, columns c0 + tx
+            const int c = c0 + tx;
+            const int64_t i = i0 + k;
+            if (c < r && i < N) out[(size_t)i * r + c] = tile[tx][k];
+        } else {         // column c0 + k of y, entries i0 + tx
+            const int c = c0 + k;
+            const int64_t i = i0 + tx;
+            if (c < r && i < N) out[(size_t)c * N + i] = tile[k][tx];
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // near-field product over the stored blocks, RB columns per pass: every block
 // entry is loaded once per pass and used for the RB columns of both the block and
@@ -796,6 +831,25 @@ int pick_rb(size_t bytes_per_col, size_t fixed = 0, size_t budget = transfer_lds
 }
 }  // namespace
 
+namespace {
+// [r][N] <-> [N][r]: tiled for 16 columns or more, direct below (a tile would be
+// mostly empty)
+void transpose_cols(hipStream_t s, int64_t N, int r, const double2 *in, double2 *out, bool to_rows)
+{
+    const int64_t tot = N * r;
+    if (r >= 16) {
+        const dim3 grid((unsigned)((N + kTT - 1) / kTT), (unsigned)((r + kTT - 1) / kTT));
+        if (to_rows) hipLaunchKernelGGL(k_transpose_t<true>, grid, dim3(256), 0, s, N, r, in, out);
+        else hipLaunchKernelGGL(k_transpose_t<false>, grid, dim3(256), 0, s, N, r, in, out);
+    } else if (to_rows) {
+        hipLaunchKernelGGL(k_to_rows, dim3((tot + 255) / 256), dim3(256), 0, s, N, r, in, out);
+    } else {
+        hipLaunchKernelGGL(k_to_cols, dim3((tot + 255) / 256), dim3(256), 0, s, N, r, in, out);
+    }
+    IGE_HIP(hipGetLastError());
+}
+}  // namespace
+
 #define IGE_RB_SWITCH(rb, KERNEL, grid, block, shm, stream, ...)                                             \
     switch (rb) {                                                                                            \
         case 8: hipLaunchKernelGGL(KERNEL<8>, grid, block, shm, stream, __VA_ARGS__); break;                \
@@ -819,8 +873,7 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
     const int64_t tot = N * r;
     auto chunks = [&](int rb) { return (r + rb - 1) / rb; };
     if (x) {   // x == nullptr: xt already holds the input (graph body)
-        hipLaunchKernelGGL(k_to_rows, dim3((tot + 255) / 256), dim3(256), 0, s, N, r, x, xt);
-        IGE_HIP(hipGetLastError());
+        transpose_cols(s, N, r, x, xt, true);
     }
     const bool far = !op->work.empty();
     mark(0);
@@ -959,23 +1012,18 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
     }
     mark(10);
     if (y) {   // y == nullptr: the result stays in yt (graph body)
-        hipLaunchKernelGGL(k_to_cols, dim3((tot + 255) / 256), dim3(256), 0, s, N, r, yt, y);
-        IGE_HIP(hipGetLastError());
+        transpose_cols(s, N, r, yt, y, false);
     }
 }
 
 void batched_to_rows(ige_op op, int r, const double2 *x, double2 *xt, hipStream_t s)
 {
-    const int64_t tot = (int64_t)op->view.N * r;
-    hipLaunchKernelGGL(k_to_rows, dim3((tot + 255) / 256), dim3(256), 0, s, (int64_t)op->view.N, r, x, xt);
-    IGE_HIP(hipGetLastError());
+    transpose_cols(s, (int64_t)op->view.N, r, x, xt, true);
 }
 
 void batched_to_cols(ige_op op, int r, const double2 *yt, double2 *y, hipStream_t s)
 {
-    const int64_t tot = (int64_t)op->view.N * r;
-    hipLaunchKernelGGL(k_to_cols, dim3((tot + 255) / 256), dim3(256), 0, s, (int64_t)op->view.N, r, yt, y);
-    IGE_HIP(hipGetLastError());
+    transpose_cols(s, (int64_t)op->view.N, r, yt, y, false);
 }
 
 }  // namespace ige
