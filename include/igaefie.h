@@ -429,8 +429,8 @@ int ige_peak_probe(ige_ctx ctx, int kind, double *value);
 
 /* Diagnostic: evaluate on the context's device the Helmholtz kernel
  * G_k(r) = e^{ikr}/(4 pi r) (Sec. 2.2, eq. (eq:HelmholtzGreen)) exactly as the
- * coupling stage does in precision prec (IGE_F64: reciprocal square root with two
- * Newton steps, table-driven sine and cosine; IGE_F32), from squared distances
+ * coupling stage does in precision prec (IGE_F64: reciprocal square root with one
+ * third-order step, table-driven sine and cosine; IGE_F32), from squared distances
  * r2[n] > 0 (host memory) into out[n] (host memory).  Synchronous. */
 int ige_helmholtz_eval(ige_ctx ctx, int64_t n, double kappa, const double *r2, ige_c64 *out, int prec);
 

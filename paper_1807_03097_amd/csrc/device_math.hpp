@@ -28,7 +28,7 @@ __device__ inline float2 cmac(float2 acc, float2 a, float2 b)
     return make_float2(fmaf(a.x, b.x, fmaf(-a.y, b.y, acc.x)), fmaf(a.x, b.y, fmaf(a.y, b.x, acc.y)));
 }
 
-// FP64: 1/r by the hardware reciprocal square root and two Newton steps
+// FP64 (near-field quadrature, potential): 1/r by the hardware reciprocal square root and two Newton steps
 // y <- y (3/2 - r^2 y^2 / 2); sin and cos of kappa r by Cody-Waite reduction
 // t = kappa r - k pi/2 (pi/2 split into three doubles, products exact through
 // fused multiply-add) and the Taylor polynomials of sin (to t^17) and cos (to t^18)
