@@ -1126,12 +1126,18 @@ constexpr int kM2LThreads = 256;
 constexpr int kM2LNT = 3;
 
 template <typename T>
-__global__ __launch_bounds__(kM2LThreads) void k_m2l(DevOp o, const M2LWork *work, const int32_t *partner,
+__global__ __launch_bounds__(kM2LThreads) void k_m2l(DevOp o, int nwork, const M2LWork *work, const int32_t *partner,
                                                       const double2 *src, double2 *part)
 {
     using C = typename dm::cplx_of<T>::type;
     extern __shared__ double smd[];
-    const M2LWork wk = work[blockIdx.x];
+    __shared__ double2 sTab[256];                               // (cos, sin)(j pi/128) / (4 pi), FP64 only
+    if constexpr (sizeof(T) == 8)
+        for (int i = threadIdx.x; i < 256; i += kM2LThreads) sTab[i] = o.sctab[i];   // first use after a barrier
+    // one work item per workgroup, or (a grid smaller than the work) items blockIdx.x,
+    // blockIdx.x + gridDim.x, ...
+    for (int wi = blockIdx.x; wi < nwork; wi += gridDim.x) {
+    const M2LWork wk = work[wi];
     // nodes of the target's level (the partners are on the same level); per-cluster
     // arrays keep the stride Qs of the largest degree
     const int Qs = o.Q;
@@ -1148,9 +1154,6 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l(DevOp o, const M2LWork *wor
     T *sX = reinterpret_cast<T *>(smd);                        // [Q][4]: x, y, z, unused
     C *sV = reinterpret_cast<C *>(smd + (4 * Q * (int)sizeof(T) + 15) / 16 * 2);   // [Q][4], 16-B aligned after sX
     double2 *red = reinterpret_cast<double2 *>(smd);           // [S][Q][2] after the partner loop
-    __shared__ double2 sTab[256];                               // (cos, sin)(j pi/128), FP64 only
-    if constexpr (sizeof(T) == 8)
-        for (int i = tid; i < 256; i += kM2LThreads) sTab[i] = o.sctab[i];   // first use after a barrier
     const T kap = (T)o.kappa;
     T xt[kM2LNT][3];
     bool val[kM2LNT];
@@ -1211,8 +1214,10 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l(DevOp o, const M2LWork *wor
             const int j = i / Q, mm = i % Q;
             double2 v = make_double2(0, 0);
             for (int q2 = 0; q2 < S; ++q2) v = cadd(v, red[((size_t)q2 * Q + mm) * 2 + j]);
-            part[((size_t)blockIdx.x * 4 + 2 * hf + j) * Qs + mm] = v;
+            part[((size_t)wi * 4 + 2 * hf + j) * Qs + mm] = v;
         }
+    }
+    __syncthreads();   // the next item's staging reuses the shared memory
     }
 }
 
@@ -1827,13 +1832,22 @@ void launch_m2l(ige_op op, int prec)
     size_t shm = m2l_shared_bytes(o.Q);   // the largest over the levels' node counts
     for (int lvl = 0; lvl <= o.L; ++lvl) shm = std::max(shm, m2l_shared_bytes((o.ql[lvl] + 1) * (o.ql[lvl] + 1)));
     shm = std::max(shm, op->m2l_lds);
+    // k = IGE_M2L_PERSIST (default 2) workgroups per CU loop over the work items, room
+    // for the near field's workgroups beside them; 0: one workgroup per item
+    const int nwork = (int)op->work.size();
+    int grid = nwork;
+    if (op->m2l_persist > 0) {
+        int ncu = 0;
+        IGE_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, op->ctx->device));
+        grid = std::max(1, std::min(nwork, ncu * op->m2l_persist));
+    }
     if (prec == IGE_F32) {
         lds_attr_once(reinterpret_cast<const void *>(&k_m2l<float>), shm);
-        hipLaunchKernelGGL(k_m2l<float>, dim3(op->work.size()), dim3(kM2LThreads), shm, lstream(op), o,
+        hipLaunchKernelGGL(k_m2l<float>, dim3(grid), dim3(kM2LThreads), shm, lstream(op), o, nwork,
                            op->d_work.p, op->d_partner.p, op->d_src.p, op->d_part.p);
     } else {
         lds_attr_once(reinterpret_cast<const void *>(&k_m2l<double>), shm);
-        hipLaunchKernelGGL(k_m2l<double>, dim3(op->work.size()), dim3(kM2LThreads), shm, lstream(op), o,
+        hipLaunchKernelGGL(k_m2l<double>, dim3(grid), dim3(kM2LThreads), shm, lstream(op), o, nwork,
                            op->d_work.p, op->d_partner.p, op->d_src.p, op->d_part.p);
     }
     IGE_LAUNCH_CHECK();

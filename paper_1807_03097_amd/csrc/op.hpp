@@ -125,6 +125,10 @@ struct ige_op_s {
     // coarsest level with far pairs (L + 1 if none): the upward pass stops there and
     // the downward pass starts there, since coarser moments and expansions are unused
     int lfar = 0;
+    // one-column coupling: workgroups per CU looping over the work items (0: one
+    // workgroup per item); two leave room for the near field's workgroups beside it
+    // (C2: 0.1793 against 0.1812 ms per apply, four runs each)
+    int m2l_persist = 2;
     bool near_first = false;           // overlap: near field beside the upward pass only, then the coupling alone
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int64_t prof_count = 0;
