@@ -125,11 +125,13 @@ int ige_geom_destroy(ige_geom geom);
  *                 the accuracy at high kappa without refining the partition; a rule is
  *                 q_l = min(15, max(q, ceil(kappa diam_l / 2) + 5)) on the levels with far
  *                 blocks, with diam_l from ige_op_info of the planned operator.  With
- *                 degrees that differ between levels (and with one degree above 10) the
- *                 operator couples on the generated FP64/FP32 kernels, one and many
- *                 columns, each level's blocks of its own size in one launch: the BF16
- *                 precisions (apply, autotuning, refinement inner solves) and stored
- *                 coupling blocks refuse it with IGE_EINVAL. */
+ *                 degrees that differ between levels the generated FP64/FP32 coupling
+ *                 takes each level's blocks at their own size in one launch (one and
+ *                 many columns), and the BF16 matrix-core coupling runs one launch per
+ *                 level with that level's padded block size.  A degree above 10 on a
+ *                 level with far pairs (also one degree q = 11) makes the BF16
+ *                 precisions (apply, autotuning, refinement inner solves) refuse with
+ *                 IGE_EINVAL; stored coupling blocks need one degree on all levels. */
 enum { IGE_OP_EFIE = 0, IGE_OP_SCALAR = 1 };
 typedef struct {
     int p, level;

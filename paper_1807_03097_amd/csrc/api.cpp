@@ -701,6 +701,46 @@ ige_op ige::assemble_on(ige_ctx ctx, const ige_geom_s *geom, const ige_params &p
                         op->d_morder_sp.upload(sp, s);
                         op->n_morder_sp = (int64_t)sp.size();
                     }
+                    if (F.varq) {
+                        // a degree per level: the matrix-core coupling runs level by level,
+                        // each with its own padded block size; block slots count from the
+                        // level's first pair, the launch order sorts within each level
+                        op->mxl.clear();
+                        for (size_t w = 0; w < morder.size(); ++w) morder[w] = (int32_t)w;
+                        int64_t p0 = 0, w0 = 0;
+                        size_t goff = 0;
+                        while (p0 < op->nfp) {
+                            const int32_t g0 = fpair[2 * p0];
+                            int lv = 0;
+                            while (lv < T.L && g0 >= op->lvl_off[lv + 1]) ++lv;
+                            int64_t p1 = p0;
+                            while (p1 < op->nfp && fpair[2 * p1] < op->lvl_off[lv + 1]) ++p1;
+                            int64_t w1 = w0;
+                            while (w1 < (int64_t)op->mwork.size() && op->mwork[w1].tgt < op->lvl_off[lv + 1]) ++w1;
+                            ige_op_s::MxLevel L;
+                            L.lvl = lv;
+                            L.Qr = (F.ql[lv] + 1) * (F.ql[lv] + 1);
+                            L.Qp = ige::coupling_qp(L.Qr);
+                            L.p0 = p0;
+                            L.np = p1 - p0;
+                            L.cl0 = (int)op->lvl_off[lv];
+                            L.ncl = (int)(op->lvl_off[lv + 1] - op->lvl_off[lv]);
+                            L.w0 = w0;
+                            L.nw = w1 - w0;
+                            L.gb_off = goff;   // in units of Qp x 2Qp blocks of one plane
+                            goff += (size_t)L.np * 2 * L.Qp * 2 * L.Qp;
+                            for (int64_t w = w0; w < w1; ++w)
+                                for (int k = op->mwork[w].beg; k < op->mwork[w].end; ++k) gslot[k] -= (int32_t)(2 * p0);
+                            std::stable_sort(morder.begin() + w0, morder.begin() + w1, [&](int32_t a, int32_t b) {
+                                return op->mwork[a].end - op->mwork[a].beg > op->mwork[b].end - op->mwork[b].beg;
+                            });
+                            op->mxl.push_back(L);
+                            p0 = p1;
+                            w0 = w1;
+                        }
+                        IGE_REQUIRE(w0 == (int64_t)op->mwork.size(), "coupling work items are not grouped by level");
+                        op->d_morder.upload(morder, s);
+                    }
                     op->d_mwork.upload(op->mwork, s);
                     op->d_mpartner.upload(mpart, s);
                     op->d_gslot.upload(gslot, s);
@@ -1015,10 +1055,17 @@ void run_graph(ige_op op, ApplyGraph *g, int r, int prec, const std::function<vo
     IGE_HIP(hipGraphLaunch(g->exec, s));
 }
 
-// the matrix-core couplings (BF16, and FP64 on the matrix cores) hold one padded block
-// size of at most 128 nodes: one degree on all levels, at most 10; other operators
-// couple on the generated FP64/FP32 kernels, whose blocks may differ per level
-bool mx_coupling_ok(const ige_op_s *op) { return !op->F.varq && op->F.q <= 10; }
+// the BF16 matrix-core couplings take blocks of at most 128 padded nodes (degree at
+// most 10 on every level with far pairs; with a degree per level, one launch per
+// level); the FP64 matrix-core coupling needs one degree on all levels.  Other
+// operators couple on the generated FP64/FP32 kernels
+bool mx_coupling_ok(const ige_op_s *op)
+{
+    if (!op->F.varq) return op->F.q <= 10;
+    for (const auto &L : op->mxl)
+        if (L.Qp > 128) return false;
+    return true;
+}
 
 // y = A x for r device columns ([r][N]) in the given precision; with g, the operator
 // body runs as a captured graph (not while profiling)
@@ -1065,7 +1112,7 @@ int apply_impl(ige_op op, int r, const ige_c64 *x, ige_c64 *y, int ptr_kind, int
         IGE_REQUIRE(ptr_kind == IGE_HOST || ptr_kind == IGE_DEVICE, "bad ptr_kind");
         IGE_REQUIRE(prec >= IGE_F64 && prec <= IGE_BF16X3_ALL, "bad coupling precision");
         IGE_REQUIRE(prec <= IGE_F32 || mx_coupling_ok(op),
-                    "the BF16 couplings need one interpolation degree on all levels, at most 10");
+                    "the BF16 couplings need interpolation degrees of at most 10 on the levels with far pairs");
         set_device(op->ctx);
         const int64_t N = op->D.N;
         hipStream_t s = op->ctx->stream;
@@ -1103,7 +1150,7 @@ int ige_op_autotune(ige_op op, int r, int prec, int *choice, int nchoice)
         IGE_REQUIRE(op->assembled, "operator was planned, not assembled");
         IGE_REQUIRE(prec >= IGE_F64 && prec <= IGE_BF16X3_ALL, "bad precision");
         IGE_REQUIRE(prec <= IGE_F32 || mx_coupling_ok(op),
-                    "the BF16 couplings need one interpolation degree on all levels, at most 10");
+                    "the BF16 couplings need interpolation degrees of at most 10 on the levels with far pairs");
         set_device(op->ctx);
         const int64_t N = op->D.N;
         hipStream_t s = op->ctx->stream;
@@ -1150,7 +1197,7 @@ int ige_op_autotune(ige_op op, int r, int prec, int *choice, int nchoice)
             }
         };
         // coordinate descent over the knobs that the (r, prec) apply uses
-        const bool mx = r > 1 && prec >= IGE_BF16, near_bx = r > 1 && prec == IGE_BF16X3_ALL;
+        const bool mx = r > 1 && prec >= IGE_BF16 && op->mxl.empty(), near_bx = r > 1 && prec == IGE_BF16X3_ALL;
         const bool near_mfma = r >= 8 && prec != IGE_BF16X3_ALL && ige::near_mfma_mtw_ok(op->view.nF, op->view.rc) &&
                                !ige::near_f64mx_ok(op, r);
         // FP64 coupling on the matrix cores (default) against the generated kernel, whose
@@ -1493,7 +1540,7 @@ int ige_solve(ige_op op, int r, const ige_c64 *f, ige_c64 *x, int ptr_kind, cons
         IGE_REQUIRE(!opts->refine || (std::isfinite(opts->inner_tol) && opts->inner_tol > 0.0 && opts->inner_tol < 1.0),
                     "inner_tol must be in (0, 1)");
         IGE_REQUIRE(!opts->refine || opts->inner_prec <= IGE_F32 || mx_coupling_ok(op),
-                    "the BF16 couplings need one interpolation degree on all levels, at most 10");
+                    "the BF16 couplings need interpolation degrees of at most 10 on the levels with far pairs");
         set_device(op->ctx);
         const auto t0 = std::chrono::steady_clock::now();
         const int64_t N = op->D.N;

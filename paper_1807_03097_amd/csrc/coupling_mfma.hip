@@ -49,9 +49,11 @@ __device__ inline void split_bf16(double x, __bf16 &hi, __bf16 &lo)
 // G in BF16: Gb[(2 pair + orientation) * planes + plane][Qp][2Qp] (planes = 2 for the
 // split form: high and low part, else 1); orientation 0 =
 // G_ts (rows: nodes of t), 1 = G_st; columns [Re | Im], zero padded
-__global__ void k_gb_store(DevOp o, int64_t nfp, const int32_t *fpair, int Qp, int split, __bf16 *Gb)
+// (Qr nodes per cluster, of the stride o.Q of the cluster arrays: the degree of the
+// pairs' level)
+__global__ void k_gb_store(DevOp o, int64_t nfp, const int32_t *fpair, int Qr, int Qp, int split, __bf16 *Gb)
 {
-    const int Q = o.Q, K2 = 2 * Qp;
+    const int Qs = o.Q, Q = Qr, K2 = 2 * Qp;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t per = (int64_t)Qp * Qp;
     if (t >= nfp * 2 * per) return;
@@ -62,8 +64,8 @@ __global__ void k_gb_store(DevOp o, int64_t nfp, const int32_t *fpair, int Qp, i
     const int ga = fpair[2 * pr + ori], gb = fpair[2 * pr + 1 - ori];
     double2 g = make_double2(0.0, 0.0);
     if (m < Q && mc < Q) {
-        const double *Xa = o.nodeX + (size_t)ga * 3 * Q, *Xb = o.nodeX + (size_t)gb * 3 * Q;
-        const double d0 = Xa[m] - Xb[mc], d1 = Xa[Q + m] - Xb[Q + mc], d2 = Xa[2 * Q + m] - Xb[2 * Q + mc];
+        const double *Xa = o.nodeX + (size_t)ga * 3 * Qs, *Xb = o.nodeX + (size_t)gb * 3 * Qs;
+        const double d0 = Xa[m] - Xb[mc], d1 = Xa[Qs + m] - Xb[Qs + mc], d2 = Xa[2 * Qs + m] - Xb[2 * Qs + mc];
         g = dm::helmholtz_r2_tab(o.kappa, fma(d0, d0, fma(d1, d1, d2 * d2)), o.sctab);
     }
     __bf16 *base = Gb + (size_t)po * (split == 3 ? 2 : 1) * Qp * K2;
@@ -85,10 +87,11 @@ __global__ void k_gb_store(DevOp o, int64_t nfp, const int32_t *fpair, int Qp, i
 // Source fields [NC][4][Q][r] -> right factor Vb[cluster][chunk][plane][ncol][2Qp]
 // (planes as for G): column n = f rc + j (field f, right-hand side ch rc + j),
 // row k < Qp: Re V[k], k >= Qp: Im V[k - Qp]; zero padded
-__global__ void k_vb_prep(DevOp o, int NC, int r, int rc, int nchunk, int ncol, int Qp, int split, const double2 *src,
-                          __bf16 *Vb)
+// (clusters cl0 .. cl0 + NC - 1 with Qr nodes each, at Vb[cluster - cl0])
+__global__ void k_vb_prep(DevOp o, int NC, int cl0, int Qr, int r, int rc, int nchunk, int ncol, int Qp, int split,
+                          const double2 *src, __bf16 *Vb)
 {
-    const int Q = o.Q, K2 = 2 * Qp;
+    const int Qs = o.Q, Q = Qr, K2 = 2 * Qp;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t per = (int64_t)ncol * K2;
     if (t >= (int64_t)NC * nchunk * per) return;
@@ -99,7 +102,7 @@ __global__ void k_vb_prep(DevOp o, int NC, int r, int rc, int nchunk, int ncol, 
     const int mm = k < Qp ? k : k - Qp;
     double v = 0.0;
     if (mm < Q && col < r && f < 4) {
-        const double2 s = src[(((size_t)gc * 4 + f) * Q + mm) * r + col];
+        const double2 s = src[(((size_t)(cl0 + gc) * 4 + f) * Qs + mm) * r + col];
         v = k < Qp ? s.x : s.y;
     }
     __bf16 *base = Vb + (size_t)cc * (split == 3 ? 2 : 1) * per;
@@ -117,11 +120,11 @@ __global__ void k_vb_prep(DevOp o, int NC, int r, int rc, int nchunk, int ncol, 
 // of one cluster and one column chunk, reads them along the columns (coalesced, the
 // layout of src) and writes each column's 32-node runs of Re and Im (contiguous in Vb).
 constexpr int kVbRows = 32;
-__global__ __launch_bounds__(256) void k_vb_prep_t(DevOp o, int r, int rc, int nchunk, int ncol, int Qp, int split,
-                                                   const double2 *src, __bf16 *Vb)
+__global__ __launch_bounds__(256) void k_vb_prep_t(DevOp o, int cl0, int Qr, int r, int rc, int nchunk, int ncol,
+                                                   int Qp, int split, const double2 *src, __bf16 *Vb)
 {
     __shared__ double2 tile[kVbRows][65];   // [node][column in chunk], rc <= 64
-    const int Q = o.Q, K2 = 2 * Qp, nrb = Qp / kVbRows;
+    const int Qs = o.Q, Q = Qr, K2 = 2 * Qp, nrb = Qp / kVbRows;
     int b = blockIdx.x;
     const int rb = b % nrb;
     b /= nrb;
@@ -131,7 +134,7 @@ __global__ __launch_bounds__(256) void k_vb_prep_t(DevOp o, int r, int rc, int n
     const int m0 = rb * kVbRows;
     for (int i = threadIdx.x; i < kVbRows * rc; i += blockDim.x) {
         const int mm = i / rc, j = i % rc, col = ch * rc + j, m = m0 + mm;
-        tile[mm][j] = (m < Q && col < r) ? src[(((size_t)gc * 4 + f) * Q + m) * r + col] : make_double2(0.0, 0.0);
+        tile[mm][j] = (m < Q && col < r) ? src[(((size_t)(cl0 + gc) * 4 + f) * Qs + m) * r + col] : make_double2(0.0, 0.0);
     }
     __syncthreads();
     const int64_t per = (int64_t)ncol * K2;
@@ -165,7 +168,7 @@ __device__ inline bf8 neg_bf8(bf8 x)
 // MT = Qp / 16 row tiles per wave, WN column waves of NT 16-column tiles each:
 // 2 WN waves, ncol = 16 WN NT columns per chunk
 template <int SPLIT, int MT, int WN, int NT>
-__global__ __launch_bounds__(128 * WN) void k_m2l_mx(DevOp o, int r, int rc, int nchunk, int64_t nwork,
+__global__ __launch_bounds__(128 * WN) void k_m2l_mx(DevOp o, int r, int rc, int nchunk, int64_t nwork, int Qr, int cl0,
                                                      const int32_t *order, const M2LWork *work,
                                                      const int32_t *partner, const int32_t *gslot, const __bf16 *Gb,
                                                      const __bf16 *Vb, float2 *part)
@@ -178,7 +181,7 @@ __global__ __launch_bounds__(128 * WN) void k_m2l_mx(DevOp o, int r, int rc, int
     constexpr bool PREF = GV <= 16;                 // next block prefetched into registers
     extern __shared__ __bf16 sG[];                  // [PL][QP][LD]
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv / WN, wn = wv % WN;
-    const int Q = o.Q;
+    const int Q = o.Q;   // stride of the partial couplings; Qr rows of them written
     // the chunks of one work item share an XCD (consecutive ids go round-robin over 8)
     const int64_t g = blockIdx.x;
     const int64_t wo = (g / (8 * nchunk)) * 8 + g % 8;
@@ -198,7 +201,7 @@ __global__ __launch_bounds__(128 * WN) void k_m2l_mx(DevOp o, int r, int rc, int
         *reinterpret_cast<uint4 *>(sG + ((size_t)pl * QP + row) * LD + 8 * k8) = v;
     };
     auto b_load = [&](bf8 (&b)[NT][PL], int kp, int s) {
-        const __bf16 *Vs = Vb + ((size_t)partner[kp] * nchunk + ch) * PL * vper;
+        const __bf16 *Vs = Vb + ((size_t)(partner[kp] - cl0) * nchunk + ch) * PL * vper;
         const int kk = 32 * s + 8 * (lane >> 4);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
@@ -309,7 +312,7 @@ __global__ __launch_bounds__(128 * WN) void k_m2l_mx(DevOp o, int r, int rc, int
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int m = 16 * a + 4 * (lane >> 4) + j;
-                if (m < Q) {
+                if (m < Qr) {
                     float *dst = reinterpret_cast<float *>(part + (((size_t)wi * 4 + f) * Q + m) * r + col);
                     dst[wm] = acc[a][t][j];
                 }
@@ -324,7 +327,7 @@ __global__ __launch_bounds__(128 * WN) void k_m2l_mx(DevOp o, int r, int rc, int
 // (one barrier per partner, a few registers for the pieces in flight instead of the
 // whole next block), which leaves room for wider column chunks.
 template <int SPLIT, int MT, int WN, int NT>
-__global__ __launch_bounds__(128 * WN) void k_m2l_mxd(DevOp o, int r, int rc, int nchunk, int64_t nwork,
+__global__ __launch_bounds__(128 * WN) void k_m2l_mxd(DevOp o, int r, int rc, int nchunk, int64_t nwork, int Qr, int cl0,
                                                       const int32_t *order, const M2LWork *work,
                                                       const int32_t *partner, const int32_t *gslot, const __bf16 *Gb,
                                                       const __bf16 *Vb, float2 *part)
@@ -338,7 +341,7 @@ __global__ __launch_bounds__(128 * WN) void k_m2l_mxd(DevOp o, int r, int rc, in
     constexpr size_t BUF = (size_t)PL * QP * LD;    // one staging buffer
     extern __shared__ __bf16 sG[];                  // [2][PL][QP][LD]
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv / WN, wn = wv % WN;
-    const int Q = o.Q;
+    const int Q = o.Q;   // stride of the partial couplings; Qr rows of them written
     const int64_t g = blockIdx.x;
     const int64_t wo = (g / (8 * nchunk)) * 8 + g % 8;
     const int ch = (int)((g / 8) % nchunk);
@@ -354,7 +357,7 @@ __global__ __launch_bounds__(128 * WN) void k_m2l_mxd(DevOp o, int r, int rc, in
         *reinterpret_cast<uint4 *>(buf + ((size_t)pl * QP + row) * LD + 8 * k8) = v;
     };
     auto b_load = [&](bf8 (&b)[NT][PL], int kp, int s) {
-        const __bf16 *Vs = Vb + ((size_t)partner[kp] * nchunk + ch) * PL * vper;
+        const __bf16 *Vs = Vb + ((size_t)(partner[kp] - cl0) * nchunk + ch) * PL * vper;
         const int kk = 32 * s + 8 * (lane >> 4);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
@@ -452,7 +455,7 @@ __global__ __launch_bounds__(128 * WN) void k_m2l_mxd(DevOp o, int r, int rc, in
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int m = 16 * a + 4 * (lane >> 4) + j;
-                if (m < Q) {
+                if (m < Qr) {
                     float *dst = reinterpret_cast<float *>(part + (((size_t)wi * 4 + f) * Q + m) * r + col);
                     dst[wm] = acc[a][t][j];
                 }
@@ -605,7 +608,7 @@ __global__ __launch_bounds__(128 * WN) void k_m2l_md(DevOp o, int r, int rc, int
 // same right-factor fragments (the kernel above loads each twice, once per row half),
 // at the price of twice the left-factor reads from shared memory.
 template <int SPLIT, int MT, int WN, int NT>
-__global__ __launch_bounds__(64 * WN) void k_m2l_mxr(DevOp o, int r, int rc, int nchunk, int64_t nwork,
+__global__ __launch_bounds__(64 * WN) void k_m2l_mxr(DevOp o, int r, int rc, int nchunk, int64_t nwork, int Qr, int cl0,
                                                      const int32_t *order, const M2LWork *work,
                                                      const int32_t *partner, const int32_t *gslot, const __bf16 *Gb,
                                                      const __bf16 *Vb, float2 *part)
@@ -619,7 +622,7 @@ __global__ __launch_bounds__(64 * WN) void k_m2l_mxr(DevOp o, int r, int rc, int
     constexpr size_t BUF = (size_t)PL * QP * LD;    // one staging buffer
     extern __shared__ __bf16 sG[];                  // [2][PL][QP][LD]
     const int tid = threadIdx.x, lane = tid & 63, wn = tid >> 6;
-    const int Q = o.Q;
+    const int Q = o.Q;   // stride of the partial couplings; Qr rows of them written
     const int64_t g = blockIdx.x;
     const int64_t wo = (g / (8 * nchunk)) * 8 + g % 8;
     const int ch = (int)((g / 8) % nchunk);
@@ -635,7 +638,7 @@ __global__ __launch_bounds__(64 * WN) void k_m2l_mxr(DevOp o, int r, int rc, int
         *reinterpret_cast<uint4 *>(buf + ((size_t)pl * QP + row) * LD + 8 * k8) = v;
     };
     auto b_load = [&](bf8 (&b)[NT][PL], int kp, int s) {
-        const __bf16 *Vs = Vb + ((size_t)partner[kp] * nchunk + ch) * PL * vper;
+        const __bf16 *Vs = Vb + ((size_t)(partner[kp] - cl0) * nchunk + ch) * PL * vper;
         const int kk = 32 * s + 8 * (lane >> 4);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
@@ -730,7 +733,7 @@ __global__ __launch_bounds__(64 * WN) void k_m2l_mxr(DevOp o, int r, int rc, int
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int m = 16 * a + 4 * (lane >> 4) + j;
-                if (m < Q) {
+                if (m < Qr) {
                     float *dst = reinterpret_cast<float *>(part + (((size_t)wi * 4 + f) * Q + m) * r + col);
                     dst[0] = acc[0][a][t][j];
                     dst[1] = acc[1][a][t][j];
@@ -748,11 +751,24 @@ void ensure_coupling_bf16(ige_op op, int split)
     DBuf<__bf16> &G = split == 3 ? op->d_Gb3 : op->d_Gb1;
     if (G.p || op->nfp == 0) return;
     const DevOp &o = op->view;
+    const int pl = split == 3 ? 2 : 1;
+    if (!op->mxl.empty()) {   // a degree per level: each level's blocks at its own size
+        size_t tot = 0;
+        for (const auto &L : op->mxl) tot += (size_t)L.np * 2 * L.Qp * 2 * L.Qp;
+        G.alloc(tot * pl);
+        for (const auto &L : op->mxl) {
+            const int64_t n = L.np * 2 * (int64_t)L.Qp * L.Qp;
+            hipLaunchKernelGGL(k_gb_store, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, op->ctx->stream, o, L.np,
+                               op->d_fpair.p + 2 * L.p0, L.Qr, L.Qp, split, G.p + L.gb_off * pl);
+            IGE_HIP(hipGetLastError());
+        }
+        return;
+    }
     const int Qp = coupling_qp(o.Q);
-    G.alloc((size_t)op->nfp * 2 * (split == 3 ? 2 : 1) * Qp * 2 * Qp);
+    G.alloc((size_t)op->nfp * 2 * pl * Qp * 2 * Qp);
     const int64_t n = op->nfp * 2 * (int64_t)Qp * Qp;
     hipLaunchKernelGGL(k_gb_store, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, op->ctx->stream, o, op->nfp,
-                       op->d_fpair.p, Qp, split, G.p);
+                       op->d_fpair.p, o.Q, Qp, split, G.p);
     IGE_HIP(hipGetLastError());
 }
 
@@ -780,14 +796,22 @@ int m2l_ncol(int r, int cap)
     return nc;
 }
 
+// the work items of one launch: their launch order (nw entries, -1 = padding), the
+// rows of their blocks and the first cluster of their level (the right factors of
+// that level start there)
+struct MxSpan {
+    const int32_t *order;
+    int64_t nw;
+    int Qr, cl0;
+};
+
 template <bool DB, int SPLIT, int MT, int WN, int NT>
-void launch_mx(ige_op op, int r, int rc, int nchunk, const __bf16 *G, const __bf16 *Vb, hipStream_t s)
+void launch_mx(ige_op op, int r, int rc, int nchunk, const __bf16 *G, const __bf16 *Vb, hipStream_t s,
+               const MxSpan &sp)
 {
     const DevOp &o = op->view;
-    // launch order: decreasing partner count (default) or cluster order per XCD
-    const bool spatial = tune_get(op, kTuneM2lOrder, r, SPLIT, 0) == 1 && op->n_morder_sp > 0;
-    const int64_t nw = spatial ? op->n_morder_sp : (int64_t)op->mwork.size();
-    const int32_t *order = spatial ? op->d_morder_sp.p : op->d_morder.p;
+    const int64_t nw = sp.nw;
+    const int32_t *order = sp.order;
     const dim3 grid((unsigned)(((nw + 7) / 8) * 8 * nchunk)), blk(128 * WN);
     constexpr int PL = SPLIT == 3 ? 2 : 1, QP = 16 * MT;
     constexpr size_t shm = sizeof(__bf16) * (DB ? 2 : 1) * PL * QP * (2 * QP + IGE_GPAD);
@@ -803,19 +827,19 @@ void launch_mx(ige_op op, int r, int rc, int nchunk, const __bf16 *G, const __bf
         return true;
     }();
     (void)attr;
-    hipLaunchKernelGGL(kern, grid, blk, shm, s, o, r, rc, nchunk, nw, order, op->d_mwork.p, op->d_mpartner.p,
-                       op->d_gslot.p, G, Vb, op->d_bmpart.p);
+    hipLaunchKernelGGL(kern, grid, blk, shm, s, o, r, rc, nchunk, nw, sp.Qr, sp.cl0, order, op->d_mwork.p,
+                       op->d_mpartner.p, op->d_gslot.p, G, Vb, op->d_bmpart.p);
     IGE_HIP(hipGetLastError());
 }
 
 // the rows-merged kernel (k_m2l_mxr): WN waves of NT column tiles
 template <int SPLIT, int MT, int WN, int NT>
-void launch_mxr(ige_op op, int r, int rc, int nchunk, const __bf16 *G, const __bf16 *Vb, hipStream_t s)
+void launch_mxr(ige_op op, int r, int rc, int nchunk, const __bf16 *G, const __bf16 *Vb, hipStream_t s,
+                const MxSpan &sp)
 {
     const DevOp &o = op->view;
-    const bool spatial = tune_get(op, kTuneM2lOrder, r, SPLIT, 0) == 1 && op->n_morder_sp > 0;
-    const int64_t nw = spatial ? op->n_morder_sp : (int64_t)op->mwork.size();
-    const int32_t *order = spatial ? op->d_morder_sp.p : op->d_morder.p;
+    const int64_t nw = sp.nw;
+    const int32_t *order = sp.order;
     const dim3 grid((unsigned)(((nw + 7) / 8) * 8 * nchunk)), blk(64 * WN);
     constexpr int PL = SPLIT == 3 ? 2 : 1, QP = 16 * MT;
     constexpr size_t shm = sizeof(__bf16) * 2 * PL * QP * (2 * QP + IGE_GPAD);
@@ -829,50 +853,51 @@ void launch_mxr(ige_op op, int r, int rc, int nchunk, const __bf16 *G, const __b
         return true;
     }();
     (void)attr;
-    hipLaunchKernelGGL(kern, grid, blk, shm, s, o, r, rc, nchunk, nw, order, op->d_mwork.p, op->d_mpartner.p,
-                       op->d_gslot.p, G, Vb, op->d_bmpart.p);
+    hipLaunchKernelGGL(kern, grid, blk, shm, s, o, r, rc, nchunk, nw, sp.Qr, sp.cl0, order, op->d_mwork.p,
+                       op->d_mpartner.p, op->d_gslot.p, G, Vb, op->d_bmpart.p);
     IGE_HIP(hipGetLastError());
 }
 
 template <bool DB, int SPLIT, int MT>
-void launch_mx_cols(ige_op op, int r, int ncol, const __bf16 *G, const __bf16 *Vb, hipStream_t s)
+void launch_mx_cols(ige_op op, int r, int ncol, const __bf16 *G, const __bf16 *Vb, hipStream_t s, const MxSpan &sp)
 {
     const int rc = ncol / 4, nchunk = (r + rc - 1) / rc;
     // wide double-buffered chunks: the rows-merged kernel (IGE_M2L_RM=0 keeps the other)
     if constexpr (DB) {
         if (op->m2l_rm && ncol == 256 && MT <= 6) {
-            launch_mxr<SPLIT, MT, 8, 2>(op, r, rc, nchunk, G, Vb, s);
+            launch_mxr<SPLIT, MT, 8, 2>(op, r, rc, nchunk, G, Vb, s, sp);
             return;
         }
         if (op->m2l_rm && ncol == 128) {
-            launch_mxr<SPLIT, MT, 8, 1>(op, r, rc, nchunk, G, Vb, s);
+            launch_mxr<SPLIT, MT, 8, 1>(op, r, rc, nchunk, G, Vb, s, sp);
             return;
         }
     }
     switch (ncol) {
-        case 16: launch_mx<DB, SPLIT, MT, 1, 1>(op, r, rc, nchunk, G, Vb, s); break;
-        case 32: launch_mx<DB, SPLIT, MT, 2, 1>(op, r, rc, nchunk, G, Vb, s); break;
-        case 64: launch_mx<DB, SPLIT, MT, 4, 1>(op, r, rc, nchunk, G, Vb, s); break;
+        case 16: launch_mx<DB, SPLIT, MT, 1, 1>(op, r, rc, nchunk, G, Vb, s, sp); break;
+        case 32: launch_mx<DB, SPLIT, MT, 2, 1>(op, r, rc, nchunk, G, Vb, s, sp); break;
+        case 64: launch_mx<DB, SPLIT, MT, 4, 1>(op, r, rc, nchunk, G, Vb, s, sp); break;
         case 128:
-            if constexpr (DB || SPLIT == 1 || MT < 8) launch_mx<DB, SPLIT, MT, 4, 2>(op, r, rc, nchunk, G, Vb, s);
+            if constexpr (DB || SPLIT == 1 || MT < 8) launch_mx<DB, SPLIT, MT, 4, 2>(op, r, rc, nchunk, G, Vb, s, sp);
             else IGE_REQUIRE(false, "coupling chunk too wide for this interpolation degree");
             break;
         default:
-            if constexpr (MT <= 4 || (DB && MT <= 6)) launch_mx<DB, SPLIT, MT, 4, 4>(op, r, rc, nchunk, G, Vb, s);
+            if constexpr (MT <= 4 || (DB && MT <= 6)) launch_mx<DB, SPLIT, MT, 4, 4>(op, r, rc, nchunk, G, Vb, s, sp);
             else IGE_REQUIRE(false, "coupling chunk too wide for this interpolation degree");
             break;
     }
 }
 
 template <bool DB, int SPLIT>
-void launch_mx_mt(ige_op op, int r, int MT, int ncol, const __bf16 *G, const __bf16 *Vb, hipStream_t s)
+void launch_mx_mt(ige_op op, int r, int MT, int ncol, const __bf16 *G, const __bf16 *Vb, hipStream_t s,
+                  const MxSpan &sp)
 {
     switch (MT) {
-        case 2: launch_mx_cols<DB, SPLIT, 2>(op, r, ncol, G, Vb, s); break;
-        case 4: launch_mx_cols<DB, SPLIT, 4>(op, r, ncol, G, Vb, s); break;
-        case 6: launch_mx_cols<DB, SPLIT, 6>(op, r, ncol, G, Vb, s); break;
+        case 2: launch_mx_cols<DB, SPLIT, 2>(op, r, ncol, G, Vb, s, sp); break;
+        case 4: launch_mx_cols<DB, SPLIT, 4>(op, r, ncol, G, Vb, s, sp); break;
+        case 6: launch_mx_cols<DB, SPLIT, 6>(op, r, ncol, G, Vb, s, sp); break;
         default:
-            if constexpr (!DB || SPLIT == 1) launch_mx_cols<DB, SPLIT, 8>(op, r, ncol, G, Vb, s);
+            if constexpr (!DB || SPLIT == 1) launch_mx_cols<DB, SPLIT, 8>(op, r, ncol, G, Vb, s, sp);
             else IGE_REQUIRE(false, "double-buffered coupling blocks do not fit in shared memory");
             break;
     }
@@ -882,16 +907,97 @@ void launch_mx_mt(ige_op op, int r, int MT, int ncol, const __bf16 *G, const __b
 
 int m2l_ncol_limit(ige_op op, int r, int split)
 {
-    const int MT = coupling_qp(op->view.Q) / 16;
+    int Qp = coupling_qp(op->view.Q);
+    if (!op->mxl.empty()) {
+        Qp = 0;
+        for (const auto &L : op->mxl) Qp = std::max(Qp, L.Qp);
+    }
+    const int MT = Qp / 16;
     const bool db = m2l_db_fits(MT, split) && tune_get(op, kTuneM2lDb, r, split, 1) != 0;
     return m2l_ncol_cap(MT, split, db);
 }
+
+namespace {
+// the right factor of clusters cl0 .. cl0 + ncl - 1 (Qr nodes each) for one chunking
+void vb_prep(ige_op op, int cl0, int ncl, int Qr, int r, int rc, int nchunk, int ncol, int Qp, int split,
+             const double2 *src, __bf16 *Vb, hipStream_t s)
+{
+    const DevOp &o = op->view;
+    if (rc <= 64) {   // every element of the chunk's right factor is written (zeros in the padding)
+        const int64_t nb = (int64_t)ncl * nchunk * 4 * (Qp / kVbRows);
+        hipLaunchKernelGGL(k_vb_prep_t, dim3((unsigned)nb), dim3(256), 0, s, o, cl0, Qr, r, rc, nchunk, ncol, Qp, split,
+                           src, Vb);
+    } else {
+        const int64_t nv = (int64_t)ncl * nchunk * ncol * 2 * Qp;
+        hipLaunchKernelGGL(k_vb_prep, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s, o, ncl, cl0, Qr, r, rc,
+                           nchunk, ncol, Qp, split, src, Vb);
+    }
+    IGE_HIP(hipGetLastError());
+}
+
+void mx_run(ige_op op, int r, int split, bool db, int MT, int ncol, const __bf16 *G, const __bf16 *Vb, hipStream_t s,
+            const MxSpan &sp)
+{
+    if (db) {
+        if (split == 3) launch_mx_mt<true, 3>(op, r, MT, ncol, G, Vb, s, sp);
+        else launch_mx_mt<true, 1>(op, r, MT, ncol, G, Vb, s, sp);
+    } else {
+        if (split == 3) launch_mx_mt<false, 3>(op, r, MT, ncol, G, Vb, s, sp);
+        else launch_mx_mt<false, 1>(op, r, MT, ncol, G, Vb, s, sp);
+    }
+}
+
+// a degree per level: per level its padded block size, chunking and launch
+void m2l_bf16_levels(ige_op op, int r, int split, const double2 *src, hipStream_t s, hipEvent_t mid)
+{
+    const DevOp &o = op->view;
+    const int planes = split == 3 ? 2 : 1;
+    const __bf16 *G = split == 3 ? op->d_Gb3.p : op->d_Gb1.p;
+    struct Plan {
+        int MT, ncol, rc, nchunk;
+        bool db;
+        size_t vb_off;
+    };
+    std::vector<Plan> pl(op->mxl.size());
+    size_t vbn = 0;
+    for (size_t i = 0; i < op->mxl.size(); ++i) {
+        const auto &L = op->mxl[i];
+        Plan &P = pl[i];
+        P.MT = L.Qp / 16;
+        IGE_REQUIRE(P.MT <= 8, "interpolation degree too large for the matrix-core coupling");
+        P.db = m2l_db_fits(P.MT, split);
+        P.ncol = m2l_ncol(r, m2l_ncol_cap(P.MT, split, P.db));
+        P.rc = P.ncol / 4;
+        P.nchunk = (r + P.rc - 1) / P.rc;
+        P.vb_off = vbn;
+        vbn += (size_t)L.ncl * P.nchunk * planes * P.ncol * 2 * L.Qp;
+    }
+    if (op->d_vb.n < vbn) op->d_vb.alloc(vbn);
+    const size_t pn = op->mwork.size() * 4 * (size_t)o.Q * r;
+    if (op->d_bmpart.n < pn) op->d_bmpart.alloc(pn);
+    for (size_t i = 0; i < op->mxl.size(); ++i) {
+        const auto &L = op->mxl[i];
+        vb_prep(op, L.cl0, L.ncl, L.Qr, r, pl[i].rc, pl[i].nchunk, pl[i].ncol, L.Qp, split, src,
+                op->d_vb.p + pl[i].vb_off, s);
+    }
+    if (mid) IGE_HIP(hipEventRecord(mid, s));
+    for (size_t i = 0; i < op->mxl.size(); ++i) {
+        const auto &L = op->mxl[i];
+        const MxSpan sp{op->d_morder.p + L.w0, L.nw, L.Qr, L.cl0};
+        mx_run(op, r, split, pl[i].db, pl[i].MT, pl[i].ncol, G + L.gb_off * planes, op->d_vb.p + pl[i].vb_off, s, sp);
+    }
+}
+}  // namespace
 
 void m2l_bf16(ige_op op, int r, int split, const double2 *src, hipStream_t s, hipEvent_t mid)
 {
     const DevOp &o = op->view;
     if (op->mwork.empty()) return;
     ensure_coupling_bf16(op, split);
+    if (!op->mxl.empty()) {
+        m2l_bf16_levels(op, r, split, src, s, mid);
+        return;
+    }
     const int Qp = coupling_qp(o.Q), K2 = 2 * Qp, MT = Qp / 16;
     IGE_REQUIRE(MT <= 8, "interpolation degree too large for the matrix-core coupling");
     // staging (single or double buffer) and chunk width: tuned values if any, else
@@ -907,24 +1013,13 @@ void m2l_bf16(ige_op op, int r, int split, const double2 *src, hipStream_t s, hi
     if (op->d_vb.n < vbn) op->d_vb.alloc(vbn);
     const size_t pn = op->mwork.size() * 4 * (size_t)o.Q * r;
     if (op->d_bmpart.n < pn) op->d_bmpart.alloc(pn);
-    if (rc <= 64) {   // every element of the chunk's right factor is written (zeros in the padding)
-        const int64_t nb = (int64_t)op->NC * nchunk * 4 * (Qp / kVbRows);
-        hipLaunchKernelGGL(k_vb_prep_t, dim3((unsigned)nb), dim3(256), 0, s, o, r, rc, nchunk, ncol, Qp, split, src,
-                           op->d_vb.p);
-    } else {
-        const int64_t nv = (int64_t)op->NC * nchunk * ncol * K2;
-        hipLaunchKernelGGL(k_vb_prep, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s, o, op->NC, r, rc, nchunk,
-                           ncol, Qp, split, src, op->d_vb.p);
-    }
-    IGE_HIP(hipGetLastError());
+    vb_prep(op, 0, op->NC, o.Q, r, rc, nchunk, ncol, Qp, split, src, op->d_vb.p, s);
     if (mid) IGE_HIP(hipEventRecord(mid, s));
-    if (db) {
-        if (split == 3) launch_mx_mt<true, 3>(op, r, MT, ncol, op->d_Gb3.p, op->d_vb.p, s);
-        else launch_mx_mt<true, 1>(op, r, MT, ncol, op->d_Gb1.p, op->d_vb.p, s);
-    } else {
-        if (split == 3) launch_mx_mt<false, 3>(op, r, MT, ncol, op->d_Gb3.p, op->d_vb.p, s);
-        else launch_mx_mt<false, 1>(op, r, MT, ncol, op->d_Gb1.p, op->d_vb.p, s);
-    }
+    // launch order: decreasing partner count (default) or cluster order per XCD
+    const bool spatial = tune_get(op, kTuneM2lOrder, r, split, 0) == 1 && op->n_morder_sp > 0;
+    const MxSpan sp{spatial ? op->d_morder_sp.p : op->d_morder.p, spatial ? op->n_morder_sp : (int64_t)op->mwork.size(),
+                    o.Q, 0};
+    mx_run(op, r, split, db, MT, ncol, split == 3 ? op->d_Gb3.p : op->d_Gb1.p, op->d_vb.p, s, sp);
 }
 
 

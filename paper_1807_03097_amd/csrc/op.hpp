@@ -206,7 +206,16 @@ struct ige_op_s {
     bool near_md_off = false;           // IGE_NEAR_F64=blocks: the unordered-block kernel instead
     int gd_fit = -1;                    // FP64 blocks fit in device memory (-1: not yet decided)
     bool f64mx_off = false;             // FP64 coupling of many columns generated per apply (IGE_M2L_F64=generate)
-    ige::DBuf<int32_t> d_morder;         // work items by decreasing partner count
+    ige::DBuf<int32_t> d_morder;         // work items by decreasing partner count (per level with mxl)
+    // a degree per level: the matrix-core coupling level by level (levels with far pairs)
+    struct MxLevel {
+        int lvl = 0, Qr = 0, Qp = 0;     // level, its nodes, padded block size
+        int64_t p0 = 0, np = 0;          // its unordered pairs [p0, p0 + np)
+        int cl0 = 0, ncl = 0;            // its clusters [cl0, cl0 + ncl)
+        int64_t w0 = 0, nw = 0;          // its work items, d_morder[w0, w0 + nw)
+        size_t gb_off = 0;               // its blocks in the BF16 store, per plane-block unit
+    };
+    std::vector<MxLevel> mxl;
     ige::DBuf<int32_t> d_morder_sp;      // work items in cluster order, one contiguous part per XCD (-1: none)
     int64_t n_morder_sp = 0;
     // split-BF16 near-field product (inner solves): blocks per ordered leaf pair,
@@ -298,6 +307,7 @@ void m2l_stored(ige_op op, int r, int prec, const double2 *src, double2 *loc, hi
 // one column on the context stream (d_src -> d_gpart, then d_gpart -> d_loc)
 void m2l_stored_one(ige_op op, int prec);
 void m2l_stored_reduce_one(ige_op op);
+int coupling_qp(int Q);   // padded block size of the matrix-core coupling (multiple of 32)
 // matrix-core coupling of r columns in BF16 (split 1) or split BF16 (split 3):
 // fields [NC][4][Q][r] -> partials per work item [mwork][4][Q][r] (d_bmpart)
 void m2l_bf16(ige_op op, int r, int split, const double2 *src, hipStream_t s, hipEvent_t mid = nullptr);

@@ -798,11 +798,11 @@ def test_level_degrees_match_oracle(oracle_mod, ctx, case):
 
 
 def test_level_degrees_refusals_and_refined_solve(oracle_mod, ctx):
-    """Operators with a degree per level (and those of one degree above 10) refuse the
-    BF16 couplings (applies, autotuning, refinement inner solves) and stored coupling
-    blocks; FP64 autotuning keeps the results to 1e-13; FP64 refinement around FP32
-    inner solves of one and of three waves reaches the tolerance on the FP64
-    operator."""
+    """Operators with a degree above 10 on a level with far pairs (one degree, or a
+    degree per level) refuse the BF16 couplings (applies, autotuning, refinement inner
+    solves); a degree per level refuses stored coupling blocks; FP64 autotuning keeps
+    the results to 1e-13; FP64 refinement around FP32 inner solves of one and of three
+    waves reaches the tolerance on the FP64 operator."""
     from paper_1807_03097_amd import binding as B
     pats = W.cube_sphere()
     geom = B.Geometry(ctx, pats)
@@ -814,14 +814,19 @@ def test_level_degrees_refusals_and_refined_solve(oracle_mod, ctx):
     op = B.Operator(geom, 2, 4, 8.0, 8, 1.0, 5, 5, 1, q_level=ql)
     x = W.random_coeffs(op.N, 0)
     q11 = B.Operator(geom, 2, 3, 8.0, 11, 1.0, 5, 5, 1)
-    for o_ in (op, q11):
+    tgeom = B.Geometry(ctx, W.torus())
+    q13 = B.Operator(tgeom, 1, 3, 4.0, 8, 1.0, 5, 5, 1, q_level=[4, 13, 5])   # degree 13 on a far level
+    for o_ in (q11, q13):
         for prec in (B.IGE_BF16, B.IGE_BF16X3, B.IGE_BF16X3_ALL):
             with pytest.raises(B.IgeError) as e:
                 o_.apply(W.random_coeffs(o_.N, 0), prec=prec)
             assert e.value.code == B.IGE_EINVAL
         with pytest.raises(B.IgeError):
             o_.autotune(4, B.IGE_BF16X3)
+    with pytest.raises(B.IgeError):
+        q13.solve(W.random_coeffs(q13.N, 1), refine=True, inner_prec=B.IGE_BF16X3)
     q11.close()
+    q13.close()
     X = np.stack([W.random_coeffs(op.N, 40 + c) for c in range(8)])
     y0 = op.apply(X)
     ch = op.autotune(8)
@@ -831,8 +836,6 @@ def test_level_degrees_refusals_and_refined_solve(oracle_mod, ctx):
     F = op.rhs_plane_wave([[0.0, 0.0, 1.0], [0.0, 1.0, 0.0], [1.0, 0.0, 0.0]],
                           [[1.0, 0.0, 0.0], [0.0, 0.0, 1.0], [0.0, 1.0, 0.0]])
     f = F[0]
-    with pytest.raises(B.IgeError):
-        op.solve(f, refine=True, inner_prec=B.IGE_BF16X3)
     xs, st, rc = op.solve(f, tol=1e-8, restart=300, maxit=3000)
     xr, sr, rcr = op.solve(f, tol=1e-8, restart=300, maxit=3000, refine=True, inner_prec=B.IGE_F32)
     _say(f"  FP64 iters {st[0][0]} relres {st[0][2]:.1e}; refined iters {sr[0][0]} relres {sr[0][2]:.1e}")
@@ -849,6 +852,55 @@ def test_level_degrees_refusals_and_refined_solve(oracle_mod, ctx):
         _say(f"  wave {c}: refined iters {s3[c][0]} relres {s3[c][2]:.1e}")
         assert _rel(R[c], F[c]) <= 1.05e-8
     assert _rel(X3[0], xs) <= 1e-4
+    op.close()
+
+
+MQ_CASES = [LQ_CASES[0], LQ_CASES[2], LQ_CASES[3]]
+
+
+@pytest.mark.parametrize("case", MQ_CASES, ids=[f"{c[0]}-q{'.'.join(map(str, c[6]))}" + ("-scalar" if c[7] else "")
+                                                for c in MQ_CASES])
+def test_level_degrees_matrix_core_coupling(oracle_mod, ctx, case):
+    """Degrees per level on the BF16 matrix cores, one launch per level with that
+    level's padded block size (and its own column chunking): plain BF16 within
+    2^-9-level error of the oracle, split BF16 within 2^-16-level error, on 1, 11 and 70
+    columns (a ragged chunk) against the FP64 product; FP64 refinement around
+    split-BF16 inner solves reaches the FP64 tolerance and the FP64 solution."""
+    from paper_1807_03097_amd import binding as B
+    name, p, m, kappa, eta, d, ql, scalar = case
+    _say(f"case {case}")
+    pats = _geom(name)
+    geom = B.Geometry(ctx, pats)
+    kind = B.IGE_OP_SCALAR if scalar else B.IGE_OP_EFIE
+    op = B.Operator(geom, p, m, kappa, 8, eta, 5, 5, d, kind=kind, q_level=ql)
+    o = oracle_mod.Oracle(pats, p, m, kappa, g=5, gs=5, scalar=scalar)
+    X = np.stack([W.random_coeffs(op.N, 600 + c) for c in range(70)])
+    yo = o.fmm_apply(X[0], ql, eta, d)
+    Y11, Y70 = op.apply(X[:11].copy()), op.apply(X)
+    assert _rel(Y11[0], yo) <= TOL
+    for prec, lo, hi in ((B.IGE_BF16, 1e-6, 1e-2), (B.IGE_BF16X3, 1e-12, 2e-4), (B.IGE_BF16X3_ALL, 1e-12, 2e-4)):
+        e1 = _rel(op.apply(X[0].copy(), prec=prec), yo)
+        Y = op.apply(X[:11].copy(), prec=prec)
+        eb = max(_rel(Y[c], Y11[c]) for c in range(11))
+        Z = op.apply(X, prec=prec)
+        e70 = max(_rel(Z[c], Y70[c]) for c in range(70))
+        _say(f"  prec {prec}: 1 column {e1:.2e}, worst of 11 {eb:.2e}, worst of 70 {e70:.2e}")
+        assert lo < e1 <= hi and eb <= hi and e70 <= hi
+    if scalar:
+        F = op.rhs_scalar(B.IGE_RHS_POINT, [[0.1, 0.2, -0.15], [0.3, -0.1, 0.2]])
+    else:
+        dirs, pols = W.fibonacci_plane_waves(2)
+        F = op.rhs_plane_wave(dirs, pols)
+    X64, st64, rc = op.solve(F, tol=1e-8, restart=300, maxit=4000)
+    assert rc == 0
+    Xr, st, rc2 = op.solve(F, tol=1e-8, restart=300, maxit=8000, refine=True, inner_tol=1e-4,
+                           inner_prec=B.IGE_BF16X3)
+    assert rc2 == 0
+    R = op.apply(Xr)
+    for c in range(2):
+        _say(f"  wave {c}: FP64 iters {st64[c][0]}, refined iters {st[c][0]} outer {st[c][1]} relres {st[c][2]:.1e}")
+        assert st[c][2] <= 1.05e-8 and _rel(R[c], F[c]) <= 1.05e-8
+        assert _rel(Xr[c], X64[c]) <= 1e-4
     op.close()
 
 
