@@ -452,8 +452,9 @@ __global__ __launch_bounds__(kM2LThreadsB) void k_m2l_b(DevOp o, int r, const M2
     const int tid = threadIdx.x;
     const int mt = tid % TPG, sp = tid / TPG;
     const bool active = sp < S;
-    T *sX = reinterpret_cast<T *>(smd);                        // [3][Q]
-    C *sV = reinterpret_cast<C *>(smd + (3 * Q * (int)sizeof(T) + 15) / 16 * 2);   // [4][Q][kRB], after sX
+    // node-major staging, so one address (and immediate offsets) reaches a node's data
+    T *sX = reinterpret_cast<T *>(smd);                        // [Q][4]: x, y, z, unused
+    C *sV = reinterpret_cast<C *>(smd + (4 * Q * (int)sizeof(T) + 15) / 16 * 2);   // [Q][4][kRB], after sX
     double2 *red = reinterpret_cast<double2 *>(smd);           // [S][Q][kRB] (one field at a time)
     __shared__ double2 sTab[256];                               // (cos, sin)(j pi/128), FP64 only
     if constexpr (sizeof(T) == 8)
@@ -484,15 +485,15 @@ __global__ __launch_bounds__(kM2LThreadsB) void k_m2l_b(DevOp o, int r, const M2
         __syncthreads();
         const double *Xs = o.nodeX + (size_t)sc * 3 * Qs;
         const double2 *Vs = src + (size_t)sc * 4 * Qs * r;
-        for (int i = tid; i < 3 * Q; i += kM2LThreadsB) sX[i] = (T)Xs[(i / Q) * Qs + i % Q];
+        for (int i = tid; i < 3 * Q; i += kM2LThreadsB) sX[(i % Q) * 4 + i / Q] = (T)Xs[(i / Q) * Qs + i % Q];
         for (int i = tid; i < 4 * Q * kRB; i += kM2LThreadsB) {
-            const int c = i % kRB, fm = i / kRB;
-            sV[i] = c < nc ? dm::to_c(Vs[((size_t)(fm / Q) * Qs + fm % Q) * r + c0 + c], T(0)) : C{0, 0};
+            const int c = i % kRB, fm = i / kRB, f = fm / Q, m = fm % Q;
+            sV[((size_t)m * 4 + f) * kRB + c] = c < nc ? dm::to_c(Vs[((size_t)f * Qs + m) * r + c0 + c], T(0)) : C{0, 0};
         }
         __syncthreads();
         if (active) {
             for (int ms = mb; ms < me; ++ms) {
-                const T x0 = sX[ms], x1 = sX[Q + ms], x2 = sX[2 * Q + ms];
+                const T x0 = sX[4 * ms], x1 = sX[4 * ms + 1], x2 = sX[4 * ms + 2];
                 C G[kNTB];
 #pragma unroll
                 for (int t = 0; t < kNTB; ++t) {
@@ -502,7 +503,7 @@ __global__ __launch_bounds__(kM2LThreadsB) void k_m2l_b(DevOp o, int r, const M2
                 }
 #pragma unroll
                 for (int f = 0; f < 4; ++f) {
-                    const C *vf = sV + ((size_t)f * Q + ms) * kRB;
+                    const C *vf = sV + ((size_t)ms * 4 + f) * kRB;
 #pragma unroll
                     for (int c = 0; c < kRB; ++c) {
                         const C v = vf[c];
@@ -937,7 +938,7 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
                     const int S = std::max(1, std::min(kM2LThreadsB / TPG, Ql));
                     per = std::max(per, std::max(sizeof(double2) * 4 * Ql, sizeof(double2) * (size_t)S * Ql));
                 }
-                const size_t fixed = sizeof(double) * (3 * o.Q + 1);
+                const size_t fixed = sizeof(double) * 4 * o.Q;
                 // registers: 3 targets x 4 fields x rb columns; a tuned value may only lower it
                 const int rbmax = std::min(4, pick_rb(per, fixed, kLdsMax));
                 const int rb = std::min(rbmax, tune_get(op, kTuneM2lRb, r, prec, rbmax));
