@@ -575,7 +575,8 @@ def main():
             alg = info.near_distinct * 16 + 2 * N * 16
             t_ms = stage_ms["near_blk"]
             achieved = alg / (t_ms * 1e-3) / 1e9
-            return {"kernel": "k_near_cmp", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+            kname = "k_near_cmp1" if os.environ.get("IGE_NEAR_ONE", "1") != "0" else "k_near_cmp"
+            return {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_ref,
                     "traffic_over_algorithmic": None if traffic_ref is None else traffic_ref / alg,
                     "algorithmic_bytes": int(alg), "near_distinct_entries": int(info.near_distinct),

@@ -133,6 +133,20 @@ __global__ __launch_bounds__(256) void k_near_cmp(NearCmpView v, int64_t obase, 
     near_cmp_item<U, RS, PRIO>(v, v.order[obase + blockIdx.x], x, part, sxr, syc);
 }
 
+// Both kinds of work items in one launch: the nw wide ones first (launch order
+// positions na .. na + nw - 1, UW column groups per lane), then the na narrow ones
+// (two column groups); one launch tail instead of two
+template <int UW, int PRIO>
+__global__ __launch_bounds__(256) void k_near_cmp1(NearCmpView v, int64_t na, int64_t nw, const double2 *x,
+                                                   double2 *part)
+{
+    __shared__ double2 sxr[kCmpRows];
+    __shared__ double2 syc[3][256];
+    const int64_t b = blockIdx.x;
+    if (b < nw) near_cmp_item<UW, 2, PRIO>(v, v.order[na + b], x, part, sxr, syc);
+    else near_cmp_item<2, 2, PRIO>(v, v.order[b - nw], x, part, sxr, syc);
+}
+
 // Values of the once-per-entry near field: entry (i, j) is the sum over the leaf
 // slots holding i and those holding j (ascending) of the leaf-pair block entries,
 // (B_ts)[slot_t(i)][slot_s(j)] for t <= s and (B_st)[slot_s(j)][slot_t(i)] for t > s,
@@ -196,6 +210,13 @@ void launch_near_once(ige_op op, const double2 *x, double2 *part, hipStream_t st
     const dim3 blk(256);
     const int64_t na = op->cmp.nnarrow, nw = v.nwork - na;
     const bool pr = op->near_prio > 0;
+    if (op->near_one && op->cmp_rs == 2 && (op->cmp.maxn + 63) / 64 <= 3 && na + nw > 0) {
+        const dim3 grid((unsigned)(na + nw));
+        if (pr) hipLaunchKernelGGL((k_near_cmp1<3, 1>), grid, blk, 0, st, v, na, nw, x, part);
+        else hipLaunchKernelGGL((k_near_cmp1<3, 0>), grid, blk, 0, st, v, na, nw, x, part);
+        IGE_HIP(hipGetLastError());
+        return;
+    }
     if (na > 0) {
         const dim3 grid((unsigned)na);
         if (op->cmp_rs == 4) {

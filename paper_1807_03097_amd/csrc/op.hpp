@@ -129,6 +129,10 @@ struct ige_op_s {
     // workgroup per item); two leave room for the near field's workgroups beside it
     // (C2: 0.1793 against 0.1812 ms per apply, four runs each)
     int m2l_persist = 2;
+    // once-per-entry near field: both item widths in one launch (C2, beside the coupling:
+    // 0.1757 against 0.1797 ms per apply, four runs each; alone it is slower, 76 against
+    // 70 us, with the registers of the wider items)
+    bool near_one = true;
     bool near_first = false;           // overlap: near field beside the upward pass only, then the coupling alone
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int64_t prof_count = 0;
