@@ -136,9 +136,10 @@ __global__ __launch_bounds__(256) void k_near_cmp(NearCmpView v, int64_t obase, 
 // Both kinds of work items in one launch: the nw wide ones first (launch order
 // positions na .. na + nw - 1, UW column groups per lane), then the na narrow ones
 // (two column groups); one launch tail instead of two
+// (at most 96 registers, five waves per SIMD: alone 73 against 76 us at 102)
 template <int UW, int PRIO>
-__global__ __launch_bounds__(256) void k_near_cmp1(NearCmpView v, int64_t na, int64_t nw, const double2 *x,
-                                                   double2 *part)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_near_cmp1(
+    NearCmpView v, int64_t na, int64_t nw, const double2 *x, double2 *part)
 {
     __shared__ double2 sxr[kCmpRows];
     __shared__ double2 syc[3][256];
