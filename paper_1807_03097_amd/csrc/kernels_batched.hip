@@ -705,16 +705,21 @@ __global__ __launch_bounds__(256) void k_l2p_leaf_b(DevOp o, int r, const double
     double2 *W0 = sm2;                    // [Q1][RL][kRB]
     double2 *W1 = W0 + Q1 * RL * kRB;
     double2 *W1d = W1 + Q1 * RL * kRB;
+    double2 *T3 = W1d + Q1 * RL * kRB;    // the leaf's three fields [3][Q][kRB], read once
     const int w1a = s + p, w1b = s + p - 1;
+    for (int i = threadIdx.x; i < 3 * Q * kRB; i += blockDim.x) {
+        const int c = i % kRB, tt = i / kRB;
+        T3[i] = c < nc ? t[(size_t)tt * r + c0 + c] : make_double2(0, 0);
+    }
+    __syncthreads();
     for (int i = threadIdx.x; i < Q1 * RL * kRB; i += blockDim.x) {
         const int c = i % kRB, tt = i / kRB, m2 = tt / RL, i1 = tt % RL;
         double2 a = make_double2(0, 0), b = make_double2(0, 0), bd = make_double2(0, 0);
         if (c < nc)
             for (int m1 = 0; m1 < Q1; ++m1) {
-                const size_t col = c0 + c;
-                const double2 f1 = t[((size_t)0 * Q + m2 * Q1 + m1) * r + col];
-                const double2 f2 = t[((size_t)1 * Q + m2 * Q1 + m1) * r + col];
-                const double2 fd = t[((size_t)2 * Q + m2 * Q1 + m1) * r + col];
+                const double2 f1 = T3[((0 * Q + m2 * Q1 + m1)) * kRB + c];
+                const double2 f2 = T3[((1 * Q + m2 * Q1 + m1)) * kRB + c];
+                const double2 fd = T3[((2 * Q + m2 * Q1 + m1)) * kRB + c];
                 if (i1 < w1a) a = caddb(a, caddb(cscaleb(Mpu[m1 * RL + i1], f1), cscaleb(Mdu[m1 * RL + i1], fd)));
                 if (i1 < w1b) {
                     b = caddb(b, cscaleb(Mqu[m1 * RL + i1], f2));
@@ -755,12 +760,18 @@ __global__ __launch_bounds__(256) void k_l2p_leaf_sc_b(DevOp o, int r, const dou
     const int gc = (int)o.lvl_off[o.L] + id;
     const double2 *t = loc + ((size_t)gc * 3 + 2) * Q * r;
     const double *Mpu = o.Mp + (size_t)k1 * Q1 * RL, *Mpv = o.Mp + (size_t)k2 * Q1 * RL;
-    double2 *Wm = sm2;   // [Q1 (m2)][W (i1)][kRB]
+    double2 *Wm = sm2;                    // [Q1 (m2)][W (i1)][kRB]
+    double2 *Td = Wm + Q1 * W * kRB;      // the leaf's field [Q][kRB], read once
+    for (int i = threadIdx.x; i < Q * kRB; i += blockDim.x) {
+        const int c = i % kRB, tt = i / kRB;
+        Td[i] = c < nc ? t[(size_t)tt * r + c0 + c] : make_double2(0, 0);
+    }
+    __syncthreads();
     for (int i = threadIdx.x; i < Q1 * W * kRB; i += blockDim.x) {
         const int c = i % kRB, tt = i / kRB, m2 = tt / W, i1 = tt % W;
         double2 a = make_double2(0, 0);
         if (c < nc)
-            for (int m1 = 0; m1 < Q1; ++m1) a = caddb(a, cscaleb(Mpu[m1 * RL + i1], t[(size_t)(m2 * Q1 + m1) * r + c0 + c]));
+            for (int m1 = 0; m1 < Q1; ++m1) a = caddb(a, cscaleb(Mpu[m1 * RL + i1], Td[(m2 * Q1 + m1) * kRB + c]));
         Wm[i] = a;
     }
     __syncthreads();
@@ -984,13 +995,13 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
         }
         mark(5);
         if (o.scalar) {
-            const size_t per = sizeof(double2) * (size_t)o.Q1 * w1a;
-            const int rb = pick_rb(per);
+            const size_t per = sizeof(double2) * ((size_t)o.Q1 * w1a + (size_t)o.Q);
+            const int rb = pick_rb(per, 0, kLdsMax);
             IGE_RB_SWITCH(rb, k_l2p_leaf_sc_b, dim3(nleaf, chunks(rb)), dim3(256), per * rb, s, o, r, op->d_bloc.p,
                           op->d_bybuf.p);
-        } else {
-            const size_t per = sizeof(double2) * 3 * (size_t)o.Q1 * o.rowlen;
-            const int rb = pick_rb(per);
+        } else {   // three intermediates and the staged fields
+            const size_t per = sizeof(double2) * (3 * (size_t)o.Q1 * o.rowlen + 3 * (size_t)o.Q);
+            const int rb = pick_rb(per, 0, kLdsMax);
             IGE_RB_SWITCH(rb, k_l2p_leaf_b, dim3(nleaf, chunks(rb)), dim3(256), per * rb, s, o, r, op->d_bloc.p,
                           op->d_bybuf.p);
         }
