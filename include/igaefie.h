@@ -307,7 +307,12 @@ typedef struct {
                         a step that reduces the FP64 residual by less than 1/2 while its
                         inner solve claimed twice as much is undone on the columns that
                         got worse and the inner precision moves towards FP64
-                        (IGE_BF16X3_ALL or IGE_BF16 -> IGE_BF16X3 -> IGE_F64); with
+                        (IGE_BF16X3_ALL or IGE_BF16 -> IGE_BF16X3 -> IGE_F64, and
+                        IGE_F32 -> IGE_F64); one right-hand side (r = 1) runs the BF16
+                        inner precisions as IGE_F32 (the matrix-core coupling would use
+                        one of its 16 columns; the one-column FP32 coupling is faster
+                        there and more accurate; IGE_SINGLE_INNER=asked keeps the asked
+                        precision); with
                         inner_tol >= 1e-5 the inner solves store their Krylov basis in
                         FP32 (sums, the vector being orthogonalised and the correction
                         in FP64; IGE_INNER_BASIS=fp64 keeps the basis in FP64) */

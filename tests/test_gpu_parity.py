@@ -437,20 +437,45 @@ def test_autotune_keeps_results(ctx, prec):
 
 def test_refinement_escalates_inner_precision(ctx):
     """Plain BF16 inner solves cannot reach 1e-10 alone (the inner operator's error
-    times the condition number is too large); the refined solve moves the inner
-    precision towards FP64 and meets the tolerance on the FP64 operator."""
+    times the condition number is too large); the refined solve of two waves moves the
+    inner precision towards FP64 and meets the tolerance on the FP64 operator."""
     from paper_1807_03097_amd import binding as B
     geom = B.Geometry(ctx, _geom("sphere"))
     op = B.Operator(geom, 2, 3, 8.0, 8, 1.6, 5, 5, 1)
-    dirs, pols = W.fibonacci_plane_waves(1)
+    dirs, pols = W.fibonacci_plane_waves(2)
     F = op.rhs_plane_wave(dirs, pols)
     X64, st64, rc = op.solve(F, tol=1e-10, restart=100, maxit=4000)
     assert rc == 0
     Xr, st, rc2 = op.solve(F, tol=1e-10, restart=100, maxit=12000, refine=True, inner_tol=1e-4,
                            inner_prec=B.IGE_BF16)
-    _say(f"  FP64 iters {st64[0][0]}, BF16-start refined iters {st[0][0]} outer {st[0][1]} relres {st[0][2]:.2e}")
-    assert rc2 == 0 and st[0][2] <= 1.05e-10
-    assert _rel(Xr[0], X64[0]) <= 1e-6
+    for c in range(2):
+        _say(f"  FP64 iters {st64[c][0]}, BF16-start refined iters {st[c][0]} outer {st[c][1]} relres {st[c][2]:.2e}")
+        assert st[c][2] <= 1.05e-10
+        assert _rel(Xr[c], X64[c]) <= 1e-6
+    assert rc2 == 0
+    op.close()
+
+
+def test_single_wave_inner_solves_run_in_fp32(ctx, monkeypatch):
+    """One right-hand side: refinement with a BF16 inner precision runs its inner solves
+    as FP32 (the same iterations and bits as inner_prec = FP32); IGE_SINGLE_INNER=asked
+    keeps the BF16 inner operator (different iterates); all meet the FP64 tolerance."""
+    from paper_1807_03097_amd import binding as B
+    geom = B.Geometry(ctx, _geom("sphere"))
+    op = B.Operator(geom, 2, 3, 8.0, 8, 1.6, 5, 5, 1)
+    dirs, pols = W.fibonacci_plane_waves(1)
+    f = op.rhs_plane_wave(dirs, pols)[0]
+    x32, s32, rc32 = op.solve(f, tol=1e-8, restart=200, maxit=4000, refine=True, inner_prec=B.IGE_F32)
+    xb, sb, rcb = op.solve(f, tol=1e-8, restart=200, maxit=4000, refine=True, inner_prec=B.IGE_BF16X3)
+    monkeypatch.setenv("IGE_SINGLE_INNER", "asked")
+    xa, sa, rca = op.solve(f, tol=1e-8, restart=200, maxit=4000, refine=True, inner_prec=B.IGE_BF16X3)
+    monkeypatch.delenv("IGE_SINGLE_INNER")
+    _say(f"  FP32 inner {s32[0][0]} iterations, BF16X3 asked {sb[0][0]}, BF16X3 kept {sa[0][0]}")
+    assert rc32 == 0 and rcb == 0 and rca == 0
+    assert np.array_equal(xb, x32) and sb[0][0] == s32[0][0]
+    assert not np.array_equal(xa, x32)
+    for st in (s32, sb, sa):
+        assert st[0][2] <= 1.05e-8
     op.close()
 
 
