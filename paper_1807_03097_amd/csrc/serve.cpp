@@ -254,9 +254,10 @@ struct ige_srv_s {
             {
                 std::unique_lock<std::mutex> lk(mu);
                 cv_work.wait(lk, [&] {
-                    if (drop) return true;   // free it outside the lock first
                     grp = pick(w, &drop);
-                    return !grp.empty() || (stop && queue.empty());
+                    // a dropped resident operator is freed at once, outside the lock (its
+                    // bytes already left in_use, so the memory must follow)
+                    return drop || !grp.empty() || (stop && queue.empty());
                 });
                 if (!grp.empty()) {
                     Resident &R = resident[w];
