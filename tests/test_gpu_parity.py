@@ -670,9 +670,9 @@ NEAR_ONCE_CASES = [CASES[0], CASES[2], CASES[4], CASES[5], CASES[7], CASES[9], C
                          ids=[f"{c[0]}-p{c[1]}-m{c[2]}-eta{c[5]}-d{c[6]}" for c in NEAR_ONCE_CASES])
 def test_near_once_per_entry_equals_leaf_pair_blocks(oracle_mod, ctx, case, monkeypatch):
     """The one-column near-field product over the distinct entries of the symmetric
-    matrix (owner blocks, upper triangles of the diagonal squares) equals the product
-    over the leaf-pair blocks and their transposes up to summation order, and the
-    whole apply matches the oracle."""
+    matrix (owner blocks, upper triangles of the diagonal squares), in one launch and in
+    two (IGE_NEAR_ONE=0), equals the product over the leaf-pair blocks and their
+    transposes up to summation order, and the whole apply matches the oracle."""
     from paper_1807_03097_amd import binding as B
     name, p, m, kappa, q, eta, d, g, gs = case
     _say(f"case {case}")
@@ -682,12 +682,17 @@ def test_near_once_per_entry_equals_leaf_pair_blocks(oracle_mod, ctx, case, monk
     op0 = B.Operator(geom, p, m, kappa, q, eta, g, gs, d)
     monkeypatch.delenv("IGE_NEAR_COMPACT")
     op1 = B.Operator(geom, p, m, kappa, q, eta, g, gs, d)
-    ys0, ys1 = [], []
+    monkeypatch.setenv("IGE_NEAR_ONE", "0")
+    op2 = B.Operator(geom, p, m, kappa, q, eta, g, gs, d)
+    monkeypatch.delenv("IGE_NEAR_ONE")
+    ys0, ys1, ys2 = [], [], []
     for seed in range(3):
         x = W.random_coeffs(op1.N, seed)
         ys0.append(op0.apply(x))
         ys1.append(op1.apply(x))
-    err = max(_rel(a, b) for a, b in zip(ys1, ys0))
+        ys2.append(op2.apply(x))
+    err = max(max(_rel(a, b) for a, b in zip(ys1, ys0)), max(_rel(a, b) for a, b in zip(ys2, ys0)))
+    op2.close()
     x = W.random_coeffs(op1.N, 0)
     dd = d if d >= 0 else int(np.ceil(np.log2((q + 1) / (p + 1)) - 1e-12))
     yo = oracle_mod.Oracle(pats, p, m, kappa, g=g, gs=gs).fmm_apply(x, q, eta, dd)
