@@ -1832,8 +1832,8 @@ void launch_m2l(ige_op op, int prec)
     size_t shm = m2l_shared_bytes(o.Q);   // the largest over the levels' node counts
     for (int lvl = 0; lvl <= o.L; ++lvl) shm = std::max(shm, m2l_shared_bytes((o.ql[lvl] + 1) * (o.ql[lvl] + 1)));
     shm = std::max(shm, op->m2l_lds);
-    // k = IGE_M2L_PERSIST (default 2) workgroups per CU loop over the work items, room
-    // for the near field's workgroups beside them; 0: one workgroup per item
+    // k = IGE_M2L_PERSIST workgroups per CU loop over the work items (room for the near
+    // field's workgroups beside them); 0 (default): one workgroup per item
     const int nwork = (int)op->work.size();
     int grid = nwork;
     if (op->m2l_persist > 0) {

@@ -126,9 +126,10 @@ struct ige_op_s {
     // the downward pass starts there, since coarser moments and expansions are unused
     int lfar = 0;
     // one-column coupling: workgroups per CU looping over the work items (0: one
-    // workgroup per item); two leave room for the near field's workgroups beside it
-    // (C2: 0.1793 against 0.1812 ms per apply, four runs each)
-    int m2l_persist = 2;
+    // workgroup per item).  Two gain 1 % on one apply beside the near field (C2: 0.1793
+    // against 0.1812 ms) but lose 20 % when several solves share the device (serving,
+    // 32 requests on 4 workers: 0.211 against 0.266 solves/s), so the default is 0
+    int m2l_persist = 0;
     // once-per-entry near field: both item widths in one launch (C2, beside the coupling:
     // 0.1757 against 0.1797 ms per apply, four runs each; alone it is slower, 76 against
     // 70 us, with the registers of the wider items)
