@@ -971,6 +971,35 @@ def test_high_kappa_rows_match_dense_with_level_degrees(oracle_mod, ctx, name):
     op.close()
 
 
+@pytest.mark.parametrize("case", [("sphere", 1, 3, 4.0, 6, 0.3, 0, 4, 4), ("sphere", 2, 3, 4.0, 8, 0.5, 1, 4, 4),
+                                  ("sphere", 1, 3, 4.0, 6, 0.5, 0, 4, 4)],
+                         ids=["far-on-leaves-only-d0", "far-on-leaves-only-d1", "far-on-two-finest"])
+def test_far_pairs_on_fine_levels_only(oracle_mod, ctx, case):
+    """Partitions whose coarse levels have no far pairs (small eta): the upward pass
+    stops at the coarsest level with far pairs and the downward pass starts there (no
+    M2M or L2L at all when only the leaves have far pairs); one and 11 columns in FP64
+    and split BF16 match the oracle."""
+    from paper_1807_03097_amd import binding as B
+    name, p, m, kappa, q, eta, d, g, gs = case
+    _say(f"case {case}")
+    pats = _geom(name)
+    geom = B.Geometry(ctx, pats)
+    op = B.Operator(geom, p, m, kappa, q, eta, g, gs, d)
+    far = op.partition()["far"]
+    levels = sorted(set(far[:, 0].tolist()))
+    assert levels[0] > 0
+    o = oracle_mod.Oracle(pats, p, m, kappa, g=g, gs=gs)
+    X = np.stack([W.random_coeffs(op.N, 700 + c) for c in range(11)])
+    yo = o.fmm_apply(X[0], q, eta, d)
+    y1 = op.apply(X[0].copy())
+    Y = op.apply(X)
+    e1, eb = _rel(y1, yo), max(_rel(Y[c], op.apply(X[c].copy())) for c in (0, 5, 10))
+    es = _rel(op.apply(X, prec=B.IGE_BF16X3)[0], yo)
+    _say(f"  far levels {levels}, N={op.N}: 1 column {e1:.1e}, 11 columns vs single {eb:.1e}, split BF16 {es:.1e}")
+    assert e1 <= TOL and _rel(Y[0], yo) <= TOL and eb <= 1e-13 and 1e-12 < es <= 2e-4
+    op.close()
+
+
 def test_edge_and_degenerate_cases(oracle_mod, ctx):
     """Degenerate inputs through the C ABI: zero columns are refused; a zero density
     gives exactly zero (product, right-hand side of zero polarisation, solve, potential);
