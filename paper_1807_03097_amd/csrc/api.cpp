@@ -575,6 +575,7 @@ ige_op ige::assemble_on(ige_ctx ctx, const ige_geom_s *geom, const ige_params &p
             if (const char *e = std::getenv("IGE_OVERLAP")) op->overlap = std::atoi(e) != 0;
             if (const char *e = std::getenv("IGE_NEAR_FIRST")) op->near_first = std::atoi(e) != 0;
             if (const char *e = std::getenv("IGE_NEAR_ONE")) op->near_one = std::atoi(e) != 0;
+            if (const char *e = std::getenv("IGE_BATCH_OVERLAP")) op->batch_overlap = std::max(0, std::min(2, std::atoi(e)));
             if (const char *e = std::getenv("IGE_M2L_PERSIST")) op->m2l_persist = std::max(0, std::min(16, std::atoi(e)));
             op->lfar = T.far.empty() ? T.L + 1 : T.far.front()[0];   // far pairs sorted by level
             std::vector<int32_t> partner;

@@ -878,9 +878,10 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
 {
     const DevOp &o = op->view;
     hipStream_t s = lstream(op);
-    auto mark = [&](int i) {
-        if (ev && prof_records(op, i)) IGE_HIP(hipEventRecord(ev[i], s));
+    auto mark_on = [&](int i, hipStream_t st) {
+        if (ev && prof_records(op, i)) IGE_HIP(hipEventRecord(ev[i], st));
     };
+    auto mark = [&](int i) { mark_on(i, s); };
     const int64_t N = o.N;
     const int64_t tot = N * r;
     auto chunks = [&](int rb) { return (r + rb - 1) / rb; };
@@ -888,6 +889,26 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
         transpose_cols(s, N, r, x, xt, true);
     }
     const bool far = !op->work.empty();
+    // the near-field product on the operator's second stream beside the far field,
+    // joined before the gather (batch_overlap 1: from the start, 2: after M2M)
+    const int ovl = far && op->overlap ? op->batch_overlap : 0;
+    hipStream_t s2 = op->aux;
+    auto near = [&](hipStream_t st) {
+        mark_on(7, st);
+        if (prec == IGE_BF16X3_ALL) near_bf16(op, r, xt, yt, st);
+        else if (near_f64mx_ok(op, r)) near_f64mx(op, r, xt, yt, st);
+        else if (r >= 8 && near_mfma_mtw_ok(o.nF, o.rc)) near_batched_mfma(op, r, xt, yt, st);
+        else near_batched(op, r, xt, yt, st);
+        mark_on(11, st);
+        mark_on(8, st);
+    };
+    auto fork_near = [&] {
+        IGE_HIP(hipEventRecord(op->ev_fork, s));
+        IGE_HIP(hipStreamWaitEvent(s2, op->ev_fork, 0));
+        near(s2);
+        IGE_HIP(hipEventRecord(op->ev_join, s2));
+    };
+    if (ovl == 1) fork_near();
     mark(0);
     if (far) {
         const int nleaf = o.P * o.SL * o.SL;
@@ -922,6 +943,7 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
                               op->d_bmom.p, op->d_bsrc.p);
             }
         mark(2);
+        if (ovl == 2) fork_near();
         if (prec == IGE_BF16 || prec == IGE_BF16X3 || prec == IGE_BF16X3_ALL) {
             m2l_bf16(op, r, prec == IGE_BF16 ? 1 : 3, op->d_bsrc.p, s, ev ? ev[12] : nullptr);
             mark(3);
@@ -1010,13 +1032,8 @@ void apply_batched(ige_op op, int r, const double2 *x, double2 *y, double2 *xt, 
         for (int i = 1; i <= 6; ++i) mark(i);
         mark(12);
     }
-    mark(7);
-    if (prec == IGE_BF16X3_ALL) near_bf16(op, r, xt, yt, s);
-    else if (near_f64mx_ok(op, r)) near_f64mx(op, r, xt, yt, s);
-    else if (r >= 8 && near_mfma_mtw_ok(o.nF, o.rc)) near_batched_mfma(op, r, xt, yt, s);
-    else near_batched(op, r, xt, yt, s);
-    mark(11);
-    mark(8);
+    if (ovl) IGE_HIP(hipStreamWaitEvent(s, op->ev_join, 0));
+    else near(s);
     mark(9);
     if (far) {
         hipLaunchKernelGGL(k_l2p_gather_b, dim3((tot + 255) / 256), dim3(256), 0, s, o, r, op->d_bybuf.p, yt);

@@ -451,15 +451,16 @@ void plan_near_bf16(ige_op op, const std::vector<int32_t> &pair, const std::vect
     op->d_nbred_idx.upload(idx, s);
 }
 
-void ensure_near_bf16(ige_op op)
+// the split-BF16 blocks, made on first use on the stream of the product that reads them
+void ensure_near_bf16(ige_op op, hipStream_t s)
 {
     if (op->d_nb3.p || op->view.nblk == 0) return;
     const DevOp &o = op->view;
     const int Qp = near_qp(o.nF);
     op->d_nb3.alloc((size_t)2 * o.nblk * 2 * Qp * 2 * Qp);
     const int64_t n = 2 * o.nblk * (int64_t)Qp * Qp;
-    hipLaunchKernelGGL(k_nb_store, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, op->ctx->stream, o.bval, o.nblk,
-                       o.nF, Qp, op->d_nb3.p);
+    hipLaunchKernelGGL(k_nb_store, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, o.bval, o.nblk, o.nF, Qp,
+                       op->d_nb3.p);
     IGE_HIP(hipGetLastError());
 }
 
@@ -493,7 +494,7 @@ void near_bf16(ige_op op, int r, const double2 *xt, double2 *yt, hipStream_t s)
 {
     const DevOp &o = op->view;
     IGE_REQUIRE(near_bf16_ok(o.nF), "near-field blocks too large for the split-BF16 product");
-    ensure_near_bf16(op);
+    ensure_near_bf16(op, s);
     const int Qp = near_qp(o.nF);
     int NT = tune_get(op, kTuneNearBxNt, r, 0, r > 32 ? 4 : (r > 16 ? 2 : 1));
     if (NT != 1 && NT != 2) NT = 4;

@@ -134,6 +134,9 @@ struct ige_op_s {
     // 0.1757 against 0.1797 ms per apply, four runs each; alone it is slower, 76 against
     // 70 us, with the registers of the wider items)
     bool near_one = true;
+    // many columns: the near-field product on the second stream beside the far field
+    // (0: in line after it, 1: from the start, 2: after M2M)
+    int batch_overlap = 1;
     bool near_first = false;           // overlap: near field beside the upward pass only, then the coupling alone
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int64_t prof_count = 0;
@@ -327,7 +330,7 @@ bool m2l_f64mx_use(ige_op op, int r);
 int m2l_ncol_limit(ige_op op, int r, int split);
 // split-BF16 near-field product (yt = near part of A x, [N][r] layout)
 void plan_near_bf16(ige_op op, const std::vector<int32_t> &pair, const std::vector<int32_t> &leafdof, int nF);
-void ensure_near_bf16(ige_op op);
+void ensure_near_bf16(ige_op op, hipStream_t s);
 int near_bf16_ok(int nF);
 void near_bf16(ige_op op, int r, const double2 *xt, double2 *yt, hipStream_t s);
 // FP64 near field of r >= 56 columns on the FP64 matrix cores (ordered-pair FP64 blocks)
