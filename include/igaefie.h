@@ -127,8 +127,9 @@ int ige_geom_destroy(ige_geom geom);
  *                 blocks, with diam_l from ige_op_info of the planned operator.  With
  *                 degrees that differ between levels the generated FP64/FP32 coupling
  *                 takes each level's blocks at their own size in one launch (one and
- *                 many columns), and the BF16 matrix-core coupling runs one launch per
- *                 level with that level's padded block size.  A degree above 10 on a
+ *                 many columns), and the matrix-core couplings (BF16, and FP64 of 8 or
+ *                 more columns) run one launch per level with that level's padded
+ *                 block size.  A degree above 10 on a
  *                 level with far pairs (also one degree q = 11) makes the BF16
  *                 precisions (apply, autotuning, refinement inner solves) refuse with
  *                 IGE_EINVAL; stored coupling blocks need one degree on all levels. */

@@ -1057,10 +1057,9 @@ void run_graph(ige_op op, ApplyGraph *g, int r, int prec, const std::function<vo
     IGE_HIP(hipGraphLaunch(g->exec, s));
 }
 
-// the BF16 matrix-core couplings take blocks of at most 128 padded nodes (degree at
-// most 10 on every level with far pairs; with a degree per level, one launch per
-// level); the FP64 matrix-core coupling needs one degree on all levels.  Other
-// operators couple on the generated FP64/FP32 kernels
+// the matrix-core couplings take blocks of at most 128 padded nodes (degree at most 10
+// on every level with far pairs; with a degree per level, one launch per level).
+// Other operators couple on the generated FP64/FP32 kernels
 bool mx_coupling_ok(const ige_op_s *op)
 {
     if (!op->F.varq) return op->F.q <= 10;

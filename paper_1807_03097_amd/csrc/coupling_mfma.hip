@@ -475,9 +475,10 @@ __global__ __launch_bounds__(128 * WN) void k_m2l_mxd(DevOp o, int r, int rc, in
 // ---------------------------------------------------------------------------
 typedef double dx4m __attribute__((ext_vector_type(4)));
 
-__global__ void k_gd_store(DevOp o, int64_t nfp, const int32_t *fpair, int Qp, double *Gd)
+// (Qr nodes per cluster, of the stride o.Q of the cluster arrays, as k_gb_store)
+__global__ void k_gd_store(DevOp o, int64_t nfp, const int32_t *fpair, int Qr, int Qp, double *Gd)
 {
-    const int Q = o.Q, K2 = 2 * Qp;
+    const int Qs = o.Q, Q = Qr, K2 = 2 * Qp;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t per = (int64_t)Qp * Qp;
     if (t >= nfp * 2 * per) return;
@@ -488,8 +489,8 @@ __global__ void k_gd_store(DevOp o, int64_t nfp, const int32_t *fpair, int Qp, d
     const int ga = fpair[2 * pr + ori], gb = fpair[2 * pr + 1 - ori];
     double2 g = make_double2(0.0, 0.0);
     if (m < Q && mc < Q) {
-        const double *Xa = o.nodeX + (size_t)ga * 3 * Q, *Xb = o.nodeX + (size_t)gb * 3 * Q;
-        const double d0 = Xa[m] - Xb[mc], d1 = Xa[Q + m] - Xb[Q + mc], d2 = Xa[2 * Q + m] - Xb[2 * Q + mc];
+        const double *Xa = o.nodeX + (size_t)ga * 3 * Qs, *Xb = o.nodeX + (size_t)gb * 3 * Qs;
+        const double d0 = Xa[m] - Xb[mc], d1 = Xa[Qs + m] - Xb[Qs + mc], d2 = Xa[2 * Qs + m] - Xb[2 * Qs + mc];
         g = dm::helmholtz_r2_tab(o.kappa, fma(d0, d0, fma(d1, d1, d2 * d2)), o.sctab);
     }
     double *base = Gd + (size_t)po * Qp * K2;
@@ -498,11 +499,11 @@ __global__ void k_gd_store(DevOp o, int64_t nfp, const int32_t *fpair, int Qp, d
 }
 
 // source fields [NC][4][Q][r] -> Vd[cluster][chunk][ncol][2Qp] (FP64), through shared memory
-__global__ __launch_bounds__(256) void k_vd_prep_t(DevOp o, int r, int rc, int nchunk, int ncol, int Qp,
-                                                   const double2 *src, double *Vd)
+__global__ __launch_bounds__(256) void k_vd_prep_t(DevOp o, int cl0, int Qr, int r, int rc, int nchunk, int ncol,
+                                                   int Qp, const double2 *src, double *Vd)
 {
     __shared__ double2 tile[kVbRows][65];
-    const int Q = o.Q, K2 = 2 * Qp, nrb = Qp / kVbRows;
+    const int Qs = o.Q, Q = Qr, K2 = 2 * Qp, nrb = Qp / kVbRows;
     int b = blockIdx.x;
     const int rb = b % nrb;
     b /= nrb;
@@ -512,7 +513,7 @@ __global__ __launch_bounds__(256) void k_vd_prep_t(DevOp o, int r, int rc, int n
     const int m0 = rb * kVbRows;
     for (int i = threadIdx.x; i < kVbRows * rc; i += blockDim.x) {
         const int mm = i / rc, j = i % rc, col = ch * rc + j, m = m0 + mm;
-        tile[mm][j] = (m < Q && col < r) ? src[(((size_t)gc * 4 + f) * Q + m) * r + col] : make_double2(0.0, 0.0);
+        tile[mm][j] = (m < Q && col < r) ? src[(((size_t)(cl0 + gc) * 4 + f) * Qs + m) * r + col] : make_double2(0.0, 0.0);
     }
     __syncthreads();
     double *base = Vd + ((size_t)gc * nchunk + ch) * (size_t)ncol * K2;
@@ -524,7 +525,7 @@ __global__ __launch_bounds__(256) void k_vd_prep_t(DevOp o, int r, int rc, int n
 }
 
 template <int MT, int WN, int NT>
-__global__ __launch_bounds__(128 * WN) void k_m2l_md(DevOp o, int r, int rc, int nchunk, int64_t nwork,
+__global__ __launch_bounds__(128 * WN) void k_m2l_md(DevOp o, int r, int rc, int nchunk, int64_t nwork, int Qr, int cl0,
                                                      const int32_t *order, const M2LWork *work,
                                                      const int32_t *partner, const int32_t *gslot, const double *Gd,
                                                      const double *Vd, double2 *part)
@@ -553,7 +554,7 @@ __global__ __launch_bounds__(128 * WN) void k_m2l_md(DevOp o, int r, int rc, int
     auto load = [&](int it) {
         const int kp = wk.beg + it / KS, s8 = it % KS;
         const double *Gp = Gd + (size_t)gslot[kp] * gper;
-        const double *Vs = Vd + ((size_t)partner[kp] * nchunk + ch) * vper;
+        const double *Vs = Vd + ((size_t)(partner[kp] - cl0) * nchunk + ch) * vper;
         const int kb = 8 * s8 + 2 * gi;
         // real rows [Gr, -Gi], imaginary rows [Gi, Gr] of the stored [Gr | Gi]; kb and
         // 8 s8 lie in the same half (QP is a multiple of 16)
@@ -595,7 +596,7 @@ __global__ __launch_bounds__(128 * WN) void k_m2l_md(DevOp o, int r, int rc, int
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int m = 16 * a + gi + 4 * j;
-                if (m < Q) {
+                if (m < Qr) {
                     double *dst = reinterpret_cast<double *>(part + (((size_t)wi * 4 + f) * Q + m) * r + col);
                     dst[wm] = acc[a][t][j];
                 }
@@ -1025,48 +1026,84 @@ void m2l_bf16(ige_op op, int r, int split, const double2 *src, hipStream_t s, hi
 
 namespace {
 template <int MT, int WN, int NT>
-void launch_md(ige_op op, int r, int rc, int nchunk, hipStream_t s)
+void launch_md(ige_op op, int r, int rc, int nchunk, hipStream_t s, const MxSpan &sp, const double *Gd,
+               const double *Vd)
 {
     const DevOp &o = op->view;
-    const int64_t nw = (int64_t)op->mwork.size();
+    const int64_t nw = sp.nw;
     const dim3 grid((unsigned)(((nw + 7) / 8) * 8 * nchunk)), blk(128 * WN);
-    hipLaunchKernelGGL((k_m2l_md<MT, WN, NT>), grid, blk, 0, s, o, r, rc, nchunk, nw, op->d_morder.p, op->d_mwork.p,
-                       op->d_mpartner.p, op->d_gslot.p, op->d_Gd.p, op->d_vd.p, op->d_bmpart64.p);
+    hipLaunchKernelGGL((k_m2l_md<MT, WN, NT>), grid, blk, 0, s, o, r, rc, nchunk, nw, sp.Qr, sp.cl0, sp.order,
+                       op->d_mwork.p, op->d_mpartner.p, op->d_gslot.p, Gd, Vd, op->d_bmpart64.p);
     IGE_HIP(hipGetLastError());
 }
 
 template <int MT>
-void launch_md_cols(ige_op op, int r, int ncol, hipStream_t s)
+void launch_md_cols(ige_op op, int r, int ncol, hipStream_t s, const MxSpan &sp, const double *Gd, const double *Vd)
 {
     const int rc = ncol / 4, nchunk = (r + rc - 1) / rc;
     switch (ncol) {
-        case 16: launch_md<MT, 1, 1>(op, r, rc, nchunk, s); break;
-        case 32: launch_md<MT, 2, 1>(op, r, rc, nchunk, s); break;
-        case 64: launch_md<MT, 4, 1>(op, r, rc, nchunk, s); break;
-        default: launch_md<MT, 4, 2>(op, r, rc, nchunk, s); break;
+        case 16: launch_md<MT, 1, 1>(op, r, rc, nchunk, s, sp, Gd, Vd); break;
+        case 32: launch_md<MT, 2, 1>(op, r, rc, nchunk, s, sp, Gd, Vd); break;
+        case 64: launch_md<MT, 4, 1>(op, r, rc, nchunk, s, sp, Gd, Vd); break;
+        default: launch_md<MT, 4, 2>(op, r, rc, nchunk, s, sp, Gd, Vd); break;
     }
 }
+
+void md_run(ige_op op, int r, int MT, int ncol, hipStream_t s, const MxSpan &sp, const double *Gd, const double *Vd)
+{
+    switch (MT) {
+        case 2: launch_md_cols<2>(op, r, ncol, s, sp, Gd, Vd); break;
+        case 4: launch_md_cols<4>(op, r, ncol, s, sp, Gd, Vd); break;
+        case 6: launch_md_cols<6>(op, r, ncol, s, sp, Gd, Vd); break;
+        default: launch_md_cols<8>(op, r, ncol, s, sp, Gd, Vd); break;
+    }
+}
+
+// the FP64 blocks of one level (or of all levels at one degree) and their size
+size_t gd_count(int64_t np, int Qp) { return (size_t)np * 2 * Qp * 2 * Qp; }
 }  // namespace
 
 void ensure_coupling_f64(ige_op op)
 {
     if (op->d_Gd.p || op->nfp == 0) return;
     const DevOp &o = op->view;
+    if (!op->mxl.empty()) {   // a degree per level: each level's blocks at its own size
+        size_t tot = 0;
+        for (const auto &L : op->mxl) tot += gd_count(L.np, L.Qp);
+        op->d_Gd.alloc(tot);
+        size_t off = 0;
+        for (const auto &L : op->mxl) {
+            const int64_t n = L.np * 2 * (int64_t)L.Qp * L.Qp;
+            hipLaunchKernelGGL(k_gd_store, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, op->ctx->stream, o, L.np,
+                               op->d_fpair.p + 2 * L.p0, L.Qr, L.Qp, op->d_Gd.p + off);
+            IGE_HIP(hipGetLastError());
+            off += gd_count(L.np, L.Qp);
+        }
+        return;
+    }
     const int Qp = coupling_qp(o.Q);
-    op->d_Gd.alloc((size_t)op->nfp * 2 * Qp * 2 * Qp);
+    op->d_Gd.alloc(gd_count(op->nfp, Qp));
     const int64_t n = op->nfp * 2 * (int64_t)Qp * Qp;
     hipLaunchKernelGGL(k_gd_store, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, op->ctx->stream, o, op->nfp,
-                       op->d_fpair.p, Qp, op->d_Gd.p);
+                       op->d_fpair.p, o.Q, Qp, op->d_Gd.p);
     IGE_HIP(hipGetLastError());
 }
 
 bool m2l_f64mx_ok(ige_op op, int r)
 {
-    if (r < 8 || op->mwork.empty() || op->f64mx_off || op->view.varq) return false;
-    const int Qp = coupling_qp(op->view.Q);
-    if (Qp > 128) return false;
+    if (r < 8 || op->mwork.empty() || op->f64mx_off) return false;
+    size_t need = 0;
+    if (!op->mxl.empty()) {   // a degree per level: every level's blocks within 128 padded nodes
+        for (const auto &L : op->mxl) {
+            if (L.Qp > 128) return false;
+            need += gd_count(L.np, L.Qp) * sizeof(double);
+        }
+    } else {
+        const int Qp = coupling_qp(op->view.Q);
+        if (Qp > 128) return false;
+        need = gd_count(op->nfp, Qp) * sizeof(double);
+    }
     if (op->gd_fit < 0) {   // decided once, at the first eligible apply (never under capture)
-        const size_t need = (size_t)op->nfp * 2 * Qp * 2 * Qp * sizeof(double);
         size_t fr = 0, tot = 0;
         IGE_HIP(hipMemGetInfo(&fr, &tot));
         op->gd_fit = op->d_Gd.p || need + ((size_t)8 << 30) < fr ? 1 : 0;
@@ -1081,25 +1118,48 @@ void m2l_f64mx(ige_op op, int r, const double2 *src, hipStream_t s, hipEvent_t m
     const DevOp &o = op->view;
     if (op->mwork.empty()) return;
     ensure_coupling_f64(op);
-    const int Qp = coupling_qp(o.Q), K2 = 2 * Qp, MT = Qp / 16;
-    IGE_REQUIRE(MT <= 8, "interpolation degree too large for the matrix-core coupling");
     int ncol = 16;
     while (ncol < 4 * r && ncol < 128) ncol *= 2;
     const int rc = ncol / 4, nchunk = (r + rc - 1) / rc;
-    const size_t vdn = (size_t)op->NC * nchunk * ncol * K2;
-    if (op->d_vd.n < vdn) op->d_vd.alloc(vdn);
     const size_t pn = op->mwork.size() * 4 * (size_t)o.Q * r;
     if (op->d_bmpart64.n < pn) op->d_bmpart64.alloc(pn);
+    if (!op->mxl.empty()) {   // level by level, each with its padded block size
+        size_t vdn = 0;
+        for (const auto &L : op->mxl) vdn += (size_t)L.ncl * nchunk * ncol * 2 * L.Qp;
+        if (op->d_vd.n < vdn) op->d_vd.alloc(vdn);
+        size_t voff = 0;
+        std::vector<size_t> vo(op->mxl.size());
+        for (size_t i = 0; i < op->mxl.size(); ++i) {
+            const auto &L = op->mxl[i];
+            vo[i] = voff;
+            const int64_t nb = (int64_t)L.ncl * nchunk * 4 * (L.Qp / kVbRows);
+            hipLaunchKernelGGL(k_vd_prep_t, dim3((unsigned)nb), dim3(256), 0, s, o, L.cl0, L.Qr, r, rc, nchunk, ncol,
+                               L.Qp, src, op->d_vd.p + voff);
+            IGE_HIP(hipGetLastError());
+            voff += (size_t)L.ncl * nchunk * ncol * 2 * L.Qp;
+        }
+        if (mid) IGE_HIP(hipEventRecord(mid, s));
+        size_t goff = 0;
+        for (size_t i = 0; i < op->mxl.size(); ++i) {
+            const auto &L = op->mxl[i];
+            IGE_REQUIRE(L.Qp / 16 <= 8, "interpolation degree too large for the matrix-core coupling");
+            const MxSpan sp{op->d_morder.p + L.w0, L.nw, L.Qr, L.cl0};
+            md_run(op, r, L.Qp / 16, ncol, s, sp, op->d_Gd.p + goff, op->d_vd.p + vo[i]);
+            goff += gd_count(L.np, L.Qp);
+        }
+        return;
+    }
+    const int Qp = coupling_qp(o.Q), K2 = 2 * Qp, MT = Qp / 16;
+    IGE_REQUIRE(MT <= 8, "interpolation degree too large for the matrix-core coupling");
+    const size_t vdn = (size_t)op->NC * nchunk * ncol * K2;
+    if (op->d_vd.n < vdn) op->d_vd.alloc(vdn);
     const int64_t nb = (int64_t)op->NC * nchunk * 4 * (Qp / kVbRows);
-    hipLaunchKernelGGL(k_vd_prep_t, dim3((unsigned)nb), dim3(256), 0, s, o, r, rc, nchunk, ncol, Qp, src, op->d_vd.p);
+    hipLaunchKernelGGL(k_vd_prep_t, dim3((unsigned)nb), dim3(256), 0, s, o, 0, o.Q, r, rc, nchunk, ncol, Qp, src,
+                       op->d_vd.p);
     IGE_HIP(hipGetLastError());
     if (mid) IGE_HIP(hipEventRecord(mid, s));
-    switch (MT) {
-        case 2: launch_md_cols<2>(op, r, ncol, s); break;
-        case 4: launch_md_cols<4>(op, r, ncol, s); break;
-        case 6: launch_md_cols<6>(op, r, ncol, s); break;
-        default: launch_md_cols<8>(op, r, ncol, s); break;
-    }
+    const MxSpan sp{op->d_morder.p, (int64_t)op->mwork.size(), o.Q, 0};
+    md_run(op, r, MT, ncol, s, sp, op->d_Gd.p, op->d_vd.p);
 }
 
 }  // namespace ige
