@@ -176,6 +176,11 @@ typedef struct {
     int32_t q_level[11];    /* interpolation degree of each level 0..leaf_level (0 beyond) */
     double level_diam[11];  /* largest bounding-ball diameter of the clusters of each level
                                0..leaf_level (0 beyond) */
+    int32_t m2l_unordered;  /* 1: the one-column FP64 coupling evaluates the kernel once per
+                               unordered far pair and serves both clusters (the kernel is
+                               symmetric), as asked by IGE_M2L_SYM=1 at creation with one
+                               degree (<= 8) on every level; 0: once per ordered pair
+                               (default) */
 } ige_op_info_t;
 int ige_op_info(ige_op op, ige_op_info_t *out);
 

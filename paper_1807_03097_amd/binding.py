@@ -41,7 +41,7 @@ class ige_op_info_t(C.Structure):
                 ("far_pairs", C.c_int64), ("near_leaf_pairs", C.c_int64), ("singular_pairs", C.c_int64),
                 ("leaf_level", C.c_int32), ("q", C.c_int32), ("device_bytes", C.c_int64),
                 ("assemble_ms", C.c_double), ("near_distinct", C.c_int64), ("q_level", C.c_int32 * 11),
-                ("level_diam", C.c_double * 11)]
+                ("level_diam", C.c_double * 11), ("m2l_unordered", C.c_int32)]
 
 
 IGE_F64, IGE_F32, IGE_BF16, IGE_BF16X3, IGE_BF16X3_ALL = 0, 1, 2, 3, 4

@@ -92,7 +92,7 @@ void apply_one(ige_op op, const double2 *x, double2 *y, int prec = IGE_F64)
             mark(12, s);
             ige::launch_m2l(op, prec);
             mark(3, s);
-            ige::launch_m2l_reduce(op);
+            ige::launch_m2l_reduce(op, prec);
             mark(4, s);
             ige::launch_l2l(op);
             mark(5, s);
@@ -132,7 +132,7 @@ void apply_one(ige_op op, const double2 *x, double2 *y, int prec = IGE_F64)
         mark(12, s);
         ige::launch_m2l(op, prec);
         mark(3, s);
-        ige::launch_m2l_reduce(op);
+        ige::launch_m2l_reduce(op, prec);
         mark(4, s);
         ige::launch_l2l(op);
         mark(5, s);
@@ -160,7 +160,7 @@ void apply_one(ige_op op, const double2 *x, double2 *y, int prec = IGE_F64)
     mark(12, s);
     ige::launch_m2l(op, prec);
     mark(3, s);
-    ige::launch_m2l_reduce(op);
+    ige::launch_m2l_reduce(op, prec);
     mark(4, s);
     ige::launch_l2l(op);
     mark(5, s);
@@ -768,6 +768,50 @@ ige_op ige::assemble_on(ige_ctx ctx, const ige_geom_s *geom, const ige_params &p
             op->d_loc.alloc((size_t)op->NC * 3 * v.Q);
             op->d_ybuf.alloc((size_t)D.P * v.SL * v.SL * 2 * F.rowlen * F.rowlen);
             op->d_part.alloc(std::max<size_t>(1, op->work.size()) * 4 * v.Q);
+            // one FP64 column, one degree (<= 8) on every level: the coupling over unordered
+            // pairs when asked (IGE_M2L_SYM=1), items = cluster t with up to
+            // IGE_M2L_SYM_CHUNK (default 4) partners s > t
+            op->m2l_sym = false;
+            if (const char *e = std::getenv("IGE_M2L_SYM"))
+                op->m2l_sym = std::atoi(e) != 0 && !F.varq && !T.far.empty() &&
+                              ige::m2l_sym_shared_bytes(v.Q) <= (size_t)64 * 1024;
+            if (op->m2l_sym) {
+                int CHS = 4;
+                if (const char *e = std::getenv("IGE_M2L_SYM_CHUNK")) CHS = std::max(1, std::min(64, std::atoi(e)));
+                std::vector<int32_t> spart;
+                op->swork.clear();
+                size_t i = 0;
+                while (i < T.far.size()) {   // sorted by level, cluster, partner
+                    const int lvl = T.far[i][0], tg = T.far[i][1];
+                    const int beg = (int)spart.size();
+                    size_t k = i;
+                    for (; k < T.far.size() && T.far[k][0] == lvl && T.far[k][1] == tg; ++k)
+                        if (T.far[k][2] > tg) spart.push_back((int32_t)(op->lvl_off[lvl] + T.far[k][2]));
+                    for (int b = beg; b < (int)spart.size(); b += CHS)
+                        op->swork.push_back({(int32_t)(op->lvl_off[lvl] + tg), b, std::min((int)spart.size(), b + CHS)});
+                    i = k;
+                }
+                IGE_REQUIRE(2 * spart.size() == T.far.size(), "far pairs are not symmetric");
+                // the longest items launch first
+                std::stable_sort(op->swork.begin(), op->swork.end(), [](const ige::M2LWork &a, const ige::M2LWork &b) {
+                    return a.end - a.beg > b.end - b.beg;
+                });
+                // per cluster its slots: the row sides of its items, then the column sides
+                // of its pairs, in that fixed order
+                const int nw = (int)op->swork.size();
+                std::vector<int32_t> sptr((size_t)op->NC + 1, 0);
+                for (const auto &w : op->swork) sptr[w.tgt + 1]++;
+                for (int32_t c : spart) sptr[c + 1]++;
+                for (int c = 0; c < op->NC; ++c) sptr[c + 1] += sptr[c];
+                std::vector<int32_t> sidx(sptr[op->NC]), fill(sptr.begin(), sptr.end() - 1);
+                for (int w = 0; w < nw; ++w) sidx[fill[op->swork[w].tgt]++] = w;
+                for (size_t k = 0; k < spart.size(); ++k) sidx[fill[spart[k]]++] = nw + (int32_t)k;
+                op->d_swork.upload(op->swork, s);
+                op->d_spartner.upload(spart, s);
+                op->d_sred_ptr.upload(sptr, s);
+                op->d_sred_idx.upload(sidx, s);
+                op->d_spart.alloc(((size_t)nw + spart.size()) * 4 * v.Q);
+            }
             if (op->stored) ige::store_coupling(op);
             IGE_HIP(hipStreamCreate(&op->aux));
             // fork/join between two streams of one device: no system-scope fence (the
@@ -835,6 +879,7 @@ int ige_op_info(ige_op op, ige_op_info_t *out)
         r.n_elements = (int64_t)op->D.P * op->D.n * op->D.n;
         r.near_nnz = op->nnz;
         r.near_distinct = op->cmp.distinct;
+        r.m2l_unordered = op->m2l_sym ? 1 : 0;
         r.far_pairs = (int64_t)op->T.far.size();
         r.near_leaf_pairs = (int64_t)op->T.near.size();
         r.singular_pairs = op->nsing;
@@ -859,6 +904,7 @@ int ige_op_info(ige_op op, ige_op_info_t *out)
         b += op->d_nbred_idx.bytes() + op->d_morder.bytes();
         b += op->d_Mp.bytes() * 3 + op->d_inc.bytes() + op->d_sing.bytes() + op->d_work.bytes();
         b += op->d_partner.bytes() + op->d_mom.bytes() + op->d_src.bytes() + op->d_loc.bytes() + op->d_part.bytes();
+        b += op->d_swork.bytes() + op->d_spartner.bytes() + op->d_sred_ptr.bytes() + op->d_sred_idx.bytes() + op->d_spart.bytes();
         b += op->d_x.bytes() + op->d_y.bytes() + op->d_V.bytes() + op->d_w.bytes() + op->d_r.bytes();
         b += op->d_cnr.bytes() + op->d_cnc.bytes() + op->d_cld.bytes() + op->d_cidx.bytes() + op->d_corder.bytes() + op->d_cred_idx.bytes();
         b += op->d_cocc_ptr.bytes() + op->d_cocc.bytes() + op->d_cnp_ptr.bytes() + op->d_cnp_leaf.bytes();

@@ -1124,6 +1124,7 @@ __global__ __launch_bounds__(256) void k_lift(DevOp o, int lvl, double2 *loc)
 // ---------------------------------------------------------------------------
 constexpr int kM2LThreads = 256;
 constexpr int kM2LNT = 3;
+constexpr int kQMaxSym = 81;    // nodes per cluster of the unordered-pair coupling (degree <= 8)
 
 template <typename T>
 __global__ __launch_bounds__(kM2LThreads) void k_m2l(DevOp o, int nwork, const M2LWork *work, const int32_t *partner,
@@ -1218,6 +1219,194 @@ __global__ __launch_bounds__(kM2LThreads) void k_m2l(DevOp o, int nwork, const M
         }
     }
     __syncthreads();   // the next item's staging reuses the shared memory
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a5 over unordered pairs (one FP64 column, one degree on every level).  The kernel
+// is symmetric, G(x, y) = G(y, x), and both clusters of a far pair sit on one level
+// with the same reference nodes, so the block of (s, t) is the transpose of the
+// block of (t, s).  Work item = cluster t with a chunk of partners s > t; every
+// kernel value is evaluated once and serves both sides:
+//   u_t[m]  += sum_m' G(|x_m - x'_m'|) v_s[m']   (row side, summed over the chunk)
+//   u_s[m'] += sum_m  G(|x_m - x'_m'|) v_t[m]    (column side, per pair)
+// Rows are taken in kM2LNT chunks of TPG rows.  In the row layout a thread holds
+// one row of the chunk and a range of columns (the row side accumulates in
+// registers); the chunk's values go to shared memory, and in the column layout a
+// thread holds kM2LNT columns and a range of the chunk's rows.  The column side's
+// parts are summed in a fixed order once per pair, the row side's once per item.
+// Slots of part: item i -> i (row side), partner k -> nwork + k (column side).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kM2LThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_m2l_sym(
+    DevOp o, int nwork, const M2LWork *work, const int32_t *partner, const double2 *src, double2 *part)
+{
+    extern __shared__ double smd[];
+    __shared__ double2 sTab[256];                               // (cos, sin)(j pi/128) / (4 pi)
+    for (int i = threadIdx.x; i < 256; i += kM2LThreads) sTab[i] = o.sctab[i];   // first use after a barrier
+    const M2LWork wk = work[blockIdx.x];
+    const int Q = o.Q;
+    const int TPG = (Q + kM2LNT - 1) / kM2LNT;
+    const int S = min(kM2LThreads / TPG, Q);
+    const int SP = (Q + S - 1) / S;       // columns per thread (row layout)
+    const int RP = (TPG + S - 1) / S;     // chunk rows per thread (column layout)
+    const int tid = threadIdx.x;
+    const int mt = tid % TPG, sp = tid / TPG;
+    const bool active = sp < S;
+    double *sX = smd;                                            // [Q][4] partner's nodes
+    double2 *sV = reinterpret_cast<double2 *>(smd + 4 * Q);     // [Q][4] partner's source fields
+    double2 *sW = sV + 4 * Q;                                    // [Q][4] row cluster's source fields
+    double2 *sG = sW + 4 * Q;                                    // [Q][TPG] chunk of G, column-major
+    double2 *red = sG;                                           // [S][Q][2] reductions
+    const double kap = o.kappa;
+    double xt[kM2LNT][3];
+    bool val[kM2LNT];
+    double2 acc[kM2LNT][4], cac[kM2LNT][4];
+    const double *Xt = o.nodeX + (size_t)wk.tgt * 3 * Q;
+#pragma unroll
+    for (int k = 0; k < kM2LNT; ++k) {
+        const int mm = mt + k * TPG;
+        val[k] = active && mm < Q;
+        const int mc = val[k] ? mm : 0;
+        xt[k][0] = Xt[mc];
+        xt[k][1] = Xt[Q + mc];
+        xt[k][2] = Xt[2 * Q + mc];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[k][j] = make_double2(0, 0);
+    }
+    {
+        const double2 *Vt = src + (size_t)wk.tgt * 4 * Q;
+        for (int i = tid; i < 4 * Q; i += kM2LThreads) sW[(i % Q) * 4 + i / Q] = Vt[i];
+    }
+    const int mb = min(Q, sp * SP), me = min(Q, mb + SP);
+    const int rb = sp * RP, re = min(TPG, rb + RP);
+    for (int kp = wk.beg; kp < wk.end; ++kp) {
+        const int sc = partner[kp];
+        __syncthreads();
+        const double *Xs = o.nodeX + (size_t)sc * 3 * Q;
+        const double2 *Vs = src + (size_t)sc * 4 * Q;
+        for (int i = tid; i < 3 * Q; i += kM2LThreads) sX[(i % Q) * 4 + i / Q] = Xs[i];
+        for (int i = tid; i < 4 * Q; i += kM2LThreads) sV[(i % Q) * 4 + i / Q] = Vs[i];
+#pragma unroll
+        for (int k = 0; k < kM2LNT; ++k)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) cac[k][j] = make_double2(0, 0);
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < kM2LNT; ++c) {
+            if (c * TPG >= Q) break;   // uniform
+            // row layout: row c TPG + mt against the columns [mb, me)
+            if (val[c]) {
+                for (int ms = mb; ms < me; ++ms) {
+                    const double d0 = xt[c][0] - sX[4 * ms], d1 = xt[c][1] - sX[4 * ms + 1], d2 = xt[c][2] - sX[4 * ms + 2];
+                    const double2 G = dm::helmholtz_r2_tab(kap, fma(d0, d0, fma(d1, d1, d2 * d2)), sTab);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[c][j] = dm::cmac(acc[c][j], G, sV[4 * ms + j]);
+                    sG[ms * TPG + mt] = G;
+                }
+            }
+            __syncthreads();
+            // column layout: columns mt + k TPG against the chunk rows [rb, re)
+            if (active) {
+                for (int r = rb; r < re; ++r) {
+                    const int gr = c * TPG + r;
+                    if (gr >= Q) break;
+                    const double2 w0 = sW[4 * gr], w1 = sW[4 * gr + 1], w2 = sW[4 * gr + 2], w3 = sW[4 * gr + 3];
+#pragma unroll
+                    for (int k = 0; k < kM2LNT; ++k)
+                        if (val[k]) {
+                            const double2 G = sG[(mt + k * TPG) * TPG + r];
+                            cac[k][0] = dm::cmac(cac[k][0], G, w0);
+                            cac[k][1] = dm::cmac(cac[k][1], G, w1);
+                            cac[k][2] = dm::cmac(cac[k][2], G, w2);
+                            cac[k][3] = dm::cmac(cac[k][3], G, w3);
+                        }
+                }
+            }
+            __syncthreads();
+        }
+        // column side of the pair: the S row ranges summed in order, two fields at a time
+#pragma unroll
+        for (int hf = 0; hf < 2; ++hf) {
+#pragma unroll
+            for (int k = 0; k < kM2LNT; ++k)
+                if (val[k]) {
+                    const int mm = mt + k * TPG;
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) red[((size_t)sp * Q + mm) * 2 + j] = cac[k][2 * hf + j];
+                }
+            __syncthreads();
+            for (int i = tid; i < 2 * Q; i += kM2LThreads) {
+                const int j = i / Q, mm = i % Q;
+                double2 v = make_double2(0, 0);
+                for (int q2 = 0; q2 < S; ++q2) v = cadd(v, red[((size_t)q2 * Q + mm) * 2 + j]);
+                part[((size_t)(nwork + kp) * 4 + 2 * hf + j) * Q + mm] = v;
+            }
+            __syncthreads();
+        }
+    }
+    // row side: the column ranges summed in order, two fields at a time
+#pragma unroll
+    for (int hf = 0; hf < 2; ++hf) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kM2LNT; ++k)
+            if (val[k]) {
+                const int mm = mt + k * TPG;
+#pragma unroll
+                for (int j = 0; j < 2; ++j) red[((size_t)sp * Q + mm) * 2 + j] = acc[k][2 * hf + j];
+            }
+        __syncthreads();
+        for (int i = tid; i < 2 * Q; i += kM2LThreads) {
+            const int j = i / Q, mm = i % Q;
+            double2 v = make_double2(0, 0);
+            for (int q2 = 0; q2 < S; ++q2) v = cadd(v, red[((size_t)q2 * Q + mm) * 2 + j]);
+            part[((size_t)blockIdx.x * 4 + 2 * hf + j) * Q + mm] = v;
+        }
+    }
+}
+
+// per cluster, the sum of its slots in list order (row sides of its items, then the
+// column sides of its pairs), converted to the test-side fields as below
+// (loads issued eight slots at a time, added in list order)
+__global__ __launch_bounds__(512) void k_m2l_reduce_sym(DevOp o, const int32_t *ptr, const int32_t *idx,
+                                                        const double2 *part, double2 *loc)
+{
+    __shared__ double2 su[4][kQMaxSym];
+    const int gc = blockIdx.x, Q = o.Q;
+    const int b = ptr[gc], e = ptr[gc + 1];
+    for (int i = threadIdx.x; i < 4 * Q; i += blockDim.x) {
+        double2 v = make_double2(0, 0);
+        for (int w0 = b; w0 < e; w0 += 8) {
+            double2 t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                t[u] = w0 + u < e ? part[(size_t)idx[w0 + u] * 4 * Q + i] : make_double2(0, 0);
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (w0 + u < e) v = cadd(v, t[u]);
+        }
+        su[i / Q][i % Q] = v;
+    }
+    __syncthreads();
+    const double ik2 = 1.0 / (o.kappa * o.kappa);
+    for (int mm = threadIdx.x; mm < Q; mm += blockDim.x) {
+        const double *T = o.nodeT + (size_t)gc * 6 * Q;
+        double2 *L = loc + (size_t)gc * 3 * Q;
+        if (o.scalar) {   // scalar: t = |J(x_m)| u (the target's surface element)
+            const double Fu[3] = {T[mm], T[Q + mm], T[2 * Q + mm]}, Fv[3] = {T[3 * Q + mm], T[4 * Q + mm], T[5 * Q + mm]};
+            L[mm] = make_double2(0, 0);
+            L[Q + mm] = make_double2(0, 0);
+            L[2 * Q + mm] = cscale(surf_elem(Fu, Fv), su[3][mm]);
+            continue;
+        }
+        double2 t1 = make_double2(0, 0), t2 = make_double2(0, 0);
+        for (int k = 0; k < 3; ++k) {
+            t1 = cadd(t1, cscale(T[k * Q + mm], su[k][mm]));
+            t2 = cadd(t2, cscale(T[(3 + k) * Q + mm], su[k][mm]));
+        }
+        L[mm] = t1;
+        L[Q + mm] = t2;
+        L[2 * Q + mm] = cscale(-ik2, su[3][mm]);
     }
 }
 
@@ -1813,6 +2002,14 @@ void lds_attr_once(const void *kern, size_t shm)
     have = shm;
 }
 
+size_t m2l_sym_shared_bytes(int Q)
+{
+    const int TPG = (Q + kM2LNT - 1) / kM2LNT;
+    const int S = std::min(kM2LThreads / TPG, Q);
+    // [Q][4] positions, two [Q][4] complex, then a chunk of G or the reduction of two fields
+    return sizeof(double) * 4 * Q + sizeof(double2) * 8 * Q + sizeof(double2) * std::max((size_t)Q * TPG, (size_t)2 * S * Q);
+}
+
 size_t m2l_shared_bytes(int Q)
 {
     const int TPG = (Q + kM2LNT - 1) / kM2LNT;
@@ -1827,6 +2024,15 @@ void launch_m2l(ige_op op, int prec)
     if (op->work.empty()) return;
     if (op->stored && !op->m2l_generate_one) {
         m2l_stored_one(op, prec);
+        return;
+    }
+    if (op->m2l_sym && prec == IGE_F64) {
+        const size_t shm = m2l_sym_shared_bytes(o.Q);
+        lds_attr_once(reinterpret_cast<const void *>(&k_m2l_sym), shm);
+        const int nw = (int)op->swork.size();
+        hipLaunchKernelGGL(k_m2l_sym, dim3(nw), dim3(kM2LThreads), shm, lstream(op), o, nw, op->d_swork.p,
+                           op->d_spartner.p, op->d_src.p, op->d_spart.p);
+        IGE_LAUNCH_CHECK();
         return;
     }
     size_t shm = m2l_shared_bytes(o.Q);   // the largest over the levels' node counts
@@ -1853,11 +2059,18 @@ void launch_m2l(ige_op op, int prec)
     IGE_LAUNCH_CHECK();
 }
 
-void launch_m2l_reduce(ige_op op)
+void launch_m2l_reduce(ige_op op, int prec)
 {
     const DevOp &o = op->view;
     if (op->stored && !op->m2l_generate_one) {
         m2l_stored_reduce_one(op);
+        return;
+    }
+    if (op->m2l_sym && prec == IGE_F64) {
+        const int nt = std::min(512, (4 * o.Q + 63) / 64 * 64);
+        hipLaunchKernelGGL(k_m2l_reduce_sym, dim3(op->NC), dim3(nt), 0, lstream(op), o, op->d_sred_ptr.p,
+                           op->d_sred_idx.p, op->d_spart.p, op->d_loc.p);
+        IGE_LAUNCH_CHECK();
         return;
     }
     hipLaunchKernelGGL(k_m2l_reduce, dim3(op->NC), dim3(128), 0, lstream(op), o, op->d_wrk_of_tgt.p,

@@ -134,6 +134,19 @@ struct ige_op_s {
     // 0.1757 against 0.1797 ms per apply, four runs each; alone it is slower, 76 against
     // 70 us, with the registers of the wider items)
     bool near_one = true;
+    // one FP64 column, one degree (<= 8) on every level: the coupling over unordered far
+    // pairs, each kernel value used for both clusters of the pair (IGE_M2L_SYM=1).  Off by
+    // default: at C2 it halves the kernel evaluations and cuts the VALU instructions per
+    // ordered node pair by about a third, yet the kernel is only 7 % faster (86 against
+    // 92 us; the values pass through shared memory, the row layout reads the partner's
+    // nodes and fields once per row instead of once per three rows, and three workgroups
+    // per CU fit instead of four), and the slot reduction costs 4.5 us more: 0.188-0.191
+    // against 0.188 ms per apply
+    bool m2l_sym = false;
+    std::vector<ige::M2LWork> swork;      // row cluster with a chunk of partners of larger index
+    ige::DBuf<ige::M2LWork> d_swork;
+    ige::DBuf<int32_t> d_spartner, d_sred_ptr, d_sred_idx;   // partners; per cluster its slots
+    ige::DBuf<double2> d_spart;           // [items + partners][4][Q] partial couplings
     // many columns: the near-field product on the second stream beside the far field
     // (0: in line after it, 1: from the start, 2: after M2M)
     int batch_overlap = 1;
@@ -336,7 +349,8 @@ void near_bf16(ige_op op, int r, const double2 *xt, double2 *yt, hipStream_t s);
 // FP64 near field of r >= 56 columns on the FP64 matrix cores (ordered-pair FP64 blocks)
 bool near_f64mx_ok(ige_op op, int r);
 void near_f64mx(ige_op op, int r, const double2 *xt, double2 *yt, hipStream_t s);
-void launch_m2l_reduce(ige_op op);
+void launch_m2l_reduce(ige_op op, int prec);
+size_t m2l_sym_shared_bytes(int Q);
 void launch_l2l(ige_op op);
 // near-field product; records mid (if given) between the block pass and the reduction
 void launch_spmv(ige_op op, const double2 *x, double2 *y, hipStream_t st, hipEvent_t mid = nullptr);

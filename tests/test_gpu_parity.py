@@ -704,6 +704,54 @@ def test_near_once_per_entry_equals_leaf_pair_blocks(oracle_mod, ctx, case, monk
     op1.close()
 
 
+SYM_CASES = [CASES[2], CASES[3], CASES[4], CASES[6], CASES[7], CASES[8], CASES[10], CASES[12],
+             ("sphere", 2, 3, 8.0, 10, 1.6, 1, 5, 5)]
+
+
+@pytest.mark.parametrize("case", SYM_CASES, ids=[f"{c[0]}-p{c[1]}-m{c[2]}-q{c[4]}-d{c[6]}" for c in SYM_CASES])
+def test_unordered_pair_coupling_equals_ordered(oracle_mod, ctx, case, monkeypatch):
+    """The one-column FP64 coupling over unordered far pairs (IGE_M2L_SYM=1: each kernel
+    value used for both clusters, the kernel being symmetric) equals the coupling over
+    ordered pairs (default) up to summation order, for one, four and eight partners per
+    work item and for the scalar single layer; degree 10 keeps the ordered form; the
+    apply matches the oracle."""
+    from paper_1807_03097_amd import binding as B
+    name, p, m, kappa, q, eta, d, g, gs = case
+    _say(f"case {case}")
+    pats = _geom(name)
+    geom = B.Geometry(ctx, pats)
+    for kind in (B.IGE_OP_EFIE, B.IGE_OP_SCALAR):
+        op0 = B.Operator(geom, p, m, kappa, q, eta, g, gs, d, kind=kind)
+        monkeypatch.setenv("IGE_M2L_SYM", "1")
+        ops = []
+        for ch in ("1", "8", None):
+            if ch is not None:
+                monkeypatch.setenv("IGE_M2L_SYM_CHUNK", ch)
+            ops.append(B.Operator(geom, p, m, kappa, q, eta, g, gs, d, kind=kind))
+            monkeypatch.delenv("IGE_M2L_SYM_CHUNK", raising=False)
+        monkeypatch.delenv("IGE_M2L_SYM")
+        assert op0.info.m2l_unordered == 0
+        assert all(o.info.m2l_unordered == (1 if (q <= 8 and op0.info.far_pairs > 0) else 0) for o in ops)
+        err = 0.0
+        for seed in range(2):
+            x = W.random_coeffs(op0.N, seed)
+            y0 = op0.apply(x)
+            for o in ops:
+                err = max(err, _rel(o.apply(x), y0))
+        if kind == B.IGE_OP_EFIE:
+            x = W.random_coeffs(op0.N, 0)
+            dd = d if d >= 0 else int(np.ceil(np.log2((q + 1) / (p + 1)) - 1e-12))
+            yo = oracle_mod.Oracle(pats, p, m, kappa, g=g, gs=gs).fmm_apply(x, q, eta, dd)
+            erro = _rel(ops[-1].apply(x), yo)
+        else:
+            erro = 0.0
+        _say(f"  kind {kind}: far pairs {op0.info.far_pairs}, unordered {ops[-1].info.m2l_unordered}; "
+             f"vs ordered {err:.1e}, vs oracle {erro:.1e}")
+        assert err <= 1e-14 and erro <= TOL
+        for o in [op0] + ops:
+            o.close()
+
+
 def test_quartic_dense_solve_matches_lapack(oracle_mod, ctx):
     """p = 4 (the paper's Table 1, last column: N = 300 at level 1): the dense operator
     (eta = 0) against the oracle's matrix, and a plane-wave GMRES solve against LAPACK
