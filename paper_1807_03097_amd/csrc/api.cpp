@@ -578,28 +578,35 @@ ige_op ige::assemble_on(ige_ctx ctx, const ige_geom_s *geom, const ige_params &p
             if (const char *e = std::getenv("IGE_BATCH_OVERLAP")) op->batch_overlap = std::max(0, std::min(2, std::atoi(e)));
             if (const char *e = std::getenv("IGE_M2L_PERSIST")) op->m2l_persist = std::max(0, std::min(16, std::atoi(e)));
             op->lfar = T.far.empty() ? T.L + 1 : T.far.front()[0];   // far pairs sorted by level
+            // the one-column kernel's items (IGE_M2L_CHUNK1, default 12 partners): longer
+            // items leave more of the device to the near-field product beside them (C2:
+            // 0.1818-0.1854 ms per apply against 0.1863-0.1885 with 8; alone the coupling
+            // kernel takes 98 against 91 us)
+            int CH1 = 12;
+            if (const char *e = std::getenv("IGE_M2L_CHUNK1")) CH1 = std::max(1, std::min(64, std::atoi(e)));
             std::vector<int32_t> partner;
-            op->wrk_of_tgt.assign(op->NC + 1, 0);
-            {
-                size_t i = 0;
+            for (const auto &f : T.far) partner.push_back((int32_t)(op->lvl_off[f[0]] + f[2]));
+            // targets with chunks of up to ch partners, and per target its range of items
+            auto chunk_items = [&](int ch, std::vector<ige::M2LWork> &work, std::vector<int32_t> &wot) {
+                work.clear();
+                wot.assign(op->NC + 1, 0);
                 std::vector<int32_t> cnt(op->NC, 0);
-                while (i < T.far.size()) {
+                size_t i = 0;
+                while (i < T.far.size()) {   // sorted by level, cluster, partner
                     const int lvl = T.far[i][0], tg = T.far[i][1];
                     const int gc = (int)op->lvl_off[lvl] + tg;
                     size_t k = i;
-                    while (k < T.far.size() && T.far[k][0] == lvl && T.far[k][1] == tg) {
-                        partner.push_back((int32_t)(op->lvl_off[lvl] + T.far[k][2]));
-                        ++k;
-                    }
-                    const int beg = (int)(partner.size() - (k - i));
-                    for (int b = beg; b < (int)partner.size(); b += CH) {
-                        op->work.push_back({gc, b, std::min((int)partner.size(), b + CH)});
+                    while (k < T.far.size() && T.far[k][0] == lvl && T.far[k][1] == tg) ++k;
+                    for (size_t b = i; b < k; b += ch) {
+                        work.push_back({gc, (int32_t)b, (int32_t)std::min(k, b + ch)});
                         cnt[gc]++;
                     }
                     i = k;
                 }
-                for (int c = 0; c < op->NC; ++c) op->wrk_of_tgt[c + 1] = op->wrk_of_tgt[c] + cnt[c];
-            }
+                for (int c = 0; c < op->NC; ++c) wot[c + 1] = wot[c] + cnt[c];
+            };
+            chunk_items(CH, op->work, op->wrk_of_tgt);
+            chunk_items(CH1, op->work1, op->wrk_of_tgt1);
             // unordered far pairs (t < s) and, per cluster, its partial couplings in
             // pair order: slot 2k = row side of pair k (cluster t), 2k+1 = column side (s)
             {
@@ -760,6 +767,8 @@ ige_op ige::assemble_on(ige_ctx ctx, const ige_geom_s *geom, const ige_params &p
             op->d_work.upload(op->work, s);
             op->d_partner.upload(partner, s);
             op->d_wrk_of_tgt.upload(op->wrk_of_tgt, s);
+            op->d_work1.upload(op->work1, s);
+            op->d_wrk_of_tgt1.upload(op->wrk_of_tgt1, s);
             op->d_mom.alloc((size_t)op->NC * 3 * v.Q);
             op->d_src.alloc((size_t)op->NC * 4 * v.Q);
             // source fields of the levels above the coarsest far level are never written
@@ -767,7 +776,7 @@ ige_op ige::assemble_on(ige_ctx ctx, const ige_geom_s *geom, const ige_params &p
             IGE_HIP(hipMemsetAsync(op->d_src.p, 0, op->d_src.bytes(), s));
             op->d_loc.alloc((size_t)op->NC * 3 * v.Q);
             op->d_ybuf.alloc((size_t)D.P * v.SL * v.SL * 2 * F.rowlen * F.rowlen);
-            op->d_part.alloc(std::max<size_t>(1, op->work.size()) * 4 * v.Q);
+            op->d_part.alloc(std::max<size_t>(1, op->work1.size()) * 4 * v.Q);
             // one FP64 column, one degree (<= 8) on every level: the coupling over unordered
             // pairs when asked (IGE_M2L_SYM=1), items = cluster t with up to
             // IGE_M2L_SYM_CHUNK (default 4) partners s > t
@@ -903,6 +912,7 @@ int ige_op_info(ige_op op, ige_op_info_t *out)
         b += op->d_nbpartner.bytes() + op->d_nbslot.bytes() + op->d_nborder.bytes() + op->d_nbred_ptr.bytes();
         b += op->d_nbred_idx.bytes() + op->d_morder.bytes();
         b += op->d_Mp.bytes() * 3 + op->d_inc.bytes() + op->d_sing.bytes() + op->d_work.bytes();
+        b += op->d_work1.bytes() + op->d_wrk_of_tgt1.bytes() + op->d_wrk_of_tgt.bytes();
         b += op->d_partner.bytes() + op->d_mom.bytes() + op->d_src.bytes() + op->d_loc.bytes() + op->d_part.bytes();
         b += op->d_swork.bytes() + op->d_spartner.bytes() + op->d_sred_ptr.bytes() + op->d_sred_idx.bytes() + op->d_spart.bytes();
         b += op->d_x.bytes() + op->d_y.bytes() + op->d_V.bytes() + op->d_w.bytes() + op->d_r.bytes();

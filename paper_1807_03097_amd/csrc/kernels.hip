@@ -2040,7 +2040,7 @@ void launch_m2l(ige_op op, int prec)
     shm = std::max(shm, op->m2l_lds);
     // k = IGE_M2L_PERSIST workgroups per CU loop over the work items (room for the near
     // field's workgroups beside them); 0 (default): one workgroup per item
-    const int nwork = (int)op->work.size();
+    const int nwork = (int)op->work1.size();
     int grid = nwork;
     if (op->m2l_persist > 0) {
         int ncu = 0;
@@ -2050,11 +2050,11 @@ void launch_m2l(ige_op op, int prec)
     if (prec == IGE_F32) {
         lds_attr_once(reinterpret_cast<const void *>(&k_m2l<float>), shm);
         hipLaunchKernelGGL(k_m2l<float>, dim3(grid), dim3(kM2LThreads), shm, lstream(op), o, nwork,
-                           op->d_work.p, op->d_partner.p, op->d_src.p, op->d_part.p);
+                           op->d_work1.p, op->d_partner.p, op->d_src.p, op->d_part.p);
     } else {
         lds_attr_once(reinterpret_cast<const void *>(&k_m2l<double>), shm);
         hipLaunchKernelGGL(k_m2l<double>, dim3(grid), dim3(kM2LThreads), shm, lstream(op), o, nwork,
-                           op->d_work.p, op->d_partner.p, op->d_src.p, op->d_part.p);
+                           op->d_work1.p, op->d_partner.p, op->d_src.p, op->d_part.p);
     }
     IGE_LAUNCH_CHECK();
 }
@@ -2073,7 +2073,7 @@ void launch_m2l_reduce(ige_op op, int prec)
         IGE_LAUNCH_CHECK();
         return;
     }
-    hipLaunchKernelGGL(k_m2l_reduce, dim3(op->NC), dim3(128), 0, lstream(op), o, op->d_wrk_of_tgt.p,
+    hipLaunchKernelGGL(k_m2l_reduce, dim3(op->NC), dim3(128), 0, lstream(op), o, op->d_wrk_of_tgt1.p,
                        op->d_part.p, op->d_loc.p);
     IGE_LAUNCH_CHECK();
     if (!o.varq) return;

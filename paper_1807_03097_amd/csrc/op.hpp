@@ -157,6 +157,10 @@ struct ige_op_s {
     std::vector<int64_t> lvl_off;   // host copy
     std::vector<ige::M2LWork> work; // M2L work items (targets with chunks of partners)
     std::vector<int32_t> wrk_of_tgt;    // [NC+1] range of work items per target cluster
+    std::vector<ige::M2LWork> work1;    // the same for the one-column kernel (its own chunk size)
+    std::vector<int32_t> wrk_of_tgt1;
+    ige::DBuf<ige::M2LWork> d_work1;
+    ige::DBuf<int32_t> d_wrk_of_tgt1;
     // stored coupling blocks (one per unordered far pair)
     bool stored = false;
     bool m2l_generate_one = true;   // single column: evaluate the kernel per apply even when stored
@@ -251,7 +255,7 @@ struct ige_op_s {
     // apply workspaces (one right-hand side at a time)
     ige::DBuf<double2> d_mom;    // [NC][3][Q]   s^1, s^2, d
     ige::DBuf<double2> d_src;    // [NC][4][Q]   v_x, v_y, v_z, d
-    ige::DBuf<double2> d_part;   // [nwork][4][Q]
+    ige::DBuf<double2> d_part;   // [one-column items][4][Q]
     ige::DBuf<double2> d_loc;    // [NC][3][Q]   t^1, t^2, t^d
     ige::DBuf<double2> d_ybuf;   // [leaves][2][rowlen][rowlen] L2P results per leaf
     ige::DBuf<double2> d_x, d_y; // staging for host pointers
