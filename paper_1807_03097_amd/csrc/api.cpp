@@ -782,7 +782,7 @@ ige_op ige::assemble_on(ige_ctx ctx, const ige_geom_s *geom, const ige_params &p
             // IGE_M2L_SYM_CHUNK (default 4) partners s > t
             op->m2l_sym = false;
             if (const char *e = std::getenv("IGE_M2L_SYM"))
-                op->m2l_sym = std::atoi(e) != 0 && !F.varq && !T.far.empty() &&
+                op->m2l_sym = std::atoi(e) != 0 && !F.varq && !T.far.empty() && v.Q <= 81 &&
                               ige::m2l_sym_shared_bytes(v.Q) <= (size_t)64 * 1024;
             if (op->m2l_sym) {
                 int CHS = 4;
